@@ -1,0 +1,121 @@
+"""Synthetic workloads and seeded input generators.
+
+This module is shared by the CPU oracle, the tests and the benchmark.  It
+holds no arithmetic of the eigenvalue method: only the workload sizes and the
+seeded random draws (coefficient fields, potential centres, mesh choices) that
+both the HIP path and the oracle take as *inputs*.
+
+Mesh conventions used by every consumer of these arrays
+--------------------------------------------------------
+* The domain is the unit box (0,1)^d, d = 2 or 3, with n = 1/h cells per side.
+* Cells are numbered lexicographically with x fastest.
+* Every cell is split into d! simplices (Kuhn / Freudenthal split, which in 2D
+  is the "/" split of each square along the diagonal from (0,0) to (1,1)).
+  Simplex p of a cell follows the monotone vertex path
+      o, o + e[perm[0]], o + e[perm[0]] + e[perm[1]], ..., o + (1,..,1)
+  with perm the p-th permutation of range(d) in itertools order.  In 2D that
+  is: p=0 the lower triangle (o, o+ex, o+ex+ey), p=1 the upper triangle
+  (o, o+ey, o+ex+ey).
+* Per-element arrays therefore have length n^d * d! and index
+  cell_index * d! + p.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic eigenvalue workload (sizes and solver knobs)."""
+    name: str
+    dim: int
+    H: float            # coarse mesh size (the augmenting space V_H)
+    h: float            # finest mesh size
+    k: int              # number of sought eigenpairs
+    smoother: str       # "jacobi" | "cheb" | "learned"
+    nu_pre: int
+    nu_post: int
+    vcycles: int        # V-cycles per boundary value problem
+    precision: str      # "fp64" | "mixed"
+    tol: float          # stop when max_i |dlambda_i| / lambda_i < tol
+    kappa: str = "one"  # "one" | "lognormal"
+    potential: str = "none"  # "none" | "quadratic"
+    seed: int = 0
+
+    @property
+    def n_fine(self) -> int:
+        return int(round(1.0 / self.h))
+
+    @property
+    def n_coarse(self) -> int:
+        return int(round(1.0 / self.H))
+
+    def n_dofs(self, n: Optional[int] = None) -> int:
+        n = self.n_fine if n is None else n
+        return (n - 1) ** self.dim
+
+
+# The five workloads.  Names say what they are.
+LAP2D_SMALL = Workload("lap2d-H8-h64-k4", 2, 1 / 8, 1 / 64, 4, "jacobi", 2, 2, 2, "fp64", 1e-10)
+# 1M fine dofs, 20 eigenpairs.  The coarse space is H = 1/32: with H = 1/16 the
+# exact discrete eigenpairs 10-12 and 15-19 are repelling fixed points of the
+# correction step (growth about 3x per step), so no implementation of the
+# method reaches them; H = 1/32 makes all 20 attracting (Remark 3.1: H is
+# chosen small enough for the wanted eigenpairs).
+LAP2D_LARGE = Workload("lap2d-H32-h1024-k20", 2, 1 / 32, 1 / 1024, 20, "cheb", 4, 4, 2, "fp64", 1e-10)
+KAPPA2D_MIXED = Workload("kappa2d-H32-h2048-k50-mixed", 2, 1 / 32, 1 / 2048, 50, "cheb", 4, 4, 2,
+                         "mixed", 1e-10, kappa="lognormal", seed=0)
+BATCH2D_UNEVEN = Workload("batch16-kappaV2d-H16-k10-mixed", 2, 1 / 16, 1 / 1024, 10, "cheb", 4, 4, 2,
+                          "mixed", 1e-10, kappa="lognormal", potential="quadratic", seed=0)
+LAP3D_LEARNED = Workload("lap3d-H8-h128-k100", 3, 1 / 8, 1 / 128, 100, "jacobi", 2, 2, 2,
+                         "mixed", 1e-10)
+
+ALL = [LAP2D_SMALL, LAP2D_LARGE, KAPPA2D_MIXED, BATCH2D_UNEVEN, LAP3D_LEARNED]
+
+
+def n_elements(dim: int, n: int) -> int:
+    return n ** dim * math.factorial(dim)
+
+
+def lognormal_kappa(dim: int, n: int, seed: int = 0, sigma: float = 1.0,
+                    rng: Optional[np.random.Generator] = None) -> np.ndarray:
+    """Per-element coefficient with log(kappa) ~ N(0, sigma^2), i.i.d.
+
+    Drawn in element order (cell x-fastest, then simplex index in the cell).
+    """
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    z = rng.standard_normal(n_elements(dim, n))
+    return np.exp(sigma * z)
+
+
+@dataclasses.dataclass
+class Instance:
+    """One member of the uneven batch: -div(kappa grad u) + V u = lambda u."""
+    n_fine: int
+    centre: np.ndarray      # (2,) centre c of V = |x - c|^2
+    kappa: np.ndarray       # per fine element
+
+
+def uneven_batch(count: int = 16, seed: int = 0, fine_choices=(256, 512, 1024)) -> List[Instance]:
+    """Draw the uneven batch: per instance, centre (2 uniforms), then the
+    fine-mesh index (integers in [0, 3)), then the per-element log-normal
+    coefficient, all from one generator seeded once."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        c = rng.uniform(0.0, 1.0, size=2)
+        idx = int(rng.integers(0, len(fine_choices)))
+        n = fine_choices[idx]
+        kappa = lognormal_kappa(2, n, rng=rng)
+        out.append(Instance(n, c, kappa))
+    return out
+
+
+def random_vectors(shape, seed: int = 0, dtype=np.float64) -> np.ndarray:
+    """Seeded standard-normal test vectors."""
+    return np.random.default_rng(seed).standard_normal(shape).astype(dtype)
