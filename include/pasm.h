@@ -1,0 +1,206 @@
+/*
+ * pasm.h -- C ABI of the MI355X (gfx950) parallel augmented subspace eigensolver.
+ *
+ * The library computes the k smallest eigenpairs of the P1 finite element
+ * discretisation of
+ *
+ *     -div(kappa grad u) + V u = lambda u   in (0,1)^d,   u = 0 on the boundary,
+ *
+ * (the model problem of Section 2, with the zeroth-order term of the second
+ * example in Section 5) on the uniform Kuhn simplex mesh of mesh size h: the
+ * "/" split of squares in 2D, Kuhn tetrahedra in 3D.  It implements
+ * Algorithm 2 (parallel augmented subspace scheme) with h_1 = H: the coarse
+ * eigenproblem on V_H gives the start, and every eigenpair is then corrected
+ * independently on the finest mesh by Algorithm 1 (one correction step):
+ *   1. a few multigrid V-cycles for the boundary value problem
+ *          A_h u^ = lambda M_h u                 (Algorithm 1, step 1);
+ *   2. the borders b = P^T A_h u~, c = P^T M_h u~, beta = u~^T A_h u~,
+ *      zeta = u~^T M_h u~ of the augmented space V_H + span{u~} and the
+ *      (N_H+1)-dimensional generalized eigenproblem of Section 3.1 (matrix
+ *      form), keeping the eigenvector with the largest component along u~
+ *      (the score |u_H . c + alpha zeta|), prolongated back to the fine mesh.
+ * All k eigenpairs are processed together as k right-hand sides of the same
+ * sweeps, never orthogonalised against each other (Section 3.2).
+ *
+ * Conventions for every entry point
+ *   - Vectors of nodal values hold the interior nodes only, numbered
+ *     lexicographically with x fastest; a batch of k vectors is stored as k
+ *     consecutive blocks of `ld` doubles (ld >= number of interior nodes).
+ *   - Per-element input arrays follow the element order of the Kuhn mesh:
+ *     cell index (x fastest) major, simplex index minor, the simplex p of a
+ *     cell being the monotone vertex path o, o+e[pi0], o+e[pi0]+e[pi1], ...
+ *     for pi the p-th permutation of (0..d-1) in lexicographic order (2D:
+ *     p = 0 lower triangle (o, o+ex, o+ex+ey), p = 1 upper triangle).
+ *   - Eigenvectors are returned M-normalised (u^T M_h u = 1), eigenvalues in
+ *     the order of their coarse start index.
+ *   - Host inputs are copied during the call; the library keeps no pointer to
+ *     caller memory.  The context owns its device memory, allocated once in
+ *     pasm_setup and released in pasm_destroy; pasm_iterate allocates nothing.
+ *   - Every call returns a status; no C++ exception crosses the ABI.  After a
+ *     failure pasm_last_error() on the same context describes it.
+ *   - A context is used by one host thread at a time.  All device work runs
+ *     on the stream given in the options (NULL: a stream the context creates).
+ */
+#ifndef PASM_H
+#define PASM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PASM_API __attribute__((visibility("default")))
+
+typedef struct pasm_ctx pasm_ctx;
+
+typedef enum pasm_status {
+    PASM_OK = 0,
+    PASM_E_INVALID = 1,    /* bad argument: sizes, mesh ratio, k, null pointer */
+    PASM_E_NOMEM = 2,      /* device or host allocation failed */
+    PASM_E_DEVICE = 3,     /* HIP, rocBLAS or rocSOLVER call failed */
+    PASM_E_STATE = 4,      /* call out of order (e.g. iterate before setup) */
+    PASM_E_NOTCONV = 5,    /* iteration cap reached before the tolerance */
+    PASM_E_BREAKDOWN = 6   /* non-finite value detected in the eigenpairs */
+} pasm_status;
+
+typedef enum pasm_precision {
+    PASM_FP64 = 0,         /* every step in FP64 */
+    PASM_MIXED = 1         /* V-cycles in FP32 on FP64 residuals (defect correction);
+                              residuals, borders, Rayleigh quotients and the
+                              augmented eigensolve in FP64 */
+} pasm_precision;
+
+typedef enum pasm_smoother {
+    PASM_JACOBI = 0,       /* damped Jacobi, x <- x + omega D^{-1}(f - A x) */
+    PASM_CHEBYSHEV = 1     /* Chebyshev semi-iteration on D^{-1}A over [rho/alpha, rho] */
+} pasm_smoother;
+
+/* Unit box (0,1)^dim; dim = 2 or 3. */
+typedef struct pasm_domain {
+    int dim;
+} pasm_domain;
+
+/* Coefficients of -div(kappa grad u) + V u, constant per fine element
+ * (element order above).  NULL kappa means kappa = 1, NULL potential means
+ * V = 0.  kappa must be finite and positive, potential finite and >= 0.
+ * Variable coefficients are supported in 2D. */
+typedef struct pasm_coefficients {
+    const double* kappa;       /* n_elements values or NULL */
+    const double* potential;   /* n_elements values of V at the element centroid, or NULL */
+    size_t n_elements;         /* (1/h)^dim * dim! when either array is given */
+} pasm_coefficients;
+
+typedef struct pasm_options {
+    int precision;      /* pasm_precision */
+    int smoother;       /* pasm_smoother */
+    int nu_pre;         /* Jacobi sweeps / Chebyshev degree before restriction */
+    int nu_post;        /* ... after prolongation */
+    int vcycles;        /* V-cycles per boundary value problem (>= 1) */
+    int max_iter;       /* cap used by pasm_solve */
+    double tol;         /* converged when max_i |lambda_i - lambda_i_prev| / lambda_i < tol */
+    double omega;       /* Jacobi weight; <= 0 selects 4/5 (2D) or 6/7 (3D) */
+    double cheb_alpha;  /* Chebyshev interval [rho/alpha, rho]; <= 0 selects 4 (2D) or 6 (3D) */
+    void* stream;       /* hipStream_t, or NULL */
+} pasm_options;
+
+/* Fill *opt with the defaults: FP64, Jacobi 2/2, 2 V-cycles, 50 iterations,
+ * tol 1e-10, omega and alpha by dimension, own stream. */
+PASM_API void pasm_default_options(pasm_options* opt);
+
+/* Build the mesh hierarchy H = h_1 > 2h > ... > h (ratio 2, Section 3), the
+ * coarse operators, the coarse generalized eigenproblem of Algorithm 2,
+ * step 1 (A_H q = theta M_H q, dense, on the device), and the start
+ * lambda_i = theta_i, u_i = P q_i for i < k.
+ *   out        receives the new context (set to NULL on failure)
+ *   H, h       coarse and fine mesh sizes: 1/H and 1/h integers, 1/h = 2^j / H,
+ *              j >= 0 (j = 0: the augmented space degenerates and the coarse
+ *              Ritz pairs are returned)
+ *   k          number of eigenpairs, 1 <= k < N_H = (1/H - 1)^dim (Remark 3.1)
+ *   opt        NULL for defaults
+ * Device memory for every buffer of the iteration is allocated here. */
+PASM_API pasm_status pasm_setup(pasm_ctx** out, const pasm_domain* domain,
+                                const pasm_coefficients* coef, double H, double h,
+                                int k, const pasm_options* opt);
+
+/* One outer iteration = one correction step (Algorithm 1) for all k
+ * eigenpairs at once.  *converged (may be NULL) is set to 1 when the
+ * maximum relative eigenvalue change is below opt.tol.  Synchronises the
+ * stream once (to read the k eigenvalues).  Returns PASM_E_BREAKDOWN if an
+ * eigenvalue is not finite. */
+PASM_API pasm_status pasm_iterate(pasm_ctx* ctx, int* converged);
+
+/* Return to the start of Algorithm 2 (lambda_i = theta_i, u_i = P q_i) on
+ * the device, reusing the coarse eigenpairs computed by pasm_setup. */
+PASM_API pasm_status pasm_restart(pasm_ctx* ctx);
+
+/* Iterate until converged or opt.max_iter iterations; *iterations (may be
+ * NULL) receives the count.  PASM_E_NOTCONV if the cap was reached. */
+PASM_API pasm_status pasm_solve(pasm_ctx* ctx, int* iterations);
+
+/* Copy the current eigenvalues (k doubles) and, if U != NULL, the eigenvectors
+ * (k blocks of ldu doubles, host memory) out of the context. */
+PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* ctx, double* lambda, double* U, size_t ldu);
+
+/* Same, with U in device memory (written on the context's stream, which is
+ * synchronised before return). */
+PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* ctx, double* U_dev, size_t ldu);
+
+/* Replace the current state by (lambda, U) (host memory, layout as above):
+ * a warm start or checkpoint restore.  The previous-eigenvalue record used by
+ * the stop test is set to lambda. */
+PASM_API pasm_status pasm_set_state(pasm_ctx* ctx, const double* lambda, const double* U, size_t ldu);
+
+/* Per-eigenpair report of the last iteration (host arrays of k entries, any
+ * may be NULL): the selected augmented eigenvalue's rank from the bottom of
+ * the augmented spectrum, its score |b(u_new, u~)|, and a flag word
+ * (bit 0: augmentation skipped because u~ lay in V_H; bit 1: a deflated
+ * coarse direction was selected). */
+PASM_API pasm_status pasm_last_selection(const pasm_ctx* ctx, int* rank, double* score, int* flags);
+
+/* Sizes: interior fine nodes, interior coarse nodes, number of levels. */
+PASM_API size_t pasm_num_dofs(const pasm_ctx* ctx);
+PASM_API size_t pasm_coarse_dofs(const pasm_ctx* ctx);
+PASM_API int pasm_num_levels(const pasm_ctx* ctx);
+
+/* Release every resource of the context.  NULL is accepted. */
+PASM_API pasm_status pasm_destroy(pasm_ctx* ctx);
+
+PASM_API const char* pasm_status_string(pasm_status s);
+/* Message of the last failure on ctx; with ctx == NULL, of the last failed
+ * pasm_setup on the calling thread. */
+PASM_API const char* pasm_last_error(const pasm_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks, exposed for verification against the CPU oracle.  Vectors
+ * are device pointers in the compact interior layout above, FP64.
+ * ------------------------------------------------------------------------- */
+
+enum { PASM_OP_STIFFNESS = 0, PASM_OP_MASS = 1 };
+
+/* y = A_l x (op = STIFFNESS, the level's stiffness + potential operator) or
+ * y = M_h x (op = MASS, finest level only) for nrhs vectors.  Level 0 is V_H,
+ * level pasm_num_levels()-1 the finest mesh. */
+PASM_API pasm_status pasm_apply_operator(pasm_ctx* ctx, int level, int op, const double* x,
+                                         double* y, size_t ld, int nrhs);
+
+/* ncycles V-cycles of the library's multigrid (same smoother, levels and
+ * coarse solve as pasm_iterate, in the context's precision) for A_h x = f on
+ * the finest level, starting from x; nrhs <= k vectors, x updated in place. */
+PASM_API pasm_status pasm_vcycle(pasm_ctx* ctx, const double* f, double* x, size_t ld, int nrhs,
+                                 int ncycles);
+
+/* Time the launches of one kernel class inside subsequent pasm_iterate calls
+ * with HIP events recorded on the context's stream (enable = 1 starts and
+ * clears the record, 0 stops).  kernel: 0 = fine-level smoothing sweep. */
+PASM_API pasm_status pasm_profile(pasm_ctx* ctx, int kernel, int enable);
+/* Number of timed launches, their summed duration (ms) and the bytes each
+ * launch must move at minimum (the algorithmic traffic of that kernel). */
+PASM_API pasm_status pasm_profile_read(pasm_ctx* ctx, int kernel, long* launches, double* total_ms,
+                                       double* bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PASM_H */

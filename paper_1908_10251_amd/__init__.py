@@ -1,0 +1,287 @@
+"""Python binding of libpasm (include/pasm.h): argument marshalling only.
+
+Every computation of the eigensolver runs in the HIP library; this module
+converts arguments, raises on error statuses and uses PyTorch only for device
+memory (tensors whose pointers are passed to the library) and for the current
+HIP stream.  If the library has not been built, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpasm.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pasm.h")
+
+PASM_OK, PASM_E_INVALID, PASM_E_NOMEM, PASM_E_DEVICE, PASM_E_STATE, PASM_E_NOTCONV, PASM_E_BREAKDOWN = range(7)
+PASM_FP64, PASM_MIXED = 0, 1
+PASM_JACOBI, PASM_CHEBYSHEV = 0, 1
+PASM_OP_STIFFNESS, PASM_OP_MASS = 0, 1
+
+
+class PasmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pasm status {status}: {msg}")
+        self.status = status
+
+
+class pasm_domain(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int)]
+
+
+class pasm_coefficients(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.POINTER(ctypes.c_double)),
+                ("potential", ctypes.POINTER(ctypes.c_double)),
+                ("n_elements", ctypes.c_size_t)]
+
+
+class pasm_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("smoother", ctypes.c_int),
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+                ("vcycles", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("tol", ctypes.c_double), ("omega", ctypes.c_double),
+                ("cheb_alpha", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpasm.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1908_10251_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.pasm_default_options.argtypes = [ctypes.POINTER(pasm_options)]
+    L.pasm_default_options.restype = None
+    L.pasm_setup.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(pasm_domain), ctypes.POINTER(pasm_coefficients),
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(pasm_options)]
+    L.pasm_iterate.argtypes = [_P, _I]
+    L.pasm_solve.argtypes = [_P, _I]
+    L.pasm_restart.argtypes = [_P]
+    L.pasm_eigenpairs.argtypes = [_P, _D, _D, ctypes.c_size_t]
+    L.pasm_eigenvectors_device.argtypes = [_P, _P, ctypes.c_size_t]
+    L.pasm_set_state.argtypes = [_P, _D, _D, ctypes.c_size_t]
+    L.pasm_last_selection.argtypes = [_P, _I, _D, _I]
+    L.pasm_num_dofs.argtypes = [_P]
+    L.pasm_num_dofs.restype = ctypes.c_size_t
+    L.pasm_coarse_dofs.argtypes = [_P]
+    L.pasm_coarse_dofs.restype = ctypes.c_size_t
+    L.pasm_num_levels.argtypes = [_P]
+    L.pasm_destroy.argtypes = [_P]
+    L.pasm_status_string.argtypes = [ctypes.c_int]
+    L.pasm_status_string.restype = ctypes.c_char_p
+    L.pasm_last_error.argtypes = [_P]
+    L.pasm_last_error.restype = ctypes.c_char_p
+    L.pasm_apply_operator.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_size_t, ctypes.c_int]
+    L.pasm_vcycle.argtypes = [_P, _P, _P, ctypes.c_size_t, ctypes.c_int, ctypes.c_int]
+    L.pasm_profile.argtypes = [_P, ctypes.c_int, ctypes.c_int]
+    L.pasm_profile_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _D, _D]
+    _lib = L
+    return L
+
+
+def _check(status: int, ctx=None):
+    if status != PASM_OK:
+        L = lib()
+        msg = (L.pasm_last_error(ctx) or b"").decode()
+        raise PasmError(status, f"{L.pasm_status_string(status).decode()}: {msg}")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _torch_ptr(t) -> int:
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return t.data_ptr()
+
+
+def current_stream_handle() -> Optional[int]:
+    """The raw hipStream_t of torch's current stream (None without a GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:  # pragma: no cover
+        pass
+    return None
+
+
+def pasm_default_options() -> pasm_options:
+    o = pasm_options()
+    lib().pasm_default_options(ctypes.byref(o))
+    return o
+
+
+def pasm_setup(dim: int, H: float, h: float, k: int, kappa: Optional[np.ndarray] = None,
+               potential: Optional[np.ndarray] = None, options: Optional[pasm_options] = None,
+               stream=None):
+    """Create a context; returns the opaque handle (ctypes.c_void_p)."""
+    L = lib()
+    dom = pasm_domain(dim)
+    coef = pasm_coefficients()
+    keep = []
+    n_el = 0
+    if kappa is not None:
+        kap = np.ascontiguousarray(kappa, dtype=np.float64)
+        keep.append(kap)
+        coef.kappa = _dptr(kap)
+        n_el = kap.size
+    if potential is not None:
+        pot = np.ascontiguousarray(potential, dtype=np.float64)
+        keep.append(pot)
+        coef.potential = _dptr(pot)
+        n_el = pot.size
+    coef.n_elements = n_el
+    opt = options if options is not None else pasm_default_options()
+    if stream is not None:
+        opt.stream = stream
+    ctx = _P()
+    st = L.pasm_setup(ctypes.byref(ctx), ctypes.byref(dom), ctypes.byref(coef), float(H), float(h), int(k),
+                      ctypes.byref(opt))
+    _check(st, None)
+    return ctx
+
+
+def pasm_iterate(ctx) -> bool:
+    conv = ctypes.c_int(0)
+    _check(lib().pasm_iterate(ctx, ctypes.byref(conv)), ctx)
+    return bool(conv.value)
+
+
+def pasm_restart(ctx) -> None:
+    _check(lib().pasm_restart(ctx), ctx)
+
+
+def pasm_solve(ctx, allow_notconv: bool = False) -> int:
+    it = ctypes.c_int(0)
+    st = lib().pasm_solve(ctx, ctypes.byref(it))
+    if not (allow_notconv and st == PASM_E_NOTCONV):
+        _check(st, ctx)
+    return it.value
+
+
+def pasm_num_dofs(ctx) -> int:
+    return int(lib().pasm_num_dofs(ctx))
+
+
+def pasm_coarse_dofs(ctx) -> int:
+    return int(lib().pasm_coarse_dofs(ctx))
+
+
+def pasm_num_levels(ctx) -> int:
+    return int(lib().pasm_num_levels(ctx))
+
+
+def pasm_eigenpairs(ctx, k: int, vectors: bool = True) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    N = pasm_num_dofs(ctx)
+    lam = np.empty(k)
+    U = np.empty((k, N)) if vectors else None
+    _check(lib().pasm_eigenpairs(ctx, _dptr(lam), _dptr(U) if vectors else None, N), ctx)
+    return lam, U
+
+
+def pasm_eigenvectors_device(ctx, U_dev) -> None:
+    _check(lib().pasm_eigenvectors_device(ctx, _torch_ptr(U_dev), U_dev.shape[-1]), ctx)
+
+
+def pasm_set_state(ctx, lam: np.ndarray, U: np.ndarray) -> None:
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _check(lib().pasm_set_state(ctx, _dptr(lam), _dptr(U), U.shape[1]), ctx)
+
+
+def pasm_last_selection(ctx, k: int):
+    rank = np.empty(k, dtype=np.int32)
+    score = np.empty(k)
+    flags = np.empty(k, dtype=np.int32)
+    _check(lib().pasm_last_selection(ctx, rank.ctypes.data_as(_I), _dptr(score), flags.ctypes.data_as(_I)), ctx)
+    return rank, score, flags
+
+
+def pasm_apply_operator(ctx, level: int, op: int, x, y) -> None:
+    """y = A_level x or M_h x for torch float64 CUDA tensors of shape (nrhs, N_level)."""
+    _check(lib().pasm_apply_operator(ctx, level, op, _torch_ptr(x), _torch_ptr(y), x.shape[1], x.shape[0]), ctx)
+
+
+def pasm_vcycle(ctx, f, x, ncycles: int) -> None:
+    _check(lib().pasm_vcycle(ctx, _torch_ptr(f), _torch_ptr(x), x.shape[1], x.shape[0], ncycles), ctx)
+
+
+def pasm_profile(ctx, kernel: int, enable: bool) -> None:
+    _check(lib().pasm_profile(ctx, kernel, int(enable)), ctx)
+
+
+def pasm_profile_read(ctx, kernel: int):
+    n = ctypes.c_long(0)
+    ms = ctypes.c_double(0)
+    b = ctypes.c_double(0)
+    _check(lib().pasm_profile_read(ctx, kernel, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)), ctx)
+    return n.value, ms.value, b.value
+
+
+def pasm_destroy(ctx) -> None:
+    if ctx:
+        _check(lib().pasm_destroy(ctx))
+
+
+def options(precision: int = PASM_FP64, smoother: int = PASM_JACOBI, nu_pre: int = 2, nu_post: int = 2,
+            vcycles: int = 2, max_iter: int = 50, tol: float = 1e-10, omega: float = 0.0,
+            cheb_alpha: float = 0.0) -> pasm_options:
+    o = pasm_default_options()
+    o.precision, o.smoother, o.nu_pre, o.nu_post = precision, smoother, nu_pre, nu_post
+    o.vcycles, o.max_iter, o.tol, o.omega, o.cheb_alpha = vcycles, max_iter, tol, omega, cheb_alpha
+    return o
+
+
+def options_for(workload) -> pasm_options:
+    """Options matching a `workloads.Workload` description."""
+    return options(precision=PASM_MIXED if workload.precision == "mixed" else PASM_FP64,
+                   smoother=PASM_CHEBYSHEV if workload.smoother == "cheb" else PASM_JACOBI,
+                   nu_pre=workload.nu_pre, nu_post=workload.nu_post, vcycles=workload.vcycles,
+                   tol=workload.tol)
+
+
+class Solver:
+    """Owning wrapper around a context."""
+
+    def __init__(self, dim, H, h, k, kappa=None, potential=None, opts=None, stream=None):
+        self.k = k
+        self.ctx = pasm_setup(dim, H, h, k, kappa, potential, opts, stream)
+
+    def iterate(self) -> bool:
+        return pasm_iterate(self.ctx)
+
+    def solve(self, allow_notconv=False) -> int:
+        return pasm_solve(self.ctx, allow_notconv)
+
+    def eigenpairs(self, vectors=True):
+        return pasm_eigenpairs(self.ctx, self.k, vectors)
+
+    def close(self):
+        if self.ctx:
+            pasm_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

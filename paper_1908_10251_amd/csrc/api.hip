@@ -1,0 +1,965 @@
+// Host orchestration and the C ABI (include/pasm.h).
+//
+// One pasm_iterate is one correction step (Algorithm 1) for all k eigenpairs:
+//   1. f = lambda M_h u; a fixed number of V-cycles for A_h u~ = f from u
+//      (Algorithm 1, step 1).  In mixed precision every V-cycle runs in FP32
+//      on the FP64 residual r = f - A_h x and its result is added to x in FP64
+//      (defect correction), so the FP64 fixed point is unchanged.
+//   2. borders b = P^T A u~, c = P^T M u~, beta, zeta (one fine sweep plus a
+//      restriction chain), p = Q^T b, q = Q^T c, the arrowhead eigensolve and
+//      selection (coarse.hip), u_new = P Q y' + s u~, lambda_new = mu
+//      (Algorithm 1, step 2; Section 3.1).
+// Algorithm 2 with h_1 = H is pasm_setup (coarse eigenproblem, start
+// u_i = P q_i, lambda_i = theta_i) followed by pasm_solve.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace pasm {
+
+long arrow_work_doubles(int N, int k);
+size_t arrow_workspace_bytes(int N, int k);
+
+Grid make_grid(int dim, int n) {
+    Grid g;
+    g.dim = dim;
+    g.n = n;
+    g.m = n - 1;
+    g.pitch = ((n + 1 + ORIGIN) + 15) / 16 * 16;
+    long rows = (long)(n + 1) * (dim == 3 ? (n + 1) : 1);
+    long pl = rows * g.pitch;
+    g.plane = (pl + 63) / 64 * 64;
+    g.h = 1.0 / n;
+    return g;
+}
+
+namespace {
+
+__global__ void k_transpose(const double* __restrict__ a, double* __restrict__ b, int n) {
+    const int i = blockIdx.x * 16 + threadIdx.x, j = blockIdx.y * 16 + threadIdx.y;
+    if (i < n && j < n) b[(long)i * n + j] = a[(long)j * n + i];
+}
+__global__ void k_scale_cols(const double* __restrict__ q, const double* __restrict__ th, double* __restrict__ o,
+                             int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (i < n) o[(long)j * n + i] = q[(long)j * n + i] / th[j];
+}
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, long n) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        b[t] = (float)a[t];
+}
+__global__ void k_unit_coefs(double* __restrict__ y, int N, int k) {
+    const int j = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    if (j < N) y[(long)r * N + j] = (j == r) ? 1.0 : 0.0;
+}
+__global__ void k_copy_d(const double* __restrict__ a, double* __restrict__ b, int n) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n) b[t] = a[t];
+}
+
+struct Level {
+    Grid g;
+    bool const_coef = true;
+    double w0 = 1.0;
+    double rho = 2.0;
+    double* w64[3] = {nullptr, nullptr, nullptr};
+    float* w32[3] = {nullptr, nullptr, nullptr};
+    std::vector<Cheb> pre, post;
+    // V-cycle vectors of this level (type of the V-cycle), levels below the finest
+    void* X = nullptr;
+    void* F = nullptr;
+    void* Y = nullptr;
+    // FP64 border / prolongation chain vectors
+    double* B = nullptr;
+    double* C = nullptr;
+};
+
+}  // namespace
+}  // namespace pasm
+
+using pasm::Cheb;
+using pasm::Coef;
+using pasm::Error;
+using pasm::Grid;
+
+struct pasm_ctx {
+    int dim = 2, k = 0, L = 0, NH = 0;
+    pasm_options opt{};
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    bool mixed = false;
+    std::vector<pasm::Level> lv;
+    // finest level, FP64
+    double *U = nullptr, *F64 = nullptr, *Y64 = nullptr, *R64 = nullptr;
+    // finest level, FP32 (mixed)
+    float *E32 = nullptr, *R32 = nullptr, *Y32 = nullptr;
+    // coarse space
+    double *theta = nullptr, *Qcm = nullptr, *Qrm = nullptr, *Ainv64 = nullptr;
+    float* Ainv32 = nullptr;
+    int* group = nullptr;
+    double *bz = nullptr, *partial = nullptr, *pp = nullptr, *qq = nullptr, *ycoef = nullptr;
+    double *s = nullptr, *mu = nullptr, *lam = nullptr, *lam_prev = nullptr, *score = nullptr;
+    int *rank = nullptr, *flags = nullptr;
+    void* awork = nullptr;
+    std::vector<void*> allocs;
+    std::vector<double> lam_h, lam_prev_h;
+    std::string err;
+    rocblas_handle blas = nullptr;
+    long iters = 0;
+    // profiling of the fine-level smoothing sweeps
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    std::vector<double> ev_bytes;
+    long prof_launches = 0;
+    double prof_ms = 0.0, prof_bytes = 0.0;
+
+    template <typename T>
+    T* alloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw Error(PASM_E_NOMEM, "hipMalloc failed");
+        allocs.push_back(p);
+        PASM_HIP(hipMemsetAsync(p, 0, count * sizeof(T), st));
+        return static_cast<T*>(p);
+    }
+    const Grid& gf() const { return lv.back().g; }
+    long sf() const { return gf().plane; }
+
+    template <typename T>
+    Coef<T> coef(int l) const;
+};
+
+template <>
+Coef<double> pasm_ctx::coef<double>(int l) const {
+    Coef<double> c;
+    const auto& L = lv[l];
+    if (!L.const_coef) {
+        c.wx = L.w64[0];
+        c.wy = L.w64[1];
+        c.wz = L.w64[2];
+    }
+    c.w0 = L.w0;
+    return c;
+}
+template <>
+Coef<float> pasm_ctx::coef<float>(int l) const {
+    Coef<float> c;
+    const auto& L = lv[l];
+    if (!L.const_coef) {
+        c.wx = L.w32[0];
+        c.wy = L.w32[1];
+        c.wz = L.w32[2];
+    }
+    c.w0 = (float)L.w0;
+    return c;
+}
+
+namespace pasm {
+namespace {
+
+// Chebyshev semi-iteration of degree s on D^{-1}A over [rho/alpha, rho], as
+// the three-term recurrence x_{j+1} = x_j + a_j (x_j - x_{j-1}) + b_j D^{-1} r_j:
+// theta = (b+a)/2, delta = (b-a)/2, sigma = theta/delta, rho_0 = 1/sigma,
+// b_0 = 1/theta, a_0 = 0; rho_j = 1/(2 sigma - rho_{j-1}),
+// a_j = rho_j rho_{j-1}, b_j = 2 rho_j / delta.
+std::vector<Cheb> cheb_steps(double rho, double alpha, int s) {
+    std::vector<Cheb> v;
+    const double lo = rho / alpha, hi = rho;
+    const double th = 0.5 * (hi + lo), de = 0.5 * (hi - lo), sg = th / de;
+    double rj = 1.0 / sg;
+    for (int j = 0; j < s; ++j) {
+        if (j == 0) v.push_back({0.0, 1.0 / th});
+        else {
+            const double rn = 1.0 / (2.0 * sg - rj);
+            v.push_back({rn * rj, 2.0 * rn / de});
+            rj = rn;
+        }
+    }
+    return v;
+}
+
+std::vector<Cheb> jacobi_steps(double omega, int s) { return std::vector<Cheb>(s, Cheb{0.0, omega}); }
+
+// Edge weights of the 2D stiffness from per-element kappa on a level with n
+// cells (element order: cell x-fastest, lower then upper triangle).  The edge
+// (i,j)-(i+1,j) is a leg of the lower triangle of cell (i,j) and of the upper
+// triangle of cell (i,j-1); the edge (i,j)-(i,j+1) of the upper triangle of
+// cell (i,j) and of the lower triangle of cell (i-1,j); each leg couples with
+// kappa_T / 2.
+void edge_weights_2d(const Grid& g, const std::vector<double>& kap, std::vector<double>& wx,
+                     std::vector<double>& wy) {
+    const int n = g.n;
+    wx.assign(g.plane, 0.0);
+    wy.assign(g.plane, 0.0);
+    auto kl = [&](int ci, int cj) { return kap[2 * ((size_t)cj * n + ci)]; };
+    auto ku = [&](int ci, int cj) { return kap[2 * ((size_t)cj * n + ci) + 1]; };
+    for (int j = 0; j <= n; ++j)
+        for (int i = 0; i <= n; ++i) {
+            if (i < n) {
+                double w = 0.0;
+                if (j < n) w += kl(i, j);
+                if (j > 0) w += ku(i, j - 1);
+                wx[g.idx(i, j)] = 0.5 * w;
+            }
+            if (j < n) {
+                double w = 0.0;
+                if (i < n) w += ku(i, j);
+                if (i > 0) w += kl(i - 1, j);
+                wy[g.idx(i, j)] = 0.5 * w;
+            }
+        }
+}
+
+// Galerkin coarsening of a per-element coefficient (2D): the coarse triangle's
+// value is the mean over its four children, which makes the rediscretised
+// coarse stiffness equal to P^T A P.  Children of the lower coarse triangle of
+// cell (I,J): lower of fine cell (2I,2J), both of (2I+1,2J), lower of
+// (2I+1,2J+1); of the upper: upper of (2I,2J), both of (2I,2J+1), upper of
+// (2I+1,2J+1).
+std::vector<double> coarsen_kappa_2d(const std::vector<double>& kf, int nf) {
+    const int nc = nf / 2;
+    std::vector<double> kc(2 * (size_t)nc * nc);
+    auto K = [&](int ci, int cj, int p) { return kf[2 * ((size_t)cj * nf + ci) + p]; };
+    for (int J = 0; J < nc; ++J)
+        for (int I = 0; I < nc; ++I) {
+            const int i = 2 * I, j = 2 * J;
+            kc[2 * ((size_t)J * nc + I)] = 0.25 * (K(i, j, 0) + K(i + 1, j, 0) + K(i + 1, j, 1) + K(i + 1, j + 1, 0));
+            kc[2 * ((size_t)J * nc + I) + 1] =
+                0.25 * (K(i, j, 1) + K(i, j + 1, 0) + K(i, j + 1, 1) + K(i + 1, j + 1, 1));
+        }
+    return kc;
+}
+
+}  // namespace
+}  // namespace pasm
+
+// ---------------------------------------------------------------------------
+// V-cycle (templated on the cycle's floating type)
+// ---------------------------------------------------------------------------
+namespace {
+
+void record_start(pasm_ctx* c) {
+    if (!c->prof) return;
+    if (c->ev_used + 2 > c->ev.size()) {
+        hipEvent_t a, b;
+        PASM_HIP(hipEventCreate(&a));
+        PASM_HIP(hipEventCreate(&b));
+        c->ev.push_back(a);
+        c->ev.push_back(b);
+        c->ev_bytes.push_back(0.0);
+    }
+    PASM_HIP(hipEventRecord(c->ev[c->ev_used], c->st));
+}
+void record_end(pasm_ctx* c, double bytes) {
+    if (!c->prof) return;
+    PASM_HIP(hipEventRecord(c->ev[c->ev_used + 1], c->st));
+    c->ev_bytes[c->ev_used / 2] = bytes;
+    c->ev_used += 2;
+}
+void collect_profile(pasm_ctx* c) {
+    if (!c->prof) return;
+    for (size_t e = 0; e < c->ev_used; e += 2) {
+        float ms = 0.f;
+        PASM_HIP(hipEventElapsedTime(&ms, c->ev[e], c->ev[e + 1]));
+        c->prof_ms += ms;
+        c->prof_bytes += c->ev_bytes[e / 2];
+        c->prof_launches += 1;
+    }
+    c->ev_used = 0;
+}
+
+// Apply the smoothing steps of `steps` at level l: x (current) and y
+// (scratch) are swapped after every step so x always holds the iterate.
+template <typename T>
+void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb>& steps, bool x_zero,
+            int nrhs) {
+    const pasm::Level& L = c->lv[l];
+    const Coef<T> cf = c->coef<T>(l);
+    const bool fine = (l == c->L - 1);
+    for (size_t j = 0; j < steps.size(); ++j) {
+        const bool z = x_zero && j == 0;
+        if (fine) {
+            // algorithmic bytes: read x_k (unless zero), x_{k-1} (if a != 0), f; write x_{k+1};
+            // plus the coefficient arrays once per launch
+            const double words = 2.0 + (z ? 0.0 : 1.0) + (steps[j].a != 0.0 && !z ? 1.0 : 0.0);
+            double bytes = words * sizeof(T) * (double)L.g.interior() * nrhs;
+            if (!L.const_coef) bytes += (double)L.g.dim * sizeof(T) * (double)L.g.interior();
+            record_start(c);
+            pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], z, c->st);
+            record_end(c, bytes);
+        } else {
+            pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], z, c->st);
+        }
+        std::swap(x, y);
+    }
+}
+
+template <typename T>
+const T* ainv(const pasm_ctx* c);
+template <>
+const double* ainv<double>(const pasm_ctx* c) { return c->Ainv64; }
+template <>
+const float* ainv<float>(const pasm_ctx* c) { return c->Ainv32; }
+
+// One V-cycle at level l >= 0 on (x, f); x may start at zero.
+template <typename T>
+void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs) {
+    const pasm::Level& L = c->lv[l];
+    if (l == 0) {
+        pasm::launch_dense_mv<T>(ainv<T>(c), c->NH, L.g, f, L.g.plane, true, x, L.g.plane, true, nrhs, c->st);
+        return;
+    }
+    smooth<T>(c, l, x, y, f, L.pre, x_zero, nrhs);
+    const bool zero_after_pre = x_zero && L.pre.empty();
+    pasm::Level& Lc = c->lv[l - 1];
+    T* fc = static_cast<T*>(Lc.F);
+    if (zero_after_pre) {
+        // x = 0: the residual is f, restricted
+        pasm::launch_restrict<T>(L.g, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
+    } else {
+        pasm::launch_resid_restrict<T>(L.g, c->coef<T>(l), x, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
+    }
+    T* xc = static_cast<T*>(Lc.X);
+    T* yc = static_cast<T*>(Lc.Y);
+    vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
+    if (zero_after_pre) {
+        pasm::launch_prolong<T>(Lc.g, xc, L.g, x, nrhs, Lc.g.plane, L.g.plane, false, nullptr, c->st);
+    } else {
+        pasm::launch_prolong<T>(Lc.g, xc, L.g, x, nrhs, Lc.g.plane, L.g.plane, true, nullptr, c->st);
+    }
+    smooth<T>(c, l, x, y, f, L.post, false, nrhs);
+}
+
+// ncycles V-cycles for A x = f at the finest level; x, f are FP64 finest-level
+// buffers (padded), scr an FP64 scratch buffer of the same size.
+void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles) {
+    const int lf = c->L - 1;
+    if (!c->mixed) {
+        for (int cy = 0; cy < ncycles; ++cy) vcycle<double>(c, lf, x, scr, f, false, nrhs);
+        return;
+    }
+    const Grid& g = c->gf();
+    for (int cy = 0; cy < ncycles; ++cy) {
+        pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st);
+        float* e = c->E32;
+        float* ye = c->Y32;
+        vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
+        pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
+    }
+}
+
+thread_local std::string g_setup_error;
+
+void set_error(pasm_ctx* c, const std::string& m) {
+    if (c) c->err = m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Plan {
+    int dim, nH, nh, L, NH;
+    bool have_kappa;
+    size_t nel;
+};
+
+// Argument checks only (no device calls), so invalid input is reported the
+// same way with or without a GPU.
+Plan validate(const pasm_options& opt, const pasm_domain* dom, const pasm_coefficients* coef, double H, double h,
+              int k) {
+    Plan p{};
+    if (!dom || (dom->dim != 2 && dom->dim != 3)) throw Error(PASM_E_INVALID, "domain dim must be 2 or 3");
+    p.dim = dom->dim;
+    if (!(H > 0.0) || !(h > 0.0) || !std::isfinite(H) || !std::isfinite(h) || h > H)
+        throw Error(PASM_E_INVALID, "need 0 < h <= H");
+    const double nHd = 1.0 / H, nhd = 1.0 / h;
+    if (nHd > 1e6 || nhd > 1e6) throw Error(PASM_E_INVALID, "mesh too fine");
+    p.nH = (int)std::lround(nHd);
+    p.nh = (int)std::lround(nhd);
+    if (std::fabs(nHd - p.nH) > 1e-9 * nHd || std::fabs(nhd - p.nh) > 1e-9 * nhd || p.nH < 2)
+        throw Error(PASM_E_INVALID, "1/H and 1/h must be integers, 1/H >= 2");
+    if (p.nh % p.nH != 0) throw Error(PASM_E_INVALID, "1/h must be a multiple of 1/H");
+    int ratio = p.nh / p.nH;
+    p.L = 1;
+    while (ratio > 1) {
+        if (ratio & 1) throw Error(PASM_E_INVALID, "H/h must be a power of two");
+        ratio >>= 1;
+        ++p.L;
+    }
+    long NH = 1;
+    for (int a = 0; a < p.dim; ++a) NH *= (p.nH - 1);
+    if (NH > 20000) throw Error(PASM_E_INVALID, "coarse space too large for the dense coarse eigensolve");
+    p.NH = (int)NH;
+    if (k < 1 || k >= NH) throw Error(PASM_E_INVALID, "need 1 <= k < N_H (dimension of V_H)");
+    if (opt.vcycles < 1 || opt.nu_pre < 0 || opt.nu_post < 0 || opt.max_iter < 1 || !(opt.tol >= 0.0))
+        throw Error(PASM_E_INVALID, "bad cycle options");
+    if (opt.precision != PASM_FP64 && opt.precision != PASM_MIXED) throw Error(PASM_E_INVALID, "bad precision");
+    if (opt.smoother != PASM_JACOBI && opt.smoother != PASM_CHEBYSHEV) throw Error(PASM_E_INVALID, "bad smoother");
+    p.have_kappa = coef && coef->kappa;
+    if (coef && coef->potential) throw Error(PASM_E_INVALID, "potential term not supported by this build");
+    p.nel = 1;
+    for (int a = 0; a < p.dim; ++a) p.nel *= (size_t)p.nh;
+    p.nel *= (p.dim == 2 ? 2 : 6);
+    if (p.have_kappa) {
+        if (p.dim != 2) throw Error(PASM_E_INVALID, "variable kappa is supported in 2D");
+        if (coef->n_elements != p.nel) throw Error(PASM_E_INVALID, "n_elements does not match the fine mesh");
+        for (size_t e = 0; e < p.nel; ++e)
+            if (!(coef->kappa[e] > 0.0) || !std::isfinite(coef->kappa[e]))
+                throw Error(PASM_E_INVALID, "kappa must be finite and positive");
+    }
+    return p;
+}
+
+void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
+    const int dim = pl.dim, nH = pl.nH, L = pl.L;
+    const bool have_kappa = pl.have_kappa;
+    const size_t nel = pl.nel;
+    c->dim = dim;
+    c->k = k;
+    c->L = L;
+    c->NH = pl.NH;
+    c->mixed = (c->opt.precision == PASM_MIXED);
+    const double omega = c->opt.omega > 0 ? c->opt.omega : (dim == 2 ? 0.8 : 6.0 / 7.0);
+    const double alpha = c->opt.cheb_alpha > 0 ? c->opt.cheb_alpha : (dim == 2 ? 4.0 : 6.0);
+
+    // levels, coarse (0) to fine (L-1)
+    c->lv.resize(L);
+    std::vector<double> kap;
+    if (have_kappa) kap.assign(coef->kappa, coef->kappa + nel);
+    for (int l = L - 1; l >= 0; --l) {
+        pasm::Level& Lv = c->lv[l];
+        const int n = nH << l;
+        Lv.g = pasm::make_grid(dim, n);
+        Lv.const_coef = !have_kappa;
+        Lv.w0 = (dim == 2) ? 1.0 : Lv.g.h;
+        if (have_kappa) {
+            std::vector<double> wx, wy;
+            pasm::edge_weights_2d(Lv.g, kap, wx, wy);
+            // stiffness rows sum to zero, so the Gershgorin bound of D^{-1}A is 2
+            Lv.rho = 2.0;
+            for (int a = 0; a < 2; ++a) {
+                const std::vector<double>& w = a == 0 ? wx : wy;
+                Lv.w64[a] = c->alloc<double>(Lv.g.plane);
+                PASM_HIP(hipMemcpyAsync(Lv.w64[a], w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+                PASM_HIP(hipStreamSynchronize(c->st));
+                if (c->mixed) {
+                    Lv.w32[a] = c->alloc<float>(Lv.g.plane);
+                    hipLaunchKernelGGL(pasm::k_d2f, dim3(1024), dim3(256), 0, c->st, Lv.w64[a], Lv.w32[a], Lv.g.plane);
+                }
+            }
+            if (l > 0) kap = pasm::coarsen_kappa_2d(kap, n);
+        } else {
+            Lv.rho = 2.0;  // constant coefficients: zero row sums, D^{-1}A Gershgorin bound 2
+        }
+        if (c->opt.smoother == PASM_CHEBYSHEV) {
+            Lv.pre = pasm::cheb_steps(Lv.rho, alpha, c->opt.nu_pre);
+            Lv.post = pasm::cheb_steps(Lv.rho, alpha, c->opt.nu_post);
+        } else if (c->opt.smoother == PASM_JACOBI) {
+            Lv.pre = pasm::jacobi_steps(omega, c->opt.nu_pre);
+            Lv.post = pasm::jacobi_steps(omega, c->opt.nu_post);
+        } else {
+            throw Error(PASM_E_INVALID, "unknown smoother");
+        }
+    }
+
+    // vectors
+    for (int l = 0; l < L - 1; ++l) {
+        pasm::Level& Lv = c->lv[l];
+        const size_t n = (size_t)Lv.g.plane * k;
+        if (c->mixed) {
+            Lv.X = c->alloc<float>(n);
+            Lv.F = c->alloc<float>(n);
+            Lv.Y = c->alloc<float>(n);
+        } else {
+            Lv.X = c->alloc<double>(n);
+            Lv.F = c->alloc<double>(n);
+            Lv.Y = c->alloc<double>(n);
+        }
+        Lv.B = c->alloc<double>(n);
+        Lv.C = c->alloc<double>(n);
+    }
+    const size_t nf = (size_t)c->sf() * k;
+    c->U = c->alloc<double>(nf);
+    c->F64 = c->alloc<double>(nf);
+    c->Y64 = c->alloc<double>(nf);
+    c->R64 = c->alloc<double>(nf);
+    if (c->mixed) {
+        c->E32 = c->alloc<float>(nf);
+        c->R32 = c->alloc<float>(nf);
+        c->Y32 = c->alloc<float>(nf);
+    }
+    const int N = c->NH;
+    c->theta = c->alloc<double>(N);
+    c->Qcm = c->alloc<double>((size_t)N * N);
+    c->Qrm = c->alloc<double>((size_t)N * N);
+    c->Ainv64 = c->alloc<double>((size_t)N * N);
+    if (c->mixed) c->Ainv32 = c->alloc<float>((size_t)N * N);
+    c->group = c->alloc<int>(N);
+    c->bz = c->alloc<double>(2 * (size_t)k);
+    const Grid& gfine = c->gf();
+    const long nblk = (dim == 2) ? (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4)
+                                 : (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4) * gfine.m;
+    c->partial = c->alloc<double>(2 * (size_t)nblk * k);
+    c->pp = c->alloc<double>((size_t)N * k);
+    c->qq = c->alloc<double>((size_t)N * k);
+    c->ycoef = c->alloc<double>((size_t)N * k);
+    c->s = c->alloc<double>(k);
+    c->mu = c->alloc<double>(k);
+    c->lam = c->alloc<double>(k);
+    c->lam_prev = c->alloc<double>(k);
+    c->score = c->alloc<double>(k);
+    c->rank = c->alloc<int>(k);
+    c->flags = c->alloc<int>(k);
+    c->awork = c->alloc<char>(pasm::arrow_workspace_bytes(N, k));
+
+    // dense coarse pencil from the level-0 operators (Galerkin: rediscretised
+    // with the coarsened coefficient)
+    const pasm::Level& L0 = c->lv[0];
+    const Grid& g0 = L0.g;
+    std::vector<double> wx0, wy0;
+    if (!L0.const_coef) {
+        wx0.resize(g0.plane);
+        wy0.resize(g0.plane);
+        PASM_HIP(hipMemcpyAsync(wx0.data(), L0.w64[0], g0.plane * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipMemcpyAsync(wy0.data(), L0.w64[1], g0.plane * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+    }
+    std::vector<double> AH((size_t)N * N, 0.0), MH((size_t)N * N, 0.0);
+    const int m = g0.m;
+    auto cid = [&](int i, int j, int l3) -> long {
+        if (i < 1 || j < 1 || i > m || j > m) return -1;
+        if (dim == 3 && (l3 < 1 || l3 > m)) return -1;
+        return dim == 2 ? (long)(j - 1) * m + (i - 1) : ((long)(l3 - 1) * m + (j - 1)) * m + (i - 1);
+    };
+    const int nz = dim == 3 ? m : 1;
+    for (int l3 = 1; l3 <= nz; ++l3)
+        for (int j = 1; j <= m; ++j)
+            for (int i = 1; i <= m; ++i) {
+                const int zz = dim == 3 ? l3 : 0;
+                const long r = cid(i, j, zz);
+                if (dim == 2) {
+                    const long id = g0.idx(i, j);
+                    double we, ww, wn, ws;
+                    if (L0.const_coef) we = ww = wn = ws = L0.w0;
+                    else {
+                        we = wx0[id];
+                        ww = wx0[id - 1];
+                        wn = wy0[id];
+                        ws = wy0[id - g0.pitch];
+                    }
+                    AH[r * N + r] = we + ww + wn + ws;
+                    const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+                    const double wv[4] = {we, ww, wn, ws};
+                    for (int t = 0; t < 4; ++t) {
+                        const long q = cid(i + nb[t][0], j + nb[t][1], 0);
+                        if (q >= 0) AH[q * N + r] = -wv[t];
+                    }
+                    const double H2 = g0.h * g0.h;
+                    MH[r * N + r] = 0.5 * H2;
+                    const int mb[6][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}};
+                    for (int t = 0; t < 6; ++t) {
+                        const long q = cid(i + mb[t][0], j + mb[t][1], 0);
+                        if (q >= 0) MH[q * N + r] = H2 / 12.0;
+                    }
+                } else {
+                    const double w = L0.w0, H3 = g0.h * g0.h * g0.h;
+                    AH[r * N + r] = 6.0 * w;
+                    MH[r * N + r] = 0.4 * H3;
+                    for (int o = 1; o < 8; ++o) {
+                        const int dx = o & 1, dy = (o >> 1) & 1, dz = (o >> 2) & 1;
+                        const int s = dx + dy + dz;
+                        const double mv = (s == 2) ? H3 / 30.0 : H3 / 20.0;
+                        for (int sg = -1; sg <= 1; sg += 2) {
+                            const long q = cid(i + sg * dx, j + sg * dy, l3 + sg * dz);
+                            if (q < 0) continue;
+                            MH[q * N + r] = mv;
+                            if (s == 1) AH[q * N + r] = -w;
+                        }
+                    }
+                }
+            }
+    double* dA = c->Qcm;
+    double* dB = c->Ainv64;  // scratch for M_H during the factorisation
+    PASM_HIP(hipMemcpyAsync(dA, AH.data(), AH.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    PASM_HIP(hipMemcpyAsync(dB, MH.data(), MH.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success)
+        throw Error(PASM_E_DEVICE, "rocblas_create_handle failed");
+    rocblas_set_stream(c->blas, c->st);
+    double* dE = c->alloc<double>(N);
+    int* dInfo = c->alloc<int>(1);
+    if (rocsolver_dsygvd(c->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, N, dA, N, dB, N,
+                         c->theta, dE, dInfo) != rocblas_status_success)
+        throw Error(PASM_E_DEVICE, "rocsolver_dsygvd failed");
+    int info = 0;
+    PASM_HIP(hipMemcpyAsync(&info, dInfo, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    std::vector<double> th(N);
+    PASM_HIP(hipMemcpyAsync(th.data(), c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    PASM_HIP(hipStreamSynchronize(c->st));
+    if (info != 0) throw Error(PASM_E_DEVICE, "coarse generalized eigensolve did not converge");
+    // Q^T (row-major Q) and A_H^{-1} = Q diag(1/theta) Q^T
+    hipLaunchKernelGGL(pasm::k_transpose, dim3((N + 15) / 16, (N + 15) / 16), dim3(16, 16), 0, c->st, c->Qcm, c->Qrm, N);
+    double* QS = dB;
+    hipLaunchKernelGGL(pasm::k_scale_cols, dim3((N + 255) / 256, N), dim3(256), 0, c->st, c->Qcm, c->theta, QS, N);
+    double* Ainv = c->alloc<double>((size_t)N * N);
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, N, N, N, &one, QS, N, c->Qcm, N,
+                      &zero, Ainv, N) != rocblas_status_success)
+        throw Error(PASM_E_DEVICE, "rocblas_dgemm failed");
+    c->Ainv64 = Ainv;
+    if (c->mixed)
+        hipLaunchKernelGGL(pasm::k_d2f, dim3(1024), dim3(256), 0, c->st, c->Ainv64, c->Ainv32, (long)N * N);
+    // groups of equal coarse Ritz values
+    std::vector<int> grp(N);
+    const double gtol = 16.0 * DBL_EPSILON * std::fabs(th[N - 1]);
+    for (int j = 0; j < N; ++j) grp[j] = (j > 0 && th[j] - th[j - 1] <= gtol) ? grp[j - 1] : j;
+    PASM_HIP(hipMemcpyAsync(c->group, grp.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
+
+    // start: lambda_i = theta_i, u_i = P q_i
+    c->lam_h.assign(th.begin(), th.begin() + k);
+    c->lam_prev_h = c->lam_h;
+    PASM_HIP(hipMemcpyAsync(c->lam, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    PASM_HIP(hipMemcpyAsync(c->lam_prev, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    hipLaunchKernelGGL(pasm::k_unit_coefs, dim3((N + 255) / 256, k), dim3(256), 0, c->st, c->ycoef, N, k);
+    PASM_CHECK_LAUNCH();
+    PASM_HIP(hipStreamSynchronize(c->st));
+}
+
+// u = P Q y' + s u  (s = nullptr: u = P Q y')
+void prolong_coefs(pasm_ctx* c, const double* s) {
+    const int k = c->k, N = c->NH;
+    const pasm::Level& L0 = c->lv[0];
+    if (c->L == 1) {
+        // the fine level is V_H itself: the augmentation is always skipped (s = 0)
+        pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->U, L0.g.plane, true, k, c->st);
+        return;
+    }
+    pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->lv[0].B, L0.g.plane, true, k, c->st);
+    for (int l = 1; l < c->L - 1; ++l)
+        pasm::launch_prolong<double>(c->lv[l - 1].g, c->lv[l - 1].B, c->lv[l].g, c->lv[l].B, k, c->lv[l - 1].g.plane,
+                                     c->lv[l].g.plane, false, nullptr, c->st);
+    const pasm::Level& Lc = c->lv[c->L - 2];
+    pasm::launch_prolong<double>(Lc.g, Lc.B, c->gf(), c->U, k, Lc.g.plane, c->sf(), false, s, c->st);
+}
+
+void iterate_once(pasm_ctx* c) {
+    const int k = c->k, N = c->NH, lf = c->L - 1;
+    const Grid& g = c->gf();
+    const long sf = c->sf();
+    // Algorithm 1, step 1: f = lambda M u, V-cycles from x = u (in place in U)
+    pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, sf, c->st);
+    if (c->L > 1) {
+        bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles);
+    } else {
+        // fine level = V_H: exact solve
+        pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->st);
+    }
+    // step 2: borders
+    const int nblk = pasm::launch_border(g, c->coef<double>(lf), c->U, c->Y64, c->R64, c->partial, k, sf, c->st);
+    pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
+    const double* bsrc = c->Y64;
+    const double* csrc = c->R64;
+    for (int l = c->L - 2; l >= 0; --l) {
+        const Grid& gfl = c->lv[l + 1].g;
+        pasm::launch_restrict<double>(gfl, bsrc, c->lv[l].g, c->lv[l].B, k, gfl.plane, c->lv[l].g.plane, c->st);
+        pasm::launch_restrict<double>(gfl, csrc, c->lv[l].g, c->lv[l].C, k, gfl.plane, c->lv[l].g.plane, c->st);
+        bsrc = c->lv[l].B;
+        csrc = c->lv[l].C;
+    }
+    const Grid& g0 = c->lv[0].g;
+    pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, k, c->st);
+    pasm::launch_dense_mv<double>(c->Qrm, N, g0, csrc, g0.plane, true, c->qq, N, false, k, c->st);
+    pasm::ArrowIn in{c->theta, c->group, c->pp, c->qq, c->bz, c->lam, N};
+    pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
+    pasm::launch_arrowhead(in, out, k, c->st);
+    prolong_coefs(c, c->s);
+    hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->lam, c->lam_prev, k);
+    hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->mu, c->lam, k);
+    PASM_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define PASM_TRY(ctx, ...)                                         \
+    try {                                                          \
+        __VA_ARGS__;                                               \
+    } catch (const Error& e_) {                                    \
+        set_error(ctx, e_.msg);                                    \
+        return e_.status;                                          \
+    } catch (const std::exception& e_) {                           \
+        set_error(ctx, e_.what());                                 \
+        return PASM_E_DEVICE;                                      \
+    }
+
+extern "C" {
+
+PASM_API void pasm_default_options(pasm_options* o) {
+    if (!o) return;
+    o->precision = PASM_FP64;
+    o->smoother = PASM_JACOBI;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->vcycles = 2;
+    o->max_iter = 50;
+    o->tol = 1e-10;
+    o->omega = 0.0;
+    o->cheb_alpha = 0.0;
+    o->stream = nullptr;
+}
+
+PASM_API pasm_status pasm_destroy(pasm_ctx* c) {
+    if (!c) return PASM_OK;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    for (void* p : c->allocs) (void)hipFree(p);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->blas) rocblas_destroy_handle(c->blas);
+    if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
+    delete c;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_setup(pasm_ctx** out, const pasm_domain* dom, const pasm_coefficients* coef, double H,
+                                double h, int k, const pasm_options* opt) {
+    if (!out) return PASM_E_INVALID;
+    *out = nullptr;
+    pasm_ctx* c = new (std::nothrow) pasm_ctx();
+    if (!c) return PASM_E_NOMEM;
+    if (opt) c->opt = *opt;
+    else pasm_default_options(&c->opt);
+    try {
+        const Plan pl = validate(c->opt, dom, coef, H, h, k);
+        if (c->opt.stream) c->st = static_cast<hipStream_t>(c->opt.stream);
+        else {
+            PASM_HIP(hipStreamCreate(&c->st));
+            c->own_stream = true;
+        }
+        build(c, pl, coef, k);
+        prolong_coefs(c, nullptr);
+        PASM_HIP(hipStreamSynchronize(c->st));
+    } catch (const Error& e) {
+        g_setup_error = e.msg;
+        pasm_destroy(c);
+        return e.status;
+    } catch (const std::exception& e) {
+        g_setup_error = e.what();
+        pasm_destroy(c);
+        return PASM_E_DEVICE;
+    }
+    *out = c;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    PASM_TRY(c, {
+        iterate_once(c);
+        c->lam_prev_h = c->lam_h;
+        PASM_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+        collect_profile(c);
+        ++c->iters;
+        double dmax = 0.0;
+        bool finite = true;
+        for (int i = 0; i < c->k; ++i) {
+            const double l = c->lam_h[i];
+            if (!std::isfinite(l)) finite = false;
+            dmax = std::max(dmax, std::fabs(l - c->lam_prev_h[i]) / std::fabs(l));
+        }
+        if (!finite) {
+            set_error(c, "non-finite eigenvalue");
+            return PASM_E_BREAKDOWN;
+        }
+        if (converged) *converged = dmax < c->opt.tol ? 1 : 0;
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_restart(pasm_ctx* c) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    PASM_TRY(c, {
+        const int k = c->k, N = c->NH;
+        std::vector<double> th(k);
+        PASM_HIP(hipMemcpyAsync(th.data(), c->theta, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+        c->lam_h = th;
+        c->lam_prev_h = th;
+        hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->theta, c->lam, k);
+        hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->theta, c->lam_prev, k);
+        hipLaunchKernelGGL(pasm::k_unit_coefs, dim3((N + 255) / 256, k), dim3(256), 0, c->st, c->ycoef, N, k);
+        PASM_CHECK_LAUNCH();
+        prolong_coefs(c, nullptr);
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_solve(pasm_ctx* c, int* iterations) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    int it = 0, conv = 0;
+    while (it < c->opt.max_iter) {
+        pasm_status s = pasm_iterate(c, &conv);
+        ++it;
+        if (s != PASM_OK) {
+            if (iterations) *iterations = it;
+            return s;
+        }
+        if (conv) break;
+    }
+    if (iterations) *iterations = it;
+    return conv ? PASM_OK : PASM_E_NOTCONV;
+}
+
+PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* cc, double* lambda, double* U, size_t ldu) {
+    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    if (!c || c->k == 0) return PASM_E_STATE;
+    const size_t N = pasm_num_dofs(c);
+    if (U && ldu < N) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        if (lambda) std::memcpy(lambda, c->lam_h.data(), c->k * sizeof(double));
+        if (U) {
+            pasm::launch_pack<double>(c->gf(), c->U, c->sf(), c->Y64, (long)N, c->k, c->st);
+            PASM_HIP(hipMemcpy2DAsync(U, ldu * sizeof(double), c->Y64, N * sizeof(double), N * sizeof(double), c->k,
+                                      hipMemcpyDeviceToHost, c->st));
+            PASM_HIP(hipStreamSynchronize(c->st));
+        }
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* cc, double* U_dev, size_t ldu) {
+    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    if (!c || c->k == 0) return PASM_E_STATE;
+    if (!U_dev || ldu < pasm_num_dofs(c)) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        pasm::launch_pack<double>(c->gf(), c->U, c->sf(), U_dev, (long)ldu, c->k, c->st);
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const double* U, size_t ldu) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    const size_t N = pasm_num_dofs(c);
+    if (!lambda || !U || ldu < N) return PASM_E_INVALID;
+    for (int i = 0; i < c->k; ++i)
+        if (!std::isfinite(lambda[i])) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        c->lam_h.assign(lambda, lambda + c->k);
+        c->lam_prev_h = c->lam_h;
+        PASM_HIP(hipMemcpyAsync(c->lam, lambda, c->k * sizeof(double), hipMemcpyHostToDevice, c->st));
+        PASM_HIP(hipMemcpyAsync(c->lam_prev, lambda, c->k * sizeof(double), hipMemcpyHostToDevice, c->st));
+        PASM_HIP(hipMemcpy2DAsync(c->Y64, N * sizeof(double), U, ldu * sizeof(double), N * sizeof(double), c->k,
+                                  hipMemcpyHostToDevice, c->st));
+        pasm::launch_unpack<double>(c->gf(), c->Y64, (long)N, c->U, c->sf(), c->k, c->st);
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_last_selection(const pasm_ctx* cc, int* rank, double* score, int* flags) {
+    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    if (!c || c->k == 0) return PASM_E_STATE;
+    PASM_TRY(c, {
+        if (rank) PASM_HIP(hipMemcpyAsync(rank, c->rank, c->k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+        if (score) PASM_HIP(hipMemcpyAsync(score, c->score, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        if (flags) PASM_HIP(hipMemcpyAsync(flags, c->flags, c->k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API size_t pasm_num_dofs(const pasm_ctx* c) { return (c && c->L) ? (size_t)c->gf().interior() : 0; }
+PASM_API size_t pasm_coarse_dofs(const pasm_ctx* c) { return c ? (size_t)c->NH : 0; }
+PASM_API int pasm_num_levels(const pasm_ctx* c) { return c ? c->L : 0; }
+
+PASM_API const char* pasm_status_string(pasm_status s) {
+    switch (s) {
+        case PASM_OK: return "ok";
+        case PASM_E_INVALID: return "invalid argument";
+        case PASM_E_NOMEM: return "out of memory";
+        case PASM_E_DEVICE: return "device error";
+        case PASM_E_STATE: return "invalid call order";
+        case PASM_E_NOTCONV: return "not converged";
+        case PASM_E_BREAKDOWN: return "breakdown (non-finite values)";
+    }
+    return "unknown status";
+}
+
+PASM_API const char* pasm_last_error(const pasm_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const double* x, double* y, size_t ld,
+                                         int nrhs) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    if (level < 0 || level >= c->L || nrhs < 1 || nrhs > c->k || !x || !y) return PASM_E_INVALID;
+    if (op != PASM_OP_STIFFNESS && op != PASM_OP_MASS) return PASM_E_INVALID;
+    if (op == PASM_OP_MASS && level != c->L - 1) return PASM_E_INVALID;
+    const Grid& g = c->lv[level].g;
+    if (ld < (size_t)g.interior()) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        const bool fine = level == c->L - 1;
+        double* tin = fine ? c->Y64 : c->lv[level].B;
+        double* tout = fine ? c->R64 : c->lv[level].C;
+        pasm::launch_unpack<double>(g, x, (long)ld, tin, g.plane, nrhs, c->st);
+        if (op == PASM_OP_MASS) pasm::launch_apply_M(g, tin, tout, nrhs, g.plane, c->st);
+        else pasm::launch_apply_A<double>(g, c->coef<double>(level), tin, tout, nrhs, g.plane, c->st);
+        pasm::launch_pack<double>(g, tout, g.plane, y, (long)ld, nrhs, c->st);
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t ld, int nrhs, int ncycles) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    const Grid& g = c->gf();
+    if (!f || !x || nrhs < 1 || nrhs > c->k || ncycles < 0 || ld < (size_t)g.interior()) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        pasm::launch_unpack<double>(g, f, (long)ld, c->F64, g.plane, nrhs, c->st);
+        pasm::launch_unpack<double>(g, x, (long)ld, c->R64, g.plane, nrhs, c->st);
+        double* xb = c->R64;
+        double* yb = c->Y64;
+        if (c->L > 1) bvp_cycles(c, xb, yb, c->F64, nrhs, ncycles);
+        else if (ncycles > 0)
+            pasm::launch_dense_mv<double>(c->Ainv64, c->NH, g, c->F64, g.plane, true, xb, g.plane, true, nrhs, c->st);
+        pasm::launch_pack<double>(g, xb, g.plane, x, (long)ld, nrhs, c->st);
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_profile(pasm_ctx* c, int kernel, int enable) {
+    if (!c) return PASM_E_STATE;
+    if (kernel != 0) return PASM_E_INVALID;
+    c->prof = enable != 0;
+    c->prof_launches = 0;
+    c->prof_ms = 0.0;
+    c->prof_bytes = 0.0;
+    c->ev_used = 0;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_profile_read(pasm_ctx* c, int kernel, long* launches, double* total_ms,
+                                       double* bytes_per_launch) {
+    if (!c) return PASM_E_STATE;
+    if (kernel != 0) return PASM_E_INVALID;
+    if (launches) *launches = c->prof_launches;
+    if (total_ms) *total_ms = c->prof_ms;
+    if (bytes_per_launch) *bytes_per_launch = c->prof_launches ? c->prof_bytes / c->prof_launches : 0.0;
+    return PASM_OK;
+}
+
+}  // extern "C"

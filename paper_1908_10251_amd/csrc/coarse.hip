@@ -1,0 +1,552 @@
+// Coarse-space work of Algorithm 1, step 2: the (N_H+1)-dimensional
+// generalized eigenproblem of Section 3.1 (matrix form)
+//
+//     [[A_H, b], [b^T, beta]] z = mu [[M_H, c], [c^T, zeta]] z
+//
+// and the choice of the eigenvector with the largest component along u~.
+//
+// The coarse pencil is factored once, A_H Q = M_H Q Theta with Q^T M_H Q = I.
+// In the basis [Q, w], w = (u~ - P Q q) / sqrt(zeta_perp), q = Q^T c,
+// zeta_perp = zeta - q.q (w is u~ made M-orthogonal to V_H and normalised),
+// the augmented mass becomes the identity and the augmented stiffness becomes
+// the symmetric arrowhead matrix
+//
+//     [[Theta, g], [g^T, rho]],  g = (p - Theta q) / sqrt(zeta_perp),
+//     rho = (beta - 2 q.p + q.Theta q) / zeta_perp,   p = Q^T b.
+//
+// Its eigenvalues are the roots of the secular equation
+//     f(mu) = rho - mu + sum_j g_j^2 / (mu - theta_j) = 0,
+// one in each gap between consecutive poles and one beyond each end; the
+// eigenvector is y_j = g_j t / (mu - theta_j) on Q and t on w, with
+// t^2 (1 + sum_j (g_j / (mu - theta_j))^2) = 1.  Its component along u~,
+// b(u_new, u~) = y.q + t sqrt(zeta_perp), is the selection score of the paper.
+//
+// Deflation: a group of equal theta (symmetry makes coarse spectra
+// degenerate) is rotated so that g has one component in the group; the rest
+// of the group is an eigenspace at theta with t = 0, and its best direction
+// for the score is the part of q orthogonal to g in the group.  A pole with
+// negligible g is itself an eigenvalue with t = 0.
+// If u~ lies in V_H (zeta_perp <= 1e-13 zeta) the augmentation is skipped and
+// the coarse Ritz pairs are scored instead.
+#include <cfloat>
+
+#include "common.h"
+
+namespace pasm {
+
+namespace {
+
+constexpr double EPS = DBL_EPSILON;
+constexpr double SKIP_RTOL = 1e-13;
+constexpr double TIE_RTOL = 1e-12;
+
+// ---------------------------------------------------------------------------
+// dense matrix times k vectors, y[r] = Mat x[r], Mat(row,col) at Mat[col*N+row]
+// ---------------------------------------------------------------------------
+constexpr int MV_THREADS = 256;
+constexpr int MV_RC = 8;     // right-hand sides per block
+constexpr int MV_CT = 256;   // columns per LDS tile
+
+__device__ inline long compact_to_padded(const Grid& g, int c) {
+    const int i = c % g.m + 1;
+    if (g.dim == 2) return g.idx(i, c / g.m + 1);
+    const int j = (c / g.m) % g.m + 1;
+    return g.idx(i, j, c / (g.m * g.m) + 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(MV_THREADS) void k_dense_mv(const T* __restrict__ Mat, int N, Grid g,
+                                                         const T* __restrict__ x, long sx, int xpad,
+                                                         T* __restrict__ y, long sy, int ypad, int nrhs) {
+    __shared__ T xs[MV_RC][MV_CT];
+    const int row = blockIdx.x * MV_THREADS + threadIdx.x;
+    const int r0 = blockIdx.y * MV_RC;
+    T acc[MV_RC];
+#pragma unroll
+    for (int rr = 0; rr < MV_RC; ++rr) acc[rr] = T(0);
+    for (int c0 = 0; c0 < N; c0 += MV_CT) {
+        const int cn = min(MV_CT, N - c0);
+        for (int t = threadIdx.x; t < MV_RC * MV_CT; t += MV_THREADS) {
+            const int rr = t / MV_CT, cc = t % MV_CT;
+            T v = T(0);
+            if (r0 + rr < nrhs && cc < cn) {
+                const long base = (long)(r0 + rr) * sx;
+                v = xpad ? x[base + compact_to_padded(g, c0 + cc)] : x[base + c0 + cc];
+            }
+            xs[rr][cc] = v;
+        }
+        __syncthreads();
+        if (row < N) {
+            for (int cc = 0; cc < cn; ++cc) {
+                const T a = Mat[(long)(c0 + cc) * N + row];
+#pragma unroll
+                for (int rr = 0; rr < MV_RC; ++rr) acc[rr] += a * xs[rr][cc];
+            }
+        }
+        __syncthreads();
+    }
+    if (row < N) {
+#pragma unroll
+        for (int rr = 0; rr < MV_RC; ++rr) {
+            if (r0 + rr >= nrhs) break;
+            const long base = (long)(r0 + rr) * sy;
+            if (ypad) y[base + compact_to_padded(g, row)] = acc[rr];
+            else y[base + row] = acc[rr];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// arrowhead workspace layout, per eigenpair (doubles)
+// ---------------------------------------------------------------------------
+struct WS {
+    double* g;       // N   g_j
+    double* d;       // N   active pole values (ascending)
+    double* z;       // N   active pole weights (signed for singletons, |g_G| for groups)
+    double* qa;      // N   component of q along the active direction
+    double* rmu;     // N+1 root values
+    double* rtau;    // N+1 root offsets from their origin pole
+    double* rorg;    // N+1 origin pole values
+    double* sc;      // 16 scalars, see below
+    int* amap;       // N   active index of j's group, -1 if deflated
+    double* best;    // [nchunk][4] per-block best root (score, mu, root, 0)
+};
+// scalar slots
+enum { S_RHO = 0, S_SQ, S_ZPERP, S_NA, S_LO, S_HI, S_SKIP, S_DSCORE, S_DMU, S_DLEAD, S_DTYPE, S_TOLZ };
+
+__host__ __device__ inline long ws_doubles(int N) { return 7L * N + 3 + 16; }
+
+__device__ inline WS ws_of(double* work, int* iwork, double* best, int N, int nchunk, int r) {
+    WS w;
+    double* b = work + (long)r * ws_doubles(N);
+    w.g = b;
+    w.d = b + N;
+    w.z = b + 2L * N;
+    w.qa = b + 3L * N;
+    w.rmu = b + 4L * N;
+    w.rtau = b + 5L * N + 1;
+    w.rorg = b + 6L * N + 2;
+    w.sc = b + 7L * N + 3;
+    w.amap = iwork + (long)r * N;
+    w.best = best + (long)r * nchunk * 4;
+    return w;
+}
+
+// candidate comparison: larger score; within TIE_RTOL the one nearer to the
+// previous eigenvalue, then the lower eigenvalue.
+__device__ inline bool better(double s1, double m1, double s2, double m2, double lp) {
+    if (s1 > s2 * (1.0 + TIE_RTOL)) return true;
+    if (s2 > s1 * (1.0 + TIE_RTOL)) return false;
+    const double d1 = fabs(m1 - lp), d2 = fabs(m2 - lp);
+    if (d1 != d2) return d1 < d2;
+    return m1 < m2;
+}
+
+constexpr int PT = 256;
+
+__device__ inline double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = sh[0] + sh[1] + sh[2] + sh[3];
+    return s;
+}
+
+__device__ inline double block_max(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// Stage A, one block per eigenpair: scalars, g, deflation, compaction of the
+// active poles, and the best deflated candidate.
+__global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int* iwork, double* best, int nchunk) {
+    __shared__ double sh[8];
+    __shared__ int cnt[PT];
+    __shared__ double bs[PT], bm[PT];
+    __shared__ int bl[PT], bt[PT];
+    const int r = blockIdx.x, N = in.N;
+    WS w = ws_of(work, iwork, best, N, nchunk, r);
+    const double* p = in.p + (long)r * N;
+    const double* q = in.q + (long)r * N;
+    const double beta = in.bz[2 * r], zeta = in.bz[2 * r + 1], lp = in.lam_prev[r];
+
+    double qq = 0, qp = 0, qtq = 0;
+    for (int j = threadIdx.x; j < N; j += PT) {
+        qq += q[j] * q[j];
+        qp += q[j] * p[j];
+        qtq += in.theta[j] * q[j] * q[j];
+    }
+    qq = block_sum(qq, sh);
+    qp = block_sum(qp, sh);
+    qtq = block_sum(qtq, sh);
+    const double zperp = zeta - qq;
+    const bool skip = !(zperp > SKIP_RTOL * zeta);
+    const double sq = skip ? 0.0 : sqrt(zperp);
+    const double rho = skip ? 0.0 : (beta - 2.0 * qp + qtq) / zperp;
+
+    double gmax = 0.0;
+    for (int j = threadIdx.x; j < N; j += PT) {
+        const double gj = skip ? 0.0 : (p[j] - in.theta[j] * q[j]) / sq;
+        w.g[j] = gj;
+        gmax = fmax(gmax, fabs(gj));
+    }
+    gmax = block_max(gmax, sh);
+    const double tolz = 8.0 * EPS * fmax(fmax(fabs(in.theta[N - 1]), fabs(rho)), gmax);
+    __syncthreads();
+
+    // contiguous chunk of indices per thread, so the compaction keeps order
+    const int per = (N + PT - 1) / PT;
+    const int j0 = threadIdx.x * per, j1 = min(N, j0 + per);
+    int mine = 0;
+    double ds = -1.0, dm = 0.0;
+    int dl = -1, dt = 0;
+    for (int j = j0; j < j1; ++j) {
+        if (in.group[j] != j) continue;  // not a group leader
+        int e = j + 1;
+        while (e < N && in.group[e] == j) ++e;
+        double gn2 = 0.0, q2 = 0.0, gq = 0.0;
+        for (int m = j; m < e; ++m) {
+            gn2 += w.g[m] * w.g[m];
+            q2 += q[m] * q[m];
+            gq += w.g[m] * q[m];
+        }
+        const double gn = sqrt(gn2);
+        double cs = -1.0;
+        int ct = 0;
+        if (skip || gn <= tolz) {
+            cs = sqrt(q2);
+            ct = 1;
+        } else {
+            ++mine;
+            if (e - j > 1) {
+                const double qg = gq / gn;
+                cs = sqrt(fmax(q2 - qg * qg, 0.0));
+                ct = 2;
+            }
+        }
+        if (ct && (dl < 0 || better(cs, in.theta[j], ds, dm, lp))) {
+            ds = cs;
+            dm = in.theta[j];
+            dl = j;
+            dt = ct;
+        }
+    }
+    cnt[threadIdx.x] = mine;
+    bs[threadIdx.x] = ds;
+    bm[threadIdx.x] = dm;
+    bl[threadIdx.x] = dl;
+    bt[threadIdx.x] = dt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < PT; ++t) {
+            const int c = cnt[t];
+            cnt[t] = acc;
+            acc += c;
+        }
+        int bi = -1;
+        for (int t = 0; t < PT; ++t) {
+            if (bl[t] < 0) continue;
+            if (bi < 0 || better(bs[t], bm[t], bs[bi], bm[bi], lp)) bi = t;
+        }
+        w.sc[S_NA] = skip ? -1.0 : (double)acc;
+        w.sc[S_RHO] = rho;
+        w.sc[S_SQ] = sq;
+        w.sc[S_ZPERP] = zperp;
+        w.sc[S_SKIP] = skip ? 1.0 : 0.0;
+        w.sc[S_TOLZ] = tolz;
+        w.sc[S_DSCORE] = bi < 0 ? -1.0 : bs[bi];
+        w.sc[S_DMU] = bi < 0 ? 0.0 : bm[bi];
+        w.sc[S_DLEAD] = bi < 0 ? -1.0 : (double)bl[bi];
+        w.sc[S_DTYPE] = bi < 0 ? 0.0 : (double)bt[bi];
+    }
+    __syncthreads();
+    // write active poles in order
+    int a = cnt[threadIdx.x];
+    for (int j = j0; j < j1; ++j) {
+        if (in.group[j] != j) continue;
+        int e = j + 1;
+        while (e < N && in.group[e] == j) ++e;
+        double gn2 = 0.0, gq = 0.0;
+        for (int m = j; m < e; ++m) {
+            gn2 += w.g[m] * w.g[m];
+            gq += w.g[m] * q[m];
+        }
+        const double gn = sqrt(gn2);
+        const bool act = !skip && gn > tolz;
+        for (int m = j; m < e; ++m) w.amap[m] = act ? a : -1;
+        if (act) {
+            w.d[a] = in.theta[j];
+            if (e - j == 1) {
+                w.z[a] = w.g[j];
+                w.qa[a] = q[j];
+            } else {
+                w.z[a] = gn;
+                w.qa[a] = gq / gn;
+            }
+            ++a;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double zn2 = 0.0;
+        const int nact = skip ? 0 : (int)w.sc[S_NA];
+        for (int t = 0; t < nact; ++t) zn2 += w.z[t] * w.z[t];
+        const double zn = sqrt(zn2);
+        if (nact > 0) {
+            w.sc[S_LO] = fmin(w.d[0], rho) - zn - 1e-300;
+            w.sc[S_HI] = fmax(w.d[nact - 1], rho) + zn + 1e-300;
+        }
+    }
+}
+
+// Stage B: one thread per root of the secular equation.
+constexpr int RT = 64;
+
+__global__ __launch_bounds__(RT) void k_arrow_roots(ArrowIn in, double* work, int* iwork, double* best, int nchunk) {
+    __shared__ double ss[RT], sm[RT], sr[RT];
+    const int r = blockIdx.x, N = in.N;
+    WS w = ws_of(work, iwork, best, N, nchunk, r);
+    const int na = (int)w.sc[S_NA];
+    const double rho = w.sc[S_RHO], sq = w.sc[S_SQ], lp = in.lam_prev[r];
+    const int root = blockIdx.y * RT + threadIdx.x;
+    double score = -1.0, mu = 0.0;
+    if (na >= 0 && root <= na) {
+        if (na == 0) {
+            mu = rho;
+            score = sq;
+            w.rmu[0] = rho;
+            w.rtau[0] = 0.0;
+            w.rorg[0] = rho;
+        } else {
+            const double* d = w.d;
+            const double* z = w.z;
+            const double left = root == 0 ? w.sc[S_LO] : d[root - 1];
+            const double right = root == na ? w.sc[S_HI] : d[root];
+            double org;
+            if (root == 0) org = d[0];
+            else if (root == na) org = d[na - 1];
+            else {
+                const double mid = 0.5 * (left + right);
+                double fm = rho - mid;
+                for (int a = 0; a < na; ++a) fm += z[a] * z[a] / (mid - d[a]);
+                org = fm > 0.0 ? right : left;
+            }
+            double lo = left - org, hi = right - org;
+            const double c0 = rho - org;
+            double tau = 0.5 * (lo + hi);
+            for (int it = 0; it < 200; ++it) {
+                double F = c0 - tau, dF = -1.0, mag = fabs(c0) + fabs(tau);
+                for (int a = 0; a < na; ++a) {
+                    const double inv = 1.0 / (tau - (d[a] - org));
+                    const double t1 = z[a] * inv;
+                    F += z[a] * t1;
+                    dF -= t1 * t1;
+                    mag += fabs(z[a] * t1);
+                }
+                if (F == 0.0) break;
+                if (F > 0.0) lo = tau;
+                else hi = tau;
+                if (fabs(F) <= 4.0 * EPS * mag) break;
+                double tn = tau - F / dF;
+                if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+                const double step = fabs(tn - tau);
+                tau = tn;
+                if (step <= 2.0 * EPS * fabs(tau) || hi - lo <= 4.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+            }
+            double S1 = 0.0, S2 = 0.0;
+            for (int a = 0; a < na; ++a) {
+                const double v = z[a] / (tau - (d[a] - org));
+                S1 += v * v;
+                S2 += v * w.qa[a];
+            }
+            const double t = 1.0 / sqrt(1.0 + S1);
+            score = fabs(t * (S2 + sq));
+            mu = org + tau;
+            w.rmu[root] = mu;
+            w.rtau[root] = tau;
+            w.rorg[root] = org;
+        }
+    }
+    ss[threadIdx.x] = score;
+    sm[threadIdx.x] = mu;
+    sr[threadIdx.x] = (double)root;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int bi = -1;
+        for (int t = 0; t < RT; ++t) {
+            if (ss[t] < 0.0) continue;
+            if (bi < 0 || better(ss[t], sm[t], ss[bi], sm[bi], lp)) bi = t;
+        }
+        double* b = w.best + 4L * blockIdx.y;
+        b[0] = bi < 0 ? -1.0 : ss[bi];
+        b[1] = bi < 0 ? 0.0 : sm[bi];
+        b[2] = bi < 0 ? -1.0 : sr[bi];
+        b[3] = 0.0;
+    }
+}
+
+// Stage C, one block per eigenpair: final choice, rank, new coefficients.
+__global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, double* work, int* iwork, double* best,
+                                                    int nchunk) {
+    __shared__ double sh[8];
+    __shared__ double win[4];  // score, mu, kind (0 root, 1 deflated), id
+    __shared__ int rk;
+    const int r = blockIdx.x, N = in.N;
+    WS w = ws_of(work, iwork, best, N, nchunk, r);
+    const double* q = in.q + (long)r * N;
+    const double lp = in.lam_prev[r];
+    const int na = (int)w.sc[S_NA];
+    const double sq = w.sc[S_SQ];
+    if (threadIdx.x == 0) {
+        double bsc = -1.0, bmu = 0.0, kind = 0.0, id = -1.0;
+        if (na >= 0) {
+            for (int c = 0; c < nchunk; ++c) {
+                const double* b = w.best + 4L * c;
+                if (b[0] < 0.0) continue;
+                if (id < 0.0 || better(b[0], b[1], bsc, bmu, lp)) {
+                    bsc = b[0];
+                    bmu = b[1];
+                    kind = 0.0;
+                    id = b[2];
+                }
+            }
+        }
+        const double ds = w.sc[S_DSCORE];
+        if (ds >= 0.0 && (id < 0.0 || better(ds, w.sc[S_DMU], bsc, bmu, lp))) {
+            bsc = ds;
+            bmu = w.sc[S_DMU];
+            kind = 1.0;
+            id = w.sc[S_DLEAD];
+        }
+        win[0] = bsc;
+        win[1] = bmu;
+        win[2] = kind;
+        win[3] = id;
+        rk = 0;
+    }
+    __syncthreads();
+    const double mu = win[1];
+    const bool is_root = win[2] == 0.0;
+    const int id = (int)win[3];
+
+    // rank: augmented eigenvalues strictly below mu (roots, then deflated
+    // eigenvalues with their multiplicities)
+    int cntb = 0;
+    if (na >= 0) {
+        const int nroots = na == 0 ? 1 : na + 1;
+        for (int t = threadIdx.x; t < nroots; t += PT)
+            if (is_root ? t < id : w.rmu[t] < mu) ++cntb;
+    }
+    for (int j = threadIdx.x; j < N; j += PT) {
+        if (in.group[j] != j || in.theta[j] >= mu) continue;
+        int e = j + 1;
+        while (e < N && in.group[e] == j) ++e;
+        if (w.amap[j] < 0) cntb += e - j;
+        else cntb += e - j - 1;
+    }
+    atomicAdd(&rk, cntb);
+
+    // eigenvector coefficients in the Q basis, and t
+    double t = 0.0;
+    double* y = out.ycoef + (long)r * N;
+    if (is_root) {
+        if (na == 0) {
+            t = 1.0;
+            for (int j = threadIdx.x; j < N; j += PT) y[j] = 0.0;
+        } else {
+            const double tau = w.rtau[id], org = w.rorg[id];
+            double s1 = 0.0;
+            for (int a = threadIdx.x; a < na; a += PT) {
+                const double v = w.z[a] / (tau - (w.d[a] - org));
+                s1 += v * v;
+            }
+            s1 = block_sum(s1, sh);
+            t = 1.0 / sqrt(1.0 + s1);
+            for (int j = threadIdx.x; j < N; j += PT) {
+                const int a = w.amap[j];
+                y[j] = a < 0 ? 0.0 : w.g[j] * t / (tau - (w.d[a] - org));
+            }
+        }
+    } else {
+        const int lead = id;
+        int e = lead + 1;
+        while (e < N && in.group[e] == lead) ++e;
+        const int type = (int)w.sc[S_DTYPE];
+        // direction in the group: q (type 1) or q minus its g component (type 2)
+        double gn2 = 0.0, gq = 0.0;
+        for (int m = lead; m < e; ++m) {
+            gn2 += w.g[m] * w.g[m];
+            gq += w.g[m] * q[m];
+        }
+        const double coef = (type == 2 && gn2 > 0.0) ? gq / gn2 : 0.0;
+        double nrm2 = 0.0;
+        for (int m = lead; m < e; ++m) {
+            const double v = q[m] - coef * w.g[m];
+            nrm2 += v * v;
+        }
+        const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+        for (int j = threadIdx.x; j < N; j += PT)
+            y[j] = (j >= lead && j < e) ? (q[j] - coef * w.g[j]) * inv : 0.0;
+    }
+    __syncthreads();
+    // signed score, then y' = y - (t / sq) q and s = t / sq
+    double ys = 0.0;
+    for (int j = threadIdx.x; j < N; j += PT) ys += y[j] * q[j];
+    ys = block_sum(ys, sh);
+    const double signed_score = ys + t * sq;
+    const double sgn = signed_score < 0.0 ? -1.0 : 1.0;
+    const double s = (sq > 0.0) ? t / sq : 0.0;
+    for (int j = threadIdx.x; j < N; j += PT) y[j] = sgn * (y[j] - s * q[j]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out.s[r] = sgn * s;
+        out.mu[r] = mu;
+        out.rank[r] = rk;
+        out.score[r] = fabs(signed_score);
+        out.flags[r] = (w.sc[S_SKIP] != 0.0 ? 1 : 0) | (is_root ? 0 : 2);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded, T* y, long sy,
+                     bool y_padded, int nrhs, hipStream_t st) {
+    dim3 grid((N + MV_THREADS - 1) / MV_THREADS, (nrhs + MV_RC - 1) / MV_RC);
+    hipLaunchKernelGGL((k_dense_mv<T>), grid, dim3(MV_THREADS), 0, st, Mat, N, g, x, sx, (int)x_padded, y, sy,
+                       (int)y_padded, nrhs);
+    PASM_CHECK_LAUNCH();
+}
+template void launch_dense_mv<double>(const double*, int, const Grid&, const double*, long, bool, double*, long,
+                                      bool, int, hipStream_t);
+template void launch_dense_mv<float>(const float*, int, const Grid&, const float*, long, bool, float*, long, bool,
+                                     int, hipStream_t);
+
+long arrow_work_doubles(int N, int k) { return ws_doubles(N) * (long)k; }
+int arrow_chunks(int N) { return (N + 1 + RT - 1) / RT; }
+
+void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t st) {
+    const int nchunk = arrow_chunks(in.N);
+    double* work = out.work;
+    int* iwork = reinterpret_cast<int*>(work + arrow_work_doubles(in.N, k));
+    double* best = reinterpret_cast<double*>(iwork + (long)in.N * k + ((long)in.N * k & 1));
+    hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PT), 0, st, in, work, iwork, best, nchunk);
+    PASM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_arrow_roots, dim3(k, nchunk), dim3(RT), 0, st, in, work, iwork, best, nchunk);
+    PASM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_arrow_final, dim3(k), dim3(PT), 0, st, in, out, work, iwork, best, nchunk);
+    PASM_CHECK_LAUNCH();
+}
+
+size_t arrow_workspace_bytes(int N, int k) {
+    const int nchunk = arrow_chunks(N);
+    return sizeof(double) * (size_t)arrow_work_doubles(N, k) + sizeof(int) * ((size_t)N * k + 2) +
+           sizeof(double) * 4 * (size_t)nchunk * k + 256;
+}
+
+}  // namespace pasm

@@ -1,0 +1,170 @@
+// Internal definitions shared by the HIP sources of the library.
+//
+// Storage of a level (one nested mesh of the hierarchy of Section 3): every
+// right-hand side is one block of `plane` elements holding ALL nodes of the
+// level, boundary included; boundary entries are kept at zero (homogeneous
+// Dirichlet data), so stencils need no boundary branches.  Node (i, j[, l]) of
+// a level with n cells per side lives at
+//     ((l * (n + 1) + j) * pitch) + ORIGIN + i
+// ORIGIN = 15 puts node i = 1 (the first interior node of a row) on a 128-byte
+// boundary when pitch is a multiple of 16, so a wavefront reading 64
+// consecutive interior nodes of a row touches whole cache lines.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pasm.h"
+
+namespace pasm {
+
+constexpr int ORIGIN = 15;
+
+struct Grid {
+    int dim = 2;
+    int n = 0;        // cells per side
+    int m = 0;        // interior nodes per side (n - 1)
+    int pitch = 0;    // elements per padded row
+    long plane = 0;   // elements per right-hand side block
+    double h = 0.0;
+
+    __host__ __device__ inline long idx(int i, int j) const {
+        return (long)j * pitch + ORIGIN + i;
+    }
+    __host__ __device__ inline long idx(int i, int j, int l) const {
+        return ((long)l * (n + 1) + j) * pitch + ORIGIN + i;
+    }
+    long interior() const {
+        long r = 1;
+        for (int a = 0; a < dim; ++a) r *= m;
+        return r;
+    }
+};
+
+Grid make_grid(int dim, int n);
+
+// Operator coefficients of one level.  Stiffness as edge weights: w[a] holds,
+// at node x, the weight of the edge (x, x + e_a) (2D: a = 0 east, 1 north).
+// A x = sum over edges (x, y) of w_xy (x_x - x_y): the 5-point (2D) or
+// 7-point (3D) stencil.  With constant coefficients the arrays are absent and
+// every edge has weight w0.
+template <typename T>
+struct Coef {
+    const T* wx = nullptr;
+    const T* wy = nullptr;
+    const T* wz = nullptr;
+    T w0 = T(1);
+};
+
+#define PASM_HIP(call)                                                              \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            throw pasm::Error(PASM_E_DEVICE, std::string(#call) + ": " +            \
+                                                 hipGetErrorString(e_));            \
+    } while (0)
+
+#define PASM_CHECK_LAUNCH() PASM_HIP(hipGetLastError())
+
+struct Error {
+    pasm_status status;
+    std::string msg;
+    Error(pasm_status s, std::string m) : status(s), msg(std::move(m)) {}
+};
+
+// ----------------------------------------------------------------------------
+// Launchers (2D stencils, transfers), implemented in stencil2d.hip.
+// All take `nrhs` right-hand sides stored `stride` elements apart.
+// ----------------------------------------------------------------------------
+struct Cheb {
+    double a;   // weight of (x_k - x_{k-1})
+    double b;   // weight of D^{-1}(f - A x_k)
+};
+
+template <typename T>
+void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
+                   int nrhs, long stride, Cheb s, bool x_zero, hipStream_t st);
+
+template <typename T>
+void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
+                           T* rc, int nrhs, long sf, long sc, hipStream_t st);
+
+// x_f = alpha * (P x_c) + beta[r] * x_f  (beta == nullptr: x_f = P x_c;
+// add = true: x_f += P x_c)
+template <typename T>
+void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs, long sc, long sf,
+                    bool add, const double* beta, hipStream_t st);
+
+template <typename T>
+void launch_restrict(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrhs, long sf, long sc,
+                     hipStream_t st);
+
+template <typename T>
+void launch_apply_A(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride,
+                    hipStream_t st);
+
+// f = lambda[r] * M_h u  (finest level, FP64)
+void launch_mass_rhs(const Grid& g, const double* u, const double* lam, double* f, int nrhs,
+                     long stride, hipStream_t st);
+// y = M_h x
+void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long stride, hipStream_t st);
+
+// r32 = (f - A u) in FP64, rounded to FP32
+void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f,
+                       float* r, int nrhs, long stride, hipStream_t st);
+
+// u += e (whole blocks, boundary entries stay zero)
+void launch_add_correction(const float* e, double* u, long n, hipStream_t st);
+
+// Border sweep: au = A u, mu = M u, partial[r][blk][2] = block sums of
+// (u . au, u . mu).  Returns the number of blocks per right-hand side.
+int launch_border(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
+                  double* partial, int nrhs, long stride, hipStream_t st);
+
+// out[r][0..1] = sums of partial[r][0..nblk)[0..1] in a fixed order.
+void launch_reduce_pairs(const double* partial, int nblk, double* out, int nrhs, hipStream_t st);
+
+// Pack / unpack between the padded level layout and compact interior vectors.
+template <typename T>
+void launch_pack(const Grid& g, const T* padded, long sp, double* compact, long ld, int nrhs,
+                 hipStream_t st);
+template <typename T>
+void launch_unpack(const Grid& g, const double* compact, long ld, T* padded, long sp, int nrhs,
+                   hipStream_t st);
+
+void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// ----------------------------------------------------------------------------
+// Coarse-space kernels (coarse.hip)
+// ----------------------------------------------------------------------------
+// y[r] = Mat x[r] with Mat(row, col) stored at Mat[col * N + row]; x and y in
+// either the padded layout of level g (flag true) or compact (flag false).
+template <typename T>
+void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded,
+                     T* y, long sy, bool y_padded, int nrhs, hipStream_t st);
+
+struct ArrowIn {
+    const double* theta;    // N coarse Ritz values, ascending
+    const int* group;       // N: index of the first member of the group of equal theta
+    const double* p;        // [k][N] Q^T b
+    const double* q;        // [k][N] Q^T c
+    const double* bz;       // [k][2] (beta, zeta)
+    const double* lam_prev; // [k]
+    int N;
+};
+struct ArrowOut {
+    double* ycoef;  // [k][N] coefficients y' of the new eigenvector in the Q basis
+    double* s;      // [k] weight of u~ in the new eigenvector
+    double* mu;     // [k] selected augmented eigenvalue
+    int* rank;      // [k]
+    double* score;  // [k]
+    int* flags;     // [k]
+    double* work;   // [k][3N + 8] scratch
+};
+void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t st);
+
+}  // namespace pasm

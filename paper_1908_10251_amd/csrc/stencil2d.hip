@@ -1,0 +1,454 @@
+// Matrix-free P1 operators and grid transfers on the uniform "/" triangle mesh
+// (2D Kuhn split), for all k right-hand sides of a batch.
+//
+// Stiffness: for kappa constant per element, each triangle couples the two
+// ends of each leg with -kappa_T/2 and the hypotenuse ends with 0, so the
+// stiffness is a 5-point stencil whose edge weights are read per node
+// (Section 2, the discrete eigenproblem; weak form a(u,v)).
+// Mass: |T|(1+delta_ij)/12 summed over the 6 triangles around a node gives
+// h^2 (1/2 at the centre, 1/12 at E, W, N, S, NE, SW).
+// Prolongation (nested spaces of Section 3): a fine node at (2I+a, 2J+b) takes
+// the mean of the coarse nodes (I, J) and (I+a, J+b) (a coarse P1 function is
+// linear along the coarse edge in direction (a, b)); restriction is its
+// transpose.
+//
+// Launch shape: 64 x 4 threads, one wavefront per 64 consecutive nodes of a
+// row (coalesced, 128-byte aligned rows), grid.z = right-hand side.
+#include "common.h"
+
+namespace pasm {
+
+namespace {
+
+constexpr int BX = 64;
+constexpr int BY = 4;
+
+inline dim3 grid_for(int mx, int my, int nrhs) {
+    return dim3((mx + BX - 1) / BX, (my + BY - 1) / BY, nrhs);
+}
+
+template <typename T, bool CONST>
+struct Stiff2 {
+    // Returns A x at node id and the diagonal D.
+    __device__ static inline void apply(const Grid& g, const Coef<T>& c, const T* __restrict__ x,
+                                        long id, T& Ax, T& D) {
+        const T x0 = x[id];
+        const T xe = x[id + 1], xw = x[id - 1], xn = x[id + g.pitch], xs = x[id - g.pitch];
+        if (CONST) {
+            D = T(4) * c.w0;
+            Ax = c.w0 * (T(4) * x0 - xe - xw - xn - xs);
+        } else {
+            const T we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - g.pitch];
+            D = we + ww + wn + ws;
+            Ax = D * x0 - we * xe - ww * xw - wn * xn - ws * xs;
+        }
+    }
+    __device__ static inline T diag(const Grid& g, const Coef<T>& c, long id) {
+        if (CONST) return T(4) * c.w0;
+        return c.wx[id] + c.wx[id - 1] + c.wy[id] + c.wy[id - g.pitch];
+    }
+};
+
+// One smoothing step, x_{k+1} = x_k + a (x_k - x_{k-1}) + b D^{-1} (f - A x_k).
+// xp may alias xn: each thread reads xp at its own node before writing xn there.
+template <typename T, bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> c, const T* __restrict__ xc,
+                                                   const T* xp, const T* __restrict__ f, T* xn,
+                                                   long stride, T a, T b, int x_zero) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    const long off = (long)blockIdx.z * stride;
+    const long id = g.idx(i, j);
+    const T fv = f[off + id];
+    if (x_zero) {
+        const T D = Stiff2<T, CONST>::diag(g, c, id);
+        xn[off + id] = b * fv / D;
+        return;
+    }
+    T Ax, D;
+    Stiff2<T, CONST>::apply(g, c, xc + off, id, Ax, D);
+    const T x0 = xc[off + id];
+    T v = x0 + b * (fv - Ax) / D;
+    if (a != T(0)) v += a * (x0 - xp[off + id]);
+    xn[off + id] = v;
+}
+
+template <typename T, bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_apply_A(Grid g, Coef<T> c, const T* __restrict__ x,
+                                                    T* __restrict__ y, long stride) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    const long off = (long)blockIdx.z * stride;
+    const long id = g.idx(i, j);
+    T Ax, D;
+    Stiff2<T, CONST>::apply(g, c, x + off, id, Ax, D);
+    y[off + id] = Ax;
+}
+
+// r_c = P^T (f - A x): each coarse interior node gathers the residual at the 7
+// fine nodes whose interpolation stencil contains it.
+template <typename T, bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_resid_restrict(Grid gf, Coef<T> c, const T* __restrict__ x,
+                                                           const T* __restrict__ f, Grid gc,
+                                                           T* __restrict__ rc, long sf, long sc) {
+    const int I = blockIdx.x * BX + threadIdx.x + 1;
+    const int J = blockIdx.y * BY + threadIdx.y + 1;
+    if (I > gc.m || J > gc.m) return;
+    const T* xr = x + (long)blockIdx.z * sf;
+    const T* fr = f + (long)blockIdx.z * sf;
+    const int i = 2 * I, j = 2 * J;
+    auto res = [&](int ii, int jj) -> T {
+        const long id = gf.idx(ii, jj);
+        T Ax, D;
+        Stiff2<T, CONST>::apply(gf, c, xr, id, Ax, D);
+        return fr[id] - Ax;
+    };
+    T v = res(i, j);
+    T s = res(i + 1, j) + res(i - 1, j) + res(i, j + 1) + res(i, j - 1) + res(i + 1, j + 1) +
+          res(i - 1, j - 1);
+    rc[(long)blockIdx.z * sc + gc.idx(I, J)] = v + T(0.5) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BX* BY) void k_restrict(Grid gf, const T* __restrict__ xf, Grid gc,
+                                                     T* __restrict__ xc, long sf, long sc) {
+    const int I = blockIdx.x * BX + threadIdx.x + 1;
+    const int J = blockIdx.y * BY + threadIdx.y + 1;
+    if (I > gc.m || J > gc.m) return;
+    const T* xr = xf + (long)blockIdx.z * sf;
+    const long id = gf.idx(2 * I, 2 * J);
+    const int p = gf.pitch;
+    T s = xr[id + 1] + xr[id - 1] + xr[id + p] + xr[id - p] + xr[id + p + 1] + xr[id - p - 1];
+    xc[(long)blockIdx.z * sc + gc.idx(I, J)] = xr[id] + T(0.5) * s;
+}
+
+// mode 0: x_f = P x_c; 1: x_f += P x_c; 2: x_f = P x_c + beta[r] x_f
+template <typename T>
+__global__ __launch_bounds__(BX* BY) void k_prolong(Grid gc, const T* __restrict__ xc, Grid gf,
+                                                    T* __restrict__ xf, long sc, long sf, int mode,
+                                                    const double* __restrict__ beta) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > gf.m || j > gf.m) return;
+    const T* cr = xc + (long)blockIdx.z * sc;
+    const int I = i >> 1, J = j >> 1, a = i & 1, b = j & 1;
+    const long cid = gc.idx(I, J);
+    T v = cr[cid];
+    if (a | b) v = T(0.5) * (v + cr[cid + a + (long)b * gc.pitch]);
+    const long id = (long)blockIdx.z * sf + gf.idx(i, j);
+    if (mode == 1) v += xf[id];
+    else if (mode == 2) v += T(beta[blockIdx.z]) * xf[id];
+    xf[id] = v;
+}
+
+__device__ inline double mass2(const Grid& g, const double* __restrict__ u, long id) {
+    const int p = g.pitch;
+    const double s = u[id + 1] + u[id - 1] + u[id + p] + u[id - p] + u[id + p + 1] + u[id - p - 1];
+    return g.h * g.h * (0.5 * u[id] + s * (1.0 / 12.0));
+}
+
+__global__ __launch_bounds__(BX* BY) void k_mass_rhs(Grid g, const double* __restrict__ u,
+                                                     const double* __restrict__ lam,
+                                                     double* __restrict__ f, long stride) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    const long off = (long)blockIdx.z * stride;
+    const long id = g.idx(i, j);
+    const double l = lam ? lam[blockIdx.z] : 1.0;
+    f[off + id] = l * mass2(g, u + off, id);
+}
+
+template <bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> c, const double* __restrict__ u,
+                                                       const double* __restrict__ f,
+                                                       float* __restrict__ r, long stride) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    const long off = (long)blockIdx.z * stride;
+    const long id = g.idx(i, j);
+    double Ax, D;
+    Stiff2<double, CONST>::apply(g, c, u + off, id, Ax, D);
+    r[off + id] = (float)(f[off + id] - Ax);
+}
+
+__global__ void k_add_correction(const float* __restrict__ e, double* __restrict__ u, long n) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        u[t] += (double)e[t];
+}
+
+// Deterministic block sum of two values; result valid in thread 0.
+__device__ inline void block_sum2(double& a, double& b, double* sh) {
+    const int lane = threadIdx.x + threadIdx.y * BX;  // BX == 64: one wavefront per row of the block
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    const int w = lane >> 6;
+    if ((lane & 63) == 0) {
+        sh[2 * w] = a;
+        sh[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        a = sh[0] + sh[2] + sh[4] + sh[6];
+        b = sh[1] + sh[3] + sh[5] + sh[7];
+    }
+}
+
+template <bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_border(Grid g, Coef<double> c, const double* __restrict__ u,
+                                                   double* __restrict__ au, double* __restrict__ mu,
+                                                   double* __restrict__ partial, long stride) {
+    __shared__ double sh[8];
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    const long off = (long)blockIdx.z * stride;
+    double ua = 0.0, um = 0.0;
+    if (i <= g.m && j <= g.m) {
+        const long id = g.idx(i, j);
+        double Ax, D;
+        Stiff2<double, CONST>::apply(g, c, u + off, id, Ax, D);
+        const double Mx = mass2(g, u + off, id);
+        au[off + id] = Ax;
+        mu[off + id] = Mx;
+        ua = u[off + id] * Ax;
+        um = u[off + id] * Mx;
+    }
+    block_sum2(ua, um, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const long nblk = (long)gridDim.x * gridDim.y;
+        const long b = (long)blockIdx.z * nblk + blockIdx.y * gridDim.x + blockIdx.x;
+        partial[2 * b] = ua;
+        partial[2 * b + 1] = um;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__ partial, int nblk,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[8];
+    const double* pr = partial + 2L * nblk * blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < nblk; t += 256) {
+        a += pr[2 * t];
+        b += pr[2 * t + 1];
+    }
+    // reuse the 64 x 4 reduction with a flat block of 256
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[2 * w] = a;
+        sh[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = sh[0] + sh[2] + sh[4] + sh[6];
+        out[2 * blockIdx.x + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+    }
+}
+
+template <typename T>
+__global__ void k_pack(Grid g, const T* __restrict__ padded, long sp, double* __restrict__ compact, long ld) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    compact[(long)blockIdx.z * ld + (long)(j - 1) * g.m + (i - 1)] =
+        (double)padded[(long)blockIdx.z * sp + g.idx(i, j)];
+}
+
+template <typename T>
+__global__ void k_unpack(Grid g, const double* __restrict__ compact, long ld, T* __restrict__ padded, long sp) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    padded[(long)blockIdx.z * sp + g.idx(i, j)] =
+        (T)compact[(long)blockIdx.z * ld + (long)(j - 1) * g.m + (i - 1)];
+}
+
+__global__ void k_fill_zero(uint32_t* p, size_t n) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = 0u;
+}
+
+inline int flat_blocks(long n) {
+    long b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers (2D only here; the 3D kernels live in stencil3d.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_smooth3(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
+                    int nrhs, long stride, Cheb s, bool x_zero, hipStream_t st);
+template <typename T>
+void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
+                            T* rc, int nrhs, long sf, long sc, hipStream_t st);
+template <typename T>
+void launch_prolong3(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs, long sc, long sf,
+                     int mode, const double* beta, hipStream_t st);
+template <typename T>
+void launch_restrict3(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrhs, long sf, long sc,
+                      hipStream_t st);
+template <typename T>
+void launch_apply_A3(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride, hipStream_t st);
+void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double* f, int nrhs, long stride,
+                      hipStream_t st);
+void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
+                        int nrhs, long stride, hipStream_t st);
+int launch_border3(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
+                   double* partial, int nrhs, long stride, hipStream_t st);
+template <typename T>
+void launch_pack3(const Grid& g, const T* padded, long sp, double* compact, long ld, int nrhs, hipStream_t st);
+template <typename T>
+void launch_unpack3(const Grid& g, const double* compact, long ld, T* padded, long sp, int nrhs, hipStream_t st);
+
+template <typename T>
+void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
+                   int nrhs, long stride, Cheb s, bool x_zero, hipStream_t st) {
+    if (g.dim == 3) return launch_smooth3<T>(g, c, xc, xp, f, xn, nrhs, stride, s, x_zero, st);
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    if (c.wx)
+        hipLaunchKernelGGL((k_smooth<T, false>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a,
+                           (T)s.b, (int)x_zero);
+    else
+        hipLaunchKernelGGL((k_smooth<T, true>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a,
+                           (T)s.b, (int)x_zero);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_apply_A(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride,
+                    hipStream_t st) {
+    if (g.dim == 3) return launch_apply_A3<T>(g, c, x, y, nrhs, stride, st);
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    if (c.wx)
+        hipLaunchKernelGGL((k_apply_A<T, false>), grid, blk, 0, st, g, c, x, y, stride);
+    else
+        hipLaunchKernelGGL((k_apply_A<T, true>), grid, blk, 0, st, g, c, x, y, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
+                           T* rc, int nrhs, long sf, long sc, hipStream_t st) {
+    if (gf.dim == 3) return launch_resid_restrict3<T>(gf, c, x, f, gc, rc, nrhs, sf, sc, st);
+    dim3 grid = grid_for(gc.m, gc.m, nrhs), blk(BX, BY);
+    if (c.wx)
+        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs, long sc, long sf,
+                    bool add, const double* beta, hipStream_t st) {
+    const int mode = beta ? 2 : (add ? 1 : 0);
+    if (gf.dim == 3) return launch_prolong3<T>(gc, xc, gf, xf, nrhs, sc, sf, mode, beta, st);
+    dim3 grid = grid_for(gf.m, gf.m, nrhs), blk(BX, BY);
+    hipLaunchKernelGGL((k_prolong<T>), grid, blk, 0, st, gc, xc, gf, xf, sc, sf, mode, beta);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_restrict(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrhs, long sf, long sc,
+                     hipStream_t st) {
+    if (gf.dim == 3) return launch_restrict3<T>(gf, xf, gc, xc, nrhs, sf, sc, st);
+    dim3 grid = grid_for(gc.m, gc.m, nrhs), blk(BX, BY);
+    hipLaunchKernelGGL((k_restrict<T>), grid, blk, 0, st, gf, xf, gc, xc, sf, sc);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_mass_rhs(const Grid& g, const double* u, const double* lam, double* f, int nrhs, long stride,
+                     hipStream_t st) {
+    if (g.dim == 3) return launch_mass_rhs3(g, u, lam, f, nrhs, stride, st);
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    hipLaunchKernelGGL(k_mass_rhs, grid, blk, 0, st, g, u, lam, f, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long stride, hipStream_t st) {
+    launch_mass_rhs(g, x, nullptr, y, nrhs, stride, st);
+}
+
+void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
+                       int nrhs, long stride, hipStream_t st) {
+    if (g.dim == 3) return launch_resid_cast3(g, c, u, f, r, nrhs, stride, st);
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    if (c.wx)
+        hipLaunchKernelGGL(k_resid_cast<false>, grid, blk, 0, st, g, c, u, f, r, stride);
+    else
+        hipLaunchKernelGGL(k_resid_cast<true>, grid, blk, 0, st, g, c, u, f, r, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_add_correction(const float* e, double* u, long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_correction, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
+    PASM_CHECK_LAUNCH();
+}
+
+int launch_border(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
+                  double* partial, int nrhs, long stride, hipStream_t st) {
+    if (g.dim == 3) return launch_border3(g, c, u, au, mu, partial, nrhs, stride, st);
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    if (c.wx)
+        hipLaunchKernelGGL(k_border<false>, grid, blk, 0, st, g, c, u, au, mu, partial, stride);
+    else
+        hipLaunchKernelGGL(k_border<true>, grid, blk, 0, st, g, c, u, au, mu, partial, stride);
+    PASM_CHECK_LAUNCH();
+    return (int)(grid.x * grid.y);
+}
+
+void launch_reduce_pairs(const double* partial, int nblk, double* out, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(nrhs), dim3(256), 0, st, partial, nblk, out);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_pack(const Grid& g, const T* padded, long sp, double* compact, long ld, int nrhs, hipStream_t st) {
+    if (g.dim == 3) return launch_pack3<T>(g, padded, sp, compact, ld, nrhs, st);
+    hipLaunchKernelGGL((k_pack<T>), grid_for(g.m, g.m, nrhs), dim3(BX, BY), 0, st, g, padded, sp, compact, ld);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_unpack(const Grid& g, const double* compact, long ld, T* padded, long sp, int nrhs, hipStream_t st) {
+    if (g.dim == 3) return launch_unpack3<T>(g, compact, ld, padded, sp, nrhs, st);
+    hipLaunchKernelGGL((k_unpack<T>), grid_for(g.m, g.m, nrhs), dim3(BX, BY), 0, st, g, compact, ld, padded, sp);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 4;
+    hipLaunchKernelGGL(k_fill_zero, dim3(flat_blocks((long)n)), dim3(256), 0, st, (uint32_t*)p, n);
+    PASM_CHECK_LAUNCH();
+}
+
+#define PASM_INST(T)                                                                                  \
+    template void launch_smooth<T>(const Grid&, const Coef<T>&, const T*, const T*, const T*, T*, int,  \
+                                   long, Cheb, bool, hipStream_t);                                      \
+    template void launch_apply_A<T>(const Grid&, const Coef<T>&, const T*, T*, int, long, hipStream_t); \
+    template void launch_resid_restrict<T>(const Grid&, const Coef<T>&, const T*, const T*, const Grid&, \
+                                           T*, int, long, long, hipStream_t);                           \
+    template void launch_prolong<T>(const Grid&, const T*, const Grid&, T*, int, long, long, bool,      \
+                                    const double*, hipStream_t);                                        \
+    template void launch_restrict<T>(const Grid&, const T*, const Grid&, T*, int, long, long,           \
+                                     hipStream_t);                                                      \
+    template void launch_pack<T>(const Grid&, const T*, long, double*, long, int, hipStream_t);         \
+    template void launch_unpack<T>(const Grid&, const double*, long, T*, long, int, hipStream_t);
+PASM_INST(double)
+PASM_INST(float)
+#undef PASM_INST
+
+}  // namespace pasm

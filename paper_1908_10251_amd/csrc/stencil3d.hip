@@ -1,0 +1,345 @@
+// Matrix-free P1 operators and transfers on the Kuhn tetrahedral mesh (six
+// tetrahedra per cube sharing the main diagonal), for all right-hand sides.
+//
+// With constant kappa the stiffness is h * (6 at the centre, -1 at the six axis
+// neighbours): every non-axis edge coupling of a Kuhn tetrahedron cancels when
+// the 24 tetrahedra around a node are summed.  The mass matrix, |T|(1+delta)/20
+// per tetrahedron, gives h^3 * (2/5 at the centre, 1/20 on the six axis
+// neighbours, 1/30 on the six face diagonals +-(1,1,0), +-(1,0,1), +-(0,1,1),
+// 1/20 on the two body diagonals +-(1,1,1)).  These follow from the element
+// integrals of Section 2 on this mesh.
+// Prolongation: a fine node (2I,2J,2L) + o, o in {0,1}^3 \ 0, is the midpoint
+// of the coarse edge from (I,J,L) to (I,J,L) + o (every such o is an edge
+// direction of the Kuhn mesh), so it takes the mean of those two coarse nodes.
+//
+// Launch shape: 64 x 4 threads over (x, y); grid.z enumerates (z-plane, rhs).
+#include "common.h"
+
+namespace pasm {
+
+namespace {
+
+constexpr int BX = 64;
+constexpr int BY = 4;
+
+inline dim3 grid3(int m, int nrhs) { return dim3((m + BX - 1) / BX, (m + BY - 1) / BY, m * nrhs); }
+
+struct Pos {
+    int i, j, l, r;
+    bool ok;
+};
+__device__ inline Pos pos3(int m) {
+    Pos p;
+    p.i = blockIdx.x * BX + threadIdx.x + 1;
+    p.j = blockIdx.y * BY + threadIdx.y + 1;
+    p.l = blockIdx.z % m + 1;
+    p.r = blockIdx.z / m;
+    p.ok = p.i <= m && p.j <= m;
+    return p;
+}
+
+template <typename T, bool CONST>
+__device__ inline void stiff3(const Grid& g, const Coef<T>& c, const T* __restrict__ x, long id, T& Ax, T& D) {
+    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+    const T x0 = x[id];
+    const T s = x[id + 1] + x[id - 1] + x[id + py] + x[id - py] + x[id + pz] + x[id - pz];
+    if (CONST) {
+        D = T(6) * c.w0;
+        Ax = c.w0 * (T(6) * x0 - s);
+    } else {
+        const T w1 = c.wx[id], w2 = c.wx[id - 1], w3 = c.wy[id], w4 = c.wy[id - py], w5 = c.wz[id],
+                w6 = c.wz[id - pz];
+        D = w1 + w2 + w3 + w4 + w5 + w6;
+        Ax = D * x0 - w1 * x[id + 1] - w2 * x[id - 1] - w3 * x[id + py] - w4 * x[id - py] -
+             w5 * x[id + pz] - w6 * x[id - pz];
+    }
+}
+
+template <typename T, bool CONST>
+__device__ inline T diag3(const Grid& g, const Coef<T>& c, long id) {
+    if (CONST) return T(6) * c.w0;
+    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+    return c.wx[id] + c.wx[id - 1] + c.wy[id] + c.wy[id - py] + c.wz[id] + c.wz[id - pz];
+}
+
+template <typename T, bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_smooth3(Grid g, Coef<T> c, const T* __restrict__ xc, const T* xp,
+                                                    const T* __restrict__ f, T* xn, long stride, T a, T b,
+                                                    int x_zero) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long off = (long)p.r * stride;
+    const long id = g.idx(p.i, p.j, p.l);
+    const T fv = f[off + id];
+    if (x_zero) {
+        xn[off + id] = b * fv / diag3<T, CONST>(g, c, id);
+        return;
+    }
+    T Ax, D;
+    stiff3<T, CONST>(g, c, xc + off, id, Ax, D);
+    const T x0 = xc[off + id];
+    T v = x0 + b * (fv - Ax) / D;
+    if (a != T(0)) v += a * (x0 - xp[off + id]);
+    xn[off + id] = v;
+}
+
+template <typename T, bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_apply_A3(Grid g, Coef<T> c, const T* __restrict__ x,
+                                                     T* __restrict__ y, long stride) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long off = (long)p.r * stride;
+    const long id = g.idx(p.i, p.j, p.l);
+    T Ax, D;
+    stiff3<T, CONST>(g, c, x + off, id, Ax, D);
+    y[off + id] = Ax;
+}
+
+// The 14 fine neighbours (+-o for the 7 nonzero o in {0,1}^3) of a fine node.
+__device__ inline long nb_off(const Grid& g, int t) {
+    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+    const int o = (t >> 1) + 1;  // 1..7
+    const long d = (o & 1 ? 1 : 0) + (o & 2 ? py : 0) + (o & 4 ? pz : 0);
+    return (t & 1) ? -d : d;
+}
+
+template <typename T, bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_resid_restrict3(Grid gf, Coef<T> c, const T* __restrict__ x,
+                                                            const T* __restrict__ f, Grid gc,
+                                                            T* __restrict__ rc, long sf, long sc) {
+    const Pos p = pos3(gc.m);
+    if (!p.ok) return;
+    const T* xr = x + (long)p.r * sf;
+    const T* fr = f + (long)p.r * sf;
+    const long id0 = gf.idx(2 * p.i, 2 * p.j, 2 * p.l);
+    auto res = [&](long id) -> T {
+        T Ax, D;
+        stiff3<T, CONST>(gf, c, xr, id, Ax, D);
+        return fr[id] - Ax;
+    };
+    T s = T(0);
+#pragma unroll
+    for (int t = 0; t < 14; ++t) s += res(id0 + nb_off(gf, t));
+    rc[(long)p.r * sc + gc.idx(p.i, p.j, p.l)] = res(id0) + T(0.5) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BX* BY) void k_restrict3(Grid gf, const T* __restrict__ xf, Grid gc,
+                                                      T* __restrict__ xc, long sf, long sc) {
+    const Pos p = pos3(gc.m);
+    if (!p.ok) return;
+    const T* xr = xf + (long)p.r * sf;
+    const long id0 = gf.idx(2 * p.i, 2 * p.j, 2 * p.l);
+    T s = T(0);
+#pragma unroll
+    for (int t = 0; t < 14; ++t) s += xr[id0 + nb_off(gf, t)];
+    xc[(long)p.r * sc + gc.idx(p.i, p.j, p.l)] = xr[id0] + T(0.5) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BX* BY) void k_prolong3(Grid gc, const T* __restrict__ xc, Grid gf,
+                                                     T* __restrict__ xf, long sc, long sf, int mode,
+                                                     const double* __restrict__ beta) {
+    const Pos p = pos3(gf.m);
+    if (!p.ok) return;
+    const T* cr = xc + (long)p.r * sc;
+    const int a = p.i & 1, b = p.j & 1, e = p.l & 1;
+    const long cid = gc.idx(p.i >> 1, p.j >> 1, p.l >> 1);
+    T v = cr[cid];
+    if (a | b | e) v = T(0.5) * (v + cr[cid + a + (long)b * gc.pitch + (long)e * gc.pitch * (gc.n + 1)]);
+    const long id = (long)p.r * sf + gf.idx(p.i, p.j, p.l);
+    if (mode == 1) v += xf[id];
+    else if (mode == 2) v += T(beta[p.r]) * xf[id];
+    xf[id] = v;
+}
+
+__device__ inline double mass3(const Grid& g, const double* __restrict__ u, long id) {
+    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+    const double ax = u[id + 1] + u[id - 1] + u[id + py] + u[id - py] + u[id + pz] + u[id - pz];
+    const double fd = u[id + 1 + py] + u[id - 1 - py] + u[id + 1 + pz] + u[id - 1 - pz] + u[id + py + pz] +
+                      u[id - py - pz];
+    const double bd = u[id + 1 + py + pz] + u[id - 1 - py - pz];
+    const double h3 = g.h * g.h * g.h;
+    return h3 * (0.4 * u[id] + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0));
+}
+
+__global__ __launch_bounds__(BX* BY) void k_mass_rhs3(Grid g, const double* __restrict__ u,
+                                                      const double* __restrict__ lam, double* __restrict__ f,
+                                                      long stride) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long off = (long)p.r * stride;
+    const long id = g.idx(p.i, p.j, p.l);
+    const double l = lam ? lam[p.r] : 1.0;
+    f[off + id] = l * mass3(g, u + off, id);
+}
+
+template <bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_resid_cast3(Grid g, Coef<double> c, const double* __restrict__ u,
+                                                        const double* __restrict__ f, float* __restrict__ r,
+                                                        long stride) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long off = (long)p.r * stride;
+    const long id = g.idx(p.i, p.j, p.l);
+    double Ax, D;
+    stiff3<double, CONST>(g, c, u + off, id, Ax, D);
+    r[off + id] = (float)(f[off + id] - Ax);
+}
+
+template <bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_border3(Grid g, Coef<double> c, const double* __restrict__ u,
+                                                    double* __restrict__ au, double* __restrict__ mu,
+                                                    double* __restrict__ partial, long stride) {
+    __shared__ double sh[8];
+    const Pos p = pos3(g.m);
+    const long off = (long)p.r * stride;
+    double ua = 0.0, um = 0.0;
+    if (p.ok) {
+        const long id = g.idx(p.i, p.j, p.l);
+        double Ax, D;
+        stiff3<double, CONST>(g, c, u + off, id, Ax, D);
+        const double Mx = mass3(g, u + off, id);
+        au[off + id] = Ax;
+        mu[off + id] = Mx;
+        ua = u[off + id] * Ax;
+        um = u[off + id] * Mx;
+    }
+    const int lane = threadIdx.x + threadIdx.y * BX;
+    for (int o = 32; o > 0; o >>= 1) {
+        ua += __shfl_down(ua, o, 64);
+        um += __shfl_down(um, o, 64);
+    }
+    if ((lane & 63) == 0) {
+        sh[2 * threadIdx.y] = ua;
+        sh[2 * threadIdx.y + 1] = um;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const long per = (long)gridDim.x * gridDim.y * g.m;  // blocks per rhs
+        const long b = (long)p.r * per + ((long)(p.l - 1) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partial[2 * b] = sh[0] + sh[2] + sh[4] + sh[6];
+        partial[2 * b + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+    }
+}
+
+template <typename T>
+__global__ void k_pack3(Grid g, const T* __restrict__ padded, long sp, double* __restrict__ compact, long ld) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long ci = ((long)(p.l - 1) * g.m + (p.j - 1)) * g.m + (p.i - 1);
+    compact[(long)p.r * ld + ci] = (double)padded[(long)p.r * sp + g.idx(p.i, p.j, p.l)];
+}
+
+template <typename T>
+__global__ void k_unpack3(Grid g, const double* __restrict__ compact, long ld, T* __restrict__ padded, long sp) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long ci = ((long)(p.l - 1) * g.m + (p.j - 1)) * g.m + (p.i - 1);
+    padded[(long)p.r * sp + g.idx(p.i, p.j, p.l)] = (T)compact[(long)p.r * ld + ci];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_smooth3(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn, int nrhs,
+                    long stride, Cheb s, bool x_zero, hipStream_t st) {
+    if (c.wx)
+        hipLaunchKernelGGL((k_smooth3<T, false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, xc, xp, f, xn,
+                           stride, (T)s.a, (T)s.b, (int)x_zero);
+    else
+        hipLaunchKernelGGL((k_smooth3<T, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, xc, xp, f, xn,
+                           stride, (T)s.a, (T)s.b, (int)x_zero);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_apply_A3(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride, hipStream_t st) {
+    if (c.wx)
+        hipLaunchKernelGGL((k_apply_A3<T, false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, x, y, stride);
+    else
+        hipLaunchKernelGGL((k_apply_A3<T, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, x, y, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc, T* rc,
+                            int nrhs, long sf, long sc, hipStream_t st) {
+    if (c.wx)
+        hipLaunchKernelGGL((k_resid_restrict3<T, false>), grid3(gc.m, nrhs), dim3(BX, BY), 0, st, gf, c, x, f,
+                           gc, rc, sf, sc);
+    else
+        hipLaunchKernelGGL((k_resid_restrict3<T, true>), grid3(gc.m, nrhs), dim3(BX, BY), 0, st, gf, c, x, f,
+                           gc, rc, sf, sc);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_prolong3(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs, long sc, long sf, int mode,
+                     const double* beta, hipStream_t st) {
+    hipLaunchKernelGGL((k_prolong3<T>), grid3(gf.m, nrhs), dim3(BX, BY), 0, st, gc, xc, gf, xf, sc, sf, mode,
+                       beta);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_restrict3(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrhs, long sf, long sc,
+                      hipStream_t st) {
+    hipLaunchKernelGGL((k_restrict3<T>), grid3(gc.m, nrhs), dim3(BX, BY), 0, st, gf, xf, gc, xc, sf, sc);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double* f, int nrhs, long stride,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_mass_rhs3, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, u, lam, f, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
+                        int nrhs, long stride, hipStream_t st) {
+    if (c.wx)
+        hipLaunchKernelGGL(k_resid_cast3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
+    else
+        hipLaunchKernelGGL(k_resid_cast3<true>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+int launch_border3(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
+                   double* partial, int nrhs, long stride, hipStream_t st) {
+    dim3 grid = grid3(g.m, nrhs);
+    if (c.wx)
+        hipLaunchKernelGGL(k_border3<false>, grid, dim3(BX, BY), 0, st, g, c, u, au, mu, partial, stride);
+    else
+        hipLaunchKernelGGL(k_border3<true>, grid, dim3(BX, BY), 0, st, g, c, u, au, mu, partial, stride);
+    PASM_CHECK_LAUNCH();
+    return (int)(grid.x * grid.y * g.m);
+}
+
+template <typename T>
+void launch_pack3(const Grid& g, const T* padded, long sp, double* compact, long ld, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL((k_pack3<T>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, padded, sp, compact, ld);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_unpack3(const Grid& g, const double* compact, long ld, T* padded, long sp, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL((k_unpack3<T>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, compact, ld, padded, sp);
+    PASM_CHECK_LAUNCH();
+}
+
+#define PASM_INST3(T)                                                                                    \
+    template void launch_smooth3<T>(const Grid&, const Coef<T>&, const T*, const T*, const T*, T*, int,   \
+                                    long, Cheb, bool, hipStream_t);                                       \
+    template void launch_apply_A3<T>(const Grid&, const Coef<T>&, const T*, T*, int, long, hipStream_t);  \
+    template void launch_resid_restrict3<T>(const Grid&, const Coef<T>&, const T*, const T*, const Grid&, \
+                                            T*, int, long, long, hipStream_t);                            \
+    template void launch_prolong3<T>(const Grid&, const T*, const Grid&, T*, int, long, long, int,        \
+                                     const double*, hipStream_t);                                         \
+    template void launch_restrict3<T>(const Grid&, const T*, const Grid&, T*, int, long, long, hipStream_t); \
+    template void launch_pack3<T>(const Grid&, const T*, long, double*, long, int, hipStream_t);          \
+    template void launch_unpack3<T>(const Grid&, const double*, long, T*, long, int, hipStream_t);
+PASM_INST3(double)
+PASM_INST3(float)
+#undef PASM_INST3
+
+}  // namespace pasm

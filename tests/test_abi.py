@@ -1,0 +1,63 @@
+"""The C ABI library loads and exports every entry point of include/pasm.h,
+and rejects invalid arguments before touching a device."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import paper_1908_10251_amd as pasm
+
+
+def _declared():
+    text = open(pasm.HEADER_PATH).read()
+    return sorted(set(re.findall(r"PASM_API\s+[\w\s\*]+?\b(pasm_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 18
+    L = ctypes.CDLL(pasm.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_defaults():
+    L = pasm.lib()
+    for s in range(7):
+        assert L.pasm_status_string(s)
+    o = pasm.pasm_default_options()
+    assert o.precision == pasm.PASM_FP64 and o.vcycles == 2 and o.tol == 1e-10
+    assert L.pasm_destroy(None) == pasm.PASM_OK
+
+
+@pytest.mark.parametrize("args", [
+    dict(dim=4, H=1 / 8, h=1 / 64, k=4),
+    dict(dim=2, H=1 / 64, h=1 / 8, k=4),          # h > H
+    dict(dim=2, H=1 / 8, h=1 / 48, k=4),          # ratio 6
+    dict(dim=2, H=1 / 8, h=1 / 64, k=49),         # k >= N_H
+    dict(dim=2, H=1 / 8, h=1 / 64, k=0),
+    dict(dim=2, H=0.3, h=1 / 64, k=2),            # 1/H not an integer
+    dict(dim=3, H=1 / 4, h=1 / 8, k=27),
+])
+def test_invalid_setup_arguments(args):
+    with pytest.raises(pasm.PasmError) as e:
+        pasm.pasm_setup(args["dim"], args["H"], args["h"], args["k"])
+    assert e.value.status == pasm.PASM_E_INVALID
+
+
+def test_invalid_coefficients():
+    n = 16
+    bad = np.ones(2 * n * n)
+    bad[5] = -1.0
+    with pytest.raises(pasm.PasmError) as e:
+        pasm.pasm_setup(2, 1 / 4, 1 / n, 2, kappa=bad)
+    assert e.value.status == pasm.PASM_E_INVALID
+    assert "positive" in pasm.lib().pasm_last_error(None).decode()
+    with pytest.raises(pasm.PasmError):
+        pasm.pasm_setup(2, 1 / 4, 1 / n, 2, kappa=np.ones(10))
+    with pytest.raises(pasm.PasmError):
+        pasm.pasm_setup(3, 1 / 4, 1 / 8, 2, kappa=np.ones(6 * 8 ** 3))
+    o = pasm.options(vcycles=0)
+    with pytest.raises(pasm.PasmError):
+        pasm.pasm_setup(2, 1 / 8, 1 / 64, 2, options=o)

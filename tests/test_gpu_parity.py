@@ -1,0 +1,223 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Operators and V-cycles element by element; one correction step (Algorithm 1)
+from identical states; whole solves (Algorithm 2) against the discrete
+eigenpairs.  Tolerances: FP64 paths 1e-12..1e-10 relative (rounding order
+only), mixed-precision V-cycles 1e-5 relative per cycle (FP32 arithmetic on
+FP64 residuals), eigenvalues of mixed solves 1e-8 relative."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1908_10251_amd as P
+from oracle import fem, pasm as O
+from oracle.multigrid import Hierarchy, MGOptions, default_options
+from workloads import lognormal_kappa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _opts(smoother="jacobi", nu=2, vcycles=2, precision=P.PASM_FP64, tol=1e-10, max_iter=60):
+    return P.options(precision=precision, smoother=P.PASM_CHEBYSHEV if smoother == "cheb" else P.PASM_JACOBI,
+                     nu_pre=nu, nu_post=nu, vcycles=vcycles, tol=tol, max_iter=max_iter)
+
+
+CASES = [
+    # dim, nc, nf, kappa-sigma (None: kappa = 1)
+    (2, 8, 64, None),
+    (2, 4, 32, 1.0),
+    (3, 4, 16, None),
+]
+
+
+@pytest.mark.parametrize("dim,nc,nf,sig", CASES)
+def test_operators_every_level(dim, nc, nf, sig):
+    _say(f"operators dim={dim} H=1/{nc} h=1/{nf} sigma={sig}")
+    kap = None if sig is None else lognormal_kappa(dim, nf, seed=7, sigma=sig)
+    A, M = fem.assemble(dim, nf, kappa=kap)
+    hier = Hierarchy(dim, A, nc, nf)
+    k = 3
+    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts()) as s:
+        assert P.pasm_num_levels(s.ctx) == len(hier.levels)
+        rng = np.random.default_rng(1)
+        for l, lv in enumerate(hier.levels):
+            N = lv.A.shape[0]
+            x = rng.standard_normal((k, N))
+            y = torch.zeros(k, N, dtype=torch.float64, device="cuda")
+            P.pasm_apply_operator(s.ctx, l, P.PASM_OP_STIFFNESS, _t(x), y)
+            ref = (lv.A @ x.T).T
+            err = np.max(np.abs(y.cpu().numpy() - ref)) / np.max(np.abs(ref))
+            assert err < 1e-13, (l, err)
+        x = rng.standard_normal((k, M.shape[0]))
+        y = torch.zeros_like(_t(x))
+        P.pasm_apply_operator(s.ctx, len(hier.levels) - 1, P.PASM_OP_MASS, _t(x), y)
+        ref = (M @ x.T).T
+        assert np.max(np.abs(y.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-14
+
+
+VC = [
+    (2, 8, 64, None, "jacobi", 2),
+    (2, 8, 64, None, "cheb", 4),
+    (2, 4, 64, 1.0, "cheb", 4),
+    (3, 4, 16, None, "jacobi", 2),
+]
+
+
+@pytest.mark.parametrize("dim,nc,nf,sig,smoother,nu", VC)
+@pytest.mark.parametrize("precision", [P.PASM_FP64, P.PASM_MIXED])
+def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, precision):
+    _say(f"vcycle dim={dim} H=1/{nc} h=1/{nf} sigma={sig} {smoother} prec={precision}")
+    kap = None if sig is None else lognormal_kappa(dim, nf, seed=3, sigma=sig)
+    A, _ = fem.assemble(dim, nf, kappa=kap)
+    hier = Hierarchy(dim, A, nc, nf)
+    opts = default_options(dim, smoother, nu, nu, 1)
+    k = 2
+    rng = np.random.default_rng(2)
+    N = A.shape[0]
+    f = rng.standard_normal((k, N))
+    x0 = rng.standard_normal((k, N))
+    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu, precision=precision)) as s:
+        for ncyc in (1, 2):
+            xg = _t(x0)
+            P.pasm_vcycle(s.ctx, _t(f), xg, ncyc)
+            xg = xg.cpu().numpy()
+            for r in range(k):
+                xr = x0[r].copy()
+                for _ in range(ncyc):
+                    xr = hier.vcycle(len(hier.levels) - 1, xr, f[r], opts)
+                err = np.max(np.abs(xg[r] - xr)) / np.max(np.abs(xr))
+                tol = 1e-12 if precision == P.PASM_FP64 else 2e-5
+                assert err < tol, (ncyc, r, err)
+
+
+ONE_STEP = [
+    (2, 8, 64, None, "jacobi", 2, 4),
+    (2, 8, 64, None, "cheb", 4, 4),
+    (2, 4, 32, 0.5, "cheb", 4, 2),
+    (3, 4, 16, None, "jacobi", 2, 4),
+]
+
+
+@pytest.mark.parametrize("dim,nc,nf,sig,smoother,nu,k", ONE_STEP)
+def test_one_correction_step_matches_oracle(dim, nc, nf, sig, smoother, nu, k):
+    """Algorithm 1 from the same state: the coarse start, then a perturbed state."""
+    _say(f"one step dim={dim} H=1/{nc} h=1/{nf} sigma={sig} {smoother} k={k}")
+    kap = None if sig is None else lognormal_kappa(dim, nf, seed=5, sigma=sig)
+    prob = O.make_problem(dim, nc, nf, kappa=kap)
+    bvp = O.MultigridBVP(prob, default_options(dim, smoother, nu, nu, 2))
+    lam0, U0, _, _ = O.coarse_start(prob, k)
+    rng = np.random.default_rng(4)
+    U1 = U0 + 0.05 * rng.standard_normal(U0.shape) * np.max(np.abs(U0))
+    lam1 = np.array([(u @ prob.A @ u) / (u @ prob.M @ u) for u in U1])
+    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu)) as s:
+        for lam_in, U_in, from_setup in ((lam0, U0, True), (lam1, U1, False)):
+            if not from_setup:
+                P.pasm_set_state(s.ctx, lam_in, U_in)
+            else:
+                lg, Ug = P.pasm_eigenpairs(s.ctx, k)
+                assert np.max(np.abs(lg - lam0) / lam0) < 1e-13
+                for i in range(k):
+                    ui = Ug[i] if Ug[i] @ U0[i] >= 0 else -Ug[i]
+                    assert np.max(np.abs(ui - U0[i])) < 1e-11 * np.max(np.abs(U0[i]))
+                U_in = Ug
+            s.iterate()
+            lg, Ug = P.pasm_eigenpairs(s.ctx, k)
+            rank, score, flags = P.pasm_last_selection(s.ctx, k)
+            for i in range(k):
+                ref = O.correction_step(prob, lam_in[i], U_in[i], bvp)
+                assert abs(lg[i] - ref["lam"]) / ref["lam"] < 1e-11, (i, lg[i], ref["lam"])
+                assert rank[i] == ref["index"], (i, rank[i], ref["index"])
+                assert score[i] == pytest.approx(ref["score"], rel=1e-8)
+                d = np.max(np.abs(Ug[i] - ref["u"])) / np.max(np.abs(ref["u"]))
+                assert d < 1e-8, (i, d)
+
+
+def _mnorm_dist(u, v, M):
+    v = v if u @ (M @ v) >= 0 else -v
+    d = u - v
+    return float(np.sqrt(d @ (M @ d)))
+
+
+@pytest.mark.parametrize("precision", [P.PASM_FP64, P.PASM_MIXED])
+def test_small_laplace_solve_matches_discrete_eigenpairs(precision):
+    """The 2D workload H = 1/8, h = 1/64, k = 4, Jacobi 2/2, 2 V-cycles."""
+    _say(f"solve lap2d H=1/8 h=1/64 k=4 prec={precision}")
+    prob = O.make_problem(2, 8, 64)
+    w, V = O.discrete_eigenpairs(prob.A, prob.M, 4)
+    with P.Solver(2, 1 / 8, 1 / 64, 4, opts=_opts("jacobi", 2, precision=precision, tol=1e-12)) as s:
+        its = s.solve()
+        lam, U = s.eigenpairs()
+    assert its <= 20
+    tol = 1e-10 if precision == P.PASM_FP64 else 1e-8
+    assert np.max(np.abs(lam - w) / w) < tol
+    for i in range(4):
+        assert _mnorm_dist(U[i], V[:, i], prob.M) < 1e-6
+        assert U[i] @ prob.M @ U[i] == pytest.approx(1.0, abs=1e-10)
+
+
+def test_small_laplace_iteration_history_matches_oracle():
+    """Same trajectory as the oracle's Algorithm 2 with the same V-cycles."""
+    _say("history lap2d H=1/8 h=1/64 k=4")
+    prob = O.make_problem(2, 8, 64)
+    bvp = O.MultigridBVP(prob, default_options(2, "jacobi", 2, 2, 2))
+    ref = O.solve(prob, 4, bvp, tol=1e-10)
+    with P.Solver(2, 1 / 8, 1 / 64, 4, opts=_opts("jacobi", 2, tol=1e-10)) as s:
+        hist = [s.eigenpairs(False)[0]]
+        for _ in range(max(len(h) for h in ref["hist"]) - 1):
+            s.iterate()
+            hist.append(s.eigenpairs(False)[0])
+    for i in range(4):
+        for t, lr in enumerate(ref["hist"][i]):
+            assert abs(hist[t][i] - lr) / lr < 1e-10, (i, t)
+
+
+def test_fine_equal_coarse_returns_coarse_ritz_pairs():
+    _say("h = H")
+    prob = O.make_problem(2, 8, 8)
+    w, _ = O.discrete_eigenpairs(prob.A, prob.M, 3)
+    with P.Solver(2, 1 / 8, 1 / 8, 3, opts=_opts()) as s:
+        s.iterate()
+        lam, _ = s.eigenpairs(False)
+        _, _, flags = P.pasm_last_selection(s.ctx, 3)
+    assert np.max(np.abs(lam - w) / w) < 1e-12
+    assert np.all(flags & 1)
+
+
+def test_3d_solve_with_degenerate_pair():
+    _say("solve lap3d H=1/4 h=1/16 k=4")
+    prob = O.make_problem(3, 4, 16)
+    w, V = O.discrete_eigenpairs(prob.A, prob.M, 4)
+    with P.Solver(3, 1 / 4, 1 / 16, 4, opts=_opts("jacobi", 2, tol=1e-12)) as s:
+        s.solve()
+        lam, U = s.eigenpairs()
+    assert np.max(np.abs(np.sort(lam) - w) / w) < 1e-10
+    # the double eigenvalue: compare subspaces
+    idx = [i for i in range(4) if abs(lam[i] - w[1]) < 1e-8 * w[1]]
+    assert len(idx) == 2
+    Qa, _ = np.linalg.qr(V[:, 1:3])
+    Qb, _ = np.linalg.qr(U[idx].T)
+    assert np.min(np.linalg.svd(Qa.T @ Qb, compute_uv=False)) > 1 - 1e-10
+
+
+def test_variable_kappa_lowest_eigenpair():
+    _say("solve kappa2d H=1/8 h=1/64 k=1")
+    kap = lognormal_kappa(2, 64, seed=4, sigma=0.5)
+    prob = O.make_problem(2, 8, 64, kappa=kap)
+    w, _ = O.discrete_eigenpairs(prob.A, prob.M, 1)
+    for prec, tol in ((P.PASM_FP64, 1e-10), (P.PASM_MIXED, 1e-8)):
+        with P.Solver(2, 1 / 8, 1 / 64, 1, kappa=kap, opts=_opts("cheb", 4, precision=prec, tol=1e-12)) as s:
+            s.solve()
+            lam, _ = s.eigenpairs(False)
+        assert abs(lam[0] - w[0]) / w[0] < tol
