@@ -158,6 +158,16 @@ PASM_API pasm_status pasm_set_state(pasm_ctx* ctx, const double* lambda, const d
  * coarse direction was selected). */
 PASM_API pasm_status pasm_last_selection(const pasm_ctx* ctx, int* rank, double* score, int* flags);
 
+/* The coarse generalized eigenpairs of Algorithm 2, step 1 (h_1 = H):
+ * theta (N_H values, ascending) and Q (N_H x N_H, column j the eigenvector of
+ * theta_j, column-major, Q^T M_H Q = I).  Either pointer may be NULL. */
+PASM_API pasm_status pasm_coarse_eigenpairs(const pasm_ctx* ctx, double* theta, double* Q);
+
+/* Border quantities of the last iteration (Section 3.1, matrix form), host
+ * arrays: beta_zeta[k][2] = (u~^T A_h u~, u~^T M_h u~), p[k][N_H] = Q^T b and
+ * q[k][N_H] = Q^T c with b = P^T A_h u~, c = P^T M_h u~.  Any pointer may be NULL. */
+PASM_API pasm_status pasm_last_borders(const pasm_ctx* ctx, double* beta_zeta, double* p, double* q);
+
 /* Sizes: interior fine nodes, interior coarse nodes, number of levels. */
 PASM_API size_t pasm_num_dofs(const pasm_ctx* ctx);
 PASM_API size_t pasm_coarse_dofs(const pasm_ctx* ctx);

@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
     L.pasm_eigenvectors_device.argtypes = [_P, _P, ctypes.c_size_t]
     L.pasm_set_state.argtypes = [_P, _D, _D, ctypes.c_size_t]
     L.pasm_last_selection.argtypes = [_P, _I, _D, _I]
+    L.pasm_coarse_eigenpairs.argtypes = [_P, _D, _D]
+    L.pasm_last_borders.argtypes = [_P, _D, _D, _D]
     L.pasm_num_dofs.argtypes = [_P]
     L.pasm_num_dofs.restype = ctypes.c_size_t
     L.pasm_coarse_dofs.argtypes = [_P]
@@ -102,8 +104,13 @@ def _dptr(a: np.ndarray):
 
 
 def _torch_ptr(t) -> int:
+    """Device pointer of a float64 CUDA tensor.  Torch's current stream is
+    synchronised first: the library works on its own stream, and must not read
+    the tensor before torch's pending writes to it have landed."""
     import torch
-    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    torch.cuda.current_stream(t.device).synchronize()
     return t.data_ptr()
 
 
@@ -208,6 +215,23 @@ def pasm_last_selection(ctx, k: int):
     flags = np.empty(k, dtype=np.int32)
     _check(lib().pasm_last_selection(ctx, rank.ctypes.data_as(_I), _dptr(score), flags.ctypes.data_as(_I)), ctx)
     return rank, score, flags
+
+
+def pasm_coarse_eigenpairs(ctx):
+    N = pasm_coarse_dofs(ctx)
+    theta = np.empty(N)
+    Q = np.empty((N, N))           # row j = eigenvector j (column-major Q)
+    _check(lib().pasm_coarse_eigenpairs(ctx, _dptr(theta), _dptr(Q)), ctx)
+    return theta, Q.T.copy()
+
+
+def pasm_last_borders(ctx, k: int):
+    N = pasm_coarse_dofs(ctx)
+    bz = np.empty((k, 2))
+    p = np.empty((k, N))
+    q = np.empty((k, N))
+    _check(lib().pasm_last_borders(ctx, _dptr(bz), _dptr(p), _dptr(q)), ctx)
+    return bz, p, q
 
 
 def pasm_apply_operator(ctx, level: int, op: int, x, y) -> None:

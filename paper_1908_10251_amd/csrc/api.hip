@@ -97,8 +97,10 @@ struct pasm_ctx {
     bool own_stream = false;
     bool mixed = false;
     std::vector<pasm::Level> lv;
-    // finest level, FP64
+    // finest level, FP64 (padded layout: boundary entries stay zero)
     double *U = nullptr, *F64 = nullptr, *Y64 = nullptr, *R64 = nullptr;
+    // compact [k][N] staging for host transfers; never used as a padded grid
+    double* stage = nullptr;
     // finest level, FP32 (mixed)
     float *E32 = nullptr, *R32 = nullptr, *Y32 = nullptr;
     // coarse space
@@ -286,18 +288,20 @@ void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb
     const Coef<T> cf = c->coef<T>(l);
     const bool fine = (l == c->L - 1);
     for (size_t j = 0; j < steps.size(); ++j) {
+        // starting from x = 0: step 0 does not read x_0, step 1 does not read x_{-1} = x_0
         const bool z = x_zero && j == 0;
+        const int zmode = (z ? 1 : 0) | ((x_zero && j == 1) ? 2 : 0);
         if (fine) {
             // algorithmic bytes: read x_k (unless zero), x_{k-1} (if a != 0), f; write x_{k+1};
             // plus the coefficient arrays once per launch
-            const double words = 2.0 + (z ? 0.0 : 1.0) + (steps[j].a != 0.0 && !z ? 1.0 : 0.0);
+            const double words = 2.0 + (z ? 0.0 : 1.0) + (steps[j].a != 0.0 && !z && !(zmode & 2) ? 1.0 : 0.0);
             double bytes = words * sizeof(T) * (double)L.g.interior() * nrhs;
             if (!L.const_coef) bytes += (double)L.g.dim * sizeof(T) * (double)L.g.interior();
             record_start(c);
-            pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], z, c->st);
+            pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], zmode, c->st);
             record_end(c, bytes);
         } else {
-            pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], z, c->st);
+            pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], zmode, c->st);
         }
         std::swap(x, y);
     }
@@ -496,6 +500,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->F64 = c->alloc<double>(nf);
     c->Y64 = c->alloc<double>(nf);
     c->R64 = c->alloc<double>(nf);
+    c->stage = c->alloc<double>((size_t)c->gf().interior() * k);
     if (c->mixed) {
         c->E32 = c->alloc<float>(nf);
         c->R32 = c->alloc<float>(nf);
@@ -832,8 +837,8 @@ PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* cc, double* lambda, double*
     PASM_TRY(c, {
         if (lambda) std::memcpy(lambda, c->lam_h.data(), c->k * sizeof(double));
         if (U) {
-            pasm::launch_pack<double>(c->gf(), c->U, c->sf(), c->Y64, (long)N, c->k, c->st);
-            PASM_HIP(hipMemcpy2DAsync(U, ldu * sizeof(double), c->Y64, N * sizeof(double), N * sizeof(double), c->k,
+            pasm::launch_pack<double>(c->gf(), c->U, c->sf(), c->stage, (long)N, c->k, c->st);
+            PASM_HIP(hipMemcpy2DAsync(U, ldu * sizeof(double), c->stage, N * sizeof(double), N * sizeof(double), c->k,
                                       hipMemcpyDeviceToHost, c->st));
             PASM_HIP(hipStreamSynchronize(c->st));
         }
@@ -863,9 +868,9 @@ PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const dou
         c->lam_prev_h = c->lam_h;
         PASM_HIP(hipMemcpyAsync(c->lam, lambda, c->k * sizeof(double), hipMemcpyHostToDevice, c->st));
         PASM_HIP(hipMemcpyAsync(c->lam_prev, lambda, c->k * sizeof(double), hipMemcpyHostToDevice, c->st));
-        PASM_HIP(hipMemcpy2DAsync(c->Y64, N * sizeof(double), U, ldu * sizeof(double), N * sizeof(double), c->k,
+        PASM_HIP(hipMemcpy2DAsync(c->stage, N * sizeof(double), U, ldu * sizeof(double), N * sizeof(double), c->k,
                                   hipMemcpyHostToDevice, c->st));
-        pasm::launch_unpack<double>(c->gf(), c->Y64, (long)N, c->U, c->sf(), c->k, c->st);
+        pasm::launch_unpack<double>(c->gf(), c->stage, (long)N, c->U, c->sf(), c->k, c->st);
         PASM_HIP(hipStreamSynchronize(c->st));
     });
     return PASM_OK;
@@ -878,6 +883,31 @@ PASM_API pasm_status pasm_last_selection(const pasm_ctx* cc, int* rank, double* 
         if (rank) PASM_HIP(hipMemcpyAsync(rank, c->rank, c->k * sizeof(int), hipMemcpyDeviceToHost, c->st));
         if (score) PASM_HIP(hipMemcpyAsync(score, c->score, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
         if (flags) PASM_HIP(hipMemcpyAsync(flags, c->flags, c->k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_coarse_eigenpairs(const pasm_ctx* cc, double* theta, double* Q) {
+    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    if (!c || c->k == 0) return PASM_E_STATE;
+    const size_t N = c->NH;
+    PASM_TRY(c, {
+        if (theta) PASM_HIP(hipMemcpyAsync(theta, c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        if (Q) PASM_HIP(hipMemcpyAsync(Q, c->Qcm, N * N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_last_borders(const pasm_ctx* cc, double* beta_zeta, double* p, double* q) {
+    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    if (!c || c->k == 0) return PASM_E_STATE;
+    const size_t N = c->NH, k = c->k;
+    PASM_TRY(c, {
+        if (beta_zeta) PASM_HIP(hipMemcpyAsync(beta_zeta, c->bz, 2 * k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        if (p) PASM_HIP(hipMemcpyAsync(p, c->pp, N * k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        if (q) PASM_HIP(hipMemcpyAsync(q, c->qq, N * k * sizeof(double), hipMemcpyDeviceToHost, c->st));
         PASM_HIP(hipStreamSynchronize(c->st));
     });
     return PASM_OK;

@@ -85,9 +85,10 @@ struct Cheb {
     double b;   // weight of D^{-1}(f - A x_k)
 };
 
+// zmode bit 0: x_k is zero (not read); bit 1: x_{k-1} is zero (not read)
 template <typename T>
 void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
-                   int nrhs, long stride, Cheb s, bool x_zero, hipStream_t st);
+                   int nrhs, long stride, Cheb s, int zmode, hipStream_t st);
 
 template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,

@@ -54,14 +54,14 @@ struct Stiff2 {
 template <typename T, bool CONST>
 __global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> c, const T* __restrict__ xc,
                                                    const T* xp, const T* __restrict__ f, T* xn,
-                                                   long stride, T a, T b, int x_zero) {
+                                                   long stride, T a, T b, int zmode) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
     const long off = (long)blockIdx.z * stride;
     const long id = g.idx(i, j);
     const T fv = f[off + id];
-    if (x_zero) {
+    if (zmode & 1) {
         const T D = Stiff2<T, CONST>::diag(g, c, id);
         xn[off + id] = b * fv / D;
         return;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> c, const T* _
     Stiff2<T, CONST>::apply(g, c, xc + off, id, Ax, D);
     const T x0 = xc[off + id];
     T v = x0 + b * (fv - Ax) / D;
-    if (a != T(0)) v += a * (x0 - xp[off + id]);
+    if (a != T(0)) v += a * (x0 - ((zmode & 2) ? T(0) : xp[off + id]));
     xn[off + id] = v;
 }
 
@@ -290,7 +290,7 @@ inline int flat_blocks(long n) {
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_smooth3(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
-                    int nrhs, long stride, Cheb s, bool x_zero, hipStream_t st);
+                    int nrhs, long stride, Cheb s, int zmode, hipStream_t st);
 template <typename T>
 void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
                             T* rc, int nrhs, long sf, long sc, hipStream_t st);
@@ -315,15 +315,15 @@ void launch_unpack3(const Grid& g, const double* compact, long ld, T* padded, lo
 
 template <typename T>
 void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
-                   int nrhs, long stride, Cheb s, bool x_zero, hipStream_t st) {
-    if (g.dim == 3) return launch_smooth3<T>(g, c, xc, xp, f, xn, nrhs, stride, s, x_zero, st);
+                   int nrhs, long stride, Cheb s, int zmode, hipStream_t st) {
+    if (g.dim == 3) return launch_smooth3<T>(g, c, xc, xp, f, xn, nrhs, stride, s, zmode, st);
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
     if (c.wx)
         hipLaunchKernelGGL((k_smooth<T, false>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a,
-                           (T)s.b, (int)x_zero);
+                           (T)s.b, zmode);
     else
         hipLaunchKernelGGL((k_smooth<T, true>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a,
-                           (T)s.b, (int)x_zero);
+                           (T)s.b, zmode);
     PASM_CHECK_LAUNCH();
 }
 
@@ -437,7 +437,7 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
 
 #define PASM_INST(T)                                                                                  \
     template void launch_smooth<T>(const Grid&, const Coef<T>&, const T*, const T*, const T*, T*, int,  \
-                                   long, Cheb, bool, hipStream_t);                                      \
+                                   long, Cheb, int, hipStream_t);                                      \
     template void launch_apply_A<T>(const Grid&, const Coef<T>&, const T*, T*, int, long, hipStream_t); \
     template void launch_resid_restrict<T>(const Grid&, const Coef<T>&, const T*, const T*, const Grid&, \
                                            T*, int, long, long, hipStream_t);                           \

@@ -65,13 +65,13 @@ __device__ inline T diag3(const Grid& g, const Coef<T>& c, long id) {
 template <typename T, bool CONST>
 __global__ __launch_bounds__(BX* BY) void k_smooth3(Grid g, Coef<T> c, const T* __restrict__ xc, const T* xp,
                                                     const T* __restrict__ f, T* xn, long stride, T a, T b,
-                                                    int x_zero) {
+                                                    int zmode) {
     const Pos p = pos3(g.m);
     if (!p.ok) return;
     const long off = (long)p.r * stride;
     const long id = g.idx(p.i, p.j, p.l);
     const T fv = f[off + id];
-    if (x_zero) {
+    if (zmode & 1) {
         xn[off + id] = b * fv / diag3<T, CONST>(g, c, id);
         return;
     }
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(BX* BY) void k_smooth3(Grid g, Coef<T> c, const T* 
     stiff3<T, CONST>(g, c, xc + off, id, Ax, D);
     const T x0 = xc[off + id];
     T v = x0 + b * (fv - Ax) / D;
-    if (a != T(0)) v += a * (x0 - xp[off + id]);
+    if (a != T(0)) v += a * (x0 - ((zmode & 2) ? T(0) : xp[off + id]));
     xn[off + id] = v;
 }
 
@@ -243,13 +243,13 @@ __global__ void k_unpack3(Grid g, const double* __restrict__ compact, long ld, T
 
 template <typename T>
 void launch_smooth3(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn, int nrhs,
-                    long stride, Cheb s, bool x_zero, hipStream_t st) {
+                    long stride, Cheb s, int zmode, hipStream_t st) {
     if (c.wx)
         hipLaunchKernelGGL((k_smooth3<T, false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, xc, xp, f, xn,
-                           stride, (T)s.a, (T)s.b, (int)x_zero);
+                           stride, (T)s.a, (T)s.b, zmode);
     else
         hipLaunchKernelGGL((k_smooth3<T, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, xc, xp, f, xn,
-                           stride, (T)s.a, (T)s.b, (int)x_zero);
+                           stride, (T)s.a, (T)s.b, zmode);
     PASM_CHECK_LAUNCH();
 }
 
@@ -329,7 +329,7 @@ void launch_unpack3(const Grid& g, const double* compact, long ld, T* padded, lo
 
 #define PASM_INST3(T)                                                                                    \
     template void launch_smooth3<T>(const Grid&, const Coef<T>&, const T*, const T*, const T*, T*, int,   \
-                                    long, Cheb, bool, hipStream_t);                                       \
+                                    long, Cheb, int, hipStream_t);                                       \
     template void launch_apply_A3<T>(const Grid&, const Coef<T>&, const T*, T*, int, long, hipStream_t);  \
     template void launch_resid_restrict3<T>(const Grid&, const Coef<T>&, const T*, const T*, const Grid&, \
                                             T*, int, long, long, hipStream_t);                            \

@@ -89,7 +89,10 @@ def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, precision):
     f = rng.standard_normal((k, N))
     x0 = rng.standard_normal((k, N))
     with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu, precision=precision)) as s:
-        for ncyc in (1, 2):
+        # host transfers of the state must leave the grids' zero boundary intact
+        lam, U = s.eigenpairs()
+        P.pasm_set_state(s.ctx, lam, U)
+        for ncyc in (2, 1, 2):
             xg = _t(x0)
             P.pasm_vcycle(s.ctx, _t(f), xg, ncyc)
             xg = xg.cpu().numpy()
@@ -100,6 +103,18 @@ def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, precision):
                 err = np.max(np.abs(xg[r] - xr)) / np.max(np.abs(xr))
                 tol = 1e-12 if precision == P.PASM_FP64 else 2e-5
                 assert err < tol, (ncyc, r, err)
+
+
+def _clusters(vals, rtol=1e-10):
+    out, cur = [], [0]
+    for i in range(1, len(vals)):
+        if abs(vals[i] - vals[cur[-1]]) <= rtol * abs(vals[i]):
+            cur.append(i)
+        else:
+            out.append(cur)
+            cur = [i]
+    out.append(cur)
+    return out
 
 
 ONE_STEP = [
@@ -128,15 +143,41 @@ def test_one_correction_step_matches_oracle(dim, nc, nf, sig, smoother, nu, k):
             else:
                 lg, Ug = P.pasm_eigenpairs(s.ctx, k)
                 assert np.max(np.abs(lg - lam0) / lam0) < 1e-13
-                for i in range(k):
-                    ui = Ug[i] if Ug[i] @ U0[i] >= 0 else -Ug[i]
-                    assert np.max(np.abs(ui - U0[i])) < 1e-11 * np.max(np.abs(U0[i]))
+                # start vectors: equal up to sign, or the same subspace inside a
+                # cluster of equal coarse eigenvalues (any basis is valid there)
+                for grp in _clusters(lam0):
+                    if len(grp) == 1:
+                        i = grp[0]
+                        ui = Ug[i] if Ug[i] @ U0[i] >= 0 else -Ug[i]
+                        assert np.max(np.abs(ui - U0[i])) < 1e-11 * np.max(np.abs(U0[i]))
+                    else:
+                        Qa, _ = np.linalg.qr(U0[grp].T)
+                        Qb, _ = np.linalg.qr(Ug[grp].T)
+                        assert np.min(np.linalg.svd(Qa.T @ Qb, compute_uv=False)) > 1 - 1e-12
                 U_in = Ug
             s.iterate()
             lg, Ug = P.pasm_eigenpairs(s.ctx, k)
             rank, score, flags = P.pasm_last_selection(s.ctx, k)
+            theta, Qg = P.pasm_coarse_eigenpairs(s.ctx)
+            bz, pg, qg = P.pasm_last_borders(s.ctx, k)
+            assert np.max(np.abs(theta - O.coarse_start(prob, k)[2]) / theta) < 1e-12
+            assert np.max(np.abs(Qg.T @ prob.MH @ Qg - np.eye(len(theta)))) < 1e-11
             for i in range(k):
                 ref = O.correction_step(prob, lam_in[i], U_in[i], bvp)
+                assert bz[i, 0] == pytest.approx(ref["beta"], rel=1e-11), (i, bz[i], ref["beta"], ref["zeta"])
+                assert bz[i, 1] == pytest.approx(ref["zeta"], rel=1e-11), (i, bz[i], ref["beta"], ref["zeta"])
+                np.testing.assert_allclose(pg[i], Qg.T @ ref["b"], rtol=0, atol=1e-10 * np.max(np.abs(pg[i])))
+                np.testing.assert_allclose(qg[i], Qg.T @ ref["c"], rtol=0, atol=1e-10 * np.max(np.abs(qg[i])))
+                # the arrowhead reduction of the same borders, solved densely
+                zp = bz[i, 1] - qg[i] @ qg[i]
+                gv = (pg[i] - theta * qg[i]) / np.sqrt(zp)
+                rho = (bz[i, 0] - 2 * qg[i] @ pg[i] + qg[i] @ (theta * qg[i])) / zp
+                Ar = np.diag(np.concatenate([theta, [rho]]))
+                Ar[:-1, -1] = gv
+                Ar[-1, :-1] = gv
+                wa, Va = np.linalg.eigh(Ar)
+                ja = int(np.argmax(np.abs(Va[:-1].T @ qg[i] + Va[-1] * np.sqrt(zp))))
+                assert abs(lg[i] - wa[ja]) / wa[ja] < 1e-11, (i, lg[i], wa[ja], ref["lam"])
                 assert abs(lg[i] - ref["lam"]) / ref["lam"] < 1e-11, (i, lg[i], ref["lam"])
                 assert rank[i] == ref["index"], (i, rank[i], ref["index"])
                 assert score[i] == pytest.approx(ref["score"], rel=1e-8)
