@@ -111,6 +111,7 @@ struct pasm_ctx {
     double *s = nullptr, *mu = nullptr, *lam = nullptr, *lam_prev = nullptr, *score = nullptr;
     int *rank = nullptr, *flags = nullptr;
     void* awork = nullptr;
+    void* dmv = nullptr;   // split-K workspace of the dense coarse products
     std::vector<void*> allocs;
     std::vector<double> lam_h, lam_prev_h;
     std::string err;
@@ -319,7 +320,7 @@ template <typename T>
 void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs) {
     const pasm::Level& L = c->lv[l];
     if (l == 0) {
-        pasm::launch_dense_mv<T>(ainv<T>(c), c->NH, L.g, f, L.g.plane, true, x, L.g.plane, true, nrhs, c->st);
+        pasm::launch_dense_mv<T>(ainv<T>(c), c->NH, L.g, f, L.g.plane, true, x, L.g.plane, true, nrhs, c->dmv, c->st);
         return;
     }
     smooth<T>(c, l, x, y, f, L.pre, x_zero, nrhs);
@@ -529,6 +530,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->rank = c->alloc<int>(k);
     c->flags = c->alloc<int>(k);
     c->awork = c->alloc<char>(pasm::arrow_workspace_bytes(N, k));
+    c->dmv = c->alloc<char>(pasm::dense_mv_workspace_bytes(N, k));
 
     // dense coarse pencil from the level-0 operators (Galerkin: rediscretised
     // with the coarsened coefficient)
@@ -648,10 +650,10 @@ void prolong_coefs(pasm_ctx* c, const double* s) {
     const pasm::Level& L0 = c->lv[0];
     if (c->L == 1) {
         // the fine level is V_H itself: the augmentation is always skipped (s = 0)
-        pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->U, L0.g.plane, true, k, c->st);
+        pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->U, L0.g.plane, true, k, c->dmv, c->st);
         return;
     }
-    pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->lv[0].B, L0.g.plane, true, k, c->st);
+    pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->lv[0].B, L0.g.plane, true, k, c->dmv, c->st);
     for (int l = 1; l < c->L - 1; ++l)
         pasm::launch_prolong<double>(c->lv[l - 1].g, c->lv[l - 1].B, c->lv[l].g, c->lv[l].B, k, c->lv[l - 1].g.plane,
                                      c->lv[l].g.plane, false, nullptr, c->st);
@@ -669,7 +671,7 @@ void iterate_once(pasm_ctx* c) {
         bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles);
     } else {
         // fine level = V_H: exact solve
-        pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->st);
+        pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->dmv, c->st);
     }
     // step 2: borders
     const int nblk = pasm::launch_border(g, c->coef<double>(lf), c->U, c->Y64, c->R64, c->partial, k, sf, c->st);
@@ -684,8 +686,8 @@ void iterate_once(pasm_ctx* c) {
         csrc = c->lv[l].C;
     }
     const Grid& g0 = c->lv[0].g;
-    pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, k, c->st);
-    pasm::launch_dense_mv<double>(c->Qrm, N, g0, csrc, g0.plane, true, c->qq, N, false, k, c->st);
+    pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, k, c->dmv, c->st);
+    pasm::launch_dense_mv<double>(c->Qrm, N, g0, csrc, g0.plane, true, c->qq, N, false, k, c->dmv, c->st);
     pasm::ArrowIn in{c->theta, c->group, c->pp, c->qq, c->bz, c->lam, N};
     pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
     pasm::launch_arrowhead(in, out, k, c->st);
@@ -964,7 +966,7 @@ PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t
         double* yb = c->Y64;
         if (c->L > 1) bvp_cycles(c, xb, yb, c->F64, nrhs, ncycles);
         else if (ncycles > 0)
-            pasm::launch_dense_mv<double>(c->Ainv64, c->NH, g, c->F64, g.plane, true, xb, g.plane, true, nrhs, c->st);
+            pasm::launch_dense_mv<double>(c->Ainv64, c->NH, g, c->F64, g.plane, true, xb, g.plane, true, nrhs, c->dmv, c->st);
         pasm::launch_pack<double>(g, xb, g.plane, x, (long)ld, nrhs, c->st);
         PASM_HIP(hipStreamSynchronize(c->st));
     });

@@ -42,10 +42,14 @@ constexpr double TIE_RTOL = 1e-12;
 
 // ---------------------------------------------------------------------------
 // dense matrix times k vectors, y[r] = Mat x[r], Mat(row,col) at Mat[col*N+row]
+//
+// Split over column chunks so that even N ~ 10^3 gives hundreds of
+// workgroups: pass 1 writes per-chunk partial sums, pass 2 adds the chunks in
+// a fixed order (deterministic, no atomics).
 // ---------------------------------------------------------------------------
-constexpr int MV_THREADS = 256;
-constexpr int MV_RC = 8;     // right-hand sides per block
-constexpr int MV_CT = 256;   // columns per LDS tile
+constexpr int DM_R = 64;   // rows per workgroup (one per thread)
+constexpr int DM_C = 64;   // columns per chunk
+constexpr int DM_K = 16;   // right-hand sides per workgroup
 
 __device__ inline long compact_to_padded(const Grid& g, int c) {
     const int i = c % g.m + 1;
@@ -55,45 +59,47 @@ __device__ inline long compact_to_padded(const Grid& g, int c) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(MV_THREADS) void k_dense_mv(const T* __restrict__ Mat, int N, Grid g,
-                                                         const T* __restrict__ x, long sx, int xpad,
-                                                         T* __restrict__ y, long sy, int ypad, int nrhs) {
-    __shared__ T xs[MV_RC][MV_CT];
-    const int row = blockIdx.x * MV_THREADS + threadIdx.x;
-    const int r0 = blockIdx.y * MV_RC;
-    T acc[MV_RC];
-#pragma unroll
-    for (int rr = 0; rr < MV_RC; ++rr) acc[rr] = T(0);
-    for (int c0 = 0; c0 < N; c0 += MV_CT) {
-        const int cn = min(MV_CT, N - c0);
-        for (int t = threadIdx.x; t < MV_RC * MV_CT; t += MV_THREADS) {
-            const int rr = t / MV_CT, cc = t % MV_CT;
-            T v = T(0);
-            if (r0 + rr < nrhs && cc < cn) {
-                const long base = (long)(r0 + rr) * sx;
-                v = xpad ? x[base + compact_to_padded(g, c0 + cc)] : x[base + c0 + cc];
-            }
-            xs[rr][cc] = v;
+__global__ __launch_bounds__(DM_R) void k_dmv_part(const T* __restrict__ Mat, int N, Grid g, const T* __restrict__ x,
+                                                   long sx, int xpad, T* __restrict__ part, int nrhs) {
+    __shared__ T xs[DM_K][DM_C];
+    const int row = blockIdx.x * DM_R + threadIdx.x;
+    const int c0 = blockIdx.y * DM_C;
+    const int r0 = blockIdx.z * DM_K;
+    const int cn = min(DM_C, N - c0);
+    for (int t = threadIdx.x; t < DM_K * DM_C; t += DM_R) {
+        const int rr = t / DM_C, cc = t % DM_C;
+        T v = T(0);
+        if (r0 + rr < nrhs && cc < cn) {
+            const long base = (long)(r0 + rr) * sx;
+            v = xpad ? x[base + compact_to_padded(g, c0 + cc)] : x[base + c0 + cc];
         }
-        __syncthreads();
-        if (row < N) {
-            for (int cc = 0; cc < cn; ++cc) {
-                const T a = Mat[(long)(c0 + cc) * N + row];
-#pragma unroll
-                for (int rr = 0; rr < MV_RC; ++rr) acc[rr] += a * xs[rr][cc];
-            }
-        }
-        __syncthreads();
+        xs[rr][cc] = v;
     }
-    if (row < N) {
+    __syncthreads();
+    if (row >= N) return;
+    T acc[DM_K];
 #pragma unroll
-        for (int rr = 0; rr < MV_RC; ++rr) {
-            if (r0 + rr >= nrhs) break;
-            const long base = (long)(r0 + rr) * sy;
-            if (ypad) y[base + compact_to_padded(g, row)] = acc[rr];
-            else y[base + row] = acc[rr];
-        }
+    for (int rr = 0; rr < DM_K; ++rr) acc[rr] = T(0);
+    for (int cc = 0; cc < cn; ++cc) {
+        const T a = Mat[(long)(c0 + cc) * N + row];
+#pragma unroll
+        for (int rr = 0; rr < DM_K; ++rr) acc[rr] += a * xs[rr][cc];
     }
+#pragma unroll
+    for (int rr = 0; rr < DM_K; ++rr)
+        if (r0 + rr < nrhs) part[((long)blockIdx.y * nrhs + r0 + rr) * N + row] = acc[rr];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dmv_sum(int N, int nchunk, const T* __restrict__ part, int nrhs, Grid g,
+                                                 T* __restrict__ y, long sy, int ypad) {
+    const int row = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    if (row >= N) return;
+    T s = T(0);
+    for (int c = 0; c < nchunk; ++c) s += part[((long)c * nrhs + r) * N + row];
+    const long base = (long)r * sy;
+    if (ypad) y[base + compact_to_padded(g, row)] = s;
+    else y[base + row] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -292,100 +298,160 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double zn2 = 0.0;
-        const int nact = skip ? 0 : (int)w.sc[S_NA];
-        for (int t = 0; t < nact; ++t) zn2 += w.z[t] * w.z[t];
+    // |z| over the active poles (a block reduction, fixed order)
+    const int nact = skip ? 0 : (int)w.sc[S_NA];
+    double zn2 = 0.0;
+    for (int t = threadIdx.x; t < nact; t += PT) zn2 += w.z[t] * w.z[t];
+    zn2 = block_sum(zn2, sh);
+    if (threadIdx.x == 0 && nact > 0) {
         const double zn = sqrt(zn2);
-        if (nact > 0) {
-            w.sc[S_LO] = fmin(w.d[0], rho) - zn - 1e-300;
-            w.sc[S_HI] = fmax(w.d[nact - 1], rho) + zn + 1e-300;
-        }
+        w.sc[S_LO] = fmin(w.d[0], rho) - zn;
+        w.sc[S_HI] = fmax(w.d[nact - 1], rho) + zn;
     }
 }
 
-// Stage B: one thread per root of the secular equation.
-constexpr int RT = 64;
+// Stage B: roots of the secular equation, one wavefront per root; the 64
+// lanes split the sums over the poles and combine them with an xor butterfly,
+// which leaves the same (bitwise) value in every lane, so the iteration stays
+// uniform across the wavefront.
+//
+// Root r lies between consecutive poles (or beyond an end).  The pole nearer
+// to the root (decided from the sign of f at the interval midpoint) becomes
+// the origin, tau = mu - origin, and Newton's method is applied to
+// h(tau) = tau f(tau), which no longer has a pole at the origin; iterates are
+// kept inside the shrinking sign bracket (bisection otherwise).
+constexpr int RW = 64;          // lanes per root
+constexpr int RWAVES = 4;       // wavefronts per block
+constexpr int RPB = 16;         // roots per block (each wavefront takes 4 in turn)
+constexpr int LDS_POLES = 2600; // poles kept in LDS up to this count
 
-__global__ __launch_bounds__(RT) void k_arrow_roots(ArrowIn in, double* work, int* iwork, double* best, int nchunk) {
-    __shared__ double ss[RT], sm[RT], sr[RT];
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* work, int* iwork, double* best,
+                                                            int nchunk) {
+    __shared__ double sd[LDS ? LDS_POLES : 1], sz[LDS ? LDS_POLES : 1], sqa[LDS ? LDS_POLES : 1];
+    __shared__ double ss[RPB], sm[RPB];
     const int r = blockIdx.x, N = in.N;
     WS w = ws_of(work, iwork, best, N, nchunk, r);
     const int na = (int)w.sc[S_NA];
     const double rho = w.sc[S_RHO], sq = w.sc[S_SQ], lp = in.lam_prev[r];
-    const int root = blockIdx.y * RT + threadIdx.x;
-    double score = -1.0, mu = 0.0;
-    if (na >= 0 && root <= na) {
-        if (na == 0) {
-            mu = rho;
-            score = sq;
-            w.rmu[0] = rho;
-            w.rtau[0] = 0.0;
-            w.rorg[0] = rho;
-        } else {
-            const double* d = w.d;
-            const double* z = w.z;
-            const double left = root == 0 ? w.sc[S_LO] : d[root - 1];
-            const double right = root == na ? w.sc[S_HI] : d[root];
-            double org;
-            if (root == 0) org = d[0];
-            else if (root == na) org = d[na - 1];
-            else {
-                const double mid = 0.5 * (left + right);
-                double fm = rho - mid;
-                for (int a = 0; a < na; ++a) fm += z[a] * z[a] / (mid - d[a]);
-                org = fm > 0.0 ? right : left;
-            }
-            double lo = left - org, hi = right - org;
-            const double c0 = rho - org;
-            double tau = 0.5 * (lo + hi);
-            for (int it = 0; it < 200; ++it) {
-                double F = c0 - tau, dF = -1.0, mag = fabs(c0) + fabs(tau);
-                for (int a = 0; a < na; ++a) {
-                    const double inv = 1.0 / (tau - (d[a] - org));
-                    const double t1 = z[a] * inv;
-                    F += z[a] * t1;
-                    dF -= t1 * t1;
-                    mag += fabs(z[a] * t1);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double* d = w.d;
+    const double* z = w.z;
+    const double* qa = w.qa;
+    if (LDS) {
+        for (int a = threadIdx.x; a < na; a += RW * RWAVES) {
+            sd[a] = w.d[a];
+            sz[a] = w.z[a];
+            sqa[a] = w.qa[a];
+        }
+        __syncthreads();
+        d = sd;
+        z = sz;
+        qa = sqa;
+    }
+    for (int slot = wave; slot < RPB; slot += RWAVES) {
+        const int root = blockIdx.y * RPB + slot;
+        double score = -1.0, mu = 0.0;
+        if (na >= 0 && root <= na) {
+            if (na == 0) {
+                mu = rho;
+                score = sq;
+                if (lane == 0) {
+                    w.rmu[0] = rho;
+                    w.rtau[0] = 0.0;
+                    w.rorg[0] = rho;
                 }
-                if (F == 0.0) break;
-                if (F > 0.0) lo = tau;
-                else hi = tau;
-                if (fabs(F) <= 4.0 * EPS * mag) break;
-                double tn = tau - F / dF;
-                if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-                const double step = fabs(tn - tau);
-                tau = tn;
-                if (step <= 2.0 * EPS * fabs(tau) || hi - lo <= 4.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+            } else {
+                const double left = root == 0 ? w.sc[S_LO] : d[root - 1];
+                const double right = root == na ? w.sc[S_HI] : d[root];
+                double org, lo, hi;
+                if (root == 0) {
+                    org = d[0];
+                    lo = left - org;
+                    hi = 0.0;
+                } else if (root == na) {
+                    org = d[na - 1];
+                    lo = 0.0;
+                    hi = right - org;
+                } else {
+                    const double mid = 0.5 * (left + right);
+                    double fm = 0.0;
+                    for (int a = lane; a < na; a += RW) fm += z[a] * z[a] / (mid - d[a]);
+                    fm = wave_sum(fm) + (rho - mid);
+                    if (fm > 0.0) {  // root in (mid, right): origin at the right pole
+                        org = right;
+                        lo = mid - org;
+                        hi = 0.0;
+                    } else {
+                        org = left;
+                        lo = 0.0;
+                        hi = mid - org;
+                    }
+                }
+                const double c0 = rho - org;
+                double tau = 0.5 * (lo + hi);
+                for (int it = 0; it < 100; ++it) {
+                    double F = 0.0, dF = 0.0, mag = 0.0;
+                    for (int a = lane; a < na; a += RW) {
+                        const double t1 = z[a] / (tau - (d[a] - org));
+                        F += z[a] * t1;
+                        dF -= t1 * t1;
+                        mag += fabs(z[a] * t1);
+                    }
+                    F = wave_sum(F) + (c0 - tau);
+                    dF = wave_sum(dF) - 1.0;
+                    mag = wave_sum(mag) + fabs(c0) + fabs(tau);
+                    if (F == 0.0) break;
+                    if (F > 0.0) lo = tau;
+                    else hi = tau;
+                    if (fabs(F) <= 4.0 * EPS * mag) break;
+                    const double hval = tau * F, dh = F + tau * dF;
+                    double tn = tau - hval / dh;
+                    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+                    const double step = fabs(tn - tau);
+                    tau = tn;
+                    if (step <= 2.0 * EPS * fabs(tau) || hi - lo <= 4.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+                }
+                double S1 = 0.0, S2 = 0.0;
+                for (int a = lane; a < na; a += RW) {
+                    const double v = z[a] / (tau - (d[a] - org));
+                    S1 += v * v;
+                    S2 += v * qa[a];
+                }
+                S1 = wave_sum(S1);
+                S2 = wave_sum(S2);
+                const double t = 1.0 / sqrt(1.0 + S1);
+                score = fabs(t * (S2 + sq));
+                mu = org + tau;
+                if (lane == 0) {
+                    w.rmu[root] = mu;
+                    w.rtau[root] = tau;
+                    w.rorg[root] = org;
+                }
             }
-            double S1 = 0.0, S2 = 0.0;
-            for (int a = 0; a < na; ++a) {
-                const double v = z[a] / (tau - (d[a] - org));
-                S1 += v * v;
-                S2 += v * w.qa[a];
-            }
-            const double t = 1.0 / sqrt(1.0 + S1);
-            score = fabs(t * (S2 + sq));
-            mu = org + tau;
-            w.rmu[root] = mu;
-            w.rtau[root] = tau;
-            w.rorg[root] = org;
+        }
+        if (lane == 0) {
+            ss[slot] = score;
+            sm[slot] = mu;
         }
     }
-    ss[threadIdx.x] = score;
-    sm[threadIdx.x] = mu;
-    sr[threadIdx.x] = (double)root;
     __syncthreads();
     if (threadIdx.x == 0) {
         int bi = -1;
-        for (int t = 0; t < RT; ++t) {
+        for (int t = 0; t < RPB; ++t) {
             if (ss[t] < 0.0) continue;
             if (bi < 0 || better(ss[t], sm[t], ss[bi], sm[bi], lp)) bi = t;
         }
         double* b = w.best + 4L * blockIdx.y;
         b[0] = bi < 0 ? -1.0 : ss[bi];
         b[1] = bi < 0 ? 0.0 : sm[bi];
-        b[2] = bi < 0 ? -1.0 : sr[bi];
+        b[2] = bi < 0 ? -1.0 : (double)(blockIdx.y * RPB + bi);
         b[3] = 0.0;
     }
 }
@@ -516,19 +582,27 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
 
 template <typename T>
 void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded, T* y, long sy,
-                     bool y_padded, int nrhs, hipStream_t st) {
-    dim3 grid((N + MV_THREADS - 1) / MV_THREADS, (nrhs + MV_RC - 1) / MV_RC);
-    hipLaunchKernelGGL((k_dense_mv<T>), grid, dim3(MV_THREADS), 0, st, Mat, N, g, x, sx, (int)x_padded, y, sy,
-                       (int)y_padded, nrhs);
+                     bool y_padded, int nrhs, void* work, hipStream_t st) {
+    const int nchunk = (N + DM_C - 1) / DM_C;
+    T* part = static_cast<T*>(work);
+    dim3 g1((N + DM_R - 1) / DM_R, nchunk, (nrhs + DM_K - 1) / DM_K);
+    hipLaunchKernelGGL((k_dmv_part<T>), g1, dim3(DM_R), 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs);
+    PASM_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_dmv_sum<T>), dim3((N + 255) / 256, nrhs), dim3(256), 0, st, N, nchunk, part, nrhs, g, y, sy,
+                       (int)y_padded);
     PASM_CHECK_LAUNCH();
 }
 template void launch_dense_mv<double>(const double*, int, const Grid&, const double*, long, bool, double*, long,
-                                      bool, int, hipStream_t);
+                                      bool, int, void*, hipStream_t);
 template void launch_dense_mv<float>(const float*, int, const Grid&, const float*, long, bool, float*, long, bool,
-                                     int, hipStream_t);
+                                     int, void*, hipStream_t);
+
+size_t dense_mv_workspace_bytes(int N, int nrhs) {
+    return sizeof(double) * (size_t)((N + DM_C - 1) / DM_C) * nrhs * N;
+}
 
 long arrow_work_doubles(int N, int k) { return ws_doubles(N) * (long)k; }
-int arrow_chunks(int N) { return (N + 1 + RT - 1) / RT; }
+int arrow_chunks(int N) { return (N + 1 + RPB - 1) / RPB; }
 
 void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t st) {
     const int nchunk = arrow_chunks(in.N);
@@ -537,7 +611,12 @@ void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t
     double* best = reinterpret_cast<double*>(iwork + (long)in.N * k + ((long)in.N * k & 1));
     hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PT), 0, st, in, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_arrow_roots, dim3(k, nchunk), dim3(RT), 0, st, in, work, iwork, best, nchunk);
+    if (in.N <= LDS_POLES)
+        hipLaunchKernelGGL(k_arrow_roots<true>, dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
+                           nchunk);
+    else
+        hipLaunchKernelGGL(k_arrow_roots<false>, dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
+                           nchunk);
     PASM_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_arrow_final, dim3(k), dim3(PT), 0, st, in, out, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();

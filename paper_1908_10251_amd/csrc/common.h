@@ -144,9 +144,11 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 // ----------------------------------------------------------------------------
 // y[r] = Mat x[r] with Mat(row, col) stored at Mat[col * N + row]; x and y in
 // either the padded layout of level g (flag true) or compact (flag false).
+// `work` holds dense_mv_workspace_bytes(N, nrhs) bytes.
 template <typename T>
 void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded,
-                     T* y, long sy, bool y_padded, int nrhs, hipStream_t st);
+                     T* y, long sy, bool y_padded, int nrhs, void* work, hipStream_t st);
+size_t dense_mv_workspace_bytes(int N, int nrhs);
 
 struct ArrowIn {
     const double* theta;    // N coarse Ritz values, ascending
