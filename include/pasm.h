@@ -102,10 +102,12 @@ typedef struct pasm_options {
     double omega;       /* Jacobi weight; <= 0 selects 4/5 (2D) or 6/7 (3D) */
     double cheb_alpha;  /* Chebyshev interval [rho/alpha, rho]; <= 0 selects 4 (2D) or 6 (3D) */
     void* stream;       /* hipStream_t, or NULL */
+    int fused_smoothing;/* 1: all steps of a smoothing phase in one pass over memory where
+                           supported (2D, up to 4 steps), 0: one launch per step */
 } pasm_options;
 
 /* Fill *opt with the defaults: FP64, Jacobi 2/2, 2 V-cycles, 50 iterations,
- * tol 1e-10, omega and alpha by dimension, own stream. */
+ * tol 1e-10, omega and alpha by dimension, own stream, fused smoothing. */
 PASM_API void pasm_default_options(pasm_options* opt);
 
 /* Build the mesh hierarchy H = h_1 > 2h > ... > h (ratio 2, Section 3), the

@@ -96,6 +96,7 @@ struct pasm_ctx {
     hipStream_t st = nullptr;
     bool own_stream = false;
     bool mixed = false;
+    bool fuse = true;      // temporal blocking of smoothing phases (2D)
     std::vector<pasm::Level> lv;
     // finest level, FP64 (padded layout: boundary entries stay zero)
     double *U = nullptr, *F64 = nullptr, *Y64 = nullptr, *R64 = nullptr;
@@ -285,9 +286,27 @@ void collect_profile(pasm_ctx* c) {
 template <typename T>
 void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb>& steps, bool x_zero,
             int nrhs) {
+    if (steps.empty()) return;
     const pasm::Level& L = c->lv[l];
     const Coef<T> cf = c->coef<T>(l);
     const bool fine = (l == c->L - 1);
+    const double nodes = (double)L.g.interior();
+    const double coef_bytes = L.const_coef ? 0.0 : (double)L.g.dim * sizeof(T) * nodes;
+    if (c->fuse && pasm::fused_supported(L.g, (int)steps.size())) {
+        pasm::SmoothSteps ss{};
+        ss.s = (int)steps.size();
+        for (size_t j = 0; j < steps.size(); ++j) {
+            ss.a[j] = steps[j].a;
+            ss.b[j] = steps[j].b;
+        }
+        // algorithmic bytes of the fused phase: read x_0 (unless zero) and f, write x_s
+        const double bytes = (x_zero ? 2.0 : 3.0) * sizeof(T) * nodes * nrhs + coef_bytes;
+        if (fine) record_start(c);
+        pasm::launch_smooth_fused<T>(L.g, cf, x, f, y, nrhs, L.g.plane, ss, x_zero, c->st);
+        if (fine) record_end(c, bytes);
+        std::swap(x, y);
+        return;
+    }
     for (size_t j = 0; j < steps.size(); ++j) {
         // starting from x = 0: step 0 does not read x_0, step 1 does not read x_{-1} = x_0
         const bool z = x_zero && j == 0;
@@ -296,8 +315,7 @@ void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb
             // algorithmic bytes: read x_k (unless zero), x_{k-1} (if a != 0), f; write x_{k+1};
             // plus the coefficient arrays once per launch
             const double words = 2.0 + (z ? 0.0 : 1.0) + (steps[j].a != 0.0 && !z && !(zmode & 2) ? 1.0 : 0.0);
-            double bytes = words * sizeof(T) * (double)L.g.interior() * nrhs;
-            if (!L.const_coef) bytes += (double)L.g.dim * sizeof(T) * (double)L.g.interior();
+            const double bytes = words * sizeof(T) * nodes * nrhs + coef_bytes;
             record_start(c);
             pasm::launch_smooth<T>(L.g, cf, x, y, f, y, nrhs, L.g.plane, steps[j], zmode, c->st);
             record_end(c, bytes);
@@ -437,6 +455,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->L = L;
     c->NH = pl.NH;
     c->mixed = (c->opt.precision == PASM_MIXED);
+    c->fuse = c->opt.fused_smoothing != 0;
     const double omega = c->opt.omega > 0 ? c->opt.omega : (dim == 2 ? 0.8 : 6.0 / 7.0);
     const double alpha = c->opt.cheb_alpha > 0 ? c->opt.cheb_alpha : (dim == 2 ? 4.0 : 6.0);
 
@@ -727,6 +746,7 @@ PASM_API void pasm_default_options(pasm_options* o) {
     o->omega = 0.0;
     o->cheb_alpha = 0.0;
     o->stream = nullptr;
+    o->fused_smoothing = 1;
 }
 
 PASM_API pasm_status pasm_destroy(pasm_ctx* c) {

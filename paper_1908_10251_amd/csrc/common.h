@@ -90,6 +90,21 @@ template <typename T>
 void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn,
                    int nrhs, long stride, Cheb s, int zmode, hipStream_t st);
 
+// Coefficients of the steps of one smoothing phase (fused kernel).
+struct SmoothSteps {
+    double a[8];
+    double b[8];
+    int s;
+};
+
+bool fused_supported(const Grid& g, int steps);
+
+// All steps of a phase in one launch (2D, s <= 4): out = x_s from x_0 (or 0).
+// Returns false when the shape is not covered (caller falls back to steps).
+template <typename T>
+bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs,
+                         long stride, const SmoothSteps& ss, bool x_zero, hipStream_t st);
+
 template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
                            T* rc, int nrhs, long sf, long sc, hipStream_t st);

@@ -74,6 +74,95 @@ __global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> c, const T* _
     xn[off + id] = v;
 }
 
+// All S steps of one smoothing phase in one pass over HBM (temporal
+// blocking).  A 64 x 4 workgroup owns a tile of 64 LDS columns by 4*ROWS LDS
+// rows: the (64 - 2S) x (4*ROWS - 2S) output nodes plus an S-node halo.
+// Thread (tx, ty) owns LDS column tx and rows ty, ty+4, ...; it keeps f,
+// x_{t-1} and x_t of its own nodes in registers, and the current iterate of
+// the tile lives in LDS (double buffered) for the neighbours.  Every step
+// updates all nodes except the outer ring of the tile: after S steps the
+// nodes at distance >= S from the tile edge hold x_S exactly (their
+// dependence cone stays inside the loaded region); values nearer the edge are
+// discarded.  Nodes on or outside the domain boundary stay zero.  A phase
+// always starts fresh (a_0 = 0), so only x_0 is read, and not at all when
+// x_0 = 0.
+template <typename T, bool CONST, int S, int ROWS>
+__global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> c, const T* __restrict__ x0,
+                                                      const T* __restrict__ f, T* __restrict__ out, long stride,
+                                                      SmoothSteps st, int x_zero) {
+    constexpr int W = 64, HH = 4 * ROWS, TX = W - 2 * S, TY = HH - 2 * S;
+    __shared__ T sa[W * HH], sb[W * HH];
+    __shared__ T swx[CONST ? 1 : W * HH], swy[CONST ? 1 : W * HH];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int i = blockIdx.x * TX + 1 - S + tx;  // global column of this thread
+    const int jb = blockIdx.y * TY + 1 - S;      // global row of LDS row 0
+    const long off = (long)blockIdx.z * stride;
+    T fr[ROWS], xc[ROWS], xp[ROWS];
+    bool upd[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int ly = ty + 4 * r, j = jb + ly;
+        const bool inner = i >= 1 && i <= g.m && j >= 1 && j <= g.m;
+        upd[r] = inner && tx > 0 && tx < W - 1 && ly > 0 && ly < HH - 1;
+        T xv = T(0), fv = T(0);
+        if (inner) {
+            const long id = off + g.idx(i, j);
+            fv = f[id];
+            if (!x_zero) xv = x0[id];
+        }
+        fr[r] = fv;
+        xc[r] = xv;
+        xp[r] = xv;
+        sa[ly * W + tx] = xv;
+        if (!CONST) {
+            const bool stored = i >= 0 && i <= g.n && j >= 0 && j <= g.n;
+            swx[ly * W + tx] = (stored && i < g.n) ? c.wx[g.idx(i, j)] : T(0);
+            swy[ly * W + tx] = (stored && j < g.n) ? c.wy[g.idx(i, j)] : T(0);
+        }
+    }
+    __syncthreads();
+    const T invD0 = T(1) / (T(4) * c.w0);
+    T* cur = sa;
+    T* nxt = sb;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const T a = (T)st.a[t], b = (T)st.b[t];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int p = (ty + 4 * r) * W + tx;
+            T v = xc[r];
+            if (upd[r]) {
+                const T xe = cur[p + 1], xw = cur[p - 1], xn = cur[p + W], xs = cur[p - W];
+                if (CONST) {
+                    const T Ax = c.w0 * (T(4) * v - xe - xw - xn - xs);
+                    v = v + b * (fr[r] - Ax) * invD0;
+                } else {
+                    const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
+                    const T D = we + ww + wn + ws;
+                    const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs;
+                    v = v + b * (fr[r] - Ax) / D;
+                }
+                if (a != T(0)) v += a * (xc[r] - xp[r]);
+            }
+            xp[r] = xc[r];
+            xc[r] = v;
+            nxt[p] = v;
+        }
+        __syncthreads();
+        T* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    if (tx < S || tx >= W - S) return;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int ly = ty + 4 * r, j = jb + ly;
+        if (ly < S || ly >= HH - S) continue;
+        if (i < 1 || i > g.m || j < 1 || j > g.m) continue;
+        out[off + g.idx(i, j)] = xc[r];
+    }
+}
+
 template <typename T, bool CONST>
 __global__ __launch_bounds__(BX* BY) void k_apply_A(Grid g, Coef<T> c, const T* __restrict__ x,
                                                     T* __restrict__ y, long stride) {
@@ -327,6 +416,38 @@ void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, co
     PASM_CHECK_LAUNCH();
 }
 
+template <typename T, bool CONST, int S>
+void fused_launch(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
+                  const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+    constexpr int ROWS = 8, TX = 64 - 2 * S, TY = 4 * ROWS - 2 * S;
+    dim3 grid((g.m + TX - 1) / TX, (g.m + TY - 1) / TY, nrhs);
+    hipLaunchKernelGGL((k_smooth_fused<T, CONST, S, ROWS>), grid, dim3(64, 4), 0, st, g, c, x0, f, out, stride, ss,
+                       (int)x_zero);
+    PASM_CHECK_LAUNCH();
+}
+
+template <typename T, int S>
+void fused_dispatch(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
+                    const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+    if (c.wx) fused_launch<T, false, S>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st);
+    else fused_launch<T, true, S>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st);
+}
+
+bool fused_supported(const Grid& g, int steps) { return g.dim == 2 && steps >= 1 && steps <= 4; }
+
+template <typename T>
+bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
+                         const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+    if (!fused_supported(g, ss.s)) return false;
+    switch (ss.s) {
+        case 1: fused_dispatch<T, 1>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
+        case 2: fused_dispatch<T, 2>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
+        case 3: fused_dispatch<T, 3>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
+        case 4: fused_dispatch<T, 4>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
+        default: return false;
+    }
+}
+
 template <typename T>
 void launch_apply_A(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride,
                     hipStream_t st) {
@@ -439,6 +560,8 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
     template void launch_smooth<T>(const Grid&, const Coef<T>&, const T*, const T*, const T*, T*, int,  \
                                    long, Cheb, int, hipStream_t);                                      \
     template void launch_apply_A<T>(const Grid&, const Coef<T>&, const T*, T*, int, long, hipStream_t); \
+    template bool launch_smooth_fused<T>(const Grid&, const Coef<T>&, const T*, const T*, T*, int, long,      \
+                                         const SmoothSteps&, bool, hipStream_t);                              \
     template void launch_resid_restrict<T>(const Grid&, const Coef<T>&, const T*, const T*, const Grid&, \
                                            T*, int, long, long, hipStream_t);                           \
     template void launch_prolong<T>(const Grid&, const T*, const Grid&, T*, int, long, long, bool,      \

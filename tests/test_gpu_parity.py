@@ -29,9 +29,9 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def _opts(smoother="jacobi", nu=2, vcycles=2, precision=P.PASM_FP64, tol=1e-10, max_iter=60):
+def _opts(smoother="jacobi", nu=2, vcycles=2, precision=P.PASM_FP64, tol=1e-10, max_iter=60, fused=True):
     return P.options(precision=precision, smoother=P.PASM_CHEBYSHEV if smoother == "cheb" else P.PASM_JACOBI,
-                     nu_pre=nu, nu_post=nu, vcycles=vcycles, tol=tol, max_iter=max_iter)
+                     nu_pre=nu, nu_post=nu, vcycles=vcycles, tol=tol, max_iter=max_iter, fused=fused)
 
 
 CASES = [
@@ -77,8 +77,9 @@ VC = [
 
 @pytest.mark.parametrize("dim,nc,nf,sig,smoother,nu", VC)
 @pytest.mark.parametrize("precision", [P.PASM_FP64, P.PASM_MIXED])
-def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, precision):
-    _say(f"vcycle dim={dim} H=1/{nc} h=1/{nf} sigma={sig} {smoother} prec={precision}")
+@pytest.mark.parametrize("fused", [True, False])
+def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, precision, fused):
+    _say(f"vcycle dim={dim} H=1/{nc} h=1/{nf} sigma={sig} {smoother} prec={precision} fused={fused}")
     kap = None if sig is None else lognormal_kappa(dim, nf, seed=3, sigma=sig)
     A, _ = fem.assemble(dim, nf, kappa=kap)
     hier = Hierarchy(dim, A, nc, nf)
@@ -88,7 +89,7 @@ def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, precision):
     N = A.shape[0]
     f = rng.standard_normal((k, N))
     x0 = rng.standard_normal((k, N))
-    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu, precision=precision)) as s:
+    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu, precision=precision, fused=fused)) as s:
         # host transfers of the state must leave the grids' zero boundary intact
         lam, U = s.eigenpairs()
         P.pasm_set_state(s.ctx, lam, U)
