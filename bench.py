@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--workload", default=W.LAP2D_LARGE.name)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=40)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="also run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the eigenpairs are independent, "
@@ -103,6 +105,16 @@ def main():
 
     import torch
     import paper_1908_10251_amd as pasm
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+        return
 
     wl = {w.name: w for w in W.ALL}[args.workload]
     if wl.kappa != "one" or wl.potential != "none":
