@@ -128,7 +128,7 @@ def main():
     ctx = solver.ctx
     k = wl.k
 
-    ref = golden(wl.name)
+    ref = golden(wl.golden_name)
     ref_kind = "oracle discrete eigenvalues (tests/golden)"
     if ref is None:
         pasm.pasm_restart(ctx)

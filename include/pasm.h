@@ -104,6 +104,9 @@ typedef struct pasm_options {
     void* stream;       /* hipStream_t, or NULL */
     int fused_smoothing;/* 1: all steps of a smoothing phase in one pass over memory where
                            supported (2D, up to 4 steps), 0: one launch per step */
+    int exhaustive_selection; /* 1: score every eigenvalue of the augmented problem;
+                                 0 (default): stop once the scores already computed
+                                 provably contain the winner (same choice, less work) */
 } pasm_options;
 
 /* Fill *opt with the defaults: FP64, Jacobi 2/2, 2 V-cycles, 50 iterations,

@@ -45,7 +45,7 @@ class pasm_options(ctypes.Structure):
                 ("vcycles", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("omega", ctypes.c_double),
                 ("cheb_alpha", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("fused_smoothing", ctypes.c_int)]
+                ("fused_smoothing", ctypes.c_int), ("exhaustive_selection", ctypes.c_int)]
 
 
 _lib = None
@@ -263,9 +263,10 @@ def pasm_destroy(ctx) -> None:
 
 def options(precision: int = PASM_FP64, smoother: int = PASM_JACOBI, nu_pre: int = 2, nu_post: int = 2,
             vcycles: int = 2, max_iter: int = 50, tol: float = 1e-10, omega: float = 0.0,
-            cheb_alpha: float = 0.0, fused: bool = True) -> pasm_options:
+            cheb_alpha: float = 0.0, fused: bool = True, exhaustive: bool = False) -> pasm_options:
     o = pasm_default_options()
     o.fused_smoothing = int(fused)
+    o.exhaustive_selection = int(exhaustive)
     o.precision, o.smoother, o.nu_pre, o.nu_post = precision, smoother, nu_pre, nu_post
     o.vcycles, o.max_iter, o.tol, o.omega, o.cheb_alpha = vcycles, max_iter, tol, omega, cheb_alpha
     return o

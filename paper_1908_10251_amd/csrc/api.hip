@@ -333,6 +333,16 @@ const double* ainv<double>(const pasm_ctx* c) { return c->Ainv64; }
 template <>
 const float* ainv<float>(const pasm_ctx* c) { return c->Ainv32; }
 
+pasm::SmoothSteps to_steps(const std::vector<Cheb>& v) {
+    pasm::SmoothSteps ss{};
+    ss.s = (int)v.size();
+    for (size_t j = 0; j < v.size() && j < 8; ++j) {
+        ss.a[j] = v[j].a;
+        ss.b[j] = v[j].b;
+    }
+    return ss;
+}
+
 // One V-cycle at level l >= 0 on (x, f); x may start at zero.
 template <typename T>
 void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs) {
@@ -341,18 +351,35 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         pasm::launch_dense_mv<T>(ainv<T>(c), c->NH, L.g, f, L.g.plane, true, x, L.g.plane, true, nrhs, c->dmv, c->st);
         return;
     }
-    smooth<T>(c, l, x, y, f, L.pre, x_zero, nrhs);
-    const bool zero_after_pre = x_zero && L.pre.empty();
     pasm::Level& Lc = c->lv[l - 1];
     T* fc = static_cast<T*>(Lc.F);
+    T* xc = static_cast<T*>(Lc.X);
+    T* yc = static_cast<T*>(Lc.Y);
+    const bool fine = (l == c->L - 1);
+    if (c->fuse && pasm::march_supported(L.g, L.const_coef, (int)L.pre.size()) &&
+        pasm::march_supported(L.g, L.const_coef, (int)L.post.size())) {
+        // marching phases: pre-smoothing with the residual restriction fused,
+        // post-smoothing with the prolongation fused
+        const double nodes = (double)L.g.interior() * nrhs, w = sizeof(T);
+        if (fine) record_start(c);
+        pasm::launch_march_pre<T>(L.g, (T)L.w0, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
+        if (fine) record_end(c, ((x_zero ? 2.0 : 3.0) + 0.25) * w * nodes);
+        std::swap(x, y);
+        vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
+        if (fine) record_start(c);
+        pasm::launch_march_post<T>(L.g, (T)L.w0, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
+        if (fine) record_end(c, 3.25 * w * nodes);
+        std::swap(x, y);
+        return;
+    }
+    smooth<T>(c, l, x, y, f, L.pre, x_zero, nrhs);
+    const bool zero_after_pre = x_zero && L.pre.empty();
     if (zero_after_pre) {
         // x = 0: the residual is f, restricted
         pasm::launch_restrict<T>(L.g, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
     } else {
         pasm::launch_resid_restrict<T>(L.g, c->coef<T>(l), x, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
     }
-    T* xc = static_cast<T*>(Lc.X);
-    T* yc = static_cast<T*>(Lc.Y);
     vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
     if (zero_after_pre) {
         pasm::launch_prolong<T>(Lc.g, xc, L.g, x, nrhs, Lc.g.plane, L.g.plane, false, nullptr, c->st);
@@ -707,7 +734,7 @@ void iterate_once(pasm_ctx* c) {
     const Grid& g0 = c->lv[0].g;
     pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, k, c->dmv, c->st);
     pasm::launch_dense_mv<double>(c->Qrm, N, g0, csrc, g0.plane, true, c->qq, N, false, k, c->dmv, c->st);
-    pasm::ArrowIn in{c->theta, c->group, c->pp, c->qq, c->bz, c->lam, N};
+    pasm::ArrowIn in{c->theta, c->group, c->pp, c->qq, c->bz, c->lam, N, c->opt.exhaustive_selection};
     pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
     pasm::launch_arrowhead(in, out, k, c->st);
     prolong_coefs(c, c->s);
@@ -747,6 +774,7 @@ PASM_API void pasm_default_options(pasm_options* o) {
     o->cheb_alpha = 0.0;
     o->stream = nullptr;
     o->fused_smoothing = 1;
+    o->exhaustive_selection = 0;
 }
 
 PASM_API pasm_status pasm_destroy(pasm_ctx* c) {

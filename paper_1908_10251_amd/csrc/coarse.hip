@@ -49,7 +49,7 @@ constexpr double TIE_RTOL = 1e-12;
 // ---------------------------------------------------------------------------
 constexpr int DM_R = 64;   // rows per workgroup (one per thread)
 constexpr int DM_C = 64;   // columns per chunk
-constexpr int DM_K = 16;   // right-hand sides per workgroup
+constexpr int DM_K = 32;   // right-hand sides per workgroup
 
 __device__ inline long compact_to_padded(const Grid& g, int c) {
     const int i = c % g.m + 1;
@@ -118,9 +118,14 @@ struct WS {
     double* best;    // [nchunk][4] per-block best root (score, mu, root, 0)
 };
 // scalar slots
-enum { S_RHO = 0, S_SQ, S_ZPERP, S_NA, S_LO, S_HI, S_SKIP, S_DSCORE, S_DMU, S_DLEAD, S_DTYPE, S_TOLZ };
+enum {
+    S_RHO = 0, S_SQ, S_ZPERP, S_NA, S_LO, S_HI, S_SKIP, S_DSCORE, S_DMU, S_DLEAD, S_DTYPE, S_TOLZ,
+    S_DMASS,   // sum of the squared scores of all deflated candidates
+    S_CERT,    // 1: the roots next to the previous eigenvalue provably contain the winner
+    S_NSCORE, S_NMU  // best of those roots (score, root index in S_NMU + 1 slot below)
+};
 
-__host__ __device__ inline long ws_doubles(int N) { return 7L * N + 3 + 16; }
+__host__ __device__ inline long ws_doubles(int N) { return 7L * N + 3 + 20; }
 
 __device__ inline WS ws_of(double* work, int* iwork, double* best, int N, int nchunk, int r) {
     WS w;
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
     const int per = (N + PT - 1) / PT;
     const int j0 = threadIdx.x * per, j1 = min(N, j0 + per);
     int mine = 0;
-    double ds = -1.0, dm = 0.0;
+    double ds = -1.0, dm = 0.0, dmass = 0.0;
     int dl = -1, dt = 0;
     for (int j = j0; j < j1; ++j) {
         if (in.group[j] != j) continue;  // not a group leader
@@ -234,6 +239,7 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
                 ct = 2;
             }
         }
+        if (ct) dmass += cs * cs;
         if (ct && (dl < 0 || better(cs, in.theta[j], ds, dm, lp))) {
             ds = cs;
             dm = in.theta[j];
@@ -241,6 +247,7 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
             dt = ct;
         }
     }
+    dmass = block_sum(dmass, sh);
     cnt[threadIdx.x] = mine;
     bs[threadIdx.x] = ds;
     bm[threadIdx.x] = dm;
@@ -265,6 +272,8 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
         w.sc[S_ZPERP] = zperp;
         w.sc[S_SKIP] = skip ? 1.0 : 0.0;
         w.sc[S_TOLZ] = tolz;
+        w.sc[S_DMASS] = dmass;
+        w.sc[S_CERT] = 0.0;
         w.sc[S_DSCORE] = bi < 0 ? -1.0 : bs[bi];
         w.sc[S_DMU] = bi < 0 ? 0.0 : bm[bi];
         w.sc[S_DLEAD] = bi < 0 ? -1.0 : (double)bl[bi];
@@ -331,13 +340,38 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-template <bool LDS>
+// Root offset of the NEAR pass: the RPB roots around the interval that holds
+// the previous eigenvalue (root a lies between active poles a-1 and a).
+__device__ inline int near_base(const double* d, int na, double lp) {
+    int lo = 0, hi = na;  // number of active poles below lp, by bisection
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (d[mid] < lp) lo = mid + 1;
+        else hi = mid;
+    }
+    int base = lo - RPB / 2;
+    if (base > na + 1 - RPB) base = na + 1 - RPB;
+    if (base < 0) base = 0;
+    return base;
+}
+
+// NEAR = true: one workgroup per eigenpair computes the RPB roots next to the
+// previous eigenvalue and decides whether they certainly contain the winner.
+// Every eigenvector of the arrowhead matrix has a score (its component along
+// m = [q; sqrt(zeta_perp)]); the eigenvectors are orthonormal, so the squared
+// scores of ALL candidates add up to |m|^2 = zeta.  If the best computed root
+// beats every deflated candidate and its squared score exceeds what is left
+// for the uncomputed roots (zeta minus the computed squared scores), no other
+// root can win, ties included.  NEAR = false: all roots, skipped when the
+// NEAR pass certified its winner.
+template <bool LDS, bool NEAR>
 __global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* work, int* iwork, double* best,
                                                             int nchunk) {
     __shared__ double sd[LDS ? LDS_POLES : 1], sz[LDS ? LDS_POLES : 1], sqa[LDS ? LDS_POLES : 1];
     __shared__ double ss[RPB], sm[RPB];
     const int r = blockIdx.x, N = in.N;
     WS w = ws_of(work, iwork, best, N, nchunk, r);
+    if (!NEAR && w.sc[S_CERT] != 0.0) return;  // uniform per workgroup
     const int na = (int)w.sc[S_NA];
     const double rho = w.sc[S_RHO], sq = w.sc[S_SQ], lp = in.lam_prev[r];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -355,8 +389,9 @@ __global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* 
         z = sz;
         qa = sqa;
     }
+    const int base = NEAR ? (na > 0 ? near_base(d, na, lp) : 0) : blockIdx.y * RPB;
     for (int slot = wave; slot < RPB; slot += RWAVES) {
-        const int root = blockIdx.y * RPB + slot;
+        const int root = base + slot;
         double score = -1.0, mu = 0.0;
         if (na >= 0 && root <= na) {
             if (na == 0) {
@@ -444,15 +479,35 @@ __global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* 
     __syncthreads();
     if (threadIdx.x == 0) {
         int bi = -1;
+        double mass = 0.0;
         for (int t = 0; t < RPB; ++t) {
             if (ss[t] < 0.0) continue;
+            mass += ss[t] * ss[t];
             if (bi < 0 || better(ss[t], sm[t], ss[bi], sm[bi], lp)) bi = t;
         }
-        double* b = w.best + 4L * blockIdx.y;
-        b[0] = bi < 0 ? -1.0 : ss[bi];
-        b[1] = bi < 0 ? 0.0 : sm[bi];
-        b[2] = bi < 0 ? -1.0 : (double)(blockIdx.y * RPB + bi);
-        b[3] = 0.0;
+        if (NEAR) {
+            w.sc[S_NSCORE] = bi < 0 ? -1.0 : ss[bi];
+            w.sc[S_NMU] = bi < 0 ? 0.0 : sm[bi];
+            w.sc[S_NMU + 1] = bi < 0 ? -1.0 : (double)(base + bi);
+            bool cert = false;
+            if (bi >= 0) {
+                const double zeta = in.bz[2 * r + 1];
+                const double rest = zeta - w.sc[S_DMASS] - mass;
+                const double b2 = ss[bi] * ss[bi];
+                const bool beats_deflated =
+                    w.sc[S_DSCORE] < 0.0 || better(ss[bi], sm[bi], w.sc[S_DSCORE], w.sc[S_DMU], lp);
+                cert = beats_deflated && b2 > fmax(rest, 0.0) * (1.0 + 1e-10) + 1e-10 * zeta * EPS;
+                if (base == 0 && na + 1 <= RPB) cert = beats_deflated;  // every root was computed
+                if (in.exhaustive) cert = false;
+            }
+            w.sc[S_CERT] = cert ? 1.0 : 0.0;
+        } else {
+            double* b = w.best + 4L * blockIdx.y;
+            b[0] = bi < 0 ? -1.0 : ss[bi];
+            b[1] = bi < 0 ? 0.0 : sm[bi];
+            b[2] = bi < 0 ? -1.0 : (double)(blockIdx.y * RPB + bi);
+            b[3] = 0.0;
+        }
     }
 }
 
@@ -470,7 +525,11 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
     const double sq = w.sc[S_SQ];
     if (threadIdx.x == 0) {
         double bsc = -1.0, bmu = 0.0, kind = 0.0, id = -1.0;
-        if (na >= 0) {
+        if (na >= 0 && w.sc[S_CERT] != 0.0) {
+            bsc = w.sc[S_NSCORE];
+            bmu = w.sc[S_NMU];
+            id = w.sc[S_NMU + 1];
+        } else if (na >= 0) {
             for (int c = 0; c < nchunk; ++c) {
                 const double* b = w.best + 4L * c;
                 if (b[0] < 0.0) continue;
@@ -611,12 +670,17 @@ void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t
     double* best = reinterpret_cast<double*>(iwork + (long)in.N * k + ((long)in.N * k & 1));
     hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PT), 0, st, in, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();
-    if (in.N <= LDS_POLES)
-        hipLaunchKernelGGL(k_arrow_roots<true>, dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
+    if (in.N <= LDS_POLES) {
+        hipLaunchKernelGGL((k_arrow_roots<true, true>), dim3(k, 1), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
                            nchunk);
-    else
-        hipLaunchKernelGGL(k_arrow_roots<false>, dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
+        hipLaunchKernelGGL((k_arrow_roots<true, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork,
+                           best, nchunk);
+    } else {
+        hipLaunchKernelGGL((k_arrow_roots<false, true>), dim3(k, 1), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
                            nchunk);
+        hipLaunchKernelGGL((k_arrow_roots<false, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork,
+                           best, nchunk);
+    }
     PASM_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_arrow_final, dim3(k), dim3(PT), 0, st, in, out, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();

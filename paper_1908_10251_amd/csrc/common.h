@@ -105,6 +105,17 @@ template <typename T>
 bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs,
                          long stride, const SmoothSteps& ss, bool x_zero, hipStream_t st);
 
+// Marching smoothing phases (2D, constant coefficients, 1..4 steps).
+// pre:  out = x_s (from x0, or from 0), rc = P^T (f - A x_s) on the coarser grid gc
+// post: out = x_s starting from x + P ec
+bool march_supported(const Grid& g, bool const_coef, int steps);
+template <typename T>
+void launch_march_pre(const Grid& g, T w0, const T* x0, const T* f, T* out, const Grid& gc, T* rc, int nrhs,
+                      const SmoothSteps& ss, bool x_zero, hipStream_t st);
+template <typename T>
+void launch_march_post(const Grid& g, T w0, const T* x, const T* f, T* out, const Grid& gc, const T* ec, int nrhs,
+                       const SmoothSteps& ss, hipStream_t st);
+
 template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
                            T* rc, int nrhs, long sf, long sc, hipStream_t st);
@@ -173,6 +184,7 @@ struct ArrowIn {
     const double* bz;       // [k][2] (beta, zeta)
     const double* lam_prev; // [k]
     int N;
+    int exhaustive;         // 1: never skip the full root pass
 };
 struct ArrowOut {
     double* ycoef;  // [k][N] coefficients y' of the new eigenvector in the Q basis

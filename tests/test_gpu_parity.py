@@ -29,9 +29,11 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def _opts(smoother="jacobi", nu=2, vcycles=2, precision=P.PASM_FP64, tol=1e-10, max_iter=60, fused=True):
+def _opts(smoother="jacobi", nu=2, vcycles=2, precision=P.PASM_FP64, tol=1e-10, max_iter=60, fused=True,
+          exhaustive=False):
     return P.options(precision=precision, smoother=P.PASM_CHEBYSHEV if smoother == "cheb" else P.PASM_JACOBI,
-                     nu_pre=nu, nu_post=nu, vcycles=vcycles, tol=tol, max_iter=max_iter, fused=fused)
+                     nu_pre=nu, nu_post=nu, vcycles=vcycles, tol=tol, max_iter=max_iter, fused=fused,
+                     exhaustive=exhaustive)
 
 
 CASES = [
@@ -127,9 +129,10 @@ ONE_STEP = [
 
 
 @pytest.mark.parametrize("dim,nc,nf,sig,smoother,nu,k", ONE_STEP)
-def test_one_correction_step_matches_oracle(dim, nc, nf, sig, smoother, nu, k):
+@pytest.mark.parametrize("exhaustive", [False, True])
+def test_one_correction_step_matches_oracle(dim, nc, nf, sig, smoother, nu, k, exhaustive):
     """Algorithm 1 from the same state: the coarse start, then a perturbed state."""
-    _say(f"one step dim={dim} H=1/{nc} h=1/{nf} sigma={sig} {smoother} k={k}")
+    _say(f"one step dim={dim} H=1/{nc} h=1/{nf} sigma={sig} {smoother} k={k} exhaustive={exhaustive}")
     kap = None if sig is None else lognormal_kappa(dim, nf, seed=5, sigma=sig)
     prob = O.make_problem(dim, nc, nf, kappa=kap)
     bvp = O.MultigridBVP(prob, default_options(dim, smoother, nu, nu, 2))
@@ -137,7 +140,7 @@ def test_one_correction_step_matches_oracle(dim, nc, nf, sig, smoother, nu, k):
     rng = np.random.default_rng(4)
     U1 = U0 + 0.05 * rng.standard_normal(U0.shape) * np.max(np.abs(U0))
     lam1 = np.array([(u @ prob.A @ u) / (u @ prob.M @ u) for u in U1])
-    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu)) as s:
+    with P.Solver(dim, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts(smoother, nu, exhaustive=exhaustive)) as s:
         for lam_in, U_in, from_setup in ((lam0, U0, True), (lam1, U1, False)):
             if not from_setup:
                 P.pasm_set_state(s.ctx, lam_in, U_in)

@@ -45,6 +45,11 @@ class Workload:
     kappa: str = "one"  # "one" | "lognormal"
     potential: str = "none"  # "none" | "quadratic"
     seed: int = 0
+    golden: str = ""    # name of the workload whose stored discrete eigenvalues apply (default: own name)
+
+    @property
+    def golden_name(self) -> str:
+        return self.golden or self.name
 
     @property
     def n_fine(self) -> int:
@@ -67,6 +72,8 @@ LAP2D_SMALL = Workload("lap2d-H8-h64-k4", 2, 1 / 8, 1 / 64, 4, "jacobi", 2, 2, 2
 # method reaches them; H = 1/32 makes all 20 attracting (Remark 3.1: H is
 # chosen small enough for the wanted eigenpairs).
 LAP2D_LARGE = Workload("lap2d-H32-h1024-k20", 2, 1 / 32, 1 / 1024, 20, "cheb", 4, 4, 2, "fp64", 1e-10)
+LAP2D_LARGE_MIXED = Workload("lap2d-H32-h1024-k20-mixed", 2, 1 / 32, 1 / 1024, 20, "cheb", 4, 4, 2, "mixed",
+                             1e-10, golden="lap2d-H32-h1024-k20")
 KAPPA2D_MIXED = Workload("kappa2d-H32-h2048-k50-mixed", 2, 1 / 32, 1 / 2048, 50, "cheb", 4, 4, 2,
                          "mixed", 1e-10, kappa="lognormal", seed=0)
 BATCH2D_UNEVEN = Workload("batch16-kappaV2d-H16-k10-mixed", 2, 1 / 16, 1 / 1024, 10, "cheb", 4, 4, 2,
@@ -74,7 +81,7 @@ BATCH2D_UNEVEN = Workload("batch16-kappaV2d-H16-k10-mixed", 2, 1 / 16, 1 / 1024,
 LAP3D_LEARNED = Workload("lap3d-H8-h128-k100", 3, 1 / 8, 1 / 128, 100, "jacobi", 2, 2, 2,
                          "mixed", 1e-10)
 
-ALL = [LAP2D_SMALL, LAP2D_LARGE, KAPPA2D_MIXED, BATCH2D_UNEVEN, LAP3D_LEARNED]
+ALL = [LAP2D_SMALL, LAP2D_LARGE, LAP2D_LARGE_MIXED, KAPPA2D_MIXED, BATCH2D_UNEVEN, LAP3D_LEARNED]
 
 
 def n_elements(dim: int, n: int) -> int:
