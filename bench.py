@@ -28,8 +28,9 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1908_10251_amd/csrc/stencil2d.hip", "paper_1908_10251_amd/csrc/stencil3d.hip",
-                  "paper_1908_10251_amd/csrc/common.h"]
+# sources of the kernels that run on the finest level of the timed workloads
+KERNEL_SOURCES = ["paper_1908_10251_amd/csrc/march2d.hip", "paper_1908_10251_amd/csrc/stencil2d.hip",
+                  "paper_1908_10251_amd/csrc/stencil3d.hip", "paper_1908_10251_amd/csrc/common.h"]
 
 
 def kernel_hash() -> str:
@@ -48,9 +49,10 @@ def golden(name: str):
 
 
 def traffic_record(workload: str):
-    """HBM bytes per launch of the fine smoothing kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_smooth_{workload}.json")
+    """HBM bytes per launch of the finest-level smoothing phases from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_fine_smoothing_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -193,7 +195,8 @@ def main():
                    "setup_s": t_setup, "fine_dof_updates_per_s": dof_updates},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "fine-level smoothing sweep", "launches": launches,
+                     "kernel": "finest-level smoothing phases (k_march: pre-smoothing with fused residual "
+                               "restriction, post-smoothing with fused prolongation)", "launches": launches,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bpl},
     }
     if not args.no_cpu_baseline:

@@ -214,6 +214,84 @@ PASM_API pasm_status pasm_profile(pasm_ctx* ctx, int kernel, int enable);
 PASM_API pasm_status pasm_profile_read(pasm_ctx* ctx, int kernel, long* launches, double* total_ms,
                                        double* bytes_per_launch);
 
+/* ---------------------------------------------------------------------------
+ * Batches of problems of uneven size.
+ *
+ * Eigenpairs are corrected independently (Algorithm 2 runs one correction
+ * step per eigenpair with no exchange between them), so several problems
+ * sharing the coarse size H and the count k can advance together.  A batch
+ * stores every multigrid level level-major: level l (1/H * 2^l cells per
+ * side) holds the k vectors of every member whose fine mesh is at least that
+ * fine, and each step of the iteration is one launch per level over all those
+ * members (members of equal fine size share the fine-level launches).  Every
+ * level uses the general 7-point operator form (stiffness + potential,
+ * Galerkin coarse levels) with the member's own coefficients and smoother
+ * bound.  V-cycles always run as defect correction: r = f - A u in FP64,
+ * the cycle from zero in the cycle's precision (FP32 for PASM_MIXED, FP64
+ * otherwise), then u += e in FP64.
+ * The device work of one iteration is recorded once into a HIP graph and
+ * replayed (pasm_batch_use_graph).  Smoothing tile heights per level are
+ * chosen at set-up by timing each candidate on the batch itself.
+ * ------------------------------------------------------------------------- */
+typedef struct pasm_batch pasm_batch;
+
+/* One member: fine mesh size and coefficients (2D, layout as for pasm_setup). */
+typedef struct pasm_instance {
+    double h;
+    pasm_coefficients coef;
+} pasm_instance;
+
+/* Set up n >= 1 members on the unit square (dim must be 2), all with coarse
+ * size H and k eigenpairs each; member i has fine size inst[i].h (1/h a
+ * multiple 2^j / H with j >= 1).  Options as for pasm_setup; the smoothing
+ * tile heights are autotuned unless opt->fused_smoothing is 0 (one launch
+ * per smoothing step).  The coarse eigenproblem of every member is solved
+ * here; the start is lambda = theta_i, u_i = P q_i per member. */
+PASM_API pasm_status pasm_batch_setup(pasm_batch** out, const pasm_domain* domain, const pasm_instance* inst,
+                                      int n, double H, int k, const pasm_options* opt);
+
+/* One correction step for all n * k eigenpairs.  *converged (may be NULL):
+ * 1 when every member's maximum relative eigenvalue change is below
+ * opt.tol.  Synchronises the stream once. */
+PASM_API pasm_status pasm_batch_iterate(pasm_batch* b, int* converged);
+PASM_API pasm_status pasm_batch_restart(pasm_batch* b);
+PASM_API pasm_status pasm_batch_solve(pasm_batch* b, int* iterations);
+
+/* Eigenvalues (k) and, if U != NULL, eigenvectors (k blocks of ldu doubles,
+ * host memory, interior nodes x fastest) of member i (0 <= i < n, in the
+ * order given at set-up). */
+PASM_API pasm_status pasm_batch_eigenpairs(const pasm_batch* b, int member, double* lambda, double* U,
+                                           size_t ldu);
+/* Replace member i's state (host memory, layout as above). */
+PASM_API pasm_status pasm_batch_set_state(pasm_batch* b, int member, const double* lambda, const double* U,
+                                          size_t ldu);
+PASM_API size_t pasm_batch_num_dofs(const pasm_batch* b, int member);
+PASM_API int pasm_batch_num_levels(const pasm_batch* b);
+
+/* 1 (default): replay the recorded graph of one iteration; 0: launch the
+ * kernels one by one (the same kernels, same order). */
+PASM_API pasm_status pasm_batch_use_graph(pasm_batch* b, int enable);
+
+/* Smoothing tile height per level (levels 1 .. pasm_batch_num_levels()-1;
+ * entry 0 unused): 0 = one launch per smoothing step, 2/4/8 = fused phase
+ * with 4*rows LDS rows per workgroup.  pasm_batch_tuning reports the choice
+ * and, if times_ms != NULL, the measured time of each candidate
+ * (times_ms[level][4] for 0, 2, 4, 8; negative if not applicable).
+ * pasm_batch_set_tiles overrides the choice (invalid entries: PASM_E_INVALID). */
+PASM_API pasm_status pasm_batch_tuning(const pasm_batch* b, int* rows, double* times_ms);
+PASM_API pasm_status pasm_batch_set_tiles(pasm_batch* b, const int* rows);
+
+/* HIP-event timing of the finest batched level's smoothing phases inside
+ * subsequent iterations (kernel 0 only), as pasm_profile / pasm_profile_read. */
+PASM_API pasm_status pasm_batch_profile(pasm_batch* b, int kernel, int enable);
+PASM_API pasm_status pasm_batch_profile_read(pasm_batch* b, int kernel, long* launches, double* total_ms,
+                                             double* bytes_per_launch);
+
+PASM_API pasm_status pasm_batch_destroy(pasm_batch* b);
+/* Last failure on b; with b == NULL, of the last failed pasm_batch_setup on
+ * the calling thread. */
+PASM_API const char* pasm_batch_last_error(const pasm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,10 @@ class pasm_coefficients(ctypes.Structure):
                 ("n_elements", ctypes.c_size_t)]
 
 
+class pasm_instance(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("coef", pasm_coefficients)]
+
+
 class pasm_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
@@ -89,6 +93,24 @@ def lib() -> ctypes.CDLL:
     L.pasm_vcycle.argtypes = [_P, _P, _P, ctypes.c_size_t, ctypes.c_int, ctypes.c_int]
     L.pasm_profile.argtypes = [_P, ctypes.c_int, ctypes.c_int]
     L.pasm_profile_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _D, _D]
+    L.pasm_batch_setup.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(pasm_domain), ctypes.POINTER(pasm_instance),
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(pasm_options)]
+    L.pasm_batch_iterate.argtypes = [_P, _I]
+    L.pasm_batch_restart.argtypes = [_P]
+    L.pasm_batch_solve.argtypes = [_P, _I]
+    L.pasm_batch_eigenpairs.argtypes = [_P, ctypes.c_int, _D, _D, ctypes.c_size_t]
+    L.pasm_batch_set_state.argtypes = [_P, ctypes.c_int, _D, _D, ctypes.c_size_t]
+    L.pasm_batch_num_dofs.argtypes = [_P, ctypes.c_int]
+    L.pasm_batch_num_dofs.restype = ctypes.c_size_t
+    L.pasm_batch_num_levels.argtypes = [_P]
+    L.pasm_batch_use_graph.argtypes = [_P, ctypes.c_int]
+    L.pasm_batch_tuning.argtypes = [_P, _I, _D]
+    L.pasm_batch_set_tiles.argtypes = [_P, _I]
+    L.pasm_batch_profile.argtypes = [_P, ctypes.c_int, ctypes.c_int]
+    L.pasm_batch_profile_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _D, _D]
+    L.pasm_batch_destroy.argtypes = [_P]
+    L.pasm_batch_last_error.argtypes = [_P]
+    L.pasm_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -300,6 +322,158 @@ class Solver:
         if self.ctx:
             pasm_destroy(self.ctx)
             self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batches of uneven instances
+# ---------------------------------------------------------------------------
+def _bcheck(status: int, b=None):
+    if status != PASM_OK:
+        L = lib()
+        msg = (L.pasm_batch_last_error(b) or b"").decode()
+        raise PasmError(status, f"{L.pasm_status_string(status).decode()}: {msg}")
+
+
+def pasm_batch_setup(H: float, k: int, instances, options: Optional[pasm_options] = None, stream=None, dim: int = 2):
+    """instances: sequence of (h, kappa or None, potential or None)."""
+    L = lib()
+    n = len(instances)
+    arr = (pasm_instance * max(n, 1))()
+    keep = []
+    for i, (h, kap, pot) in enumerate(instances):
+        arr[i].h = float(h)
+        n_el = 0
+        if kap is not None:
+            a = np.ascontiguousarray(kap, dtype=np.float64)
+            keep.append(a)
+            arr[i].coef.kappa = _dptr(a)
+            n_el = a.size
+        if pot is not None:
+            a = np.ascontiguousarray(pot, dtype=np.float64)
+            keep.append(a)
+            arr[i].coef.potential = _dptr(a)
+            n_el = a.size
+        arr[i].coef.n_elements = n_el
+    opt = options if options is not None else pasm_default_options()
+    if stream is not None:
+        opt.stream = stream
+    b = _P()
+    st = L.pasm_batch_setup(ctypes.byref(b), ctypes.byref(pasm_domain(dim)), arr, n, float(H), int(k),
+                            ctypes.byref(opt))
+    _bcheck(st, None)
+    return b
+
+
+def pasm_batch_iterate(b) -> bool:
+    conv = ctypes.c_int(0)
+    _bcheck(lib().pasm_batch_iterate(b, ctypes.byref(conv)), b)
+    return bool(conv.value)
+
+
+def pasm_batch_restart(b) -> None:
+    _bcheck(lib().pasm_batch_restart(b), b)
+
+
+def pasm_batch_solve(b, allow_notconv: bool = False) -> int:
+    it = ctypes.c_int(0)
+    st = lib().pasm_batch_solve(b, ctypes.byref(it))
+    if not (allow_notconv and st == PASM_E_NOTCONV):
+        _bcheck(st, b)
+    return it.value
+
+
+def pasm_batch_num_dofs(b, member: int) -> int:
+    return int(lib().pasm_batch_num_dofs(b, member))
+
+
+def pasm_batch_num_levels(b) -> int:
+    return int(lib().pasm_batch_num_levels(b))
+
+
+def pasm_batch_eigenpairs(b, member: int, k: int, vectors: bool = True):
+    N = pasm_batch_num_dofs(b, member)
+    lam = np.empty(k)
+    U = np.empty((k, N)) if vectors else None
+    _bcheck(lib().pasm_batch_eigenpairs(b, member, _dptr(lam), _dptr(U) if vectors else None, N), b)
+    return lam, U
+
+
+def pasm_batch_set_state(b, member: int, lam: np.ndarray, U: np.ndarray) -> None:
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _bcheck(lib().pasm_batch_set_state(b, member, _dptr(lam), _dptr(U), U.shape[1]), b)
+
+
+def pasm_batch_use_graph(b, enable: bool) -> None:
+    _bcheck(lib().pasm_batch_use_graph(b, int(enable)), b)
+
+
+def pasm_batch_tuning(b):
+    L = pasm_batch_num_levels(b)
+    rows = np.zeros(L, dtype=np.int32)
+    ms = np.zeros((L, 4))
+    _bcheck(lib().pasm_batch_tuning(b, rows.ctypes.data_as(_I), _dptr(ms)), b)
+    return rows, ms
+
+
+def pasm_batch_set_tiles(b, rows) -> None:
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    _bcheck(lib().pasm_batch_set_tiles(b, r.ctypes.data_as(_I)), b)
+
+
+def pasm_batch_profile(b, kernel: int, enable: bool) -> None:
+    _bcheck(lib().pasm_batch_profile(b, kernel, int(enable)), b)
+
+
+def pasm_batch_profile_read(b, kernel: int):
+    n = ctypes.c_long(0)
+    ms = ctypes.c_double(0)
+    by = ctypes.c_double(0)
+    _bcheck(lib().pasm_batch_profile_read(b, kernel, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)), b)
+    return n.value, ms.value, by.value
+
+
+def pasm_batch_destroy(b) -> None:
+    if b:
+        _bcheck(lib().pasm_batch_destroy(b))
+
+
+class Batch:
+    """Owning wrapper around a batch of instances (h, kappa, potential)."""
+
+    def __init__(self, H, k, instances, opts=None, stream=None):
+        self.k = k
+        self.n = len(instances)
+        self.b = pasm_batch_setup(H, k, instances, opts, stream)
+
+    def iterate(self) -> bool:
+        return pasm_batch_iterate(self.b)
+
+    def solve(self, allow_notconv=False) -> int:
+        return pasm_batch_solve(self.b, allow_notconv)
+
+    def eigenpairs(self, member, vectors=True):
+        return pasm_batch_eigenpairs(self.b, member, self.k, vectors)
+
+    def eigenvalues(self) -> np.ndarray:
+        return np.stack([self.eigenpairs(i, False)[0] for i in range(self.n)])
+
+    def close(self):
+        if self.b:
+            pasm_batch_destroy(self.b)
+            self.b = None
 
     def __enter__(self):
         return self

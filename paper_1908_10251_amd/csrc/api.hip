@@ -43,35 +43,15 @@ Grid make_grid(int dim, int n) {
 
 namespace {
 
-__global__ void k_transpose(const double* __restrict__ a, double* __restrict__ b, int n) {
-    const int i = blockIdx.x * 16 + threadIdx.x, j = blockIdx.y * 16 + threadIdx.y;
-    if (i < n && j < n) b[(long)i * n + j] = a[(long)j * n + i];
-}
-__global__ void k_scale_cols(const double* __restrict__ q, const double* __restrict__ th, double* __restrict__ o,
-                             int n) {
-    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
-    if (i < n) o[(long)j * n + i] = q[(long)j * n + i] / th[j];
-}
-__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, long n) {
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
-        b[t] = (float)a[t];
-}
-__global__ void k_unit_coefs(double* __restrict__ y, int N, int k) {
-    const int j = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
-    if (j < N) y[(long)r * N + j] = (j == r) ? 1.0 : 0.0;
-}
-__global__ void k_copy_d(const double* __restrict__ a, double* __restrict__ b, int n) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < n) b[t] = a[t];
-}
-
 struct Level {
     Grid g;
     bool const_coef = true;
+    bool general = false;  // general 7-point stencil (potential term present)
     double w0 = 1.0;
     double rho = 2.0;
-    double* w64[3] = {nullptr, nullptr, nullptr};
-    float* w32[3] = {nullptr, nullptr, nullptr};
+    // coefficient arrays: 0 wx, 1 wy, 2 wz, 3 diagonal, 4 north-east weight
+    double* w64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float* w32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     std::vector<Cheb> pre, post;
     // V-cycle vectors of this level (type of the V-cycle), levels below the finest
     void* X = nullptr;
@@ -150,6 +130,10 @@ Coef<double> pasm_ctx::coef<double>(int l) const {
         c.wx = L.w64[0];
         c.wy = L.w64[1];
         c.wz = L.w64[2];
+        if (L.general) {
+            c.d = L.w64[3];
+            c.wne = L.w64[4];
+        }
     }
     c.w0 = L.w0;
     return c;
@@ -162,6 +146,10 @@ Coef<float> pasm_ctx::coef<float>(int l) const {
         c.wx = L.w32[0];
         c.wy = L.w32[1];
         c.wz = L.w32[2];
+        if (L.general) {
+            c.d = L.w32[3];
+            c.wne = L.w32[4];
+        }
     }
     c.w0 = (float)L.w0;
     return c;
@@ -170,78 +158,6 @@ Coef<float> pasm_ctx::coef<float>(int l) const {
 namespace pasm {
 namespace {
 
-// Chebyshev semi-iteration of degree s on D^{-1}A over [rho/alpha, rho], as
-// the three-term recurrence x_{j+1} = x_j + a_j (x_j - x_{j-1}) + b_j D^{-1} r_j:
-// theta = (b+a)/2, delta = (b-a)/2, sigma = theta/delta, rho_0 = 1/sigma,
-// b_0 = 1/theta, a_0 = 0; rho_j = 1/(2 sigma - rho_{j-1}),
-// a_j = rho_j rho_{j-1}, b_j = 2 rho_j / delta.
-std::vector<Cheb> cheb_steps(double rho, double alpha, int s) {
-    std::vector<Cheb> v;
-    const double lo = rho / alpha, hi = rho;
-    const double th = 0.5 * (hi + lo), de = 0.5 * (hi - lo), sg = th / de;
-    double rj = 1.0 / sg;
-    for (int j = 0; j < s; ++j) {
-        if (j == 0) v.push_back({0.0, 1.0 / th});
-        else {
-            const double rn = 1.0 / (2.0 * sg - rj);
-            v.push_back({rn * rj, 2.0 * rn / de});
-            rj = rn;
-        }
-    }
-    return v;
-}
-
-std::vector<Cheb> jacobi_steps(double omega, int s) { return std::vector<Cheb>(s, Cheb{0.0, omega}); }
-
-// Edge weights of the 2D stiffness from per-element kappa on a level with n
-// cells (element order: cell x-fastest, lower then upper triangle).  The edge
-// (i,j)-(i+1,j) is a leg of the lower triangle of cell (i,j) and of the upper
-// triangle of cell (i,j-1); the edge (i,j)-(i,j+1) of the upper triangle of
-// cell (i,j) and of the lower triangle of cell (i-1,j); each leg couples with
-// kappa_T / 2.
-void edge_weights_2d(const Grid& g, const std::vector<double>& kap, std::vector<double>& wx,
-                     std::vector<double>& wy) {
-    const int n = g.n;
-    wx.assign(g.plane, 0.0);
-    wy.assign(g.plane, 0.0);
-    auto kl = [&](int ci, int cj) { return kap[2 * ((size_t)cj * n + ci)]; };
-    auto ku = [&](int ci, int cj) { return kap[2 * ((size_t)cj * n + ci) + 1]; };
-    for (int j = 0; j <= n; ++j)
-        for (int i = 0; i <= n; ++i) {
-            if (i < n) {
-                double w = 0.0;
-                if (j < n) w += kl(i, j);
-                if (j > 0) w += ku(i, j - 1);
-                wx[g.idx(i, j)] = 0.5 * w;
-            }
-            if (j < n) {
-                double w = 0.0;
-                if (i < n) w += ku(i, j);
-                if (i > 0) w += kl(i - 1, j);
-                wy[g.idx(i, j)] = 0.5 * w;
-            }
-        }
-}
-
-// Galerkin coarsening of a per-element coefficient (2D): the coarse triangle's
-// value is the mean over its four children, which makes the rediscretised
-// coarse stiffness equal to P^T A P.  Children of the lower coarse triangle of
-// cell (I,J): lower of fine cell (2I,2J), both of (2I+1,2J), lower of
-// (2I+1,2J+1); of the upper: upper of (2I,2J), both of (2I,2J+1), upper of
-// (2I+1,2J+1).
-std::vector<double> coarsen_kappa_2d(const std::vector<double>& kf, int nf) {
-    const int nc = nf / 2;
-    std::vector<double> kc(2 * (size_t)nc * nc);
-    auto K = [&](int ci, int cj, int p) { return kf[2 * ((size_t)cj * nf + ci) + p]; };
-    for (int J = 0; J < nc; ++J)
-        for (int I = 0; I < nc; ++I) {
-            const int i = 2 * I, j = 2 * J;
-            kc[2 * ((size_t)J * nc + I)] = 0.25 * (K(i, j, 0) + K(i + 1, j, 0) + K(i + 1, j, 1) + K(i + 1, j + 1, 0));
-            kc[2 * ((size_t)J * nc + I) + 1] =
-                0.25 * (K(i, j, 1) + K(i, j + 1, 0) + K(i, j + 1, 1) + K(i + 1, j + 1, 1));
-        }
-    return kc;
-}
 
 }  // namespace
 }  // namespace pasm
@@ -291,8 +207,16 @@ void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb
     const Coef<T> cf = c->coef<T>(l);
     const bool fine = (l == c->L - 1);
     const double nodes = (double)L.g.interior();
-    const double coef_bytes = L.const_coef ? 0.0 : (double)L.g.dim * sizeof(T) * nodes;
-    if (c->fuse && pasm::fused_supported(L.g, (int)steps.size())) {
+    const double coef_bytes = L.const_coef ? 0.0 : (double)(L.general ? 4 : L.g.dim) * sizeof(T) * nodes;
+    // tallest fused tile whose LDS fits (general stencils need four coefficient tiles)
+    int rows = 0;
+    for (int r : {8, 4}) {
+        if (pasm::fused_lds_bytes(pasm::coef_kind(cf), sizeof(T), r) <= 65536 && 4 * r > 2 * (int)steps.size()) {
+            rows = r;
+            break;
+        }
+    }
+    if (c->fuse && rows > 0 && pasm::fused_supported(L.g, (int)steps.size())) {
         pasm::SmoothSteps ss{};
         ss.s = (int)steps.size();
         for (size_t j = 0; j < steps.size(); ++j) {
@@ -302,7 +226,8 @@ void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb
         // algorithmic bytes of the fused phase: read x_0 (unless zero) and f, write x_s
         const double bytes = (x_zero ? 2.0 : 3.0) * sizeof(T) * nodes * nrhs + coef_bytes;
         if (fine) record_start(c);
-        pasm::launch_smooth_fused<T>(L.g, cf, x, f, y, nrhs, L.g.plane, ss, x_zero, c->st);
+        const bool ok = pasm::launch_smooth_fused<T>(L.g, cf, x, f, y, nrhs, L.g.plane, ss, x_zero, c->st, rows);
+        if (!ok) throw Error(PASM_E_INVALID, "fused smoothing shape not supported");
         if (fine) record_end(c, bytes);
         std::swap(x, y);
         return;
@@ -422,7 +347,7 @@ namespace {
 
 struct Plan {
     int dim, nH, nh, L, NH;
-    bool have_kappa;
+    bool have_kappa, have_pot;
     size_t nel;
 };
 
@@ -459,17 +384,22 @@ Plan validate(const pasm_options& opt, const pasm_domain* dom, const pasm_coeffi
     if (opt.precision != PASM_FP64 && opt.precision != PASM_MIXED) throw Error(PASM_E_INVALID, "bad precision");
     if (opt.smoother != PASM_JACOBI && opt.smoother != PASM_CHEBYSHEV) throw Error(PASM_E_INVALID, "bad smoother");
     p.have_kappa = coef && coef->kappa;
-    if (coef && coef->potential) throw Error(PASM_E_INVALID, "potential term not supported by this build");
+    p.have_pot = coef && coef->potential;
     p.nel = 1;
     for (int a = 0; a < p.dim; ++a) p.nel *= (size_t)p.nh;
     p.nel *= (p.dim == 2 ? 2 : 6);
-    if (p.have_kappa) {
-        if (p.dim != 2) throw Error(PASM_E_INVALID, "variable kappa is supported in 2D");
+    if (p.have_kappa || p.have_pot) {
+        if (p.dim != 2) throw Error(PASM_E_INVALID, "variable kappa and the potential term are supported in 2D");
         if (coef->n_elements != p.nel) throw Error(PASM_E_INVALID, "n_elements does not match the fine mesh");
+    }
+    if (p.have_kappa)
         for (size_t e = 0; e < p.nel; ++e)
             if (!(coef->kappa[e] > 0.0) || !std::isfinite(coef->kappa[e]))
                 throw Error(PASM_E_INVALID, "kappa must be finite and positive");
-    }
+    if (p.have_pot)
+        for (size_t e = 0; e < p.nel; ++e)
+            if (!(coef->potential[e] >= 0.0) || !std::isfinite(coef->potential[e]))
+                throw Error(PASM_E_INVALID, "potential must be finite and non-negative");
     return p;
 }
 
@@ -488,29 +418,44 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
 
     // levels, coarse (0) to fine (L-1)
     c->lv.resize(L);
-    std::vector<double> kap;
+    std::vector<double> kap, pot;
     if (have_kappa) kap.assign(coef->kappa, coef->kappa + nel);
+    const bool general = pl.have_pot;
+    if (general) pot.assign(coef->potential, coef->potential + nel);
+    pasm::Stencil7 sten;   // general stencil of the level being built (host)
+    auto upload = [&](pasm::Level& Lv, int a, const std::vector<double>& w) {
+        Lv.w64[a] = c->alloc<double>(Lv.g.plane);
+        PASM_HIP(hipMemcpyAsync(Lv.w64[a], w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+        if (c->mixed) {
+            Lv.w32[a] = c->alloc<float>(Lv.g.plane);
+            pasm::launch_d2f(Lv.w64[a], Lv.w32[a], Lv.g.plane, c->st);
+            PASM_CHECK_LAUNCH();
+        }
+    };
     for (int l = L - 1; l >= 0; --l) {
         pasm::Level& Lv = c->lv[l];
         const int n = nH << l;
         Lv.g = pasm::make_grid(dim, n);
-        Lv.const_coef = !have_kappa;
+        Lv.const_coef = !have_kappa && !general;
+        Lv.general = general;
         Lv.w0 = (dim == 2) ? 1.0 : Lv.g.h;
-        if (have_kappa) {
+        if (general) {
+            // finest level assembled with the potential, coarser ones Galerkin
+            sten = (l == L - 1) ? pasm::fine_stencil_2d(Lv.g, kap, pot)
+                                : pasm::galerkin_stencil_2d(c->lv[l + 1].g, sten, Lv.g);
+            Lv.rho = pasm::gershgorin_2d(Lv.g, sten);
+            upload(Lv, 0, sten.wx);
+            upload(Lv, 1, sten.wy);
+            upload(Lv, 3, sten.d);
+            upload(Lv, 4, sten.wne);
+        } else if (have_kappa) {
             std::vector<double> wx, wy;
             pasm::edge_weights_2d(Lv.g, kap, wx, wy);
             // stiffness rows sum to zero, so the Gershgorin bound of D^{-1}A is 2
             Lv.rho = 2.0;
-            for (int a = 0; a < 2; ++a) {
-                const std::vector<double>& w = a == 0 ? wx : wy;
-                Lv.w64[a] = c->alloc<double>(Lv.g.plane);
-                PASM_HIP(hipMemcpyAsync(Lv.w64[a], w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
-                PASM_HIP(hipStreamSynchronize(c->st));
-                if (c->mixed) {
-                    Lv.w32[a] = c->alloc<float>(Lv.g.plane);
-                    hipLaunchKernelGGL(pasm::k_d2f, dim3(1024), dim3(256), 0, c->st, Lv.w64[a], Lv.w32[a], Lv.g.plane);
-                }
-            }
+            upload(Lv, 0, wx);
+            upload(Lv, 1, wy);
             if (l > 0) kap = pasm::coarsen_kappa_2d(kap, n);
         } else {
             Lv.rho = 2.0;  // constant coefficients: zero row sums, D^{-1}A Gershgorin bound 2
@@ -579,11 +524,12 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->dmv = c->alloc<char>(pasm::dense_mv_workspace_bytes(N, k));
 
     // dense coarse pencil from the level-0 operators (Galerkin: rediscretised
-    // with the coarsened coefficient)
+    // with the coarsened coefficient, or the Galerkin general stencil)
     const pasm::Level& L0 = c->lv[0];
     const Grid& g0 = L0.g;
-    std::vector<double> wx0, wy0;
-    if (!L0.const_coef) {
+    std::vector<double> wx0, wy0, AHgen;
+    if (L0.general) pasm::dense_from_stencil_2d(g0, sten, AHgen);
+    if (!L0.const_coef && !L0.general) {
         wx0.resize(g0.plane);
         wy0.resize(g0.plane);
         PASM_HIP(hipMemcpyAsync(wx0.data(), L0.w64[0], g0.plane * sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -604,21 +550,23 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
                 const int zz = dim == 3 ? l3 : 0;
                 const long r = cid(i, j, zz);
                 if (dim == 2) {
-                    const long id = g0.idx(i, j);
-                    double we, ww, wn, ws;
-                    if (L0.const_coef) we = ww = wn = ws = L0.w0;
-                    else {
-                        we = wx0[id];
-                        ww = wx0[id - 1];
-                        wn = wy0[id];
-                        ws = wy0[id - g0.pitch];
-                    }
-                    AH[r * N + r] = we + ww + wn + ws;
-                    const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
-                    const double wv[4] = {we, ww, wn, ws};
-                    for (int t = 0; t < 4; ++t) {
-                        const long q = cid(i + nb[t][0], j + nb[t][1], 0);
-                        if (q >= 0) AH[q * N + r] = -wv[t];
+                    if (!L0.general) {
+                        const long id = g0.idx(i, j);
+                        double we, ww, wn, ws;
+                        if (L0.const_coef) we = ww = wn = ws = L0.w0;
+                        else {
+                            we = wx0[id];
+                            ww = wx0[id - 1];
+                            wn = wy0[id];
+                            ws = wy0[id - g0.pitch];
+                        }
+                        AH[r * N + r] = we + ww + wn + ws;
+                        const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+                        const double wv[4] = {we, ww, wn, ws};
+                        for (int t = 0; t < 4; ++t) {
+                            const long q = cid(i + nb[t][0], j + nb[t][1], 0);
+                            if (q >= 0) AH[q * N + r] = -wv[t];
+                        }
                     }
                     const double H2 = g0.h * g0.h;
                     MH[r * N + r] = 0.5 * H2;
@@ -644,6 +592,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
                     }
                 }
             }
+    if (L0.general) AH.swap(AHgen);
     double* dA = c->Qcm;
     double* dB = c->Ainv64;  // scratch for M_H during the factorisation
     PASM_HIP(hipMemcpyAsync(dA, AH.data(), AH.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
@@ -663,9 +612,9 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     PASM_HIP(hipStreamSynchronize(c->st));
     if (info != 0) throw Error(PASM_E_DEVICE, "coarse generalized eigensolve did not converge");
     // Q^T (row-major Q) and A_H^{-1} = Q diag(1/theta) Q^T
-    hipLaunchKernelGGL(pasm::k_transpose, dim3((N + 15) / 16, (N + 15) / 16), dim3(16, 16), 0, c->st, c->Qcm, c->Qrm, N);
+    pasm::launch_transpose(c->Qcm, c->Qrm, N, c->st);
     double* QS = dB;
-    hipLaunchKernelGGL(pasm::k_scale_cols, dim3((N + 255) / 256, N), dim3(256), 0, c->st, c->Qcm, c->theta, QS, N);
+    pasm::launch_scale_cols(c->Qcm, c->theta, QS, N, c->st);
     double* Ainv = c->alloc<double>((size_t)N * N);
     const double one = 1.0, zero = 0.0;
     if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, N, N, N, &one, QS, N, c->Qcm, N,
@@ -673,7 +622,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
         throw Error(PASM_E_DEVICE, "rocblas_dgemm failed");
     c->Ainv64 = Ainv;
     if (c->mixed)
-        hipLaunchKernelGGL(pasm::k_d2f, dim3(1024), dim3(256), 0, c->st, c->Ainv64, c->Ainv32, (long)N * N);
+        pasm::launch_d2f(c->Ainv64, c->Ainv32, (long)N * N, c->st);
     // groups of equal coarse Ritz values
     std::vector<int> grp(N);
     const double gtol = 16.0 * DBL_EPSILON * std::fabs(th[N - 1]);
@@ -685,7 +634,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->lam_prev_h = c->lam_h;
     PASM_HIP(hipMemcpyAsync(c->lam, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
     PASM_HIP(hipMemcpyAsync(c->lam_prev, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
-    hipLaunchKernelGGL(pasm::k_unit_coefs, dim3((N + 255) / 256, k), dim3(256), 0, c->st, c->ycoef, N, k);
+    pasm::launch_unit_coefs(c->ycoef, N, k, k, c->st);
     PASM_CHECK_LAUNCH();
     PASM_HIP(hipStreamSynchronize(c->st));
 }
@@ -738,8 +687,8 @@ void iterate_once(pasm_ctx* c) {
     pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
     pasm::launch_arrowhead(in, out, k, c->st);
     prolong_coefs(c, c->s);
-    hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->lam, c->lam_prev, k);
-    hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->mu, c->lam, k);
+    pasm::launch_copy(c->lam, c->lam_prev, k, c->st);
+    pasm::launch_copy(c->mu, c->lam, k, c->st);
     PASM_CHECK_LAUNCH();
 }
 
@@ -853,9 +802,9 @@ PASM_API pasm_status pasm_restart(pasm_ctx* c) {
         PASM_HIP(hipStreamSynchronize(c->st));
         c->lam_h = th;
         c->lam_prev_h = th;
-        hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->theta, c->lam, k);
-        hipLaunchKernelGGL(pasm::k_copy_d, dim3((k + 255) / 256), dim3(256), 0, c->st, c->theta, c->lam_prev, k);
-        hipLaunchKernelGGL(pasm::k_unit_coefs, dim3((N + 255) / 256, k), dim3(256), 0, c->st, c->ycoef, N, k);
+        pasm::launch_copy(c->theta, c->lam, k, c->st);
+        pasm::launch_copy(c->theta, c->lam_prev, k, c->st);
+        pasm::launch_unit_coefs(c->ycoef, N, k, k, c->st);
         PASM_CHECK_LAUNCH();
         prolong_coefs(c, nullptr);
         PASM_HIP(hipStreamSynchronize(c->st));

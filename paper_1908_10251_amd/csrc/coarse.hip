@@ -58,18 +58,27 @@ __device__ inline long compact_to_padded(const Grid& g, int c) {
     return g.idx(i, j, c / (g.m * g.m) + 1);
 }
 
+// Batches: right-hand side r belongs to member r / kpm, whose matrix starts
+// mstride elements after the previous member's; a workgroup's right-hand
+// sides never straddle two members.
 template <typename T>
 __global__ __launch_bounds__(DM_R) void k_dmv_part(const T* __restrict__ Mat, int N, Grid g, const T* __restrict__ x,
-                                                   long sx, int xpad, T* __restrict__ part, int nrhs) {
+                                                   long sx, int xpad, T* __restrict__ part, int nrhs, int kpm,
+                                                   long mstride) {
     __shared__ T xs[DM_K][DM_C];
     const int row = blockIdx.x * DM_R + threadIdx.x;
     const int c0 = blockIdx.y * DM_C;
-    const int r0 = blockIdx.z * DM_K;
+    const int zb = (kpm + DM_K - 1) / DM_K;  // workgroups per member
+    const int mem = blockIdx.z / zb;
+    const int rlo = (blockIdx.z % zb) * DM_K;  // first right-hand side within the member
+    const int r0 = mem * kpm + rlo;
+    const int rn = min(DM_K, kpm - rlo);       // right-hand sides of this workgroup
+    Mat += (long)mem * mstride;
     const int cn = min(DM_C, N - c0);
     for (int t = threadIdx.x; t < DM_K * DM_C; t += DM_R) {
         const int rr = t / DM_C, cc = t % DM_C;
         T v = T(0);
-        if (r0 + rr < nrhs && cc < cn) {
+        if (rr < rn && cc < cn) {
             const long base = (long)(r0 + rr) * sx;
             v = xpad ? x[base + compact_to_padded(g, c0 + cc)] : x[base + c0 + cc];
         }
@@ -87,7 +96,7 @@ __global__ __launch_bounds__(DM_R) void k_dmv_part(const T* __restrict__ Mat, in
     }
 #pragma unroll
     for (int rr = 0; rr < DM_K; ++rr)
-        if (r0 + rr < nrhs) part[((long)blockIdx.y * nrhs + r0 + rr) * N + row] = acc[rr];
+        if (rr < rn) part[((long)blockIdx.y * nrhs + r0 + rr) * N + row] = acc[rr];
 }
 
 template <typename T>
@@ -180,6 +189,8 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
     __shared__ double bs[PT], bm[PT];
     __shared__ int bl[PT], bt[PT];
     const int r = blockIdx.x, N = in.N;
+    in.theta += (long)(r / in.kpm) * N;  // this eigenpair's member
+    in.group += (long)(r / in.kpm) * N;
     WS w = ws_of(work, iwork, best, N, nchunk, r);
     const double* p = in.p + (long)r * N;
     const double* q = in.q + (long)r * N;
@@ -518,6 +529,8 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
     __shared__ double win[4];  // score, mu, kind (0 root, 1 deflated), id
     __shared__ int rk;
     const int r = blockIdx.x, N = in.N;
+    in.theta += (long)(r / in.kpm) * N;  // this eigenpair's member
+    in.group += (long)(r / in.kpm) * N;
     WS w = ws_of(work, iwork, best, N, nchunk, r);
     const double* q = in.q + (long)r * N;
     const double lp = in.lam_prev[r];
@@ -641,20 +654,24 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
 
 template <typename T>
 void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded, T* y, long sy,
-                     bool y_padded, int nrhs, void* work, hipStream_t st) {
+                     bool y_padded, int nrhs, void* work, hipStream_t st, int kpm, long mstride) {
+    if (kpm <= 0) kpm = nrhs;
+    if (nrhs % kpm != 0) throw Error(PASM_E_INVALID, "dense products: right-hand sides not a multiple per member");
     const int nchunk = (N + DM_C - 1) / DM_C;
     T* part = static_cast<T*>(work);
-    dim3 g1((N + DM_R - 1) / DM_R, nchunk, (nrhs + DM_K - 1) / DM_K);
-    hipLaunchKernelGGL((k_dmv_part<T>), g1, dim3(DM_R), 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs);
+    const int zb = (kpm + DM_K - 1) / DM_K;
+    dim3 g1((N + DM_R - 1) / DM_R, nchunk, (nrhs / kpm) * zb);
+    hipLaunchKernelGGL((k_dmv_part<T>), g1, dim3(DM_R), 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs, kpm,
+                       mstride);
     PASM_CHECK_LAUNCH();
     hipLaunchKernelGGL((k_dmv_sum<T>), dim3((N + 255) / 256, nrhs), dim3(256), 0, st, N, nchunk, part, nrhs, g, y, sy,
                        (int)y_padded);
     PASM_CHECK_LAUNCH();
 }
 template void launch_dense_mv<double>(const double*, int, const Grid&, const double*, long, bool, double*, long,
-                                      bool, int, void*, hipStream_t);
+                                      bool, int, void*, hipStream_t, int, long);
 template void launch_dense_mv<float>(const float*, int, const Grid&, const float*, long, bool, float*, long, bool,
-                                     int, void*, hipStream_t);
+                                     int, void*, hipStream_t, int, long);
 
 size_t dense_mv_workspace_bytes(int N, int nrhs) {
     return sizeof(double) * (size_t)((N + DM_C - 1) / DM_C) * nrhs * N;
@@ -663,7 +680,9 @@ size_t dense_mv_workspace_bytes(int N, int nrhs) {
 long arrow_work_doubles(int N, int k) { return ws_doubles(N) * (long)k; }
 int arrow_chunks(int N) { return (N + 1 + RPB - 1) / RPB; }
 
-void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t st) {
+void launch_arrowhead(const ArrowIn& in0, const ArrowOut& out, int k, hipStream_t st) {
+    ArrowIn in = in0;
+    if (in.kpm <= 0) in.kpm = k;
     const int nchunk = arrow_chunks(in.N);
     double* work = out.work;
     int* iwork = reinterpret_cast<int*>(work + arrow_work_doubles(in.N, k));

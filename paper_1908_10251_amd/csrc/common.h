@@ -47,18 +47,39 @@ struct Grid {
 
 Grid make_grid(int dim, int n);
 
-// Operator coefficients of one level.  Stiffness as edge weights: w[a] holds,
-// at node x, the weight of the edge (x, x + e_a) (2D: a = 0 east, 1 north).
-// A x = sum over edges (x, y) of w_xy (x_x - x_y): the 5-point (2D) or
-// 7-point (3D) stencil.  With constant coefficients the arrays are absent and
-// every edge has weight w0.
+// Operator coefficients of one level, in one of three forms:
+//  constant  (wx == nullptr): every edge has weight w0, A x = sum over edges
+//            (x, y) of w0 (x_x - x_y): the 5-point (2D) or 7-point (3D)
+//            stencil;
+//  edge      (wx set, d == nullptr): w[a] holds, at node x, the weight of the
+//            edge (x, x + e_a) (2D: a = 0 east, 1 north); the diagonal is the
+//            sum of the four edge weights at the node (zero row sums);
+//  general   (d set, 2D): (A x)_x = d_x x_x - sum over the six neighbours y of
+//            the "/" mesh of w_xy x_y, with w_xy in wx (east), wy (north) and
+//            wne (north-east) at the lower-left node of the edge.  This holds
+//            the stiffness plus a potential's mass-type term, and their
+//            Galerkin coarsenings.
+// A batch of several problems of the same grid stores one coefficient plane
+// per member, ms elements apart; right-hand side z belongs to member z / kpm.
+// bsc (optional, per member) scales the b coefficients of the smoother steps.
 template <typename T>
 struct Coef {
     const T* wx = nullptr;
     const T* wy = nullptr;
     const T* wz = nullptr;
+    const T* d = nullptr;
+    const T* wne = nullptr;
     T w0 = T(1);
+    long ms = 0;
+    int kpm = 1;
+    const T* bsc = nullptr;
 };
+
+// 0: constant, 1: edge weights, 2: general 7-point
+template <typename T>
+inline int coef_kind(const Coef<T>& c) {
+    return c.d ? 2 : (c.wx ? 1 : 0);
+}
 
 #define PASM_HIP(call)                                                              \
     do {                                                                            \
@@ -99,22 +120,33 @@ struct SmoothSteps {
 
 bool fused_supported(const Grid& g, int steps);
 
+// Tile heights of the fused smoothing phase: a workgroup covers 4 * rows LDS
+// rows of 64 columns.  rows must be one of these.
+constexpr int kFusedRows[3] = {2, 4, 8};
+// LDS bytes a fused launch of this shape needs (must stay within 64 KiB).
+size_t fused_lds_bytes(int kind, size_t elem, int rows);
+
 // All steps of a phase in one launch (2D, s <= 4): out = x_s from x_0 (or 0).
 // Returns false when the shape is not covered (caller falls back to steps).
 template <typename T>
 bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs,
-                         long stride, const SmoothSteps& ss, bool x_zero, hipStream_t st);
+                         long stride, const SmoothSteps& ss, bool x_zero, hipStream_t st, int rows = 8);
 
 // Marching smoothing phases (2D, constant coefficients, 1..4 steps).
 // pre:  out = x_s (from x0, or from 0), rc = P^T (f - A x_s) on the coarser grid gc
 // post: out = x_s starting from x + P ec
+// rows: rows of the band a wavefront marches down (even); 0 picks it so that
+// the whole grid is resident at once where possible.
 bool march_supported(const Grid& g, bool const_coef, int steps);
+struct MarchShape {
+    int strips, segs, mseg, work, blocks;
+};
 template <typename T>
 void launch_march_pre(const Grid& g, T w0, const T* x0, const T* f, T* out, const Grid& gc, T* rc, int nrhs,
-                      const SmoothSteps& ss, bool x_zero, hipStream_t st);
+                      const SmoothSteps& ss, bool x_zero, hipStream_t st, int rows = 0);
 template <typename T>
 void launch_march_post(const Grid& g, T w0, const T* x, const T* f, T* out, const Grid& gc, const T* ec, int nrhs,
-                       const SmoothSteps& ss, hipStream_t st);
+                       const SmoothSteps& ss, hipStream_t st, int rows = 0);
 
 template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
@@ -143,9 +175,14 @@ void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long st
 // r32 = (f - A u) in FP64, rounded to FP32
 void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f,
                        float* r, int nrhs, long stride, hipStream_t st);
+// r = f - A u in FP64, stored as TO (2D)
+template <typename TO>
+void launch_resid_to(const Grid& g, const Coef<double>& c, const double* u, const double* f, TO* r, int nrhs,
+                     long stride, hipStream_t st);
 
 // u += e (whole blocks, boundary entries stay zero)
 void launch_add_correction(const float* e, double* u, long n, hipStream_t st);
+void launch_add_correction(const double* e, double* u, long n, hipStream_t st);
 
 // Border sweep: au = A u, mu = M u, partial[r][blk][2] = block sums of
 // (u . au, u . mu).  Returns the number of blocks per right-hand side.
@@ -166,14 +203,45 @@ void launch_unpack(const Grid& g, const double* compact, long ld, T* padded, lon
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // ----------------------------------------------------------------------------
+// Host-side level construction (levels.hip)
+// ----------------------------------------------------------------------------
+// A general 2D stencil on a padded plane (see Coef): diagonal d and the
+// weights of the east, north and north-east edges at their lower-left node.
+struct Stencil7 {
+    std::vector<double> d, wx, wy, wne;
+};
+void edge_weights_2d(const Grid& g, const std::vector<double>& kap, std::vector<double>& wx,
+                     std::vector<double>& wy);
+std::vector<double> coarsen_kappa_2d(const std::vector<double>& kf, int nf);
+Stencil7 fine_stencil_2d(const Grid& g, const std::vector<double>& kap, const std::vector<double>& pot);
+Stencil7 galerkin_stencil_2d(const Grid& gf, const Stencil7& sf, const Grid& gc);
+double gershgorin_2d(const Grid& g, const Stencil7& s);
+void dense_from_stencil_2d(const Grid& g, const Stencil7& s, std::vector<double>& A);
+
+// Chebyshev steps of degree s on [rho/alpha, rho]; damped Jacobi steps.
+std::vector<Cheb> cheb_steps(double rho, double alpha, int s);
+std::vector<Cheb> jacobi_steps(double omega, int s);
+
+// b = a^T (n x n); o[:, j] = q[:, j] / th[j]; b = (float) a; y[r][j] = (j == r mod kpm);
+// b = a (n doubles)
+void launch_transpose(const double* a, double* b, int n, hipStream_t st);
+void launch_scale_cols(const double* q, const double* th, double* o, int n, hipStream_t st);
+void launch_d2f(const double* a, float* b, long n, hipStream_t st);
+void launch_unit_coefs(double* y, int N, int nrhs, int kpm, hipStream_t st);
+void launch_copy(const double* a, double* b, int n, hipStream_t st);
+
+// ----------------------------------------------------------------------------
 // Coarse-space kernels (coarse.hip)
 // ----------------------------------------------------------------------------
 // y[r] = Mat x[r] with Mat(row, col) stored at Mat[col * N + row]; x and y in
 // either the padded layout of level g (flag true) or compact (flag false).
 // `work` holds dense_mv_workspace_bytes(N, nrhs) bytes.
+// Batches: kpm right-hand sides per member, member m multiplies by the
+// matrix at Mat + m * mstride (kpm = 0: one matrix for all).
 template <typename T>
 void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded,
-                     T* y, long sy, bool y_padded, int nrhs, void* work, hipStream_t st);
+                     T* y, long sy, bool y_padded, int nrhs, void* work, hipStream_t st, int kpm = 0,
+                     long mstride = 0);
 size_t dense_mv_workspace_bytes(int N, int nrhs);
 
 struct ArrowIn {
@@ -185,6 +253,7 @@ struct ArrowIn {
     const double* lam_prev; // [k]
     int N;
     int exhaustive;         // 1: never skip the full root pass
+    int kpm = 0;            // eigenpairs per member: theta and group hold N values per member
 };
 struct ArrowOut {
     double* ycoef;  // [k][N] coefficients y' of the new eigenvector in the Q basis
@@ -196,5 +265,6 @@ struct ArrowOut {
     double* work;   // [k][3N + 8] scratch
 };
 void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t st);
+size_t arrow_workspace_bytes(int N, int k);
 
 }  // namespace pasm

@@ -21,6 +21,8 @@
 //         x_0 = x + P e_c.
 // Steps follow x_{t+1} = x_t + a_t (x_t - x_{t-1}) + b_t D^{-1} (f - A x_t)
 // with a_0 = 0 (a phase starts fresh).
+#include <algorithm>
+
 #include "common.h"
 
 namespace pasm {
@@ -29,9 +31,17 @@ namespace {
 
 constexpr int NL = 64;      // lanes per wavefront
 constexpr int MW = 2 * NL;  // strip width: each lane owns two adjacent columns
-constexpr int MSEG = 64;    // rows owned by one wavefront (even)
-constexpr int MWAVES = 4;   // wavefronts per workgroup (consecutive segments)
-constexpr int PF = 3;       // rows loaded ahead of the one being processed
+constexpr int XCDS = 8;     // accelerator dies; workgroup w runs on die w % 8
+// Rows loaded ahead of the one being processed.  The loop over rows is
+// unrolled by PF so that every prefetch slot is a fixed set of registers: a
+// slot is consumed and refilled in the same unrolled body, and the only wait
+// is for the oldest row in flight (rotating a register queue instead would
+// make the compiler wait for every outstanding load).
+template <typename T>
+constexpr int prefetch_rows() { return sizeof(T) == 8 ? 3 : 6; }
+constexpr int gcd_(int a, int b) { return b == 0 ? a : gcd_(b, a % b); }
+constexpr int lcm_(int a, int b) { return a / gcd_(a, b) * b; }
+constexpr int march_unroll(int S, int PF) { return lcm_(lcm_(3, S + 2), PF); }
 
 // Cross-lane moves of a double by one lane (DPP wave shifts; the lane at the
 // wavefront edge receives 0, which only ever reaches halo columns).
@@ -52,29 +62,52 @@ __device__ inline float from_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 
-template <typename T, int S, int MODE>
-__global__ __launch_bounds__(NL* MWAVES) void k_march(Grid g, T w0, const T* __restrict__ x0,
-                                                      const T* __restrict__ f, T* __restrict__ out,
-                                                      const T* __restrict__ ec, Grid gc, T* __restrict__ rc, long sf,
-                                                      long sc, SmoothSteps st, int x_zero) {
+// A register copy the compiler cannot fold away: the copy, not the loaded
+// register, lives on in the row windows.
+__device__ inline double detach(double v) {
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ inline float detach(float v) {
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+template <typename T, int S, int MODE, bool XZ>
+__global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
+                                              T* __restrict__ out, const T* __restrict__ ec, Grid gc,
+                                              T* __restrict__ rc, long sf, long sc, SmoothSteps st, MarchShape sh) {
+    constexpr int PF = prefetch_rows<T>();
     constexpr int HX = S + 2;
     constexpr int TXO = MW - 2 * HX;
+    // One wavefront per workgroup.  Consecutive pieces of work (strips of a
+    // band of rows, then the next band, then the next right-hand side) go to
+    // the same die, so the halos that neighbouring strips and bands share are
+    // found in that die's L2.
+    const int per = sh.blocks / XCDS;
+    const int work = (blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
+    if (work >= sh.work) return;  // uniform per wavefront
+    const int strip = work % sh.strips;
+    const int band = (work / sh.strips) % sh.segs;
+    const int z = work / (sh.strips * sh.segs);
+    const int MSEG = sh.mseg;
     const int lane = threadIdx.x;
-    const int y0 = (blockIdx.y * MWAVES + threadIdx.y) * MSEG;
-    if (y0 > g.n) return;  // uniform per wavefront
+    const int y0 = band * MSEG;
     const int c0 = 2 * lane;                      // strip column of the lane's first column
-    const int i0 = blockIdx.x * TXO - HX + c0;    // global column (even)
+    const int i0 = strip * TXO - HX + c0;         // global column (even)
     bool inner[2], owned[2];
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc) {
         inner[cc] = (i0 + cc) >= 1 && (i0 + cc) <= g.m;
         owned[cc] = (c0 + cc) >= HX && (c0 + cc) < MW - HX;
     }
-    const long off = (long)blockIdx.z * sf;
+    const long off = (long)z * sf;
     const T* xr = x0 + off;
     const T* fr = f + off;
     T* outr = out + off;
-    const T* ecr = ec + (long)blockIdx.z * sc;
+    const T* ecr = ec + (long)z * sc;
     const T invD = T(1) / (T(4) * w0);
     T bs[S], as[S];
 #pragma unroll
@@ -103,53 +136,59 @@ __global__ __launch_bounds__(NL* MWAVES) void k_march(Grid g, T w0, const T* __r
     // whose stored values are zero (the Dirichlet data), which is exactly the
     // value such positions must have.
     const int ia = min(max(i0, 0), g.n), ib = min(max(i0 + 1, 0), g.n);
-    auto prolong_at = [&](int i, int r) -> T {
-        // nodal interpolation of the coarse correction at fine node (i, r):
-        // the mean of coarse nodes (I, J) and (I + a, J + b); for a = b = 0 both
-        // reads are the same node and the mean is exact, so there is no branch
-        const int a = i & 1, b = r & 1;
-        const long cid = gc.idx(i >> 1, r >> 1);
-        return T(0.5) * (ecr[cid] + ecr[cid + a + (long)b * gc.pitch]);
+    // One prefetched row: the raw loaded values, combined only when the row
+    // is consumed, PF rows later (combining at load time would wait for the
+    // loads at once).  POST reads the two coarse nodes whose mean is the
+    // nodal interpolation of the coarse correction at the fine node: coarse
+    // (I, J) and (I + a, J + b), a = i & 1, b = r & 1; for a = b = 0 both
+    // reads are the same node and the mean is exact, so there is no branch.
+    struct Slot {
+        T x[2], f[2], e0[2], e1[2];
     };
-    auto load = [&](int r, T* xv, T* fv) {
+    auto load = [&](int r, Slot& sl) {
         const int rr = min(max(r, 0), g.n);
         const long row = (long)rr * g.pitch + ORIGIN;
-        fv[0] = fr[row + ia];
-        fv[1] = fr[row + ib];
+        sl.f[0] = fr[row + ia];
+        sl.f[1] = fr[row + ib];
+        if (MODE == 2 || !XZ) {
+            sl.x[0] = xr[row + ia];
+            sl.x[1] = xr[row + ib];
+        }
         if (MODE == 2) {
-            xv[0] = xr[row + ia] + prolong_at(ia, rr);
-            xv[1] = xr[row + ib] + prolong_at(ib, rr);
-        } else if (!x_zero) {
-            xv[0] = xr[row + ia];
-            xv[1] = xr[row + ib];
-        } else {
-            xv[0] = xv[1] = T(0);
+            const int cols[2] = {ia, ib};
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const int i = cols[cc], a = i & 1, b = rr & 1;
+                const long cid = gc.idx(i >> 1, rr >> 1);
+                sl.e0[cc] = ecr[cid];
+                sl.e1[cc] = ecr[cid + a + (long)b * gc.pitch];
+            }
         }
     };
 
-    T qx[PF][2], qf[PF][2];
-#pragma unroll
-    for (int p = 0; p < PF; ++p) load(r_begin + p, qx[p], qf[p]);
-
-    for (int r = r_begin; r <= r_end; ++r) {
-        T cx[2] = {qx[0][0], qx[0][1]}, cf[2] = {qf[0][0], qf[0][1]};
-#pragma unroll
-        for (int p = 0; p < PF - 1; ++p) {
-            qx[p][0] = qx[p + 1][0];
-            qx[p][1] = qx[p + 1][1];
-            qf[p][0] = qf[p + 1][0];
-            qf[p][1] = qf[p + 1][1];
-        }
-        load(r + PF, qx[PF - 1], qf[PF - 1]);
+    // Row r enters the windows of x_0 and f.  The window registers are fresh
+    // copies, so the slot's registers are free for the next load at once.
+    auto shift_in = [&](const Slot& sl) {
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
+            T cx;
+            if (MODE == 2)
+                cx = sl.x[cc] + T(0.5) * (sl.e0[cc] + sl.e1[cc]);
+            else if (!XZ)
+                cx = detach(sl.x[cc]);
+            else
+                cx = T(0);
 #pragma unroll
             for (int j = S + 1; j > 0; --j) fw[j][cc] = fw[j - 1][cc];
-            fw[0][cc] = cf[cc];
+            fw[0][cc] = detach(sl.f[cc]);
             xw[0][2][cc] = xw[0][1][cc];
             xw[0][1][cc] = xw[0][0][cc];
-            xw[0][0][cc] = cx[cc];
+            xw[0][0][cc] = cx;
         }
+    };
+    // After row r entered: advance every stage by one row, store x_S of row
+    // r - S, and (PRE) the residual and its restriction.
+    auto advance = [&](const int r) {
 #pragma unroll
         for (int t = 1; t <= S; ++t) {
             const int q = r - t;
@@ -210,33 +249,95 @@ __global__ __launch_bounds__(NL* MWAVES) void k_march(Grid g, T w0, const T* __r
             if (((q2 & 1) == 0) && q2 >= y0 && q2 < y0 + MSEG && owned[0]) {
                 const int I = i0 >> 1, J = q2 >> 1;
                 if (I >= 1 && I <= gc.m && J >= 1 && J <= gc.m)
-                    rc[(long)blockIdx.z * sc + gc.idx(I, J)] =
+                    rc[(long)z * sc + gc.idx(I, J)] =
                         rw[1][0] + T(0.5) * (rw[1][1] + mid_left + rw[0][0] + rw[2][0] + rw[0][1] + dn_left);
             }
+        }
+    };
+
+    Slot q[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load(r_begin + p, q[p]);
+    // The loop body covers UNR rows, a multiple of PF and of the periods of
+    // the rotating row windows (3 rows of x, S + 2 rows of f), so that after
+    // unrolling every window and slot is back in its own registers at the
+    // back edge.  Rows past r_end (at most UNR - 1) only feed halo stages:
+    // nothing stored depends on them.
+    constexpr int UNR = march_unroll(S, PF);
+    const int iters = (r_end - r_begin + UNR) / UNR;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            // the slot is refilled as soon as its row is in the windows
+            const int r = r_begin + it * UNR + u;
+            shift_in(q[u % PF]);
+            load(r + PF, q[u % PF]);
+            advance(r);
         }
     }
 }
 
+// Workgroup slots of the whole device for a kernel (one wavefront each).
+template <typename K>
+int device_wave_slots(K kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    PASM_HIP(hipGetDevice(&dev));
+    PASM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    PASM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NL, 0));
+    return std::max(1, cus * per_cu);
+}
+
+// Rows per band: all wavefronts resident at once where the grid allows it
+// (a second partial round would double the time), else 64.
+MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows) {
+    MarchShape sh{};
+    sh.strips = (g.n + 1 + txo - 1) / txo;
+    const long base = (long)sh.strips * nrhs;
+    int mseg = rows;
+    if (mseg <= 0) {
+        const long bands64 = (g.n + 1 + 63) / 64;
+        if (base * bands64 >= slots) {
+            mseg = 64;
+        } else {
+            const long bands = std::max<long>(1, slots / base);
+            mseg = (int)((g.n + 1 + bands - 1) / bands);
+            mseg = std::max(32, (mseg + 1) & ~1);
+        }
+    }
+    sh.mseg = (mseg + 1) & ~1;
+    sh.segs = (g.n + 1 + sh.mseg - 1) / sh.mseg;
+    sh.work = (int)(base * sh.segs);
+    sh.blocks = (sh.work + XCDS - 1) / XCDS * XCDS;
+    return sh;
+}
+
 template <typename T, int S, int MODE>
 void march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc,
-                  int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+                  int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows, hipStream_t st) {
     constexpr int TXO = MW - 2 * (S + 2);
-    const int strips = (g.n + 1 + TXO - 1) / TXO;
-    const int segs = (g.n + 1 + MSEG - 1) / MSEG;
-    dim3 grid(strips, (segs + MWAVES - 1) / MWAVES, nrhs);
-    hipLaunchKernelGGL((k_march<T, S, MODE>), grid, dim3(NL, MWAVES), 0, st, g, w0, x0, f, out, ec, gc, rc, sf, sc,
-                       ss, (int)x_zero);
+    static const int slots = device_wave_slots(k_march<T, S, MODE, false>);
+    const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
+    if constexpr (MODE == 1) {
+        if (x_zero) {
+            hipLaunchKernelGGL((k_march<T, S, MODE, true>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
+                               gc, rc, sf, sc, ss, sh);
+            PASM_CHECK_LAUNCH();
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_march<T, S, MODE, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
+                       sf, sc, ss, sh);
     PASM_CHECK_LAUNCH();
 }
 
 template <typename T, int MODE>
 void march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc,
-                    int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+                    int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows, hipStream_t st) {
     switch (ss.s) {
-        case 1: march_launch<T, 1, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, st); break;
-        case 2: march_launch<T, 2, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, st); break;
-        case 3: march_launch<T, 3, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, st); break;
-        case 4: march_launch<T, 4, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, st); break;
+        case 1: march_launch<T, 1, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
+        case 2: march_launch<T, 2, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
+        case 3: march_launch<T, 3, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
+        case 4: march_launch<T, 4, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
         default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
     }
 }
@@ -252,23 +353,24 @@ bool march_supported(const Grid& g, bool const_coef, int steps) {
 
 template <typename T>
 void launch_march_pre(const Grid& g, T w0, const T* x0, const T* f, T* out, const Grid& gc, T* rc, int nrhs,
-                      const SmoothSteps& ss, bool x_zero, hipStream_t st) {
-    march_dispatch<T, 1>(g, w0, x0, f, out, (const T*)nullptr, gc, rc, nrhs, g.plane, gc.plane, ss, x_zero, st);
+                      const SmoothSteps& ss, bool x_zero, hipStream_t st, int rows) {
+    march_dispatch<T, 1>(g, w0, x0, f, out, (const T*)nullptr, gc, rc, nrhs, g.plane, gc.plane, ss, x_zero, rows,
+                         st);
 }
 
 template <typename T>
 void launch_march_post(const Grid& g, T w0, const T* x, const T* f, T* out, const Grid& gc, const T* ec, int nrhs,
-                       const SmoothSteps& ss, hipStream_t st) {
-    march_dispatch<T, 2>(g, w0, x, f, out, ec, gc, (T*)nullptr, nrhs, g.plane, gc.plane, ss, false, st);
+                       const SmoothSteps& ss, hipStream_t st, int rows) {
+    march_dispatch<T, 2>(g, w0, x, f, out, ec, gc, (T*)nullptr, nrhs, g.plane, gc.plane, ss, false, rows, st);
 }
 
 template void launch_march_pre<double>(const Grid&, double, const double*, const double*, double*, const Grid&,
-                                       double*, int, const SmoothSteps&, bool, hipStream_t);
+                                       double*, int, const SmoothSteps&, bool, hipStream_t, int);
 template void launch_march_pre<float>(const Grid&, float, const float*, const float*, float*, const Grid&, float*,
-                                      int, const SmoothSteps&, bool, hipStream_t);
+                                      int, const SmoothSteps&, bool, hipStream_t, int);
 template void launch_march_post<double>(const Grid&, double, const double*, const double*, double*, const Grid&,
-                                        const double*, int, const SmoothSteps&, hipStream_t);
+                                        const double*, int, const SmoothSteps&, hipStream_t, int);
 template void launch_march_post<float>(const Grid&, float, const float*, const float*, float*, const Grid&,
-                                       const float*, int, const SmoothSteps&, hipStream_t);
+                                       const float*, int, const SmoothSteps&, hipStream_t, int);
 
 }  // namespace pasm

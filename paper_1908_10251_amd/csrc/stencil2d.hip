@@ -27,47 +27,74 @@ inline dim3 grid_for(int mx, int my, int nrhs) {
     return dim3((mx + BX - 1) / BX, (my + BY - 1) / BY, nrhs);
 }
 
-template <typename T, bool CONST>
+// KIND: 0 constant coefficients, 1 edge weights, 2 general 7-point (see Coef).
+template <typename T, int KIND>
 struct Stiff2 {
     // Returns A x at node id and the diagonal D.
     __device__ static inline void apply(const Grid& g, const Coef<T>& c, const T* __restrict__ x,
                                         long id, T& Ax, T& D) {
+        const int p = g.pitch;
         const T x0 = x[id];
-        const T xe = x[id + 1], xw = x[id - 1], xn = x[id + g.pitch], xs = x[id - g.pitch];
-        if (CONST) {
+        const T xe = x[id + 1], xw = x[id - 1], xn = x[id + p], xs = x[id - p];
+        if (KIND == 0) {
             D = T(4) * c.w0;
             Ax = c.w0 * (T(4) * x0 - xe - xw - xn - xs);
-        } else {
-            const T we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - g.pitch];
+        } else if (KIND == 1) {
+            const T we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - p];
             D = we + ww + wn + ws;
             Ax = D * x0 - we * xe - ww * xw - wn * xn - ws * xs;
+        } else {
+            const T we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - p];
+            const T wa = c.wne[id], wb = c.wne[id - p - 1];
+            D = c.d[id];
+            Ax = D * x0 - we * xe - ww * xw - wn * xn - ws * xs - wa * x[id + p + 1] - wb * x[id - p - 1];
         }
     }
     __device__ static inline T diag(const Grid& g, const Coef<T>& c, long id) {
-        if (CONST) return T(4) * c.w0;
-        return c.wx[id] + c.wx[id - 1] + c.wy[id] + c.wy[id - g.pitch];
+        if (KIND == 0) return T(4) * c.w0;
+        if (KIND == 1) return c.wx[id] + c.wx[id - 1] + c.wy[id] + c.wy[id - g.pitch];
+        return c.d[id];
     }
 };
 
+// The coefficients of the member that right-hand side z belongs to, and that
+// member's factor on the smoother's b coefficients.
+template <typename T>
+__device__ inline Coef<T> member_coef(const Coef<T>& c, int z, T& bscale) {
+    Coef<T> r = c;
+    const int mem = z / c.kpm;
+    const long o = (long)mem * c.ms;
+    if (r.wx) r.wx += o;
+    if (r.wy) r.wy += o;
+    if (r.wz) r.wz += o;
+    if (r.d) r.d += o;
+    if (r.wne) r.wne += o;
+    bscale = c.bsc ? c.bsc[mem] : T(1);
+    return r;
+}
+
 // One smoothing step, x_{k+1} = x_k + a (x_k - x_{k-1}) + b D^{-1} (f - A x_k).
 // xp may alias xn: each thread reads xp at its own node before writing xn there.
-template <typename T, bool CONST>
-__global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> c, const T* __restrict__ xc,
+template <typename T, int KIND>
+__global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> cg, const T* __restrict__ xc,
                                                    const T* xp, const T* __restrict__ f, T* xn,
                                                    long stride, T a, T b, int zmode) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
+    T bs;
+    const Coef<T> c = member_coef(cg, blockIdx.z, bs);
+    b *= bs;
     const long off = (long)blockIdx.z * stride;
     const long id = g.idx(i, j);
     const T fv = f[off + id];
     if (zmode & 1) {
-        const T D = Stiff2<T, CONST>::diag(g, c, id);
+        const T D = Stiff2<T, KIND>::diag(g, c, id);
         xn[off + id] = b * fv / D;
         return;
     }
     T Ax, D;
-    Stiff2<T, CONST>::apply(g, c, xc + off, id, Ax, D);
+    Stiff2<T, KIND>::apply(g, c, xc + off, id, Ax, D);
     const T x0 = xc[off + id];
     T v = x0 + b * (fv - Ax) / D;
     if (a != T(0)) v += a * (x0 - ((zmode & 2) ? T(0) : xp[off + id]));
@@ -86,13 +113,18 @@ __global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> c, const T* _
 // discarded.  Nodes on or outside the domain boundary stay zero.  A phase
 // always starts fresh (a_0 = 0), so only x_0 is read, and not at all when
 // x_0 = 0.
-template <typename T, bool CONST, int S, int ROWS>
-__global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> c, const T* __restrict__ x0,
+template <typename T, int KIND, int S, int ROWS>
+__global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> cg, const T* __restrict__ x0,
                                                       const T* __restrict__ f, T* __restrict__ out, long stride,
                                                       SmoothSteps st, int x_zero) {
     constexpr int W = 64, HH = 4 * ROWS, TX = W - 2 * S, TY = HH - 2 * S;
+    constexpr bool CONST = KIND == 0;
+    constexpr bool GEN = KIND == 2;
     __shared__ T sa[W * HH], sb[W * HH];
     __shared__ T swx[CONST ? 1 : W * HH], swy[CONST ? 1 : W * HH];
+    __shared__ T sd[GEN ? W * HH : 1], swne[GEN ? W * HH : 1];
+    T bsc;
+    const Coef<T> c = member_coef(cg, blockIdx.z, bsc);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int i = blockIdx.x * TX + 1 - S + tx;  // global column of this thread
     const int jb = blockIdx.y * TY + 1 - S;      // global row of LDS row 0
@@ -118,6 +150,10 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> c, const T
             const bool stored = i >= 0 && i <= g.n && j >= 0 && j <= g.n;
             swx[ly * W + tx] = (stored && i < g.n) ? c.wx[g.idx(i, j)] : T(0);
             swy[ly * W + tx] = (stored && j < g.n) ? c.wy[g.idx(i, j)] : T(0);
+            if (GEN) {
+                swne[ly * W + tx] = (stored && i < g.n && j < g.n) ? c.wne[g.idx(i, j)] : T(0);
+                sd[ly * W + tx] = inner ? c.d[g.idx(i, j)] : T(1);
+            }
         }
     }
     __syncthreads();
@@ -126,7 +162,7 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> c, const T
     T* nxt = sb;
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        const T a = (T)st.a[t], b = (T)st.b[t];
+        const T a = (T)st.a[t], b = (T)st.b[t] * bsc;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int p = (ty + 4 * r) * W + tx;
@@ -136,10 +172,17 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> c, const T
                 if (CONST) {
                     const T Ax = c.w0 * (T(4) * v - xe - xw - xn - xs);
                     v = v + b * (fr[r] - Ax) * invD0;
-                } else {
+                } else if (!GEN) {
                     const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
                     const T D = we + ww + wn + ws;
                     const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs;
+                    v = v + b * (fr[r] - Ax) / D;
+                } else {
+                    const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
+                    const T wa = swne[p], wb = swne[p - W - 1];
+                    const T D = sd[p];
+                    const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs - wa * cur[p + W + 1] -
+                                 wb * cur[p - W - 1];
                     v = v + b * (fr[r] - Ax) / D;
                 }
                 if (a != T(0)) v += a * (xc[r] - xp[r]);
@@ -163,35 +206,39 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> c, const T
     }
 }
 
-template <typename T, bool CONST>
-__global__ __launch_bounds__(BX* BY) void k_apply_A(Grid g, Coef<T> c, const T* __restrict__ x,
+template <typename T, int KIND>
+__global__ __launch_bounds__(BX* BY) void k_apply_A(Grid g, Coef<T> cg, const T* __restrict__ x,
                                                     T* __restrict__ y, long stride) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
+    T bs;
+    const Coef<T> c = member_coef(cg, blockIdx.z, bs);
     const long off = (long)blockIdx.z * stride;
     const long id = g.idx(i, j);
     T Ax, D;
-    Stiff2<T, CONST>::apply(g, c, x + off, id, Ax, D);
+    Stiff2<T, KIND>::apply(g, c, x + off, id, Ax, D);
     y[off + id] = Ax;
 }
 
 // r_c = P^T (f - A x): each coarse interior node gathers the residual at the 7
 // fine nodes whose interpolation stencil contains it.
-template <typename T, bool CONST>
-__global__ __launch_bounds__(BX* BY) void k_resid_restrict(Grid gf, Coef<T> c, const T* __restrict__ x,
+template <typename T, int KIND>
+__global__ __launch_bounds__(BX* BY) void k_resid_restrict(Grid gf, Coef<T> cg, const T* __restrict__ x,
                                                            const T* __restrict__ f, Grid gc,
                                                            T* __restrict__ rc, long sf, long sc) {
     const int I = blockIdx.x * BX + threadIdx.x + 1;
     const int J = blockIdx.y * BY + threadIdx.y + 1;
     if (I > gc.m || J > gc.m) return;
+    T bs;
+    const Coef<T> c = member_coef(cg, blockIdx.z, bs);
     const T* xr = x + (long)blockIdx.z * sf;
     const T* fr = f + (long)blockIdx.z * sf;
     const int i = 2 * I, j = 2 * J;
     auto res = [&](int ii, int jj) -> T {
         const long id = gf.idx(ii, jj);
         T Ax, D;
-        Stiff2<T, CONST>::apply(gf, c, xr, id, Ax, D);
+        Stiff2<T, KIND>::apply(gf, c, xr, id, Ax, D);
         return fr[id] - Ax;
     };
     T v = res(i, j);
@@ -250,21 +297,24 @@ __global__ __launch_bounds__(BX* BY) void k_mass_rhs(Grid g, const double* __res
     f[off + id] = l * mass2(g, u + off, id);
 }
 
-template <bool CONST>
-__global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> c, const double* __restrict__ u,
+template <int KIND, typename TO>
+__global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, const double* __restrict__ u,
                                                        const double* __restrict__ f,
-                                                       float* __restrict__ r, long stride) {
+                                                       TO* __restrict__ r, long stride, long rstride) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
+    double bs;
+    const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const long off = (long)blockIdx.z * stride;
     const long id = g.idx(i, j);
     double Ax, D;
-    Stiff2<double, CONST>::apply(g, c, u + off, id, Ax, D);
-    r[off + id] = (float)(f[off + id] - Ax);
+    Stiff2<double, KIND>::apply(g, c, u + off, id, Ax, D);
+    r[(long)blockIdx.z * rstride + id] = (TO)(f[off + id] - Ax);
 }
 
-__global__ void k_add_correction(const float* __restrict__ e, double* __restrict__ u, long n) {
+template <typename TE>
+__global__ void k_add_correction(const TE* __restrict__ e, double* __restrict__ u, long n) {
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
         u[t] += (double)e[t];
 }
@@ -288,19 +338,21 @@ __device__ inline void block_sum2(double& a, double& b, double* sh) {
     }
 }
 
-template <bool CONST>
-__global__ __launch_bounds__(BX* BY) void k_border(Grid g, Coef<double> c, const double* __restrict__ u,
+template <int KIND>
+__global__ __launch_bounds__(BX* BY) void k_border(Grid g, Coef<double> cg, const double* __restrict__ u,
                                                    double* __restrict__ au, double* __restrict__ mu,
                                                    double* __restrict__ partial, long stride) {
     __shared__ double sh[8];
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     const long off = (long)blockIdx.z * stride;
+    double bs;
+    const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     double ua = 0.0, um = 0.0;
     if (i <= g.m && j <= g.m) {
         const long id = g.idx(i, j);
         double Ax, D;
-        Stiff2<double, CONST>::apply(g, c, u + off, id, Ax, D);
+        Stiff2<double, KIND>::apply(g, c, u + off, id, Ax, D);
         const double Mx = mass2(g, u + off, id);
         au[off + id] = Ax;
         mu[off + id] = Mx;
@@ -407,43 +459,74 @@ void launch_smooth(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, co
                    int nrhs, long stride, Cheb s, int zmode, hipStream_t st) {
     if (g.dim == 3) return launch_smooth3<T>(g, c, xc, xp, f, xn, nrhs, stride, s, zmode, st);
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (c.wx)
-        hipLaunchKernelGGL((k_smooth<T, false>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a,
-                           (T)s.b, zmode);
-    else
-        hipLaunchKernelGGL((k_smooth<T, true>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a,
-                           (T)s.b, zmode);
+    switch (coef_kind(c)) {
+        case 0: hipLaunchKernelGGL((k_smooth<T, 0>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a, (T)s.b, zmode); break;
+        case 1: hipLaunchKernelGGL((k_smooth<T, 1>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a, (T)s.b, zmode); break;
+        default: hipLaunchKernelGGL((k_smooth<T, 2>), grid, blk, 0, st, g, c, xc, xp, f, xn, stride, (T)s.a, (T)s.b, zmode); break;
+    }
     PASM_CHECK_LAUNCH();
 }
 
-template <typename T, bool CONST, int S>
+// LDS of a fused launch: the double-buffered iterate plus 0 / 2 / 4
+// coefficient tiles (constant / edge / general).
+constexpr size_t fused_lds(int kind, size_t elem, int rows) {
+    return (2 + (kind == 0 ? 0 : kind == 1 ? 2 : 4)) * (size_t)64 * 4 * rows * elem;
+}
+constexpr size_t kLdsLimit = 65536;
+
+size_t fused_lds_bytes(int kind, size_t elem, int rows) { return fused_lds(kind, elem, rows); }
+
+template <typename T, int KIND, int S, int ROWS>
 void fused_launch(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
                   const SmoothSteps& ss, bool x_zero, hipStream_t st) {
-    constexpr int ROWS = 8, TX = 64 - 2 * S, TY = 4 * ROWS - 2 * S;
-    dim3 grid((g.m + TX - 1) / TX, (g.m + TY - 1) / TY, nrhs);
-    hipLaunchKernelGGL((k_smooth_fused<T, CONST, S, ROWS>), grid, dim3(64, 4), 0, st, g, c, x0, f, out, stride, ss,
-                       (int)x_zero);
-    PASM_CHECK_LAUNCH();
+    if constexpr (fused_lds(KIND, sizeof(T), ROWS) <= kLdsLimit && 4 * ROWS - 2 * S > 0) {
+        constexpr int TX = 64 - 2 * S, TY = 4 * ROWS - 2 * S;
+        dim3 grid((g.m + TX - 1) / TX, (g.m + TY - 1) / TY, nrhs);
+        hipLaunchKernelGGL((k_smooth_fused<T, KIND, S, ROWS>), grid, dim3(64, 4), 0, st, g, c, x0, f, out, stride,
+                           ss, (int)x_zero);
+        PASM_CHECK_LAUNCH();
+    } else {
+        throw Error(PASM_E_INVALID, "fused smoothing tile too large for LDS or too short for the steps");
+    }
+}
+
+template <typename T, int S, int ROWS>
+void fused_kind(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
+                const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+    switch (coef_kind(c)) {
+        case 0: fused_launch<T, 0, S, ROWS>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); break;
+        case 1: fused_launch<T, 1, S, ROWS>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); break;
+        default: fused_launch<T, 2, S, ROWS>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); break;
+    }
 }
 
 template <typename T, int S>
 void fused_dispatch(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
-                    const SmoothSteps& ss, bool x_zero, hipStream_t st) {
-    if (c.wx) fused_launch<T, false, S>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st);
-    else fused_launch<T, true, S>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st);
+                    const SmoothSteps& ss, bool x_zero, hipStream_t st, int rows) {
+    switch (rows) {
+        case 2: fused_kind<T, S, 2>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); break;
+        case 4: fused_kind<T, S, 4>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); break;
+        default: fused_kind<T, S, 8>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); break;
+    }
 }
 
 bool fused_supported(const Grid& g, int steps) { return g.dim == 2 && steps >= 1 && steps <= 4; }
 
 template <typename T>
 bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* out, int nrhs, long stride,
-                         const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+                         const SmoothSteps& ss, bool x_zero, hipStream_t st, int rows) {
     if (!fused_supported(g, ss.s)) return false;
+    if (rows != 2 && rows != 4 && rows != 8) return false;
+    if (4 * rows - 2 * ss.s <= 0) return false;
+    if (fused_lds(coef_kind(c), sizeof(T), rows) > kLdsLimit) return false;
     switch (ss.s) {
-        case 1: fused_dispatch<T, 1>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
-        case 2: fused_dispatch<T, 2>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
-        case 3: fused_dispatch<T, 3>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
-        case 4: fused_dispatch<T, 4>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st); return true;
+        case 1: fused_dispatch<T, 1>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st, rows); return true;
+        case 2: fused_dispatch<T, 2>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st, rows); return true;
+        case 3: fused_dispatch<T, 3>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st, rows); return true;
+        case 4:
+            if (rows == 2) return false;  // a 4-step phase needs more than 8 LDS rows
+            fused_dispatch<T, 4>(g, c, x0, f, out, nrhs, stride, ss, x_zero, st, rows);
+            return true;
         default: return false;
     }
 }
@@ -453,10 +536,11 @@ void launch_apply_A(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs,
                     hipStream_t st) {
     if (g.dim == 3) return launch_apply_A3<T>(g, c, x, y, nrhs, stride, st);
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (c.wx)
-        hipLaunchKernelGGL((k_apply_A<T, false>), grid, blk, 0, st, g, c, x, y, stride);
-    else
-        hipLaunchKernelGGL((k_apply_A<T, true>), grid, blk, 0, st, g, c, x, y, stride);
+    switch (coef_kind(c)) {
+        case 0: hipLaunchKernelGGL((k_apply_A<T, 0>), grid, blk, 0, st, g, c, x, y, stride); break;
+        case 1: hipLaunchKernelGGL((k_apply_A<T, 1>), grid, blk, 0, st, g, c, x, y, stride); break;
+        default: hipLaunchKernelGGL((k_apply_A<T, 2>), grid, blk, 0, st, g, c, x, y, stride); break;
+    }
     PASM_CHECK_LAUNCH();
 }
 
@@ -465,10 +549,11 @@ void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T
                            T* rc, int nrhs, long sf, long sc, hipStream_t st) {
     if (gf.dim == 3) return launch_resid_restrict3<T>(gf, c, x, f, gc, rc, nrhs, sf, sc, st);
     dim3 grid = grid_for(gc.m, gc.m, nrhs), blk(BX, BY);
-    if (c.wx)
-        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc);
-    else
-        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc);
+    switch (coef_kind(c)) {
+        case 0: hipLaunchKernelGGL((k_resid_restrict<T, 0>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc); break;
+        case 1: hipLaunchKernelGGL((k_resid_restrict<T, 1>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc); break;
+        default: hipLaunchKernelGGL((k_resid_restrict<T, 2>), grid, blk, 0, st, gf, c, x, f, gc, rc, sf, sc); break;
+    }
     PASM_CHECK_LAUNCH();
 }
 
@@ -506,16 +591,32 @@ void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long st
 void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
                        int nrhs, long stride, hipStream_t st) {
     if (g.dim == 3) return launch_resid_cast3(g, c, u, f, r, nrhs, stride, st);
-    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (c.wx)
-        hipLaunchKernelGGL(k_resid_cast<false>, grid, blk, 0, st, g, c, u, f, r, stride);
-    else
-        hipLaunchKernelGGL(k_resid_cast<true>, grid, blk, 0, st, g, c, u, f, r, stride);
-    PASM_CHECK_LAUNCH();
+    launch_resid_to<float>(g, c, u, f, r, nrhs, stride, st);
 }
 
+template <typename TO>
+void launch_resid_to(const Grid& g, const Coef<double>& c, const double* u, const double* f, TO* r, int nrhs,
+                     long stride, hipStream_t st) {
+    if (g.dim == 3) throw Error(PASM_E_INVALID, "residual kernel: 2D only");
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    switch (coef_kind(c)) {
+        case 0: hipLaunchKernelGGL((k_resid_cast<0, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride); break;
+        case 1: hipLaunchKernelGGL((k_resid_cast<1, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride); break;
+        default: hipLaunchKernelGGL((k_resid_cast<2, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride); break;
+    }
+    PASM_CHECK_LAUNCH();
+}
+template void launch_resid_to<float>(const Grid&, const Coef<double>&, const double*, const double*, float*, int,
+                                     long, hipStream_t);
+template void launch_resid_to<double>(const Grid&, const Coef<double>&, const double*, const double*, double*, int,
+                                      long, hipStream_t);
+
 void launch_add_correction(const float* e, double* u, long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_add_correction, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
+    hipLaunchKernelGGL(k_add_correction<float>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
+    PASM_CHECK_LAUNCH();
+}
+void launch_add_correction(const double* e, double* u, long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_correction<double>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
     PASM_CHECK_LAUNCH();
 }
 
@@ -523,10 +624,11 @@ int launch_border(const Grid& g, const Coef<double>& c, const double* u, double*
                   double* partial, int nrhs, long stride, hipStream_t st) {
     if (g.dim == 3) return launch_border3(g, c, u, au, mu, partial, nrhs, stride, st);
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (c.wx)
-        hipLaunchKernelGGL(k_border<false>, grid, blk, 0, st, g, c, u, au, mu, partial, stride);
-    else
-        hipLaunchKernelGGL(k_border<true>, grid, blk, 0, st, g, c, u, au, mu, partial, stride);
+    switch (coef_kind(c)) {
+        case 0: hipLaunchKernelGGL(k_border<0>, grid, blk, 0, st, g, c, u, au, mu, partial, stride); break;
+        case 1: hipLaunchKernelGGL(k_border<1>, grid, blk, 0, st, g, c, u, au, mu, partial, stride); break;
+        default: hipLaunchKernelGGL(k_border<2>, grid, blk, 0, st, g, c, u, au, mu, partial, stride); break;
+    }
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y);
 }
@@ -561,7 +663,7 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
                                    long, Cheb, int, hipStream_t);                                      \
     template void launch_apply_A<T>(const Grid&, const Coef<T>&, const T*, T*, int, long, hipStream_t); \
     template bool launch_smooth_fused<T>(const Grid&, const Coef<T>&, const T*, const T*, T*, int, long,      \
-                                         const SmoothSteps&, bool, hipStream_t);                              \
+                                         const SmoothSteps&, bool, hipStream_t, int);                         \
     template void launch_resid_restrict<T>(const Grid&, const Coef<T>&, const T*, const T*, const Grid&, \
                                            T*, int, long, long, hipStream_t);                           \
     template void launch_prolong<T>(const Grid&, const T*, const Grid&, T*, int, long, long, bool,      \

@@ -61,3 +61,35 @@ def test_invalid_coefficients():
     o = pasm.options(vcycles=0)
     with pytest.raises(pasm.PasmError):
         pasm.pasm_setup(2, 1 / 8, 1 / 64, 2, options=o)
+    badv = np.zeros(2 * n * n)
+    badv[3] = -0.5
+    with pytest.raises(pasm.PasmError) as e:
+        pasm.pasm_setup(2, 1 / 4, 1 / n, 2, potential=badv)
+    assert e.value.status == pasm.PASM_E_INVALID
+    assert "non-negative" in pasm.lib().pasm_last_error(None).decode()
+    badv[3] = np.nan
+    with pytest.raises(pasm.PasmError):
+        pasm.pasm_setup(2, 1 / 4, 1 / n, 2, potential=badv)
+    with pytest.raises(pasm.PasmError):
+        pasm.pasm_setup(3, 1 / 4, 1 / 8, 2, potential=np.zeros(6 * 8 ** 3))
+
+
+def test_invalid_batch_arguments():
+    """Rejected before any device call."""
+    ok = (1 / 32, None, None)
+    cases = [
+        dict(H=1 / 8, k=2, inst=[]),                              # no instance
+        dict(H=1 / 8, k=2, inst=[(1 / 8, None, None)]),           # h == H
+        dict(H=1 / 8, k=2, inst=[ok, (1 / 24, None, None)]),      # H/h not a power of two
+        dict(H=1 / 8, k=49, inst=[ok]),                           # k >= N_H
+        dict(H=1 / 8, k=2, inst=[(1 / 32, np.ones(10), None)]),   # wrong element count
+        dict(H=1 / 8, k=2, inst=[(1 / 32, None, -np.ones(2 * 32 * 32))]),  # negative potential
+    ]
+    for c in cases:
+        with pytest.raises(pasm.PasmError) as e:
+            pasm.pasm_batch_setup(c["H"], c["k"], c["inst"])
+        assert e.value.status == pasm.PASM_E_INVALID, c
+    with pytest.raises(pasm.PasmError) as e:
+        pasm.pasm_batch_setup(1 / 4, 2, [(1 / 16, None, None)], dim=3)
+    assert e.value.status == pasm.PASM_E_INVALID
+    assert "dim 2" in pasm.lib().pasm_batch_last_error(None).decode()

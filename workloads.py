@@ -123,6 +123,21 @@ def uneven_batch(count: int = 16, seed: int = 0, fine_choices=(256, 512, 1024)) 
     return out
 
 
+def quadratic_potential_elements(n: int, centre, scale: float = 1.0) -> np.ndarray:
+    """Per-element values of the potential V(x) = scale |x - c|^2 at the
+    element centroids of the 2D "/" mesh with n cells per side, in element
+    order (lower triangle centroid o + (2/3, 1/3) h, upper o + (1/3, 2/3) h)."""
+    h = 1.0 / n
+    c = np.asarray(centre, dtype=np.float64)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")  # [j][i]: x fastest
+    out = np.empty((n, n, 2))
+    for p, (ax, ay) in enumerate(((2.0 / 3.0, 1.0 / 3.0), (1.0 / 3.0, 2.0 / 3.0))):
+        x = (ii + ax) * h
+        y = (jj + ay) * h
+        out[:, :, p] = scale * ((x - c[0]) ** 2 + (y - c[1]) ** 2)
+    return out.reshape(-1)
+
+
 def random_vectors(shape, seed: int = 0, dtype=np.float64) -> np.ndarray:
     """Seeded standard-normal test vectors."""
     return np.random.default_rng(seed).standard_normal(shape).astype(dtype)
