@@ -16,6 +16,9 @@ multigrid  the V-cycle used as "some multigrid steps" for the boundary value
 pasm       Algorithm 1 (one correction step) and Algorithm 2 (the parallel
            augmented subspace scheme), with the definition of the result
            (the discrete eigenpairs of the pencil) beside it.
+learned    the learned convolutional smoother (not in the paper; an
+           alternative smoother for the multigrid steps of Algorithm 1):
+           forward map, training loss and its gradient, Adam update.
 
 Every function states which part of the paper it follows.  Parity status of
 every function is listed in its module header.

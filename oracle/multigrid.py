@@ -20,6 +20,8 @@ throughout this project (and by the GPU library, implemented independently) is:
     fixed number of V-cycles;
   * smoothers, with D = diag(A_l):
         damped Jacobi, nu sweeps:   x <- x + omega D^{-1} (f - A x)
+        learned (3D): nu steps of the convolutional corrector of
+        oracle.learned, x <- x + N(D^{-1} (f - A x))
         Chebyshev of degree s on D^{-1} A over [rho/alpha, rho], rho the
         Gershgorin bound max_i sum_j |a_ij| / a_ii.  Written here in the
         two-vector (direction, residual) form of the Chebyshev semi-iteration.
@@ -52,12 +54,14 @@ class Level:
 
 @dataclasses.dataclass
 class MGOptions:
-    smoother: str = "jacobi"     # "jacobi" | "cheb"
+    smoother: str = "jacobi"     # "jacobi" | "cheb" | "learned"
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8
     cheb_alpha: float = 4.0
     vcycles: int = 2
+    weights: tuple = None        # (W1, W2) of the learned smoother (oracle.learned)
+    learned_bf16: bool = True    # round the learned smoother's operands as the GPU does
 
 
 def default_options(dim: int, smoother: str, nu_pre: int, nu_post: int, vcycles: int) -> MGOptions:
@@ -133,6 +137,11 @@ class Hierarchy:
             return self.jacobi(lv, x, f, opts.omega, nu)
         if opts.smoother == "cheb":
             return self.chebyshev(lv, x, f, opts.cheb_alpha, nu)
+        if opts.smoother == "learned":
+            from . import learned
+            for _ in range(nu):
+                x = learned.step_matrix(lv.A, lv.D, x, f, opts.weights[0], opts.weights[1], opts.learned_bf16)
+            return x
         raise ValueError(opts.smoother)
 
     # -- cycle -----------------------------------------------------------
