@@ -73,7 +73,13 @@ typedef enum pasm_precision {
 
 typedef enum pasm_smoother {
     PASM_JACOBI = 0,       /* damped Jacobi, x <- x + omega D^{-1}(f - A x) */
-    PASM_CHEBYSHEV = 1     /* Chebyshev semi-iteration on D^{-1}A over [rho/alpha, rho] */
+    PASM_CHEBYSHEV = 1,    /* Chebyshev semi-iteration on D^{-1}A over [rho/alpha, rho] */
+    PASM_LEARNED = 2       /* 3D, constant coefficients: one step of a learned convolutional
+                              corrector per smoothing phase, x <- x + N(D^{-1}(f - A x)),
+                              trained at set-up on residuals of plain V-cycles; damped
+                              Jacobi (nu_pre / nu_post sweeps) is the fallback, taken for
+                              any V-cycle whose residual reduction is worse than the plain
+                              cycle's (see pasm_learned_report) */
 } pasm_smoother;
 
 /* Unit box (0,1)^dim; dim = 2 or 3. */
@@ -213,6 +219,51 @@ PASM_API pasm_status pasm_profile(pasm_ctx* ctx, int kernel, int enable);
  * launch must move at minimum (the algorithmic traffic of that kernel). */
 PASM_API pasm_status pasm_profile_read(pasm_ctx* ctx, int kernel, long* launches, double* total_ms,
                                        double* bytes_per_launch);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoother (opt.smoother = PASM_LEARNED; not part of the paper's
+ * method: an alternative for its "some multigrid steps").
+ *
+ * N(rho)(v) = sum_{c,t} W2[c][t] h_c(v + t), h_c = max(0, sum_t W1[c][t] rho(v + t)),
+ * 16 channels c, 27 offsets t in {-1,0,1}^3 (index (dz+1)*9 + (dy+1)*3 + (dx+1)),
+ * h zero off the interior nodes.  Both convolutions run as bfloat16 matrix
+ * products with FP32 accumulation.  Weights are FP32 [2][16][27] (W1 then
+ * W2).  Training (at set-up, and by pasm_learned_train) minimises
+ * (1/S) sum_s ||r_s - A N(r_s / D)||^2 / ||r_s||^2 with Adam, over residuals
+ * r_s that plain V-cycles leave on random errors, on the level with 32 cells
+ * per side (or the finest level below the finest).  The weights start as the
+ * damped Jacobi step (two channels passing +rho and -rho).
+ * ------------------------------------------------------------------------- */
+typedef struct pasm_learned_stats {
+    int enabled;            /* 1 while the learned smoother is in use */
+    int train_steps;        /* Adam steps taken so far */
+    double loss_first;      /* training loss at the first and the latest step */
+    double loss_last;
+    double plain_rate;      /* residual reduction of one plain V-cycle (set-up, worst right-hand side) */
+    double learned_rate;    /* ... of one learned V-cycle */
+    long cycles_learned;    /* V-cycles kept with the learned smoother */
+    long cycles_fallback;   /* V-cycles redone with the plain smoother */
+} pasm_learned_stats;
+
+PASM_API pasm_status pasm_learned_report(const pasm_ctx* ctx, pasm_learned_stats* out);
+PASM_API pasm_status pasm_learned_weights(const pasm_ctx* ctx, float* w);
+/* Replace the weights (host [2][16][27]); the stored rates are kept. */
+PASM_API pasm_status pasm_learned_set_weights(pasm_ctx* ctx, const float* w);
+/* Fallback threshold: a learned V-cycle is redone with the plain smoother
+ * when it reduces some right-hand side's residual by less than this factor.
+ * rate <= 0 restores the default, the plain cycle's rate measured at set-up. */
+PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* ctx, double rate);
+/* steps more Adam steps from the current weights; loss_history (may be NULL)
+ * receives the loss of each step. */
+PASM_API pasm_status pasm_learned_train(pasm_ctx* ctx, int steps, double* loss_history);
+/* One learned step on level l >= 1, out = x + N((f - A_l x) / D), for nrhs
+ * vectors (device, compact FP64, ld apart), in the context's V-cycle precision. */
+PASM_API pasm_status pasm_learned_step(pasm_ctx* ctx, int level, const double* x, const double* f, double* out,
+                                       size_t ld, int nrhs);
+/* Training loss and gradient (host grad [2][16][27]) of ns residual samples
+ * r (device, compact FP64, ld apart) on level l >= 1, with the current weights. */
+PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* ctx, int level, const double* r, size_t ld, int ns,
+                                            double* loss, double* grad);
 
 /* ---------------------------------------------------------------------------
  * Batches of problems of uneven size.

@@ -19,7 +19,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pasm.h")
 
 PASM_OK, PASM_E_INVALID, PASM_E_NOMEM, PASM_E_DEVICE, PASM_E_STATE, PASM_E_NOTCONV, PASM_E_BREAKDOWN = range(7)
 PASM_FP64, PASM_MIXED = 0, 1
-PASM_JACOBI, PASM_CHEBYSHEV = 0, 1
+PASM_JACOBI, PASM_CHEBYSHEV, PASM_LEARNED = 0, 1, 2
 PASM_OP_STIFFNESS, PASM_OP_MASS = 0, 1
 
 
@@ -41,6 +41,13 @@ class pasm_coefficients(ctypes.Structure):
 
 class pasm_instance(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("coef", pasm_coefficients)]
+
+
+class pasm_learned_stats(ctypes.Structure):
+    _fields_ = [("enabled", ctypes.c_int), ("train_steps", ctypes.c_int),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("plain_rate", ctypes.c_double), ("learned_rate", ctypes.c_double),
+                ("cycles_learned", ctypes.c_long), ("cycles_fallback", ctypes.c_long)]
 
 
 class pasm_options(ctypes.Structure):
@@ -93,6 +100,14 @@ def lib() -> ctypes.CDLL:
     L.pasm_vcycle.argtypes = [_P, _P, _P, ctypes.c_size_t, ctypes.c_int, ctypes.c_int]
     L.pasm_profile.argtypes = [_P, ctypes.c_int, ctypes.c_int]
     L.pasm_profile_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _D, _D]
+    _F = ctypes.POINTER(ctypes.c_float)
+    L.pasm_learned_report.argtypes = [_P, ctypes.POINTER(pasm_learned_stats)]
+    L.pasm_learned_weights.argtypes = [_P, _F]
+    L.pasm_learned_set_weights.argtypes = [_P, _F]
+    L.pasm_learned_train.argtypes = [_P, ctypes.c_int, _D]
+    L.pasm_learned_set_threshold.argtypes = [_P, ctypes.c_double]
+    L.pasm_learned_step.argtypes = [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, ctypes.c_int]
+    L.pasm_learned_loss_grad.argtypes = [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int, _D, _D]
     L.pasm_batch_setup.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(pasm_domain), ctypes.POINTER(pasm_instance),
                                    ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(pasm_options)]
     L.pasm_batch_iterate.argtypes = [_P, _I]
@@ -296,8 +311,9 @@ def options(precision: int = PASM_FP64, smoother: int = PASM_JACOBI, nu_pre: int
 
 def options_for(workload) -> pasm_options:
     """Options matching a `workloads.Workload` description."""
+    sm = {"cheb": PASM_CHEBYSHEV, "jacobi": PASM_JACOBI, "learned": PASM_LEARNED}[workload.smoother]
     return options(precision=PASM_MIXED if workload.precision == "mixed" else PASM_FP64,
-                   smoother=PASM_CHEBYSHEV if workload.smoother == "cheb" else PASM_JACOBI,
+                   smoother=sm,
                    nu_pre=workload.nu_pre, nu_post=workload.nu_post, vcycles=workload.vcycles,
                    tol=workload.tol)
 
@@ -334,6 +350,51 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# learned smoother
+# ---------------------------------------------------------------------------
+def pasm_learned_report(ctx) -> dict:
+    st = pasm_learned_stats()
+    _check(lib().pasm_learned_report(ctx, ctypes.byref(st)), ctx)
+    return {f: getattr(st, f) for f, _ in pasm_learned_stats._fields_}
+
+
+def pasm_learned_weights(ctx) -> np.ndarray:
+    w = np.empty((2, 16, 27), dtype=np.float32)
+    _check(lib().pasm_learned_weights(ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), ctx)
+    return w
+
+
+def pasm_learned_set_weights(ctx, w) -> None:
+    w = np.ascontiguousarray(w, dtype=np.float32).reshape(2, 16, 27)
+    _check(lib().pasm_learned_set_weights(ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), ctx)
+
+
+def pasm_learned_set_threshold(ctx, rate: float) -> None:
+    _check(lib().pasm_learned_set_threshold(ctx, float(rate)), ctx)
+
+
+def pasm_learned_train(ctx, steps: int) -> np.ndarray:
+    h = np.zeros(max(steps, 1))
+    _check(lib().pasm_learned_train(ctx, steps, _dptr(h)), ctx)
+    return h[:steps]
+
+
+def pasm_learned_step(ctx, level: int, x, f, out) -> None:
+    """out = x + N((f - A x)/D) for torch float64 CUDA tensors (nrhs, N_level)."""
+    _check(lib().pasm_learned_step(ctx, level, _torch_ptr(x), _torch_ptr(f), _torch_ptr(out), x.shape[1],
+                                   x.shape[0]), ctx)
+
+
+def pasm_learned_loss_grad(ctx, level: int, r):
+    """Training loss and gradient [2][16][27] of samples r (torch float64 CUDA, (ns, N_level))."""
+    loss = ctypes.c_double(0)
+    g = np.zeros((2, 16, 27))
+    _check(lib().pasm_learned_loss_grad(ctx, level, _torch_ptr(r), r.shape[1], r.shape[0], ctypes.byref(loss),
+                                        _dptr(g)), ctx)
+    return loss.value, g
 
 
 # ---------------------------------------------------------------------------

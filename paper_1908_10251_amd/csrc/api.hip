@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <random>
 
 #include "common.h"
 
@@ -98,6 +99,24 @@ struct pasm_ctx {
     std::string err;
     rocblas_handle blas = nullptr;
     long iters = 0;
+    // learned smoother (3D): weights [2][16][27], Adam state, operand words
+    // of the inference kernel, fallback bookkeeping
+    bool learned = false;       // smoother is PASM_LEARNED
+    bool learned_on = false;    // currently smoothing with the learned step
+    std::vector<float> lw;
+    std::vector<double> lm, lv2;
+    int ltrain_steps = 0;
+    double lloss_first = 0.0, lloss_last = 0.0, lplain_rate = 0.0, llearned_rate = 0.0;
+    long lcycles_learned = 0, lcycles_fallback = 0;
+    double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
+    std::vector<double> lratio; // residual reduction of the last V-cycles (diagnostics)
+    unsigned long long* lops = nullptr;
+    float* lpool = nullptr;     // training residuals [lpool_n][m^3]
+    int lpool_n = 0, ltrain_level = -1;
+    pasm::LearnedTrainer ltrainer;
+    double* Xb = nullptr;       // finest-level backup of x for a rejected V-cycle
+    double* rnpart = nullptr;   // residual-norm partials and per-rhs sums
+    double* rnsum = nullptr;
     // profiling of the fine-level smoothing sweeps
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -202,6 +221,17 @@ void collect_profile(pasm_ctx* c) {
 template <typename T>
 void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb>& steps, bool x_zero,
             int nrhs) {
+    if (c->learned_on && l >= 1) {
+        // one learned step per phase (3D constant-coefficient levels)
+        const pasm::Level& L = c->lv[l];
+        const bool fine = (l == c->L - 1);
+        const double nodes = (double)L.g.interior() * nrhs;
+        if (fine) record_start(c);
+        pasm::launch_learned_step<T>(L.g, (T)L.w0, x, f, y, nrhs, L.g.plane, c->lops, x_zero, c->st);
+        if (fine) record_end(c, (x_zero ? 2.0 : 3.0) * sizeof(T) * nodes);
+        std::swap(x, y);
+        return;
+    }
     if (steps.empty()) return;
     const pasm::Level& L = c->lv[l];
     const Coef<T> cf = c->coef<T>(l);
@@ -316,19 +346,71 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
 
 // ncycles V-cycles for A x = f at the finest level; x, f are FP64 finest-level
 // buffers (padded), scr an FP64 scratch buffer of the same size.
-void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles) {
+// One V-cycle for A x = f at the finest level: in place (FP64), or as
+// defect correction with an FP32 cycle (mixed).
+void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs) {
     const int lf = c->L - 1;
     if (!c->mixed) {
-        for (int cy = 0; cy < ncycles; ++cy) vcycle<double>(c, lf, x, scr, f, false, nrhs);
+        vcycle<double>(c, lf, x, scr, f, false, nrhs);
         return;
     }
     const Grid& g = c->gf();
+    pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st);
+    float* e = c->E32;
+    float* ye = c->Y32;
+    vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
+    pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
+}
+
+// ||f - A x||^2 per right-hand side (finest level, FP64, 3D), to the host
+std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, int nrhs) {
+    const Grid& g = c->gf();
+    const int nb = pasm::launch_resid_norm3<double>(g, c->lv.back().w0, x, f, c->rnpart, nrhs, g.plane, c->st);
+    pasm::launch_reduce_pairs(c->rnpart, nb, c->rnsum, nrhs, c->st);
+    std::vector<double> out(2 * (size_t)nrhs);
+    PASM_HIP(hipMemcpyAsync(out.data(), c->rnsum, out.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    PASM_HIP(hipStreamSynchronize(c->st));
+    std::vector<double> n(nrhs);
+    for (int r = 0; r < nrhs; ++r) n[r] = out[2 * r];
+    return n;
+}
+
+// ncycles V-cycles for A x = f at the finest level; x, f are FP64 finest-level
+// buffers (padded), scr an FP64 scratch buffer of the same size.  With the
+// learned smoother every cycle is checked: if it reduced the residual of some
+// right-hand side by less than the plain cycle does (the rate measured at
+// set-up), x is restored and the cycle is redone with the plain smoother.
+void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles) {
+    if (!c->learned_on) {
+        for (int cy = 0; cy < ncycles; ++cy) one_cycle(c, x, scr, f, nrhs);
+        return;
+    }
+    const Grid& g = c->gf();
+    const size_t bytes = (size_t)g.plane * nrhs * sizeof(double);
+    std::vector<double> n0 = resid_norms(c, x, f, nrhs);
+    const double thr = c->lthreshold > 0.0 ? c->lthreshold : c->lplain_rate;
+    const double lim = thr * thr;
     for (int cy = 0; cy < ncycles; ++cy) {
-        pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st);
-        float* e = c->E32;
-        float* ye = c->Y32;
-        vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
-        pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
+        PASM_HIP(hipMemcpyAsync(c->Xb, x, bytes, hipMemcpyDeviceToDevice, c->st));
+        one_cycle(c, x, scr, f, nrhs);
+        std::vector<double> n1 = resid_norms(c, x, f, nrhs);
+        bool worse = false;
+        for (int r = 0; r < nrhs; ++r) {
+            worse |= !(n1[r] <= lim * n0[r]) && n0[r] > 0.0;
+            if (n0[r] > 0.0) c->lratio.push_back(std::sqrt(n1[r] / n0[r]));
+        }
+        if (c->lratio.size() > 4096) c->lratio.erase(c->lratio.begin(), c->lratio.end() - 4096);
+        if (worse) {
+            PASM_HIP(hipMemcpyAsync(x, c->Xb, bytes, hipMemcpyDeviceToDevice, c->st));
+            c->learned_on = false;
+            one_cycle(c, x, scr, f, nrhs);
+            c->learned_on = true;
+            n1 = resid_norms(c, x, f, nrhs);
+            ++c->lcycles_fallback;
+        } else {
+            ++c->lcycles_learned;
+        }
+        n0 = n1;
     }
 }
 
@@ -382,7 +464,10 @@ Plan validate(const pasm_options& opt, const pasm_domain* dom, const pasm_coeffi
     if (opt.vcycles < 1 || opt.nu_pre < 0 || opt.nu_post < 0 || opt.max_iter < 1 || !(opt.tol >= 0.0))
         throw Error(PASM_E_INVALID, "bad cycle options");
     if (opt.precision != PASM_FP64 && opt.precision != PASM_MIXED) throw Error(PASM_E_INVALID, "bad precision");
-    if (opt.smoother != PASM_JACOBI && opt.smoother != PASM_CHEBYSHEV) throw Error(PASM_E_INVALID, "bad smoother");
+    if (opt.smoother != PASM_JACOBI && opt.smoother != PASM_CHEBYSHEV && opt.smoother != PASM_LEARNED)
+        throw Error(PASM_E_INVALID, "bad smoother");
+    if (opt.smoother == PASM_LEARNED && (p.dim != 3 || (coef && (coef->kappa || coef->potential))))
+        throw Error(PASM_E_INVALID, "the learned smoother is for 3D problems with constant coefficients");
     p.have_kappa = coef && coef->kappa;
     p.have_pot = coef && coef->potential;
     p.nel = 1;
@@ -463,7 +548,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
         if (c->opt.smoother == PASM_CHEBYSHEV) {
             Lv.pre = pasm::cheb_steps(Lv.rho, alpha, c->opt.nu_pre);
             Lv.post = pasm::cheb_steps(Lv.rho, alpha, c->opt.nu_post);
-        } else if (c->opt.smoother == PASM_JACOBI) {
+        } else if (c->opt.smoother == PASM_JACOBI || c->opt.smoother == PASM_LEARNED) {
             Lv.pre = pasm::jacobi_steps(omega, c->opt.nu_pre);
             Lv.post = pasm::jacobi_steps(omega, c->opt.nu_post);
         } else {
@@ -692,6 +777,147 @@ void iterate_once(pasm_ctx* c) {
     PASM_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------------------
+// learned smoother: training data, training, rates
+// ---------------------------------------------------------------------------
+constexpr int kLearnedBatch = 8;       // residual samples per Adam step
+constexpr int kLearnedPool = 64;       // residual samples drawn from plain V-cycles
+constexpr int kLearnedSetupSteps = 160;
+constexpr double kLearnedLr = 2e-3;
+
+void learned_pack(pasm_ctx* c) {
+    unsigned long long ops[256];
+    pasm::learned_pack_taps_by_channel(c->lw.data(), ops);
+    pasm::learned_pack_channels_by_tap(c->lw.data() + 16 * 27, ops + 128);
+    PASM_HIP(hipMemcpyAsync(c->lops, ops, sizeof(ops), hipMemcpyHostToDevice, c->st));
+    PASM_HIP(hipStreamSynchronize(c->st));
+}
+
+// Residuals that plain V-cycles leave: random errors x (f = 0) on the
+// training level, r = -A x after 0, 1 and 2 plain cycles.
+template <typename T>
+void learned_pool(pasm_ctx* c) {
+    const int lt = c->ltrain_level, k = c->k;
+    pasm::Level& Lv = c->lv[lt];
+    const Grid& g = Lv.g;
+    const long vol = g.interior();
+    const bool was = c->learned_on;
+    c->learned_on = false;
+    int have = 0;
+    for (unsigned seed = 1; have < kLearnedPool; ++seed) {
+        T* x = static_cast<T*>(Lv.X);
+        T* y = static_cast<T*>(Lv.Y);
+        T* f = static_cast<T*>(Lv.F);
+        pasm::launch_fill_zero(f, (size_t)g.plane * k * sizeof(T), c->st);
+        pasm::launch_fill_zero(x, (size_t)g.plane * k * sizeof(T), c->st);
+        pasm::launch_fill_normal3<T>(g, x, k, g.plane, 0x5eed0000ull + seed, c->st);
+        for (int round = 0; round < 3 && have < kLearnedPool; ++round) {
+            const int take = std::min(k, kLearnedPool - have);
+            pasm::launch_pack_negA3<T>(g, (T)Lv.w0, x, take, g.plane, c->lpool + (long)have * vol, c->st);
+            have += take;
+            vcycle<T>(c, lt, x, y, f, false, k);
+        }
+    }
+    c->lpool_n = have;
+    c->learned_on = was;
+    PASM_HIP(hipStreamSynchronize(c->st));
+}
+
+void learned_train(pasm_ctx* c, int steps, double* hist) {
+    const long vol = c->lv[c->ltrain_level].g.interior();
+    std::vector<double> grad(864);
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    for (int it = 0; it < steps; ++it) {
+        const int first = (c->ltrain_steps * kLearnedBatch) % (c->lpool_n - kLearnedBatch + 1);
+        const double L = c->ltrainer.loss_grad(c->lpool + (long)first * vol, c->lw.data(), grad.data(), c->st);
+        if (!std::isfinite(L)) throw Error(PASM_E_BREAKDOWN, "learned smoother: non-finite training loss");
+        const int t = ++c->ltrain_steps;
+        if (t == 1) c->lloss_first = L;
+        c->lloss_last = L;
+        if (hist) hist[it] = L;
+        for (int j = 0; j < 864; ++j) {
+            c->lm[j] = b1 * c->lm[j] + (1 - b1) * grad[j];
+            c->lv2[j] = b2 * c->lv2[j] + (1 - b2) * grad[j] * grad[j];
+            const double mh = c->lm[j] / (1 - std::pow(b1, t)), vh = c->lv2[j] / (1 - std::pow(b2, t));
+            c->lw[j] = (float)(c->lw[j] - kLearnedLr * mh / (std::sqrt(vh) + eps));
+        }
+    }
+    learned_pack(c);
+}
+
+// Residual reduction per V-cycle of plain and learned cycles on the start
+// boundary value problems (f = lambda M u from x = u): the worst ratio over
+// the right-hand sides and three consecutive cycles (the later cycles see the
+// smoother residuals that dominate the rate).
+void learned_rates(pasm_ctx* c) {
+    const Grid& g = c->gf();
+    const int k = c->k;
+    const size_t bytes = (size_t)g.plane * k * sizeof(double);
+    pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, g.plane, c->st);
+    double rate[2] = {0.0, 0.0};
+    for (int mode = 0; mode < 2; ++mode) {
+        double* x = c->R64;
+        double* scr = c->Y64;
+        PASM_HIP(hipMemcpyAsync(x, c->U, bytes, hipMemcpyDeviceToDevice, c->st));
+        c->learned_on = mode == 1;
+        std::vector<double> n0 = resid_norms(c, x, c->F64, k);
+        for (int cy = 0; cy < 3; ++cy) {
+            one_cycle(c, x, scr, c->F64, k);
+            const std::vector<double> n1 = resid_norms(c, x, c->F64, k);
+            for (int r = 0; r < k; ++r)
+                if (n0[r] > 0.0) rate[mode] = std::max(rate[mode], std::sqrt(n1[r] / n0[r]));
+            n0 = n1;
+        }
+    }
+    c->lplain_rate = rate[0];
+    c->llearned_rate = rate[1];
+    // use the learned smoother only if it beats the plain one on this start
+    c->learned_on = rate[1] < rate[0];
+}
+
+void learned_setup(pasm_ctx* c) {
+    c->lw.assign(864, 0.f);
+    c->lm.assign(864, 0.0);
+    c->lv2.assign(864, 0.0);
+    // start from damped Jacobi: channel 0 passes +rho, channel 1 passes -rho,
+    // x + omega (h_0 - h_1) = x + omega rho; the other channels start small
+    const double omega = c->opt.omega > 0 ? c->opt.omega : 6.0 / 7.0;
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<double> nd(0.0, 0.02);
+    for (int j = 0; j < 864; ++j) c->lw[j] = (float)nd(rng);
+    for (int t = 0; t < 27; ++t) {
+        c->lw[0 * 27 + t] = c->lw[1 * 27 + t] = 0.f;
+        c->lw[16 * 27 + 0 * 27 + t] = c->lw[16 * 27 + 1 * 27 + t] = 0.f;
+    }
+    c->lw[0 * 27 + 13] = 1.f;
+    c->lw[1 * 27 + 13] = -1.f;
+    c->lw[16 * 27 + 0 * 27 + 13] = (float)omega;
+    c->lw[16 * 27 + 1 * 27 + 13] = (float)-omega;
+    c->lops = c->alloc<unsigned long long>(256);
+    const Grid& g = c->gf();
+    c->Xb = c->alloc<double>((size_t)g.plane * c->k);
+    const long nb = (g.interior() + 255) / 256;
+    c->rnpart = c->alloc<double>(2 * (size_t)nb * c->k);
+    c->rnsum = c->alloc<double>(2 * (size_t)c->k);
+    learned_pack(c);
+    // training level: 32 cells per side where available, below the finest
+    int lt = -1;
+    for (int l = 1; l < c->L - 1; ++l)
+        if (c->lv[l].g.n <= 32) lt = l;
+    c->ltrain_level = lt;
+    if (lt < 1) {  // no level to train on: plain smoothing throughout
+        c->learned_on = false;
+        return;
+    }
+    const Grid& gt = c->lv[lt].g;
+    c->lpool = c->alloc<float>((size_t)kLearnedPool * gt.interior());
+    c->ltrainer.init(gt.m, kLearnedBatch, (float)c->lv[lt].w0, [c](size_t b) { return (void*)c->alloc<char>(b); });
+    if (c->mixed) learned_pool<float>(c);
+    else learned_pool<double>(c);
+    learned_train(c, kLearnedSetupSteps, nullptr);
+    learned_rates(c);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -755,6 +981,10 @@ PASM_API pasm_status pasm_setup(pasm_ctx** out, const pasm_domain* dom, const pa
         build(c, pl, coef, k);
         prolong_coefs(c, nullptr);
         PASM_HIP(hipStreamSynchronize(c->st));
+        if (c->opt.smoother == PASM_LEARNED) {
+            c->learned = true;
+            learned_setup(c);
+        }
     } catch (const Error& e) {
         g_setup_error = e.msg;
         pasm_destroy(c);
@@ -966,6 +1196,129 @@ PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t
             pasm::launch_dense_mv<double>(c->Ainv64, c->NH, g, c->F64, g.plane, true, xb, g.plane, true, nrhs, c->dmv, c->st);
         pasm::launch_pack<double>(g, xb, g.plane, x, (long)ld, nrhs, c->st);
         PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_report(const pasm_ctx* c, pasm_learned_stats* o) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    if (!o) return PASM_E_INVALID;
+    if (!c->learned) return PASM_E_STATE;
+    o->enabled = c->learned_on ? 1 : 0;
+    o->train_steps = c->ltrain_steps;
+    o->loss_first = c->lloss_first;
+    o->loss_last = c->lloss_last;
+    o->plain_rate = c->lplain_rate;
+    o->learned_rate = c->llearned_rate;
+    o->cycles_learned = c->lcycles_learned;
+    o->cycles_fallback = c->lcycles_fallback;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_weights(const pasm_ctx* c, float* w) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (!w) return PASM_E_INVALID;
+    std::memcpy(w, c->lw.data(), 864 * sizeof(float));
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_set_weights(pasm_ctx* c, const float* w) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (!w) return PASM_E_INVALID;
+    for (int j = 0; j < 864; ++j)
+        if (!std::isfinite(w[j])) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        c->lw.assign(w, w + 864);
+        learned_pack(c);
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* c, double rate) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (!std::isfinite(rate)) return PASM_E_INVALID;
+    c->lthreshold = rate > 0.0 ? rate : 0.0;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_train(pasm_ctx* c, int steps, double* hist) {
+    if (!c || c->k == 0 || !c->learned || c->ltrain_level < 1) return PASM_E_STATE;
+    if (steps < 0) return PASM_E_INVALID;
+    PASM_TRY(c, learned_train(c, steps, hist));
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_step(pasm_ctx* c, int level, const double* x, const double* f, double* out,
+                                       size_t ld, int nrhs) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (level < 1 || level >= c->L || nrhs < 1 || nrhs > c->k || !x || !f || !out) return PASM_E_INVALID;
+    const pasm::Level& L = c->lv[level];
+    const Grid& g = L.g;
+    if (ld < (size_t)g.interior()) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        const bool fine = level == c->L - 1;
+        if (c->mixed) {
+            float* xb = fine ? c->E32 : static_cast<float*>(L.X);
+            float* fb = fine ? c->R32 : static_cast<float*>(L.F);
+            float* ob = fine ? c->Y32 : static_cast<float*>(L.Y);
+            pasm::launch_unpack<float>(g, x, (long)ld, xb, g.plane, nrhs, c->st);
+            pasm::launch_unpack<float>(g, f, (long)ld, fb, g.plane, nrhs, c->st);
+            pasm::launch_learned_step<float>(g, (float)L.w0, xb, fb, ob, nrhs, g.plane, c->lops, false, c->st);
+            pasm::launch_pack<float>(g, ob, g.plane, out, (long)ld, nrhs, c->st);
+        } else {
+            double* xb = fine ? c->R64 : static_cast<double*>(L.X);
+            double* fb = fine ? c->F64 : static_cast<double*>(L.F);
+            double* ob = fine ? c->Y64 : static_cast<double*>(L.Y);
+            pasm::launch_unpack<double>(g, x, (long)ld, xb, g.plane, nrhs, c->st);
+            pasm::launch_unpack<double>(g, f, (long)ld, fb, g.plane, nrhs, c->st);
+            pasm::launch_learned_step<double>(g, L.w0, xb, fb, ob, nrhs, g.plane, c->lops, false, c->st);
+            pasm::launch_pack<double>(g, ob, g.plane, out, (long)ld, nrhs, c->st);
+        }
+        PASM_HIP(hipStreamSynchronize(c->st));
+    });
+    return PASM_OK;
+}
+
+namespace {
+__global__ void k_compact_d2f(const double* __restrict__ a, long lda, float* __restrict__ b, long n) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) b[(long)blockIdx.y * n + t] = (float)a[(long)blockIdx.y * lda + t];
+}
+}  // namespace
+
+PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* c, int level, const double* r, size_t ld, int ns,
+                                            double* loss, double* grad) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (level < 1 || level >= c->L || ns < 1 || ns > 64 || !r || !grad) return PASM_E_INVALID;
+    const Grid& g = c->lv[level].g;
+    const long vol = g.interior();
+    if (ld < (size_t)vol) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        // a trainer sized for this level and sample count (not the hot path)
+        std::vector<void*> mine;
+        auto alloc = [&](size_t b) {
+            void* p = nullptr;
+            if (hipMalloc(&p, b ? b : 1) != hipSuccess) throw Error(PASM_E_NOMEM, "hipMalloc failed");
+            mine.push_back(p);
+            PASM_HIP(hipMemsetAsync(p, 0, b ? b : 1, c->st));
+            return p;
+        };
+        try {
+            pasm::LearnedTrainer tr;
+            tr.init(g.m, ns, (float)c->lv[level].w0, alloc);
+            float* rf = static_cast<float*>(alloc(sizeof(float) * vol * ns));
+            hipLaunchKernelGGL(k_compact_d2f, dim3((unsigned)((vol + 255) / 256), ns), dim3(256), 0, c->st, r, (long)ld,
+                               rf, vol);
+            PASM_CHECK_LAUNCH();
+            const double L = tr.loss_grad(rf, c->lw.data(), grad, c->st);
+            if (loss) *loss = L;
+        } catch (...) {
+            (void)hipStreamSynchronize(c->st);
+            for (void* p : mine) (void)hipFree(p);
+            throw;
+        }
+        PASM_HIP(hipStreamSynchronize(c->st));
+        for (void* p : mine) (void)hipFree(p);
     });
     return PASM_OK;
 }

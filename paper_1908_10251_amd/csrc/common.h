@@ -15,6 +15,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -266,5 +267,41 @@ struct ArrowOut {
 };
 void launch_arrowhead(const ArrowIn& in, const ArrowOut& out, int k, hipStream_t st);
 size_t arrow_workspace_bytes(int N, int k);
+
+// ----------------------------------------------------------------------------
+// Learned smoother (learned3d.hip): 3D constant-coefficient levels
+// ----------------------------------------------------------------------------
+// Operand words of the two weight arrays W[16][27] (see learned3d.hip).
+void learned_pack_taps_by_channel(const float* W, unsigned long long* out);   // 128 words
+void learned_pack_channels_by_tap(const float* W, unsigned long long* out);   // 128 words
+// out = x + N((f - A x) / D) (x treated as zero when x_zero); ops = 256 words
+// (layer-1 operand, then layer-2 operand).  out must not alias x or f.
+template <typename T>
+void launch_learned_step(const Grid& g, T w0, const T* x, const T* f, T* out, int nrhs, long stride,
+                         const unsigned long long* ops, bool x_zero, hipStream_t st);
+// partial[rhs][blk][2] = (sum of (f - A x)^2 over the block, 0); returns blocks per rhs
+template <typename T>
+int launch_resid_norm3(const Grid& g, T w0, const T* x, const T* f, double* partial, int nrhs, long stride,
+                       hipStream_t st);
+template <typename T>
+void launch_fill_normal3(const Grid& g, T* x, int nrhs, long stride, unsigned long long seed, hipStream_t st);
+template <typename T>
+void launch_pack_negA3(const Grid& g, T w0, const T* x, int nrhs, long stride, float* pool, hipStream_t st);
+
+// Training buffers and the loss/gradient evaluation on an m^3 interior grid.
+struct LearnedTrainer {
+    int m = 0, S = 0;
+    float w0 = 1.f;
+    unsigned short *rho_p = nullptr, *h_p = nullptr, *g_p = nullptr, *gh = nullptr;
+    float *z1 = nullptr, *y_p = nullptr, *d_p = nullptr, *res_p = nullptr;
+    float *nr_part = nullptr, *res_part = nullptr, *coef = nullptr, *dw_part = nullptr;
+    double* sums = nullptr;
+    unsigned long long* ops = nullptr;
+    int nblk_vox = 0, dw_blocks = 0, dw_kpw = 16;
+    void init(int m, int S, float w0, std::function<void*(size_t)> alloc);
+    // loss of the samples r[0..S) (FP32 compact m^3 each) and its gradient
+    // (grad [2][16][27]) for the weights W [2][16][27]
+    double loss_grad(const float* r, const float* W, double* grad, hipStream_t st);
+};
 
 }  // namespace pasm

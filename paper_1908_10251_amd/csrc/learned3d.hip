@@ -1,0 +1,728 @@
+// Learned convolutional smoother for the 3D constant-coefficient levels:
+// inference inside the V-cycle and training on residuals of plain V-cycles.
+//
+// The smoothing step is x <- x + N(rho), rho = (f - A x) / D, with
+//   z1[c](v) = sum_t W1[c][t] rho(v + t),  h = max(z1, 0) (zero off the
+//   interior), N(rho)(v) = sum_{c,t} W2[c][t] h[c](v + t),
+// t over the 27 offsets {-1,0,1}^3 (index (dz+1)*9 + (dy+1)*3 + (dx+1)) and
+// c over 16 channels.  Both contractions run on the matrix cores as bfloat16
+// products with FP32 accumulation (v_mfma_f32_16x16x16_bf16); rho, h and the
+// weights are rounded to bfloat16 (nearest even) where they enter them.
+//
+// Matrix-core operand layout (16x16x16, one wavefront): lane l holds
+//   A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16], D[4 (l / 16) + j][l % 16]
+// for j = 0..3.
+//
+// Inference (k_learned_step): a workgroup owns a 16 x 16 column of output
+// nodes and marches in z.  Per z slice it loads x with a halo of 3 and f with
+// a halo of 2, forms rho on 20 x 20 nodes, the hidden layer on 18 x 18 nodes
+// (layer 1: M = nodes, K = taps, N = channels), then Y[u][t] = sum_c h[u][c]
+// W2[c][t] (layer 2: M = nodes, K = channels, N = taps), and gathers
+// N(rho)(v) = sum_t Y[v + t][t] into three running output slices.
+//
+// Training: loss L = (1/S) sum_s ||r_s - A N(rho_s)||^2 / ||r_s||^2 over
+// residual samples; the backward contractions (hidden gradient: M = nodes,
+// K = taps, N = channels; weight gradients: M = channels, K = nodes, N = taps)
+// run on the matrix cores as well.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace pasm {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline unsigned short f2bf(float f) {
+    unsigned u;
+    __builtin_memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__device__ inline f32x4 mfma(const bf16x4& a, const bf16x4& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__host__ __device__ inline void tap_off(int t, int& dx, int& dy, int& dz) {
+    dx = t % 3 - 1;
+    dy = (t / 3) % 3 - 1;
+    dz = t / 9 - 1;
+}
+
+// ---------------------------------------------------------------------------
+// fused inference step
+// ---------------------------------------------------------------------------
+constexpr int OT = 16;            // output tile edge (x, y)
+constexpr int XT = OT + 6;        // x tile edge (halo 3)
+constexpr int RT = OT + 4;        // rho tile edge (halo 2)
+constexpr int HT = OT + 2;        // hidden tile edge (halo 1)
+constexpr int HN = HT * HT;       // hidden nodes per slice (324)
+constexpr int HB = (HN + 15) / 16;  // 16-node blocks (21)
+constexpr int LT = 256;           // threads per workgroup
+
+// ops: [0..127] layer-1 operand (2 K-steps x 64 lanes, 4 bf16 each as 64-bit
+// words), [128..255] layer-2 operand (2 N-blocks x 64 lanes) -- both packed
+// on the host from W1, W2.
+template <typename T>
+__global__ __launch_bounds__(LT) void k_learned_step(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
+                                                     T* __restrict__ out, long stride,
+                                                     const unsigned long long* __restrict__ ops, int zseg,
+                                                     int x_zero) {
+    __shared__ T xs[4][XT * XT];
+    __shared__ T fs[RT * RT];
+    __shared__ unsigned short rs[3][RT * RT];
+    __shared__ unsigned short hs[HB * 16 * 16];
+    __shared__ float ys[HB * 16 * 16];
+    __shared__ float acc[3][OT * OT];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles = (g.m + OT - 1) / OT;
+    const int bx = blockIdx.x % tiles, by = blockIdx.x / tiles;
+    const int z0 = 1 + blockIdx.y * zseg, z1 = min(g.m + 1, z0 + zseg);  // output slices [z0, z1)
+    const long off = (long)blockIdx.z * stride;
+    const T* xr = x + off;
+    const T* fr = f + off;
+    T* outr = out + off;
+    const int i0 = bx * OT + 1, j0 = by * OT + 1;  // first output node (interior indices from 1)
+    const T invD = T(1) / (T(6) * w0);
+
+    bf16x4 b1[2], b2[2];
+    {
+        const unsigned long long* o = ops;
+        for (int s = 0; s < 2; ++s) {
+            const unsigned long long w = o[s * 64 + lane];
+            __builtin_memcpy(&b1[s], &w, 8);
+            const unsigned long long v = o[128 + s * 64 + lane];
+            __builtin_memcpy(&b2[s], &v, 8);
+        }
+    }
+    for (int t = tid; t < 3 * OT * OT; t += LT) (&acc[0][0])[t] = 0.f;
+    for (int t = tid; t < 3 * RT * RT; t += LT) (&rs[0][0])[t] = 0;
+
+    auto load_x = [&](int l) {  // x slice l (grid node index) into ring slot l & 3
+        T* d = xs[l & 3];
+        for (int t = tid; t < XT * XT; t += LT) {
+            const int a = t % XT, b = t / XT;
+            const int i = i0 - 3 + a, j = j0 - 3 + b;
+            T v = T(0);
+            if (!x_zero && l >= 0 && l <= g.n && i >= 0 && i <= g.n && j >= 0 && j <= g.n) v = xr[g.idx(i, j, l)];
+            d[t] = v;
+        }
+    };
+    load_x(z0 - 3);
+    load_x(z0 - 2);
+    __syncthreads();
+    for (int q = z0 - 2; q <= z1 + 1; ++q) {
+        // 1. x slice q + 1, f slice q
+        load_x(q + 1);
+        for (int t = tid; t < RT * RT; t += LT) {
+            const int a = t % RT, b = t / RT;
+            const int i = i0 - 2 + a, j = j0 - 2 + b;
+            T v = T(0);
+            if (q >= 1 && q <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) v = fr[g.idx(i, j, q)];
+            fs[t] = v;
+        }
+        __syncthreads();
+        // 2. rho slice q (zero off the interior)
+        {
+            unsigned short* d = rs[(q + 3) % 3];
+            const T* xc = xs[q & 3];
+            const T* xp = xs[(q + 1) & 3];
+            for (int t = tid; t < RT * RT; t += LT) {
+                const int a = t % RT, b = t / RT;
+                const int i = i0 - 2 + a, j = j0 - 2 + b;
+                float v = 0.f;
+                if (q >= 1 && q <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
+                    const int p = (b + 1) * XT + (a + 1);
+                    const T* xq = xs[(q - 1) & 3];
+                    const T Ax = w0 * (T(6) * xc[p] - xc[p - 1] - xc[p + 1] - xc[p - XT] - xc[p + XT] - xq[p] - xp[p]);
+                    v = (float)((fs[t] - Ax) * invD);
+                }
+                d[t] = f2bf(v);
+            }
+        }
+        __syncthreads();
+        // 3. hidden slice p = q - 1 from rho slices p - 1, p, p + 1
+        const int p = q - 1;
+        for (int blk = wave; blk < HB; blk += LT / 64) {
+            const int v = blk * 16 + (lane & 15);
+            const int hx = v % HT, hy = v / HT;
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                bf16x4 a;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int t = ks * 16 + 4 * (lane >> 4) + jj;
+                    unsigned short val = 0;
+                    if (t < 27 && v < HN) {
+                        int dx, dy, dz;
+                        tap_off(t, dx, dy, dz);
+                        val = rs[(p + dz + 3) % 3][(hy + 1 + dy) * RT + (hx + 1 + dx)];
+                    }
+                    a[jj] = (short)val;
+                }
+                c = mfma(a, b1[ks], c);
+            }
+            // rows 4 (lane / 16) + jj of the block, channel lane % 16
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int u = blk * 16 + 4 * (lane >> 4) + jj;
+                const int ux = u % HT, uy = u / HT;
+                const int i = i0 - 1 + ux, j = j0 - 1 + uy;
+                const bool in = u < HN && p >= 1 && p <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m;
+                hs[u * 16 + (lane & 15)] = f2bf(in ? fmaxf(c[jj], 0.f) : 0.f);
+            }
+        }
+        __syncthreads();
+        // 4. Y = h W2 per tap block, gathered into the output slices p - dz
+        for (int nb = 0; nb < 2; ++nb) {
+            for (int blk = wave; blk < HB; blk += LT / 64) {
+                const int v = blk * 16 + (lane & 15);
+                bf16x4 a;
+                const unsigned short* hp = &hs[v * 16 + 4 * (lane >> 4)];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) a[jj] = (short)hp[jj];
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                c = mfma(a, b2[nb], c);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) ys[(blk * 16 + 4 * (lane >> 4) + jj) * 16 + (lane & 15)] = c[jj];
+            }
+            __syncthreads();
+            {
+                const int ox = tid % OT, oy = tid / OT;  // LT == OT * OT
+                const int tn = nb == 0 ? 16 : 11;
+                for (int tt = 0; tt < tn; ++tt) {
+                    const int t = nb * 16 + tt;
+                    int dx, dy, dz;
+                    tap_off(t, dx, dy, dz);
+                    // hidden node u = v + t lies in slice p, so it feeds output slice p - dz
+                    const int u = (oy + 1 + dy) * HT + (ox + 1 + dx);
+                    acc[(p - dz + 3) % 3][tid] += ys[u * 16 + tt];
+                }
+            }
+            __syncthreads();
+        }
+        // 5. output slice o = p - 1 is complete
+        const int o = p - 1;
+        {
+            const int ox = tid % OT, oy = tid / OT;
+            float* a = acc[(o + 3) % 3];
+            if (o >= z0 && o < z1) {
+                const int i = i0 + ox, j = j0 + oy;
+                if (i <= g.m && j <= g.m) {
+                    const T xv = xs[o & 3][(oy + 3) * XT + (ox + 3)];
+                    outr[g.idx(i, j, o)] = xv + (T)a[tid];
+                }
+            }
+            a[tid] = 0.f;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training kernels (FP32 fields on an m^3 interior grid, S samples;
+// "padded" arrays have one zero node around the interior)
+// ---------------------------------------------------------------------------
+struct TGrid {
+    int m, mp;       // interior edge, padded edge m + 2
+    long vol, pvol;  // m^3, (m + 2)^3
+    __host__ __device__ inline long pidx(int x, int y, int z) const {
+        return ((long)(z + 1) * mp + (y + 1)) * mp + (x + 1);
+    }
+};
+
+__device__ inline void vox(const TGrid& tg, long u, int& x, int& y, int& z) {
+    x = (int)(u % tg.m);
+    y = (int)((u / tg.m) % tg.m);
+    z = (int)(u / ((long)tg.m * tg.m));
+}
+
+// rho = r / D rounded (padded), and ||r||^2 per sample (block partials)
+__global__ __launch_bounds__(256) void k_lt_rho(TGrid tg, const float* __restrict__ r, float invD,
+                                                unsigned short* __restrict__ rho_p, float* __restrict__ nr_part) {
+    __shared__ float sh[4];
+    const int s = blockIdx.y;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    float q = 0.f;
+    if (u < tg.vol) {
+        int x, y, z;
+        vox(tg, u, x, y, z);
+        const float v = r[s * tg.vol + u];
+        rho_p[s * tg.pvol + tg.pidx(x, y, z)] = f2bf(v * invD);
+        q = v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) nr_part[(long)s * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// out[u][c] = sum_t src(u + sgn * t) W[c][t] over 16-node blocks of all
+// samples (M = nodes, K = taps, N = channels).  Mode 0 (layer 1): stores z1
+// and h = bf16(relu) padded.  Mode 1 (hidden gradient): multiplies by the
+// ReLU mask of z1 and stores bf16 unpadded.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_lt_tapconv(TGrid tg, int S, const unsigned short* __restrict__ src_p,
+                                                    const unsigned long long* __restrict__ wop, int sgn,
+                                                    float* __restrict__ z1, unsigned short* __restrict__ outb) {
+    const int lane = threadIdx.x & 63;
+    const long nblk = (tg.vol * S + 15) / 16;
+    const long blk = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (blk >= nblk) return;
+    bf16x4 b[2];
+    for (int ks = 0; ks < 2; ++ks) {
+        const unsigned long long w = wop[ks * 64 + lane];
+        __builtin_memcpy(&b[ks], &w, 8);
+    }
+    const long gu = blk * 16 + (lane & 15);
+    const bool valid = gu < tg.vol * S;
+    const int s = valid ? (int)(gu / tg.vol) : 0;
+    int x = 0, y = 0, z = 0;
+    if (valid) vox(tg, gu - (long)s * tg.vol, x, y, z);
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        bf16x4 a;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int t = ks * 16 + 4 * (lane >> 4) + jj;
+            unsigned short val = 0;
+            if (t < 27 && valid) {
+                int dx, dy, dz;
+                tap_off(t, dx, dy, dz);
+                val = src_p[(long)s * tg.pvol + tg.pidx(x + sgn * dx, y + sgn * dy, z + sgn * dz)];
+            }
+            a[jj] = (short)val;
+        }
+        c = mfma(a, b[ks], c);
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const long ou = blk * 16 + 4 * (lane >> 4) + jj;
+        if (ou >= tg.vol * S) continue;
+        const int ch = lane & 15;
+        const int os = (int)(ou / tg.vol);
+        const long lu = ou - (long)os * tg.vol;
+        if (MODE == 0) {
+            z1[ou * 16 + ch] = c[jj];
+            int ox, oy, oz;
+            vox(tg, lu, ox, oy, oz);
+            outb[((long)os * tg.pvol + tg.pidx(ox, oy, oz)) * 16 + ch] = f2bf(fmaxf(c[jj], 0.f));
+        } else {
+            const float v = z1[ou * 16 + ch] > 0.f ? c[jj] : 0.f;
+            outb[ou * 16 + ch] = f2bf(v);
+        }
+    }
+}
+
+// Y[u][t] = sum_c h[u][c] W2[c][t] (M = nodes, K = channels, N = taps),
+// stored padded [pvol][32] so the gather needs no bounds checks
+__global__ __launch_bounds__(256) void k_lt_y(TGrid tg, int S, const unsigned short* __restrict__ h_p,
+                                              const unsigned long long* __restrict__ wop, float* __restrict__ y_p) {
+    const int lane = threadIdx.x & 63;
+    const long nblk = (tg.vol * S + 15) / 16;
+    const long blk = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (blk >= nblk) return;
+    const long gu = blk * 16 + (lane & 15);
+    const bool valid = gu < tg.vol * S;
+    const int s = valid ? (int)(gu / tg.vol) : 0;
+    int x = 0, y = 0, z = 0;
+    if (valid) vox(tg, gu - (long)s * tg.vol, x, y, z);
+    bf16x4 a;
+    const long hb = ((long)s * tg.pvol + tg.pidx(x, y, z)) * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) a[jj] = valid ? (short)h_p[hb + jj] : (short)0;
+    for (int nb = 0; nb < 2; ++nb) {
+        bf16x4 b;
+        const unsigned long long w = wop[nb * 64 + lane];
+        __builtin_memcpy(&b, &w, 8);
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = mfma(a, b, c);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const long ou = blk * 16 + 4 * (lane >> 4) + jj;
+            if (ou >= tg.vol * S) continue;
+            const int os = (int)(ou / tg.vol);
+            int ox, oy, oz;
+            vox(tg, ou - (long)os * tg.vol, ox, oy, oz);
+            y_p[((long)os * tg.pvol + tg.pidx(ox, oy, oz)) * 32 + nb * 16 + (lane & 15)] = c[jj];
+        }
+    }
+}
+
+// delta(v) = sum_t Y[v + t][t] (padded output)
+__global__ __launch_bounds__(256) void k_lt_delta(TGrid tg, const float* __restrict__ y_p, float* __restrict__ d_p) {
+    const int s = blockIdx.y;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    if (u >= tg.vol) return;
+    int x, y, z;
+    vox(tg, u, x, y, z);
+    const float* yb = y_p + (long)s * tg.pvol * 32;
+    float acc = 0.f;
+    for (int t = 0; t < 27; ++t) {
+        int dx, dy, dz;
+        tap_off(t, dx, dy, dz);
+        acc += yb[tg.pidx(x + dx, y + dy, z + dz) * 32 + t];
+    }
+    d_p[(long)s * tg.pvol + tg.pidx(x, y, z)] = acc;
+}
+
+__device__ inline float lap7(const TGrid& tg, const float* a, long p, float w0) {
+    const long sy = tg.mp, sz = (long)tg.mp * tg.mp;
+    return w0 * (6.f * a[p] - a[p - 1] - a[p + 1] - a[p - sy] - a[p + sy] - a[p - sz] - a[p + sz]);
+}
+
+// res = r - A delta (padded), and block partials of res^2 per sample
+__global__ __launch_bounds__(256) void k_lt_res(TGrid tg, const float* __restrict__ r, const float* __restrict__ d_p,
+                                                float w0, float* __restrict__ res_p, float* __restrict__ part) {
+    __shared__ float sh[4];
+    const int s = blockIdx.y;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    float q = 0.f;
+    if (u < tg.vol) {
+        int x, y, z;
+        vox(tg, u, x, y, z);
+        const long p = tg.pidx(x, y, z);
+        const float v = r[s * tg.vol + u] - lap7(tg, d_p + (long)s * tg.pvol, p, w0);
+        res_p[(long)s * tg.pvol + p] = v;
+        q = v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long)s * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// g = coef[s] * A res, rounded (padded)
+__global__ __launch_bounds__(256) void k_lt_g(TGrid tg, const float* __restrict__ res_p, const float* __restrict__ coef,
+                                              float w0, unsigned short* __restrict__ g_p) {
+    const int s = blockIdx.y;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    if (u >= tg.vol) return;
+    int x, y, z;
+    vox(tg, u, x, y, z);
+    const long p = tg.pidx(x, y, z);
+    g_p[(long)s * tg.pvol + p] = f2bf(coef[s] * lap7(tg, res_p + (long)s * tg.pvol, p, w0));
+}
+
+// dW[c][t] = sum_u X[u][c] src(u + sgn t) (M = channels, K = nodes, N = taps),
+// one partial [16][32] per workgroup; X is padded (layer-2 gradient: h) or
+// not (layer-1 gradient: hidden gradient)
+template <bool XPAD>
+__global__ __launch_bounds__(256) void k_lt_dw(TGrid tg, int S, const unsigned short* __restrict__ X,
+                                               const unsigned short* __restrict__ src_p, int sgn,
+                                               float* __restrict__ part, int kblocks_per_wave) {
+    __shared__ float red[4][16 * 32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long nk = (tg.vol * S + 15) / 16;
+    f32x4 c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    const long kb0 = ((long)blockIdx.x * 4 + wave) * kblocks_per_wave;
+    for (long kb = kb0; kb < kb0 + kblocks_per_wave && kb < nk; ++kb) {
+        bf16x4 a, b[2];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const long gu = kb * 16 + 4 * (lane >> 4) + jj;  // node of K row 4 (lane / 16) + jj
+            unsigned short av = 0, bv0 = 0, bv1 = 0;
+            if (gu < tg.vol * S) {
+                const int s = (int)(gu / tg.vol);
+                int x, y, z;
+                vox(tg, gu - (long)s * tg.vol, x, y, z);
+                const int ch = lane & 15;
+                av = XPAD ? X[((long)s * tg.pvol + tg.pidx(x, y, z)) * 16 + ch] : X[gu * 16 + ch];
+                const int t0 = lane & 15, t1 = 16 + (lane & 15);
+                int dx, dy, dz;
+                tap_off(t0, dx, dy, dz);
+                bv0 = src_p[(long)s * tg.pvol + tg.pidx(x + sgn * dx, y + sgn * dy, z + sgn * dz)];
+                if (t1 < 27) {
+                    tap_off(t1, dx, dy, dz);
+                    bv1 = src_p[(long)s * tg.pvol + tg.pidx(x + sgn * dx, y + sgn * dy, z + sgn * dz)];
+                }
+            }
+            // A[c][k]: lane holds row c = lane % 16, columns 4 (lane / 16) + jj:
+            // X at node k for channel c -- the same (node, channel) pairs as above
+            a[jj] = (short)av;
+            b[0][jj] = (short)bv0;
+            b[1][jj] = (short)bv1;
+        }
+        c[0] = mfma(a, b[0], c[0]);
+        c[1] = mfma(a, b[1], c[1]);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) red[wave][(4 * (lane >> 4) + jj) * 32 + nb * 16 + (lane & 15)] = c[nb][jj];
+    __syncthreads();
+    for (int t = threadIdx.x; t < 16 * 32; t += 256)
+        part[(long)blockIdx.x * 512 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+// fixed-order sums of nparts partials of n floats
+__global__ __launch_bounds__(256) void k_lt_sum(const float* __restrict__ part, int nparts, int n,
+                                                double* __restrict__ out) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[(long)p * n + t];
+    out[t] = s;
+}
+
+__global__ void k_lt_zero_u16(unsigned short* p, long n) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = 0;
+}
+__global__ void k_lt_zero_f(float* p, long n) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) p[t] = 0.f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+// Operand words (4 bfloat16 per 64-bit word, lane order) of a [16][27]
+// weight array as the B operand of a (nodes x taps) x (taps x channels)
+// product: B[t][c] = W[c][t], K-steps of 16 taps (taps >= 27 are zero).
+void learned_pack_taps_by_channel(const float* W, unsigned long long* out) {
+    for (int ks = 0; ks < 2; ++ks)
+        for (int lane = 0; lane < 64; ++lane) {
+            unsigned short v[4];
+            for (int j = 0; j < 4; ++j) {
+                const int t = ks * 16 + 4 * (lane / 16) + j, c = lane % 16;
+                v[j] = t < 27 ? f2bf(W[c * 27 + t]) : 0;
+            }
+            __builtin_memcpy(&out[ks * 64 + lane], v, 8);
+        }
+}
+// ... as the B operand of a (nodes x channels) x (channels x taps) product:
+// B[c][t] = W[c][t], N-blocks of 16 taps.
+void learned_pack_channels_by_tap(const float* W, unsigned long long* out) {
+    for (int nb = 0; nb < 2; ++nb)
+        for (int lane = 0; lane < 64; ++lane) {
+            unsigned short v[4];
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * (lane / 16) + j, t = nb * 16 + lane % 16;
+                v[j] = t < 27 ? f2bf(W[c * 27 + t]) : 0;
+            }
+            __builtin_memcpy(&out[nb * 64 + lane], v, 8);
+        }
+}
+
+constexpr int kLearnedZseg = 32;
+
+template <typename T>
+void launch_learned_step(const Grid& g, T w0, const T* x, const T* f, T* out, int nrhs, long stride,
+                         const unsigned long long* ops, bool x_zero, hipStream_t st) {
+    if (g.dim != 3) throw Error(PASM_E_INVALID, "learned smoother: 3D levels only");
+    const int tiles = (g.m + OT - 1) / OT;
+    dim3 grid(tiles * tiles, (g.m + kLearnedZseg - 1) / kLearnedZseg, nrhs);
+    hipLaunchKernelGGL((k_learned_step<T>), grid, dim3(LT), 0, st, g, w0, x, f, out, stride, ops, kLearnedZseg,
+                       (int)x_zero);
+    PASM_CHECK_LAUNCH();
+}
+template void launch_learned_step<float>(const Grid&, float, const float*, const float*, float*, int, long,
+                                         const unsigned long long*, bool, hipStream_t);
+template void launch_learned_step<double>(const Grid&, double, const double*, const double*, double*, int, long,
+                                          const unsigned long long*, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// residual norms, random fields and sample packing (3D levels)
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_norm3(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
+                                                     long stride, double* __restrict__ partial) {
+    __shared__ double sh[4];
+    const long n = (long)g.m * g.m * g.m;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    const long off = (long)blockIdx.y * stride;
+    double q = 0.0;
+    if (u < n) {
+        const int i = (int)(u % g.m) + 1, j = (int)((u / g.m) % g.m) + 1, l = (int)(u / ((long)g.m * g.m)) + 1;
+        const long id = off + g.idx(i, j, l);
+        const long sy = g.pitch, sz = (long)(g.n + 1) * g.pitch;
+        const double Ax = (double)w0 * (6.0 * (double)x[id] - (double)x[id - 1] - (double)x[id + 1] -
+                                        (double)x[id - sy] - (double)x[id + sy] - (double)x[id - sz] - (double)x[id + sz]);
+        const double r = (double)f[id] - Ax;
+        q = r * r;
+    }
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        partial[2 * b] = sh[0] + sh[1] + sh[2] + sh[3];
+        partial[2 * b + 1] = 0.0;
+    }
+}
+
+// standard normal values on the interior nodes (splitmix64 + Box-Muller)
+__device__ inline unsigned long long splitmix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_normal3(Grid g, T* __restrict__ x, long stride, unsigned long long seed) {
+    const long n = (long)g.m * g.m * g.m;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    if (u >= n) return;
+    const int i = (int)(u % g.m) + 1, j = (int)((u / g.m) % g.m) + 1, l = (int)(u / ((long)g.m * g.m)) + 1;
+    const unsigned long long key = seed * 0x100000001B3ull + (unsigned long long)blockIdx.y * n + u;
+    const unsigned long long a = splitmix64(key), b = splitmix64(key ^ 0xD1B54A32D192ED03ull);
+    const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0), u2 = (b >> 11) * (1.0 / 9007199254740992.0);
+    x[(long)blockIdx.y * stride + g.idx(i, j, l)] = (T)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
+// pool[s] = -(A x)[r] as FP32 compact (the residual for f = 0)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_negA3(Grid g, T w0, const T* __restrict__ x, long stride,
+                                                    float* __restrict__ pool) {
+    const long n = (long)g.m * g.m * g.m;
+    const long u = (long)blockIdx.x * 256 + threadIdx.x;
+    if (u >= n) return;
+    const int i = (int)(u % g.m) + 1, j = (int)((u / g.m) % g.m) + 1, l = (int)(u / ((long)g.m * g.m)) + 1;
+    const long id = (long)blockIdx.y * stride + g.idx(i, j, l);
+    const long sy = g.pitch, sz = (long)(g.n + 1) * g.pitch;
+    const T Ax = w0 * (T(6) * x[id] - x[id - 1] - x[id + 1] - x[id - sy] - x[id + sy] - x[id - sz] - x[id + sz]);
+    pool[(long)blockIdx.y * n + u] = (float)(-Ax);
+}
+
+}  // namespace
+
+template <typename T>
+int launch_resid_norm3(const Grid& g, T w0, const T* x, const T* f, double* partial, int nrhs, long stride,
+                       hipStream_t st) {
+    const long n = (long)g.m * g.m * g.m;
+    dim3 grid((unsigned)((n + 255) / 256), nrhs);
+    hipLaunchKernelGGL((k_resid_norm3<T>), grid, dim3(256), 0, st, g, w0, x, f, stride, partial);
+    PASM_CHECK_LAUNCH();
+    return (int)grid.x;
+}
+template int launch_resid_norm3<float>(const Grid&, float, const float*, const float*, double*, int, long, hipStream_t);
+template int launch_resid_norm3<double>(const Grid&, double, const double*, const double*, double*, int, long,
+                                        hipStream_t);
+
+template <typename T>
+void launch_fill_normal3(const Grid& g, T* x, int nrhs, long stride, unsigned long long seed, hipStream_t st) {
+    const long n = (long)g.m * g.m * g.m;
+    hipLaunchKernelGGL((k_fill_normal3<T>), dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, st, g, x, stride,
+                       seed);
+    PASM_CHECK_LAUNCH();
+}
+template void launch_fill_normal3<float>(const Grid&, float*, int, long, unsigned long long, hipStream_t);
+template void launch_fill_normal3<double>(const Grid&, double*, int, long, unsigned long long, hipStream_t);
+
+template <typename T>
+void launch_pack_negA3(const Grid& g, T w0, const T* x, int nrhs, long stride, float* pool, hipStream_t st) {
+    const long n = (long)g.m * g.m * g.m;
+    hipLaunchKernelGGL((k_pack_negA3<T>), dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, st, g, w0, x, stride,
+                       pool);
+    PASM_CHECK_LAUNCH();
+}
+template void launch_pack_negA3<float>(const Grid&, float, const float*, int, long, float*, hipStream_t);
+template void launch_pack_negA3<double>(const Grid&, double, const double*, int, long, float*, hipStream_t);
+
+void LearnedTrainer::init(int m_, int S_, float w0_, std::function<void*(size_t)> alloc) {
+    m = m_;
+    S = S_;
+    w0 = w0_;
+    const long vol = (long)m * m * m, pvol = (long)(m + 2) * (m + 2) * (m + 2);
+    rho_p = (unsigned short*)alloc(sizeof(unsigned short) * pvol * S);
+    h_p = (unsigned short*)alloc(sizeof(unsigned short) * pvol * S * 16);
+    g_p = (unsigned short*)alloc(sizeof(unsigned short) * pvol * S);
+    gh = (unsigned short*)alloc(sizeof(unsigned short) * vol * S * 16);
+    z1 = (float*)alloc(sizeof(float) * vol * S * 16);
+    y_p = (float*)alloc(sizeof(float) * pvol * S * 32);
+    d_p = (float*)alloc(sizeof(float) * pvol * S);
+    res_p = (float*)alloc(sizeof(float) * pvol * S);
+    nblk_vox = (int)((vol + 255) / 256);
+    nr_part = (float*)alloc(sizeof(float) * nblk_vox * S);
+    res_part = (float*)alloc(sizeof(float) * nblk_vox * S);
+    coef = (float*)alloc(sizeof(float) * S);
+    const long nk = (vol * S + 15) / 16;
+    dw_kpw = 16;
+    dw_blocks = (int)((nk + 4L * dw_kpw - 1) / (4L * dw_kpw));
+    dw_part = (float*)alloc(sizeof(float) * 512 * dw_blocks);
+    sums = (double*)alloc(sizeof(double) * (2 * 512 + 2 * nblk_vox * S));
+    ops = (unsigned long long*)alloc(sizeof(unsigned long long) * 3 * 128);
+}
+
+// Loss and gradient of the samples r[0..S) (FP32, interior m^3 each) with
+// the weights W (FP32 [2][16][27]); gradient in grad [2][16][27].
+double LearnedTrainer::loss_grad(const float* r, const float* W, double* grad, hipStream_t st) {
+    const TGrid tg{m, m + 2, (long)m * m * m, (long)(m + 2) * (m + 2) * (m + 2)};
+    // operands: layer 1 (W1 as taps x channels), layer 2 (W2 as channels x
+    // taps), hidden gradient (W2 as taps x channels)
+    unsigned long long hops[3 * 128];
+    learned_pack_taps_by_channel(W, hops);
+    learned_pack_channels_by_tap(W + 16 * 27, hops + 128);
+    learned_pack_taps_by_channel(W + 16 * 27, hops + 256);
+    PASM_HIP(hipMemcpyAsync(ops, hops, sizeof(hops), hipMemcpyHostToDevice, st));
+    const dim3 gv(nblk_vox, S);
+    const long pvol = tg.pvol * S;
+    // zero borders of the padded arrays (their interiors are overwritten)
+    hipLaunchKernelGGL(k_lt_zero_u16, dim3(1024), dim3(256), 0, st, rho_p, pvol);
+    hipLaunchKernelGGL(k_lt_zero_u16, dim3(1024), dim3(256), 0, st, h_p, pvol * 16);
+    hipLaunchKernelGGL(k_lt_zero_u16, dim3(1024), dim3(256), 0, st, g_p, pvol);
+    hipLaunchKernelGGL(k_lt_zero_f, dim3(1024), dim3(256), 0, st, y_p, pvol * 32);
+    hipLaunchKernelGGL(k_lt_zero_f, dim3(1024), dim3(256), 0, st, d_p, pvol);
+    hipLaunchKernelGGL(k_lt_zero_f, dim3(1024), dim3(256), 0, st, res_p, pvol);
+    PASM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_lt_rho, gv, dim3(256), 0, st, tg, r, 1.f / (6.f * w0), rho_p, nr_part);
+    const long nb16 = (tg.vol * S + 15) / 16;
+    const int g16 = (int)((nb16 + 3) / 4);
+    hipLaunchKernelGGL((k_lt_tapconv<0>), dim3(g16), dim3(256), 0, st, tg, S, rho_p, ops, 1, z1, h_p);
+    hipLaunchKernelGGL(k_lt_y, dim3(g16), dim3(256), 0, st, tg, S, h_p, ops + 128, y_p);
+    hipLaunchKernelGGL(k_lt_delta, gv, dim3(256), 0, st, tg, y_p, d_p);
+    hipLaunchKernelGGL(k_lt_res, gv, dim3(256), 0, st, tg, r, d_p, w0, res_p, res_part);
+    PASM_CHECK_LAUNCH();
+    // per-sample norms on the host (S values), then coef = -2 / (S ||r||^2)
+    double* hs = sums;
+    hipLaunchKernelGGL(k_lt_sum, dim3((nblk_vox * S + 255) / 256), dim3(256), 0, st, nr_part, 1, nblk_vox * S, hs);
+    hipLaunchKernelGGL(k_lt_sum, dim3((nblk_vox * S + 255) / 256), dim3(256), 0, st, res_part, 1, nblk_vox * S,
+                       hs + nblk_vox * S);
+    std::vector<double> pn(2 * (size_t)nblk_vox * S);
+    PASM_HIP(hipMemcpyAsync(pn.data(), hs, pn.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    PASM_HIP(hipStreamSynchronize(st));
+    std::vector<float> cf(S);
+    double loss = 0.0;
+    for (int s = 0; s < S; ++s) {
+        double nr = 0.0, rr = 0.0;
+        for (int b = 0; b < nblk_vox; ++b) {
+            nr += pn[(size_t)s * nblk_vox + b];
+            rr += pn[(size_t)nblk_vox * S + (size_t)s * nblk_vox + b];
+        }
+        loss += rr / nr / S;
+        cf[s] = (float)(-2.0 / (S * nr));
+    }
+    PASM_HIP(hipMemcpyAsync(coef, cf.data(), S * sizeof(float), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_lt_g, gv, dim3(256), 0, st, tg, res_p, coef, w0, g_p);
+    // hidden gradient: sum_t W2[c][t] g(u - t), masked by z1 > 0
+    hipLaunchKernelGGL((k_lt_tapconv<1>), dim3(g16), dim3(256), 0, st, tg, S, g_p, ops + 256, -1, z1, gh);
+    // dW2[c][t] = sum_u h(u)[c] g(u - t); dW1[c][t] = sum_u gh(u)[c] rho(u + t)
+    hipLaunchKernelGGL((k_lt_dw<true>), dim3(dw_blocks), dim3(256), 0, st, tg, S, h_p, g_p, -1, dw_part, dw_kpw);
+    hipLaunchKernelGGL(k_lt_sum, dim3(2), dim3(256), 0, st, dw_part, dw_blocks, 512, sums + 512);
+    hipLaunchKernelGGL((k_lt_dw<false>), dim3(dw_blocks), dim3(256), 0, st, tg, S, gh, rho_p, 1, dw_part, dw_kpw);
+    hipLaunchKernelGGL(k_lt_sum, dim3(2), dim3(256), 0, st, dw_part, dw_blocks, 512, sums);
+    PASM_CHECK_LAUNCH();
+    std::vector<double> gd(1024);
+    PASM_HIP(hipMemcpyAsync(gd.data(), sums, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PASM_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < 16; ++c)
+        for (int t = 0; t < 27; ++t) {
+            grad[c * 27 + t] = gd[c * 32 + t];
+            grad[16 * 27 + c * 27 + t] = gd[512 + c * 32 + t];
+        }
+    return loss;
+}
+
+}  // namespace pasm
