@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the parallel augmented subspace eigensolver on one MI355X.
 
-A step is one whole solve of the hot path: restart from the coarse start of
-Algorithm 2 (u_i = P q_i, lambda_i = theta_i, on the device) and correction
-steps (Algorithm 1: V-cycles, borders, arrowhead eigensolve, prolongation)
-for all k eigenpairs until every eigenvalue is within 1e-8 relative of the
-discrete eigenvalue (the oracle's stored values when present, else this
-run's own tightly converged values).  metric = eigenpairs per second to 1e-8
-relative eigenvalue error, whole job, inputs resident in HBM.
+Default workload (lap2d-H64-h1024-k20): a step is one whole solve of the hot
+path: restart from the coarse start of Algorithm 2 (u_i = P q_i,
+lambda_i = theta_i, on the device) and correction steps (Algorithm 1:
+V-cycles, borders, arrowhead eigensolve, prolongation) for all k eigenpairs
+until every eigenvalue is within 1e-8 relative of the discrete eigenvalue
+(the oracle's stored values when present, else this run's own tightly
+converged values).  metric = eigenpairs per second to 1e-8 relative
+eigenvalue error, whole job, inputs resident in HBM.
+
+Other workloads (--workload NAME, see workloads.py):
+  * the same solve metric for the mixed-precision and the 3D workloads
+    (plain and learned smoother);
+  * for the rough-coefficient workloads, whose eigenpairs mostly do not
+    converge with this coarse space, and for the batch of uneven instances:
+    eigenpair correction steps per second (k eigenpairs x iterations /
+    time), with the batch compared against the same members run one after
+    the other.
 
 Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
 """
@@ -28,9 +38,20 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
 # sources of the kernels that run on the finest level of the timed workloads
 KERNEL_SOURCES = ["paper_1908_10251_amd/csrc/march2d.hip", "paper_1908_10251_amd/csrc/stencil2d.hip",
-                  "paper_1908_10251_amd/csrc/stencil3d.hip", "paper_1908_10251_amd/csrc/common.h"]
+                  "paper_1908_10251_amd/csrc/stencil3d.hip", "paper_1908_10251_amd/csrc/learned3d.hip",
+                  "paper_1908_10251_amd/csrc/common.h"]
+
+KERNEL_NAMES = {
+    2: "finest-level smoothing phases (k_march: pre-smoothing with fused residual restriction, "
+       "post-smoothing with fused prolongation; k_smooth_fused where coefficients vary)",
+    3: "finest-level smoothing sweeps (k_smooth3)",
+    "learned": "finest-level learned smoothing step (k_learned_step: residual, two bfloat16 matrix-core "
+               "convolutions, update)",
+    "batch": "finest batched level smoothing phases (k_smooth_fused, general 7-point operators)",
+}
 
 
 def kernel_hash() -> str:
@@ -49,9 +70,8 @@ def golden(name: str):
 
 
 def traffic_record(workload: str):
-    """HBM bytes per launch of the finest-level smoothing phases from the
-    committed rocprofv3 counter summary, if it was taken on the current
-    kernel sources."""
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_fine_smoothing_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -89,14 +109,213 @@ def cpu_baseline(wl: W.Workload, ref: np.ndarray, budget_s: float = 25.0):
                       f"to 1e-8 in {t_iter:.1f} s, one core; oracle set-up {t_setup:.1f} s not counted"}
 
 
+def roofline(launches, ms, bpl, workload, kernel, flops_per_launch=None):
+    avg_ms = ms / max(launches, 1)
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_record(workload), "kernel": kernel,
+           "launches": launches, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bpl}
+    if flops_per_launch and launches:
+        tf = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        out["mfma_tflops"] = tf
+        out["mfma_frac_of_bf16_peak"] = tf / PEAK_BF16_TFLOPS
+    return out
+
+
+def line(wl, metric, value, unit, steps, warmup, ms_per_step, config, roof, dtype):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": dict({"workload": wl.name}, **config),
+            "roofline": roof}
+
+
+def coefficients(wl: W.Workload):
+    """Per-element inputs of a single-instance workload."""
+    kap = W.lognormal_kappa(wl.dim, wl.n_fine, seed=wl.seed) if wl.kappa == "lognormal" else None
+    return kap, None
+
+
+def bench_solve(args, wl, pasm, torch):
+    """A step = one whole solve to 1e-8 relative eigenvalue error."""
+    opts = pasm.options_for(wl)
+    opts.max_iter = args.max_iter
+    kap, pot = coefficients(wl)
+    t0 = time.perf_counter()
+    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts)
+    t_setup = time.perf_counter() - t0
+    ctx, k = solver.ctx, wl.k
+
+    ref = golden(wl.golden_name)
+    ref_kind = "oracle discrete eigenvalues (tests/golden)"
+    if ref is None:
+        # tightly converged FP64 values of the same problem with the plain smoother
+        o2 = pasm.options_for(wl)
+        o2.precision = pasm.PASM_FP64
+        if o2.smoother == pasm.PASM_LEARNED:
+            o2.smoother = pasm.PASM_JACOBI
+        o2.tol, o2.max_iter = 1e-14, args.ref_iter
+        with pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=o2) as rs:
+            its = rs.solve(allow_notconv=True)
+            ref = rs.eigenpairs(False)[0]
+        ref_kind = f"this problem's eigenvalues from {its} FP64 plain-smoother iterations (tol 1e-14)"
+    ref = np.asarray(ref[:k])
+
+    # Eigenvalues are compared as sorted lists: inside a degenerate cluster
+    # (the 3D cube keeps exact multiplicities) any member of the cluster is a
+    # correct answer for any process of it.
+    def rel_err(lam):
+        return np.abs(np.sort(lam) - np.sort(ref)) / np.sort(ref)
+
+    def one_solve():
+        pasm.pasm_restart(ctx)
+        its = 0
+        while its < args.max_iter:
+            pasm.pasm_iterate(ctx)
+            its += 1
+            lam = solver.eigenpairs(False)[0]
+            if np.max(rel_err(lam)) <= 1e-8:
+                return its, lam
+        return its, solver.eigenpairs(False)[0]
+
+    for _ in range(args.warmup):
+        one_solve()
+    pasm.pasm_profile(ctx, 0, True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    iters = []
+    for _ in range(args.steps):
+        its, lam = one_solve()
+        iters.append(its)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    launches, ms, bpl = pasm.pasm_profile_read(ctx, 0)
+    pasm.pasm_profile(ctx, 0, False)
+    err = rel_err(lam)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = k / (ms_per_step / 1e3) if float(np.max(err)) <= 1e-8 else 0.0
+    n_dofs = pasm.pasm_num_dofs(ctx)
+    learned = wl.smoother == "learned"
+    sweeps = wl.vcycles * (2 if learned else wl.nu_pre + wl.nu_post)
+    cfg = {"dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": n_dofs, "coarse_dofs": pasm.pasm_coarse_dofs(ctx),
+           "smoother": wl.smoother, "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles,
+           "precision": wl.precision, "iterations_per_step": iters, "max_rel_err": float(np.max(err)),
+           "eigenpairs_within_1e-8": int(np.sum(err <= 1e-8)), "reference": ref_kind, "setup_s": t_setup,
+           "fine_dof_updates_per_s": n_dofs * k * sweeps * float(np.mean(iters)) / (ms_per_step / 1e3)}
+    flops = None
+    if learned:
+        rep = pasm.pasm_learned_report(ctx)
+        cfg["learned"] = rep
+        # 16 channels x 27 taps multiply-adds in each of the two layers per node
+        flops = 2.0 * 2 * 16 * 27 * n_dofs * k
+        kernel = KERNEL_NAMES["learned"]
+    else:
+        kernel = KERNEL_NAMES[wl.dim]
+    roof = roofline(launches, ms, bpl, wl.name, kernel, flops)
+    out = line(wl, "eigenpairs/sec to 1e-8 rel eigenvalue error", value, "eigenpairs/s", args.steps, args.warmup,
+               ms_per_step, cfg, roof, "f64" if wl.precision == "fp64" else "f32+f64")
+    if not args.no_cpu_baseline and wl.dim == 2 and wl.kappa == "one":
+        out["cpu_baseline"] = cpu_baseline(wl, ref)
+    solver.close()
+    return out
+
+
+def bench_steps(args, wl, pasm, torch):
+    """Rough-coefficient single instance: correction steps per second."""
+    opts = pasm.options_for(wl)
+    kap, pot = coefficients(wl)
+    t0 = time.perf_counter()
+    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts)
+    t_setup = time.perf_counter() - t0
+    ctx, k = solver.ctx, wl.k
+    for _ in range(args.warmup):
+        pasm.pasm_iterate(ctx)
+    pasm.pasm_profile(ctx, 0, True)
+    hist = [solver.eigenpairs(False)[0]]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.iters):
+        pasm.pasm_iterate(ctx)
+        hist.append(solver.eigenpairs(False)[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    launches, ms, bpl = pasm.pasm_profile_read(ctx, 0)
+    H = np.array(hist)
+    d = np.abs(H[1:] - H[:-1]) / H[1:]
+    ms_per_step = 1e3 * elapsed / args.iters
+    cfg = {"dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": pasm.pasm_num_dofs(ctx),
+           "smoother": wl.smoother, "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles, "precision": wl.precision,
+           "kappa": "log-normal, sigma 1, i.i.d. per fine element", "iterations": args.iters,
+           "eigenpairs_with_last_change_below_1e-10": int(np.sum(d[-1] < 1e-10)), "setup_s": t_setup,
+           "step": "one outer iteration (one correction step for all k eigenpairs)"}
+    roof = roofline(launches, ms, bpl, wl.name, KERNEL_NAMES[2])
+    solver.close()
+    return line(wl, "eigenpair correction steps/sec", k / (ms_per_step / 1e3), "eigenpair-steps/s", args.iters,
+                args.warmup, ms_per_step, cfg, roof, "f32+f64")
+
+
+def bench_batch(args, wl, pasm, torch):
+    """16 uneven instances: batched (one launch per level, graph replay) vs the
+    same members as single contexts one after the other."""
+    inst = W.uneven_batch(16, seed=wl.seed)
+    members = [(1.0 / I.n_fine, I.kappa, W.quadratic_potential_elements(I.n_fine, I.centre)) for I in inst]
+    opts = pasm.options_for(wl)
+    k = wl.k
+    t0 = time.perf_counter()
+    b = pasm.Batch(wl.H, k, members, opts=opts)
+    t_setup = time.perf_counter() - t0
+    rows, tms = pasm.pasm_batch_tuning(b.b)
+
+    def timed(fn, n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / n
+
+    for _ in range(args.warmup):
+        b.iterate()
+    pasm.pasm_batch_profile(b.b, 0, True)
+    t_prof = timed(b.iterate, 2)  # events are recorded outside the graph
+    launches, ms, bpl = pasm.pasm_batch_profile_read(b.b, 0)
+    pasm.pasm_batch_profile(b.b, 0, False)
+    pasm.pasm_batch_use_graph(b.b, False)
+    t_eager = timed(b.iterate, args.iters)
+    pasm.pasm_batch_use_graph(b.b, True)
+    t_graph = timed(b.iterate, args.iters)
+    lam = b.eigenvalues()
+    b.close()
+    singles = [pasm.Solver(2, wl.H, h, k, kappa=kap, potential=pot, opts=opts) for h, kap, pot in members]
+    for s in singles:
+        s.iterate()
+    t_seq = timed(lambda: [s.iterate() for s in singles], max(1, args.iters // 2))
+    for s in singles:
+        s.close()
+    n = len(members)
+    cfg = {"instances": n, "fine_cells": [I.n_fine for I in inst], "H": wl.H, "k_per_instance": k,
+           "total_fine_dofs": int(sum((I.n_fine - 1) ** 2 for I in inst)), "smoother": wl.smoother,
+           "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles, "precision": wl.precision,
+           "kappa": "log-normal, sigma 1, i.i.d. per fine element", "potential": "|x - c|^2, seeded centre",
+           "tiles_per_level": rows.tolist(), "setup_s": t_setup,
+           "ms_per_iteration": {"batched_graph": 1e3 * t_graph, "batched_eager": 1e3 * t_eager,
+                                "sequential_single_contexts": 1e3 * t_seq},
+           "speedup_vs_sequential": t_seq / t_graph, "all_eigenvalues_finite": bool(np.all(np.isfinite(lam))),
+           "step": "one outer iteration for all 16 x k eigenpairs"}
+    roof = roofline(launches, ms, bpl, wl.name, KERNEL_NAMES["batch"])
+    return line(wl, "eigenpair correction steps/sec", n * k / t_graph, "eigenpair-steps/s", args.iters,
+                args.warmup, 1e3 * t_graph, cfg, roof, "f32+f64")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=W.LAP2D_LARGE.name)
+    ap.add_argument("--workload", default=W.LAP2D_LARGE_H64.name)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=40)
+    ap.add_argument("--ref-iter", type=int, default=200, help="iterations of the reference run (no stored values)")
+    ap.add_argument("--iters", type=int, default=10, help="timed iterations (step-throughput workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="also run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -119,89 +338,13 @@ def main():
         return
 
     wl = {w.name: w for w in W.ALL}[args.workload]
-    if wl.kappa != "one" or wl.potential != "none":
-        raise SystemExit("bench.py currently times the constant-coefficient workloads")
     torch.cuda.set_device(0)
-    opts = pasm.options_for(wl)
-    opts.max_iter = args.max_iter
-    t0 = time.perf_counter()
-    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, opts=opts)
-    t_setup = time.perf_counter() - t0
-    ctx = solver.ctx
-    k = wl.k
-
-    ref = golden(wl.golden_name)
-    ref_kind = "oracle discrete eigenvalues (tests/golden)"
-    if ref is None:
-        pasm.pasm_restart(ctx)
-        o2 = pasm.options_for(wl)
-        for _ in range(60):
-            if pasm.pasm_iterate(ctx):
-                break
-        ref = solver.eigenpairs(False)[0]
-        ref_kind = "this run's converged eigenvalues"
-    ref = np.asarray(ref[:k])
-
-    def one_solve():
-        pasm.pasm_restart(ctx)
-        its = 0
-        while its < args.max_iter:
-            pasm.pasm_iterate(ctx)
-            its += 1
-            lam = solver.eigenpairs(False)[0]
-            if np.max(np.abs(lam - ref) / ref) <= 1e-8:
-                return its, lam
-        return its, solver.eigenpairs(False)[0]
-
-    for _ in range(args.warmup):
-        one_solve()
-    pasm.pasm_profile(ctx, 0, True)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    iters = []
-    for _ in range(args.steps):
-        its, lam = one_solve()
-        iters.append(its)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t
-    launches, ms, bpl = pasm.pasm_profile_read(ctx, 0)
-    pasm.pasm_profile(ctx, 0, False)
-    err = float(np.max(np.abs(lam - ref) / ref))
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = k / (ms_per_step / 1e3) if err <= 1e-8 else 0.0
-    avg_ms = ms / max(launches, 1)
-    achieved = bpl / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    traffic = traffic_record(wl.name)
-    n_dofs = pasm.pasm_num_dofs(ctx)
-    sweeps_per_iter = wl.vcycles * (wl.nu_pre + wl.nu_post)
-    dof_updates = n_dofs * k * sweeps_per_iter * float(np.mean(iters)) / (ms_per_step / 1e3)
-    out = {
-        "metric": "eigenpairs/sec to 1e-8 rel eigenvalue error",
-        "value": value,
-        "unit": "eigenpairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if wl.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": n_dofs,
-                   "coarse_dofs": pasm.pasm_coarse_dofs(ctx), "smoother": wl.smoother,
-                   "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles, "precision": wl.precision,
-                   "iterations_per_step": iters, "max_rel_err": err, "reference": ref_kind,
-                   "setup_s": t_setup, "fine_dof_updates_per_s": dof_updates},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "finest-level smoothing phases (k_march: pre-smoothing with fused residual "
-                               "restriction, post-smoothing with fused prolongation)", "launches": launches,
-                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bpl},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, ref)
-    solver.close()
+    if wl is W.BATCH2D_UNEVEN:
+        out = bench_batch(args, wl, pasm, torch)
+    elif wl.kappa != "one":
+        out = bench_steps(args, wl, pasm, torch)
+    else:
+        out = bench_solve(args, wl, pasm, torch)
     print(json.dumps(out), flush=True)
 
 

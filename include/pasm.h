@@ -79,7 +79,9 @@ typedef enum pasm_smoother {
                               trained at set-up on residuals of plain V-cycles; damped
                               Jacobi (nu_pre / nu_post sweeps) is the fallback, taken for
                               any V-cycle whose residual reduction is worse than the plain
-                              cycle's (see pasm_learned_report) */
+                              cycle's, and throughout when the learned cycle reduces the
+                              residual less per unit time than the plain one at set-up
+                              (see pasm_learned_report) */
 } pasm_smoother;
 
 /* Unit box (0,1)^dim; dim = 2 or 3. */
@@ -241,6 +243,8 @@ typedef struct pasm_learned_stats {
     double loss_last;
     double plain_rate;      /* residual reduction of one plain V-cycle (set-up, worst right-hand side) */
     double learned_rate;    /* ... of one learned V-cycle */
+    double plain_cycle_ms;  /* time of one plain / learned V-cycle at set-up */
+    double learned_cycle_ms;
     long cycles_learned;    /* V-cycles kept with the learned smoother */
     long cycles_fallback;   /* V-cycles redone with the plain smoother */
 } pasm_learned_stats;
@@ -253,6 +257,9 @@ PASM_API pasm_status pasm_learned_set_weights(pasm_ctx* ctx, const float* w);
  * when it reduces some right-hand side's residual by less than this factor.
  * rate <= 0 restores the default, the plain cycle's rate measured at set-up. */
 PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* ctx, double rate);
+/* Override the set-up decision: 1 smooths with the learned step (with the
+ * per-cycle fallback), 0 with the plain smoother only. */
+PASM_API pasm_status pasm_learned_enable(pasm_ctx* ctx, int enable);
 /* steps more Adam steps from the current weights; loss_history (may be NULL)
  * receives the loss of each step. */
 PASM_API pasm_status pasm_learned_train(pasm_ctx* ctx, int steps, double* loss_history);

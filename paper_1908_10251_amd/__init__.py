@@ -47,6 +47,7 @@ class pasm_learned_stats(ctypes.Structure):
     _fields_ = [("enabled", ctypes.c_int), ("train_steps", ctypes.c_int),
                 ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
                 ("plain_rate", ctypes.c_double), ("learned_rate", ctypes.c_double),
+                ("plain_cycle_ms", ctypes.c_double), ("learned_cycle_ms", ctypes.c_double),
                 ("cycles_learned", ctypes.c_long), ("cycles_fallback", ctypes.c_long)]
 
 
@@ -106,6 +107,7 @@ def lib() -> ctypes.CDLL:
     L.pasm_learned_set_weights.argtypes = [_P, _F]
     L.pasm_learned_train.argtypes = [_P, ctypes.c_int, _D]
     L.pasm_learned_set_threshold.argtypes = [_P, ctypes.c_double]
+    L.pasm_learned_enable.argtypes = [_P, ctypes.c_int]
     L.pasm_learned_step.argtypes = [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, ctypes.c_int]
     L.pasm_learned_loss_grad.argtypes = [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int, _D, _D]
     L.pasm_batch_setup.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(pasm_domain), ctypes.POINTER(pasm_instance),
@@ -374,6 +376,10 @@ def pasm_learned_set_weights(ctx, w) -> None:
 
 def pasm_learned_set_threshold(ctx, rate: float) -> None:
     _check(lib().pasm_learned_set_threshold(ctx, float(rate)), ctx)
+
+
+def pasm_learned_enable(ctx, enable: bool) -> None:
+    _check(lib().pasm_learned_enable(ctx, int(enable)), ctx)
 
 
 def pasm_learned_train(ctx, steps: int) -> np.ndarray:

@@ -107,6 +107,7 @@ struct pasm_ctx {
     std::vector<double> lm, lv2;
     int ltrain_steps = 0;
     double lloss_first = 0.0, lloss_last = 0.0, lplain_rate = 0.0, llearned_rate = 0.0;
+    double lplain_ms = 0.0, llearned_ms = 0.0;
     long lcycles_learned = 0, lcycles_fallback = 0;
     double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
     std::vector<double> lratio; // residual reduction of the last V-cycles (diagnostics)
@@ -569,8 +570,9 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
             Lv.F = c->alloc<double>(n);
             Lv.Y = c->alloc<double>(n);
         }
-        Lv.B = c->alloc<double>(n);
-        Lv.C = c->alloc<double>(n);
+        // B and C adjacent, so the two coarse products with Q^T share one pass
+        Lv.B = c->alloc<double>(2 * n);
+        Lv.C = Lv.B + n;
     }
     const size_t nf = (size_t)c->sf() * k;
     c->U = c->alloc<double>(nf);
@@ -595,8 +597,8 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     const long nblk = (dim == 2) ? (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4)
                                  : (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4) * gfine.m;
     c->partial = c->alloc<double>(2 * (size_t)nblk * k);
-    c->pp = c->alloc<double>((size_t)N * k);
-    c->qq = c->alloc<double>((size_t)N * k);
+    c->pp = c->alloc<double>(2 * (size_t)N * k);
+    c->qq = c->pp + (size_t)N * k;
     c->ycoef = c->alloc<double>((size_t)N * k);
     c->s = c->alloc<double>(k);
     c->mu = c->alloc<double>(k);
@@ -606,7 +608,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->rank = c->alloc<int>(k);
     c->flags = c->alloc<int>(k);
     c->awork = c->alloc<char>(pasm::arrow_workspace_bytes(N, k));
-    c->dmv = c->alloc<char>(pasm::dense_mv_workspace_bytes(N, k));
+    c->dmv = c->alloc<char>(pasm::dense_mv_workspace_bytes(N, 2 * k));
 
     // dense coarse pencil from the level-0 operators (Galerkin: rediscretised
     // with the coarsened coefficient, or the Galerkin general stencil)
@@ -753,21 +755,42 @@ void iterate_once(pasm_ctx* c) {
         // fine level = V_H: exact solve
         pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->dmv, c->st);
     }
-    // step 2: borders
-    const int nblk = pasm::launch_border(g, c->coef<double>(lf), c->U, c->Y64, c->R64, c->partial, k, sf, c->st);
-    pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
+    // step 2: borders (2D: fused with the first restriction)
     const double* bsrc = c->Y64;
     const double* csrc = c->R64;
-    for (int l = c->L - 2; l >= 0; --l) {
+    int lstart = c->L - 2;
+    if (c->dim == 2 && c->L >= 2) {
+        pasm::Level& Lc = c->lv[c->L - 2];
+        const int nblk = pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C, c->partial, k,
+                                                      sf, Lc.g.plane, c->st);
+        pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
+        bsrc = Lc.B;
+        csrc = Lc.C;
+        lstart = c->L - 3;
+    } else {
+        const int nblk = pasm::launch_border(g, c->coef<double>(lf), c->U, c->Y64, c->R64, c->partial, k, sf, c->st);
+        pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
+    }
+    for (int l = lstart; l >= 0; --l) {
         const Grid& gfl = c->lv[l + 1].g;
-        pasm::launch_restrict<double>(gfl, bsrc, c->lv[l].g, c->lv[l].B, k, gfl.plane, c->lv[l].g.plane, c->st);
-        pasm::launch_restrict<double>(gfl, csrc, c->lv[l].g, c->lv[l].C, k, gfl.plane, c->lv[l].g.plane, c->st);
+        if (csrc == bsrc + (long)gfl.plane * k) {  // b and c adjacent: one launch for both
+            pasm::launch_restrict<double>(gfl, bsrc, c->lv[l].g, c->lv[l].B, 2 * k, gfl.plane, c->lv[l].g.plane,
+                                          c->st);
+        } else {
+            pasm::launch_restrict<double>(gfl, bsrc, c->lv[l].g, c->lv[l].B, k, gfl.plane, c->lv[l].g.plane, c->st);
+            pasm::launch_restrict<double>(gfl, csrc, c->lv[l].g, c->lv[l].C, k, gfl.plane, c->lv[l].g.plane, c->st);
+        }
         bsrc = c->lv[l].B;
         csrc = c->lv[l].C;
     }
     const Grid& g0 = c->lv[0].g;
-    pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, k, c->dmv, c->st);
-    pasm::launch_dense_mv<double>(c->Qrm, N, g0, csrc, g0.plane, true, c->qq, N, false, k, c->dmv, c->st);
+    if (csrc == bsrc + (long)g0.plane * k) {
+        // p = Q^T b and q = Q^T c in one pass over Q^T (2k right-hand sides)
+        pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, 2 * k, c->dmv, c->st);
+    } else {
+        pasm::launch_dense_mv<double>(c->Qrm, N, g0, bsrc, g0.plane, true, c->pp, N, false, k, c->dmv, c->st);
+        pasm::launch_dense_mv<double>(c->Qrm, N, g0, csrc, g0.plane, true, c->qq, N, false, k, c->dmv, c->st);
+    }
     pasm::ArrowIn in{c->theta, c->group, c->pp, c->qq, c->bz, c->lam, N, c->opt.exhaustive_selection};
     pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
     pasm::launch_arrowhead(in, out, k, c->st);
@@ -854,7 +877,10 @@ void learned_rates(pasm_ctx* c) {
     const int k = c->k;
     const size_t bytes = (size_t)g.plane * k * sizeof(double);
     pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, g.plane, c->st);
-    double rate[2] = {0.0, 0.0};
+    double rate[2] = {0.0, 0.0}, ms[2] = {0.0, 0.0};
+    hipEvent_t e0, e1;
+    PASM_HIP(hipEventCreate(&e0));
+    PASM_HIP(hipEventCreate(&e1));
     for (int mode = 0; mode < 2; ++mode) {
         double* x = c->R64;
         double* scr = c->Y64;
@@ -862,17 +888,29 @@ void learned_rates(pasm_ctx* c) {
         c->learned_on = mode == 1;
         std::vector<double> n0 = resid_norms(c, x, c->F64, k);
         for (int cy = 0; cy < 3; ++cy) {
+            PASM_HIP(hipEventRecord(e0, c->st));
             one_cycle(c, x, scr, c->F64, k);
+            PASM_HIP(hipEventRecord(e1, c->st));
             const std::vector<double> n1 = resid_norms(c, x, c->F64, k);
+            float t = 0.f;
+            PASM_HIP(hipEventElapsedTime(&t, e0, e1));
+            if (cy > 0) ms[mode] += t / 2.0;  // the first cycle warms up
             for (int r = 0; r < k; ++r)
                 if (n0[r] > 0.0) rate[mode] = std::max(rate[mode], std::sqrt(n1[r] / n0[r]));
             n0 = n1;
         }
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     c->lplain_rate = rate[0];
     c->llearned_rate = rate[1];
-    // use the learned smoother only if it beats the plain one on this start
-    c->learned_on = rate[1] < rate[0];
+    c->lplain_ms = ms[0];
+    c->llearned_ms = ms[1];
+    // use the learned smoother only if it reduces the residual more per unit
+    // time than the plain one on this start (log rate per millisecond)
+    const double gp = std::log(std::max(rate[0], 1e-300)) / std::max(ms[0], 1e-6);
+    const double gl = std::log(std::max(rate[1], 1e-300)) / std::max(ms[1], 1e-6);
+    c->learned_on = rate[1] < 1.0 && gl < gp;
 }
 
 void learned_setup(pasm_ctx* c) {
@@ -1210,6 +1248,8 @@ PASM_API pasm_status pasm_learned_report(const pasm_ctx* c, pasm_learned_stats* 
     o->loss_last = c->lloss_last;
     o->plain_rate = c->lplain_rate;
     o->learned_rate = c->llearned_rate;
+    o->plain_cycle_ms = c->lplain_ms;
+    o->learned_cycle_ms = c->llearned_ms;
     o->cycles_learned = c->lcycles_learned;
     o->cycles_fallback = c->lcycles_fallback;
     return PASM_OK;
@@ -1238,6 +1278,12 @@ PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* c, double rate) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
     if (!std::isfinite(rate)) return PASM_E_INVALID;
     c->lthreshold = rate > 0.0 ? rate : 0.0;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_learned_enable(pasm_ctx* c, int enable) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    c->learned_on = enable != 0;
     return PASM_OK;
 }
 

@@ -343,18 +343,23 @@ void biterate_device(pasm_batch* b) {
             bcorrect<double>(b, bvcycle<double>(b));
         }
     }
-    // step 2: borders (A u~ and M u~ into the top level's B and C planes)
+    // step 2: borders fused with the first restriction: P^T A u~ and P^T M u~
+    // of every group land in the B and C planes one level below its top
     for (const BGroup& G : b->grp) {
         const BLevel& Lv = b->lv[G.top];
-        const long o = (long)G.a * k * Lv.g.plane;
-        pasm::launch_border(Lv.g, b->coef64_slots(G.top, G.a), G.U, Lv.B + o, Lv.C + o, G.partial, (G.b - G.a) * k,
-                            Lv.g.plane, b->st);
-        pasm::launch_reduce_pairs(G.partial, G.nblk, b->bz + 2L * G.a * k, (G.b - G.a) * k, b->st);
+        const BLevel& Lc = b->lv[G.top - 1];
+        const long o = (long)G.a * k * Lc.g.plane;
+        const int nblk = pasm::launch_border_restrict(Lv.g, b->coef64_slots(G.top, G.a), G.U, Lc.g, Lc.B + o,
+                                                      Lc.C + o, G.partial, (G.b - G.a) * k, Lv.g.plane, Lc.g.plane,
+                                                      b->st);
+        pasm::launch_reduce_pairs(G.partial, nblk, b->bz + 2L * G.a * k, (G.b - G.a) * k, b->st);
     }
-    for (int l = L - 2; l >= 0; --l) {
+    // the chain continues for the members whose top is at least two levels up
+    for (int l = L - 3; l >= 0; --l) {
         const BLevel& Lf = b->lv[l + 1];
         const BLevel& Lc = b->lv[l];
-        const int nr = Lf.count * k;
+        const int nr = b->lv[l + 2].count * k;
+        if (nr == 0) continue;
         pasm::launch_restrict<double>(Lf.g, Lf.B, Lc.g, Lc.B, nr, Lf.g.plane, Lc.g.plane, b->st);
         pasm::launch_restrict<double>(Lf.g, Lf.C, Lc.g, Lc.C, nr, Lf.g.plane, Lc.g.plane, b->st);
     }

@@ -28,6 +28,7 @@
 // negligible g is itself an eigenvalue with t = 0.
 // If u~ lies in V_H (zeta_perp <= 1e-13 zeta) the augmentation is skipped and
 // the coarse Ritz pairs are scored instead.
+#include <algorithm>
 #include <cfloat>
 
 #include "common.h"
@@ -47,9 +48,10 @@ constexpr double TIE_RTOL = 1e-12;
 // workgroups: pass 1 writes per-chunk partial sums, pass 2 adds the chunks in
 // a fixed order (deterministic, no atomics).
 // ---------------------------------------------------------------------------
-constexpr int DM_R = 64;   // rows per workgroup (one per thread)
-constexpr int DM_C = 64;   // columns per chunk
-constexpr int DM_K = 32;   // right-hand sides per workgroup
+// Shapes: WAVES wavefronts of 64 rows each per workgroup, DC columns per
+// chunk, KB right-hand sides per workgroup (the member's k rounded up to a
+// multiple of 4, at most 48) -- small coarse spaces take one-wavefront
+// workgroups and 64-column chunks, large ones four wavefronts and 128.
 
 __device__ inline long compact_to_padded(const Grid& g, int c) {
     const int i = c % g.m + 1;
@@ -61,22 +63,22 @@ __device__ inline long compact_to_padded(const Grid& g, int c) {
 // Batches: right-hand side r belongs to member r / kpm, whose matrix starts
 // mstride elements after the previous member's; a workgroup's right-hand
 // sides never straddle two members.
-template <typename T>
-__global__ __launch_bounds__(DM_R) void k_dmv_part(const T* __restrict__ Mat, int N, Grid g, const T* __restrict__ x,
-                                                   long sx, int xpad, T* __restrict__ part, int nrhs, int kpm,
-                                                   long mstride) {
-    __shared__ T xs[DM_K][DM_C];
-    const int row = blockIdx.x * DM_R + threadIdx.x;
-    const int c0 = blockIdx.y * DM_C;
-    const int zb = (kpm + DM_K - 1) / DM_K;  // workgroups per member
+template <typename T, int KB, int WAVES, int DC>
+__global__ __launch_bounds__(64 * WAVES) void k_dmv_part(const T* __restrict__ Mat, int N, Grid g,
+                                                         const T* __restrict__ x, long sx, int xpad,
+                                                         T* __restrict__ part, int nrhs, int kpm, long mstride) {
+    __shared__ T xs[KB][DC];
+    const int row = blockIdx.x * (64 * WAVES) + threadIdx.x;
+    const int c0 = blockIdx.y * DC;
+    const int zb = (kpm + KB - 1) / KB;  // workgroups per member
     const int mem = blockIdx.z / zb;
-    const int rlo = (blockIdx.z % zb) * DM_K;  // first right-hand side within the member
+    const int rlo = (blockIdx.z % zb) * KB;  // first right-hand side within the member
     const int r0 = mem * kpm + rlo;
-    const int rn = min(DM_K, kpm - rlo);       // right-hand sides of this workgroup
+    const int rn = min(KB, kpm - rlo);       // right-hand sides of this workgroup
     Mat += (long)mem * mstride;
-    const int cn = min(DM_C, N - c0);
-    for (int t = threadIdx.x; t < DM_K * DM_C; t += DM_R) {
-        const int rr = t / DM_C, cc = t % DM_C;
+    const int cn = min(DC, N - c0);
+    for (int t = threadIdx.x; t < KB * DC; t += 64 * WAVES) {
+        const int rr = t / DC, cc = t % DC;
         T v = T(0);
         if (rr < rn && cc < cn) {
             const long base = (long)(r0 + rr) * sx;
@@ -86,16 +88,18 @@ __global__ __launch_bounds__(DM_R) void k_dmv_part(const T* __restrict__ Mat, in
     }
     __syncthreads();
     if (row >= N) return;
-    T acc[DM_K];
+    T acc[KB];
 #pragma unroll
-    for (int rr = 0; rr < DM_K; ++rr) acc[rr] = T(0);
+    for (int rr = 0; rr < KB; ++rr) acc[rr] = T(0);
+    const T* mc = Mat + (long)c0 * N + row;
+#pragma unroll 4
     for (int cc = 0; cc < cn; ++cc) {
-        const T a = Mat[(long)(c0 + cc) * N + row];
+        const T a = mc[(long)cc * N];
 #pragma unroll
-        for (int rr = 0; rr < DM_K; ++rr) acc[rr] += a * xs[rr][cc];
+        for (int rr = 0; rr < KB; ++rr) acc[rr] += a * xs[rr][cc];
     }
 #pragma unroll
-    for (int rr = 0; rr < DM_K; ++rr)
+    for (int rr = 0; rr < KB; ++rr)
         if (rr < rn) part[((long)blockIdx.y * nrhs + r0 + rr) * N + row] = acc[rr];
 }
 
@@ -163,6 +167,7 @@ __device__ inline bool better(double s1, double m1, double s2, double m2, double
 }
 
 constexpr int PT = 256;
+constexpr int PP = 1024;  // threads of the preparation workgroup
 
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -170,6 +175,29 @@ __device__ inline double block_sum(double v, double* sh) {
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = sh[0] + sh[1] + sh[2] + sh[3];
+    return s;
+}
+// the same for NW wavefronts, in a fixed order
+template <int NW>
+__device__ inline double block_sum_n(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += sh[w];
+    return s;
+}
+template <int NW>
+__device__ inline double block_max_n(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = sh[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = fmax(s, sh[w]);
     return s;
 }
 
@@ -183,11 +211,13 @@ __device__ inline double block_max(double v, double* sh) {
 
 // Stage A, one block per eigenpair: scalars, g, deflation, compaction of the
 // active poles, and the best deflated candidate.
-__global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int* iwork, double* best, int nchunk) {
-    __shared__ double sh[8];
-    __shared__ int cnt[PT];
-    __shared__ double bs[PT], bm[PT];
-    __shared__ int bl[PT], bt[PT];
+__global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int* iwork, double* best, int nchunk) {
+    constexpr int NWV = PP / 64;
+    __shared__ double sh[NWV];
+    __shared__ int wtot[NWV];
+    __shared__ int cnt[PP];
+    __shared__ double bs[PP], bm[PP];
+    __shared__ int bl[PP], bt[PP];
     const int r = blockIdx.x, N = in.N;
     in.theta += (long)(r / in.kpm) * N;  // this eigenpair's member
     in.group += (long)(r / in.kpm) * N;
@@ -197,31 +227,31 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
     const double beta = in.bz[2 * r], zeta = in.bz[2 * r + 1], lp = in.lam_prev[r];
 
     double qq = 0, qp = 0, qtq = 0;
-    for (int j = threadIdx.x; j < N; j += PT) {
+    for (int j = threadIdx.x; j < N; j += PP) {
         qq += q[j] * q[j];
         qp += q[j] * p[j];
         qtq += in.theta[j] * q[j] * q[j];
     }
-    qq = block_sum(qq, sh);
-    qp = block_sum(qp, sh);
-    qtq = block_sum(qtq, sh);
+    qq = block_sum_n<NWV>(qq, sh);
+    qp = block_sum_n<NWV>(qp, sh);
+    qtq = block_sum_n<NWV>(qtq, sh);
     const double zperp = zeta - qq;
     const bool skip = !(zperp > SKIP_RTOL * zeta);
     const double sq = skip ? 0.0 : sqrt(zperp);
     const double rho = skip ? 0.0 : (beta - 2.0 * qp + qtq) / zperp;
 
     double gmax = 0.0;
-    for (int j = threadIdx.x; j < N; j += PT) {
+    for (int j = threadIdx.x; j < N; j += PP) {
         const double gj = skip ? 0.0 : (p[j] - in.theta[j] * q[j]) / sq;
         w.g[j] = gj;
         gmax = fmax(gmax, fabs(gj));
     }
-    gmax = block_max(gmax, sh);
+    gmax = block_max_n<NWV>(gmax, sh);
     const double tolz = 8.0 * EPS * fmax(fmax(fabs(in.theta[N - 1]), fabs(rho)), gmax);
     __syncthreads();
 
     // contiguous chunk of indices per thread, so the compaction keeps order
-    const int per = (N + PT - 1) / PT;
+    const int per = (N + PP - 1) / PP;
     const int j0 = threadIdx.x * per, j1 = min(N, j0 + per);
     int mine = 0;
     double ds = -1.0, dm = 0.0, dmass = 0.0;
@@ -258,25 +288,45 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
             dt = ct;
         }
     }
-    dmass = block_sum(dmass, sh);
-    cnt[threadIdx.x] = mine;
+    dmass = block_sum_n<NWV>(dmass, sh);
+    // exclusive prefix of the active counts (wavefront scans, then the
+    // wavefront totals), so that active poles keep their order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int inc = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wtot[wv] = inc;
     bs[threadIdx.x] = ds;
     bm[threadIdx.x] = dm;
     bl[threadIdx.x] = dl;
     bt[threadIdx.x] = dt;
     __syncthreads();
+    int woff = 0, acc = 0;
+    for (int t = 0; t < NWV; ++t) {
+        if (t < wv) woff += wtot[t];
+        acc += wtot[t];
+    }
+    cnt[threadIdx.x] = woff + inc - mine;
+    // best deflated candidate: pairwise reduction in a fixed tree
+    for (int h = PP / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const int o = threadIdx.x + h;
+            const bool take = bl[o] >= 0 &&
+                              (bl[threadIdx.x] < 0 || better(bs[o], bm[o], bs[threadIdx.x], bm[threadIdx.x], lp) ||
+                               (!better(bs[threadIdx.x], bm[threadIdx.x], bs[o], bm[o], lp) && bl[o] < bl[threadIdx.x]));
+            if (take) {
+                bs[threadIdx.x] = bs[o];
+                bm[threadIdx.x] = bm[o];
+                bl[threadIdx.x] = bl[o];
+                bt[threadIdx.x] = bt[o];
+            }
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int t = 0; t < PT; ++t) {
-            const int c = cnt[t];
-            cnt[t] = acc;
-            acc += c;
-        }
-        int bi = -1;
-        for (int t = 0; t < PT; ++t) {
-            if (bl[t] < 0) continue;
-            if (bi < 0 || better(bs[t], bm[t], bs[bi], bm[bi], lp)) bi = t;
-        }
+        const int bi = bl[0] >= 0 ? 0 : -1;
         w.sc[S_NA] = skip ? -1.0 : (double)acc;
         w.sc[S_RHO] = rho;
         w.sc[S_SQ] = sq;
@@ -321,8 +371,8 @@ __global__ __launch_bounds__(PT) void k_arrow_prep(ArrowIn in, double* work, int
     // |z| over the active poles (a block reduction, fixed order)
     const int nact = skip ? 0 : (int)w.sc[S_NA];
     double zn2 = 0.0;
-    for (int t = threadIdx.x; t < nact; t += PT) zn2 += w.z[t] * w.z[t];
-    zn2 = block_sum(zn2, sh);
+    for (int t = threadIdx.x; t < nact; t += PP) zn2 += w.z[t] * w.z[t];
+    zn2 = block_sum_n<NWV>(zn2, sh);
     if (threadIdx.x == 0 && nact > 0) {
         const double zn = sqrt(zn2);
         w.sc[S_LO] = fmin(w.d[0], rho) - zn;
@@ -344,6 +394,7 @@ constexpr int RW = 64;          // lanes per root
 constexpr int RWAVES = 4;       // wavefronts per block
 constexpr int RPB = 16;         // roots per block (each wavefront takes 4 in turn)
 constexpr int LDS_POLES = 2600; // poles kept in LDS up to this count
+constexpr int LDS_POLES_BIG = 6400;  // ... for the one-workgroup-per-eigenpair NEAR pass (150 KiB of LDS)
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -375,10 +426,11 @@ __device__ inline int near_base(const double* d, int na, double lp) {
 // for the uncomputed roots (zeta minus the computed squared scores), no other
 // root can win, ties included.  NEAR = false: all roots, skipped when the
 // NEAR pass certified its winner.
-template <bool LDS, bool NEAR>
-__global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* work, int* iwork, double* best,
-                                                            int nchunk) {
-    __shared__ double sd[LDS ? LDS_POLES : 1], sz[LDS ? LDS_POLES : 1], sqa[LDS ? LDS_POLES : 1];
+template <int LDSN, bool NEAR, int NW = RWAVES>
+__global__ __launch_bounds__(RW* NW) void k_arrow_roots(ArrowIn in, double* work, int* iwork, double* best,
+                                                        int nchunk) {
+    constexpr bool LDS = LDSN > 0;
+    __shared__ double sd[LDS ? LDSN : 1], sz[LDS ? LDSN : 1], sqa[LDS ? LDSN : 1];
     __shared__ double ss[RPB], sm[RPB];
     const int r = blockIdx.x, N = in.N;
     WS w = ws_of(work, iwork, best, N, nchunk, r);
@@ -390,7 +442,7 @@ __global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* 
     const double* z = w.z;
     const double* qa = w.qa;
     if (LDS) {
-        for (int a = threadIdx.x; a < na; a += RW * RWAVES) {
+        for (int a = threadIdx.x; a < na; a += RW * NW) {
             sd[a] = w.d[a];
             sz[a] = w.z[a];
             sqa[a] = w.qa[a];
@@ -401,7 +453,7 @@ __global__ __launch_bounds__(RW* RWAVES) void k_arrow_roots(ArrowIn in, double* 
         qa = sqa;
     }
     const int base = NEAR ? (na > 0 ? near_base(d, na, lp) : 0) : blockIdx.y * RPB;
-    for (int slot = wave; slot < RPB; slot += RWAVES) {
+    for (int slot = wave; slot < RPB; slot += NW) {
         const int root = base + slot;
         double score = -1.0, mu = 0.0;
         if (na >= 0 && root <= na) {
@@ -652,18 +704,44 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
 
 }  // namespace
 
+constexpr int kDmvBigN = 2048;  // coarse spaces from this size take the large shape
+
+inline int dmv_chunk(int N) { return N >= kDmvBigN ? 128 : 64; }
+
+template <typename T, int WAVES, int DC>
+void dmv_part_launch(int kb, const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded, T* part,
+                     int nrhs, int kpm, long mstride, hipStream_t st) {
+    const int nchunk = (N + DC - 1) / DC;
+    const int zb = (kpm + kb - 1) / kb;
+    dim3 grid((N + 64 * WAVES - 1) / (64 * WAVES), nchunk, (nrhs / kpm) * zb);
+    dim3 blk(64 * WAVES);
+#define PASM_DMV(KB)                                                                                            \
+    case KB:                                                                                                    \
+        hipLaunchKernelGGL((k_dmv_part<T, KB, WAVES, DC>), grid, blk, 0, st, Mat, N, g, x, sx, (int)x_padded,   \
+                           part, nrhs, kpm, mstride);                                                           \
+        break;
+    switch (kb) {
+        PASM_DMV(4) PASM_DMV(8) PASM_DMV(12) PASM_DMV(16) PASM_DMV(20) PASM_DMV(24) PASM_DMV(28) PASM_DMV(32)
+        PASM_DMV(36) PASM_DMV(40) PASM_DMV(44) PASM_DMV(48)
+        default: throw Error(PASM_E_INVALID, "dense products: bad block width");
+    }
+#undef PASM_DMV
+    PASM_CHECK_LAUNCH();
+}
+
 template <typename T>
 void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded, T* y, long sy,
                      bool y_padded, int nrhs, void* work, hipStream_t st, int kpm, long mstride) {
     if (kpm <= 0) kpm = nrhs;
     if (nrhs % kpm != 0) throw Error(PASM_E_INVALID, "dense products: right-hand sides not a multiple per member");
-    const int nchunk = (N + DM_C - 1) / DM_C;
+    const int kb = std::min(48, (kpm + 3) / 4 * 4);
+    const int DC = dmv_chunk(N);
+    const int nchunk = (N + DC - 1) / DC;
     T* part = static_cast<T*>(work);
-    const int zb = (kpm + DM_K - 1) / DM_K;
-    dim3 g1((N + DM_R - 1) / DM_R, nchunk, (nrhs / kpm) * zb);
-    hipLaunchKernelGGL((k_dmv_part<T>), g1, dim3(DM_R), 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs, kpm,
-                       mstride);
-    PASM_CHECK_LAUNCH();
+    if (N >= kDmvBigN)
+        dmv_part_launch<T, 4, 128>(kb, Mat, N, g, x, sx, x_padded, part, nrhs, kpm, mstride, st);
+    else
+        dmv_part_launch<T, 1, 64>(kb, Mat, N, g, x, sx, x_padded, part, nrhs, kpm, mstride, st);
     hipLaunchKernelGGL((k_dmv_sum<T>), dim3((N + 255) / 256, nrhs), dim3(256), 0, st, N, nchunk, part, nrhs, g, y, sy,
                        (int)y_padded);
     PASM_CHECK_LAUNCH();
@@ -674,7 +752,7 @@ template void launch_dense_mv<float>(const float*, int, const Grid&, const float
                                      int, void*, hipStream_t, int, long);
 
 size_t dense_mv_workspace_bytes(int N, int nrhs) {
-    return sizeof(double) * (size_t)((N + DM_C - 1) / DM_C) * nrhs * N;
+    return sizeof(double) * (size_t)((N + 63) / 64) * nrhs * N;
 }
 
 long arrow_work_doubles(int N, int k) { return ws_doubles(N) * (long)k; }
@@ -687,19 +765,27 @@ void launch_arrowhead(const ArrowIn& in0, const ArrowOut& out, int k, hipStream_
     double* work = out.work;
     int* iwork = reinterpret_cast<int*>(work + arrow_work_doubles(in.N, k));
     double* best = reinterpret_cast<double*>(iwork + (long)in.N * k + ((long)in.N * k & 1));
-    hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PT), 0, st, in, work, iwork, best, nchunk);
+    hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PP), 0, st, in, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();
-    if (in.N <= LDS_POLES) {
-        hipLaunchKernelGGL((k_arrow_roots<true, true>), dim3(k, 1), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
-                           nchunk);
-        hipLaunchKernelGGL((k_arrow_roots<true, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork,
+    // NEAR pass: one workgroup per eigenpair and one wavefront per root,
+    // poles in LDS up to 6400 of them
+    if (in.N <= LDS_POLES)
+        hipLaunchKernelGGL((k_arrow_roots<LDS_POLES, true, RPB>), dim3(k, 1), dim3(RW * RPB), 0, st, in, work, iwork,
                            best, nchunk);
-    } else {
-        hipLaunchKernelGGL((k_arrow_roots<false, true>), dim3(k, 1), dim3(RW * RWAVES), 0, st, in, work, iwork, best,
+    else if (in.N <= LDS_POLES_BIG)
+        hipLaunchKernelGGL((k_arrow_roots<LDS_POLES_BIG, true, RPB>), dim3(k, 1), dim3(RW * RPB), 0, st, in, work,
+                           iwork, best, nchunk);
+    else
+        hipLaunchKernelGGL((k_arrow_roots<0, true, RPB>), dim3(k, 1), dim3(RW * RPB), 0, st, in, work, iwork, best,
                            nchunk);
-        hipLaunchKernelGGL((k_arrow_roots<false, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork,
+    // full pass (its workgroups return at once when the NEAR pass certified
+    // its winner); many workgroups per eigenpair, so the smaller LDS copy
+    if (in.N <= LDS_POLES)
+        hipLaunchKernelGGL((k_arrow_roots<LDS_POLES, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work,
+                           iwork, best, nchunk);
+    else
+        hipLaunchKernelGGL((k_arrow_roots<0, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork,
                            best, nchunk);
-    }
     PASM_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_arrow_final, dim3(k), dim3(PT), 0, st, in, out, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();

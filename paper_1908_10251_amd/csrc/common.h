@@ -190,6 +190,12 @@ void launch_add_correction(const double* e, double* u, long n, hipStream_t st);
 int launch_border(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
                   double* partial, int nrhs, long stride, hipStream_t st);
 
+// 2D borders fused with the restriction to the next coarser grid gc:
+// bc = P^T A u, cc = P^T M u on gc, partial as for launch_border (blocks over
+// the coarse grid).  Returns the number of blocks per right-hand side.
+int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
+                           double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st);
+
 // out[r][0..1] = sums of partial[r][0..nblk)[0..1] in a fixed order.
 void launch_reduce_pairs(const double* partial, int nblk, double* out, int nrhs, hipStream_t st);
 

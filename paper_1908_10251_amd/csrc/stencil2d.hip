@@ -14,6 +14,8 @@
 //
 // Launch shape: 64 x 4 threads, one wavefront per 64 consecutive nodes of a
 // row (coalesced, 128-byte aligned rows), grid.z = right-hand side.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pasm {
@@ -116,36 +118,31 @@ __global__ __launch_bounds__(BX* BY) void k_smooth(Grid g, Coef<T> cg, const T* 
 template <typename T, int KIND, int S, int ROWS>
 __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> cg, const T* __restrict__ x0,
                                                       const T* __restrict__ f, T* __restrict__ out, long stride,
-                                                      SmoothSteps st, int x_zero) {
+                                                      SmoothSteps st, int x_zero, int share, int rb) {
     constexpr int W = 64, HH = 4 * ROWS, TX = W - 2 * S, TY = HH - 2 * S;
     constexpr bool CONST = KIND == 0;
     constexpr bool GEN = KIND == 2;
     __shared__ T sa[W * HH], sb[W * HH];
     __shared__ T swx[CONST ? 1 : W * HH], swy[CONST ? 1 : W * HH];
     __shared__ T sd[GEN ? W * HH : 1], swne[GEN ? W * HH : 1];
+    // this workgroup's right-hand sides [r0, r1): consecutive ones sharing
+    // one coefficient array, which is staged in LDS once for all of them
+    const int zb = (share + rb - 1) / rb;
+    const int grp = blockIdx.z / zb;
+    const int r0 = grp * share + (blockIdx.z % zb) * rb;
+    const int r1 = min(r0 + rb, (grp + 1) * share);
     T bsc;
-    const Coef<T> c = member_coef(cg, blockIdx.z, bsc);
+    const Coef<T> c = member_coef(cg, r0, bsc);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int i = blockIdx.x * TX + 1 - S + tx;  // global column of this thread
     const int jb = blockIdx.y * TY + 1 - S;      // global row of LDS row 0
-    const long off = (long)blockIdx.z * stride;
-    T fr[ROWS], xc[ROWS], xp[ROWS];
-    bool upd[ROWS];
+    bool upd[ROWS], inn[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int ly = ty + 4 * r, j = jb + ly;
         const bool inner = i >= 1 && i <= g.m && j >= 1 && j <= g.m;
+        inn[r] = inner;
         upd[r] = inner && tx > 0 && tx < W - 1 && ly > 0 && ly < HH - 1;
-        T xv = T(0), fv = T(0);
-        if (inner) {
-            const long id = off + g.idx(i, j);
-            fv = f[id];
-            if (!x_zero) xv = x0[id];
-        }
-        fr[r] = fv;
-        xc[r] = xv;
-        xp[r] = xv;
-        sa[ly * W + tx] = xv;
         if (!CONST) {
             const bool stored = i >= 0 && i <= g.n && j >= 0 && j <= g.n;
             swx[ly * W + tx] = (stored && i < g.n) ? c.wx[g.idx(i, j)] : T(0);
@@ -156,53 +153,86 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> cg, const 
             }
         }
     }
-    __syncthreads();
     const T invD0 = T(1) / (T(4) * c.w0);
-    T* cur = sa;
-    T* nxt = sb;
+    // reciprocal diagonal of the own nodes, once for all right-hand sides
+    T idg[ROWS];
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-        const T a = (T)st.a[t], b = (T)st.b[t] * bsc;
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int p = (ty + 4 * r) * W + tx;
-            T v = xc[r];
-            if (upd[r]) {
-                const T xe = cur[p + 1], xw = cur[p - 1], xn = cur[p + W], xs = cur[p - W];
-                if (CONST) {
-                    const T Ax = c.w0 * (T(4) * v - xe - xw - xn - xs);
-                    v = v + b * (fr[r] - Ax) * invD0;
-                } else if (!GEN) {
-                    const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
-                    const T D = we + ww + wn + ws;
-                    const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs;
-                    v = v + b * (fr[r] - Ax) / D;
-                } else {
-                    const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
-                    const T wa = swne[p], wb = swne[p - W - 1];
-                    const T D = sd[p];
-                    const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs - wa * cur[p + W + 1] -
-                                 wb * cur[p - W - 1];
-                    v = v + b * (fr[r] - Ax) / D;
-                }
-                if (a != T(0)) v += a * (xc[r] - xp[r]);
-            }
-            xp[r] = xc[r];
-            xc[r] = v;
-            nxt[p] = v;
-        }
-        __syncthreads();
-        T* tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-    }
-    if (tx < S || tx >= W - S) return;
+    for (int r = 0; r < ROWS; ++r) idg[r] = invD0;
+    __syncthreads();  // coefficient tiles complete before they are read
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
-        const int ly = ty + 4 * r, j = jb + ly;
-        if (ly < S || ly >= HH - S) continue;
-        if (i < 1 || i > g.m || j < 1 || j > g.m) continue;
-        out[off + g.idx(i, j)] = xc[r];
+        const int p = (ty + 4 * r) * W + tx;
+        if (!CONST && upd[r]) {
+            const T D = GEN ? sd[p] : (swx[p] + swx[p - 1] + swy[p] + swy[p - W]);
+            idg[r] = T(1) / D;
+        }
+    }
+    for (int rhs = r0; rhs < r1; ++rhs) {
+        const long off = (long)rhs * stride;
+        T fr[ROWS], xc[ROWS], xp[ROWS];
+        __syncthreads();  // the previous right-hand side is done with sa / sb
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int ly = ty + 4 * r, j = jb + ly;
+            T xv = T(0), fv = T(0);
+            if (inn[r]) {
+                const long id = off + g.idx(i, j);
+                fv = f[id];
+                if (!x_zero) xv = x0[id];
+            }
+            fr[r] = fv;
+            xc[r] = xv;
+            xp[r] = xv;
+            sa[ly * W + tx] = xv;
+        }
+        __syncthreads();
+        T* cur = sa;
+        T* nxt = sb;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const T a = (T)st.a[t], b = (T)st.b[t] * bsc;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int p = (ty + 4 * r) * W + tx;
+                T v = xc[r];
+                if (upd[r]) {
+                    const T xe = cur[p + 1], xw = cur[p - 1], xn = cur[p + W], xs = cur[p - W];
+                    if (CONST) {
+                        const T Ax = c.w0 * (T(4) * v - xe - xw - xn - xs);
+                        v = v + b * (fr[r] - Ax) * invD0;
+                    } else if (!GEN) {
+                        const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
+                        const T D = we + ww + wn + ws;
+                        const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs;
+                        v = v + b * (fr[r] - Ax) * idg[r];
+                    } else {
+                        const T we = swx[p], ww = swx[p - 1], wn = swy[p], ws = swy[p - W];
+                        const T wa = swne[p], wb = swne[p - W - 1];
+                        const T D = sd[p];
+                        const T Ax = D * v - we * xe - ww * xw - wn * xn - ws * xs - wa * cur[p + W + 1] -
+                                     wb * cur[p - W - 1];
+                        v = v + b * (fr[r] - Ax) * idg[r];
+                    }
+                    if (a != T(0)) v += a * (xc[r] - xp[r]);
+                }
+                xp[r] = xc[r];
+                xc[r] = v;
+                nxt[p] = v;
+            }
+            __syncthreads();
+            T* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+        if (tx >= S && tx < W - S) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int ly = ty + 4 * r, j = jb + ly;
+                if (ly < S || ly >= HH - S) continue;
+                if (i < 1 || i > g.m || j < 1 || j > g.m) continue;
+                out[off + g.idx(i, j)] = xc[r];
+            }
+        }
     }
 }
 
@@ -368,6 +398,58 @@ __global__ __launch_bounds__(BX* BY) void k_border(Grid g, Coef<double> cg, cons
     }
 }
 
+// Borders fused with the first restriction: each thread owns coarse node
+// (I, J) of the next coarser grid (I, J = 1 .. nc, the last row/column only
+// for the sums), computes A u and M u at the seven fine nodes whose
+// interpolation reaches (I, J), writes b_c = P^T A u and c_c = P^T M u there,
+// and adds u.Au, u.Mu over the four fine nodes (2I - a, 2J - b), a, b in
+// {0, 1}, that it owns, so every fine node is counted once.
+template <int KIND>
+__global__ __launch_bounds__(BX* BY) void k_border_restrict(Grid g, Coef<double> cg, const double* __restrict__ u,
+                                                            Grid gc, double* __restrict__ bc,
+                                                            double* __restrict__ cc, double* __restrict__ partial,
+                                                            long stride, long sc) {
+    __shared__ double sh[8];
+    const int I = blockIdx.x * BX + threadIdx.x + 1;
+    const int J = blockIdx.y * BY + threadIdx.y + 1;
+    double bs;
+    const Coef<double> c = member_coef(cg, blockIdx.z, bs);
+    const double* ur = u + (long)blockIdx.z * stride;
+    double ua = 0.0, um = 0.0;
+    if (I <= gc.n && J <= gc.n) {
+        constexpr int off[7][2] = {{0, 0}, {-1, 0}, {0, -1}, {-1, -1}, {1, 0}, {0, 1}, {1, 1}};
+        double rb = 0.0, rc = 0.0;
+#pragma unroll
+        for (int o = 0; o < 7; ++o) {
+            const int i = 2 * I + off[o][0], j = 2 * J + off[o][1];
+            if (i < 1 || j < 1 || i > g.m || j > g.m) continue;
+            const long id = g.idx(i, j);
+            double Ax, D;
+            Stiff2<double, KIND>::apply(g, c, ur, id, Ax, D);
+            const double Mx = mass2(g, ur, id);
+            const double w = o == 0 ? 1.0 : 0.5;
+            rb += w * Ax;
+            rc += w * Mx;
+            if (o < 4) {  // owned: offsets (0,0), (-1,0), (0,-1), (-1,-1)
+                ua += ur[id] * Ax;
+                um += ur[id] * Mx;
+            }
+        }
+        if (I <= gc.m && J <= gc.m) {
+            const long cid = (long)blockIdx.z * sc + gc.idx(I, J);
+            bc[cid] = rb;
+            cc[cid] = rc;
+        }
+    }
+    block_sum2(ua, um, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const long nblk = (long)gridDim.x * gridDim.y;
+        const long b = (long)blockIdx.z * nblk + blockIdx.y * gridDim.x + blockIdx.x;
+        partial[2 * b] = ua;
+        partial[2 * b + 1] = um;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__ partial, int nblk,
                                                       double* __restrict__ out) {
     __shared__ double sh[8];
@@ -473,6 +555,8 @@ constexpr size_t fused_lds(int kind, size_t elem, int rows) {
     return (2 + (kind == 0 ? 0 : kind == 1 ? 2 : 4)) * (size_t)64 * 4 * rows * elem;
 }
 constexpr size_t kLdsLimit = 65536;
+// right-hand sides a fused workgroup smooths with one staged coefficient tile
+constexpr int kFusedRhsPerBlock = 8;
 
 size_t fused_lds_bytes(int kind, size_t elem, int rows) { return fused_lds(kind, elem, rows); }
 
@@ -481,9 +565,18 @@ void fused_launch(const Grid& g, const Coef<T>& c, const T* x0, const T* f, T* o
                   const SmoothSteps& ss, bool x_zero, hipStream_t st) {
     if constexpr (fused_lds(KIND, sizeof(T), ROWS) <= kLdsLimit && 4 * ROWS - 2 * S > 0) {
         constexpr int TX = 64 - 2 * S, TY = 4 * ROWS - 2 * S;
-        dim3 grid((g.m + TX - 1) / TX, (g.m + TY - 1) / TY, nrhs);
+        // right-hand sides that share coefficients: all of them for one
+        // problem, a member's for a batch; constant coefficients need no sharing
+        int share = (KIND == 0) ? 1 : (c.ms == 0 ? nrhs : c.kpm);
+        if (share < 1 || nrhs % share != 0) share = 1;
+        // group right-hand sides only as far as the grid keeps ~2048 workgroups
+        const long tiles = (long)((g.m + TX - 1) / TX) * ((g.m + TY - 1) / TY);
+        const int rb = (int)std::max<long>(1, std::min<long>({(long)share, (long)kFusedRhsPerBlock,
+                                                              tiles * nrhs / 2048}));
+        const int zb = (share + rb - 1) / rb;
+        dim3 grid((g.m + TX - 1) / TX, (g.m + TY - 1) / TY, (nrhs / share) * zb);
         hipLaunchKernelGGL((k_smooth_fused<T, KIND, S, ROWS>), grid, dim3(64, 4), 0, st, g, c, x0, f, out, stride,
-                           ss, (int)x_zero);
+                           ss, (int)x_zero, share, rb);
         PASM_CHECK_LAUNCH();
     } else {
         throw Error(PASM_E_INVALID, "fused smoothing tile too large for LDS or too short for the steps");
@@ -628,6 +721,19 @@ int launch_border(const Grid& g, const Coef<double>& c, const double* u, double*
         case 0: hipLaunchKernelGGL(k_border<0>, grid, blk, 0, st, g, c, u, au, mu, partial, stride); break;
         case 1: hipLaunchKernelGGL(k_border<1>, grid, blk, 0, st, g, c, u, au, mu, partial, stride); break;
         default: hipLaunchKernelGGL(k_border<2>, grid, blk, 0, st, g, c, u, au, mu, partial, stride); break;
+    }
+    PASM_CHECK_LAUNCH();
+    return (int)(grid.x * grid.y);
+}
+
+int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
+                           double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st) {
+    if (g.dim != 2 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 2D, ratio 2");
+    dim3 grid = grid_for(gc.n, gc.n, nrhs), blk(BX, BY);
+    switch (coef_kind(c)) {
+        case 0: hipLaunchKernelGGL(k_border_restrict<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
+        case 1: hipLaunchKernelGGL(k_border_restrict<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
+        default: hipLaunchKernelGGL(k_border_restrict<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
     }
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y);

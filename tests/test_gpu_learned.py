@@ -100,6 +100,8 @@ def test_learned_solve_reaches_discrete_eigenvalues(precision):
         rep0 = P.pasm_learned_report(s.ctx)
         _say(f"  set-up: {rep0}")
         assert rep0["train_steps"] > 0 and rep0["loss_last"] < rep0["loss_first"]
+        assert 0 < rep0["learned_rate"] < 1 and 0 < rep0["plain_rate"] < 1
+        P.pasm_learned_enable(s.ctx, True)  # whatever the speed test decided
         s.solve(allow_notconv=True)
         lam, _ = s.eigenpairs(False)
         rep = P.pasm_learned_report(s.ctx)
@@ -107,6 +109,7 @@ def test_learned_solve_reaches_discrete_eigenvalues(precision):
         assert rep["cycles_learned"] + rep["cycles_fallback"] > 0 or not rep["enabled"]
     tol = 1e-8 if precision == P.PASM_MIXED else 1e-10
     assert np.max(np.abs(np.sort(lam) - w) / w) < tol
+    assert rep["cycles_learned"] > 0
 
 
 def test_bad_weights_fall_back_to_jacobi():
@@ -120,12 +123,12 @@ def test_bad_weights_fall_back_to_jacobi():
         W[0, 0, 13], W[0, 1, 13] = 1.0, -1.0
         W[1, 0, 13], W[1, 1, 13] = -1.5, 1.5
         P.pasm_learned_set_weights(s.ctx, W)
+        P.pasm_learned_enable(s.ctx, True)
         before = P.pasm_learned_report(s.ctx)
         s.solve(allow_notconv=True)
         lam, _ = s.eigenpairs(False)
         rep = P.pasm_learned_report(s.ctx)
-    if before["enabled"]:
-        assert rep["cycles_fallback"] > before["cycles_fallback"]
+    assert rep["cycles_fallback"] > before["cycles_fallback"]
     assert np.max(np.abs(np.sort(lam) - w) / w) < 1e-8
 
 
@@ -141,6 +144,7 @@ def test_learned_vcycle_matches_oracle():
     x0 = rng.standard_normal((2, N))
     with P.Solver(3, 1 / NC, 1 / NF, K, opts=_opts(P.PASM_FP64)) as s:
         W = P.pasm_learned_weights(s.ctx).astype(np.float64)
+        P.pasm_learned_enable(s.ctx, True)
         before = P.pasm_learned_report(s.ctx)
         xg = _t(x0)
         P.pasm_vcycle(s.ctx, _t(f), xg, 1)
