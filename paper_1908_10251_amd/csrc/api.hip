@@ -809,9 +809,8 @@ constexpr int kLearnedSetupSteps = 160;
 constexpr double kLearnedLr = 2e-3;
 
 void learned_pack(pasm_ctx* c) {
-    unsigned long long ops[256];
-    pasm::learned_pack_taps_by_channel(c->lw.data(), ops);
-    pasm::learned_pack_channels_by_tap(c->lw.data() + 16 * 27, ops + 128);
+    unsigned long long ops[pasm::kLearnedStepOps];
+    pasm::learned_pack_step(c->lw.data(), ops);
     PASM_HIP(hipMemcpyAsync(c->lops, ops, sizeof(ops), hipMemcpyHostToDevice, c->st));
     PASM_HIP(hipStreamSynchronize(c->st));
 }
@@ -931,7 +930,7 @@ void learned_setup(pasm_ctx* c) {
     c->lw[1 * 27 + 13] = -1.f;
     c->lw[16 * 27 + 0 * 27 + 13] = (float)omega;
     c->lw[16 * 27 + 1 * 27 + 13] = (float)-omega;
-    c->lops = c->alloc<unsigned long long>(256);
+    c->lops = c->alloc<unsigned long long>(pasm::kLearnedStepOps);
     const Grid& g = c->gf();
     c->Xb = c->alloc<double>((size_t)g.plane * c->k);
     const long nb = (g.interior() + 255) / 256;

@@ -280,8 +280,10 @@ size_t arrow_workspace_bytes(int N, int k);
 // Operand words of the two weight arrays W[16][27] (see learned3d.hip).
 void learned_pack_taps_by_channel(const float* W, unsigned long long* out);   // 128 words
 void learned_pack_channels_by_tap(const float* W, unsigned long long* out);   // 128 words
-// out = x + N((f - A x) / D) (x treated as zero when x_zero); ops = 256 words
-// (layer-1 operand, then layer-2 operand).  out must not alias x or f.
+void learned_pack_step(const float* W, unsigned long long* out);            // kLearnedStepOps words
+constexpr int kLearnedStepOps = 320;
+// out = x + N((f - A x) / D) (x treated as zero when x_zero); ops =
+// learned_pack_step(W1 W2).  out must not alias x or f.
 template <typename T>
 void launch_learned_step(const Grid& g, T w0, const T* x, const T* f, T* out, int nrhs, long stride,
                          const unsigned long long* ops, bool x_zero, hipStream_t st);

@@ -15,10 +15,14 @@
 //
 // Inference (k_learned_step): a workgroup owns a 16 x 16 column of output
 // nodes and marches in z.  Per z slice it loads x with a halo of 3 and f with
-// a halo of 2, forms rho on 20 x 20 nodes, the hidden layer on 18 x 18 nodes
-// (layer 1: M = nodes, K = taps, N = channels), then Y[u][t] = sum_c h[u][c]
-// W2[c][t] (layer 2: M = nodes, K = channels, N = taps), and gathers
-// N(rho)(v) = sum_t Y[v + t][t] into three running output slices.
+// a halo of 2 (one slice ahead, in registers), forms rho on 20 x 20 nodes
+// (each thread keeps the last two rho values of its nodes, so it writes the
+// z triplet of the slice below as one 8-byte word), the hidden layer on
+// 18 x 18 nodes (layer 1: M = channels, K = z triplets of the 9 in-plane
+// offsets, N = nodes; its result stays in registers as the next operand),
+// then Y[u][t] = sum_c h[u][c] W2[c][t] (layer 2: M = nodes, K = channels,
+// N = taps), and gathers N(rho)(v) = sum_t Y[v + t][t] into three running
+// output sums held in registers.
 //
 // Training: loss L = (1/S) sum_s ||r_s - A N(rho_s)||^2 / ||r_s||^2 over
 // residual samples; the backward contractions (hidden gradient: M = nodes,
@@ -64,22 +68,28 @@ constexpr int RT = OT + 4;        // rho tile edge (halo 2)
 constexpr int HT = OT + 2;        // hidden tile edge (halo 1)
 constexpr int HN = HT * HT;       // hidden nodes per slice (324)
 constexpr int HB = (HN + 15) / 16;  // 16-node blocks (21)
+constexpr int YS = 340;           // Y row stride (taps x nodes; >= 16 HB, 4-aligned, bank-spread)
 constexpr int LT = 256;           // threads per workgroup
 
-// ops: [0..127] layer-1 operand (2 K-steps x 64 lanes, 4 bf16 each as 64-bit
-// words), [128..255] layer-2 operand (2 N-blocks x 64 lanes) -- both packed
-// on the host from W1, W2.
+// ops: [0..191] layer-1 operand (3 K-steps x 64 lanes, as the A operand,
+// M = channels), [192..319] layer-2 operand (2 N-blocks x 64 lanes) -- both
+// packed on the host from W1, W2 (learned_pack_step).
+//
+// Layer 1 runs as D[c][v] = sum_k W1'[c][k] P[k][v] with the K index split
+// into 12 groups of 4: group G < 9 is the in-plane offset (dx, dy) =
+// (G % 3 - 1, G / 3 - 1) and slot j < 3 of the group the z offset j - 1, so
+// the four values a lane feeds per group are one 8-byte word of the "z
+// triplet" tile (rho at z - 1, z, z + 1 and a zero).  Its result D holds in
+// lane l channels 4 (l / 16) + j of node l % 16 -- exactly the A operand of
+// the layer-2 product, so the hidden layer never leaves the registers.
 template <typename T>
 __global__ __launch_bounds__(LT) void k_learned_step(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
                                                      T* __restrict__ out, long stride,
                                                      const unsigned long long* __restrict__ ops, int zseg,
                                                      int x_zero) {
-    __shared__ T xs[4][XT * XT];
-    __shared__ T fs[RT * RT];
-    __shared__ unsigned short rs[3][RT * RT];
-    __shared__ unsigned short hs[HB * 16 * 16];
-    __shared__ float ys[HB * 16 * 16];
-    __shared__ float acc[3][OT * OT];
+    __shared__ T xs[4][XT * XT];     // x slices, ring of 4
+    __shared__ bf16x4 tri[RT * RT];  // rho z triplets around the hidden slice
+    __shared__ __attribute__((aligned(16))) float ys[27 * YS];  // Y[t][u] of the hidden slice
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles = (g.m + OT - 1) / OT;
@@ -92,138 +102,159 @@ __global__ __launch_bounds__(LT) void k_learned_step(Grid g, T w0, const T* __re
     const int i0 = bx * OT + 1, j0 = by * OT + 1;  // first output node (interior indices from 1)
     const T invD = T(1) / (T(6) * w0);
 
-    bf16x4 b1[2], b2[2];
-    {
-        const unsigned long long* o = ops;
-        for (int s = 0; s < 2; ++s) {
-            const unsigned long long w = o[s * 64 + lane];
-            __builtin_memcpy(&b1[s], &w, 8);
-            const unsigned long long v = o[128 + s * 64 + lane];
-            __builtin_memcpy(&b2[s], &v, 8);
-        }
+    bf16x4 w1[3], w2[2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const unsigned long long w = ops[s * 64 + lane];
+        __builtin_memcpy(&w1[s], &w, 8);
     }
-    for (int t = tid; t < 3 * OT * OT; t += LT) (&acc[0][0])[t] = 0.f;
-    for (int t = tid; t < 3 * RT * RT; t += LT) (&rs[0][0])[t] = 0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const unsigned long long w = ops[192 + s * 64 + lane];
+        __builtin_memcpy(&w2[s], &w, 8);
+    }
+    // this lane's triplet offsets in the rho tile for its three K groups
+    int toff[3];
+    bool tuse[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int G = 4 * s + (lane >> 4);
+        tuse[s] = G < 9;
+        toff[s] = tuse[s] ? (G / 3) * RT + (G % 3) : 0;  // (1 + dy) RT + (1 + dx)
+    }
 
-    auto load_x = [&](int l) {  // x slice l (grid node index) into ring slot l & 3
-        T* d = xs[l & 3];
-        for (int t = tid; t < XT * XT; t += LT) {
+    // Global loads run one slice ahead in registers (px, pf), so their
+    // latency overlaps the previous slice's work instead of stalling it.
+    constexpr int XPT = (XT * XT + LT - 1) / LT, FPT = (RT * RT + LT - 1) / LT;
+    T px[XPT], pf[FPT];
+    auto fetch_x = [&](int l) {  // x slice l (grid node index)
+#pragma unroll
+        for (int e = 0; e < XPT; ++e) {
+            const int t = tid + e * LT;
             const int a = t % XT, b = t / XT;
             const int i = i0 - 3 + a, j = j0 - 3 + b;
             T v = T(0);
-            if (!x_zero && l >= 0 && l <= g.n && i >= 0 && i <= g.n && j >= 0 && j <= g.n) v = xr[g.idx(i, j, l)];
-            d[t] = v;
+            if (t < XT * XT && !x_zero && l >= 0 && l <= g.n && i >= 0 && i <= g.n && j >= 0 && j <= g.n)
+                v = xr[g.idx(i, j, l)];
+            px[e] = v;
         }
     };
-    load_x(z0 - 3);
-    load_x(z0 - 2);
-    __syncthreads();
-    for (int q = z0 - 2; q <= z1 + 1; ++q) {
-        // 1. x slice q + 1, f slice q
-        load_x(q + 1);
-        for (int t = tid; t < RT * RT; t += LT) {
+    auto fetch_f = [&](int l) {  // f slice l, interior nodes of the rho tile
+#pragma unroll
+        for (int e = 0; e < FPT; ++e) {
+            const int t = tid + e * LT;
             const int a = t % RT, b = t / RT;
             const int i = i0 - 2 + a, j = j0 - 2 + b;
             T v = T(0);
-            if (q >= 1 && q <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) v = fr[g.idx(i, j, q)];
-            fs[t] = v;
+            if (t < RT * RT && l >= 1 && l <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) v = fr[g.idx(i, j, l)];
+            pf[e] = v;
         }
+    };
+    auto put_x = [&](int l) {
+#pragma unroll
+        for (int e = 0; e < XPT; ++e)
+            if (tid + e * LT < XT * XT) xs[l & 3][tid + e * LT] = px[e];
+    };
+    fetch_x(z0 - 3);
+    put_x(z0 - 3);
+    fetch_x(z0 - 2);
+    put_x(z0 - 2);
+    fetch_x(z0 - 1);
+    fetch_f(z0 - 2);
+    const int ox = tid % OT, oy = tid / OT;  // this thread's output node (LT == OT * OT)
+    unsigned short r1[FPT], r2[FPT];         // bf16 rho of this thread's rho nodes, slices q - 1, q - 2
+#pragma unroll
+    for (int e = 0; e < FPT; ++e) r1[e] = r2[e] = 0;
+    float cm1 = 0.f, c0 = 0.f, cp1 = 0.f;  // running output sums, slices p - 1, p, p + 1
+    const float* ybase = ys + (oy + 1) * HT + (ox + 1);
+    for (int q = z0 - 2; q <= z1 + 1; ++q) {
+        // 1. slices fetched during the previous iteration enter LDS / registers; fetch the next
+        put_x(q + 1);
+        T fv[FPT];
+#pragma unroll
+        for (int e = 0; e < FPT; ++e) fv[e] = pf[e];
+        const T xo = xs[(q - 2) & 3][(oy + 3) * XT + (ox + 3)];  // x of this thread's output node, slice q - 2
+        fetch_x(q + 2);
+        fetch_f(q + 1);
         __syncthreads();
-        // 2. rho slice q (zero off the interior)
+        // 2. rho slice q on this thread's nodes (zero off the interior); the z
+        // triplet centred on slice q - 1 goes to LDS
         {
-            unsigned short* d = rs[(q + 3) % 3];
             const T* xc = xs[q & 3];
+            const T* xq = xs[(q - 1) & 3];
             const T* xp = xs[(q + 1) & 3];
-            for (int t = tid; t < RT * RT; t += LT) {
-                const int a = t % RT, b = t / RT;
-                const int i = i0 - 2 + a, j = j0 - 2 + b;
-                float v = 0.f;
-                if (q >= 1 && q <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
-                    const int p = (b + 1) * XT + (a + 1);
-                    const T* xq = xs[(q - 1) & 3];
-                    const T Ax = w0 * (T(6) * xc[p] - xc[p - 1] - xc[p + 1] - xc[p - XT] - xc[p + XT] - xq[p] - xp[p]);
-                    v = (float)((fs[t] - Ax) * invD);
+#pragma unroll
+            for (int e = 0; e < FPT; ++e) {
+                const int t = tid + e * LT;
+                if (t < RT * RT) {
+                    const int a = t % RT, b = t / RT;
+                    const int i = i0 - 2 + a, j = j0 - 2 + b;
+                    float v = 0.f;
+                    if (q >= 1 && q <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
+                        const int pp = (b + 1) * XT + (a + 1);
+                        const T Ax = w0 * (T(6) * xc[pp] - xc[pp - 1] - xc[pp + 1] - xc[pp - XT] - xc[pp + XT] - xq[pp] -
+                                           xp[pp]);
+                        v = (float)((fv[e] - Ax) * invD);
+                    }
+                    const unsigned short rq = f2bf(v);
+                    bf16x4 w;
+                    w[0] = (short)r2[e];
+                    w[1] = (short)r1[e];
+                    w[2] = (short)rq;
+                    w[3] = 0;
+                    tri[t] = w;
+                    r2[e] = r1[e];
+                    r1[e] = rq;
                 }
-                d[t] = f2bf(v);
             }
         }
         __syncthreads();
-        // 3. hidden slice p = q - 1 from rho slices p - 1, p, p + 1
-        const int p = q - 1;
+        const int p = q - 1;  // hidden slice
+        if (p < z0 - 1) continue;  // feeds no output slice of this workgroup (uniform)
+        // 3. hidden slice p (layer 1, ReLU) and Y = h W2 (layer 2) per 16-node block
         for (int blk = wave; blk < HB; blk += LT / 64) {
             const int v = blk * 16 + (lane & 15);
-            const int hx = v % HT, hy = v / HT;
+            const int vc = v < HN ? v : HN - 1;
+            const int hx = vc % HT, hy = vc / HT;
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bf16x4 a;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int t = ks * 16 + 4 * (lane >> 4) + jj;
-                    unsigned short val = 0;
-                    if (t < 27 && v < HN) {
-                        int dx, dy, dz;
-                        tap_off(t, dx, dy, dz);
-                        val = rs[(p + dz + 3) % 3][(hy + 1 + dy) * RT + (hx + 1 + dx)];
-                    }
-                    a[jj] = (short)val;
-                }
-                c = mfma(a, b1[ks], c);
+            for (int s = 0; s < 3; ++s) {
+                bf16x4 b = {0, 0, 0, 0};
+                if (tuse[s]) b = tri[hy * RT + hx + toff[s]];
+                c = mfma(w1[s], b, c);
             }
-            // rows 4 (lane / 16) + jj of the block, channel lane % 16
+            const int i = i0 - 1 + hx, j = j0 - 1 + hy;
+            const bool in = v < HN && p >= 1 && p <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m;
+            bf16x4 hv;
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int u = blk * 16 + 4 * (lane >> 4) + jj;
-                const int ux = u % HT, uy = u / HT;
-                const int i = i0 - 1 + ux, j = j0 - 1 + uy;
-                const bool in = u < HN && p >= 1 && p <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m;
-                hs[u * 16 + (lane & 15)] = f2bf(in ? fmaxf(c[jj], 0.f) : 0.f);
+            for (int jj = 0; jj < 4; ++jj) hv[jj] = (short)f2bf(in ? fmaxf(c[jj], 0.f) : 0.f);
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+                const f32x4 d = mfma(hv, w2[nb], zero);  // Y[blk 16 + 4 (lane / 16) + jj][nb 16 + lane % 16]
+                const int t = nb * 16 + (lane & 15);
+                if (t < 27) *reinterpret_cast<f32x4*>(&ys[t * YS + blk * 16 + 4 * (lane >> 4)]) = d;
             }
         }
         __syncthreads();
-        // 4. Y = h W2 per tap block, gathered into the output slices p - dz
-        for (int nb = 0; nb < 2; ++nb) {
-            for (int blk = wave; blk < HB; blk += LT / 64) {
-                const int v = blk * 16 + (lane & 15);
-                bf16x4 a;
-                const unsigned short* hp = &hs[v * 16 + 4 * (lane >> 4)];
+        // 4. gather: hidden node v + (dx, dy) of slice p feeds output slice p - dz
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) a[jj] = (short)hp[jj];
-                f32x4 c = {0.f, 0.f, 0.f, 0.f};
-                c = mfma(a, b2[nb], c);
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) ys[(blk * 16 + 4 * (lane >> 4) + jj) * 16 + (lane & 15)] = c[jj];
-            }
-            __syncthreads();
-            {
-                const int ox = tid % OT, oy = tid / OT;  // LT == OT * OT
-                const int tn = nb == 0 ? 16 : 11;
-                for (int tt = 0; tt < tn; ++tt) {
-                    const int t = nb * 16 + tt;
-                    int dx, dy, dz;
-                    tap_off(t, dx, dy, dz);
-                    // hidden node u = v + t lies in slice p, so it feeds output slice p - dz
-                    const int u = (oy + 1 + dy) * HT + (ox + 1 + dx);
-                    acc[(p - dz + 3) % 3][tid] += ys[u * 16 + tt];
-                }
-            }
-            __syncthreads();
+        for (int t = 0; t < 27; ++t) {
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            const float yv = ybase[t * YS + dy * HT + dx];
+            if (dz == 1) cm1 += yv;
+            else if (dz == 0) c0 += yv;
+            else cp1 += yv;
         }
         // 5. output slice o = p - 1 is complete
         const int o = p - 1;
-        {
-            const int ox = tid % OT, oy = tid / OT;
-            float* a = acc[(o + 3) % 3];
-            if (o >= z0 && o < z1) {
-                const int i = i0 + ox, j = j0 + oy;
-                if (i <= g.m && j <= g.m) {
-                    const T xv = xs[o & 3][(oy + 3) * XT + (ox + 3)];
-                    outr[g.idx(i, j, o)] = xv + (T)a[tid];
-                }
-            }
-            a[tid] = 0.f;
+        if (o >= z0 && o < z1) {
+            const int i = i0 + ox, j = j0 + oy;
+            if (i <= g.m && j <= g.m) outr[g.idx(i, j, o)] = xo + (T)cm1;
         }
-        __syncthreads();
+        cm1 = c0;
+        c0 = cp1;
+        cp1 = 0.f;
     }
 }
 
@@ -486,6 +517,21 @@ __global__ void k_lt_zero_f(float* p, long n) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Operand words of the inference step (320 words): layer 1 as the A
+// operand of (channels x K) x (K x nodes) with K slot 4 G + j of group G < 9
+// holding tap 9 j + G (j < 3; the rest zero), then layer 2 as the B operand
+// of (nodes x channels) x (channels x taps).
+void learned_pack_step(const float* W, unsigned long long* out) {
+    for (int s = 0; s < 3; ++s)
+        for (int lane = 0; lane < 64; ++lane) {
+            unsigned short v[4];
+            const int G = 4 * s + lane / 16, c = lane % 16;
+            for (int j = 0; j < 4; ++j) v[j] = (G < 9 && j < 3) ? f2bf(W[c * 27 + 9 * j + G]) : 0;
+            __builtin_memcpy(&out[s * 64 + lane], v, 8);
+        }
+    learned_pack_channels_by_tap(W + 16 * 27, out + 192);
+}
+
 // Operand words (4 bfloat16 per 64-bit word, lane order) of a [16][27]
 // weight array as the B operand of a (nodes x taps) x (taps x channels)
 // product: B[t][c] = W[c][t], K-steps of 16 taps (taps >= 27 are zero).
