@@ -49,6 +49,15 @@ __host__ __device__ inline unsigned short f2bf(float f) {
 }
 __device__ inline float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
+// Round-to-nearest-even bfloat16 of two floats in one hardware conversion
+// (bits of a in the low half); the same rounding as f2bf for finite values.
+__device__ inline unsigned bf16_pair(float a, float b) {
+    typedef __bf16 bfv2 __attribute__((ext_vector_type(2)));
+    typedef float fv2 __attribute__((ext_vector_type(2)));
+    const fv2 v = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bfv2));
+}
+
 __device__ inline f32x4 mfma(const bf16x4& a, const bf16x4& b, const f32x4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -68,30 +77,48 @@ constexpr int RT = OT + 4;        // rho tile edge (halo 2)
 constexpr int HT = OT + 2;        // hidden tile edge (halo 1)
 constexpr int HN = HT * HT;       // hidden nodes per slice (324)
 constexpr int HB = (HN + 15) / 16;  // 16-node blocks (21)
-constexpr int YS = 340;           // Y row stride (taps x nodes; >= 16 HB, 4-aligned, bank-spread)
+constexpr int XRING = 5;          // x slices kept in LDS
 constexpr int LT = 256;           // threads per workgroup
 
-// ops: [0..191] layer-1 operand (3 K-steps x 64 lanes, as the A operand,
-// M = channels), [192..319] layer-2 operand (2 N-blocks x 64 lanes) -- both
-// packed on the host from W1, W2 (learned_pack_step).
+// Value of lane l - 1 within each row of 16 lanes (zero in the row's first lane).
+__device__ inline float row_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+}
+
+// ops (learned_pack_step): [0, 192) layer-1 operand (3 K-steps x 64 lanes,
+// the A operand, M = channels), [192, 768) layer-2 operand (9 K-steps x 64
+// lanes, the B operand, N = z offsets).
 //
 // Layer 1 runs as D[c][v] = sum_k W1'[c][k] P[k][v] with the K index split
 // into 12 groups of 4: group G < 9 is the in-plane offset (dx, dy) =
 // (G % 3 - 1, G / 3 - 1) and slot j < 3 of the group the z offset j - 1, so
 // the four values a lane feeds per group are one 8-byte word of the "z
-// triplet" tile (rho at z - 1, z, z + 1 and a zero).  Its result D holds in
-// lane l channels 4 (l / 16) + j of node l % 16 -- exactly the A operand of
-// the layer-2 product, so the hidden layer never leaves the registers.
+// triplet" tile (rho at z - 1, z, z + 1 and a zero).  D holds in lane l
+// channels 4 (l / 16) + j of node l % 16: one 8-byte word of the hidden tile.
+//
+// Layer 2 contracts over the in-plane offsets and the channels at once:
+// E[v][c'] = sum over K-step s = (dy + 1) 3 + (dx + 1) and channel c of
+// h[v + (dx, dy)][c] W2[c][9 c' + s], with column c' = dz + 1 < 3 (the other
+// columns are zero).  Column c' of hidden slice p belongs to output slice
+// p + 1 - c'; E lands in lane l as rows 4 (l / 16) + j, column l % 16, so the
+// three partial sums of an output node pass along the row of lanes
+// (column 0 -> 1 -> 2) one slice per step and are complete in column 2.
 template <typename T>
-__global__ __launch_bounds__(LT) void k_learned_step(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
+__global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
                                                      T* __restrict__ out, long stride,
                                                      const unsigned long long* __restrict__ ops, int zseg,
                                                      int x_zero) {
-    __shared__ T xs[4][XT * XT];     // x slices, ring of 4
-    __shared__ bf16x4 tri[RT * RT];  // rho z triplets around the hidden slice
-    __shared__ __attribute__((aligned(16))) float ys[27 * YS];  // Y[t][u] of the hidden slice
+    __shared__ T xs[XRING][XT * XT];  // x slices, ring of 5
+    __shared__ T fs[RT * RT];         // f slice of the rho tile
+    __shared__ bf16x4 tri[RT * RT];   // rho z triplets around the hidden slice
+    // hidden slice: [channel group][node], 4 channels a word; the group
+    // stride (336 words) puts two groups' 16-node runs on disjoint banks
+    constexpr int HSTR = HB * 16;
+    __shared__ bf16x4 hs[4 * HSTR];
+    __shared__ __attribute__((aligned(16))) float os[OT * OT];  // completed N(rho) of the output slice
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = lane >> 4, col = lane & 15;
     const int tiles = (g.m + OT - 1) / OT;
     const int bx = blockIdx.x % tiles, by = blockIdx.x / tiles;
     const int z0 = 1 + blockIdx.y * zseg, z1 = min(g.m + 1, z0 + zseg);  // output slices [z0, z1)
@@ -101,59 +128,95 @@ __global__ __launch_bounds__(LT) void k_learned_step(Grid g, T w0, const T* __re
     T* outr = out + off;
     const int i0 = bx * OT + 1, j0 = by * OT + 1;  // first output node (interior indices from 1)
     const T invD = T(1) / (T(6) * w0);
+    // offsets inside one right-hand side stay below 2^31 (32-bit arithmetic)
+    const int zst = (g.n + 1) * g.pitch;  // z stride of the padded layout
 
-    bf16x4 w1[3], w2[2];
+    bf16x4 w1[3], w2[9];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const unsigned long long w = ops[s * 64 + lane];
         __builtin_memcpy(&w1[s], &w, 8);
     }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < 9; ++s) {
         const unsigned long long w = ops[192 + s * 64 + lane];
         __builtin_memcpy(&w2[s], &w, 8);
     }
-    // this lane's triplet offsets in the rho tile for its three K groups
+    // layer 1: this lane's triplet offsets for its K groups (group 4 s + grp;
+    // groups >= 9 exist only for s = 2, grp > 0, and read zeros), and per
+    // hidden block (blk = wave + 4 k) its node's triplet base; bit k of hmask
+    // says whether that node is interior in x and y
     int toff[3];
-    bool tuse[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int G = 4 * s + (lane >> 4);
-        tuse[s] = G < 9;
-        toff[s] = tuse[s] ? (G / 3) * RT + (G % 3) : 0;  // (1 + dy) RT + (1 + dx)
+        const int G = min(4 * s + grp, 8);
+        toff[s] = (G / 3) * RT + (G % 3);  // (1 + dy) RT + (1 + dx)
+    }
+    constexpr int HK = (HB + 3) / 4;  // hidden blocks per wave (the last only for wave 0)
+    int tb[HK];
+    unsigned hmask = 0;
+#pragma unroll
+    for (int k = 0; k < HK; ++k) {
+        const int v = (wave + 4 * k) * 16 + col;
+        const int vc = v < HN ? v : HN - 1;
+        const int hx = vc % HT, hy = vc / HT;
+        const int i = i0 - 1 + hx, j = j0 - 1 + hy;
+        tb[k] = hy * RT + hx;
+        if (v < HN && i >= 1 && i <= g.m && j >= 1 && j <= g.m) hmask |= 1u << k;
     }
 
     // Global loads run one slice ahead in registers (px, pf), so their
     // latency overlaps the previous slice's work instead of stalling it.
+    // They are unconditional, from clamped addresses inside the field, and
+    // the values off the tile's valid nodes are replaced by zeros when they
+    // enter LDS: no load sits in a branch, so the wait for them can stay at
+    // the top of the next iteration.
     constexpr int XPT = (XT * XT + LT - 1) / LT, FPT = (RT * RT + LT - 1) / LT;
+    static_assert(FPT == 2, "two rho nodes per thread");
+    const T* xsrc = x_zero ? fr : xr;  // x == 0: loads are discarded
+    int xoff[XPT], foff[FPT];
+    unsigned okmask = 0;  // bit e: x node e valid; bit 8 + e: f node e interior; bit 16: output node interior
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+        const int t = tid + e * LT;
+        const int i = i0 - 3 + t % XT, j = j0 - 3 + t / XT;
+        if (t < XT * XT && i >= 0 && i <= g.n && j >= 0 && j <= g.n) okmask |= 1u << e;
+        xoff[e] = (int)g.idx(min(max(i, 0), g.n), min(max(j, 0), g.n), 0);
+    }
+#pragma unroll
+    for (int e = 0; e < FPT; ++e) {
+        const int t = tid + e * LT;
+        const int i = i0 - 2 + t % RT, j = j0 - 2 + t / RT;
+        if (t < RT * RT && i >= 1 && i <= g.m && j >= 1 && j <= g.m) okmask |= 1u << (8 + e);
+        foff[e] = (int)g.idx(min(max(i, 0), g.n), min(max(j, 0), g.n), 0);
+    }
+    const int ox = tid % OT, oy = tid / OT;  // this thread's output node (LT == OT * OT)
+    if (i0 + ox <= g.m && j0 + oy <= g.m) okmask |= 1u << 16;
+    const int ooff = (int)g.idx(min(i0 + ox, g.m), min(j0 + oy, g.m), 0);
     T px[XPT], pf[FPT];
     auto fetch_x = [&](int l) {  // x slice l (grid node index)
+        const int zo = min(max(l, 0), g.n) * zst;
 #pragma unroll
-        for (int e = 0; e < XPT; ++e) {
-            const int t = tid + e * LT;
-            const int a = t % XT, b = t / XT;
-            const int i = i0 - 3 + a, j = j0 - 3 + b;
-            T v = T(0);
-            if (t < XT * XT && !x_zero && l >= 0 && l <= g.n && i >= 0 && i <= g.n && j >= 0 && j <= g.n)
-                v = xr[g.idx(i, j, l)];
-            px[e] = v;
-        }
+        for (int e = 0; e < XPT; ++e) px[e] = xsrc[(unsigned)(zo + xoff[e])];
     };
-    auto fetch_f = [&](int l) {  // f slice l, interior nodes of the rho tile
+    auto fetch_f = [&](int l) {  // f slice l on the rho tile
+        const int zo = min(max(l, 0), g.n) * zst;
 #pragma unroll
-        for (int e = 0; e < FPT; ++e) {
-            const int t = tid + e * LT;
-            const int a = t % RT, b = t / RT;
-            const int i = i0 - 2 + a, j = j0 - 2 + b;
-            T v = T(0);
-            if (t < RT * RT && l >= 1 && l <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) v = fr[g.idx(i, j, l)];
-            pf[e] = v;
-        }
+        for (int e = 0; e < FPT; ++e) pf[e] = fr[(unsigned)(zo + foff[e])];
     };
+    auto slot = [](int l) { return (l + 2 * XRING) % XRING; };  // l >= -3
     auto put_x = [&](int l) {
+        const bool lok = !x_zero && l >= 0 && l <= g.n;
+        T* d = xs[slot(l)];
 #pragma unroll
         for (int e = 0; e < XPT; ++e)
-            if (tid + e * LT < XT * XT) xs[l & 3][tid + e * LT] = px[e];
+            if (tid + e * LT < XT * XT) d[tid + e * LT] = (lok && ((okmask >> e) & 1u)) ? px[e] : T(0);
+    };
+    auto put_f = [&](int l) {
+        const bool lok = l >= 1 && l <= g.m;
+#pragma unroll
+        for (int e = 0; e < FPT; ++e)
+            if (tid + e * LT < RT * RT) fs[tid + e * LT] = (lok && ((okmask >> (8 + e)) & 1u)) ? pf[e] : T(0);
     };
     fetch_x(z0 - 3);
     put_x(z0 - 3);
@@ -161,100 +224,130 @@ __global__ __launch_bounds__(LT) void k_learned_step(Grid g, T w0, const T* __re
     put_x(z0 - 2);
     fetch_x(z0 - 1);
     fetch_f(z0 - 2);
-    const int ox = tid % OT, oy = tid / OT;  // this thread's output node (LT == OT * OT)
-    unsigned short r1[FPT], r2[FPT];         // bf16 rho of this thread's rho nodes, slices q - 1, q - 2
+    unsigned short r1[FPT], r2[FPT];  // bf16 rho of this thread's rho nodes, slices q - 1, q - 2
 #pragma unroll
     for (int e = 0; e < FPT; ++e) r1[e] = r2[e] = 0;
-    float cm1 = 0.f, c0 = 0.f, cp1 = 0.f;  // running output sums, slices p - 1, p, p + 1
-    const float* ybase = ys + (oy + 1) * HT + (ox + 1);
-    for (int q = z0 - 2; q <= z1 + 1; ++q) {
-        // 1. slices fetched during the previous iteration enter LDS / registers; fetch the next
-        put_x(q + 1);
-        T fv[FPT];
+    constexpr int OK = OT / 4;  // output rows per wave (row ob = wave + 4 k)
+    float S[OK][4];             // running sums of output nodes 4 grp + j of row ob (see above)
 #pragma unroll
-        for (int e = 0; e < FPT; ++e) fv[e] = pf[e];
-        const T xo = xs[(q - 2) & 3][(oy + 3) * XT + (ox + 3)];  // x of this thread's output node, slice q - 2
+    for (int k = 0; k < OK; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) S[k][j] = 0.f;
+    for (int q = z0 - 2; q <= z1 + 1; ++q) {
+        // 1. slices fetched during the previous iteration enter LDS; fetch the next
+        put_x(q + 1);
+        put_f(q);
         fetch_x(q + 2);
         fetch_f(q + 1);
         __syncthreads();
-        // 2. rho slice q on this thread's nodes (zero off the interior); the z
+        // 2. output slice q - 3, completed in the previous iteration, to memory
+        {
+            const int o = q - 3;
+            if (o >= z0 && o < z1 && ((okmask >> 16) & 1u))
+                outr[(unsigned)(o * zst + ooff)] = xs[slot(o)][(oy + 3) * XT + ox + 3] + (T)os[tid];
+        }
+        // 3. rho slice q on this thread's nodes (zero off the interior); the z
         // triplet centred on slice q - 1 goes to LDS
         {
-            const T* xc = xs[q & 3];
-            const T* xq = xs[(q - 1) & 3];
-            const T* xp = xs[(q + 1) & 3];
+            const T* xc = xs[slot(q)];
+            const T* xq = xs[slot(q - 1)];
+            const T* xp = xs[slot(q + 1)];
+            float rv[2] = {0.f, 0.f};
 #pragma unroll
             for (int e = 0; e < FPT; ++e) {
                 const int t = tid + e * LT;
+                const int a = t % RT, b = t / RT;
+                if (t < RT * RT && q >= 1 && q <= g.m && ((okmask >> (8 + e)) & 1u)) {
+                    const int pp = (b + 1) * XT + (a + 1);
+                    const T Ax =
+                        w0 * (T(6) * xc[pp] - xc[pp - 1] - xc[pp + 1] - xc[pp - XT] - xc[pp + XT] - xq[pp] - xp[pp]);
+                    rv[e] = (float)((fs[t] - Ax) * invD);
+                }
+            }
+            const unsigned rp = bf16_pair(rv[0], rv[1]);
+#pragma unroll
+            for (int e = 0; e < FPT; ++e) {
+                const int t = tid + e * LT;
+                const unsigned short rq = (unsigned short)(rp >> (16 * e));
                 if (t < RT * RT) {
-                    const int a = t % RT, b = t / RT;
-                    const int i = i0 - 2 + a, j = j0 - 2 + b;
-                    float v = 0.f;
-                    if (q >= 1 && q <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
-                        const int pp = (b + 1) * XT + (a + 1);
-                        const T Ax = w0 * (T(6) * xc[pp] - xc[pp - 1] - xc[pp + 1] - xc[pp - XT] - xc[pp + XT] - xq[pp] -
-                                           xp[pp]);
-                        v = (float)((fv[e] - Ax) * invD);
-                    }
-                    const unsigned short rq = f2bf(v);
                     bf16x4 w;
                     w[0] = (short)r2[e];
                     w[1] = (short)r1[e];
                     w[2] = (short)rq;
                     w[3] = 0;
                     tri[t] = w;
-                    r2[e] = r1[e];
-                    r1[e] = rq;
                 }
+                r2[e] = r1[e];
+                r1[e] = rq;
             }
         }
         __syncthreads();
         const int p = q - 1;  // hidden slice
         if (p < z0 - 1) continue;  // feeds no output slice of this workgroup (uniform)
-        // 3. hidden slice p (layer 1, ReLU) and Y = h W2 (layer 2) per 16-node block
-        for (int blk = wave; blk < HB; blk += LT / 64) {
-            const int v = blk * 16 + (lane & 15);
-            const int vc = v < HN ? v : HN - 1;
-            const int hx = vc % HT, hy = vc / HT;
-            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        // 4. hidden slice p: layer 1, ReLU, zero off the interior, to LDS
+        // (the blocks' product chains interleave)
+        const bool pin = p >= 1 && p <= g.m;
+        const int nhk = wave == 0 ? HK : HK - 1;  // blocks of this wave (uniform)
+        {
+            f32x4 c[HK];
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                bf16x4 b = {0, 0, 0, 0};
-                if (tuse[s]) b = tri[hy * RT + hx + toff[s]];
-                c = mfma(w1[s], b, c);
-            }
-            const int i = i0 - 1 + hx, j = j0 - 1 + hy;
-            const bool in = v < HN && p >= 1 && p <= g.m && i >= 1 && i <= g.m && j >= 1 && j <= g.m;
-            bf16x4 hv;
+            for (int k = 0; k < HK; ++k) c[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) hv[jj] = (short)f2bf(in ? fmaxf(c[jj], 0.f) : 0.f);
+            for (int s = 0; s < 3; ++s)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-                const f32x4 d = mfma(hv, w2[nb], zero);  // Y[blk 16 + 4 (lane / 16) + jj][nb 16 + lane % 16]
-                const int t = nb * 16 + (lane & 15);
-                if (t < 27) *reinterpret_cast<f32x4*>(&ys[t * YS + blk * 16 + 4 * (lane >> 4)]) = d;
-            }
+                for (int k = 0; k < HK; ++k)
+                    if (k < nhk) {
+                        bf16x4 b = tri[tb[k] + toff[s]];
+                        if (s == 2 && grp != 0) b = bf16x4{0, 0, 0, 0};
+                        c[k] = mfma(w1[s], b, c[k]);
+                    }
+#pragma unroll
+            for (int k = 0; k < HK; ++k)
+                if (k < nhk) {
+                    // ReLU on the rounded values (a negative bfloat16 is a
+                    // negative 16-bit integer), then the interior mask
+                    typedef short sv2 __attribute__((ext_vector_type(2)));
+                    typedef unsigned uv2 __attribute__((ext_vector_type(2)));
+                    const sv2 zero2 = {0, 0};
+                    const unsigned keep = (pin && ((hmask >> k) & 1u)) ? ~0u : 0u;
+                    const sv2 lo = __builtin_elementwise_max(
+                        __builtin_bit_cast(sv2, bf16_pair(c[k][0], c[k][1])), zero2);
+                    const sv2 hi = __builtin_elementwise_max(
+                        __builtin_bit_cast(sv2, bf16_pair(c[k][2], c[k][3])), zero2);
+                    const uv2 w = {__builtin_bit_cast(unsigned, lo) & keep, __builtin_bit_cast(unsigned, hi) & keep};
+                    hs[grp * HSTR + (wave + 4 * k) * 16 + col] = __builtin_bit_cast(bf16x4, w);
+                }
         }
         __syncthreads();
-        // 4. gather: hidden node v + (dx, dy) of slice p feeds output slice p - dz
+        // 5. layer 2 per output row ob (chains interleaved); the sums move one
+        // column along the row, and column 2 holds output slice p - 1, which
+        // goes to LDS for the next iteration to store
+        const bf16x4* hp = hs + grp * HSTR + (wave + 1) * HT + col + 1;
+        f32x4 e[OK];
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            const float yv = ybase[t * YS + dy * HT + dx];
-            if (dz == 1) cm1 += yv;
-            else if (dz == 0) c0 += yv;
-            else cp1 += yv;
+        for (int k = 0; k < OK; ++k) e[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            const int dx = s % 3 - 1, dy = s / 3 - 1;
+#pragma unroll
+            for (int k = 0; k < OK; ++k) e[k] = mfma(hp[4 * k * HT + dy * HT + dx], w2[s], e[k]);
         }
-        // 5. output slice o = p - 1 is complete
-        const int o = p - 1;
-        if (o >= z0 && o < z1) {
-            const int i = i0 + ox, j = j0 + oy;
-            if (i <= g.m && j <= g.m) outr[g.idx(i, j, o)] = xo + (T)cm1;
+#pragma unroll
+        for (int k = 0; k < OK; ++k) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) S[k][j] = row_shr1(S[k][j]) + e[k][j];
+            if (col == 2) {
+                const f32x4 v = {S[k][0], S[k][1], S[k][2], S[k][3]};
+                *reinterpret_cast<f32x4*>(&os[(wave + 4 * k) * OT + 4 * grp]) = v;
+            }
         }
-        cm1 = c0;
-        c0 = cp1;
-        cp1 = 0.f;
+    }
+    // the last output slice (z1 - 1) was completed in the final iteration
+    __syncthreads();
+    {
+        const int o = z1 - 1;
+        if (o >= z0 && ((okmask >> 16) & 1u))
+            outr[(unsigned)(o * zst + ooff)] = xs[slot(o)][(oy + 3) * XT + ox + 3] + (T)os[tid];
     }
 }
 
@@ -517,10 +610,11 @@ __global__ void k_lt_zero_f(float* p, long n) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// Operand words of the inference step (320 words): layer 1 as the A
+// Operand words of the inference step (kLearnedStepOps): layer 1 as the A
 // operand of (channels x K) x (K x nodes) with K slot 4 G + j of group G < 9
 // holding tap 9 j + G (j < 3; the rest zero), then layer 2 as the B operand
-// of (nodes x channels) x (channels x taps).
+// of (nodes x K) x (K x z offsets), K-step s = in-plane offset (tap s + 9 c'
+// in column c' < 3), K slot = channel.
 void learned_pack_step(const float* W, unsigned long long* out) {
     for (int s = 0; s < 3; ++s)
         for (int lane = 0; lane < 64; ++lane) {
@@ -529,7 +623,17 @@ void learned_pack_step(const float* W, unsigned long long* out) {
             for (int j = 0; j < 4; ++j) v[j] = (G < 9 && j < 3) ? f2bf(W[c * 27 + 9 * j + G]) : 0;
             __builtin_memcpy(&out[s * 64 + lane], v, 8);
         }
-    learned_pack_channels_by_tap(W + 16 * 27, out + 192);
+    const float* W2 = W + 16 * 27;
+    for (int s = 0; s < 9; ++s)
+        for (int lane = 0; lane < 64; ++lane) {
+            unsigned short v[4];
+            const int cz = lane % 16;
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * (lane / 16) + j;
+                v[j] = cz < 3 ? f2bf(W2[c * 27 + 9 * cz + s]) : 0;
+            }
+            __builtin_memcpy(&out[192 + s * 64 + lane], v, 8);
+        }
 }
 
 // Operand words (4 bfloat16 per 64-bit word, lane order) of a [16][27]
