@@ -281,7 +281,7 @@ size_t arrow_workspace_bytes(int N, int k);
 void learned_pack_taps_by_channel(const float* W, unsigned long long* out);   // 128 words
 void learned_pack_channels_by_tap(const float* W, unsigned long long* out);   // 128 words
 void learned_pack_step(const float* W, unsigned long long* out);            // kLearnedStepOps words
-constexpr int kLearnedStepOps = 768;
+constexpr int kLearnedStepOps = 512;
 // out = x + N((f - A x) / D) (x treated as zero when x_zero); ops =
 // learned_pack_step(W1 W2).  out must not alias x or f.
 template <typename T>

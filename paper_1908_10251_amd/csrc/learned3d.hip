@@ -58,6 +58,18 @@ __device__ inline unsigned bf16_pair(float a, float b) {
     return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bfv2));
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16 x 16 x 32: lane l holds A[l % 16][k], B[k][l % 16] for the eight K
+// slots of lane group l / 16 (the same slots pair in the product) and D as
+// in the 16 x 16 x 16 form.
+__device__ inline f32x4 mfma32(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline bf16x8 join8(const bf16x4& lo, const bf16x4& hi) {
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2 w = {__builtin_bit_cast(unsigned long long, lo), __builtin_bit_cast(unsigned long long, hi)};
+    return __builtin_bit_cast(bf16x8, w);
+}
 __device__ inline f32x4 mfma(const bf16x4& a, const bf16x4& b, const f32x4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -80,42 +92,43 @@ constexpr int HB = (HN + 15) / 16;  // 16-node blocks (21)
 constexpr int XRING = 5;          // x slices kept in LDS
 constexpr int LT = 256;           // threads per workgroup
 
-// Value of lane l - 1 within each row of 16 lanes (zero in the row's first lane).
-__device__ inline float row_shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
-}
-
-// ops (learned_pack_step): [0, 192) layer-1 operand (3 K-steps x 64 lanes,
-// the A operand, M = channels), [192, 768) layer-2 operand (9 K-steps x 64
-// lanes, the B operand, N = z offsets).
+// ops (learned_pack_step, 64-bit words): [0, 256) layer-1 operand (2 K-steps
+// x 64 lanes x 2 words, the A operand, M = channels), [256, 512) layer-2
+// operand (2 K-steps x 64 lanes x 2 words, the B operand).
 //
-// Layer 1 runs as D[c][v] = sum_k W1'[c][k] P[k][v] with the K index split
-// into 12 groups of 4: group G < 9 is the in-plane offset (dx, dy) =
-// (G % 3 - 1, G / 3 - 1) and slot j < 3 of the group the z offset j - 1, so
-// the four values a lane feeds per group are one 8-byte word of the "z
-// triplet" tile (rho at z - 1, z, z + 1 and a zero).  D holds in lane l
-// channels 4 (l / 16) + j of node l % 16: one 8-byte word of the hidden tile.
+// Both layers run on the 16 x 16 x 32 bfloat16 product.  Layer 1 is
+// D[c][v] = sum_k W1'[c][k] P[k][v]: the eight K slots of lane group g in
+// K-step s are two groups G = 8 s + 2 g + w (w = 0, 1) of four, group G < 9
+// being the in-plane offset (dx, dy) = (G % 3 - 1, G / 3 - 1) and slot jz < 3
+// of the group the z offset jz - 1.  So the four values a lane feeds per
+// group are one 8-byte word of the "z triplet" tile (rho at z - 1, z, z + 1
+// and a zero).  D holds in lane l channels 4 (l / 16) + j of node l % 16: an
+// 8-byte word of the hidden tile.
 //
-// Layer 2 contracts over the in-plane offsets and the channels at once:
-// E[v][c'] = sum over K-step s = (dy + 1) 3 + (dx + 1) and channel c of
-// h[v + (dx, dy)][c] W2[c][9 c' + s], with column c' = dz + 1 < 3 (the other
-// columns are zero).  Column c' of hidden slice p belongs to output slice
-// p + 1 - c'; E lands in lane l as rows 4 (l / 16) + j, column l % 16, so the
-// three partial sums of an output node pass along the row of lanes
-// (column 0 -> 1 -> 2) one slice per step and are complete in column 2.
+// Layer 2 contracts over the x offsets and the channels:
+// E[u][col] = sum over dx and channels c of h[u + dx][c] W2[c][3 col + dx + 1]
+// for the nine columns col = 3 (dz + 1) + (dy + 1), evaluated on 16-node rows
+// u of the hidden tile (18 rows).  Lane group g of K-step s covers x offset
+// 2 s + g / 2 - 1 and channels 8 (g % 2) .. + 7: one 16-byte word of the
+// hidden tile.  N(rho) at output node v then gathers the nine values
+// E[v + (0, dy)][col] of each hidden slice, column (dz, dy) of hidden slice p
+// belonging to output slice p - dz.
 template <typename T>
 __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
-                                                     T* __restrict__ out, long stride,
-                                                     const unsigned long long* __restrict__ ops, int zseg,
-                                                     int x_zero) {
+                                                        T* __restrict__ out, long stride,
+                                                        const unsigned long long* __restrict__ ops, int zseg,
+                                                        int x_zero) {
     __shared__ T xs[XRING][XT * XT];  // x slices, ring of 5
     __shared__ T fs[RT * RT];         // f slice of the rho tile
     __shared__ bf16x4 tri[RT * RT];   // rho z triplets around the hidden slice
-    // hidden slice: [channel group][node], 4 channels a word; the group
-    // stride (336 words) puts two groups' 16-node runs on disjoint banks
+    // hidden slice: [channel half][node], 8 channels in a 16-byte word
     constexpr int HSTR = HB * 16;
-    __shared__ bf16x4 hs[4 * HSTR];
-    __shared__ __attribute__((aligned(16))) float os[OT * OT];  // completed N(rho) of the output slice
+    __shared__ bf16x8 hs[2 * HSTR];
+    // layer-2 result of the hidden slice: [column][hidden row][x], the column
+    // stride padded so that the nine columns a lane group writes spread over
+    // the banks
+    constexpr int ER = HT, EC = 9, ES = ER * OT + 4;
+    __shared__ __attribute__((aligned(16))) float es[EC * ES];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane >> 4, col = lane & 15;
@@ -131,26 +144,25 @@ __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* _
     // offsets inside one right-hand side stay below 2^31 (32-bit arithmetic)
     const int zst = (g.n + 1) * g.pitch;  // z stride of the padded layout
 
-    bf16x4 w1[3], w2[9];
+    bf16x8 w1[2], w2[2];
+    {
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        const u64x2* o2 = reinterpret_cast<const u64x2*>(ops);
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const unsigned long long w = ops[s * 64 + lane];
-        __builtin_memcpy(&w1[s], &w, 8);
+        for (int s = 0; s < 2; ++s) {
+            w1[s] = __builtin_bit_cast(bf16x8, o2[s * 64 + lane]);
+            w2[s] = __builtin_bit_cast(bf16x8, o2[128 + s * 64 + lane]);
+        }
     }
+    // layer 1: this lane's triplet offsets for its four K groups
+    // G = 8 s + 2 grp + w (groups >= 9 read zeros), and per hidden block
+    // (blk = wave + 4 k) its node's triplet base; bit k of hmask says whether
+    // that node is interior in x and y
+    int toff[4];
 #pragma unroll
-    for (int s = 0; s < 9; ++s) {
-        const unsigned long long w = ops[192 + s * 64 + lane];
-        __builtin_memcpy(&w2[s], &w, 8);
-    }
-    // layer 1: this lane's triplet offsets for its K groups (group 4 s + grp;
-    // groups >= 9 exist only for s = 2, grp > 0, and read zeros), and per
-    // hidden block (blk = wave + 4 k) its node's triplet base; bit k of hmask
-    // says whether that node is interior in x and y
-    int toff[3];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const int G = min(4 * s + grp, 8);
-        toff[s] = (G / 3) * RT + (G % 3);  // (1 + dy) RT + (1 + dx)
+    for (int sw = 0; sw < 4; ++sw) {
+        const int G = min(8 * (sw >> 1) + 2 * grp + (sw & 1), 8);
+        toff[sw] = (G / 3) * RT + (G % 3);  // (1 + dy) RT + (1 + dx)
     }
     constexpr int HK = (HB + 3) / 4;  // hidden blocks per wave (the last only for wave 0)
     int tb[HK];
@@ -164,6 +176,7 @@ __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* _
         tb[k] = hy * RT + hx;
         if (v < HN && i >= 1 && i <= g.m && j >= 1 && j <= g.m) hmask |= 1u << k;
     }
+    constexpr int EK = (ER + 3) / 4;  // layer-2 rows per wave (row wave + 4 k < 18)
 
     // Global loads run one slice ahead in registers (px, pf), so their
     // latency overlaps the previous slice's work instead of stalling it.
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* _
 #pragma unroll
         for (int e = 0; e < FPT; ++e) pf[e] = fr[(unsigned)(zo + foff[e])];
     };
-    auto slot = [](int l) { return (l + 2 * XRING) % XRING; };  // l >= -3
+    auto slot = [](int l) { return (l + 2 * XRING) % XRING; };  // l >= -4
     auto put_x = [&](int l) {
         const bool lok = !x_zero && l >= 0 && l <= g.n;
         T* d = xs[slot(l)];
@@ -227,24 +240,35 @@ __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* _
     unsigned short r1[FPT], r2[FPT];  // bf16 rho of this thread's rho nodes, slices q - 1, q - 2
 #pragma unroll
     for (int e = 0; e < FPT; ++e) r1[e] = r2[e] = 0;
-    constexpr int OK = OT / 4;  // output rows per wave (row ob = wave + 4 k)
-    float S[OK][4];             // running sums of output nodes 4 grp + j of row ob (see above)
-#pragma unroll
-    for (int k = 0; k < OK; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) S[k][j] = 0.f;
-    for (int q = z0 - 2; q <= z1 + 1; ++q) {
+    float cm1 = 0.f, c0 = 0.f, cp1 = 0.f;  // running sums of output slices pg - 1, pg, pg + 1
+    const float* ebase = es + (oy + 1) * OT + ox;
+    // Iteration q: rho of slice q, both layers of hidden slice q - 1 (E to
+    // LDS), and the gather of hidden slice q - 2's E, which completes output
+    // slice q - 3.
+    for (int q = z0 - 2; q <= z1 + 2; ++q) {
         // 1. slices fetched during the previous iteration enter LDS; fetch the next
         put_x(q + 1);
         put_f(q);
         fetch_x(q + 2);
         fetch_f(q + 1);
         __syncthreads();
-        // 2. output slice q - 3, completed in the previous iteration, to memory
-        {
-            const int o = q - 3;
+        // 2. gather E of hidden slice pg = q - 2; output slice pg - 1 is complete
+        const int pg = q - 2;
+        if (pg >= z0 - 1 && pg <= z1) {  // uniform
+#pragma unroll
+            for (int cz = 0; cz < EC; ++cz) {
+                const int dz = cz / 3 - 1, dy = cz % 3 - 1;
+                const float v = ebase[cz * ES + dy * OT];
+                if (dz == 1) cm1 += v;
+                else if (dz == 0) c0 += v;
+                else cp1 += v;
+            }
+            const int o = pg - 1;
             if (o >= z0 && o < z1 && ((okmask >> 16) & 1u))
-                outr[(unsigned)(o * zst + ooff)] = xs[slot(o)][(oy + 3) * XT + ox + 3] + (T)os[tid];
+                outr[(unsigned)(o * zst + ooff)] = xs[slot(o)][(oy + 3) * XT + ox + 3] + (T)cm1;
+            cm1 = c0;
+            c0 = cp1;
+            cp1 = 0.f;
         }
         // 3. rho slice q on this thread's nodes (zero off the interior); the z
         // triplet centred on slice q - 1 goes to LDS
@@ -283,24 +307,28 @@ __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* _
         }
         __syncthreads();
         const int p = q - 1;  // hidden slice
-        if (p < z0 - 1) continue;  // feeds no output slice of this workgroup (uniform)
+        if (p < z0 - 1 || p > z1) continue;  // feeds no output slice of this workgroup (uniform)
         // 4. hidden slice p: layer 1, ReLU, zero off the interior, to LDS
         // (the blocks' product chains interleave)
-        const bool pin = p >= 1 && p <= g.m;
-        const int nhk = wave == 0 ? HK : HK - 1;  // blocks of this wave (uniform)
         {
+            const bool pin = p >= 1 && p <= g.m;
+            const int nhk = wave == 0 ? HK : HK - 1;  // blocks of this wave (uniform)
             f32x4 c[HK];
 #pragma unroll
             for (int k = 0; k < HK; ++k) c[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < 3; ++s)
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
                 for (int k = 0; k < HK; ++k)
                     if (k < nhk) {
-                        bf16x4 b = tri[tb[k] + toff[s]];
-                        if (s == 2 && grp != 0) b = bf16x4{0, 0, 0, 0};
-                        c[k] = mfma(w1[s], b, c[k]);
+                        // step 1 holds only group 8 (lane group 0, first
+                        // word); the other lanes skip the LDS read
+                        bf16x4 b0 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
+                        if (s == 0 || grp == 0) b0 = tri[tb[k] + toff[2 * s]];
+                        if (s == 0) b1 = tri[tb[k] + toff[2 * s + 1]];
+                        c[k] = mfma32(w1[s], join8(b0, b1), c[k]);
                     }
+            bf16x4* hw = reinterpret_cast<bf16x4*>(hs);
 #pragma unroll
             for (int k = 0; k < HK; ++k)
                 if (k < nhk) {
@@ -315,39 +343,33 @@ __global__ __launch_bounds__(LT, 4) void k_learned_step(Grid g, T w0, const T* _
                     const sv2 hi = __builtin_elementwise_max(
                         __builtin_bit_cast(sv2, bf16_pair(c[k][2], c[k][3])), zero2);
                     const uv2 w = {__builtin_bit_cast(unsigned, lo) & keep, __builtin_bit_cast(unsigned, hi) & keep};
-                    hs[grp * HSTR + (wave + 4 * k) * 16 + col] = __builtin_bit_cast(bf16x4, w);
+                    hw[((grp >> 1) * HSTR + (wave + 4 * k) * 16 + col) * 2 + (grp & 1)] = __builtin_bit_cast(bf16x4, w);
                 }
         }
         __syncthreads();
-        // 5. layer 2 per output row ob (chains interleaved); the sums move one
-        // column along the row, and column 2 holds output slice p - 1, which
-        // goes to LDS for the next iteration to store
-        const bf16x4* hp = hs + grp * HSTR + (wave + 1) * HT + col + 1;
-        f32x4 e[OK];
+        // 5. layer 2 on hidden rows r = wave + 4 k (chains interleaved), E to LDS
+        {
+            const int nek = wave < ER - 4 * (EK - 1) ? EK : EK - 1;  // rows of this wave (uniform)
+            f32x4 e[EK];
 #pragma unroll
-        for (int k = 0; k < OK; ++k) e[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < EK; ++k) e[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 9; ++s) {
-            const int dx = s % 3 - 1, dy = s / 3 - 1;
+            for (int s = 0; s < 2; ++s) {
+                const int dx = 2 * s + (grp >> 1) - 1;  // x offset of this lane group (2 in step 1 reads zeros)
+                const bf16x8* hp = hs + (grp & 1) * HSTR + wave * HT + col + 1 + min(dx, 1);
 #pragma unroll
-            for (int k = 0; k < OK; ++k) e[k] = mfma(hp[4 * k * HT + dy * HT + dx], w2[s], e[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < OK; ++k) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) S[k][j] = row_shr1(S[k][j]) + e[k][j];
-            if (col == 2) {
-                const f32x4 v = {S[k][0], S[k][1], S[k][2], S[k][3]};
-                *reinterpret_cast<f32x4*>(&os[(wave + 4 * k) * OT + 4 * grp]) = v;
+                for (int k = 0; k < EK; ++k)
+                    if (k < nek) {
+                        bf16x8 a = {};
+                        if (s == 0 || (grp >> 1) == 0) a = hp[4 * k * HT];  // x offset 2 does not exist
+                        e[k] = mfma32(a, w2[s], e[k]);
+                    }
             }
+#pragma unroll
+            for (int k = 0; k < EK; ++k)
+                if (k < nek && col < EC)
+                    *reinterpret_cast<f32x4*>(&es[col * ES + (wave + 4 * k) * OT + 4 * grp]) = e[k];
         }
-    }
-    // the last output slice (z1 - 1) was completed in the final iteration
-    __syncthreads();
-    {
-        const int o = z1 - 1;
-        if (o >= z0 && ((okmask >> 16) & 1u))
-            outr[(unsigned)(o * zst + ooff)] = xs[slot(o)][(oy + 3) * XT + ox + 3] + (T)os[tid];
     }
 }
 
@@ -610,29 +632,35 @@ __global__ void k_lt_zero_f(float* p, long n) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// Operand words of the inference step (kLearnedStepOps): layer 1 as the A
-// operand of (channels x K) x (K x nodes) with K slot 4 G + j of group G < 9
-// holding tap 9 j + G (j < 3; the rest zero), then layer 2 as the B operand
-// of (nodes x K) x (K x z offsets), K-step s = in-plane offset (tap s + 9 c'
-// in column c' < 3), K slot = channel.
+// Operand words of the inference step (kLearnedStepOps, 8 bfloat16 per lane
+// and K-step as two 64-bit words): layer 1 as the A operand of
+// (channels x K) x (K x nodes), lane group g of K-step s holding groups
+// G = 8 s + 2 g + w, slot jz < 3 of group G < 9 being tap 9 jz + G (the rest
+// zero); then layer 2 as the B operand of (nodes x K) x (K x columns), lane
+// group g of K-step s holding x offset index dxi = 2 s + g / 2 (< 3) and
+// channels 8 (g % 2) .. + 7, column col < 9 being tap 3 col + dxi.
 void learned_pack_step(const float* W, unsigned long long* out) {
-    for (int s = 0; s < 3; ++s)
+    for (int s = 0; s < 2; ++s)
         for (int lane = 0; lane < 64; ++lane) {
-            unsigned short v[4];
-            const int G = 4 * s + lane / 16, c = lane % 16;
-            for (int j = 0; j < 4; ++j) v[j] = (G < 9 && j < 3) ? f2bf(W[c * 27 + 9 * j + G]) : 0;
-            __builtin_memcpy(&out[s * 64 + lane], v, 8);
+            unsigned short v[8];
+            const int c = lane % 16, gq = lane / 16;
+            for (int w = 0; w < 2; ++w) {
+                const int G = 8 * s + 2 * gq + w;
+                for (int jz = 0; jz < 4; ++jz) v[4 * w + jz] = (G < 9 && jz < 3) ? f2bf(W[c * 27 + 9 * jz + G]) : 0;
+            }
+            __builtin_memcpy(&out[(s * 64 + lane) * 2], v, 16);
         }
     const float* W2 = W + 16 * 27;
-    for (int s = 0; s < 9; ++s)
+    for (int s = 0; s < 2; ++s)
         for (int lane = 0; lane < 64; ++lane) {
-            unsigned short v[4];
-            const int cz = lane % 16;
-            for (int j = 0; j < 4; ++j) {
-                const int c = 4 * (lane / 16) + j;
-                v[j] = cz < 3 ? f2bf(W2[c * 27 + 9 * cz + s]) : 0;
+            unsigned short v[8];
+            const int cl = lane % 16, gq = lane / 16;
+            const int dxi = 2 * s + gq / 2;
+            for (int j = 0; j < 8; ++j) {
+                const int c = 8 * (gq % 2) + j;
+                v[j] = (cl < 9 && dxi < 3) ? f2bf(W2[c * 27 + 3 * cl + dxi]) : 0;
             }
-            __builtin_memcpy(&out[192 + s * 64 + lane], v, 8);
+            __builtin_memcpy(&out[256 + (s * 64 + lane) * 2], v, 16);
         }
 }
 
