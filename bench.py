@@ -144,6 +144,9 @@ def bench_solve(args, wl, pasm, torch):
     solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts)
     t_setup = time.perf_counter() - t0
     ctx, k = solver.ctx, wl.k
+    learned = wl.smoother == "learned"
+    if learned and args.learned == "on":
+        pasm.pasm_learned_enable(ctx, True)  # override the set-up speed test
 
     ref = golden(wl.golden_name)
     ref_kind = "oracle discrete eigenvalues (tests/golden)"
@@ -179,6 +182,7 @@ def bench_solve(args, wl, pasm, torch):
 
     for _ in range(args.warmup):
         one_solve()
+    rep0 = pasm.pasm_learned_report(ctx) if learned else None
     pasm.pasm_profile(ctx, 0, True)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -194,7 +198,6 @@ def bench_solve(args, wl, pasm, torch):
     ms_per_step = 1e3 * elapsed / args.steps
     value = k / (ms_per_step / 1e3) if float(np.max(err)) <= 1e-8 else 0.0
     n_dofs = pasm.pasm_num_dofs(ctx)
-    learned = wl.smoother == "learned"
     sweeps = wl.vcycles * (2 if learned else wl.nu_pre + wl.nu_post)
     cfg = {"dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": n_dofs, "coarse_dofs": pasm.pasm_coarse_dofs(ctx),
            "smoother": wl.smoother, "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles,
@@ -202,14 +205,21 @@ def bench_solve(args, wl, pasm, torch):
            "eigenpairs_within_1e-8": int(np.sum(err <= 1e-8)), "reference": ref_kind, "setup_s": t_setup,
            "fine_dof_updates_per_s": n_dofs * k * sweeps * float(np.mean(iters)) / (ms_per_step / 1e3)}
     flops = None
+    kernel = KERNEL_NAMES[wl.dim]
     if learned:
         rep = pasm.pasm_learned_report(ctx)
         cfg["learned"] = rep
-        # 16 channels x 27 taps multiply-adds in each of the two layers per node
-        flops = 2.0 * 2 * 16 * 27 * n_dofs * k
-        kernel = KERNEL_NAMES["learned"]
-    else:
-        kernel = KERNEL_NAMES[wl.dim]
+        cfg["learned_mode"] = args.learned
+        # the timed launches are the learned step's only if the learned
+        # smoother ran (the set-up speed test may have left it off)
+        if rep["cycles_learned"] > rep0["cycles_learned"]:
+            # 16 channels x 27 taps multiply-adds in each of the two layers per node
+            flops = 2.0 * 2 * 16 * 27 * n_dofs * k
+            kernel = KERNEL_NAMES["learned"]
+            if rep["cycles_fallback"] > rep0["cycles_fallback"]:
+                kernel += "; some cycles fell back to plain smoothing"
+        else:
+            kernel += " (the learned smoother was off: the set-up speed test found plain cycles faster)"
     roof = roofline(launches, ms, bpl, wl.name, kernel, flops)
     out = line(wl, "eigenpairs/sec to 1e-8 rel eigenvalue error", value, "eigenpairs/s", args.steps, args.warmup,
                ms_per_step, cfg, roof, "f64" if wl.precision == "fp64" else "f32+f64")
@@ -316,6 +326,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=40)
     ap.add_argument("--ref-iter", type=int, default=200, help="iterations of the reference run (no stored values)")
     ap.add_argument("--iters", type=int, default=10, help="timed iterations (step-throughput workloads)")
+    ap.add_argument("--learned", choices=["auto", "on"], default="auto",
+                    help="learned-smoother workloads: keep the set-up speed test's choice, or force it on")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="also run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()

@@ -91,12 +91,24 @@ __global__ __launch_bounds__(64 * WAVES) void k_dmv_part(const T* __restrict__ M
     T acc[KB];
 #pragma unroll
     for (int rr = 0; rr < KB; ++rr) acc[rr] = T(0);
+    // Columns go in groups of PF whose loads are issued one group ahead
+    // (enough bytes in flight to cover the memory latency); a partial last
+    // chunk re-reads its last column, which meets a zero of xs.
     const T* mc = Mat + (long)c0 * N + row;
-#pragma unroll 4
-    for (int cc = 0; cc < cn; ++cc) {
-        const T a = mc[(long)cc * N];
+    constexpr int PF = 8;
+    static_assert(DC % PF == 0, "column chunk must hold whole groups");
+    T a[PF], b[PF];
 #pragma unroll
-        for (int rr = 0; rr < KB; ++rr) acc[rr] += a * xs[rr][cc];
+    for (int u = 0; u < PF; ++u) a[u] = mc[(long)min(u, cn - 1) * N];
+    for (int cc = 0; cc < DC; cc += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) b[u] = mc[(long)min(cc + PF + u, cn - 1) * N];
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+#pragma unroll
+            for (int rr = 0; rr < KB; ++rr) acc[rr] += a[u] * xs[rr][cc + u];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) a[u] = b[u];
     }
 #pragma unroll
     for (int rr = 0; rr < KB; ++rr)
