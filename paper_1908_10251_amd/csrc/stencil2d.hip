@@ -450,6 +450,99 @@ __global__ __launch_bounds__(BX* BY) void k_border_restrict(Grid g, Coef<double>
     }
 }
 
+// The same through LDS: a workgroup owns 32 x 8 coarse nodes, stages u on
+// the 67 x 19 fine nodes around them once (coalesced rows), forms A u and M u
+// on the 65 x 17 fine nodes their restriction reaches, and then restricts
+// from LDS.  It owns the fine nodes of the first 64 x 16 of those for the
+// sums (coarse I, J = 1 .. nc over the grid, as above).
+constexpr int BRX = 32, BRY = 8;                  // coarse nodes per workgroup
+constexpr int BFX = 2 * BRX + 1, BFY = 2 * BRY + 1;  // fine nodes with A u, M u
+constexpr int BUX = BFX + 2, BUY = BFY + 2;          // fine nodes of u (halo 1)
+template <int KIND>
+__global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> cg, const double* __restrict__ u,
+                                                          Grid gc, double* __restrict__ bc,
+                                                          double* __restrict__ cc, double* __restrict__ partial,
+                                                          long stride, long sc) {
+    __shared__ double us[BUY][BUX];
+    __shared__ double as[BFY][BFX];
+    __shared__ double ms[BFY][BFX];
+    __shared__ double sh[8];
+    const int tid = threadIdx.x;
+    const int I0 = blockIdx.x * BRX + 1, J0 = blockIdx.y * BRY + 1;  // first coarse node
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;                    // first fine node with A u
+    double bs;
+    const Coef<double> c = member_coef(cg, blockIdx.z, bs);
+    const double* ur = u + (long)blockIdx.z * stride;
+    for (int t = tid; t < BUX * BUY; t += 256) {
+        const int a = t % BUX, b = t / BUX;
+        const int i = fi0 - 1 + a, j = fj0 - 1 + b;
+        us[b][a] = (i <= g.n && j <= g.n) ? ur[g.idx(i, j)] : 0.0;
+    }
+    __syncthreads();
+    const double h2 = g.h * g.h;
+    double ua = 0.0, um = 0.0;
+    for (int t = tid; t < BFX * BFY; t += 256) {
+        const int a = t % BFX, b = t / BFX;
+        const int i = fi0 + a, j = fj0 + b;
+        double Ax = 0.0, Mx = 0.0;
+        if (i <= g.m && j <= g.m) {
+            const double x0 = us[b + 1][a + 1];
+            const double xe = us[b + 1][a + 2], xw = us[b + 1][a], xn = us[b + 2][a + 1], xs = us[b][a + 1];
+            const double xne = us[b + 2][a + 2], xsw = us[b][a];
+            if (KIND == 0) {
+                Ax = c.w0 * (4.0 * x0 - xe - xw - xn - xs);
+            } else {
+                const long id = g.idx(i, j);
+                const int p = g.pitch;
+                const double we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - p];
+                if (KIND == 1) {
+                    Ax = (we + ww + wn + ws) * x0 - we * xe - ww * xw - wn * xn - ws * xs;
+                } else {
+                    Ax = c.d[id] * x0 - we * xe - ww * xw - wn * xn - ws * xs - c.wne[id] * xne -
+                         c.wne[id - p - 1] * xsw;
+                }
+            }
+            Mx = h2 * (0.5 * x0 + (xe + xw + xn + xs + xne + xsw) * (1.0 / 12.0));
+            if (a < 2 * BRX && b < 2 * BRY) {  // owned
+                ua += x0 * Ax;
+                um += x0 * Mx;
+            }
+        }
+        as[b][a] = Ax;
+        ms[b][a] = Mx;
+    }
+    __syncthreads();
+    {
+        const int cx = tid % BRX, cy = tid / BRX;
+        const int I = I0 + cx, J = J0 + cy;
+        if (I <= gc.m && J <= gc.m) {
+            const int a = 2 * cx + 1, b = 2 * cy + 1;
+            const double rb = as[b][a] + 0.5 * (as[b][a - 1] + as[b - 1][a] + as[b - 1][a - 1] + as[b][a + 1] +
+                                                as[b + 1][a] + as[b + 1][a + 1]);
+            const double rc = ms[b][a] + 0.5 * (ms[b][a - 1] + ms[b - 1][a] + ms[b - 1][a - 1] + ms[b][a + 1] +
+                                                ms[b + 1][a] + ms[b + 1][a + 1]);
+            const long cid = (long)blockIdx.z * sc + gc.idx(I, J);
+            bc[cid] = rb;
+            cc[cid] = rc;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ua += __shfl_down(ua, o, 64);
+        um += __shfl_down(um, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        sh[2 * (tid >> 6)] = ua;
+        sh[2 * (tid >> 6) + 1] = um;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const long nblk = (long)gridDim.x * gridDim.y;
+        const long blk = (long)blockIdx.z * nblk + blockIdx.y * gridDim.x + blockIdx.x;
+        partial[2 * blk] = sh[0] + sh[2] + sh[4] + sh[6];
+        partial[2 * blk + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__ partial, int nblk,
                                                       double* __restrict__ out) {
     __shared__ double sh[8];
@@ -729,11 +822,11 @@ int launch_border(const Grid& g, const Coef<double>& c, const double* u, double*
 int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st) {
     if (g.dim != 2 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 2D, ratio 2");
-    dim3 grid = grid_for(gc.n, gc.n, nrhs), blk(BX, BY);
+    dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
     switch (coef_kind(c)) {
-        case 0: hipLaunchKernelGGL(k_border_restrict<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
-        case 1: hipLaunchKernelGGL(k_border_restrict<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
-        default: hipLaunchKernelGGL(k_border_restrict<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
+        case 0: hipLaunchKernelGGL(k_border_restrict_t<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
+        case 1: hipLaunchKernelGGL(k_border_restrict_t<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
+        default: hipLaunchKernelGGL(k_border_restrict_t<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
     }
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y);
