@@ -586,6 +586,178 @@ __global__ __launch_bounds__(RW* NW) void k_arrow_roots(ArrowIn in, double* work
     }
 }
 
+// The NEAR pass spread over the machine: one workgroup of four wavefronts
+// per (eigenpair, root), the active poles in registers (PPL per lane), the
+// sums over poles reduced across the workgroup in a fixed order so that every
+// wavefront takes the same Newton steps.  Same iteration as k_arrow_roots;
+// its (score, root value) goes to nres for k_arrow_near_cert.
+constexpr int NT = 256;  // threads per root
+template <int PPL>
+__global__ __launch_bounds__(NT) void k_arrow_near_root(ArrowIn in, double* work, int* iwork, double* best,
+                                                        int nchunk, double* nres) {
+    __shared__ double red[2][3][NT / 64];
+    const int r = blockIdx.x, slot = blockIdx.y, N = in.N;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    WS w = ws_of(work, iwork, best, N, nchunk, r);
+    double* res = nres + ((long)r * RPB + slot) * 2;
+    const int na = (int)w.sc[S_NA];
+    const double rho = w.sc[S_RHO], sq = w.sc[S_SQ], lp = in.lam_prev[r];
+    const int base = na > 0 ? near_base(w.d, na, lp) : 0;
+    const int root = base + slot;
+    if (na < 0 || root > na) {  // uniform
+        if (tid == 0) {
+            res[0] = -1.0;
+            res[1] = 0.0;
+        }
+        return;
+    }
+    if (na == 0) {
+        if (tid == 0) {
+            w.rmu[0] = rho;
+            w.rtau[0] = 0.0;
+            w.rorg[0] = rho;
+            res[0] = sq;
+            res[1] = rho;
+        }
+        return;
+    }
+    // poles beyond na: weight 0 and a far pole, so that they add exact zeros
+    double dr[PPL], zr[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        const int a = tid + NT * p;
+        dr[p] = a < na ? w.d[a] : 1e300;
+        zr[p] = a < na ? w.z[a] : 0.0;
+    }
+    int par = 0;
+    auto sum3 = [&](double& x, double& y, double& z) {
+        x = wave_sum(x);
+        y = wave_sum(y);
+        z = wave_sum(z);
+        if ((tid & 63) == 0) {
+            red[par][0][wave] = x;
+            red[par][1][wave] = y;
+            red[par][2][wave] = z;
+        }
+        __syncthreads();
+        x = y = z = 0.0;
+#pragma unroll
+        for (int v = 0; v < NT / 64; ++v) {
+            x += red[par][0][v];
+            y += red[par][1][v];
+            z += red[par][2][v];
+        }
+        par ^= 1;
+    };
+    const double left = root == 0 ? w.sc[S_LO] : w.d[root - 1];
+    const double right = root == na ? w.sc[S_HI] : w.d[root];
+    double org, lo, hi;
+    if (root == 0) {
+        org = w.d[0];
+        lo = left - org;
+        hi = 0.0;
+    } else if (root == na) {
+        org = w.d[na - 1];
+        lo = 0.0;
+        hi = right - org;
+    } else {
+        const double mid = 0.5 * (left + right);
+        double fm = 0.0, u1 = 0.0, u2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) fm += zr[p] * zr[p] / (mid - dr[p]);
+        sum3(fm, u1, u2);
+        fm += rho - mid;
+        if (fm > 0.0) {  // root in (mid, right): origin at the right pole
+            org = right;
+            lo = mid - org;
+            hi = 0.0;
+        } else {
+            org = left;
+            lo = 0.0;
+            hi = mid - org;
+        }
+    }
+    const double c0 = rho - org;
+    double tau = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        double F = 0.0, dF = 0.0, mag = 0.0;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const double t1 = zr[p] / (tau - (dr[p] - org));
+            F += zr[p] * t1;
+            dF -= t1 * t1;
+            mag += fabs(zr[p] * t1);
+        }
+        sum3(F, dF, mag);
+        F += c0 - tau;
+        dF -= 1.0;
+        mag += fabs(c0) + fabs(tau);
+        if (F == 0.0) break;
+        if (F > 0.0) lo = tau;
+        else hi = tau;
+        if (fabs(F) <= 4.0 * EPS * mag) break;
+        const double hval = tau * F, dh = F + tau * dF;
+        double tn = tau - hval / dh;
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        const double step = fabs(tn - tau);
+        tau = tn;
+        if (step <= 2.0 * EPS * fabs(tau) || hi - lo <= 4.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+    }
+    double S1 = 0.0, S2 = 0.0, u3 = 0.0;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        const int a = tid + NT * p;
+        const double v = zr[p] / (tau - (dr[p] - org));
+        S1 += v * v;
+        S2 += v * (a < na ? w.qa[a] : 0.0);
+    }
+    sum3(S1, S2, u3);
+    if (tid == 0) {
+        const double t = 1.0 / sqrt(1.0 + S1);
+        const double mu = org + tau;
+        w.rmu[root] = mu;
+        w.rtau[root] = tau;
+        w.rorg[root] = org;
+        res[0] = fabs(t * (S2 + sq));
+        res[1] = mu;
+    }
+}
+
+// Selection and certificate of the NEAR pass (as at the end of k_arrow_roots).
+__global__ __launch_bounds__(64) void k_arrow_near_cert(ArrowIn in, double* work, int* iwork, double* best,
+                                                        int nchunk, const double* nres) {
+    if (threadIdx.x != 0) return;
+    const int r = blockIdx.x, N = in.N;
+    WS w = ws_of(work, iwork, best, N, nchunk, r);
+    const int na = (int)w.sc[S_NA];
+    const double lp = in.lam_prev[r];
+    const int base = na > 0 ? near_base(w.d, na, lp) : 0;
+    const double* res = nres + (long)r * RPB * 2;
+    int bi = -1;
+    double mass = 0.0;
+    for (int t = 0; t < RPB; ++t) {
+        const double st = res[2 * t], mt = res[2 * t + 1];
+        if (st < 0.0) continue;
+        mass += st * st;
+        if (bi < 0 || better(st, mt, res[2 * bi], res[2 * bi + 1], lp)) bi = t;
+    }
+    const double sb = bi < 0 ? -1.0 : res[2 * bi], mb = bi < 0 ? 0.0 : res[2 * bi + 1];
+    w.sc[S_NSCORE] = sb;
+    w.sc[S_NMU] = mb;
+    w.sc[S_NMU + 1] = bi < 0 ? -1.0 : (double)(base + bi);
+    bool cert = false;
+    if (bi >= 0) {
+        const double zeta = in.bz[2 * r + 1];
+        const double rest = zeta - w.sc[S_DMASS] - mass;
+        const double b2 = sb * sb;
+        const bool beats_deflated = w.sc[S_DSCORE] < 0.0 || better(sb, mb, w.sc[S_DSCORE], w.sc[S_DMU], lp);
+        cert = beats_deflated && b2 > fmax(rest, 0.0) * (1.0 + 1e-10) + 1e-10 * zeta * EPS;
+        if (base == 0 && na + 1 <= RPB) cert = beats_deflated;  // every root was computed
+        if (in.exhaustive) cert = false;
+    }
+    w.sc[S_CERT] = cert ? 1.0 : 0.0;
+}
+
 // Stage C, one block per eigenpair: final choice, rank, new coefficients.
 __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, double* work, int* iwork, double* best,
                                                     int nchunk) {
@@ -779,11 +951,20 @@ void launch_arrowhead(const ArrowIn& in0, const ArrowOut& out, int k, hipStream_
     double* best = reinterpret_cast<double*>(iwork + (long)in.N * k + ((long)in.N * k & 1));
     hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PP), 0, st, in, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();
-    // NEAR pass: one workgroup per eigenpair and one wavefront per root,
-    // poles in LDS up to 6400 of them
-    if (in.N <= LDS_POLES)
-        hipLaunchKernelGGL((k_arrow_roots<LDS_POLES, true, RPB>), dim3(k, 1), dim3(RW * RPB), 0, st, in, work, iwork,
-                           best, nchunk);
+    // NEAR pass: one workgroup per (eigenpair, root) with the poles in
+    // registers up to 8192 of them, else one workgroup per eigenpair and one
+    // wavefront per root
+    double* nres = best + 4L * nchunk * k;
+    auto near = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(k, RPB), dim3(NT), 0, st, in, work, iwork, best, nchunk, nres);
+        PASM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_arrow_near_cert, dim3(k), dim3(64), 0, st, in, work, iwork, best, nchunk,
+                           (const double*)nres);
+    };
+    if (in.N <= 4 * NT) near(k_arrow_near_root<4>);
+    else if (in.N <= 8 * NT) near(k_arrow_near_root<8>);
+    else if (in.N <= 16 * NT) near(k_arrow_near_root<16>);
+    else if (in.N <= 32 * NT) near(k_arrow_near_root<32>);
     else if (in.N <= LDS_POLES_BIG)
         hipLaunchKernelGGL((k_arrow_roots<LDS_POLES_BIG, true, RPB>), dim3(k, 1), dim3(RW * RPB), 0, st, in, work,
                            iwork, best, nchunk);
@@ -806,7 +987,7 @@ void launch_arrowhead(const ArrowIn& in0, const ArrowOut& out, int k, hipStream_
 size_t arrow_workspace_bytes(int N, int k) {
     const int nchunk = arrow_chunks(N);
     return sizeof(double) * (size_t)arrow_work_doubles(N, k) + sizeof(int) * ((size_t)N * k + 2) +
-           sizeof(double) * 4 * (size_t)nchunk * k + 256;
+           sizeof(double) * 4 * (size_t)nchunk * k + sizeof(double) * 2 * RPB * (size_t)k + 256;
 }
 
 }  // namespace pasm

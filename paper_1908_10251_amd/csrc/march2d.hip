@@ -301,7 +301,7 @@ MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows) {
         } else {
             const long bands = std::max<long>(1, slots / base);
             mseg = (int)((g.n + 1 + bands - 1) / bands);
-            mseg = std::max(32, (mseg + 1) & ~1);
+            mseg = std::max(16, (mseg + 1) & ~1);
         }
     }
     sh.mseg = (mseg + 1) & ~1;
