@@ -21,6 +21,7 @@
 #include <cstring>
 #include <memory>
 #include <random>
+#include <type_traits>
 
 #include "common.h"
 
@@ -108,6 +109,9 @@ struct pasm_ctx {
     int ltrain_steps = 0;
     double lloss_first = 0.0, lloss_last = 0.0, lplain_rate = 0.0, llearned_rate = 0.0;
     double lplain_ms = 0.0, llearned_ms = 0.0;
+    // borders formed by the last V-cycle's fine post-smoothing (2D, FP64)
+    bool border_next = false, border_done = false;
+    int border_nblk = 0;
     long lcycles_learned = 0, lcycles_fallback = 0;
     double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
     std::vector<double> lratio; // residual reduction of the last V-cycles (diagnostics)
@@ -323,7 +327,16 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         std::swap(x, y);
         vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
         if (fine) record_start(c);
-        pasm::launch_march_post<T>(L.g, (T)L.w0, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
+        bool fused_border = false;
+        if constexpr (std::is_same<T, double>::value) {
+            if (fine && c->border_next && c->dim == 2) {
+                // the borders of the next step come from this post-smoothing's output
+                c->border_nblk = pasm::launch_march_post_border(L.g, L.w0, x, f, y, Lc.g, xc, Lc.B, Lc.C, c->partial,
+                                                                nrhs, to_steps(L.post), c->st);
+                c->border_done = fused_border = true;
+            }
+        }
+        if (!fused_border) pasm::launch_march_post<T>(L.g, (T)L.w0, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
         if (fine) record_end(c, 3.25 * w * nodes);
         std::swap(x, y);
         return;
@@ -381,9 +394,15 @@ std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, i
 // learned smoother every cycle is checked: if it reduced the residual of some
 // right-hand side by less than the plain cycle does (the rate measured at
 // set-up), x is restored and the cycle is redone with the plain smoother.
-void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles) {
+void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles,
+                bool border = false) {
     if (!c->learned_on) {
-        for (int cy = 0; cy < ncycles; ++cy) one_cycle(c, x, scr, f, nrhs);
+        for (int cy = 0; cy < ncycles; ++cy) {
+            // the last FP64 cycle may form the borders of the next step on its way out
+            c->border_next = border && cy == ncycles - 1 && !c->mixed;
+            one_cycle(c, x, scr, f, nrhs);
+            c->border_next = false;
+        }
         return;
     }
     const Grid& g = c->gf();
@@ -749,8 +768,9 @@ void iterate_once(pasm_ctx* c) {
     const long sf = c->sf();
     // Algorithm 1, step 1: f = lambda M u, V-cycles from x = u (in place in U)
     pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, sf, c->st);
+    c->border_done = false;
     if (c->L > 1) {
-        bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles);
+        bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles, c->dim == 2 && c->L >= 2);
     } else {
         // fine level = V_H: exact solve
         pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->dmv, c->st);
@@ -761,8 +781,9 @@ void iterate_once(pasm_ctx* c) {
     int lstart = c->L - 2;
     if (c->dim == 2 && c->L >= 2) {
         pasm::Level& Lc = c->lv[c->L - 2];
-        const int nblk = pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C, c->partial, k,
-                                                      sf, Lc.g.plane, c->st);
+        const int nblk = c->border_done ? c->border_nblk
+                                        : pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
+                                                                       c->partial, k, sf, Lc.g.plane, c->st);
         pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
         bsrc = Lc.B;
         csrc = Lc.C;

@@ -148,6 +148,13 @@ void launch_march_pre(const Grid& g, T w0, const T* x0, const T* f, T* out, cons
 template <typename T>
 void launch_march_post(const Grid& g, T w0, const T* x, const T* f, T* out, const Grid& gc, const T* ec, int nrhs,
                        const SmoothSteps& ss, hipStream_t st, int rows = 0);
+// launch_march_post, then from its output u also b_c = P^T A u and
+// c_c = P^T M u on gc (as launch_border_restrict) and the pairs (u.Au, u.Mu)
+// of every wavefront's own nodes in partial; returns the pairs per
+// right-hand side (for launch_reduce_pairs).
+int launch_march_post_border(const Grid& g, double w0, const double* x, const double* f, double* out, const Grid& gc,
+                             const double* ec, double* bc, double* cc, double* partial, int nrhs,
+                             const SmoothSteps& ss, hipStream_t st, int rows = 0);
 
 template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,

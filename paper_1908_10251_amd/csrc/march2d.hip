@@ -18,7 +18,11 @@
 //         r_c = P^T r to the next coarser grid (the transpose of nodal
 //         interpolation: centre 1, the six neighbours of the "/" mesh 1/2);
 //   POST  the coarse correction is prolongated while loading:
-//         x_0 = x + P e_c.
+//         x_0 = x + P e_c;
+//   POST with borders (double): as POST, then from u = x_S also A u and
+//         M u, their restrictions b_c = P^T A u and c_c = P^T M u, and the
+//         sums u.Au, u.Mu over the wavefront's own nodes (one pair per
+//         wavefront), which the augmented pencil needs next.
 // Steps follow x_{t+1} = x_t + a_t (x_t - x_{t-1}) + b_t D^{-1} (f - A x_t)
 // with a_0 = 0 (a phase starts fresh).
 #include <algorithm>
@@ -78,7 +82,9 @@ __device__ inline float detach(float v) {
 template <typename T, int S, int MODE, bool XZ>
 __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
                                               T* __restrict__ out, const T* __restrict__ ec, Grid gc,
-                                              T* __restrict__ rc, long sf, long sc, SmoothSteps st, MarchShape sh) {
+                                              T* __restrict__ rc, T* __restrict__ rc2, double* __restrict__ part,
+                                              long sf, long sc, SmoothSteps st, MarchShape sh) {
+    constexpr bool POSTLIKE = MODE == 2 || MODE == 3;
     constexpr int PF = prefetch_rows<T>();
     constexpr int HX = S + 2;
     constexpr int TXO = MW - 2 * HX;
@@ -119,6 +125,8 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     T xw[S + 1][3][2];
     T fw[S + 2][2];
     T rw[3][2];
+    T mw[3][2];  // MODE 3: rw holds A u, mw holds M u
+    double ua = 0.0, um = 0.0;
 #pragma unroll
     for (int t = 0; t <= S; ++t)
 #pragma unroll
@@ -126,7 +134,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
 #pragma unroll
     for (int j = 0; j < S + 2; ++j) fw[j][0] = fw[j][1] = T(0);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) rw[k][0] = rw[k][1] = T(0);
+    for (int k = 0; k < 3; ++k) rw[k][0] = rw[k][1] = mw[k][0] = mw[k][1] = T(0);
 
     const int r_begin = y0 - 2 - S;
     const int r_end = y0 + MSEG + S;
@@ -150,11 +158,11 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
         const long row = (long)rr * g.pitch + ORIGIN;
         sl.f[0] = fr[row + ia];
         sl.f[1] = fr[row + ib];
-        if (MODE == 2 || !XZ) {
+        if (POSTLIKE || !XZ) {
             sl.x[0] = xr[row + ia];
             sl.x[1] = xr[row + ib];
         }
-        if (MODE == 2) {
+        if (POSTLIKE) {
             const int cols[2] = {ia, ib};
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
@@ -172,7 +180,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
             T cx;
-            if (MODE == 2)
+            if (POSTLIKE)
                 cx = sl.x[cc] + T(0.5) * (sl.e0[cc] + sl.e1[cc]);
             else if (!XZ)
                 cx = detach(sl.x[cc]);
@@ -253,6 +261,60 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
                         rw[1][0] + T(0.5) * (rw[1][1] + mid_left + rw[0][0] + rw[2][0] + rw[0][1] + dn_left);
             }
         }
+        if (MODE == 3) {
+            // A u and M u at row r - S - 1 from u = x_S rows (r-S, r-S-1, r-S-2)
+            const int q1 = r - S - 1;
+            const bool row_in = q1 >= 1 && q1 <= g.m;
+            const T m0 = xw[S][1][0], m1 = xw[S][1][1];
+            const T left = from_left(m1), right = from_right(m0);
+            const T up0 = xw[S][0][0], up1 = xw[S][0][1], dn0 = xw[S][2][0], dn1 = xw[S][2][1];
+            const T nb0 = left + m1 + up0 + dn0;
+            const T nb1 = m0 + right + up1 + dn1;
+            // the "/" diagonal: (i + 1, q1 + 1) and (i - 1, q1 - 1)
+            const T ne0 = up1, ne1 = from_right(up0);
+            const T sw0 = from_left(dn1), sw1 = dn0;
+            const T h2 = T(g.h * g.h);
+            T a0 = w0 * (T(4) * m0 - nb0), a1 = w0 * (T(4) * m1 - nb1);
+            T b0 = h2 * (T(0.5) * m0 + (nb0 + ne0 + sw0) * T(1.0 / 12.0));
+            T b1 = h2 * (T(0.5) * m1 + (nb1 + ne1 + sw1) * T(1.0 / 12.0));
+            const bool in0 = row_in && inner[0], in1 = row_in && inner[1];
+            a0 = in0 ? a0 : T(0);
+            a1 = in1 ? a1 : T(0);
+            b0 = in0 ? b0 : T(0);
+            b1 = in1 ? b1 : T(0);
+            if (q1 >= y0 && q1 < y0 + MSEG) {  // this wavefront's own rows (and columns) for the sums
+                if (owned[0]) {
+                    ua += (double)(m0 * a0);
+                    um += (double)(m0 * b0);
+                }
+                if (owned[1]) {
+                    ua += (double)(m1 * a1);
+                    um += (double)(m1 * b1);
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                rw[2][cc] = rw[1][cc];
+                rw[1][cc] = rw[0][cc];
+                mw[2][cc] = mw[1][cc];
+                mw[1][cc] = mw[0][cc];
+            }
+            rw[0][0] = a0;
+            rw[0][1] = a1;
+            mw[0][0] = b0;
+            mw[0][1] = b1;
+            const int q2 = r - S - 2;
+            const T ra = from_left(rw[1][1]), rb = from_left(rw[2][1]);
+            const T ma = from_left(mw[1][1]), mb = from_left(mw[2][1]);
+            if (((q2 & 1) == 0) && q2 >= y0 && q2 < y0 + MSEG && owned[0]) {
+                const int I = i0 >> 1, J = q2 >> 1;
+                if (I >= 1 && I <= gc.m && J >= 1 && J <= gc.m) {
+                    const long cid = (long)z * sc + gc.idx(I, J);
+                    rc[cid] = rw[1][0] + T(0.5) * (rw[1][1] + ra + rw[0][0] + rw[2][0] + rw[0][1] + rb);
+                    rc2[cid] = mw[1][0] + T(0.5) * (mw[1][1] + ma + mw[0][0] + mw[2][0] + mw[0][1] + mb);
+                }
+            }
+        }
     };
 
     Slot q[PF];
@@ -273,6 +335,18 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
             shift_in(q[u % PF]);
             load(r + PF, q[u % PF]);
             advance(r);
+        }
+    }
+    if (MODE == 3) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            ua += __shfl_xor(ua, o, 64);
+            um += __shfl_xor(um, o, 64);
+        }
+        if (lane == 0) {
+            const long b = (long)z * (sh.strips * sh.segs) + (work % (sh.strips * sh.segs));
+            part[2 * b] = ua;
+            part[2 * b + 1] = um;
         }
     }
 }
@@ -311,33 +385,37 @@ MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows) {
     return sh;
 }
 
+// Returns the wavefronts per right-hand side (MODE 3: pairs of sums in part).
 template <typename T, int S, int MODE>
-void march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc,
-                  int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows, hipStream_t st) {
+int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc, T* rc2,
+                 double* part, int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows,
+                 hipStream_t st) {
     constexpr int TXO = MW - 2 * (S + 2);
     static const int slots = device_wave_slots(k_march<T, S, MODE, false>);
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
     if constexpr (MODE == 1) {
         if (x_zero) {
             hipLaunchKernelGGL((k_march<T, S, MODE, true>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
-                               gc, rc, sf, sc, ss, sh);
+                               gc, rc, rc2, part, sf, sc, ss, sh);
             PASM_CHECK_LAUNCH();
-            return;
+            return sh.strips * sh.segs;
         }
     }
     hipLaunchKernelGGL((k_march<T, S, MODE, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
-                       sf, sc, ss, sh);
+                       rc2, part, sf, sc, ss, sh);
     PASM_CHECK_LAUNCH();
+    return sh.strips * sh.segs;
 }
 
 template <typename T, int MODE>
-void march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc,
-                    int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows, hipStream_t st) {
+int march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc,
+                   T* rc2, double* part, int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows,
+                   hipStream_t st) {
     switch (ss.s) {
-        case 1: march_launch<T, 1, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
-        case 2: march_launch<T, 2, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
-        case 3: march_launch<T, 3, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
-        case 4: march_launch<T, 4, MODE>(g, w0, x0, f, out, ec, gc, rc, nrhs, sf, sc, ss, x_zero, rows, st); break;
+        case 1: return march_launch<T, 1, MODE>(g, w0, x0, f, out, ec, gc, rc, rc2, part, nrhs, sf, sc, ss, x_zero, rows, st);
+        case 2: return march_launch<T, 2, MODE>(g, w0, x0, f, out, ec, gc, rc, rc2, part, nrhs, sf, sc, ss, x_zero, rows, st);
+        case 3: return march_launch<T, 3, MODE>(g, w0, x0, f, out, ec, gc, rc, rc2, part, nrhs, sf, sc, ss, x_zero, rows, st);
+        case 4: return march_launch<T, 4, MODE>(g, w0, x0, f, out, ec, gc, rc, rc2, part, nrhs, sf, sc, ss, x_zero, rows, st);
         default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
     }
 }
@@ -354,14 +432,23 @@ bool march_supported(const Grid& g, bool const_coef, int steps) {
 template <typename T>
 void launch_march_pre(const Grid& g, T w0, const T* x0, const T* f, T* out, const Grid& gc, T* rc, int nrhs,
                       const SmoothSteps& ss, bool x_zero, hipStream_t st, int rows) {
-    march_dispatch<T, 1>(g, w0, x0, f, out, (const T*)nullptr, gc, rc, nrhs, g.plane, gc.plane, ss, x_zero, rows,
-                         st);
+    march_dispatch<T, 1>(g, w0, x0, f, out, (const T*)nullptr, gc, rc, (T*)nullptr, nullptr, nrhs, g.plane, gc.plane,
+                         ss, x_zero, rows, st);
 }
 
 template <typename T>
 void launch_march_post(const Grid& g, T w0, const T* x, const T* f, T* out, const Grid& gc, const T* ec, int nrhs,
                        const SmoothSteps& ss, hipStream_t st, int rows) {
-    march_dispatch<T, 2>(g, w0, x, f, out, ec, gc, (T*)nullptr, nrhs, g.plane, gc.plane, ss, false, rows, st);
+    march_dispatch<T, 2>(g, w0, x, f, out, ec, gc, (T*)nullptr, (T*)nullptr, nullptr, nrhs, g.plane, gc.plane, ss,
+                         false, rows, st);
+}
+
+int launch_march_post_border(const Grid& g, double w0, const double* x, const double* f, double* out, const Grid& gc,
+                             const double* ec, double* bc, double* cc, double* partial, int nrhs,
+                             const SmoothSteps& ss, hipStream_t st, int rows) {
+    if (g.dim != 2 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 2D, ratio 2");
+    return march_dispatch<double, 3>(g, w0, x, f, out, ec, gc, bc, cc, partial, nrhs, g.plane, gc.plane, ss, false,
+                                     rows, st);
 }
 
 template void launch_march_pre<double>(const Grid&, double, const double*, const double*, double*, const Grid&,
