@@ -112,6 +112,9 @@ struct pasm_ctx {
     // borders formed by the last V-cycle's fine post-smoothing (2D, FP64)
     bool border_next = false, border_done = false;
     int border_nblk = 0;
+    // F64 holds lambda M u for the current U and lam (formed by the last
+    // step's prolongation); anything else that touches U, lam or F64 clears it
+    bool f_ready = false;
     long lcycles_learned = 0, lcycles_fallback = 0;
     double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
     std::vector<double> lratio; // residual reduction of the last V-cycles (diagnostics)
@@ -759,6 +762,15 @@ void prolong_coefs(pasm_ctx* c, const double* s) {
         pasm::launch_prolong<double>(c->lv[l - 1].g, c->lv[l - 1].B, c->lv[l].g, c->lv[l].B, k, c->lv[l - 1].g.plane,
                                      c->lv[l].g.plane, false, nullptr, c->st);
     const pasm::Level& Lc = c->lv[c->L - 2];
+    if (s && c->dim == 2) {
+        // the new u into the scratch field (then swapped in), with the next
+        // step's right-hand side lambda M u from the same pass
+        pasm::launch_prolong_mass(Lc.g, Lc.B, c->gf(), c->U, c->Y64, c->F64, k, Lc.g.plane, c->sf(), s, c->mu,
+                                  c->st);
+        std::swap(c->U, c->Y64);
+        c->f_ready = true;
+        return;
+    }
     pasm::launch_prolong<double>(Lc.g, Lc.B, c->gf(), c->U, k, Lc.g.plane, c->sf(), false, s, c->st);
 }
 
@@ -766,8 +778,10 @@ void iterate_once(pasm_ctx* c) {
     const int k = c->k, N = c->NH, lf = c->L - 1;
     const Grid& g = c->gf();
     const long sf = c->sf();
-    // Algorithm 1, step 1: f = lambda M u, V-cycles from x = u (in place in U)
-    pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, sf, c->st);
+    // Algorithm 1, step 1: f = lambda M u (unless the previous step's
+    // prolongation formed it), V-cycles from x = u (in place in U)
+    if (!c->f_ready) pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, sf, c->st);
+    c->f_ready = false;
     c->border_done = false;
     if (c->L > 1) {
         bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles, c->dim == 2 && c->L >= 2);
@@ -1083,6 +1097,7 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
 
 PASM_API pasm_status pasm_restart(pasm_ctx* c) {
     if (!c || c->k == 0) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     PASM_TRY(c, {
         const int k = c->k, N = c->NH;
         std::vector<double> th(k);
@@ -1146,6 +1161,7 @@ PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* cc, double* U_dev,
 
 PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const double* U, size_t ldu) {
     if (!c || c->k == 0) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     const size_t N = pasm_num_dofs(c);
     if (!lambda || !U || ldu < N) return PASM_E_INVALID;
     for (int i = 0; i < c->k; ++i)
@@ -1222,6 +1238,7 @@ PASM_API const char* pasm_last_error(const pasm_ctx* c) { return c ? c->err.c_st
 PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const double* x, double* y, size_t ld,
                                          int nrhs) {
     if (!c || c->k == 0) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     if (level < 0 || level >= c->L || nrhs < 1 || nrhs > c->k || !x || !y) return PASM_E_INVALID;
     if (op != PASM_OP_STIFFNESS && op != PASM_OP_MASS) return PASM_E_INVALID;
     if (op == PASM_OP_MASS && level != c->L - 1) return PASM_E_INVALID;
@@ -1242,6 +1259,7 @@ PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const d
 
 PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t ld, int nrhs, int ncycles) {
     if (!c || c->k == 0) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     const Grid& g = c->gf();
     if (!f || !x || nrhs < 1 || nrhs > c->k || ncycles < 0 || ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
@@ -1284,6 +1302,7 @@ PASM_API pasm_status pasm_learned_weights(const pasm_ctx* c, float* w) {
 
 PASM_API pasm_status pasm_learned_set_weights(pasm_ctx* c, const float* w) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     if (!w) return PASM_E_INVALID;
     for (int j = 0; j < 864; ++j)
         if (!std::isfinite(w[j])) return PASM_E_INVALID;
@@ -1296,6 +1315,7 @@ PASM_API pasm_status pasm_learned_set_weights(pasm_ctx* c, const float* w) {
 
 PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* c, double rate) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     if (!std::isfinite(rate)) return PASM_E_INVALID;
     c->lthreshold = rate > 0.0 ? rate : 0.0;
     return PASM_OK;
@@ -1303,12 +1323,14 @@ PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* c, double rate) {
 
 PASM_API pasm_status pasm_learned_enable(pasm_ctx* c, int enable) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     c->learned_on = enable != 0;
     return PASM_OK;
 }
 
 PASM_API pasm_status pasm_learned_train(pasm_ctx* c, int steps, double* hist) {
     if (!c || c->k == 0 || !c->learned || c->ltrain_level < 1) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     if (steps < 0) return PASM_E_INVALID;
     PASM_TRY(c, learned_train(c, steps, hist));
     return PASM_OK;
@@ -1317,6 +1339,7 @@ PASM_API pasm_status pasm_learned_train(pasm_ctx* c, int steps, double* hist) {
 PASM_API pasm_status pasm_learned_step(pasm_ctx* c, int level, const double* x, const double* f, double* out,
                                        size_t ld, int nrhs) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     if (level < 1 || level >= c->L || nrhs < 1 || nrhs > c->k || !x || !f || !out) return PASM_E_INVALID;
     const pasm::Level& L = c->lv[level];
     const Grid& g = L.g;
@@ -1355,6 +1378,7 @@ __global__ void k_compact_d2f(const double* __restrict__ a, long lda, float* __r
 PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* c, int level, const double* r, size_t ld, int ns,
                                             double* loss, double* grad) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (c) c->f_ready = false;
     if (level < 1 || level >= c->L || ns < 1 || ns > 64 || !r || !grad) return PASM_E_INVALID;
     const Grid& g = c->lv[level].g;
     const long vol = g.interior();

@@ -473,10 +473,22 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
     double bs;
     const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const double* ur = u + (long)blockIdx.z * stride;
-    for (int t = tid; t < BUX * BUY; t += 256) {
-        const int a = t % BUX, b = t / BUX;
-        const int i = fi0 - 1 + a, j = fj0 - 1 + b;
-        us[b][a] = (i <= g.n && j <= g.n) ? ur[g.idx(i, j)] : 0.0;
+    {
+        // all of a thread's loads are issued before any of them is used
+        constexpr int NPT = (BUX * BUY + 255) / 256;
+        double v[NPT];
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            const int t = tid + 256 * e;
+            const int a = t % BUX, b = t / BUX;
+            const int i = fi0 - 1 + a, j = fj0 - 1 + b;
+            v[e] = (t < BUX * BUY && i <= g.n && j <= g.n) ? ur[g.idx(i, j)] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            const int t = tid + 256 * e;
+            if (t < BUX * BUY) us[t / BUX][t % BUX] = v[e];
+        }
     }
     __syncthreads();
     const double h2 = g.h * g.h;
@@ -540,6 +552,61 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
         const long blk = (long)blockIdx.z * nblk + blockIdx.y * gridDim.x + blockIdx.x;
         partial[2 * blk] = sh[0] + sh[2] + sh[4] + sh[6];
         partial[2 * blk + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+    }
+}
+
+// Prolongation and combination with the mass right-hand side of the next
+// step in one pass: xn = P xc + beta[r] xo on every fine node, and
+// f = lam[r] M xn on the workgroup's 64 x 16 nodes (xn on their one-node
+// halo is formed again from xo and xc).  xn must not alias xo.
+constexpr int PMX = 64, PMY = 16;
+__global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __restrict__ xc, Grid gf,
+                                                      const double* __restrict__ xo, double* __restrict__ xn,
+                                                      double* __restrict__ f, long sc, long sf,
+                                                      const double* __restrict__ beta,
+                                                      const double* __restrict__ lam) {
+    constexpr int UX = PMX + 2, UY = PMY + 2, NPT = (UX * UY + 255) / 256;
+    __shared__ double us[UY][UX];
+    const int tid = threadIdx.x, z = blockIdx.z;
+    const int i0 = blockIdx.x * PMX + 1, j0 = blockIdx.y * PMY + 1;
+    const double* cr = xc + (long)z * sc;
+    const double* xr = xo + (long)z * sf;
+    const double bz = beta[z], lz = lam[z];
+    double c0[NPT], c1[NPT], xv[NPT];
+    bool ok[NPT];
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+        const int t = tid + 256 * e;
+        const int i = i0 - 1 + t % UX, j = j0 - 1 + t / UX;
+        ok[e] = t < UX * UY && i >= 1 && i <= gf.m && j >= 1 && j <= gf.m;
+        const int ic = ok[e] ? i : 1, jc = ok[e] ? j : 1;
+        const int a = ic & 1, b = jc & 1;
+        const long cid = gc.idx(ic >> 1, jc >> 1);
+        c0[e] = cr[cid];
+        c1[e] = cr[cid + a + (long)b * gc.pitch];
+        xv[e] = xr[gf.idx(ic, jc)];
+    }
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+        const int t = tid + 256 * e;
+        const int i = i0 - 1 + t % UX, j = j0 - 1 + t / UX;
+        double v = c0[e];
+        if ((i | j) & 1) v = 0.5 * (v + c1[e]);
+        v += bz * xv[e];
+        if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
+    }
+    __syncthreads();
+    const double h2 = gf.h * gf.h;
+    for (int t = tid; t < PMX * PMY; t += 256) {
+        const int a = t % PMX, b = t / PMX;
+        const int i = i0 + a, j = j0 + b;
+        if (i > gf.m || j > gf.m) continue;
+        const double x0 = us[b + 1][a + 1];
+        const double sn = us[b + 1][a + 2] + us[b + 1][a] + us[b + 2][a + 1] + us[b][a + 1] + us[b + 2][a + 2] +
+                          us[b][a];
+        const long id = (long)z * sf + gf.idx(i, j);
+        xn[id] = x0;
+        f[id] = lz * (h2 * (0.5 * x0 + sn * (1.0 / 12.0)));
     }
 }
 
@@ -750,6 +817,15 @@ void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs
     if (gf.dim == 3) return launch_prolong3<T>(gc, xc, gf, xf, nrhs, sc, sf, mode, beta, st);
     dim3 grid = grid_for(gf.m, gf.m, nrhs), blk(BX, BY);
     hipLaunchKernelGGL((k_prolong<T>), grid, blk, 0, st, gc, xc, gf, xf, sc, sf, mode, beta);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
+                         double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
+                         hipStream_t st) {
+    if (gf.dim != 2 || gc.n * 2 != gf.n || xn == xo) throw Error(PASM_E_INVALID, "prolong with mass: 2D, ratio 2");
+    dim3 grid((gf.m + PMX - 1) / PMX, (gf.m + PMY - 1) / PMY, nrhs);
+    hipLaunchKernelGGL(k_prolong_mass, grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta, lam);
     PASM_CHECK_LAUNCH();
 }
 
