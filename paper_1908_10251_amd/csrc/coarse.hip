@@ -31,6 +31,8 @@
 #include <algorithm>
 #include <cfloat>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace pasm {
@@ -113,6 +115,119 @@ __global__ __launch_bounds__(64 * WAVES) void k_dmv_part(const T* __restrict__ M
 #pragma unroll
     for (int rr = 0; rr < KB; ++rr)
         if (rr < rn) part[((long)blockIdx.y * nrhs + r0 + rr) * N + row] = acc[rr];
+}
+
+// Double-precision products on the matrix cores (v_mfma_f64_16x16x4_f64):
+// a wavefront owns 64 rows (four 16-row tiles) of a DC-column chunk and 16 NT
+// right-hand sides; per K-step of 4 columns it loads one matrix element per
+// lane and tile (A: lane l holds A[l % 16][l / 16], a coalesced 16-row run
+// of each of 4 columns) and reads the staged x as B (lane l holds
+// B[l / 16][l % 16]); D comes back as D[4 j + l / 16][l % 16].  Partial sums
+// go to part[chunk][row][rhs], summed by k_dmv_sum_rm.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int DMW = 2;  // wavefronts per workgroup (128 rows)
+template <int NT, int DC>
+__global__ __launch_bounds__(64 * DMW) void k_dmv_mfma(const double* __restrict__ Mat, int N, Grid g,
+                                                       const double* __restrict__ x, long sx, int xpad,
+                                                       double* __restrict__ part, int nrhs, int kpm, long mstride) {
+    constexpr int KBP = 16 * NT;
+    constexpr int PF = 4;  // K-steps whose loads are in flight
+    __shared__ double xs[DC][KBP + 1];  // padded rows: the staging stores spread over the banks
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row0 = blockIdx.x * (64 * DMW) + wave * 64;
+    const int c0 = blockIdx.y * DC;
+    const int zb = (kpm + KBP - 1) / KBP;  // workgroups per member
+    const int mem = blockIdx.z / zb;
+    const int rlo = (blockIdx.z % zb) * KBP;
+    const int r0 = mem * kpm + rlo;
+    const int rn = min(KBP, kpm - rlo);
+    Mat += (long)mem * mstride;
+    const int cn = min(DC, N - c0);
+    {
+        // consecutive threads take consecutive columns (coalesced), and a
+        // thread issues a batch of loads before storing any of them
+        constexpr int TPB = 64 * DMW, E = DC * KBP / TPB, BATCH = 8;
+        static_assert(DC % TPB == 0 || TPB % DC == 0, "staging layout");
+        const int cc = threadIdx.x % DC;
+        const long xc = cc < cn ? (xpad ? compact_to_padded(g, c0 + cc) : c0 + cc) : 0;
+        for (int e0 = 0; e0 < E; e0 += BATCH) {
+            double v[BATCH];
+#pragma unroll
+            for (int e = 0; e < BATCH; ++e) {
+                const int rr = (threadIdx.x + TPB * (e0 + e)) / DC;
+                v[e] = (e0 + e < E && rr < rn && cc < cn) ? x[(long)(r0 + rr) * sx + xc] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < BATCH; ++e) {
+                const int rr = (threadIdx.x + TPB * (e0 + e)) / DC;
+                if (e0 + e < E) xs[cc][rr] = v[e];
+            }
+        }
+    }
+    __syncthreads();
+    const int ar = lane & 15, ak = lane >> 4;
+    // rows past N read row N - 1 (never stored); columns past the chunk read
+    // its last column, which meets zeros in xs
+    const double* mp[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) mp[mt] = Mat + (long)c0 * N + min(row0 + 16 * mt + ar, N - 1);
+    f64x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    constexpr int KS = DC / 4;
+    static_assert(KS % PF == 0, "whole prefetch groups");
+    double a[PF][4];
+    auto load = [&](int ks, double* dst) {
+        const long col = min(4 * ks + ak, cn - 1);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) dst[mt] = mp[mt][col * N];
+    };
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load(p, a[p]);
+    for (int k0 = 0; k0 < KS; k0 += PF) {
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int ks = k0 + p;
+            double b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b[nt] = xs[4 * ks + ak][16 * nt + ar];
+            double cur[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) cur[mt] = a[p][mt];
+            load(min(ks + PF, KS - 1), a[p]);  // the slot refills at once
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[mt], b[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int rr = 16 * nt + ar;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = row0 + 16 * mt + 4 * j + ak;
+                if (rr < rn && row < N) part[((long)blockIdx.y * N + row) * nrhs + r0 + rr] = acc[mt][nt][j];
+            }
+        }
+}
+
+// y[r][row] = sum over chunks of part[chunk][row][r]
+__global__ __launch_bounds__(256) void k_dmv_sum_rm(int N, int nchunk, const double* __restrict__ part, int nrhs,
+                                                    Grid g, double* __restrict__ y, long sy, int ypad) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)N * nrhs) return;
+    const int row = (int)(t / nrhs), r = (int)(t % nrhs);
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[(long)c * N * nrhs + t];
+    const long base = (long)r * sy;
+    if (ypad) y[base + compact_to_padded(g, row)] = s;
+    else y[base + row] = s;
 }
 
 template <typename T>
@@ -918,6 +1033,28 @@ void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bo
                      bool y_padded, int nrhs, void* work, hipStream_t st, int kpm, long mstride) {
     if (kpm <= 0) kpm = nrhs;
     if (nrhs % kpm != 0) throw Error(PASM_E_INVALID, "dense products: right-hand sides not a multiple per member");
+    if constexpr (std::is_same<T, double>::value) {
+        if (N >= kDmvBigN) {
+            // large coarse spaces: matrix-core products, 128-column chunks
+            constexpr int DC = 128;
+            const int nchunk = (N + DC - 1) / DC;
+            const int nt = std::min(3, (kpm + 15) / 16);
+            const int zb = (kpm + 16 * nt - 1) / (16 * nt);
+            dim3 grid((N + 64 * DMW - 1) / (64 * DMW), nchunk, (nrhs / kpm) * zb), blk(64 * DMW);
+            double* part = static_cast<double*>(work);
+            switch (nt) {
+                case 1: hipLaunchKernelGGL((k_dmv_mfma<1, DC>), grid, blk, 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs, kpm, mstride); break;
+                case 2: hipLaunchKernelGGL((k_dmv_mfma<2, DC>), grid, blk, 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs, kpm, mstride); break;
+                default: hipLaunchKernelGGL((k_dmv_mfma<3, DC>), grid, blk, 0, st, Mat, N, g, x, sx, (int)x_padded, part, nrhs, kpm, mstride); break;
+            }
+            PASM_CHECK_LAUNCH();
+            const long tot = (long)N * nrhs;
+            hipLaunchKernelGGL(k_dmv_sum_rm, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, N, nchunk, part, nrhs,
+                               g, y, sy, (int)y_padded);
+            PASM_CHECK_LAUNCH();
+            return;
+        }
+    }
     const int kb = std::min(48, (kpm + 3) / 4 * 4);
     const int DC = dmv_chunk(N);
     const int nchunk = (N + DC - 1) / DC;
