@@ -340,7 +340,8 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
             }
         }
         if (!fused_border) pasm::launch_march_post<T>(L.g, (T)L.w0, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
-        if (fine) record_end(c, 3.25 * w * nodes);
+        // x, f, y and the coarse correction; with the borders also b_c, c_c
+        if (fine) record_end(c, (fused_border ? 3.75 : 3.25) * w * nodes);
         std::swap(x, y);
         return;
     }
