@@ -251,6 +251,11 @@ typedef struct pasm_learned_stats {
 
 PASM_API pasm_status pasm_learned_report(const pasm_ctx* ctx, pasm_learned_stats* out);
 PASM_API pasm_status pasm_learned_weights(const pasm_ctx* ctx, float* w);
+/* The most recent per-cycle residual reductions sqrt(|r_new|^2 / |r_old|^2)
+ * of learned V-cycles, one per right-hand side and cycle, oldest first (the
+ * library keeps the last 4096).  Copies at most max into out (host);
+ * returns the count, or -1 for a null context or a null out with max > 0. */
+PASM_API int pasm_learned_ratios(const pasm_ctx* ctx, double* out, int max);
 /* Replace the weights (host [2][16][27]); the stored rates are kept. */
 PASM_API pasm_status pasm_learned_set_weights(pasm_ctx* ctx, const float* w);
 /* Fallback threshold: a learned V-cycle is redone with the plain smoother

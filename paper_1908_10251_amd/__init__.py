@@ -104,6 +104,8 @@ def lib() -> ctypes.CDLL:
     _F = ctypes.POINTER(ctypes.c_float)
     L.pasm_learned_report.argtypes = [_P, ctypes.POINTER(pasm_learned_stats)]
     L.pasm_learned_weights.argtypes = [_P, _F]
+    L.pasm_learned_ratios.argtypes = [_P, _D, ctypes.c_int]
+    L.pasm_learned_ratios.restype = ctypes.c_int
     L.pasm_learned_set_weights.argtypes = [_P, _F]
     L.pasm_learned_train.argtypes = [_P, ctypes.c_int, _D]
     L.pasm_learned_set_threshold.argtypes = [_P, ctypes.c_double]
@@ -367,6 +369,15 @@ def pasm_learned_weights(ctx) -> np.ndarray:
     w = np.empty((2, 16, 27), dtype=np.float32)
     _check(lib().pasm_learned_weights(ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), ctx)
     return w
+
+
+def pasm_learned_ratios(ctx, max_count: int = 4096) -> np.ndarray:
+    """Recent per-cycle, per-right-hand-side residual reductions of learned V-cycles."""
+    out = np.empty(max_count, dtype=np.float64)
+    n = lib().pasm_learned_ratios(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(max_count))
+    if n < 0:
+        raise PasmError(-1, "pasm_learned_ratios: invalid arguments")
+    return out[:n].copy()
 
 
 def pasm_learned_set_weights(ctx, w) -> None:

@@ -115,6 +115,7 @@ struct pasm_ctx {
     // F64 holds lambda M u for the current U and lam (formed by the last
     // step's prolongation); anything else that touches U, lam or F64 clears it
     bool f_ready = false;
+    std::vector<char> lstag;  // per eigenpair: the plain V-cycle stagnated too (learned fallback test)
     long lcycles_learned = 0, lcycles_fallback = 0;
     double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
     std::vector<double> lratio; // residual reduction of the last V-cycles (diagnostics)
@@ -380,8 +381,10 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs)
     pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
 }
 
-// ||f - A x||^2 per right-hand side (finest level, FP64, 3D), to the host
-std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, int nrhs) {
+// ||f - A x||^2 per right-hand side (finest level, FP64, 3D), to the host;
+// ||f||^2 per right-hand side into *fn if given
+std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, int nrhs,
+                                std::vector<double>* fn = nullptr) {
     const Grid& g = c->gf();
     const int nb = pasm::launch_resid_norm3<double>(g, c->lv.back().w0, x, f, c->rnpart, nrhs, g.plane, c->st);
     pasm::launch_reduce_pairs(c->rnpart, nb, c->rnsum, nrhs, c->st);
@@ -390,6 +393,10 @@ std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, i
     PASM_HIP(hipStreamSynchronize(c->st));
     std::vector<double> n(nrhs);
     for (int r = 0; r < nrhs; ++r) n[r] = out[2 * r];
+    if (fn) {
+        fn->resize(nrhs);
+        for (int r = 0; r < nrhs; ++r) (*fn)[r] = out[2 * r + 1];
+    }
     return n;
 }
 
@@ -399,7 +406,7 @@ std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, i
 // right-hand side by less than the plain cycle does (the rate measured at
 // set-up), x is restored and the cycle is redone with the plain smoother.
 void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles,
-                bool border = false) {
+                bool border = false, bool eig = false) {
     if (!c->learned_on) {
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
@@ -411,16 +418,28 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
     }
     const Grid& g = c->gf();
     const size_t bytes = (size_t)g.plane * nrhs * sizeof(double);
-    std::vector<double> n0 = resid_norms(c, x, f, nrhs);
+    std::vector<double> nf;
+    std::vector<double> n0 = resid_norms(c, x, f, nrhs, &nf);
     const double thr = c->lthreshold > 0.0 ? c->lthreshold : c->lplain_rate;
     const double lim = thr * thr;
+    // a residual already at the cycle's rounding level (relative to f) can
+    // not shrink further under any smoother: such right-hand sides do not
+    // count against the learned cycle
+    // (residuals are formed in FP64 in both precisions: defect correction)
+    const double floor2 = (64.0 * DBL_EPSILON) * (64.0 * DBL_EPSILON);
     for (int cy = 0; cy < ncycles; ++cy) {
         PASM_HIP(hipMemcpyAsync(c->Xb, x, bytes, hipMemcpyDeviceToDevice, c->st));
         one_cycle(c, x, scr, f, nrhs);
         std::vector<double> n1 = resid_norms(c, x, f, nrhs);
+        // right-hand sides of the eigen-iteration that the plain cycle could
+        // not reduce either (stagnant: at a floor of the arithmetic) only
+        // must not grow
+        const bool track = eig && (int)c->lstag.size() == nrhs;
         bool worse = false;
         for (int r = 0; r < nrhs; ++r) {
-            worse |= !(n1[r] <= lim * n0[r]) && n0[r] > 0.0;
+            const bool at_floor = n1[r] <= floor2 * nf[r];
+            if (track && c->lstag[r]) worse |= !(n1[r] <= 1.21 * n0[r]);
+            else worse |= !(n1[r] <= lim * n0[r]) && n0[r] > 0.0 && !at_floor;
             if (n0[r] > 0.0) c->lratio.push_back(std::sqrt(n1[r] / n0[r]));
         }
         if (c->lratio.size() > 4096) c->lratio.erase(c->lratio.begin(), c->lratio.end() - 4096);
@@ -431,6 +450,9 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
             c->learned_on = true;
             n1 = resid_norms(c, x, f, nrhs);
             ++c->lcycles_fallback;
+            if (track)
+                for (int r = 0; r < nrhs; ++r)
+                    if (!(n1[r] <= lim * n0[r]) && !(n1[r] <= floor2 * nf[r])) c->lstag[r] = 1;
         } else {
             ++c->lcycles_learned;
         }
@@ -785,7 +807,7 @@ void iterate_once(pasm_ctx* c) {
     c->f_ready = false;
     c->border_done = false;
     if (c->L > 1) {
-        bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles, c->dim == 2 && c->L >= 2);
+        bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles, c->dim == 2 && c->L >= 2, true);
     } else {
         // fine level = V_H: exact solve
         pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->dmv, c->st);
@@ -949,6 +971,7 @@ void learned_rates(pasm_ctx* c) {
 }
 
 void learned_setup(pasm_ctx* c) {
+    c->lstag.assign(c->k, 0);
     c->lw.assign(864, 0.f);
     c->lm.assign(864, 0.0);
     c->lv2.assign(864, 0.0);
@@ -1099,6 +1122,7 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
 PASM_API pasm_status pasm_restart(pasm_ctx* c) {
     if (!c || c->k == 0) return PASM_E_STATE;
     if (c) c->f_ready = false;
+    c->lstag.assign(c->k, 0);
     PASM_TRY(c, {
         const int k = c->k, N = c->NH;
         std::vector<double> th(k);
@@ -1163,6 +1187,7 @@ PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* cc, double* U_dev,
 PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const double* U, size_t ldu) {
     if (!c || c->k == 0) return PASM_E_STATE;
     if (c) c->f_ready = false;
+    c->lstag.assign(c->k, 0);
     const size_t N = pasm_num_dofs(c);
     if (!lambda || !U || ldu < N) return PASM_E_INVALID;
     for (int i = 0; i < c->k; ++i)
@@ -1292,6 +1317,13 @@ PASM_API pasm_status pasm_learned_report(const pasm_ctx* c, pasm_learned_stats* 
     o->cycles_learned = c->lcycles_learned;
     o->cycles_fallback = c->lcycles_fallback;
     return PASM_OK;
+}
+
+PASM_API int pasm_learned_ratios(const pasm_ctx* c, double* out, int max) {
+    if (!c || max < 0 || (max > 0 && !out)) return -1;
+    const int n = (int)std::min<size_t>(c->lratio.size(), (size_t)max);
+    for (int i = 0; i < n; ++i) out[i] = c->lratio[c->lratio.size() - n + i];
+    return n;
 }
 
 PASM_API pasm_status pasm_learned_weights(const pasm_ctx* c, float* w) {

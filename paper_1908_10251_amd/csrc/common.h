@@ -298,7 +298,7 @@ constexpr int kLearnedStepOps = 512;
 template <typename T>
 void launch_learned_step(const Grid& g, T w0, const T* x, const T* f, T* out, int nrhs, long stride,
                          const unsigned long long* ops, bool x_zero, hipStream_t st);
-// partial[rhs][blk][2] = (sum of (f - A x)^2 over the block, 0); returns blocks per rhs
+// partial[rhs][blk][2] = (sum of (f - A x)^2, sum of f^2 over the block); returns blocks per rhs
 template <typename T>
 int launch_resid_norm3(const Grid& g, T w0, const T* x, const T* f, double* partial, int nrhs, long stride,
                        hipStream_t st);

@@ -717,11 +717,11 @@ namespace {
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_norm3(Grid g, T w0, const T* __restrict__ x, const T* __restrict__ f,
                                                      long stride, double* __restrict__ partial) {
-    __shared__ double sh[4];
+    __shared__ double sh[8];
     const long n = (long)g.m * g.m * g.m;
     const long u = (long)blockIdx.x * 256 + threadIdx.x;
     const long off = (long)blockIdx.y * stride;
-    double q = 0.0;
+    double q = 0.0, qf = 0.0;
     if (u < n) {
         const int i = (int)(u % g.m) + 1, j = (int)((u / g.m) % g.m) + 1, l = (int)(u / ((long)g.m * g.m)) + 1;
         const long id = off + g.idx(i, j, l);
@@ -730,14 +730,21 @@ __global__ __launch_bounds__(256) void k_resid_norm3(Grid g, T w0, const T* __re
                                         (double)x[id - sy] - (double)x[id + sy] - (double)x[id - sz] - (double)x[id + sz]);
         const double r = (double)f[id] - Ax;
         q = r * r;
+        qf = (double)f[id] * (double)f[id];
     }
-    for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+    for (int o = 32; o > 0; o >>= 1) {
+        q += __shfl_down(q, o, 64);
+        qf += __shfl_down(qf, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = q;
+        sh[4 + (threadIdx.x >> 6)] = qf;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
         partial[2 * b] = sh[0] + sh[1] + sh[2] + sh[3];
-        partial[2 * b + 1] = 0.0;
+        partial[2 * b + 1] = sh[4] + sh[5] + sh[6] + sh[7];
     }
 }
 
