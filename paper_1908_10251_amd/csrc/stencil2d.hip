@@ -167,24 +167,39 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> cg, const 
             idg[r] = T(1) / D;
         }
     }
+    // x and f of the next right-hand side are loaded while this one is
+    // smoothed: unconditional loads from clamped positions (the values off
+    // the interior are replaced by zeros when they are used)
+    long rid[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+        rid[r] = g.idx(min(max(i, 1), g.m), min(max(jb + ty + 4 * r, 1), g.m));
+    const T* xsrc = x_zero ? f : x0;
+    T nf[ROWS], nx[ROWS];
+    auto fetch = [&](int rhs) {
+        const long off = (long)rhs * stride;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            nf[r] = f[off + rid[r]];
+            nx[r] = xsrc[off + rid[r]];
+        }
+    };
+    fetch(r0);
     for (int rhs = r0; rhs < r1; ++rhs) {
         const long off = (long)rhs * stride;
         T fr[ROWS], xc[ROWS], xp[ROWS];
         __syncthreads();  // the previous right-hand side is done with sa / sb
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const int ly = ty + 4 * r, j = jb + ly;
-            T xv = T(0), fv = T(0);
-            if (inn[r]) {
-                const long id = off + g.idx(i, j);
-                fv = f[id];
-                if (!x_zero) xv = x0[id];
-            }
+            const int ly = ty + 4 * r;
+            const T fv = inn[r] ? nf[r] : T(0);
+            const T xv = (inn[r] && !x_zero) ? nx[r] : T(0);
             fr[r] = fv;
             xc[r] = xv;
             xp[r] = xv;
             sa[ly * W + tx] = xv;
         }
+        if (rhs + 1 < r1) fetch(rhs + 1);
         __syncthreads();
         T* cur = sa;
         T* nxt = sb;
