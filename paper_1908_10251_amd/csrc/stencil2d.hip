@@ -170,10 +170,10 @@ __global__ __launch_bounds__(256) void k_smooth_fused(Grid g, Coef<T> cg, const 
     // x and f of the next right-hand side are loaded while this one is
     // smoothed: unconditional loads from clamped positions (the values off
     // the interior are replaced by zeros when they are used)
-    long rid[ROWS];
+    int rid[ROWS];  // offsets within one right-hand side's block (< 2^31)
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
-        rid[r] = g.idx(min(max(i, 1), g.m), min(max(jb + ty + 4 * r, 1), g.m));
+        rid[r] = (int)g.idx(min(max(i, 1), g.m), min(max(jb + ty + 4 * r, 1), g.m));
     const T* xsrc = x_zero ? f : x0;
     T nf[ROWS], nx[ROWS];
     auto fetch = [&](int rhs) {
