@@ -223,8 +223,17 @@ __global__ __launch_bounds__(256) void k_dmv_sum_rm(int N, int nchunk, const dou
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long)N * nrhs) return;
     const int row = (int)(t / nrhs), r = (int)(t % nrhs);
+    const long cs = (long)N * nrhs;
     double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += part[(long)c * N * nrhs + t];
+    int c = 0;
+    for (; c + 8 <= nchunk; c += 8) {  // eight loads in flight, summed in chunk order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(c + u) * cs + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nchunk; ++c) s += part[c * cs + t];
     const long base = (long)r * sy;
     if (ypad) y[base + compact_to_padded(g, row)] = s;
     else y[base + row] = s;
@@ -874,9 +883,10 @@ __global__ __launch_bounds__(64) void k_arrow_near_cert(ArrowIn in, double* work
 }
 
 // Stage C, one block per eigenpair: final choice, rank, new coefficients.
-__global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, double* work, int* iwork, double* best,
+constexpr int PF_T = 1024;  // threads of the final stage
+__global__ __launch_bounds__(PF_T) void k_arrow_final(ArrowIn in, ArrowOut out, double* work, int* iwork, double* best,
                                                     int nchunk) {
-    __shared__ double sh[8];
+    __shared__ double sh[PF_T / 64];
     __shared__ double win[4];  // score, mu, kind (0 root, 1 deflated), id
     __shared__ int rk;
     const int r = blockIdx.x, N = in.N;
@@ -928,10 +938,10 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
     int cntb = 0;
     if (na >= 0) {
         const int nroots = na == 0 ? 1 : na + 1;
-        for (int t = threadIdx.x; t < nroots; t += PT)
+        for (int t = threadIdx.x; t < nroots; t += PF_T)
             if (is_root ? t < id : w.rmu[t] < mu) ++cntb;
     }
-    for (int j = threadIdx.x; j < N; j += PT) {
+    for (int j = threadIdx.x; j < N; j += PF_T) {
         if (in.group[j] != j || in.theta[j] >= mu) continue;
         int e = j + 1;
         while (e < N && in.group[e] == j) ++e;
@@ -946,17 +956,17 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
     if (is_root) {
         if (na == 0) {
             t = 1.0;
-            for (int j = threadIdx.x; j < N; j += PT) y[j] = 0.0;
+            for (int j = threadIdx.x; j < N; j += PF_T) y[j] = 0.0;
         } else {
             const double tau = w.rtau[id], org = w.rorg[id];
             double s1 = 0.0;
-            for (int a = threadIdx.x; a < na; a += PT) {
+            for (int a = threadIdx.x; a < na; a += PF_T) {
                 const double v = w.z[a] / (tau - (w.d[a] - org));
                 s1 += v * v;
             }
-            s1 = block_sum(s1, sh);
+            s1 = block_sum_n<PF_T / 64>(s1, sh);
             t = 1.0 / sqrt(1.0 + s1);
-            for (int j = threadIdx.x; j < N; j += PT) {
+            for (int j = threadIdx.x; j < N; j += PF_T) {
                 const int a = w.amap[j];
                 y[j] = a < 0 ? 0.0 : w.g[j] * t / (tau - (w.d[a] - org));
             }
@@ -979,18 +989,18 @@ __global__ __launch_bounds__(PT) void k_arrow_final(ArrowIn in, ArrowOut out, do
             nrm2 += v * v;
         }
         const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-        for (int j = threadIdx.x; j < N; j += PT)
+        for (int j = threadIdx.x; j < N; j += PF_T)
             y[j] = (j >= lead && j < e) ? (q[j] - coef * w.g[j]) * inv : 0.0;
     }
     __syncthreads();
     // signed score, then y' = y - (t / sq) q and s = t / sq
     double ys = 0.0;
-    for (int j = threadIdx.x; j < N; j += PT) ys += y[j] * q[j];
-    ys = block_sum(ys, sh);
+    for (int j = threadIdx.x; j < N; j += PF_T) ys += y[j] * q[j];
+    ys = block_sum_n<PF_T / 64>(ys, sh);
     const double signed_score = ys + t * sq;
     const double sgn = signed_score < 0.0 ? -1.0 : 1.0;
     const double s = (sq > 0.0) ? t / sq : 0.0;
-    for (int j = threadIdx.x; j < N; j += PT) y[j] = sgn * (y[j] - s * q[j]);
+    for (int j = threadIdx.x; j < N; j += PF_T) y[j] = sgn * (y[j] - s * q[j]);
     __syncthreads();
     if (threadIdx.x == 0) {
         out.s[r] = sgn * s;
@@ -1117,7 +1127,7 @@ void launch_arrowhead(const ArrowIn& in0, const ArrowOut& out, int k, hipStream_
         hipLaunchKernelGGL((k_arrow_roots<0, false>), dim3(k, nchunk), dim3(RW * RWAVES), 0, st, in, work, iwork,
                            best, nchunk);
     PASM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_arrow_final, dim3(k), dim3(PT), 0, st, in, out, work, iwork, best, nchunk);
+    hipLaunchKernelGGL(k_arrow_final, dim3(k), dim3(PF_T), 0, st, in, out, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();
 }
 
