@@ -812,15 +812,17 @@ void iterate_once(pasm_ctx* c) {
         // fine level = V_H: exact solve
         pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->dmv, c->st);
     }
-    // step 2: borders (2D: fused with the first restriction)
+    // step 2: borders, fused with the first restriction
     const double* bsrc = c->Y64;
     const double* csrc = c->R64;
     int lstart = c->L - 2;
-    if (c->dim == 2 && c->L >= 2) {
+    if (c->L >= 2) {
         pasm::Level& Lc = c->lv[c->L - 2];
-        const int nblk = c->border_done ? c->border_nblk
-                                        : pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
-                                                                       c->partial, k, sf, Lc.g.plane, c->st);
+        const int nblk = c->border_done   ? c->border_nblk
+                         : c->dim == 2    ? pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B,
+                                                                         Lc.C, c->partial, k, sf, Lc.g.plane, c->st)
+                                          : pasm::launch_border_restrict3(g, c->coef<double>(lf), c->U, Lc.g, Lc.B,
+                                                                          Lc.C, c->partial, k, sf, Lc.g.plane, c->st);
         pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
         bsrc = Lc.B;
         csrc = Lc.C;

@@ -198,6 +198,11 @@ void launch_add_correction(const double* e, double* u, long n, hipStream_t st);
 
 // Border sweep: au = A u, mu = M u, partial[r][blk][2] = block sums of
 // (u . au, u . mu).  Returns the number of blocks per right-hand side.
+// 3D: b_c = P^T A u, c_c = P^T M u on the next coarser grid and the pairs
+// (u.Au, u.Mu) per workgroup in partial (through an LDS tile); returns the
+// pairs per right-hand side
+int launch_border_restrict3(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
+                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st);
 int launch_border(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
                   double* partial, int nrhs, long stride, hipStream_t st);
 

@@ -136,6 +136,127 @@ __global__ __launch_bounds__(BX* BY) void k_restrict3(Grid gf, const T* __restri
     xc[(long)p.r * sc + gc.idx(p.i, p.j, p.l)] = xr[id0] + T(0.5) * s;
 }
 
+// Restriction through an LDS tile: a workgroup owns 8 x 8 x 4 coarse nodes,
+// stages x on the 19 x 19 x 11 fine nodes around them once, forms the fine
+// values v on the 17 x 17 x 9 nodes their restriction reaches, and restricts
+// from LDS (centre 1, the 14 Kuhn-edge neighbours 1/2).
+//   MODE 0: v = f - A x (the residual restriction of a V-cycle);
+//   MODE 1 (double): v = A u and w = M u, both restricted, and the sums u.Au,
+//           u.Mu over the workgroup's own fine nodes (the first 16 x 16 x 8 of
+//           the 17 x 17 x 9; coarse nodes up to nc over the grid, so every
+//           fine interior node is counted once), one pair per workgroup.
+constexpr int RCX = 8, RCY = 8, RCZ = 4;                                 // coarse nodes per workgroup
+constexpr int RFX = 2 * RCX + 1, RFY = 2 * RCY + 1, RFZ = 2 * RCZ + 1;   // fine nodes with values
+constexpr int RUX = RFX + 2, RUY = RFY + 2, RUZ = RFZ + 2;               // fine nodes of x (halo 1)
+template <typename T, int MODE, bool CONST>
+__global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, const T* __restrict__ x,
+                                                        const T* __restrict__ f, Grid gc, T* __restrict__ oc,
+                                                        T* __restrict__ oc2, double* __restrict__ partial, long sf,
+                                                        long sc, int zblocks) {
+    constexpr int NU = RUX * RUY * RUZ, NV = RFX * RFY * RFZ, NPT = (NU + 255) / 256;
+    __shared__ T us[NU];
+    __shared__ T vs[NV];
+    __shared__ T ws[MODE == 1 ? NV : 1];
+    __shared__ double sh[8];
+    const int tid = threadIdx.x;
+    const int zb = blockIdx.z % zblocks, r = blockIdx.z / zblocks;
+    const int I0 = blockIdx.x * RCX + 1, J0 = blockIdx.y * RCY + 1, K0 = zb * RCZ + 1;
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1, fk0 = 2 * K0 - 1;  // first fine node with a value
+    const T* xr = x + (long)r * sf;
+    const long py = gf.pitch, pz = (long)gf.pitch * (gf.n + 1);
+    {
+        T v[NPT];
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            const int t = tid + 256 * e;
+            const int a = t % RUX, b = (t / RUX) % RUY, cz = t / (RUX * RUY);
+            const int i = min(fi0 - 1 + a, gf.n), j = min(fj0 - 1 + b, gf.n), k = min(fk0 - 1 + cz, gf.n);
+            v[e] = xr[gf.idx(i, j, k)];
+            if (t >= NU || fi0 - 1 + a > gf.n || fj0 - 1 + b > gf.n || fk0 - 1 + cz > gf.n) v[e] = T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < NPT; ++e)
+            if (tid + 256 * e < NU) us[tid + 256 * e] = v[e];
+    }
+    __syncthreads();
+    const T* fr = MODE == 0 ? f + (long)r * sf : nullptr;
+    double ua = 0.0, um = 0.0;
+    const double h3 = gf.h * gf.h * gf.h;
+    for (int t = tid; t < NV; t += 256) {
+        const int a = t % RFX, b = (t / RFX) % RFY, cz = t / (RFX * RFY);
+        const int i = fi0 + a, j = fj0 + b, k = fk0 + cz;
+        T val = T(0), wal = T(0);
+        if (i <= gf.m && j <= gf.m && k <= gf.m) {
+            const int q = ((cz + 1) * RUY + (b + 1)) * RUX + (a + 1);
+            constexpr int QY = RUX, QZ = RUX * RUY;
+            const T x0 = us[q];
+            const T xe = us[q + 1], xw = us[q - 1], xn = us[q + QY], xs = us[q - QY], xu = us[q + QZ], xd = us[q - QZ];
+            T Ax;
+            if (CONST) {
+                Ax = c.w0 * (T(6) * x0 - (xe + xw + xn + xs + xu + xd));
+            } else {
+                const long id = gf.idx(i, j, k);
+                const T w1 = c.wx[id], w2 = c.wx[id - 1], w3 = c.wy[id], w4 = c.wy[id - py], w5 = c.wz[id],
+                        w6 = c.wz[id - pz];
+                Ax = (w1 + w2 + w3 + w4 + w5 + w6) * x0 - w1 * xe - w2 * xw - w3 * xn - w4 * xs - w5 * xu - w6 * xd;
+            }
+            if (MODE == 0) {
+                val = fr[gf.idx(i, j, k)] - Ax;
+            } else {
+                const T ax = xe + xw + xn + xs + xu + xd;
+                const T fd = us[q + 1 + QY] + us[q - 1 - QY] + us[q + 1 + QZ] + us[q - 1 - QZ] + us[q + QY + QZ] +
+                             us[q - QY - QZ];
+                const T bd = us[q + 1 + QY + QZ] + us[q - 1 - QY - QZ];
+                val = Ax;
+                wal = (T)h3 * (T(0.4) * x0 + (ax + bd) * T(1.0 / 20.0) + fd * T(1.0 / 30.0));
+                if (a < 2 * RCX && b < 2 * RCY && cz < 2 * RCZ) {  // own node
+                    ua += (double)(x0 * val);
+                    um += (double)(x0 * wal);
+                }
+            }
+        }
+        vs[t] = val;
+        if (MODE == 1) ws[t] = wal;
+    }
+    __syncthreads();
+    {
+        const int cx = tid % RCX, cy = (tid / RCX) % RCY, cz = tid / (RCX * RCY);
+        const int I = I0 + cx, J = J0 + cy, K = K0 + cz;
+        if (I <= gc.m && J <= gc.m && K <= gc.m) {
+            const int q = ((2 * cz + 1) * RFY + (2 * cy + 1)) * RFX + (2 * cx + 1);
+            T sv = T(0), sw = T(0);
+#pragma unroll
+            for (int t = 0; t < 14; ++t) {
+                const int o = (t >> 1) + 1;
+                const int d = ((o & 1) ? 1 : 0) + ((o & 2) ? RFX : 0) + ((o & 4) ? RFX * RFY : 0);
+                const int qq = (t & 1) ? q - d : q + d;
+                sv += vs[qq];
+                if (MODE == 1) sw += ws[qq];
+            }
+            const long cid = (long)r * sc + gc.idx(I, J, K);
+            oc[cid] = vs[q] + T(0.5) * sv;
+            if (MODE == 1) oc2[cid] = ws[q] + T(0.5) * sw;
+        }
+    }
+    if (MODE == 1) {
+        for (int o = 32; o > 0; o >>= 1) {
+            ua += __shfl_down(ua, o, 64);
+            um += __shfl_down(um, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            sh[2 * (tid >> 6)] = ua;
+            sh[2 * (tid >> 6) + 1] = um;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const long per = (long)gridDim.x * gridDim.y * zblocks;  // workgroups per right-hand side
+            const long b = (long)r * per + ((long)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            partial[2 * b] = sh[0] + sh[2] + sh[4] + sh[6];
+            partial[2 * b + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(BX* BY) void k_prolong3(Grid gc, const T* __restrict__ xc, Grid gf,
                                                      T* __restrict__ xf, long sc, long sf, int mode,
@@ -265,6 +386,18 @@ void launch_apply_A3(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs
 template <typename T>
 void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc, T* rc,
                             int nrhs, long sf, long sc, hipStream_t st) {
+    if (gc.n * 2 == gf.n) {  // the tiled form (ratio 2, which every hierarchy here has)
+        const int zb = (gc.m + RCZ - 1) / RCZ;
+        dim3 grid((gc.m + RCX - 1) / RCX, (gc.m + RCY - 1) / RCY, zb * nrhs);
+        if (c.wx)
+            hipLaunchKernelGGL((k_tile_restrict3<T, 0, false>), grid, dim3(256), 0, st, gf, c, x, f, gc, rc,
+                               (T*)nullptr, nullptr, sf, sc, zb);
+        else
+            hipLaunchKernelGGL((k_tile_restrict3<T, 0, true>), grid, dim3(256), 0, st, gf, c, x, f, gc, rc,
+                               (T*)nullptr, nullptr, sf, sc, zb);
+        PASM_CHECK_LAUNCH();
+        return;
+    }
     if (c.wx)
         hipLaunchKernelGGL((k_resid_restrict3<T, false>), grid3(gc.m, nrhs), dim3(BX, BY), 0, st, gf, c, x, f,
                            gc, rc, sf, sc);
@@ -272,6 +405,22 @@ void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const 
         hipLaunchKernelGGL((k_resid_restrict3<T, true>), grid3(gc.m, nrhs), dim3(BX, BY), 0, st, gf, c, x, f,
                            gc, rc, sf, sc);
     PASM_CHECK_LAUNCH();
+}
+
+int launch_border_restrict3(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
+                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st) {
+    if (g.dim != 3 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 3D, ratio 2");
+    // coarse nodes up to nc (not only the interior ones) own fine nodes for the sums
+    const int zb = (gc.n + RCZ - 1) / RCZ;
+    dim3 grid((gc.n + RCX - 1) / RCX, (gc.n + RCY - 1) / RCY, zb * nrhs);
+    if (c.wx)
+        hipLaunchKernelGGL((k_tile_restrict3<double, 1, false>), grid, dim3(256), 0, st, g, c, u, (const double*)nullptr,
+                           gc, bc, cc, partial, stride, sc, zb);
+    else
+        hipLaunchKernelGGL((k_tile_restrict3<double, 1, true>), grid, dim3(256), 0, st, g, c, u, (const double*)nullptr,
+                           gc, bc, cc, partial, stride, sc, zb);
+    PASM_CHECK_LAUNCH();
+    return (int)(grid.x * grid.y * zb);
 }
 
 template <typename T>
