@@ -785,7 +785,7 @@ void prolong_coefs(pasm_ctx* c, const double* s) {
         pasm::launch_prolong<double>(c->lv[l - 1].g, c->lv[l - 1].B, c->lv[l].g, c->lv[l].B, k, c->lv[l - 1].g.plane,
                                      c->lv[l].g.plane, false, nullptr, c->st);
     const pasm::Level& Lc = c->lv[c->L - 2];
-    if (s && c->dim == 2) {
+    if (s) {
         // the new u into the scratch field (then swapped in), with the next
         // step's right-hand side lambda M u from the same pass
         pasm::launch_prolong_mass(Lc.g, Lc.B, c->gf(), c->U, c->Y64, c->F64, k, Lc.g.plane, c->sf(), s, c->mu,

@@ -160,7 +160,10 @@ template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
                            T* rc, int nrhs, long sf, long sc, hipStream_t st);
 
-// xn = P xc + beta[r] xo and f = lam[r] M xn (2D, double; xn != xo)
+void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
+                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
+                          hipStream_t st);
+// xn = P xc + beta[r] xo and f = lam[r] M xn (double; xn != xo)
 void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                          hipStream_t st);

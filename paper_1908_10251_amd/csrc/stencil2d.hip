@@ -838,7 +838,8 @@ void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs
 void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                          hipStream_t st) {
-    if (gf.dim != 2 || gc.n * 2 != gf.n || xn == xo) throw Error(PASM_E_INVALID, "prolong with mass: 2D, ratio 2");
+    if (gc.n * 2 != gf.n || xn == xo) throw Error(PASM_E_INVALID, "prolong with mass: ratio 2, separate output");
+    if (gf.dim == 3) return launch_prolong_mass3(gc, xc, gf, xo, xn, f, nrhs, sc, sf, beta, lam, st);
     dim3 grid((gf.m + PMX - 1) / PMX, (gf.m + PMY - 1) / PMY, nrhs);
     hipLaunchKernelGGL(k_prolong_mass, grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta, lam);
     PASM_CHECK_LAUNCH();

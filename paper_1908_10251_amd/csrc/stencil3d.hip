@@ -257,6 +257,68 @@ __global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, cons
     }
 }
 
+// Prolongation and combination with the mass right-hand side of the next
+// step (3D): xn = P xc + beta[r] xo on every fine node, and f = lam[r] M xn on
+// the workgroup's 32 x 8 x 4 nodes (xn on their one-node halo is formed again
+// from xo and xc).  xn must not alias xo.
+constexpr int QMX = 32, QMY = 8, QMZ = 4;
+__global__ __launch_bounds__(256) void k_prolong_mass3(Grid gc, const double* __restrict__ xc, Grid gf,
+                                                       const double* __restrict__ xo, double* __restrict__ xn,
+                                                       double* __restrict__ f, long sc, long sf,
+                                                       const double* __restrict__ beta,
+                                                       const double* __restrict__ lam, int zblocks) {
+    constexpr int UX = QMX + 2, UY = QMY + 2, UZ = QMZ + 2, NU = UX * UY * UZ, NPT = (NU + 255) / 256;
+    __shared__ double us[NU];
+    const int tid = threadIdx.x;
+    const int zb = blockIdx.z % zblocks, r = blockIdx.z / zblocks;
+    const int i0 = blockIdx.x * QMX + 1, j0 = blockIdx.y * QMY + 1, k0 = zb * QMZ + 1;
+    const double* cr = xc + (long)r * sc;
+    const double* xr = xo + (long)r * sf;
+    const double bz = beta[r], lz = lam[r];
+    const long cpz = (long)gc.pitch * (gc.n + 1);
+    {
+        double c0[NPT], c1[NPT], xv[NPT];
+        bool ok[NPT];
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            const int t = tid + 256 * e;
+            const int i = i0 - 1 + t % UX, j = j0 - 1 + (t / UX) % UY, k = k0 - 1 + t / (UX * UY);
+            ok[e] = t < NU && i >= 1 && i <= gf.m && j >= 1 && j <= gf.m && k >= 1 && k <= gf.m;
+            const int ic = ok[e] ? i : 1, jc = ok[e] ? j : 1, kc = ok[e] ? k : 1;
+            const long cid = gc.idx(ic >> 1, jc >> 1, kc >> 1);
+            c0[e] = cr[cid];
+            c1[e] = cr[cid + (ic & 1) + (long)(jc & 1) * gc.pitch + (long)(kc & 1) * cpz];
+            xv[e] = xr[gf.idx(ic, jc, kc)];
+        }
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            const int t = tid + 256 * e;
+            const int i = i0 - 1 + t % UX, j = j0 - 1 + (t / UX) % UY, k = k0 - 1 + t / (UX * UY);
+            double v = c0[e];
+            if ((i | j | k) & 1) v = 0.5 * (v + c1[e]);
+            v += bz * xv[e];
+            if (t < NU) us[t] = ok[e] ? v : 0.0;
+        }
+    }
+    __syncthreads();
+    const double h3 = gf.h * gf.h * gf.h;
+    constexpr int QY = UX, QZ = UX * UY;
+    for (int t = tid; t < QMX * QMY * QMZ; t += 256) {
+        const int a = t % QMX, b = (t / QMX) % QMY, cz = t / (QMX * QMY);
+        const int i = i0 + a, j = j0 + b, k = k0 + cz;
+        if (i > gf.m || j > gf.m || k > gf.m) continue;
+        const int q = ((cz + 1) * UY + (b + 1)) * UX + (a + 1);
+        const double x0 = us[q];
+        const double ax = us[q + 1] + us[q - 1] + us[q + QY] + us[q - QY] + us[q + QZ] + us[q - QZ];
+        const double fd = us[q + 1 + QY] + us[q - 1 - QY] + us[q + 1 + QZ] + us[q - 1 - QZ] + us[q + QY + QZ] +
+                          us[q - QY - QZ];
+        const double bd = us[q + 1 + QY + QZ] + us[q - 1 - QY - QZ];
+        const long id = (long)r * sf + gf.idx(i, j, k);
+        xn[id] = x0;
+        f[id] = lz * (h3 * (0.4 * x0 + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0)));
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(BX* BY) void k_prolong3(Grid gc, const T* __restrict__ xc, Grid gf,
                                                      T* __restrict__ xf, long sc, long sf, int mode,
@@ -435,6 +497,15 @@ template <typename T>
 void launch_restrict3(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrhs, long sf, long sc,
                       hipStream_t st) {
     hipLaunchKernelGGL((k_restrict3<T>), grid3(gc.m, nrhs), dim3(BX, BY), 0, st, gf, xf, gc, xc, sf, sc);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
+                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
+                          hipStream_t st) {
+    const int zb = (gf.m + QMZ - 1) / QMZ;
+    dim3 grid((gf.m + QMX - 1) / QMX, (gf.m + QMY - 1) / QMY, zb * nrhs);
+    hipLaunchKernelGGL(k_prolong_mass3, grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta, lam, zb);
     PASM_CHECK_LAUNCH();
 }
 
