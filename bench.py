@@ -48,7 +48,8 @@ KERNEL_NAMES = {
     2: "finest-level smoothing phases (k_march: pre-smoothing with fused residual restriction, "
        "post-smoothing with fused prolongation, the last one also forming the borders; k_smooth_fused where "
        "coefficients vary)",
-    3: "finest-level smoothing sweeps (k_smooth3)",
+    3: "finest-level smoothing phases (k_march3: all steps of a phase in one pass marching along z, "
+       "post-smoothing with fused prolongation)",
     "learned": "finest-level learned smoothing step (k_learned_step: residual, two bfloat16 matrix-core "
                "convolutions, update)",
     "batch": "finest batched level smoothing phases (k_smooth_fused, general 7-point operators)",

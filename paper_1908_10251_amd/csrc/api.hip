@@ -346,6 +346,23 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         std::swap(x, y);
         return;
     }
+    if (c->fuse && !c->learned_on && pasm::march3_supported(L.g, L.const_coef, (int)L.pre.size()) &&
+        pasm::march3_supported(L.g, L.const_coef, (int)L.post.size())) {
+        // 3D marching phases: all steps of a phase in one pass, the
+        // prolongation fused into post-smoothing
+        const double nodes = (double)L.g.interior() * nrhs, w = sizeof(T);
+        if (fine) record_start(c);
+        pasm::launch_march3_smooth<T>(L.g, (T)L.w0, x, f, y, nrhs, to_steps(L.pre), x_zero, c->st);
+        if (fine) record_end(c, (x_zero ? 2.0 : 3.0) * w * nodes);
+        std::swap(x, y);
+        pasm::launch_resid_restrict<T>(L.g, c->coef<T>(l), x, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
+        vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
+        if (fine) record_start(c);
+        pasm::launch_march3_post<T>(L.g, (T)L.w0, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
+        if (fine) record_end(c, 3.125 * w * nodes);
+        std::swap(x, y);
+        return;
+    }
     smooth<T>(c, l, x, y, f, L.pre, x_zero, nrhs);
     const bool zero_after_pre = x_zero && L.pre.empty();
     if (zero_after_pre) {

@@ -156,6 +156,16 @@ int launch_march_post_border(const Grid& g, double w0, const double* x, const do
                              const double* ec, double* bc, double* cc, double* partial, int nrhs,
                              const SmoothSteps& ss, hipStream_t st, int rows = 0);
 
+// Marching smoothing phases (3D, constant coefficients, 128 cells per side,
+// 1 or 2 steps): out = x_s from x0 (or from 0), or (post) from x + P ec.
+bool march3_supported(const Grid& g, bool const_coef, int steps);
+template <typename T>
+void launch_march3_smooth(const Grid& g, T w0, const T* x0, const T* f, T* out, int nrhs, const SmoothSteps& ss,
+                          bool x_zero, hipStream_t st);
+template <typename T>
+void launch_march3_post(const Grid& g, T w0, const T* x, const T* f, T* out, const Grid& gc, const T* ec, int nrhs,
+                        const SmoothSteps& ss, hipStream_t st);
+
 template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
                            T* rc, int nrhs, long sf, long sc, hipStream_t st);

@@ -138,6 +138,48 @@ def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, pot, precision, f
                 assert err < tol, (ncyc, r, err)
 
 
+_HIER_3D = {}
+
+
+def _hier_3d(nc, nf):
+    # stiffness from its stencil (pinned to the assembly in test_oracle_fem.py):
+    # assembling 128^3 element by element takes minutes
+    if (nc, nf) not in _HIER_3D:
+        from stencil_ops import constant_stiffness_3d
+        _HIER_3D[(nc, nf)] = Hierarchy(3, constant_stiffness_3d(nf), nc, nf)
+    return _HIER_3D[(nc, nf)]
+
+
+@pytest.mark.parametrize("smoother,nu", [("jacobi", 2), ("cheb", 2), ("jacobi", 1)])
+@pytest.mark.parametrize("precision", [P.PASM_FP64, P.PASM_MIXED])
+@pytest.mark.parametrize("fused", [True, False])
+def test_vcycle_3d_128_matches_oracle(smoother, nu, precision, fused):
+    # 128 cells per side: with fusion the finest level takes the marching
+    # smoother (slabs of 32 rows overlapping by 2 nu, 127 rows leave a ragged
+    # last slab); FP64 V-cycles start from a nonzero x, mixed ones from 0
+    nc, nf, k = 8, 128, 2
+    _say(f"vcycle 3d H=1/{nc} h=1/{nf} {smoother} nu={nu} prec={precision} fused={fused}")
+    hier = _hier_3d(nc, nf)
+    opts = default_options(3, smoother, nu, nu, 1)
+    rng = np.random.default_rng(11)
+    N = hier.levels[-1].A.shape[0]
+    f = rng.standard_normal((k, N))
+    x0 = rng.standard_normal((k, N))
+    with P.Solver(3, 1 / nc, 1 / nf, k, opts=_opts(smoother, nu, precision=precision, fused=fused)) as s:
+        for ncyc in (2, 1):
+            xg = _t(x0)
+            P.pasm_vcycle(s.ctx, _t(f), xg, ncyc)
+            xg = xg.cpu().numpy()
+            for r in range(k):
+                xr = x0[r].copy()
+                for _ in range(ncyc):
+                    xr = hier.vcycle(len(hier.levels) - 1, xr, f[r], opts)
+                err = np.max(np.abs(xg[r] - xr)) / np.max(np.abs(xr))
+                tol = 1e-12 * (nf / 64) ** 2 if precision == P.PASM_FP64 else 2e-5
+                _say(f"  ncyc={ncyc} rhs={r} err={err:.2e} tol={tol:.1e}")
+                assert err < tol, (ncyc, r, err)
+
+
 def _clusters(vals, rtol=1e-10):
     out, cur = [], [0]
     for i in range(1, len(vals)):

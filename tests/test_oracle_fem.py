@@ -192,3 +192,11 @@ def test_rayleigh_quotient_expansion_is_exact():
         d = w - u
         rhs = (d @ A @ d) / bw - lam[i] * (d @ M @ d) / bw
         assert lhs == pytest.approx(rhs, rel=1e-9, abs=1e-12)
+
+
+def test_stencil_built_stiffness_3d_equals_assembly():
+    from stencil_ops import constant_stiffness_3d
+    for n in (4, 8):
+        A, _ = fem.assemble(3, n)
+        B = constant_stiffness_3d(n)
+        assert abs(A - B).max() < 1e-15
