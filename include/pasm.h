@@ -143,6 +143,15 @@ PASM_API pasm_status pasm_setup(pasm_ctx** out, const pasm_domain* domain,
  * eigenvalue is not finite. */
 PASM_API pasm_status pasm_iterate(pasm_ctx* ctx, int* converged);
 
+/* n >= 1 steps of Algorithm 1 back to back, with one synchronisation of the
+ * stream at the end (pasm_iterate synchronises after every step): for
+ * callers that know how many steps they need before testing.  *converged
+ * (may be NULL) reports the stop test of the last step (maximum relative
+ * eigenvalue change over that step below opt.tol).  PASM_E_INVALID if
+ * n < 1; PASM_E_BREAKDOWN if an eigenvalue is not finite after the last
+ * step.  Allocates nothing. */
+PASM_API pasm_status pasm_iterate_n(pasm_ctx* ctx, int n, int* converged);
+
 /* Return to the start of Algorithm 2 (lambda_i = theta_i, u_i = P q_i) on
  * the device, reusing the coarse eigenpairs computed by pasm_setup. */
 PASM_API pasm_status pasm_restart(pasm_ctx* ctx);

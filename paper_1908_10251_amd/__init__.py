@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.pasm_setup.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(pasm_domain), ctypes.POINTER(pasm_coefficients),
                              ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(pasm_options)]
     L.pasm_iterate.argtypes = [_P, _I]
+    L.pasm_iterate_n.argtypes = [_P, ctypes.c_int, _I]
     L.pasm_solve.argtypes = [_P, _I]
     L.pasm_restart.argtypes = [_P]
     L.pasm_eigenpairs.argtypes = [_P, _D, _D, ctypes.c_size_t]
@@ -209,6 +210,12 @@ def pasm_iterate(ctx) -> bool:
     return bool(conv.value)
 
 
+def pasm_iterate_n(ctx, n: int) -> bool:
+    conv = ctypes.c_int(0)
+    _check(lib().pasm_iterate_n(ctx, int(n), ctypes.byref(conv)), ctx)
+    return bool(conv.value)
+
+
 def pasm_restart(ctx) -> None:
     _check(lib().pasm_restart(ctx), ctx)
 
@@ -331,6 +338,9 @@ class Solver:
 
     def iterate(self) -> bool:
         return pasm_iterate(self.ctx)
+
+    def iterate_n(self, n: int) -> bool:
+        return pasm_iterate_n(self.ctx, n)
 
     def solve(self, allow_notconv=False) -> int:
         return pasm_solve(self.ctx, allow_notconv)

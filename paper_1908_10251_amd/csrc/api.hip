@@ -199,8 +199,10 @@ void record_start(pasm_ctx* c) {
     if (!c->prof) return;
     if (c->ev_used + 2 > c->ev.size()) {
         hipEvent_t a, b;
-        PASM_HIP(hipEventCreate(&a));
-        PASM_HIP(hipEventCreate(&b));
+        // timing only: no system-scope fence (it would write back and
+        // invalidate the caches around every timed launch)
+        PASM_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+        PASM_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
         c->ev.push_back(a);
         c->ev.push_back(b);
         c->ev_bytes.push_back(0.0);
@@ -872,9 +874,9 @@ void iterate_once(pasm_ctx* c) {
     pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
     pasm::launch_arrowhead(in, out, k, c->st);
     prolong_coefs(c, c->s);
-    pasm::launch_copy(c->lam, c->lam_prev, k, c->st);
-    pasm::launch_copy(c->mu, c->lam, k, c->st);
-    PASM_CHECK_LAUNCH();
+    // lam_prev <- lam, lam <- mu by rotating the three buffers (no copies)
+    std::swap(c->lam_prev, c->lam);
+    std::swap(c->lam, c->mu);
 }
 
 // ---------------------------------------------------------------------------
@@ -955,8 +957,8 @@ void learned_rates(pasm_ctx* c) {
     pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, g.plane, c->st);
     double rate[2] = {0.0, 0.0}, ms[2] = {0.0, 0.0};
     hipEvent_t e0, e1;
-    PASM_HIP(hipEventCreate(&e0));
-    PASM_HIP(hipEventCreate(&e1));
+    PASM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    PASM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     for (int mode = 0; mode < 2; ++mode) {
         double* x = c->R64;
         double* scr = c->Y64;
@@ -1122,6 +1124,34 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
         PASM_HIP(hipStreamSynchronize(c->st));
         collect_profile(c);
         ++c->iters;
+        double dmax = 0.0;
+        bool finite = true;
+        for (int i = 0; i < c->k; ++i) {
+            const double l = c->lam_h[i];
+            if (!std::isfinite(l)) finite = false;
+            dmax = std::max(dmax, std::fabs(l - c->lam_prev_h[i]) / std::fabs(l));
+        }
+        if (!finite) {
+            set_error(c, "non-finite eigenvalue");
+            return PASM_E_BREAKDOWN;
+        }
+        if (converged) *converged = dmax < c->opt.tol ? 1 : 0;
+    });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    if (n < 1) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        for (int i = 0; i < n; ++i) iterate_once(c);
+        // the eigenvalues before and after the last step, in one synchronisation
+        PASM_HIP(hipMemcpyAsync(c->lam_prev_h.data(), c->lam_prev, c->k * sizeof(double), hipMemcpyDeviceToHost,
+                                c->st));
+        PASM_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+        collect_profile(c);
+        c->iters += n;
         double dmax = 0.0;
         bool finite = true;
         for (int i = 0; i < c->k; ++i) {

@@ -173,8 +173,9 @@ void brecord_start(pasm_batch* b) {
     if (!b->prof) return;
     if (b->ev_used + 2 > b->ev.size()) {
         hipEvent_t e0, e1;
-        PASM_HIP(hipEventCreate(&e0));
-        PASM_HIP(hipEventCreate(&e1));
+        // timing only: no system-scope fence around the timed launches
+        PASM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+        PASM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
         b->ev.push_back(e0);
         b->ev.push_back(e1);
         b->ev_bytes.push_back(0.0);
@@ -383,8 +384,8 @@ void biterate_device(pasm_batch* b) {
 template <typename T>
 void btune(pasm_batch* b) {
     hipEvent_t e0, e1;
-    PASM_HIP(hipEventCreate(&e0));
-    PASM_HIP(hipEventCreate(&e1));
+    PASM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    PASM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     for (int l = 1; l < b->Lmax; ++l) {
         BLevel& Lv = b->lv[l];
         const int nr = Lv.count * b->k;

