@@ -89,6 +89,9 @@ struct pasm_ctx {
     // coarse space
     double *theta = nullptr, *Qcm = nullptr, *Qrm = nullptr, *Ainv64 = nullptr;
     float* Ainv32 = nullptr;
+    // sine-transform tables of a constant-coefficient 2D coarse operator
+    // (nullptr: the coarse solve is the dense product with A_H^{-1})
+    double *dstS = nullptr, *dstInv = nullptr;
     int* group = nullptr;
     double *bz = nullptr, *partial = nullptr, *pp = nullptr, *qq = nullptr, *ycoef = nullptr;
     double *s = nullptr, *mu = nullptr, *lam = nullptr, *lam_prev = nullptr, *score = nullptr;
@@ -309,12 +312,25 @@ pasm::SmoothSteps to_steps(const std::vector<Cheb>& v) {
     return ss;
 }
 
+// Exact solve on V_H (level 0, padded fields): by the sine transform where
+// the coarse operator is the constant-coefficient 2D one, else the dense
+// product with A_H^{-1}.
+template <typename T>
+void coarse_solve(pasm_ctx* c, const T* f, T* x, int nrhs) {
+    const pasm::Level& L0 = c->lv[0];
+    if (c->dstS)
+        pasm::launch_dst_solve<T>(L0.g, c->dstS, c->dstInv, f, L0.g.plane, x, L0.g.plane, nrhs, c->st);
+    else
+        pasm::launch_dense_mv<T>(ainv<T>(c), c->NH, L0.g, f, L0.g.plane, true, x, L0.g.plane, true, nrhs, c->dmv,
+                                 c->st);
+}
+
 // One V-cycle at level l >= 0 on (x, f); x may start at zero.
 template <typename T>
 void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs) {
     const pasm::Level& L = c->lv[l];
     if (l == 0) {
-        pasm::launch_dense_mv<T>(ainv<T>(c), c->NH, L.g, f, L.g.plane, true, x, L.g.plane, true, nrhs, c->dmv, c->st);
+        coarse_solve<T>(c, f, x, nrhs);
         return;
     }
     pasm::Level& Lc = c->lv[l - 1];
@@ -774,6 +790,15 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->Ainv64 = Ainv;
     if (c->mixed)
         pasm::launch_d2f(c->Ainv64, c->Ainv32, (long)N * N, c->st);
+    if (dim == 2 && L0.const_coef && !L0.general && pasm::dst_solve_supported(g0)) {
+        std::vector<double> S, inv;
+        pasm::dst_solve_tables(g0, L0.w0, S, inv);
+        c->dstS = c->alloc<double>(S.size());
+        c->dstInv = c->alloc<double>(inv.size());
+        PASM_HIP(hipMemcpyAsync(c->dstS, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+        PASM_HIP(hipMemcpyAsync(c->dstInv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+        PASM_HIP(hipStreamSynchronize(c->st));
+    }
     // groups of equal coarse Ritz values
     std::vector<int> grp(N);
     const double gtol = 16.0 * DBL_EPSILON * std::fabs(th[N - 1]);
@@ -829,7 +854,7 @@ void iterate_once(pasm_ctx* c) {
         bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles, c->dim == 2 && c->L >= 2, true);
     } else {
         // fine level = V_H: exact solve
-        pasm::launch_dense_mv<double>(c->Ainv64, N, g, c->F64, sf, true, c->U, sf, true, k, c->dmv, c->st);
+        coarse_solve<double>(c, c->F64, c->U, k);
     }
     // step 2: borders, fused with the first restriction
     const double* bsrc = c->Y64;
@@ -1344,7 +1369,7 @@ PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t
         double* yb = c->Y64;
         if (c->L > 1) bvp_cycles(c, xb, yb, c->F64, nrhs, ncycles);
         else if (ncycles > 0)
-            pasm::launch_dense_mv<double>(c->Ainv64, c->NH, g, c->F64, g.plane, true, xb, g.plane, true, nrhs, c->dmv, c->st);
+            coarse_solve<double>(c, c->F64, xb, nrhs);
         pasm::launch_pack<double>(g, xb, g.plane, x, (long)ld, nrhs, c->st);
         PASM_HIP(hipStreamSynchronize(c->st));
     });

@@ -33,6 +33,8 @@
 
 #include <type_traits>
 
+#include <cmath>
+
 #include "common.h"
 
 namespace pasm {
@@ -1011,6 +1013,58 @@ __global__ __launch_bounds__(PF_T) void k_arrow_final(ArrowIn in, ArrowOut out, 
     }
 }
 
+
+// Exact coarse solve for the constant-coefficient 2D operator: A_H = w0 (4 at
+// the centre, -1 at the four axis neighbours) is diagonalised by the sine
+// transform in each direction, A_H = (S x S) diag(w0 (c_a + c_b)) (S x S),
+// with S the orthonormal DST-I matrix of order n - 1 (S = S^T = S^-1,
+// S_aj = sqrt(2/n) sin(pi (a+1)(j+1)/n)) and c_a = 2 - 2 cos(pi (a+1)/n), so
+// x = S (inv .* (S r S)) S with inv_ab = 1 / (w0 (c_a + c_b)).  One workgroup
+// of four wavefronts per right-hand side; fields padded with zeros to 64 x 64;
+// the four 64 x 64 x 64 products on the FP64 matrix cores (layouts as in
+// k_dmv_mfma), in FP64 for either field type.
+constexpr int DSTN = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void k_dst_solve(Grid g, const double* __restrict__ S,
+                                                   const double* __restrict__ inv, const T* __restrict__ f, long sf,
+                                                   T* __restrict__ x, long sx) {
+    __shared__ double Sl[DSTN][DSTN + 1];
+    __shared__ double Ba[DSTN][DSTN + 1];
+    __shared__ double Bb[DSTN][DSTN + 1];
+    const int r = blockIdx.x, tid = threadIdx.x, m = g.m;
+    const T* fr = f + (long)r * sf;
+    for (int e = tid; e < DSTN * DSTN; e += 256) {
+        const int a = e / DSTN, b = e % DSTN;  // row a: node row a + 1; column b: node column b + 1
+        Sl[a][b] = S[e];
+        Ba[a][b] = (a < m && b < m) ? (double)fr[g.idx(b + 1, a + 1)] : 0.0;
+    }
+    __syncthreads();
+    const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    // Out = Lm * Rm; wavefront w owns the 16 x 16 output tiles w, w + 4, w + 8, w + 12
+    auto gemm = [&](const double (*Lm)[DSTN + 1], const double (*Rm)[DSTN + 1], auto&& emit) {
+        for (int t = w; t < 16; t += 4) {
+            const int ti = t >> 2, tj = t & 3;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < DSTN / 4; ++ks)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lm[16 * ti + lr][4 * ks + lk], Rm[4 * ks + lk][16 * tj + lr],
+                                                           acc, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) emit(16 * ti + 4 * j + lk, 16 * tj + lr, acc[j]);
+        }
+    };
+    gemm(Sl, Ba, [&](int i, int j, double v) { Bb[i][j] = v; });  // S r
+    __syncthreads();
+    gemm(Bb, Sl, [&](int i, int j, double v) { Ba[i][j] = v * inv[i * DSTN + j]; });  // (S r S) ./ eigenvalues
+    __syncthreads();
+    gemm(Sl, Ba, [&](int i, int j, double v) { Bb[i][j] = v; });  // S y
+    __syncthreads();
+    T* xr = x + (long)r * sx;
+    gemm(Bb, Sl, [&](int i, int j, double v) {
+        if (i < m && j < m) xr[g.idx(j + 1, i + 1)] = (T)v;
+    });
+}
+
 }  // namespace
 
 constexpr int kDmvBigN = 2048;  // coarse spaces from this size take the large shape
@@ -1081,6 +1135,37 @@ template void launch_dense_mv<double>(const double*, int, const Grid&, const dou
                                       bool, int, void*, hipStream_t, int, long);
 template void launch_dense_mv<float>(const float*, int, const Grid&, const float*, long, bool, float*, long, bool,
                                      int, void*, hipStream_t, int, long);
+
+bool dst_solve_supported(const Grid& g) { return g.dim == 2 && g.n >= 2 && g.n <= DSTN; }
+
+void dst_solve_tables(const Grid& g, double w0, std::vector<double>& S, std::vector<double>& inv) {
+    const int n = g.n, m = g.m;
+    const double pi = 3.14159265358979323846;
+    S.assign((size_t)DSTN * DSTN, 0.0);
+    inv.assign((size_t)DSTN * DSTN, 0.0);
+    std::vector<double> c(m);
+    for (int a = 0; a < m; ++a) c[a] = 2.0 - 2.0 * std::cos(pi * (a + 1) / n);
+    const double sc = std::sqrt(2.0 / n);
+    for (int a = 0; a < m; ++a)
+        for (int j = 0; j < m; ++j) {
+            // sin of pi (a+1)(j+1)/n with the argument reduced modulo 2n exactly
+            const long q = ((long)(a + 1) * (j + 1)) % (2 * n);
+            S[(size_t)a * DSTN + j] = sc * std::sin(pi * (double)q / n);
+            inv[(size_t)a * DSTN + j] = 1.0 / (w0 * (c[a] + c[j]));
+        }
+}
+
+template <typename T>
+void launch_dst_solve(const Grid& g, const double* S, const double* inv, const T* f, long sf, T* x, long sx,
+                      int nrhs, hipStream_t st) {
+    if (!dst_solve_supported(g)) throw Error(PASM_E_INVALID, "sine-transform coarse solve: 2D, at most 64 cells");
+    hipLaunchKernelGGL((k_dst_solve<T>), dim3(nrhs), dim3(256), 0, st, g, S, inv, f, sf, x, sx);
+    PASM_CHECK_LAUNCH();
+}
+template void launch_dst_solve<double>(const Grid&, const double*, const double*, const double*, long, double*, long,
+                                       int, hipStream_t);
+template void launch_dst_solve<float>(const Grid&, const double*, const double*, const float*, long, float*, long,
+                                      int, hipStream_t);
 
 size_t dense_mv_workspace_bytes(int N, int nrhs) {
     return sizeof(double) * (size_t)((N + 63) / 64) * nrhs * N;

@@ -170,6 +170,14 @@ template <typename T>
 void launch_resid_restrict(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc,
                            T* rc, int nrhs, long sf, long sc, hipStream_t st);
 
+// Exact solve with a constant-coefficient 2D coarse operator w0 (5-point) by
+// its sine transform (n <= 64 cells per side): tables built on the host once.
+bool dst_solve_supported(const Grid& g);
+void dst_solve_tables(const Grid& g, double w0, std::vector<double>& S, std::vector<double>& inv);
+template <typename T>
+void launch_dst_solve(const Grid& g, const double* S, const double* inv, const T* f, long sf, T* x, long sx,
+                      int nrhs, hipStream_t st);
+
 void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                           double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                           hipStream_t st);
