@@ -1033,34 +1033,58 @@ __global__ __launch_bounds__(256) void k_dst_solve(Grid g, const double* __restr
     __shared__ double Bb[DSTN][DSTN + 1];
     const int r = blockIdx.x, tid = threadIdx.x, m = g.m;
     const T* fr = f + (long)r * sf;
-    for (int e = tid; e < DSTN * DSTN; e += 256) {
-        const int a = e / DSTN, b = e % DSTN;  // row a: node row a + 1; column b: node column b + 1
-        Sl[a][b] = S[e];
-        Ba[a][b] = (a < m && b < m) ? (double)fr[g.idx(b + 1, a + 1)] : 0.0;
-    }
-    __syncthreads();
     const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    {
+        // every load of the thread in flight at once, then the LDS stores
+        constexpr int E = DSTN * DSTN / 256;
+        double sv[E], fv[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int e = tid + 256 * u, a = e / DSTN, b = e % DSTN;  // row a: node row a + 1; column b: column b + 1
+            sv[u] = S[e];
+            const bool in = a < m && b < m;
+            const T v = fr[g.idx(in ? b + 1 : 1, in ? a + 1 : 1)];
+            fv[u] = in ? (double)v : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int e = tid + 256 * u, a = e / DSTN, b = e % DSTN;
+            Sl[a][b] = sv[u];
+            Ba[a][b] = fv[u];
+        }
+    }
+    // the eigenvalue factors of this thread's outputs of the scaled product
+    double iv[4][4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = w + 4 * s4, ti = t >> 2, tj = t & 3;
+            iv[s4][j] = inv[(16 * ti + 4 * j + lk) * DSTN + 16 * tj + lr];
+        }
+    __syncthreads();
     // Out = Lm * Rm; wavefront w owns the 16 x 16 output tiles w, w + 4, w + 8, w + 12
     auto gemm = [&](const double (*Lm)[DSTN + 1], const double (*Rm)[DSTN + 1], auto&& emit) {
-        for (int t = w; t < 16; t += 4) {
-            const int ti = t >> 2, tj = t & 3;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int t = w + 4 * s4, ti = t >> 2, tj = t & 3;
             f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int ks = 0; ks < DSTN / 4; ++ks)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lm[16 * ti + lr][4 * ks + lk], Rm[4 * ks + lk][16 * tj + lr],
                                                            acc, 0, 0, 0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) emit(16 * ti + 4 * j + lk, 16 * tj + lr, acc[j]);
+            for (int j = 0; j < 4; ++j) emit(s4, j, 16 * ti + 4 * j + lk, 16 * tj + lr, acc[j]);
         }
     };
-    gemm(Sl, Ba, [&](int i, int j, double v) { Bb[i][j] = v; });  // S r
+    gemm(Sl, Ba, [&](int, int, int i, int j, double v) { Bb[i][j] = v; });  // S r
     __syncthreads();
-    gemm(Bb, Sl, [&](int i, int j, double v) { Ba[i][j] = v * inv[i * DSTN + j]; });  // (S r S) ./ eigenvalues
+    gemm(Bb, Sl, [&](int s4, int jj, int i, int j, double v) { Ba[i][j] = v * iv[s4][jj]; });  // (S r S) ./ eigenvalues
     __syncthreads();
-    gemm(Sl, Ba, [&](int i, int j, double v) { Bb[i][j] = v; });  // S y
+    gemm(Sl, Ba, [&](int, int, int i, int j, double v) { Bb[i][j] = v; });  // S y
     __syncthreads();
     T* xr = x + (long)r * sx;
-    gemm(Bb, Sl, [&](int i, int j, double v) {
+    gemm(Bb, Sl, [&](int, int, int i, int j, double v) {
         if (i < m && j < m) xr[g.idx(j + 1, i + 1)] = (T)v;
     });
 }
