@@ -426,7 +426,7 @@ int march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T
 // needs many strips and segments to fill the machine; smaller levels use the
 // tile kernels.
 bool march_supported(const Grid& g, bool const_coef, int steps) {
-    return g.dim == 2 && const_coef && steps >= 1 && steps <= 4 && g.n >= 512;
+    return g.dim == 2 && const_coef && steps >= 1 && steps <= 4 && g.n >= 256;
 }
 
 template <typename T>
