@@ -825,6 +825,15 @@ void prolong_coefs(pasm_ctx* c, const double* s) {
         return;
     }
     pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->lv[0].B, L0.g.plane, true, k, c->dmv, c->st);
+    if (s && c->dim == 2) {
+        // 2D: from the coarse space straight to the finest level (P1
+        // interpolation on the coarse triangles), with the next step's
+        // right-hand side lambda M u from the same pass
+        pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->F64, k, L0.g.plane, c->sf(), s, c->mu, c->st);
+        std::swap(c->U, c->Y64);
+        c->f_ready = true;
+        return;
+    }
     for (int l = 1; l < c->L - 1; ++l)
         pasm::launch_prolong<double>(c->lv[l - 1].g, c->lv[l - 1].B, c->lv[l].g, c->lv[l].B, k, c->lv[l - 1].g.plane,
                                      c->lv[l].g.plane, false, nullptr, c->st);

@@ -573,13 +573,20 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
 // Prolongation and combination with the mass right-hand side of the next
 // step in one pass: xn = P xc + beta[r] xo on every fine node, and
 // f = lam[r] M xn on the workgroup's 64 x 16 nodes (xn on their one-node
-// halo is formed again from xo and xc).  xn must not alias xo.
+// halo is formed again from xo and xc).  xn must not alias xo.  The coarse
+// field may lie any power-of-two ratio R = 2^lr below: the spaces are nested,
+// so the prolongation through all levels in between is the P1 interpolant on
+// the coarse "/" triangles.  For a fine node in coarse cell (I, J) at
+// offsets (a, b) < R, on the lower triangle (a >= b)
+//   xn = ((R - a) x(I,J) + (a - b) x(I+1,J) + b x(I+1,J+1)) / R,
+// on the upper one the same with the roles of a, b and of (I+1,J), (I,J+1)
+// exchanged (R = 2 gives the midpoints of the coarse edges).
 constexpr int PMX = 64, PMY = 16;
 __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __restrict__ xc, Grid gf,
                                                       const double* __restrict__ xo, double* __restrict__ xn,
                                                       double* __restrict__ f, long sc, long sf,
                                                       const double* __restrict__ beta,
-                                                      const double* __restrict__ lam) {
+                                                      const double* __restrict__ lam, int lr) {
     constexpr int UX = PMX + 2, UY = PMY + 2, NPT = (UX * UY + 255) / 256;
     __shared__ double us[UY][UX];
     const int tid = threadIdx.x, z = blockIdx.z;
@@ -587,7 +594,10 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
     const double* cr = xc + (long)z * sc;
     const double* xr = xo + (long)z * sf;
     const double bz = beta[z], lz = lam[z];
-    double c0[NPT], c1[NPT], xv[NPT];
+    const int R = 1 << lr;
+    const double invR = 1.0 / R;
+    double c0[NPT], c1[NPT], c2[NPT], xv[NPT];
+    int wa[NPT], wb[NPT];
     bool ok[NPT];
 #pragma unroll
     for (int e = 0; e < NPT; ++e) {
@@ -595,18 +605,20 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
         const int i = i0 - 1 + t % UX, j = j0 - 1 + t / UX;
         ok[e] = t < UX * UY && i >= 1 && i <= gf.m && j >= 1 && j <= gf.m;
         const int ic = ok[e] ? i : 1, jc = ok[e] ? j : 1;
-        const int a = ic & 1, b = jc & 1;
-        const long cid = gc.idx(ic >> 1, jc >> 1);
+        const int a = ic & (R - 1), b = jc & (R - 1);
+        const long cid = gc.idx(ic >> lr, jc >> lr);
+        const bool lower = a >= b;
+        wa[e] = lower ? a : b;  // the larger offset
+        wb[e] = lower ? b : a;  // the smaller one
         c0[e] = cr[cid];
-        c1[e] = cr[cid + a + (long)b * gc.pitch];
+        c1[e] = cr[cid + (lower ? 1 : (long)gc.pitch)];
+        c2[e] = cr[cid + 1 + (long)gc.pitch];
         xv[e] = xr[gf.idx(ic, jc)];
     }
 #pragma unroll
     for (int e = 0; e < NPT; ++e) {
         const int t = tid + 256 * e;
-        const int i = i0 - 1 + t % UX, j = j0 - 1 + t / UX;
-        double v = c0[e];
-        if ((i | j) & 1) v = 0.5 * (v + c1[e]);
+        double v = ((double)(R - wa[e]) * c0[e] + (double)(wa[e] - wb[e]) * c1[e] + (double)wb[e] * c2[e]) * invR;
         v += bz * xv[e];
         if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
     }
@@ -838,10 +850,16 @@ void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs
 void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                          hipStream_t st) {
-    if (gc.n * 2 != gf.n || xn == xo) throw Error(PASM_E_INVALID, "prolong with mass: ratio 2, separate output");
-    if (gf.dim == 3) return launch_prolong_mass3(gc, xc, gf, xo, xn, f, nrhs, sc, sf, beta, lam, st);
+    if (xn == xo) throw Error(PASM_E_INVALID, "prolong with mass: separate output");
+    if (gf.dim == 3) {
+        if (gc.n * 2 != gf.n) throw Error(PASM_E_INVALID, "prolong with mass (3D): ratio 2");
+        return launch_prolong_mass3(gc, xc, gf, xo, xn, f, nrhs, sc, sf, beta, lam, st);
+    }
+    int lr = 0;
+    while ((gc.n << lr) < gf.n) ++lr;
+    if (lr < 1 || (gc.n << lr) != gf.n) throw Error(PASM_E_INVALID, "prolong with mass: power-of-two ratio");
     dim3 grid((gf.m + PMX - 1) / PMX, (gf.m + PMY - 1) / PMY, nrhs);
-    hipLaunchKernelGGL(k_prolong_mass, grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta, lam);
+    hipLaunchKernelGGL(k_prolong_mass, grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta, lam, lr);
     PASM_CHECK_LAUNCH();
 }
 
