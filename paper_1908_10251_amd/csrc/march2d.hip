@@ -100,7 +100,18 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     const int z = work / (sh.strips * sh.segs);
     const int MSEG = sh.mseg;
     const int lane = threadIdx.x;
-    const int y0 = band * MSEG;
+    // Odd bands run point-reflected: kernel position (i, r) is grid node
+    // (n - i, n - r), coarse (I, J) is (nc - I, nc - J).  The operator, the
+    // mass matrix and both transfers of the "/" mesh are symmetric under that
+    // reflection, so the arithmetic is unchanged; each band boundary is then
+    // reached by both neighbouring bands at the same time (both start there or
+    // both end there), and the rows they share come from HBM once and from the
+    // die's L2 the second time.
+    const bool flip = band & 1;
+    const int y0 = flip ? g.n + 1 - (band + 1) * MSEG : band * MSEG;
+    const int fs = flip ? -1 : 1;
+    auto gx = [&](int i) { return flip ? g.n - i : i; };
+    auto gcx = [&](int I) { return flip ? gc.n - I : I; };
     const int c0 = 2 * lane;                      // strip column of the lane's first column
     const int i0 = strip * TXO - HX + c0;         // global column (even)
     bool inner[2], owned[2];
@@ -144,6 +155,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     // whose stored values are zero (the Dirichlet data), which is exactly the
     // value such positions must have.
     const int ia = min(max(i0, 0), g.n), ib = min(max(i0 + 1, 0), g.n);
+    const int ga = gx(ia), gb = gx(ib);  // their grid columns
     // One prefetched row: the raw loaded values, combined only when the row
     // is consumed, PF rows later (combining at load time would wait for the
     // loads at once).  POST reads the two coarse nodes whose mean is the
@@ -155,21 +167,21 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     };
     auto load = [&](int r, Slot& sl) {
         const int rr = min(max(r, 0), g.n);
-        const long row = (long)rr * g.pitch + ORIGIN;
-        sl.f[0] = fr[row + ia];
-        sl.f[1] = fr[row + ib];
+        const long row = (long)gx(rr) * g.pitch + ORIGIN;
+        sl.f[0] = fr[row + ga];
+        sl.f[1] = fr[row + gb];
         if (POSTLIKE || !XZ) {
-            sl.x[0] = xr[row + ia];
-            sl.x[1] = xr[row + ib];
+            sl.x[0] = xr[row + ga];
+            sl.x[1] = xr[row + gb];
         }
         if (POSTLIKE) {
             const int cols[2] = {ia, ib};
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
                 const int i = cols[cc], a = i & 1, b = rr & 1;
-                const long cid = gc.idx(i >> 1, rr >> 1);
+                const long cid = gc.idx(gcx(i >> 1), gcx(rr >> 1));
                 sl.e0[cc] = ecr[cid];
-                sl.e1[cc] = ecr[cid + a + (long)b * gc.pitch];
+                sl.e1[cc] = ecr[cid + fs * (a + (long)b * gc.pitch)];
             }
         }
     };
@@ -225,10 +237,10 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
         {
             const int q = r - S;
             if (q >= y0 && q < y0 + MSEG && q >= 1 && q <= g.m) {
-                const long id = g.idx(i0, q);
+                const long id = g.idx(gx(i0), gx(q));
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc)
-                    if (owned[cc] && inner[cc]) outr[id + cc] = xw[S][0][cc];
+                    if (owned[cc] && inner[cc]) outr[id + fs * cc] = xw[S][0][cc];
             }
         }
         if (MODE == 1) {
@@ -257,7 +269,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
             if (((q2 & 1) == 0) && q2 >= y0 && q2 < y0 + MSEG && owned[0]) {
                 const int I = i0 >> 1, J = q2 >> 1;
                 if (I >= 1 && I <= gc.m && J >= 1 && J <= gc.m)
-                    rc[(long)z * sc + gc.idx(I, J)] =
+                    rc[(long)z * sc + gc.idx(gcx(I), gcx(J))] =
                         rw[1][0] + T(0.5) * (rw[1][1] + mid_left + rw[0][0] + rw[2][0] + rw[0][1] + dn_left);
             }
         }
@@ -309,7 +321,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
             if (((q2 & 1) == 0) && q2 >= y0 && q2 < y0 + MSEG && owned[0]) {
                 const int I = i0 >> 1, J = q2 >> 1;
                 if (I >= 1 && I <= gc.m && J >= 1 && J <= gc.m) {
-                    const long cid = (long)z * sc + gc.idx(I, J);
+                    const long cid = (long)z * sc + gc.idx(gcx(I), gcx(J));
                     rc[cid] = rw[1][0] + T(0.5) * (rw[1][1] + ra + rw[0][0] + rw[2][0] + rw[0][1] + rb);
                     rc2[cid] = mw[1][0] + T(0.5) * (mw[1][1] + ma + mw[0][0] + mw[2][0] + mw[0][1] + mb);
                 }
