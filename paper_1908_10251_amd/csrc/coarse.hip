@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_dmv_part(const T* __restrict__ M
 // B[l / 16][l % 16]); D comes back as D[4 j + l / 16][l % 16].  Partial sums
 // go to part[chunk][row][rhs], summed by k_dmv_sum_rm.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int DMW = 2;  // wavefronts per workgroup (128 rows)
+constexpr int DMW = 4;  // wavefronts per workgroup (256 rows)
 template <int NT, int DC>
 __global__ __launch_bounds__(64 * DMW) void k_dmv_mfma(const double* __restrict__ Mat, int N, Grid g,
                                                        const double* __restrict__ x, long sx, int xpad,
