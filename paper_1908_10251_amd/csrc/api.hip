@@ -100,6 +100,8 @@ struct pasm_ctx {
     void* dmv = nullptr;   // split-K workspace of the dense coarse products
     std::vector<void*> allocs;
     std::vector<double> lam_h, lam_prev_h;
+    std::vector<double> theta_h;  // the k smallest coarse Ritz values (the start), kept on the host
+    double* zeros = nullptr;      // k zeros: the combination weights of a restart
     std::string err;
     rocblas_handle blas = nullptr;
     long iters = 0;
@@ -808,6 +810,9 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     // start: lambda_i = theta_i, u_i = P q_i
     c->lam_h.assign(th.begin(), th.begin() + k);
     c->lam_prev_h = c->lam_h;
+    c->theta_h = c->lam_h;
+    c->zeros = c->alloc<double>(k);
+    PASM_HIP(hipMemsetAsync(c->zeros, 0, k * sizeof(double), c->st));
     PASM_HIP(hipMemcpyAsync(c->lam, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
     PASM_HIP(hipMemcpyAsync(c->lam_prev, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
     pasm::launch_unit_coefs(c->ycoef, N, k, k, c->st);
@@ -816,7 +821,10 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
 }
 
 // u = P Q y' + s u  (s = nullptr: u = P Q y')
-void prolong_coefs(pasm_ctx* c, const double* s) {
+// u = P Q y' + s u~ (s == nullptr: u = P Q y'); with s given, also the next
+// step's right-hand side f = lamf M u in the same pass (lamf == nullptr: the
+// new eigenvalues mu).
+void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr) {
     const int k = c->k, N = c->NH;
     const pasm::Level& L0 = c->lv[0];
     if (c->L == 1) {
@@ -829,7 +837,8 @@ void prolong_coefs(pasm_ctx* c, const double* s) {
         // 2D: from the coarse space straight to the finest level (P1
         // interpolation on the coarse triangles), with the next step's
         // right-hand side lambda M u from the same pass
-        pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->F64, k, L0.g.plane, c->sf(), s, c->mu, c->st);
+        pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->F64, k, L0.g.plane, c->sf(), s,
+                                  lamf ? lamf : c->mu, c->st);
         std::swap(c->U, c->Y64);
         c->f_ready = true;
         return;
@@ -841,8 +850,8 @@ void prolong_coefs(pasm_ctx* c, const double* s) {
     if (s) {
         // the new u into the scratch field (then swapped in), with the next
         // step's right-hand side lambda M u from the same pass
-        pasm::launch_prolong_mass(Lc.g, Lc.B, c->gf(), c->U, c->Y64, c->F64, k, Lc.g.plane, c->sf(), s, c->mu,
-                                  c->st);
+        pasm::launch_prolong_mass(Lc.g, Lc.B, c->gf(), c->U, c->Y64, c->F64, k, Lc.g.plane, c->sf(), s,
+                                  lamf ? lamf : c->mu, c->st);
         std::swap(c->U, c->Y64);
         c->f_ready = true;
         return;
@@ -1208,16 +1217,15 @@ PASM_API pasm_status pasm_restart(pasm_ctx* c) {
     c->lstag.assign(c->k, 0);
     PASM_TRY(c, {
         const int k = c->k, N = c->NH;
-        std::vector<double> th(k);
-        PASM_HIP(hipMemcpyAsync(th.data(), c->theta, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
-        PASM_HIP(hipStreamSynchronize(c->st));
-        c->lam_h = th;
-        c->lam_prev_h = th;
+        c->lam_h = c->theta_h;
+        c->lam_prev_h = c->theta_h;
         pasm::launch_copy(c->theta, c->lam, k, c->st);
         pasm::launch_copy(c->theta, c->lam_prev, k, c->st);
         pasm::launch_unit_coefs(c->ycoef, N, k, k, c->st);
         PASM_CHECK_LAUNCH();
-        prolong_coefs(c, nullptr);
+        // u_i = P q_i (weights of the old u all zero) and the first step's
+        // right-hand side theta_i M u_i in the same pass
+        prolong_coefs(c, c->zeros, c->lam);
         PASM_HIP(hipStreamSynchronize(c->st));
     });
     return PASM_OK;

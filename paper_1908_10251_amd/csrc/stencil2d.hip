@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
     for (int e = 0; e < NPT; ++e) {
         const int t = tid + 256 * e;
         double v = ((double)(R - wa[e]) * c0[e] + (double)(wa[e] - wb[e]) * c1[e] + (double)wb[e] * c2[e]) * invR;
-        v += bz * xv[e];
+        if (bz != 0.0) v += bz * xv[e];  // a zero weight drops the old field (whatever it holds)
         if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
     }
     __syncthreads();

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_prolong_mass3(Grid gc, const double* __
             const int i = i0 - 1 + t % UX, j = j0 - 1 + (t / UX) % UY, k = k0 - 1 + t / (UX * UY);
             double v = c0[e];
             if ((i | j | k) & 1) v = 0.5 * (v + c1[e]);
-            v += bz * xv[e];
+            if (bz != 0.0) v += bz * xv[e];  // a zero weight drops the old field (whatever it holds)
             if (t < NU) us[t] = ok[e] ? v : 0.0;
         }
     }
