@@ -153,7 +153,9 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* ctx, int* converged);
 PASM_API pasm_status pasm_iterate_n(pasm_ctx* ctx, int n, int* converged);
 
 /* Return to the start of Algorithm 2 (lambda_i = theta_i, u_i = P q_i) on
- * the device, reusing the coarse eigenpairs computed by pasm_setup. */
+ * the device, reusing the coarse eigenpairs computed by pasm_setup.  The
+ * work is enqueued on the context's stream without waiting for it (every
+ * later call on the context is ordered after it). */
 PASM_API pasm_status pasm_restart(pasm_ctx* ctx);
 
 /* Iterate until converged or opt.max_iter iterations; *iterations (may be

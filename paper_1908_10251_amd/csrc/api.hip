@@ -1224,9 +1224,9 @@ PASM_API pasm_status pasm_restart(pasm_ctx* c) {
         pasm::launch_unit_coefs(c->ycoef, N, k, k, c->st);
         PASM_CHECK_LAUNCH();
         // u_i = P q_i (weights of the old u all zero) and the first step's
-        // right-hand side theta_i M u_i in the same pass
+        // right-hand side theta_i M u_i in the same pass; left in flight on
+        // the context's stream (everything that reads it is ordered there)
         prolong_coefs(c, c->zeros, c->lam);
-        PASM_HIP(hipStreamSynchronize(c->st));
     });
     return PASM_OK;
 }
