@@ -596,29 +596,37 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
     const double bz = beta[z], lz = lam[z];
     const int R = 1 << lr;
     const double invR = 1.0 / R;
-    double c0[NPT], c1[NPT], c2[NPT], xv[NPT];
-    int wa[NPT], wb[NPT];
+    // the coarse nodes under the tile and its halo (at most 35 x 11 for R >= 2)
+    constexpr int CSX = PMX / 2 + 3, CSY = PMY / 2 + 3;
+    __shared__ double cs[CSY][CSX];
+    const int I0 = (i0 - 1) >> lr, J0 = (j0 - 1) >> lr;
+    const int CX = min(((i0 + PMX) >> lr) - I0 + 2, CSX), CY = min(((j0 + PMY) >> lr) - J0 + 2, CSY);
+    double xv[NPT];
     bool ok[NPT];
+    int ic_[NPT], jc_[NPT];
 #pragma unroll
     for (int e = 0; e < NPT; ++e) {
         const int t = tid + 256 * e;
         const int i = i0 - 1 + t % UX, j = j0 - 1 + t / UX;
         ok[e] = t < UX * UY && i >= 1 && i <= gf.m && j >= 1 && j <= gf.m;
-        const int ic = ok[e] ? i : 1, jc = ok[e] ? j : 1;
-        const int a = ic & (R - 1), b = jc & (R - 1);
-        const long cid = gc.idx(ic >> lr, jc >> lr);
-        const bool lower = a >= b;
-        wa[e] = lower ? a : b;  // the larger offset
-        wb[e] = lower ? b : a;  // the smaller one
-        c0[e] = cr[cid];
-        c1[e] = cr[cid + (lower ? 1 : (long)gc.pitch)];
-        c2[e] = cr[cid + 1 + (long)gc.pitch];
-        xv[e] = xr[gf.idx(ic, jc)];
+        ic_[e] = ok[e] ? i : i0;
+        jc_[e] = ok[e] ? j : j0;
+        xv[e] = xr[gf.idx(ic_[e], jc_[e])];
     }
+    for (int t = tid; t < CX * CY; t += 256) {
+        const int a = t % CX, b = t / CX;
+        cs[b][a] = cr[gc.idx(min(I0 + a, gc.n), min(J0 + b, gc.n))];
+    }
+    __syncthreads();
 #pragma unroll
     for (int e = 0; e < NPT; ++e) {
         const int t = tid + 256 * e;
-        double v = ((double)(R - wa[e]) * c0[e] + (double)(wa[e] - wb[e]) * c1[e] + (double)wb[e] * c2[e]) * invR;
+        const int a = ic_[e] & (R - 1), b = jc_[e] & (R - 1);
+        const int ir = (ic_[e] >> lr) - I0, jr = (jc_[e] >> lr) - J0;  // within the staged block
+        const bool lower = a >= b;
+        const int wa = lower ? a : b, wb = lower ? b : a;  // the larger and the smaller offset
+        const double c0 = cs[jr][ir], c1 = lower ? cs[jr][ir + 1] : cs[jr + 1][ir], c2 = cs[jr + 1][ir + 1];
+        double v = ((double)(R - wa) * c0 + (double)(wa - wb) * c1 + (double)wb * c2) * invR;
         if (bz != 0.0) v += bz * xv[e];  // a zero weight drops the old field (whatever it holds)
         if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
     }
