@@ -404,17 +404,29 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
 // buffers (padded), scr an FP64 scratch buffer of the same size.
 // One V-cycle for A x = f at the finest level: in place (FP64), or as
 // defect correction with an FP32 cycle (mixed).
-void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs) {
+//
+// Mixed: r_ready says that R32 already holds f - A x (formed by the previous
+// cycle's last pass); with next set (3D), this cycle's correction and the
+// next cycle's residual are formed in one pass, x moving to scr.
+void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, bool* r_ready = nullptr,
+               bool next = false) {
     const int lf = c->L - 1;
     if (!c->mixed) {
         vcycle<double>(c, lf, x, scr, f, false, nrhs);
         return;
     }
     const Grid& g = c->gf();
-    pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st);
+    if (!(r_ready && *r_ready)) pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st);
+    if (r_ready) *r_ready = false;
     float* e = c->E32;
     float* ye = c->Y32;
     vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
+    if (next && r_ready && g.dim == 3) {
+        pasm::launch_add_resid3(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st);
+        std::swap(x, scr);
+        *r_ready = true;
+        return;
+    }
     pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
 }
 
@@ -445,10 +457,11 @@ std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, i
 void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles,
                 bool border = false, bool eig = false) {
     if (!c->learned_on) {
+        bool r_ready = false;
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
             c->border_next = border && cy == ncycles - 1 && !c->mixed;
-            one_cycle(c, x, scr, f, nrhs);
+            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles);
             c->border_next = false;
         }
         return;

@@ -178,6 +178,9 @@ template <typename T>
 void launch_dst_solve(const Grid& g, const double* S, const double* inv, const T* f, long sf, T* x, long sx,
                       int nrhs, hipStream_t st);
 
+// un = u + e and r = f - A un (to FP32) in one pass (3D); un must not alias u.
+void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
+                       double* un, float* r, int nrhs, long stride, hipStream_t st);
 void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                           double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                           hipStream_t st);

@@ -370,6 +370,35 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast3(Grid g, Coef<double> c, 
     r[off + id] = (float)(f[off + id] - Ax);
 }
 
+// Defect correction between two cycles in one pass: un = u + e on every
+// interior node and r = f - A un (FP64, rounded to FP32) for the next cycle;
+// un at the neighbours is formed again from u and e.  un must not alias u.
+template <bool CONST>
+__global__ __launch_bounds__(BX* BY) void k_add_resid3(Grid g, Coef<double> c, const double* __restrict__ u,
+                                                       const float* __restrict__ e, const double* __restrict__ f,
+                                                       double* __restrict__ un, float* __restrict__ r, long stride) {
+    const Pos p = pos3(g.m);
+    if (!p.ok) return;
+    const long off = (long)p.r * stride;
+    const long id = g.idx(p.i, p.j, p.l);
+    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+    const double* ur = u + off;
+    const float* er = e + off;
+    auto v = [&](long q) { return ur[q] + (double)er[q]; };
+    const double x0 = v(id), xe = v(id + 1), xw = v(id - 1), xn = v(id + py), xs = v(id - py), xu = v(id + pz),
+                 xd = v(id - pz);
+    double Ax;
+    if (CONST) {
+        Ax = c.w0 * (6.0 * x0 - (xe + xw + xn + xs + xu + xd));
+    } else {
+        const double w1 = c.wx[id], w2 = c.wx[id - 1], w3 = c.wy[id], w4 = c.wy[id - py], w5 = c.wz[id],
+                     w6 = c.wz[id - pz];
+        Ax = (w1 + w2 + w3 + w4 + w5 + w6) * x0 - w1 * xe - w2 * xw - w3 * xn - w4 * xs - w5 * xu - w6 * xd;
+    }
+    un[off + id] = x0;
+    r[off + id] = (float)(f[off + id] - Ax);
+}
+
 template <bool CONST>
 __global__ __launch_bounds__(BX* BY) void k_border3(Grid g, Coef<double> c, const double* __restrict__ u,
                                                     double* __restrict__ au, double* __restrict__ mu,
@@ -521,6 +550,16 @@ void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, c
         hipLaunchKernelGGL(k_resid_cast3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
     else
         hipLaunchKernelGGL(k_resid_cast3<true>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
+                       double* un, float* r, int nrhs, long stride, hipStream_t st) {
+    if (g.dim != 3 || un == u) throw Error(PASM_E_INVALID, "add and residual: 3D, separate output");
+    if (c.wx)
+        hipLaunchKernelGGL(k_add_resid3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride);
+    else
+        hipLaunchKernelGGL(k_add_resid3<true>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride);
     PASM_CHECK_LAUNCH();
 }
 
