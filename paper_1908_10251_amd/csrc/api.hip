@@ -406,7 +406,7 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
 // defect correction with an FP32 cycle (mixed).
 //
 // Mixed: r_ready says that R32 already holds f - A x (formed by the previous
-// cycle's last pass); with next set (3D), this cycle's correction and the
+// cycle's last pass); with next set, this cycle's correction and the
 // next cycle's residual are formed in one pass, x moving to scr.
 void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, bool* r_ready = nullptr,
                bool next = false) {
@@ -421,8 +421,8 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
     float* e = c->E32;
     float* ye = c->Y32;
     vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
-    if (next && r_ready && g.dim == 3) {
-        pasm::launch_add_resid3(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st);
+    if (next && r_ready && pasm::add_resid_supported(g, c->coef<double>(lf))) {
+        pasm::launch_add_resid(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st);
         std::swap(x, scr);
         *r_ready = true;
         return;

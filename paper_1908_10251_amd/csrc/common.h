@@ -178,6 +178,11 @@ template <typename T>
 void launch_dst_solve(const Grid& g, const double* S, const double* inv, const T* f, long sf, T* x, long sx,
                       int nrhs, hipStream_t st);
 
+// un = u + e and r = f - A un (to FP32) in one pass (3D, or 2D with constant
+// coefficients); un must not alias u.
+bool add_resid_supported(const Grid& g, const Coef<double>& c);
+void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
+                      double* un, float* r, int nrhs, long stride, hipStream_t st);
 // un = u + e and r = f - A un (to FP32) in one pass (3D); un must not alias u.
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                        double* un, float* r, int nrhs, long stride, hipStream_t st);

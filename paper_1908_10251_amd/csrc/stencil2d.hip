@@ -358,6 +358,25 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
     r[(long)blockIdx.z * rstride + id] = (TO)(f[off + id] - Ax);
 }
 
+// Defect correction between two cycles in one pass (2D, constant
+// coefficients): un = u + e on every interior node and r = f - A un (FP64,
+// rounded to FP32) for the next cycle; un at the neighbours is formed again
+// from u and e.  un must not alias u.
+__global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, double w0, const double* __restrict__ u,
+                                                      const float* __restrict__ e, const double* __restrict__ f,
+                                                      double* __restrict__ un, float* __restrict__ r, long stride) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    const long off = (long)blockIdx.z * stride;
+    const long id = off + g.idx(i, j);
+    auto v = [&](long q) { return u[q] + (double)e[q]; };
+    const double x0 = v(id);
+    const double Ax = w0 * (4.0 * x0 - (v(id + 1) + v(id - 1) + v(id + g.pitch) + v(id - g.pitch)));
+    un[id] = x0;
+    r[id] = (float)(f[id] - Ax);
+}
+
 template <typename TE>
 __global__ void k_add_correction(const TE* __restrict__ e, double* __restrict__ u, long n) {
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
@@ -919,6 +938,17 @@ void launch_add_correction(const float* e, double* u, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_add_correction<float>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
     PASM_CHECK_LAUNCH();
 }
+bool add_resid_supported(const Grid& g, const Coef<double>& c) { return g.dim == 3 || coef_kind(c) == 0; }
+
+void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
+                      double* un, float* r, int nrhs, long stride, hipStream_t st) {
+    if (g.dim == 3) return launch_add_resid3(g, c, u, e, f, un, r, nrhs, stride, st);
+    if (coef_kind(c) != 0 || un == u) throw Error(PASM_E_INVALID, "add and residual: constant 2D, separate output");
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    hipLaunchKernelGGL(k_add_resid, grid, blk, 0, st, g, c.w0, u, e, f, un, r, stride);
+    PASM_CHECK_LAUNCH();
+}
+
 void launch_add_correction(const double* e, double* u, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_add_correction<double>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
     PASM_CHECK_LAUNCH();
