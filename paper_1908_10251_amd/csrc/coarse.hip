@@ -364,8 +364,26 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
     const double* q = in.q + (long)r * N;
     const double beta = in.bz[2 * r], zeta = in.bz[2 * r + 1], lp = in.lam_prev[r];
 
+    // the first CE poles of the thread in registers, their loads issued
+    // together (the sums keep the order of a plain strided loop)
+    constexpr int CE = 4;
+    double qv[CE], pv[CE], tv[CE];
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int j = min((int)threadIdx.x + e * PP, N - 1);
+        qv[e] = q[j];
+        pv[e] = p[j];
+        tv[e] = in.theta[j];
+    }
     double qq = 0, qp = 0, qtq = 0;
-    for (int j = threadIdx.x; j < N; j += PP) {
+#pragma unroll
+    for (int e = 0; e < CE; ++e)
+        if ((int)threadIdx.x + e * PP < N) {
+            qq += qv[e] * qv[e];
+            qp += qv[e] * pv[e];
+            qtq += tv[e] * qv[e] * qv[e];
+        }
+    for (int j = threadIdx.x + CE * PP; j < N; j += PP) {
         qq += q[j] * q[j];
         qp += q[j] * p[j];
         qtq += in.theta[j] * q[j] * q[j];
@@ -379,7 +397,16 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
     const double rho = skip ? 0.0 : (beta - 2.0 * qp + qtq) / zperp;
 
     double gmax = 0.0;
-    for (int j = threadIdx.x; j < N; j += PP) {
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int j = threadIdx.x + e * PP;
+        if (j < N) {
+            const double gj = skip ? 0.0 : (pv[e] - tv[e] * qv[e]) / sq;
+            w.g[j] = gj;
+            gmax = fmax(gmax, fabs(gj));
+        }
+    }
+    for (int j = threadIdx.x + CE * PP; j < N; j += PP) {
         const double gj = skip ? 0.0 : (p[j] - in.theta[j] * q[j]) / sq;
         w.g[j] = gj;
         gmax = fmax(gmax, fabs(gj));
