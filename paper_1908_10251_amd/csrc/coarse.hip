@@ -349,8 +349,15 @@ __device__ inline double block_max(double v, double* sh) {
 
 // Stage A, one block per eigenpair: scalars, g, deflation, compaction of the
 // active poles, and the best deflated candidate.
+// ST: the group map, g and q of the eigenpair staged in LDS (N <= PMAXN), so
+// that the group scans below read LDS instead of waiting on global loads.
+constexpr int PMAXN = 4096;
+template <bool ST>
 __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int* iwork, double* best, int nchunk) {
     constexpr int NWV = PP / 64;
+    constexpr int NS = ST ? PMAXN : 1;
+    __shared__ int lgrp[NS];
+    __shared__ double lg[NS], lq[NS];
     __shared__ double sh[NWV];
     __shared__ int wtot[NWV];
     __shared__ int cnt[PP];
@@ -362,18 +369,43 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
     WS w = ws_of(work, iwork, best, N, nchunk, r);
     const double* p = in.p + (long)r * N;
     const double* q = in.q + (long)r * N;
+    auto GRP = [&](int j) -> int {
+        if constexpr (ST) return lgrp[j];
+        else return in.group[j];
+    };
+    auto GG = [&](int j) -> double {
+        if constexpr (ST) return lg[j];
+        else return w.g[j];
+    };
+    auto QQ = [&](int j) -> double {
+        if constexpr (ST) return lq[j];
+        else return q[j];
+    };
     const double beta = in.bz[2 * r], zeta = in.bz[2 * r + 1], lp = in.lam_prev[r];
 
     // the first CE poles of the thread in registers, their loads issued
     // together (the sums keep the order of a plain strided loop)
     constexpr int CE = 4;
+    static_assert(!ST || CE * PP >= PMAXN, "staged poles all in the register cache");
     double qv[CE], pv[CE], tv[CE];
+    int gv[CE];
 #pragma unroll
     for (int e = 0; e < CE; ++e) {
         const int j = min((int)threadIdx.x + e * PP, N - 1);
         qv[e] = q[j];
         pv[e] = p[j];
         tv[e] = in.theta[j];
+        if constexpr (ST) gv[e] = in.group[j];
+    }
+    if constexpr (ST) {
+#pragma unroll
+        for (int e = 0; e < CE; ++e) {
+            const int j = threadIdx.x + e * PP;
+            if (j < N) {
+                lgrp[j] = gv[e];
+                lq[j] = qv[e];
+            }
+        }
     }
     double qq = 0, qp = 0, qtq = 0;
 #pragma unroll
@@ -403,12 +435,14 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
         if (j < N) {
             const double gj = skip ? 0.0 : (pv[e] - tv[e] * qv[e]) / sq;
             w.g[j] = gj;
+            if constexpr (ST) lg[j] = gj;
             gmax = fmax(gmax, fabs(gj));
         }
     }
     for (int j = threadIdx.x + CE * PP; j < N; j += PP) {
         const double gj = skip ? 0.0 : (p[j] - in.theta[j] * q[j]) / sq;
         w.g[j] = gj;
+        if constexpr (ST) lg[j] = gj;
         gmax = fmax(gmax, fabs(gj));
     }
     gmax = block_max_n<NWV>(gmax, sh);
@@ -422,14 +456,14 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
     double ds = -1.0, dm = 0.0, dmass = 0.0;
     int dl = -1, dt = 0;
     for (int j = j0; j < j1; ++j) {
-        if (in.group[j] != j) continue;  // not a group leader
+        if (GRP(j) != j) continue;  // not a group leader
         int e = j + 1;
-        while (e < N && in.group[e] == j) ++e;
+        while (e < N && GRP(e) == j) ++e;
         double gn2 = 0.0, q2 = 0.0, gq = 0.0;
         for (int m = j; m < e; ++m) {
-            gn2 += w.g[m] * w.g[m];
-            q2 += q[m] * q[m];
-            gq += w.g[m] * q[m];
+            gn2 += GG(m) * GG(m);
+            q2 += QQ(m) * QQ(m);
+            gq += GG(m) * QQ(m);
         }
         const double gn = sqrt(gn2);
         double cs = -1.0;
@@ -509,13 +543,13 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
     // write active poles in order
     int a = cnt[threadIdx.x];
     for (int j = j0; j < j1; ++j) {
-        if (in.group[j] != j) continue;
+        if (GRP(j) != j) continue;
         int e = j + 1;
-        while (e < N && in.group[e] == j) ++e;
+        while (e < N && GRP(e) == j) ++e;
         double gn2 = 0.0, gq = 0.0;
         for (int m = j; m < e; ++m) {
-            gn2 += w.g[m] * w.g[m];
-            gq += w.g[m] * q[m];
+            gn2 += GG(m) * GG(m);
+            gq += GG(m) * QQ(m);
         }
         const double gn = sqrt(gn2);
         const bool act = !skip && gn > tolz;
@@ -523,8 +557,8 @@ __global__ __launch_bounds__(PP) void k_arrow_prep(ArrowIn in, double* work, int
         if (act) {
             w.d[a] = in.theta[j];
             if (e - j == 1) {
-                w.z[a] = w.g[j];
-                w.qa[a] = q[j];
+                w.z[a] = GG(j);
+                w.qa[a] = QQ(j);
             } else {
                 w.z[a] = gn;
                 w.qa[a] = gq / gn;
@@ -1232,7 +1266,10 @@ void launch_arrowhead(const ArrowIn& in0, const ArrowOut& out, int k, hipStream_
     double* work = out.work;
     int* iwork = reinterpret_cast<int*>(work + arrow_work_doubles(in.N, k));
     double* best = reinterpret_cast<double*>(iwork + (long)in.N * k + ((long)in.N * k & 1));
-    hipLaunchKernelGGL(k_arrow_prep, dim3(k), dim3(PP), 0, st, in, work, iwork, best, nchunk);
+    if (in.N <= PMAXN)
+        hipLaunchKernelGGL(k_arrow_prep<true>, dim3(k), dim3(PP), 0, st, in, work, iwork, best, nchunk);
+    else
+        hipLaunchKernelGGL(k_arrow_prep<false>, dim3(k), dim3(PP), 0, st, in, work, iwork, best, nchunk);
     PASM_CHECK_LAUNCH();
     // NEAR pass: one workgroup per (eigenpair, root) with the poles in
     // registers up to 8192 of them, else one workgroup per eigenpair and one
