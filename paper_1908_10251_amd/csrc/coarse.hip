@@ -1013,13 +1013,21 @@ __global__ __launch_bounds__(PF_T) void k_arrow_final(ArrowIn in, ArrowOut out, 
     }
     atomicAdd(&rk, cntb);
 
-    // eigenvector coefficients in the Q basis, and t
+    // eigenvector coefficients in the Q basis, and t; the thread's first CE
+    // coefficients (and q values) stay in registers until the final write
+    constexpr int CE = 4;
+    double yv[CE], qv[CE];
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        qv[e] = q[min((int)threadIdx.x + e * PF_T, N - 1)];
+        yv[e] = 0.0;
+    }
     double t = 0.0;
     double* y = out.ycoef + (long)r * N;
     if (is_root) {
         if (na == 0) {
             t = 1.0;
-            for (int j = threadIdx.x; j < N; j += PF_T) y[j] = 0.0;
+            for (int j = threadIdx.x + CE * PF_T; j < N; j += PF_T) y[j] = 0.0;
         } else {
             const double tau = w.rtau[id], org = w.rorg[id];
             double s1 = 0.0;
@@ -1029,7 +1037,15 @@ __global__ __launch_bounds__(PF_T) void k_arrow_final(ArrowIn in, ArrowOut out, 
             }
             s1 = block_sum_n<PF_T / 64>(s1, sh);
             t = 1.0 / sqrt(1.0 + s1);
-            for (int j = threadIdx.x; j < N; j += PF_T) {
+#pragma unroll
+            for (int e = 0; e < CE; ++e) {
+                const int j = threadIdx.x + e * PF_T;
+                if (j < N) {
+                    const int a = w.amap[j];
+                    yv[e] = a < 0 ? 0.0 : w.g[j] * t / (tau - (w.d[a] - org));
+                }
+            }
+            for (int j = threadIdx.x + CE * PF_T; j < N; j += PF_T) {
                 const int a = w.amap[j];
                 y[j] = a < 0 ? 0.0 : w.g[j] * t / (tau - (w.d[a] - org));
             }
@@ -1052,18 +1068,31 @@ __global__ __launch_bounds__(PF_T) void k_arrow_final(ArrowIn in, ArrowOut out, 
             nrm2 += v * v;
         }
         const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-        for (int j = threadIdx.x; j < N; j += PF_T)
+#pragma unroll
+        for (int ce = 0; ce < CE; ++ce) {
+            const int j = threadIdx.x + ce * PF_T;
+            if (j < N && j >= lead && j < e) yv[ce] = (qv[ce] - coef * w.g[j]) * inv;
+        }
+        for (int j = threadIdx.x + CE * PF_T; j < N; j += PF_T)
             y[j] = (j >= lead && j < e) ? (q[j] - coef * w.g[j]) * inv : 0.0;
     }
     __syncthreads();
     // signed score, then y' = y - (t / sq) q and s = t / sq
     double ys = 0.0;
-    for (int j = threadIdx.x; j < N; j += PF_T) ys += y[j] * q[j];
+#pragma unroll
+    for (int e = 0; e < CE; ++e)
+        if ((int)threadIdx.x + e * PF_T < N) ys += yv[e] * qv[e];
+    for (int j = threadIdx.x + CE * PF_T; j < N; j += PF_T) ys += y[j] * q[j];
     ys = block_sum_n<PF_T / 64>(ys, sh);
     const double signed_score = ys + t * sq;
     const double sgn = signed_score < 0.0 ? -1.0 : 1.0;
     const double s = (sq > 0.0) ? t / sq : 0.0;
-    for (int j = threadIdx.x; j < N; j += PF_T) y[j] = sgn * (y[j] - s * q[j]);
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int j = threadIdx.x + e * PF_T;
+        if (j < N) y[j] = sgn * (yv[e] - s * qv[e]);
+    }
+    for (int j = threadIdx.x + CE * PF_T; j < N; j += PF_T) y[j] = sgn * (y[j] - s * q[j]);
     __syncthreads();
     if (threadIdx.x == 0) {
         out.s[r] = sgn * s;
