@@ -145,6 +145,24 @@ __global__ __launch_bounds__(64 * DMW) void k_dmv_mfma(const double* __restrict_
     const int rn = min(KBP, kpm - rlo);
     Mat += (long)mem * mstride;
     const int cn = min(DC, N - c0);
+    const int ar = lane & 15, ak = lane >> 4;
+    // rows past N read row N - 1 (never stored); columns past the chunk read
+    // its last column, which meets zeros in xs
+    const double* mp[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) mp[mt] = Mat + (long)c0 * N + min(row0 + 16 * mt + ar, N - 1);
+    constexpr int KS = DC / 4;
+    static_assert(KS % PF == 0, "whole prefetch groups");
+    double a[PF][4];
+    auto load = [&](int ks, double* dst) {
+        const long col = min(4 * ks + ak, cn - 1);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) dst[mt] = mp[mt][col * N];
+    };
+    // the first K-steps' matrix loads go out before the staging of x, which
+    // they do not need
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load(p, a[p]);
     {
         // consecutive threads take consecutive columns (coalesced), and a
         // thread issues a batch of loads before storing any of them
@@ -167,27 +185,11 @@ __global__ __launch_bounds__(64 * DMW) void k_dmv_mfma(const double* __restrict_
         }
     }
     __syncthreads();
-    const int ar = lane & 15, ak = lane >> 4;
-    // rows past N read row N - 1 (never stored); columns past the chunk read
-    // its last column, which meets zeros in xs
-    const double* mp[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) mp[mt] = Mat + (long)c0 * N + min(row0 + 16 * mt + ar, N - 1);
     f64x4 acc[4][NT];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
-    constexpr int KS = DC / 4;
-    static_assert(KS % PF == 0, "whole prefetch groups");
-    double a[PF][4];
-    auto load = [&](int ks, double* dst) {
-        const long col = min(4 * ks + ak, cn - 1);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) dst[mt] = mp[mt][col * N];
-    };
-#pragma unroll
-    for (int p = 0; p < PF; ++p) load(p, a[p]);
     for (int k0 = 0; k0 < KS; k0 += PF) {
 #pragma unroll
         for (int p = 0; p < PF; ++p) {
