@@ -102,6 +102,7 @@ struct pasm_ctx {
     std::vector<double> lam_h, lam_prev_h;
     std::vector<double> theta_h;  // the k smallest coarse Ritz values (the start), kept on the host
     double* zeros = nullptr;      // k zeros: the combination weights of a restart
+    double* lam_pin = nullptr;    // pinned host copy of lambda_prev and lambda (2k)
     std::string err;
     rocblas_handle blas = nullptr;
     long iters = 0;
@@ -825,6 +826,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->lam_prev_h = c->lam_h;
     c->theta_h = c->lam_h;
     c->zeros = c->alloc<double>(k);
+    PASM_HIP(hipHostMalloc((void**)&c->lam_pin, 2 * k * sizeof(double), hipHostMallocDefault));
     PASM_HIP(hipMemsetAsync(c->zeros, 0, k * sizeof(double), c->st));
     PASM_HIP(hipMemcpyAsync(c->lam, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
     PASM_HIP(hipMemcpyAsync(c->lam_prev, c->lam_h.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
@@ -837,15 +839,21 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
 // u = P Q y' + s u~ (s == nullptr: u = P Q y'); with s given, also the next
 // step's right-hand side f = lamf M u in the same pass (lamf == nullptr: the
 // new eigenvalues mu).
-void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr) {
+// coarse_ready: Q y' is already in place (U when the fine level is V_H, else
+// the coarse level's B).
+void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, bool coarse_ready = false) {
     const int k = c->k, N = c->NH;
     const pasm::Level& L0 = c->lv[0];
     if (c->L == 1) {
         // the fine level is V_H itself: the augmentation is always skipped (s = 0)
-        pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->U, L0.g.plane, true, k, c->dmv, c->st);
+        if (!coarse_ready)
+            pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->U, L0.g.plane, true, k, c->dmv,
+                                          c->st);
         return;
     }
-    pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->lv[0].B, L0.g.plane, true, k, c->dmv, c->st);
+    if (!coarse_ready)
+        pasm::launch_dense_mv<double>(c->Qcm, N, L0.g, c->ycoef, N, false, c->lv[0].B, L0.g.plane, true, k, c->dmv,
+                                      c->st);
     if (s && c->dim == 2) {
         // 2D: from the coarse space straight to the finest level (P1
         // interpolation on the coarse triangles), with the next step's
@@ -1129,6 +1137,7 @@ PASM_API pasm_status pasm_destroy(pasm_ctx* c) {
     if (!c) return PASM_OK;
     if (c->st) (void)hipStreamSynchronize(c->st);
     for (void* p : c->allocs) (void)hipFree(p);
+    if (c->lam_pin) (void)hipHostFree(c->lam_pin);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->blas) rocblas_destroy_handle(c->blas);
     if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
@@ -1176,8 +1185,9 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
     PASM_TRY(c, {
         iterate_once(c);
         c->lam_prev_h = c->lam_h;
-        PASM_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
         PASM_HIP(hipStreamSynchronize(c->st));
+        std::copy(c->lam_pin, c->lam_pin + c->k, c->lam_h.begin());
         collect_profile(c);
         ++c->iters;
         double dmax = 0.0;
@@ -1202,10 +1212,12 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
     PASM_TRY(c, {
         for (int i = 0; i < n; ++i) iterate_once(c);
         // the eigenvalues before and after the last step, in one synchronisation
-        PASM_HIP(hipMemcpyAsync(c->lam_prev_h.data(), c->lam_prev, c->k * sizeof(double), hipMemcpyDeviceToHost,
-                                c->st));
-        PASM_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        // (pinned host memory: both copies are asynchronous)
+        PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam_prev, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        PASM_HIP(hipMemcpyAsync(c->lam_pin + c->k, c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
         PASM_HIP(hipStreamSynchronize(c->st));
+        std::copy(c->lam_pin, c->lam_pin + c->k, c->lam_prev_h.begin());
+        std::copy(c->lam_pin + c->k, c->lam_pin + 2 * c->k, c->lam_h.begin());
         collect_profile(c);
         c->iters += n;
         double dmax = 0.0;
@@ -1232,14 +1244,15 @@ PASM_API pasm_status pasm_restart(pasm_ctx* c) {
         const int k = c->k, N = c->NH;
         c->lam_h = c->theta_h;
         c->lam_prev_h = c->theta_h;
-        pasm::launch_copy(c->theta, c->lam, k, c->st);
-        pasm::launch_copy(c->theta, c->lam_prev, k, c->st);
-        pasm::launch_unit_coefs(c->ycoef, N, k, k, c->st);
-        PASM_CHECK_LAUNCH();
+        // lambda = lambda_prev = theta, unit coefficients, and q_i itself as
+        // the coarse vector Q e_i, in one launch
+        const pasm::Level& L0 = c->lv[0];
+        pasm::launch_restart_coarse(c->Qcm, N, L0.g, c->L == 1 ? c->U : L0.B, L0.g.plane, c->ycoef, k, k, 0,
+                                    c->theta, 0, c->lam, c->lam_prev, c->st);
         // u_i = P q_i (weights of the old u all zero) and the first step's
         // right-hand side theta_i M u_i in the same pass; left in flight on
         // the context's stream (everything that reads it is ordered there)
-        prolong_coefs(c, c->zeros, c->lam);
+        prolong_coefs(c, c->zeros, c->lam, true);
     });
     return PASM_OK;
 }

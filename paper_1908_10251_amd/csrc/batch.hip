@@ -306,11 +306,13 @@ void bcorrect(pasm_batch* b, const std::vector<T*>& cur) {
 }
 
 // u = P Q y' (+ s u when s != nullptr) for every member
-void bprolong_coefs(pasm_batch* b, const double* s) {
+// coarse_ready: Q y' is already in the coarse level's B.
+void bprolong_coefs(pasm_batch* b, const double* s, bool coarse_ready = false) {
     const int k = b->k, N = b->NH, L = b->Lmax;
     const BLevel& L0 = b->lv[0];
-    pasm::launch_dense_mv<double>(b->Qcm, N, L0.g, b->ycoef, N, false, L0.B, L0.g.plane, true, b->n * k, b->dmv,
-                                  b->st, k, (long)N * N);
+    if (!coarse_ready)
+        pasm::launch_dense_mv<double>(b->Qcm, N, L0.g, b->ycoef, N, false, L0.B, L0.g.plane, true, b->n * k, b->dmv,
+                                      b->st, k, (long)N * N);
     for (int l = 1; l < L; ++l) {
         const BLevel& Lv = b->lv[l];
         const BLevel& Lc = b->lv[l - 1];
@@ -671,13 +673,12 @@ void bbuild(pasm_batch* b, const BPlan& pl, const pasm_instance* inst) {
 
 void brestart(pasm_batch* b) {
     const int nk = b->n * b->k, N = b->NH;
-    // lambda = theta_i per member
-    for (int s = 0; s < b->n; ++s) {
-        pasm::launch_copy(b->theta + (size_t)s * N, b->lam + (size_t)s * b->k, b->k, b->st);
-        pasm::launch_copy(b->theta + (size_t)s * N, b->lam_prev + (size_t)s * b->k, b->k, b->st);
-    }
-    pasm::launch_unit_coefs(b->ycoef, N, nk, b->k, b->st);
-    bprolong_coefs(b, nullptr);
+    // lambda = lambda_prev = theta_i per member, unit coefficients, and q_i
+    // itself as the coarse vector Q e_i, in one launch
+    const BLevel& L0 = b->lv[0];
+    pasm::launch_restart_coarse(b->Qcm, N, L0.g, L0.B, L0.g.plane, b->ycoef, nk, b->k, (long)N * N, b->theta, N,
+                                b->lam, b->lam_prev, b->st);
+    bprolong_coefs(b, nullptr, true);
     PASM_HIP(hipMemcpyAsync(b->lam_h.data(), b->lam, nk * sizeof(double), hipMemcpyDeviceToHost, b->st));
     PASM_HIP(hipStreamSynchronize(b->st));
     b->lam_prev_h = b->lam_h;

@@ -1208,6 +1208,38 @@ void dmv_part_launch(int kb, const T* Mat, int N, const Grid& g, const T* x, lon
     PASM_CHECK_LAUNCH();
 }
 
+// Restart of the iteration.  With unit coefficients y_r = e_j (j = r mod kpm)
+// the coarse vector Q y_r is column j of Q itself, so it is gathered (the
+// value the dense product gives, without streaming the whole of Q); the same
+// launch sets the unit coefficients and lambda = lambda_prev = theta_j.
+__global__ __launch_bounds__(256) void k_restart_coarse(const double* __restrict__ Mat, int N, Grid g,
+                                                        double* __restrict__ y, long sy, double* __restrict__ ycoef,
+                                                        int kpm, long mstride, const double* __restrict__ theta,
+                                                        long tstride, double* __restrict__ lam,
+                                                        double* __restrict__ lam_prev) {
+    const int row = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    const int mem = r / kpm, j = r % kpm;
+    if (row < N) {
+        ycoef[(long)r * N + row] = row == j ? 1.0 : 0.0;
+        y[(long)r * sy + compact_to_padded(g, row)] = Mat[(long)mem * mstride + (long)j * N + row];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double t = theta[(long)mem * tstride + j];
+        lam[r] = t;
+        lam_prev[r] = t;
+    }
+}
+
+void launch_restart_coarse(const double* Mat, int N, const Grid& g, double* y, long sy, double* ycoef, int nrhs,
+                           int kpm, long mstride, const double* theta, long tstride, double* lam, double* lam_prev,
+                           hipStream_t st) {
+    if (nrhs <= 0 || kpm <= 0 || nrhs % kpm != 0 || kpm > N)
+        throw Error(PASM_E_INVALID, "restart: right-hand sides not a multiple per member");
+    hipLaunchKernelGGL(k_restart_coarse, dim3((N + 255) / 256, nrhs), dim3(256), 0, st, Mat, N, g, y, sy, ycoef, kpm,
+                       mstride, theta, tstride, lam, lam_prev);
+    PASM_CHECK_LAUNCH();
+}
+
 template <typename T>
 void launch_dense_mv(const T* Mat, int N, const Grid& g, const T* x, long sx, bool x_padded, T* y, long sy,
                      bool y_padded, int nrhs, void* work, hipStream_t st, int kpm, long mstride) {

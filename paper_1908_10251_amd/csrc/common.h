@@ -281,6 +281,11 @@ void launch_scale_cols(const double* q, const double* th, double* o, int n, hipS
 void launch_d2f(const double* a, float* b, long n, hipStream_t st);
 void launch_unit_coefs(double* y, int N, int nrhs, int kpm, hipStream_t st);
 void launch_copy(const double* a, double* b, int n, hipStream_t st);
+// Restart: y_r = column (r mod kpm) of member r / kpm's Q (padded layout, stride
+// sy), unit coefficients in ycoef, lam = lam_prev = theta[member * tstride + j].
+void launch_restart_coarse(const double* Mat, int N, const Grid& g, double* y, long sy, double* ycoef, int nrhs,
+                           int kpm, long mstride, const double* theta, long tstride, double* lam, double* lam_prev,
+                           hipStream_t st);
 
 // ----------------------------------------------------------------------------
 // Coarse-space kernels (coarse.hip)

@@ -121,6 +121,26 @@ def test_batch_graph_replays_equal_eager_launches():
             assert np.array_equal(r, runs[0])
 
 
+def test_batch_restart_matches_the_start_after_setup():
+    """A restart (columns of each member's Q gathered, lambda = theta per
+    member) gives the iterates of the start that set-up forms with the dense
+    products."""
+    _say("batch restart vs set-up start")
+    k = 2
+    mem = _members()
+    with P.Batch(H, k, [(1 / nf, kap, vel) for nf, _, kap, vel in mem], opts=_opts()) as b:
+        runs = []
+        for restart in (False, True):
+            if restart:
+                P.pasm_batch_restart(b.b)
+            h = []
+            for _ in range(3):
+                b.iterate()
+                h.append(b.eigenvalues())
+            runs.append(np.array(h))
+    assert np.max(np.abs(runs[1] - runs[0]) / runs[0]) < 1e-12
+
+
 def test_batch_every_tile_height_agrees():
     _say("batch tiles")
     k = 2

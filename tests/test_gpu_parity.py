@@ -349,6 +349,27 @@ def test_iterate_n_equals_single_steps():
         assert P.pasm_iterate_n(s.ctx, 1) in (True, False)
 
 
+def test_restart_matches_the_start_after_setup():
+    # set-up forms u_i = P q_i with the dense product Q e_i; a restart gathers
+    # the column q_i instead and fuses the first right-hand side into the
+    # prolongation: the same iterates to rounding
+    _say("restart vs set-up start")
+    with P.Solver(2, 1 / 8, 1 / 64, 4, opts=_opts("cheb", 4)) as s:
+        hist0 = []
+        for _ in range(3):
+            s.iterate()
+            hist0.append(s.eigenpairs()[0])
+        U0 = s.eigenpairs()[1]
+        P.pasm_restart(s.ctx)
+        hist1 = []
+        for _ in range(3):
+            s.iterate()
+            hist1.append(s.eigenpairs()[0])
+        U1 = s.eigenpairs()[1]
+    assert np.max(np.abs(np.array(hist1) - np.array(hist0)) / np.array(hist0)) < 1e-12
+    assert np.max(np.abs(U1 - U0)) < 1e-10 * np.max(np.abs(U0))
+
+
 def test_fine_equal_coarse_returns_coarse_ritz_pairs():
     _say("h = H")
     prob = O.make_problem(2, 8, 8)
