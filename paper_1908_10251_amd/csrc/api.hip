@@ -117,6 +117,10 @@ struct pasm_ctx {
     double lplain_ms = 0.0, llearned_ms = 0.0;
     // borders formed by the last V-cycle's fine post-smoothing (2D, FP64)
     bool border_next = false, border_done = false;
+    // FP64 cycles in a row: the finest post-smoothing of a cycle followed by a
+    // further cycle runs together with that cycle's pre-smoothing, which then
+    // finds its work done (x pre-smoothed, the coarse right-hand side formed)
+    bool pair_next = false, fine_pre_done = false;
     int border_nblk = 0;
     // F64 holds lambda M u for the current U and lam (formed by the last
     // step's prolongation); anything else that touches U, lam or F64 clears it
@@ -346,14 +350,30 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         // marching phases: pre-smoothing with the residual restriction fused,
         // post-smoothing with the prolongation fused
         const double nodes = (double)L.g.interior() * nrhs, w = sizeof(T);
-        if (fine) record_start(c);
-        pasm::launch_march_pre<T>(L.g, (T)L.w0, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
-        if (fine) record_end(c, ((x_zero ? 2.0 : 3.0) + 0.25) * w * nodes);
-        std::swap(x, y);
+        const bool pre_done = fine && c->fine_pre_done;
+        if (fine) c->fine_pre_done = false;
+        if (!pre_done) {
+            if (fine) record_start(c);
+            pasm::launch_march_pre<T>(L.g, (T)L.w0, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
+            if (fine) record_end(c, ((x_zero ? 2.0 : 3.0) + 0.25) * w * nodes);
+            std::swap(x, y);
+        }
         vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
         if (fine) record_start(c);
         bool fused_border = false;
         if constexpr (std::is_same<T, double>::value) {
+            if (fine && c->pair_next &&
+                pasm::march_pair_supported(L.g, L.const_coef, (int)L.post.size(), (int)L.pre.size())) {
+                // this cycle's post-smoothing and the next cycle's pre-smoothing
+                // in one pass: x, f, y, the coarse correction and the coarse
+                // right-hand side
+                pasm::launch_march_post_pre(L.g, L.w0, x, f, y, Lc.g, xc, fc, nrhs, to_steps(L.post),
+                                            to_steps(L.pre), c->st);
+                record_end(c, 3.5 * w * nodes);
+                std::swap(x, y);
+                c->fine_pre_done = true;
+                return;
+            }
             if (fine && c->border_next && c->dim == 2) {
                 // the borders of the next step come from this post-smoothing's output
                 c->border_nblk = pasm::launch_march_post_border(L.g, L.w0, x, f, y, Lc.g, xc, Lc.B, Lc.C, c->partial,
@@ -413,7 +433,9 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
                bool next = false) {
     const int lf = c->L - 1;
     if (!c->mixed) {
+        c->pair_next = next;
         vcycle<double>(c, lf, x, scr, f, false, nrhs);
+        c->pair_next = false;
         return;
     }
     const Grid& g = c->gf();
@@ -459,12 +481,14 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
                 bool border = false, bool eig = false) {
     if (!c->learned_on) {
         bool r_ready = false;
+        c->fine_pre_done = false;
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
             c->border_next = border && cy == ncycles - 1 && !c->mixed;
             one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles);
             c->border_next = false;
         }
+        if (c->fine_pre_done) throw Error(PASM_E_DEVICE, "paired smoothing phases: a cycle left unfinished");
         return;
     }
     const Grid& g = c->gf();

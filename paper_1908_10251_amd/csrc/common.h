@@ -155,6 +155,14 @@ void launch_march_post(const Grid& g, T w0, const T* x, const T* f, T* out, cons
 int launch_march_post_border(const Grid& g, double w0, const double* x, const double* f, double* out, const Grid& gc,
                              const double* ec, double* bc, double* cc, double* partial, int nrhs,
                              const SmoothSteps& ss, hipStream_t st, int rows = 0);
+// The post-smoothing of one V-cycle and the pre-smoothing of the next in one
+// pass (FP64): out = the pre-smoothed x of the next cycle, starting from
+// x + P ec, and rc = P^T (f - A out) on gc; post.s + pre.s <= 8.  Equal to
+// launch_march_post followed by launch_march_pre on its output.
+bool march_pair_supported(const Grid& g, bool const_coef, int post, int pre);
+void launch_march_post_pre(const Grid& g, double w0, const double* x, const double* f, double* out, const Grid& gc,
+                           const double* ec, double* rc, int nrhs, const SmoothSteps& post, const SmoothSteps& pre,
+                           hipStream_t st);
 
 // Marching smoothing phases (3D, constant coefficients, 128 cells per side,
 // 1 or 2 steps): out = x_s from x0 (or from 0), or (post) from x + P ec.

@@ -46,6 +46,10 @@ constexpr int prefetch_rows() { return sizeof(T) == 8 ? 3 : 6; }
 constexpr int gcd_(int a, int b) { return b == 0 ? a : gcd_(b, a % b); }
 constexpr int lcm_(int a, int b) { return a / gcd_(a, b) * b; }
 constexpr int march_unroll(int S, int PF) { return lcm_(lcm_(3, S + 2), PF); }
+// Columns of halo on each side of a strip: S + 2 (S smoothing steps, then the
+// residual and its restriction one node further each), rounded up to even so
+// that every lane's first column, the centre of a restriction, is even.
+constexpr int march_halo(int S) { return (S + 3) & ~1; }
 
 // Cross-lane moves of a double by one lane (DPP wave shifts; the lane at the
 // wavefront edge receives 0, which only ever reaches halo columns).
@@ -80,13 +84,16 @@ __device__ inline float detach(float v) {
 }
 
 template <typename T, int S, int MODE, bool XZ>
-__global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
+__global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
                                               T* __restrict__ out, const T* __restrict__ ec, Grid gc,
                                               T* __restrict__ rc, T* __restrict__ rc2, double* __restrict__ part,
                                               long sf, long sc, SmoothSteps st, MarchShape sh) {
-    constexpr bool POSTLIKE = MODE == 2 || MODE == 3;
+    // MODE 4: the post-smoothing of one V-cycle and the pre-smoothing of the
+    // next in one pass (S = post + pre stages; the host zeroes the momentum
+    // coefficient of the first pre-smoothing stage)
+    constexpr bool POSTLIKE = MODE == 2 || MODE == 3 || MODE == 4;
     constexpr int PF = prefetch_rows<T>();
-    constexpr int HX = S + 2;
+    constexpr int HX = march_halo(S);
     constexpr int TXO = MW - 2 * HX;
     // One wavefront per workgroup.  Consecutive pieces of work (strips of a
     // band of rows, then the next band, then the next right-hand side) go to
@@ -129,7 +136,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     T bs[S], as[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        bs[t] = (T)st.b[t] * invD;
+        bs[t] = MODE == 4 ? (T)st.b[t] : (T)st.b[t] * invD;  // MODE 4: scaled by the host
         as[t] = (T)st.a[t];
     }
 
@@ -148,7 +155,9 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     for (int k = 0; k < 3; ++k) rw[k][0] = rw[k][1] = mw[k][0] = mw[k][1] = T(0);
 
     const int r_begin = y0 - 2 - S;
-    const int r_end = y0 + MSEG + S;
+    // the restriction centred on the band's last row (even in a reflected
+    // band) is formed one row after x_S of the row below it
+    const int r_end = y0 + MSEG + S + 1;
 
     // Loads are branch-free so that rows requested PF steps ahead stay in
     // flight: positions outside the grid are clamped onto the boundary ring,
@@ -243,7 +252,7 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
                     if (owned[cc] && inner[cc]) outr[id + fs * cc] = xw[S][0][cc];
             }
         }
-        if (MODE == 1) {
+        if (MODE == 1 || MODE == 4) {
             // residual at row r - S - 1 from x_S rows (r-S, r-S-1, r-S-2)
             const int q1 = r - S - 1;
             const bool row_in = q1 >= 1 && q1 <= g.m;
@@ -337,7 +346,9 @@ __global__ __launch_bounds__(NL) void k_march(Grid g, T w0, const T* __restrict_
     // unrolling every window and slot is back in its own registers at the
     // back edge.  Rows past r_end (at most UNR - 1) only feed halo stages:
     // nothing stored depends on them.
-    constexpr int UNR = march_unroll(S, PF);
+    // (MODE 4's f window of S + 2 rows is left out of the period: its
+    // registers are moved once per body instead of unrolling 30 rows.)
+    constexpr int UNR = MODE == 4 ? lcm_(3, PF) : march_unroll(S, PF);
     const int iters = (r_end - r_begin + UNR) / UNR;
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
@@ -402,7 +413,7 @@ template <typename T, int S, int MODE>
 int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc, T* rc2,
                  double* part, int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows,
                  hipStream_t st) {
-    constexpr int TXO = MW - 2 * (S + 2);
+    constexpr int TXO = MW - 2 * march_halo(S);
     static const int slots = device_wave_slots(k_march<T, S, MODE, false>);
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
     if constexpr (MODE == 1) {
@@ -417,6 +428,24 @@ int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* 
                        rc2, part, sf, sc, ss, sh);
     PASM_CHECK_LAUNCH();
     return sh.strips * sh.segs;
+}
+
+// MODE 4 (FP64): the post-smoothing of one V-cycle, with its prolongation,
+// and the next cycle's pre-smoothing, with its residual restriction, in one
+// pass.  More registers per wavefront than one phase, so the bands are sized
+// for a single round of resident wavefronts.
+template <int S>
+void march_pair_launch(const Grid& g, double w0, const double* x, const double* f, double* out, const double* ec,
+                       const Grid& gc, double* rc, int nrhs, const SmoothSteps& ss, hipStream_t st) {
+    constexpr int TXO = MW - 2 * march_halo(S);
+    static const int slots = device_wave_slots(k_march<double, S, 4, false>);
+    const long strips = (g.n + 1 + TXO - 1) / TXO;
+    const long bands = std::max<long>(1, slots / (strips * nrhs));
+    const int rows = std::max(16, (int)((g.n + 1 + bands - 1) / bands));
+    const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
+    hipLaunchKernelGGL((k_march<double, S, 4, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x, f, out, ec, gc,
+                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh);
+    PASM_CHECK_LAUNCH();
 }
 
 template <typename T, int MODE>
@@ -439,6 +468,40 @@ int march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T
 // tile kernels.
 bool march_supported(const Grid& g, bool const_coef, int steps) {
     return g.dim == 2 && const_coef && steps >= 1 && steps <= 4 && g.n >= 256;
+}
+
+bool march_pair_supported(const Grid& g, bool const_coef, int post, int pre) {
+    return march_supported(g, const_coef, post) && march_supported(g, const_coef, pre) && post + pre <= 8;
+}
+
+void launch_march_post_pre(const Grid& g, double w0, const double* x, const double* f, double* out, const Grid& gc,
+                           const double* ec, double* rc, int nrhs, const SmoothSteps& post, const SmoothSteps& pre,
+                           hipStream_t st) {
+    if (!march_pair_supported(g, true, post.s, pre.s) || gc.n * 2 != g.n)
+        throw Error(PASM_E_INVALID, "paired marching phases: 2D, ratio 2, at most 8 steps");
+    // the step sizes come scaled by 1 / (4 w0) (the diagonal), as the
+    // one-phase kernels scale them, so that they stay in scalar registers
+    const double invD = 1.0 / (4.0 * w0);
+    SmoothSteps ss{};
+    ss.s = post.s + pre.s;
+    for (int t = 0; t < post.s; ++t) {
+        ss.a[t] = post.a[t];
+        ss.b[t] = post.b[t] * invD;
+    }
+    for (int t = 0; t < pre.s; ++t) {
+        // the first pre-smoothing step starts a new recurrence: no momentum term
+        ss.a[post.s + t] = t == 0 ? 0.0 : pre.a[t];
+        ss.b[post.s + t] = pre.b[t] * invD;
+    }
+    switch (ss.s) {
+        case 2: march_pair_launch<2>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+        case 3: march_pair_launch<3>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+        case 4: march_pair_launch<4>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+        case 5: march_pair_launch<5>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+        case 6: march_pair_launch<6>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+        case 7: march_pair_launch<7>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+        default: march_pair_launch<8>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+    }
 }
 
 template <typename T>

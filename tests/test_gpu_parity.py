@@ -95,6 +95,8 @@ VC = [
     # transfers; 513 nodes per side leave ragged strips and segments
     (2, 32, 512, None, "cheb", 4, False),
     (2, 64, 512, None, "jacobi", 2, False),
+    # odd step counts: strip halos rounded up to an even width
+    (2, 32, 512, None, "jacobi", 3, False),
     # general 7-point operators (potential term), Galerkin coarse levels
     (2, 4, 64, 1.0, "cheb", 4, True),
     (2, 8, 64, None, "jacobi", 2, True),
@@ -136,6 +138,34 @@ def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, pot, precision, f
                 tol = 1e-12 * max(1.0, (nf / 64) ** 2) if precision == P.PASM_FP64 else 2e-5
                 _say(f"  ncyc={ncyc} rhs={r} err={err:.2e} tol={tol:.1e}")
                 assert err < tol, (ncyc, r, err)
+
+
+@pytest.mark.parametrize("nf,smoother,pre,post", [(256, "cheb", 4, 4), (512, "jacobi", 2, 2), (256, "cheb", 3, 1),
+                                                  (512, "cheb", 1, 4), (256, "jacobi", 1, 1), (512, "jacobi", 3, 3)])
+def test_paired_smoothing_phases_equal_single_cycles(nf, smoother, pre, post):
+    # cycles in a row run the finest post-smoothing of one cycle and the
+    # pre-smoothing of the next in one pass; one cycle per call runs them as
+    # two passes: the same arithmetic (the two kernels may contract different
+    # products into fused multiply-adds, so equal to rounding).  Odd step
+    # counts and reflected bands whose last row carries a coarse node are
+    # among the cases.
+    _say(f"paired phases h=1/{nf} {smoother} pre={pre} post={post}")
+    nc, k = 8, 3
+    rng = np.random.default_rng(5)
+    o = P.options(smoother=P.PASM_CHEBYSHEV if smoother == "cheb" else P.PASM_JACOBI, nu_pre=pre, nu_post=post)
+    with P.Solver(2, 1 / nc, 1 / nf, k, opts=o) as s:
+        N = P.pasm_num_dofs(s.ctx)
+        f = _t(rng.standard_normal((k, N)))
+        x0 = rng.standard_normal((k, N))
+        xa = _t(x0)
+        P.pasm_vcycle(s.ctx, f, xa, 3)
+        xb = _t(x0)
+        for _ in range(3):
+            P.pasm_vcycle(s.ctx, f, xb, 1)
+        rel = float(torch.max(torch.abs(xa - xb)) / torch.max(torch.abs(xb)))
+        _say(f"  paired vs single cycles: {rel:.2e}")
+        assert rel < 1e-13
+        assert float(torch.max(torch.abs(xa - _t(x0)))) > 0.0
 
 
 _HIER_3D = {}
