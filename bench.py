@@ -45,9 +45,10 @@ PEAK_BF16_TFLOPS = 2500.0
 KERNEL_SOURCES = ["paper_1908_10251_amd/csrc/march2d.hip"]
 
 KERNEL_NAMES = {
-    2: "finest-level smoothing phases (k_march: pre-smoothing with fused residual restriction, "
-       "post-smoothing with fused prolongation, the last one also forming the borders; k_smooth_fused where "
-       "coefficients vary)",
+    2: "finest-level smoothing phases (k_march: pre-smoothing with fused residual restriction; a V-cycle's "
+       "post-smoothing with fused prolongation together with the next cycle's pre-smoothing and restriction in "
+       "one pass; the last post-smoothing of a step also forming the borders; k_smooth_fused where coefficients "
+       "vary)",
     3: "finest-level smoothing phases (k_march3: all steps of a phase in one pass marching along z, "
        "post-smoothing with fused prolongation)",
     "learned": "finest-level learned smoothing step (k_learned_step: residual, two bfloat16 matrix-core "
