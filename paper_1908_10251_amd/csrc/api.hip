@@ -121,6 +121,10 @@ struct pasm_ctx {
     // further cycle runs together with that cycle's pre-smoothing, which then
     // finds its work done (x pre-smoothed, the coarse right-hand side formed)
     bool pair_next = false, fine_pre_done = false;
+    // steps in a row (FP64 2D): a step's prolongation u = P Q y' + s u~ and
+    // the next right-hand side are left to the next step's first finest
+    // pre-smoothing, which forms both in its pass (Q y' waits in lv[0].B)
+    bool prolong_pending = false;
     int border_nblk = 0;
     // F64 holds lambda M u for the current U and lam (formed by the last
     // step's prolongation); anything else that touches U, lam or F64 clears it
@@ -354,7 +358,21 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         if (fine) c->fine_pre_done = false;
         if (!pre_done) {
             if (fine) record_start(c);
-            pasm::launch_march_pre<T>(L.g, (T)L.w0, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
+            bool prolonged = false;
+            if constexpr (std::is_same<T, double>::value) {
+                if (fine && c->prolong_pending) {
+                    // x holds u~; x_0 = P Q y' + s u~ and f = lambda M x_0 come
+                    // from the pass (f into F64, which f points to), then PRE
+                    if (f != c->F64) throw Error(PASM_E_DEVICE, "prolonging pre-smoothing: unexpected right-hand side");
+                    pasm::launch_march_pre_prolong(L.g, L.w0, x, c->F64, y, Lc.g, fc, c->lv[0].g, c->lv[0].B, c->s,
+                                                   c->lam, nrhs, to_steps(L.pre), c->st);
+                    c->prolong_pending = false;
+                    prolonged = true;
+                }
+            }
+            if (!prolonged)
+                pasm::launch_march_pre<T>(L.g, (T)L.w0, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
+            // u~ (or x_0), f, y and the coarse right-hand side
             if (fine) record_end(c, ((x_zero ? 2.0 : 3.0) + 0.25) * w * nodes);
             std::swap(x, y);
         }
@@ -904,7 +922,18 @@ void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, b
     pasm::launch_prolong<double>(Lc.g, Lc.B, c->gf(), c->U, k, Lc.g.plane, c->sf(), false, s, c->st);
 }
 
-void iterate_once(pasm_ctx* c) {
+// Whether a step's prolongation can be left to the next step's first
+// pre-smoothing (FP64 2D marching finest level, at least one V-cycle).
+bool prolong_deferrable(const pasm_ctx* c) {
+    if (c->dim != 2 || c->mixed || c->learned_on || c->L < 2 || !c->fuse || c->opt.vcycles < 1) return false;
+    const pasm::Level& L = c->lv[c->L - 1];
+    return pasm::march_supported(L.g, L.const_coef, (int)L.post.size()) &&
+           pasm::march_prolong_supported(L.g, L.const_coef, (int)L.pre.size(), c->lv[0].g);
+}
+
+// One correction step.  defer: another step follows at once, so the
+// prolongation may be left to its first pre-smoothing.
+void iterate_once(pasm_ctx* c, bool defer = false) {
     const int k = c->k, N = c->NH, lf = c->L - 1;
     const Grid& g = c->gf();
     const long sf = c->sf();
@@ -915,6 +944,10 @@ void iterate_once(pasm_ctx* c) {
     c->border_done = false;
     if (c->L > 1) {
         bvp_cycles(c, c->U, c->Y64, c->F64, k, c->opt.vcycles, c->dim == 2 && c->L >= 2, true);
+        if (c->prolong_pending) {
+            c->prolong_pending = false;
+            throw Error(PASM_E_DEVICE, "prolonging pre-smoothing: the prolongation was not consumed");
+        }
     } else {
         // fine level = V_H: exact solve
         coarse_solve<double>(c, c->F64, c->U, k);
@@ -961,7 +994,15 @@ void iterate_once(pasm_ctx* c) {
     pasm::ArrowIn in{c->theta, c->group, c->pp, c->qq, c->bz, c->lam, N, c->opt.exhaustive_selection};
     pasm::ArrowOut out{c->ycoef, c->s, c->mu, c->rank, c->score, c->flags, static_cast<double*>(c->awork)};
     pasm::launch_arrowhead(in, out, k, c->st);
-    prolong_coefs(c, c->s);
+    if (defer && prolong_deferrable(c)) {
+        // Q y' now; P Q y' + s u~ and f = mu M u in the next step's first pass
+        pasm::launch_dense_mv<double>(c->Qcm, N, c->lv[0].g, c->ycoef, N, false, c->lv[0].B, c->lv[0].g.plane, true,
+                                      k, c->dmv, c->st);
+        c->prolong_pending = true;
+        c->f_ready = true;
+    } else {
+        prolong_coefs(c, c->s);
+    }
     // lam_prev <- lam, lam <- mu by rotating the three buffers (no copies)
     std::swap(c->lam_prev, c->lam);
     std::swap(c->lam, c->mu);
@@ -1234,7 +1275,8 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
     if (!c || c->k == 0) return PASM_E_STATE;
     if (n < 1) return PASM_E_INVALID;
     PASM_TRY(c, {
-        for (int i = 0; i < n; ++i) iterate_once(c);
+        c->prolong_pending = false;
+        for (int i = 0; i < n; ++i) iterate_once(c, i + 1 < n);
         // the eigenvalues before and after the last step, in one synchronisation
         // (pinned host memory: both copies are asynchronous)
         PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam_prev, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));

@@ -163,6 +163,16 @@ bool march_pair_supported(const Grid& g, bool const_coef, int post, int pre);
 void launch_march_post_pre(const Grid& g, double w0, const double* x, const double* f, double* out, const Grid& gc,
                            const double* ec, double* rc, int nrhs, const SmoothSteps& post, const SmoothSteps& pre,
                            hipStream_t st);
+// The first pre-smoothing of a correction step (FP64) with the previous
+// step's prolongation in the pass: x_0 = P q + beta u (u the old field, q the
+// coarse-space field on gq, P1 interpolation on the coarse "/" triangles,
+// power-of-two ratio), f = lam M x_0 written to fout, out = x_s and
+// rc = P^T (f - A out) on gc.  Equal to launch_prolong_mass followed by
+// launch_march_pre on its output.
+bool march_prolong_supported(const Grid& g, bool const_coef, int pre, const Grid& gq);
+void launch_march_pre_prolong(const Grid& g, double w0, const double* u, double* fout, double* out, const Grid& gc,
+                              double* rc, const Grid& gq, const double* q, const double* beta, const double* lam,
+                              int nrhs, const SmoothSteps& pre, hipStream_t st);
 
 // Marching smoothing phases (3D, constant coefficients, 128 cells per side,
 // 1 or 2 steps): out = x_s from x0 (or from 0), or (post) from x + P ec.

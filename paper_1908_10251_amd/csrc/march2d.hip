@@ -83,15 +83,34 @@ __device__ inline float detach(float v) {
     return r;
 }
 
+// MODE 5: the coarse-space field q (padded level, ratio 2^lr to the fine grid)
+// that the first pre-smoothing interpolates, with the weights beta of the old
+// field and the eigenvalues lam of the right-hand side f = lam M x_0 it forms.
+struct ProlongSrc {
+    Grid gq;
+    const double* q;
+    long sq;
+    int lr;
+    const double* beta;
+    const double* lam;
+    double* fout;
+};
+
 template <typename T, int S, int MODE, bool XZ>
 __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
                                               T* __restrict__ out, const T* __restrict__ ec, Grid gc,
                                               T* __restrict__ rc, T* __restrict__ rc2, double* __restrict__ part,
-                                              long sf, long sc, SmoothSteps st, MarchShape sh) {
+                                              long sf, long sc, SmoothSteps st, MarchShape sh, ProlongSrc ps) {
     // MODE 4: the post-smoothing of one V-cycle and the pre-smoothing of the
     // next in one pass (S = post + pre stages; the host zeroes the momentum
     // coefficient of the first pre-smoothing stage)
     constexpr bool POSTLIKE = MODE == 2 || MODE == 3 || MODE == 4;
+    // MODE 5: pre-smoothing whose x_0 = P q + beta u (P1 interpolation on the
+    // coarse "/" triangles) and whose right-hand side f = lam M x_0 are formed
+    // in the pass (f is also written out): the prolongation of the previous
+    // correction step and this step's first pre-smoothing in one pass
+    constexpr bool PROLONG = MODE == 5;
+    static_assert(!PROLONG || sizeof(T) == 8, "the prolonging pass is FP64");
     constexpr int PF = prefetch_rows<T>();
     constexpr int HX = march_halo(S);
     constexpr int TXO = MW - 2 * HX;
@@ -132,6 +151,18 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const T* fr = f + off;
     T* outr = out + off;
     const T* ecr = ec + (long)z * sc;
+    double bz = 0.0, lz = 0.0;
+    const double* qr = nullptr;
+    double* fo = nullptr;
+    if constexpr (PROLONG) {
+        bz = ps.beta[z];
+        lz = ps.lam[z];
+        qr = ps.q + (long)z * ps.sq;
+        fo = ps.fout + off;
+    }
+    const int PR = 1 << ps.lr;
+    const double invPR = 1.0 / PR;
+    const double h2 = g.h * g.h;
     const T invD = T(1) / (T(4) * w0);
     T bs[S], as[S];
 #pragma unroll
@@ -173,10 +204,29 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // reads are the same node and the mean is exact, so there is no branch.
     struct Slot {
         T x[2], f[2], e0[2], e1[2];
+        T q[2][3];  // MODE 5: the three coarse nodes of the triangle under each column
     };
     auto load = [&](int r, Slot& sl) {
         const int rr = min(max(r, 0), g.n);
         const long row = (long)gx(rr) * g.pitch + ORIGIN;
+        if constexpr (PROLONG) {
+            // the old field (used when its weight is nonzero) and the corners
+            // (I, J), (I + 1, J) or (I, J + 1), (I + 1, J + 1) of the coarse
+            // triangle, indices clamped onto the last coarse line where their
+            // weights are zero
+            sl.x[0] = xr[row + ga];
+            sl.x[1] = xr[row + gb];
+            const int gj = gx(rr), J = gj >> ps.lr, b = gj & (PR - 1), J1 = min(J + 1, ps.gq.n);
+            const int gcol[2] = {ga, gb};
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const int gi = gcol[cc], I = gi >> ps.lr, a = gi & (PR - 1), I1 = min(I + 1, ps.gq.n);
+                sl.q[cc][0] = qr[ps.gq.idx(I, J)];
+                sl.q[cc][1] = a >= b ? qr[ps.gq.idx(I1, J)] : qr[ps.gq.idx(I, J1)];
+                sl.q[cc][2] = qr[ps.gq.idx(I1, J1)];
+            }
+            return;
+        }
         sl.f[0] = fr[row + ga];
         sl.f[1] = fr[row + gb];
         if (POSTLIKE || !XZ) {
@@ -197,22 +247,60 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
     // Row r enters the windows of x_0 and f.  The window registers are fresh
     // copies, so the slot's registers are free for the next load at once.
-    auto shift_in = [&](const Slot& sl) {
+    auto shift_in = [&](const Slot& sl, const int r) {
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
             T cx;
-            if (POSTLIKE)
+            if constexpr (PROLONG) {
+                // P1 weights (R - wa, wa - wb, wb) / R in the grid's own
+                // coordinates, as the stand-alone prolongation computes them
+                const int rr = min(max(r, 0), g.n);
+                const int b = gx(rr) & (PR - 1), a = (cc ? gb : ga) & (PR - 1);
+                const int wa = a >= b ? a : b, wb = a >= b ? b : a;
+                double v = __builtin_fma((double)wb, sl.q[cc][2],
+                                         __builtin_fma((double)(wa - wb), sl.q[cc][1], (double)(PR - wa) * sl.q[cc][0])) *
+                           invPR;
+                if (bz != 0.0) v = __builtin_fma(bz, sl.x[cc], v);
+                cx = (r >= 1 && r <= g.m && inner[cc]) ? v : 0.0;
+            } else if (POSTLIKE) {
                 cx = sl.x[cc] + T(0.5) * (sl.e0[cc] + sl.e1[cc]);
-            else if (!XZ)
+            } else if (!XZ) {
                 cx = detach(sl.x[cc]);
-            else
+            } else {
                 cx = T(0);
+            }
 #pragma unroll
             for (int j = S + 1; j > 0; --j) fw[j][cc] = fw[j - 1][cc];
-            fw[0][cc] = detach(sl.f[cc]);
+            fw[0][cc] = PROLONG ? T(0) : detach(sl.f[cc]);
             xw[0][2][cc] = xw[0][1][cc];
             xw[0][1][cc] = xw[0][0][cc];
             xw[0][0][cc] = cx;
+        }
+        if constexpr (PROLONG) {
+            // f = lam M x_0 at row r - 1 from the x_0 rows (r, r-1, r-2): the
+            // six neighbours summed in the grid's order (right, left, up, down,
+            // (i+1, j+1), (i-1, j-1)); a reflected band sees each pair swapped
+            const int q = r - 1;
+            const T m0 = xw[0][1][0], m1 = xw[0][1][1];
+            const T up0 = xw[0][0][0], up1 = xw[0][0][1], dn0 = xw[0][2][0], dn1 = xw[0][2][1];
+            const T lf[2] = {from_left(m1), m0}, rt[2] = {m1, from_right(m0)};
+            const T up[2] = {up0, up1}, dn[2] = {dn0, dn1};
+            const T ne[2] = {up1, from_right(up0)}, sw[2] = {from_left(dn1), dn0};
+            const T mc[2] = {m0, m1};
+            const bool row_in = q >= 1 && q <= g.m;
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const T sn = (flip ? lf[cc] : rt[cc]) + (flip ? rt[cc] : lf[cc]) + (flip ? dn[cc] : up[cc]) +
+                             (flip ? up[cc] : dn[cc]) + (flip ? sw[cc] : ne[cc]) + (flip ? ne[cc] : sw[cc]);
+                const T fv = lz * (h2 * __builtin_fma(sn, 1.0 / 12.0, 0.5 * mc[cc]));
+                fw[1][cc] = (row_in && inner[cc]) ? fv : T(0);
+            }
+            if (q >= y0 && q < y0 + MSEG && row_in) {
+                const long id = g.idx(gx(i0), gx(q));
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc)
+                    if (owned[cc] && inner[cc]) fo[id + fs * cc] = fw[1][cc];
+            }
         }
     };
     // After row r entered: advance every stage by one row, store x_S of row
@@ -252,7 +340,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     if (owned[cc] && inner[cc]) outr[id + fs * cc] = xw[S][0][cc];
             }
         }
-        if (MODE == 1 || MODE == 4) {
+        if (MODE == 1 || MODE == 4 || MODE == 5) {
             // residual at row r - S - 1 from x_S rows (r-S, r-S-1, r-S-2)
             const int q1 = r - S - 1;
             const bool row_in = q1 >= 1 && q1 <= g.m;
@@ -355,7 +443,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
         for (int u = 0; u < UNR; ++u) {
             // the slot is refilled as soon as its row is in the windows
             const int r = r_begin + it * UNR + u;
-            shift_in(q[u % PF]);
+            shift_in(q[u % PF], r);
             load(r + PF, q[u % PF]);
             advance(r);
         }
@@ -419,13 +507,13 @@ int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* 
     if constexpr (MODE == 1) {
         if (x_zero) {
             hipLaunchKernelGGL((k_march<T, S, MODE, true>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
-                               gc, rc, rc2, part, sf, sc, ss, sh);
+                               gc, rc, rc2, part, sf, sc, ss, sh, ProlongSrc{});
             PASM_CHECK_LAUNCH();
             return sh.strips * sh.segs;
         }
     }
     hipLaunchKernelGGL((k_march<T, S, MODE, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
-                       rc2, part, sf, sc, ss, sh);
+                       rc2, part, sf, sc, ss, sh, ProlongSrc{});
     PASM_CHECK_LAUNCH();
     return sh.strips * sh.segs;
 }
@@ -434,17 +522,35 @@ int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* 
 // and the next cycle's pre-smoothing, with its residual restriction, in one
 // pass.  More registers per wavefront than one phase, so the bands are sized
 // for a single round of resident wavefronts.
+// Rows per band such that every wavefront of the launch is resident at once.
+int one_round_rows(const Grid& g, int txo, int nrhs, int slots) {
+    const long strips = (g.n + 1 + txo - 1) / txo;
+    const long bands = std::max<long>(1, slots / (strips * nrhs));
+    return std::max(16, (int)((g.n + 1 + bands - 1) / bands));
+}
+
 template <int S>
 void march_pair_launch(const Grid& g, double w0, const double* x, const double* f, double* out, const double* ec,
                        const Grid& gc, double* rc, int nrhs, const SmoothSteps& ss, hipStream_t st) {
     constexpr int TXO = MW - 2 * march_halo(S);
     static const int slots = device_wave_slots(k_march<double, S, 4, false>);
-    const long strips = (g.n + 1 + TXO - 1) / TXO;
-    const long bands = std::max<long>(1, slots / (strips * nrhs));
-    const int rows = std::max(16, (int)((g.n + 1 + bands - 1) / bands));
-    const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
+    const MarchShape sh = march_shape(g, TXO, nrhs, slots, one_round_rows(g, TXO, nrhs, slots));
     hipLaunchKernelGGL((k_march<double, S, 4, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x, f, out, ec, gc,
-                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh);
+                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh, ProlongSrc{});
+    PASM_CHECK_LAUNCH();
+}
+
+// MODE 5 (FP64): the first pre-smoothing of a correction step with the
+// previous step's prolongation and its right-hand side formed in the pass.
+template <int S>
+void march_prolong_launch(const Grid& g, double w0, const double* u, double* fout, double* out, const Grid& gc,
+                          double* rc, const ProlongSrc& ps, int nrhs, const SmoothSteps& ss, hipStream_t st) {
+    constexpr int TXO = MW - 2 * march_halo(S);
+    static const int slots = device_wave_slots(k_march<double, S, 5, false>);
+    const MarchShape sh = march_shape(g, TXO, nrhs, slots, one_round_rows(g, TXO, nrhs, slots));
+    hipLaunchKernelGGL((k_march<double, S, 5, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, u, fout, out,
+                       (const double*)nullptr, gc, rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh,
+                       ps);
     PASM_CHECK_LAUNCH();
 }
 
@@ -501,6 +607,33 @@ void launch_march_post_pre(const Grid& g, double w0, const double* x, const doub
         case 6: march_pair_launch<6>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
         case 7: march_pair_launch<7>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
         default: march_pair_launch<8>(g, w0, x, f, out, ec, gc, rc, nrhs, ss, st); break;
+    }
+}
+
+int ratio_log2(const Grid& g, const Grid& gq) {
+    if (gq.n <= 0 || g.n % gq.n != 0) return -1;
+    const int r = g.n / gq.n;
+    if (r < 2 || (r & (r - 1)) != 0) return -1;
+    int lr = 0;
+    while ((1 << lr) < r) ++lr;
+    return lr;
+}
+
+bool march_prolong_supported(const Grid& g, bool const_coef, int pre, const Grid& gq) {
+    return march_supported(g, const_coef, pre) && gq.dim == 2 && ratio_log2(g, gq) > 0;
+}
+
+void launch_march_pre_prolong(const Grid& g, double w0, const double* u, double* fout, double* out, const Grid& gc,
+                              double* rc, const Grid& gq, const double* q, const double* beta, const double* lam,
+                              int nrhs, const SmoothSteps& pre, hipStream_t st) {
+    if (!march_prolong_supported(g, true, pre.s, gq) || gc.n * 2 != g.n)
+        throw Error(PASM_E_INVALID, "prolonging pre-smoothing: 2D, power-of-two ratio to the coarse space");
+    const ProlongSrc ps{gq, q, gq.plane, ratio_log2(g, gq), beta, lam, fout};
+    switch (pre.s) {
+        case 1: march_prolong_launch<1>(g, w0, u, fout, out, gc, rc, ps, nrhs, pre, st); break;
+        case 2: march_prolong_launch<2>(g, w0, u, fout, out, gc, rc, ps, nrhs, pre, st); break;
+        case 3: march_prolong_launch<3>(g, w0, u, fout, out, gc, rc, ps, nrhs, pre, st); break;
+        default: march_prolong_launch<4>(g, w0, u, fout, out, gc, rc, ps, nrhs, pre, st); break;
     }
 }
 

@@ -645,8 +645,10 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
         const bool lower = a >= b;
         const int wa = lower ? a : b, wb = lower ? b : a;  // the larger and the smaller offset
         const double c0 = cs[jr][ir], c1 = lower ? cs[jr][ir + 1] : cs[jr + 1][ir], c2 = cs[jr + 1][ir + 1];
-        double v = ((double)(R - wa) * c0 + (double)(wa - wb) * c1 + (double)wb * c2) * invR;
-        if (bz != 0.0) v += bz * xv[e];  // a zero weight drops the old field (whatever it holds)
+        // explicit fused multiply-adds: the marching pre-smoothing that forms
+        // the same field on the fly rounds identically
+        double v = __builtin_fma((double)wb, c2, __builtin_fma((double)(wa - wb), c1, (double)(R - wa) * c0)) * invR;
+        if (bz != 0.0) v = __builtin_fma(bz, xv[e], v);  // a zero weight drops the old field (whatever it holds)
         if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
     }
     __syncthreads();
@@ -660,7 +662,7 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
                           us[b][a];
         const long id = (long)z * sf + gf.idx(i, j);
         xn[id] = x0;
-        f[id] = lz * (h2 * (0.5 * x0 + sn * (1.0 / 12.0)));
+        f[id] = lz * (h2 * __builtin_fma(sn, 1.0 / 12.0, 0.5 * x0));
     }
 }
 

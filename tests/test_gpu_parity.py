@@ -360,10 +360,16 @@ def test_small_laplace_iteration_history_matches_oracle():
             assert abs(hist[t][i] - lr) / lr < 1e-10, (i, t)
 
 
-def test_iterate_n_equals_single_steps():
-    # n steps with one synchronisation: the same launches as n single steps,
-    # so the same eigenvalues bit for bit and the same stop-test outcome
-    with P.Solver(2, 1 / 8, 1 / 64, 4, opts=_opts("cheb", 4)) as s:
+@pytest.mark.parametrize("nc,nf,smoother,nu", [(8, 64, "cheb", 4), (8, 256, "cheb", 4), (16, 512, "jacobi", 2),
+                                               (8, 256, "jacobi", 1)])
+def test_iterate_n_equals_single_steps(nc, nf, smoother, nu):
+    # n steps with one synchronisation.  From 256 cells on, each step but the
+    # last leaves its prolongation (u = P Q y' + s u~, f = lambda M u) to the
+    # next step's first marching pre-smoothing, which forms both in its pass
+    # with the stand-alone prolongation's arithmetic: the same eigenvalues
+    # and vectors bit for bit as n single steps, and the same stop test
+    _say(f"iterate_n H=1/{nc} h=1/{nf} {smoother} nu={nu}")
+    with P.Solver(2, 1 / nc, 1 / nf, 4, opts=_opts(smoother, nu)) as s:
         with pytest.raises(P.PasmError):
             P.pasm_iterate_n(s.ctx, 0)
         P.pasm_restart(s.ctx)
