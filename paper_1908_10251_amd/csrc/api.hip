@@ -125,6 +125,7 @@ struct pasm_ctx {
     // the next right-hand side are left to the next step's first finest
     // pre-smoothing, which forms both in its pass (Q y' waits in lv[0].B)
     bool prolong_pending = false;
+    const double* pend_beta = nullptr;  // the weights of u~ in the pending prolongation (s, or zeros after a restart)
     int border_nblk = 0;
     // F64 holds lambda M u for the current U and lam (formed by the last
     // step's prolongation); anything else that touches U, lam or F64 clears it
@@ -364,8 +365,8 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
                     // x holds u~; x_0 = P Q y' + s u~ and f = lambda M x_0 come
                     // from the pass (f into F64, which f points to), then PRE
                     if (f != c->F64) throw Error(PASM_E_DEVICE, "prolonging pre-smoothing: unexpected right-hand side");
-                    pasm::launch_march_pre_prolong(L.g, L.w0, x, c->F64, y, Lc.g, fc, c->lv[0].g, c->lv[0].B, c->s,
-                                                   c->lam, nrhs, to_steps(L.pre), c->st);
+                    pasm::launch_march_pre_prolong(L.g, L.w0, x, c->F64, y, Lc.g, fc, c->lv[0].g, c->lv[0].B,
+                                                   c->pend_beta, c->lam, nrhs, to_steps(L.pre), c->st);
                     c->prolong_pending = false;
                     prolonged = true;
                 }
@@ -999,6 +1000,7 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
         pasm::launch_dense_mv<double>(c->Qcm, N, c->lv[0].g, c->ycoef, N, false, c->lv[0].B, c->lv[0].g.plane, true,
                                       k, c->dmv, c->st);
         c->prolong_pending = true;
+        c->pend_beta = c->s;
         c->f_ready = true;
     } else {
         prolong_coefs(c, c->s);
@@ -1006,6 +1008,19 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
     // lam_prev <- lam, lam <- mu by rotating the three buffers (no copies)
     std::swap(c->lam_prev, c->lam);
     std::swap(c->lam, c->mu);
+}
+
+// Forms a prolongation left pending for the next correction step with the
+// stand-alone kernel (u = P Q y' + beta u~, f = lambda M u), for every caller
+// that reads u, f or the level buffers in between.
+void settle_prolongation(pasm_ctx* c) {
+    if (!c->prolong_pending) return;
+    c->prolong_pending = false;
+    const pasm::Level& L0 = c->lv[0];
+    pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->F64, c->k, L0.g.plane, c->sf(), c->pend_beta,
+                              c->lam, c->st);
+    std::swap(c->U, c->Y64);
+    c->f_ready = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1275,7 +1290,6 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
     if (!c || c->k == 0) return PASM_E_STATE;
     if (n < 1) return PASM_E_INVALID;
     PASM_TRY(c, {
-        c->prolong_pending = false;
         for (int i = 0; i < n; ++i) iterate_once(c, i + 1 < n);
         // the eigenvalues before and after the last step, in one synchronisation
         // (pinned host memory: both copies are asynchronous)
@@ -1316,9 +1330,18 @@ PASM_API pasm_status pasm_restart(pasm_ctx* c) {
         pasm::launch_restart_coarse(c->Qcm, N, L0.g, c->L == 1 ? c->U : L0.B, L0.g.plane, c->ycoef, k, k, 0,
                                     c->theta, 0, c->lam, c->lam_prev, c->st);
         // u_i = P q_i (weights of the old u all zero) and the first step's
-        // right-hand side theta_i M u_i in the same pass; left in flight on
-        // the context's stream (everything that reads it is ordered there)
-        prolong_coefs(c, c->zeros, c->lam, true);
+        // right-hand side theta_i M u_i: left to the next step's first
+        // marching pre-smoothing where it can form them in its pass (any
+        // other caller forms them first), else in one pass now; in flight on
+        // the context's stream either way
+        c->prolong_pending = false;
+        if (prolong_deferrable(c)) {
+            c->prolong_pending = true;
+            c->pend_beta = c->zeros;
+            c->f_ready = true;
+        } else {
+            prolong_coefs(c, c->zeros, c->lam, true);
+        }
     });
     return PASM_OK;
 }
@@ -1345,6 +1368,7 @@ PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* cc, double* lambda, double*
     const size_t N = pasm_num_dofs(c);
     if (U && ldu < N) return PASM_E_INVALID;
     PASM_TRY(c, {
+        settle_prolongation(c);
         if (lambda) std::memcpy(lambda, c->lam_h.data(), c->k * sizeof(double));
         if (U) {
             pasm::launch_pack<double>(c->gf(), c->U, c->sf(), c->stage, (long)N, c->k, c->st);
@@ -1361,6 +1385,7 @@ PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* cc, double* U_dev,
     if (!c || c->k == 0) return PASM_E_STATE;
     if (!U_dev || ldu < pasm_num_dofs(c)) return PASM_E_INVALID;
     PASM_TRY(c, {
+        settle_prolongation(c);
         pasm::launch_pack<double>(c->gf(), c->U, c->sf(), U_dev, (long)ldu, c->k, c->st);
         PASM_HIP(hipStreamSynchronize(c->st));
     });
@@ -1369,13 +1394,14 @@ PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* cc, double* U_dev,
 
 PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const double* U, size_t ldu) {
     if (!c || c->k == 0) return PASM_E_STATE;
-    if (c) c->f_ready = false;
+    c->f_ready = false;
     c->lstag.assign(c->k, 0);
     const size_t N = pasm_num_dofs(c);
     if (!lambda || !U || ldu < N) return PASM_E_INVALID;
     for (int i = 0; i < c->k; ++i)
         if (!std::isfinite(lambda[i])) return PASM_E_INVALID;
     PASM_TRY(c, {
+        c->prolong_pending = false;  // the state is replaced
         c->lam_h.assign(lambda, lambda + c->k);
         c->lam_prev_h = c->lam_h;
         PASM_HIP(hipMemcpyAsync(c->lam, lambda, c->k * sizeof(double), hipMemcpyHostToDevice, c->st));
@@ -1454,6 +1480,7 @@ PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const d
     const Grid& g = c->lv[level].g;
     if (ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
+        settle_prolongation(c);
         const bool fine = level == c->L - 1;
         double* tin = fine ? c->Y64 : c->lv[level].B;
         double* tout = fine ? c->R64 : c->lv[level].C;
@@ -1472,6 +1499,7 @@ PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t
     const Grid& g = c->gf();
     if (!f || !x || nrhs < 1 || nrhs > c->k || ncycles < 0 || ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
+        settle_prolongation(c);
         pasm::launch_unpack<double>(g, f, (long)ld, c->F64, g.plane, nrhs, c->st);
         pasm::launch_unpack<double>(g, x, (long)ld, c->R64, g.plane, nrhs, c->st);
         double* xb = c->R64;
@@ -1539,7 +1567,8 @@ PASM_API pasm_status pasm_learned_set_threshold(pasm_ctx* c, double rate) {
 
 PASM_API pasm_status pasm_learned_enable(pasm_ctx* c, int enable) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
-    if (c) c->f_ready = false;
+    PASM_TRY(c, settle_prolongation(c));
+    c->f_ready = false;
     c->learned_on = enable != 0;
     return PASM_OK;
 }
@@ -1548,7 +1577,10 @@ PASM_API pasm_status pasm_learned_train(pasm_ctx* c, int steps, double* hist) {
     if (!c || c->k == 0 || !c->learned || c->ltrain_level < 1) return PASM_E_STATE;
     if (c) c->f_ready = false;
     if (steps < 0) return PASM_E_INVALID;
-    PASM_TRY(c, learned_train(c, steps, hist));
+    PASM_TRY(c, {
+        settle_prolongation(c);
+        learned_train(c, steps, hist);
+    });
     return PASM_OK;
 }
 
@@ -1561,6 +1593,7 @@ PASM_API pasm_status pasm_learned_step(pasm_ctx* c, int level, const double* x, 
     const Grid& g = L.g;
     if (ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
+        settle_prolongation(c);
         const bool fine = level == c->L - 1;
         if (c->mixed) {
             float* xb = fine ? c->E32 : static_cast<float*>(L.X);
@@ -1600,6 +1633,7 @@ PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* c, int level, const double
     const long vol = g.interior();
     if (ld < (size_t)vol) return PASM_E_INVALID;
     PASM_TRY(c, {
+        settle_prolongation(c);
         // a trainer sized for this level and sample count (not the hot path)
         std::vector<void*> mine;
         auto alloc = [&](size_t b) {

@@ -406,6 +406,26 @@ def test_restart_matches_the_start_after_setup():
     assert np.max(np.abs(U1 - U0)) < 1e-10 * np.max(np.abs(U0))
 
 
+def test_restart_start_read_first_equals_fused_start():
+    # from 256 cells on, a restart leaves u_i = P q_i and theta_i M u_i to
+    # the next step's first marching pre-smoothing; a caller that reads u in
+    # between gets them from the stand-alone prolongation (the same
+    # arithmetic): the same iterates bit for bit either way
+    _say("restart: start read first vs formed in the first pass")
+    with P.Solver(2, 1 / 8, 1 / 256, 4, opts=_opts("cheb", 4)) as s:
+        P.pasm_restart(s.ctx)
+        lam0, U0 = s.eigenpairs()
+        assert np.all(np.isfinite(U0)) and np.max(np.abs(U0)) > 0.0
+        for _ in range(2):
+            s.iterate()
+        la, Ua = s.eigenpairs()
+        P.pasm_restart(s.ctx)
+        assert P.pasm_iterate_n(s.ctx, 2) in (True, False)
+        lb, Ub = s.eigenpairs()
+    assert np.array_equal(la, lb)
+    assert np.array_equal(Ua, Ub)
+
+
 def test_fine_equal_coarse_returns_coarse_ritz_pairs():
     _say("h = H")
     prob = O.make_problem(2, 8, 8)
