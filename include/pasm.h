@@ -147,15 +147,21 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* ctx, int* converged);
  * stream at the end (pasm_iterate synchronises after every step): for
  * callers that know how many steps they need before testing.  *converged
  * (may be NULL) reports the stop test of the last step (maximum relative
- * eigenvalue change over that step below opt.tol).  PASM_E_INVALID if
- * n < 1; PASM_E_BREAKDOWN if an eigenvalue is not finite after the last
- * step.  Allocates nothing. */
+ * eigenvalue change over that step below opt.tol).  The results equal n
+ * calls of pasm_iterate bit for bit; on 2D FP64 contexts whose finest level
+ * takes the marching smoother, a step's prolongation is formed inside the
+ * next step's first pre-smoothing pass.  PASM_E_INVALID if n < 1;
+ * PASM_E_BREAKDOWN if an eigenvalue is not finite after the last step.
+ * Allocates nothing. */
 PASM_API pasm_status pasm_iterate_n(pasm_ctx* ctx, int n, int* converged);
 
 /* Return to the start of Algorithm 2 (lambda_i = theta_i, u_i = P q_i) on
  * the device, reusing the coarse eigenpairs computed by pasm_setup.  The
  * work is enqueued on the context's stream without waiting for it (every
- * later call on the context is ordered after it). */
+ * later call on the context is ordered after it).  Where the next step's
+ * first pre-smoothing can form u_i and theta_i M u_i in its own pass (2D
+ * FP64, marching finest level), they are left to it; every other call that
+ * reads u forms them first, so callers see no difference. */
 PASM_API pasm_status pasm_restart(pasm_ctx* ctx);
 
 /* Iterate until converged or opt.max_iter iterations; *iterations (may be
