@@ -974,6 +974,15 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
     }
     for (int l = lstart; l >= 0; --l) {
         const Grid& gfl = c->lv[l + 1].g;
+        if (c->dim == 2 && l >= 2 && csrc == bsrc + (long)gfl.plane * k) {
+            // three levels down in one pass (b and c together)
+            pasm::launch_restrict_chain3(gfl, bsrc, c->lv[l].g, c->lv[l - 1].g, c->lv[l - 2].g, c->lv[l - 2].B, 2 * k,
+                                         gfl.plane, c->lv[l - 2].g.plane, c->st);
+            bsrc = c->lv[l - 2].B;
+            csrc = c->lv[l - 2].C;
+            l -= 2;
+            continue;
+        }
         if (csrc == bsrc + (long)gfl.plane * k) {  // b and c adjacent: one launch for both
             pasm::launch_restrict<double>(gfl, bsrc, c->lv[l].g, c->lv[l].B, 2 * k, gfl.plane, c->lv[l].g.plane,
                                           c->st);

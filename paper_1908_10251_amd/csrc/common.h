@@ -217,6 +217,10 @@ template <typename T>
 void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs, long sc, long sf,
                     bool add, const double* beta, hipStream_t st);
 
+// Three 2D restrictions in a row (g3 -> g2 -> g1 -> g0, FP64) in one pass:
+// equal to three launch_restrict calls; the intermediate levels are not written.
+void launch_restrict_chain3(const Grid& g3, const double* x3, const Grid& g2, const Grid& g1, const Grid& g0,
+                            double* x0, int nrhs, long s3, long s0, hipStream_t st);
 template <typename T>
 void launch_restrict(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrhs, long sf, long sc,
                      hipStream_t st);

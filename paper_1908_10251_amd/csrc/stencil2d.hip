@@ -302,7 +302,71 @@ __global__ __launch_bounds__(BX* BY) void k_restrict(Grid gf, const T* __restric
     const long id = gf.idx(2 * I, 2 * J);
     const int p = gf.pitch;
     T s = xr[id + 1] + xr[id - 1] + xr[id + p] + xr[id - p] + xr[id + p + 1] + xr[id - p - 1];
-    xc[(long)blockIdx.z * sc + gc.idx(I, J)] = xr[id] + T(0.5) * s;
+    T v;
+    if constexpr (sizeof(T) == 8)
+        v = __builtin_fma(0.5, s, xr[id]);  // as the chained restriction forms it
+    else
+        v = xr[id] + T(0.5) * s;
+    xc[(long)blockIdx.z * sc + gc.idx(I, J)] = v;
+}
+
+// Three restrictions in a row (FP64, 2D): a workgroup stages a tile of the
+// finest of the four levels in LDS, forms the two intermediate levels there
+// and writes RC_T x RC_T nodes of the coarsest.  Every node is formed as
+// k_restrict forms it (the six neighbours in the same order, one fused
+// multiply-add), nodes off a level's interior are zero, so the result equals
+// three k_restrict launches bit for bit, with one pass over the fine field.
+constexpr int RC_T = 8;
+__global__ __launch_bounds__(256) void k_restrict_chain3(Grid g3, const double* __restrict__ x3, Grid g2, Grid g1,
+                                                         Grid g0, double* __restrict__ x0, long s3, long s0) {
+    constexpr int N3 = 8 * RC_T + 7, N2 = 4 * RC_T + 3, N1 = 2 * RC_T + 1;
+    __shared__ double a3[N3][N3 + 1];
+    __shared__ double a2[N2][N2 + 1];
+    __shared__ double a1[N1][N1 + 1];
+    const int I0 = blockIdx.x * RC_T + 1, J0 = blockIdx.y * RC_T + 1;
+    // first node of each level's tile: coarse node I needs 2I - 1 .. 2I + 1
+    // one level finer, so the tiles start at 2 o - 1 of the level below
+    const int o1i = 2 * I0 - 1, o1j = 2 * J0 - 1;
+    const int o2i = 2 * o1i - 1, o2j = 2 * o1j - 1;
+    const int o3i = 2 * o2i - 1, o3j = 2 * o2j - 1;
+    const double* xr = x3 + (long)blockIdx.z * s3;
+    {
+        // every load of the thread in flight at once, then the LDS stores
+        constexpr int E = (N3 * N3 + 255) / 256;
+        double v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e, a = t % N3, b = t / N3, i = o3i + a, j = o3j + b;
+            v[e] = (t < N3 * N3 && i >= 0 && i <= g3.n && j >= 0 && j <= g3.n) ? xr[g3.idx(i, j)] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            if (t < N3 * N3) a3[t / N3][t % N3] = v[e];
+        }
+    }
+    __syncthreads();
+    // node (i, j) of the coarser level from local (2a + 1, 2b + 1) of the finer
+    auto rstr = [](const double* A, int ld, int c, int r) {
+        const double s = A[r * ld + c + 1] + A[r * ld + c - 1] + A[(r + 1) * ld + c] + A[(r - 1) * ld + c] +
+                         A[(r + 1) * ld + c + 1] + A[(r - 1) * ld + c - 1];
+        return __builtin_fma(0.5, s, A[r * ld + c]);
+    };
+    for (int t = threadIdx.x; t < N2 * N2; t += 256) {
+        const int a = t % N2, b = t / N2, i = o2i + a, j = o2j + b;
+        a2[b][a] = (i >= 1 && i <= g2.m && j >= 1 && j <= g2.m) ? rstr(&a3[0][0], N3 + 1, 2 * a + 1, 2 * b + 1) : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < N1 * N1; t += 256) {
+        const int a = t % N1, b = t / N1, i = o1i + a, j = o1j + b;
+        a1[b][a] = (i >= 1 && i <= g1.m && j >= 1 && j <= g1.m) ? rstr(&a2[0][0], N2 + 1, 2 * a + 1, 2 * b + 1) : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < RC_T * RC_T) {
+        const int a = threadIdx.x % RC_T, b = threadIdx.x / RC_T, I = I0 + a, J = J0 + b;
+        if (I <= g0.m && J <= g0.m)
+            x0[(long)blockIdx.z * s0 + g0.idx(I, J)] = rstr(&a1[0][0], N1 + 1, 2 * a + 1, 2 * b + 1);
+    }
 }
 
 // mode 0: x_f = P x_c; 1: x_f += P x_c; 2: x_f = P x_c + beta[r] x_f
@@ -898,6 +962,15 @@ void launch_restrict(const Grid& gf, const T* xf, const Grid& gc, T* xc, int nrh
     if (gf.dim == 3) return launch_restrict3<T>(gf, xf, gc, xc, nrhs, sf, sc, st);
     dim3 grid = grid_for(gc.m, gc.m, nrhs), blk(BX, BY);
     hipLaunchKernelGGL((k_restrict<T>), grid, blk, 0, st, gf, xf, gc, xc, sf, sc);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_restrict_chain3(const Grid& g3, const double* x3, const Grid& g2, const Grid& g1, const Grid& g0,
+                            double* x0, int nrhs, long s3, long s0, hipStream_t st) {
+    if (g3.dim != 2 || g2.n * 2 != g3.n || g1.n * 2 != g2.n || g0.n * 2 != g1.n)
+        throw Error(PASM_E_INVALID, "chained restriction: 2D levels of ratio 2");
+    dim3 grid((g0.m + RC_T - 1) / RC_T, (g0.m + RC_T - 1) / RC_T, nrhs);
+    hipLaunchKernelGGL(k_restrict_chain3, grid, dim3(256), 0, st, g3, x3, g2, g1, g0, x0, s3, s0);
     PASM_CHECK_LAUNCH();
 }
 
