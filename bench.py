@@ -45,8 +45,9 @@ PEAK_BF16_TFLOPS = 2500.0
 KERNEL_SOURCES = ["paper_1908_10251_amd/csrc/march2d.hip"]
 
 KERNEL_NAMES = {
-    2: "finest-level smoothing phases (k_march: pre-smoothing with fused residual restriction, from the second "
-       "step of a solve on also forming the previous step's prolongation and right-hand side; a V-cycle's "
+    2: "finest-level smoothing phases (k_march: pre-smoothing with fused residual restriction, the first one of "
+       "each step of a solve also forming the previous step's prolongation (or the restart's start) and the "
+       "right-hand side; a V-cycle's "
        "post-smoothing with fused prolongation together with the next cycle's pre-smoothing and restriction in "
        "one pass; the last post-smoothing of a step also forming the borders; k_smooth_fused where coefficients "
        "vary)",
