@@ -230,6 +230,10 @@ void record_end(pasm_ctx* c, double bytes) {
     c->ev_bytes[c->ev_used / 2] = bytes;
     c->ev_used += 2;
 }
+// Recorded launches are summed when the profile is read, or after a
+// synchronisation once this many events are held (every recorded event has
+// completed then), so that the timing reads stay off the path between steps.
+constexpr size_t kProfileBatch = 512;
 void collect_profile(pasm_ctx* c) {
     if (!c->prof) return;
     for (size_t e = 0; e < c->ev_used; e += 2) {
@@ -1277,7 +1281,7 @@ PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
         PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
         PASM_HIP(hipStreamSynchronize(c->st));
         std::copy(c->lam_pin, c->lam_pin + c->k, c->lam_h.begin());
-        collect_profile(c);
+        if (c->ev_used >= kProfileBatch) collect_profile(c);
         ++c->iters;
         double dmax = 0.0;
         bool finite = true;
@@ -1307,7 +1311,7 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
         PASM_HIP(hipStreamSynchronize(c->st));
         std::copy(c->lam_pin, c->lam_pin + c->k, c->lam_prev_h.begin());
         std::copy(c->lam_pin + c->k, c->lam_pin + 2 * c->k, c->lam_h.begin());
-        collect_profile(c);
+        if (c->ev_used >= kProfileBatch) collect_profile(c);
         c->iters += n;
         double dmax = 0.0;
         bool finite = true;
@@ -1687,6 +1691,10 @@ PASM_API pasm_status pasm_profile_read(pasm_ctx* c, int kernel, long* launches, 
                                        double* bytes_per_launch) {
     if (!c) return PASM_E_STATE;
     if (kernel != 0) return PASM_E_INVALID;
+    PASM_TRY(c, {
+        PASM_HIP(hipStreamSynchronize(c->st));
+        collect_profile(c);
+    });
     if (launches) *launches = c->prof_launches;
     if (total_ms) *total_ms = c->prof_ms;
     if (bytes_per_launch) *bytes_per_launch = c->prof_launches ? c->prof_bytes / c->prof_launches : 0.0;
