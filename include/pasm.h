@@ -169,16 +169,22 @@ PASM_API pasm_status pasm_restart(pasm_ctx* ctx);
 PASM_API pasm_status pasm_solve(pasm_ctx* ctx, int* iterations);
 
 /* Copy the current eigenvalues (k doubles) and, if U != NULL, the eigenvectors
- * (k blocks of ldu doubles, host memory) out of the context. */
-PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* ctx, double* lambda, double* U, size_t ldu);
+ * (k blocks of ldu doubles, host memory) out of the context.  With U != NULL
+ * the call may first enqueue device work that changes the context: a step
+ * of pasm_iterate_n or a pasm_restart can leave the last prolongation
+ * u = P Q y' + s u~ to the next step's first pass, and it is formed here
+ * instead.  An eigenvalue-only call (U == NULL) enqueues nothing. */
+PASM_API pasm_status pasm_eigenpairs(pasm_ctx* ctx, double* lambda, double* U, size_t ldu);
 
 /* Same, with U in device memory (written on the context's stream, which is
- * synchronised before return). */
-PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* ctx, double* U_dev, size_t ldu);
+ * synchronised before return); may form a pending prolongation first, as
+ * pasm_eigenpairs. */
+PASM_API pasm_status pasm_eigenvectors_device(pasm_ctx* ctx, double* U_dev, size_t ldu);
 
 /* Replace the current state by (lambda, U) (host memory, layout as above):
  * a warm start or checkpoint restore.  The previous-eigenvalue record used by
- * the stop test is set to lambda. */
+ * the stop test is set to lambda.  PASM_E_INVALID (state unchanged) if any
+ * lambda_i or entry of U is not finite: no kernel ever sees such input. */
 PASM_API pasm_status pasm_set_state(pasm_ctx* ctx, const double* lambda, const double* U, size_t ldu);
 
 /* Per-eigenpair report of the last iteration (host arrays of k entries, any
@@ -342,7 +348,8 @@ PASM_API pasm_status pasm_batch_solve(pasm_batch* b, int* iterations);
  * order given at set-up). */
 PASM_API pasm_status pasm_batch_eigenpairs(const pasm_batch* b, int member, double* lambda, double* U,
                                            size_t ldu);
-/* Replace member i's state (host memory, layout as above). */
+/* Replace member i's state (host memory, layout as above); non-finite
+ * values are refused (PASM_E_INVALID) as in pasm_set_state. */
 PASM_API pasm_status pasm_batch_set_state(pasm_batch* b, int member, const double* lambda, const double* U,
                                           size_t ldu);
 PASM_API size_t pasm_batch_num_dofs(const pasm_batch* b, int member);

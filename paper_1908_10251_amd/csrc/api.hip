@@ -103,7 +103,7 @@ struct pasm_ctx {
     std::vector<double> theta_h;  // the k smallest coarse Ritz values (the start), kept on the host
     double* zeros = nullptr;      // k zeros: the combination weights of a restart
     double* lam_pin = nullptr;    // pinned host copy of lambda_prev and lambda (2k)
-    std::string err;
+    mutable std::string err;  // last failure (also set by the read-only queries)
     rocblas_handle blas = nullptr;
     long iters = 0;
     // learned smoother (3D): weights [2][16][27], Adam state, operand words
@@ -560,7 +560,7 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
 
 thread_local std::string g_setup_error;
 
-void set_error(pasm_ctx* c, const std::string& m) {
+void set_error(const pasm_ctx* c, const std::string& m) {
     if (c) c->err = m;
 }
 
@@ -1375,15 +1375,15 @@ PASM_API pasm_status pasm_solve(pasm_ctx* c, int* iterations) {
     return conv ? PASM_OK : PASM_E_NOTCONV;
 }
 
-PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* cc, double* lambda, double* U, size_t ldu) {
-    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+PASM_API pasm_status pasm_eigenpairs(pasm_ctx* c, double* lambda, double* U, size_t ldu) {
     if (!c || c->k == 0) return PASM_E_STATE;
     const size_t N = pasm_num_dofs(c);
     if (U && ldu < N) return PASM_E_INVALID;
     PASM_TRY(c, {
-        settle_prolongation(c);
         if (lambda) std::memcpy(lambda, c->lam_h.data(), c->k * sizeof(double));
         if (U) {
+            // eigenvectors whose last prolongation is still pending are formed first
+            settle_prolongation(c);
             pasm::launch_pack<double>(c->gf(), c->U, c->sf(), c->stage, (long)N, c->k, c->st);
             PASM_HIP(hipMemcpy2DAsync(U, ldu * sizeof(double), c->stage, N * sizeof(double), N * sizeof(double), c->k,
                                       hipMemcpyDeviceToHost, c->st));
@@ -1393,8 +1393,7 @@ PASM_API pasm_status pasm_eigenpairs(const pasm_ctx* cc, double* lambda, double*
     return PASM_OK;
 }
 
-PASM_API pasm_status pasm_eigenvectors_device(const pasm_ctx* cc, double* U_dev, size_t ldu) {
-    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+PASM_API pasm_status pasm_eigenvectors_device(pasm_ctx* c, double* U_dev, size_t ldu) {
     if (!c || c->k == 0) return PASM_E_STATE;
     if (!U_dev || ldu < pasm_num_dofs(c)) return PASM_E_INVALID;
     PASM_TRY(c, {
@@ -1413,6 +1412,13 @@ PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const dou
     if (!lambda || !U || ldu < N) return PASM_E_INVALID;
     for (int i = 0; i < c->k; ++i)
         if (!std::isfinite(lambda[i])) return PASM_E_INVALID;
+    // non-finite vector entries are refused here, before any kernel sees them
+    for (int i = 0; i < c->k; ++i)
+        for (size_t j = 0; j < N; ++j)
+            if (!std::isfinite(U[(size_t)i * ldu + j])) {
+                set_error(c, "pasm_set_state: U holds a non-finite value");
+                return PASM_E_INVALID;
+            }
     PASM_TRY(c, {
         c->prolong_pending = false;  // the state is replaced
         c->lam_h.assign(lambda, lambda + c->k);
@@ -1428,7 +1434,7 @@ PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const dou
 }
 
 PASM_API pasm_status pasm_last_selection(const pasm_ctx* cc, int* rank, double* score, int* flags) {
-    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    const pasm_ctx* c = cc;
     if (!c || c->k == 0) return PASM_E_STATE;
     PASM_TRY(c, {
         if (rank) PASM_HIP(hipMemcpyAsync(rank, c->rank, c->k * sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -1440,7 +1446,7 @@ PASM_API pasm_status pasm_last_selection(const pasm_ctx* cc, int* rank, double* 
 }
 
 PASM_API pasm_status pasm_coarse_eigenpairs(const pasm_ctx* cc, double* theta, double* Q) {
-    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    const pasm_ctx* c = cc;
     if (!c || c->k == 0) return PASM_E_STATE;
     const size_t N = c->NH;
     PASM_TRY(c, {
@@ -1452,7 +1458,7 @@ PASM_API pasm_status pasm_coarse_eigenpairs(const pasm_ctx* cc, double* theta, d
 }
 
 PASM_API pasm_status pasm_last_borders(const pasm_ctx* cc, double* beta_zeta, double* p, double* q) {
-    pasm_ctx* c = const_cast<pasm_ctx*>(cc);
+    const pasm_ctx* c = cc;
     if (!c || c->k == 0) return PASM_E_STATE;
     const size_t N = c->NH, k = c->k;
     PASM_TRY(c, {
@@ -1486,7 +1492,6 @@ PASM_API const char* pasm_last_error(const pasm_ctx* c) { return c ? c->err.c_st
 PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const double* x, double* y, size_t ld,
                                          int nrhs) {
     if (!c || c->k == 0) return PASM_E_STATE;
-    if (c) c->f_ready = false;
     if (level < 0 || level >= c->L || nrhs < 1 || nrhs > c->k || !x || !y) return PASM_E_INVALID;
     if (op != PASM_OP_STIFFNESS && op != PASM_OP_MASS) return PASM_E_INVALID;
     if (op == PASM_OP_MASS && level != c->L - 1) return PASM_E_INVALID;
@@ -1494,6 +1499,8 @@ PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const d
     if (ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
         settle_prolongation(c);
+        // F64 may be overwritten below: the next step forms lambda M u again
+        c->f_ready = false;
         const bool fine = level == c->L - 1;
         double* tin = fine ? c->Y64 : c->lv[level].B;
         double* tout = fine ? c->R64 : c->lv[level].C;
@@ -1508,11 +1515,12 @@ PASM_API pasm_status pasm_apply_operator(pasm_ctx* c, int level, int op, const d
 
 PASM_API pasm_status pasm_vcycle(pasm_ctx* c, const double* f, double* x, size_t ld, int nrhs, int ncycles) {
     if (!c || c->k == 0) return PASM_E_STATE;
-    if (c) c->f_ready = false;
     const Grid& g = c->gf();
     if (!f || !x || nrhs < 1 || nrhs > c->k || ncycles < 0 || ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
         settle_prolongation(c);
+        // F64 may be overwritten below: the next step forms lambda M u again
+        c->f_ready = false;
         pasm::launch_unpack<double>(g, f, (long)ld, c->F64, g.plane, nrhs, c->st);
         pasm::launch_unpack<double>(g, x, (long)ld, c->R64, g.plane, nrhs, c->st);
         double* xb = c->R64;
@@ -1588,10 +1596,11 @@ PASM_API pasm_status pasm_learned_enable(pasm_ctx* c, int enable) {
 
 PASM_API pasm_status pasm_learned_train(pasm_ctx* c, int steps, double* hist) {
     if (!c || c->k == 0 || !c->learned || c->ltrain_level < 1) return PASM_E_STATE;
-    if (c) c->f_ready = false;
     if (steps < 0) return PASM_E_INVALID;
     PASM_TRY(c, {
         settle_prolongation(c);
+        // F64 may be overwritten below: the next step forms lambda M u again
+        c->f_ready = false;
         learned_train(c, steps, hist);
     });
     return PASM_OK;
@@ -1600,13 +1609,14 @@ PASM_API pasm_status pasm_learned_train(pasm_ctx* c, int steps, double* hist) {
 PASM_API pasm_status pasm_learned_step(pasm_ctx* c, int level, const double* x, const double* f, double* out,
                                        size_t ld, int nrhs) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
-    if (c) c->f_ready = false;
     if (level < 1 || level >= c->L || nrhs < 1 || nrhs > c->k || !x || !f || !out) return PASM_E_INVALID;
     const pasm::Level& L = c->lv[level];
     const Grid& g = L.g;
     if (ld < (size_t)g.interior()) return PASM_E_INVALID;
     PASM_TRY(c, {
         settle_prolongation(c);
+        // F64 may be overwritten below: the next step forms lambda M u again
+        c->f_ready = false;
         const bool fine = level == c->L - 1;
         if (c->mixed) {
             float* xb = fine ? c->E32 : static_cast<float*>(L.X);
@@ -1640,13 +1650,14 @@ __global__ void k_compact_d2f(const double* __restrict__ a, long lda, float* __r
 PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* c, int level, const double* r, size_t ld, int ns,
                                             double* loss, double* grad) {
     if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
-    if (c) c->f_ready = false;
     if (level < 1 || level >= c->L || ns < 1 || ns > 64 || !r || !grad) return PASM_E_INVALID;
     const Grid& g = c->lv[level].g;
     const long vol = g.interior();
     if (ld < (size_t)vol) return PASM_E_INVALID;
     PASM_TRY(c, {
         settle_prolongation(c);
+        // F64 may be overwritten below: the next step forms lambda M u again
+        c->f_ready = false;
         // a trainer sized for this level and sample count (not the hot path)
         std::vector<void*> mine;
         auto alloc = [&](size_t b) {

@@ -94,7 +94,7 @@ struct pasm_batch {
     std::vector<double> lam_h, lam_prev_h;
     std::vector<void*> allocs;
     rocblas_handle blas = nullptr;
-    std::string err;
+    mutable std::string err;  // last failure (also set by read-only queries)
     // graph of one iteration's device work
     bool use_graph = true;
     hipGraph_t graph = nullptr;
@@ -684,7 +684,7 @@ void brestart(pasm_batch* b) {
     b->lam_prev_h = b->lam_h;
 }
 
-void bset_error(pasm_batch* b, const std::string& m) {
+void bset_error(const pasm_batch* b, const std::string& m) {
     if (b) b->err = m;
 }
 
@@ -822,8 +822,7 @@ PASM_API size_t pasm_batch_num_dofs(const pasm_batch* b, int member) {
 
 PASM_API int pasm_batch_num_levels(const pasm_batch* b) { return b ? b->Lmax : 0; }
 
-PASM_API pasm_status pasm_batch_eigenpairs(const pasm_batch* cb, int member, double* lambda, double* U, size_t ldu) {
-    pasm_batch* b = const_cast<pasm_batch*>(cb);
+PASM_API pasm_status pasm_batch_eigenpairs(const pasm_batch* b, int member, double* lambda, double* U, size_t ldu) {
     if (!b || b->n == 0) return PASM_E_STATE;
     if (member < 0 || member >= b->n) return PASM_E_INVALID;
     const int s = b->slot_of[member];
@@ -855,6 +854,13 @@ PASM_API pasm_status pasm_batch_set_state(pasm_batch* b, int member, const doubl
     if (ldu < N) return PASM_E_INVALID;
     for (int i = 0; i < b->k; ++i)
         if (!std::isfinite(lambda[i])) return PASM_E_INVALID;
+    // non-finite vector entries are refused here, before any kernel sees them
+    for (int i = 0; i < b->k; ++i)
+        for (size_t j = 0; j < N; ++j)
+            if (!std::isfinite(U[(size_t)i * ldu + j])) {
+                bset_error(b, "pasm_batch_set_state: U holds a non-finite value");
+                return PASM_E_INVALID;
+            }
     PASM_BTRY(b, {
         const size_t o = (size_t)s * b->k;
         std::copy(lambda, lambda + b->k, b->lam_h.begin() + o);
