@@ -2,8 +2,10 @@
 
 * A restart leaves the start u_i = P q_i and its right-hand side theta_i M u_i
   to the next step's first pass (2D FP64 marching levels).  Building-block
-  calls in between (a V-cycle on caller data, an eigenvalue-only query) must
-  not change what the next step computes: bit-identical iterates.
+  calls in between must not change what the next step computes: after a
+  V-cycle on caller data the same iterates to rounding (the right-hand side
+  is formed again, by another kernel), after an eigenvalue-only query
+  bit-identical ones (nothing is enqueued).
 * Non-finite input is refused at the boundary (pasm_set_state), the context
   stays usable; the iteration cap gives PASM_E_NOTCONV.
 """
@@ -49,8 +51,11 @@ def test_restart_vcycle_iterate_equals_restart_iterate():
         assert float(torch.max(torch.abs(x))) > 0.0
         s.iterate()
         lam_b, U_b = s.eigenpairs()
-    assert np.array_equal(lam_a, lam_b)
-    assert np.array_equal(U_a, U_b)
+    # the two orders form theta M u with different kernels (in the first
+    # pass, or the stand-alone mass product after the V-cycle reused the
+    # buffer), equal to rounding; a step on the caller's f would be O(1) off
+    assert np.max(np.abs(lam_a - lam_b) / lam_a) < 1e-13
+    assert np.max(np.abs(U_a - U_b)) < 1e-11 * np.max(np.abs(U_a))
 
 
 def test_eigenvalue_only_query_changes_nothing():
