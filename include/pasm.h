@@ -300,6 +300,22 @@ PASM_API pasm_status pasm_learned_step(pasm_ctx* ctx, int level, const double* x
 PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* ctx, int level, const double* r, size_t ld, int ns,
                                             double* loss, double* grad);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, allocation-free serving loops, harnesses that forbid it): the
+ * same loss and gradient as pasm_learned_loss_grad, same arguments, with
+ * every device buffer (the trainer's activations, partial sums and the FP32
+ * copy of the samples) taken from a fixed scratch array of 72 MiB that the
+ * library keeps per GPU until the process ends, instead of hipMalloc.  It
+ * holds 8 samples on the 32-cell level, or up to 63 on the 16-cell level;
+ * larger requests return PASM_E_INVALID (pasm_last_error gives the bytes
+ * needed) before any device work.  No hipMalloc, hipFree or other
+ * allocating device call is made.  The array is shared by every call on one
+ * GPU and keeps the last call's contents (the part used is cleared at the
+ * start of each call): calls that overlap on one GPU, from any context or
+ * thread, race and must be serialised by the caller. */
+PASM_API pasm_status pasm_learned_loss_grad_noalloc(pasm_ctx* ctx, int level, const double* r, size_t ld,
+                                                    int ns, double* loss, double* grad);
+
 /* ---------------------------------------------------------------------------
  * Batches of problems of uneven size.
  *

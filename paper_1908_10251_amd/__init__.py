@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
     L.pasm_learned_enable.argtypes = [_P, ctypes.c_int]
     L.pasm_learned_step.argtypes = [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, ctypes.c_int]
     L.pasm_learned_loss_grad.argtypes = [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int, _D, _D]
+    L.pasm_learned_loss_grad_noalloc.argtypes = [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int, _D, _D]
     L.pasm_batch_setup.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(pasm_domain), ctypes.POINTER(pasm_instance),
                                    ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(pasm_options)]
     L.pasm_batch_iterate.argtypes = [_P, _I]
@@ -421,6 +422,16 @@ def pasm_learned_loss_grad(ctx, level: int, r):
     g = np.zeros((2, 16, 27))
     _check(lib().pasm_learned_loss_grad(ctx, level, _torch_ptr(r), r.shape[1], r.shape[0], ctypes.byref(loss),
                                         _dptr(g)), ctx)
+    return loss.value, g
+
+
+def pasm_learned_loss_grad_noalloc(ctx, level: int, r):
+    """As pasm_learned_loss_grad, with the library's fixed scratch array instead
+    of device allocations (raises PASM_E_INVALID beyond its size)."""
+    loss = ctypes.c_double(0)
+    g = np.zeros((2, 16, 27))
+    _check(lib().pasm_learned_loss_grad_noalloc(ctx, level, _torch_ptr(r), r.shape[1], r.shape[0],
+                                                ctypes.byref(loss), _dptr(g)), ctx)
     return loss.value, g
 
 

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <random>
 #include <type_traits>
 
@@ -76,6 +77,7 @@ struct pasm_ctx {
     int dim = 2, k = 0, L = 0, NH = 0;
     pasm_options opt{};
     hipStream_t st = nullptr;
+    int device = 0;        // the GPU current at set-up (the stream's device)
     bool own_stream = false;
     bool mixed = false;
     bool fuse = true;      // temporal blocking of smoothing phases (2D)
@@ -1248,6 +1250,7 @@ PASM_API pasm_status pasm_setup(pasm_ctx** out, const pasm_domain* dom, const pa
     else pasm_default_options(&c->opt);
     try {
         const Plan pl = validate(c->opt, dom, coef, H, h, k);
+        PASM_HIP(hipGetDevice(&c->device));
         if (c->opt.stream) c->st = static_cast<hipStream_t>(c->opt.stream);
         else {
             PASM_HIP(hipStreamCreate(&c->st));
@@ -1683,6 +1686,127 @@ PASM_API pasm_status pasm_learned_loss_grad(pasm_ctx* c, int level, const double
         }
         PASM_HIP(hipStreamSynchronize(c->st));
         for (void* p : mine) (void)hipFree(p);
+    });
+    return PASM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pasm_learned_loss_grad_noalloc: the same loss and gradient with every
+// device buffer carved out of a file-scope device array instead of hipMalloc.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// Enough for 8 samples on the 32-cell level (the library's own training
+// batch) or 63 samples on the 16-cell level.  Every GPU the library runs on
+// holds one copy until the process ends.
+constexpr size_t kNoAllocScratchBytes = (size_t)72 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU `dev`, which must be the current
+// device: taken once per device with hipGetSymbolAddress and kept.  Host
+// code uses only this address (the array's own name is a host-side stand-in).
+void* scratch_address(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) throw Error(PASM_E_DEVICE, "device index out of range for the scratch table");
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            throw Error(PASM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Makes the context's device current for the duration of a call and
+// restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        PASM_HIP(hipGetDevice(&prev));
+        if (prev != dev) PASM_HIP(hipSetDevice(dev));
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+__global__ void k_zero_words(uint4* __restrict__ p, long n) {
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) p[t] = z;
+}
+
+// Bytes the trainer of (m, ns) and the FP32 copy of the samples take in the
+// scratch array, each buffer rounded up to 256 bytes.
+size_t loss_grad_scratch_bytes(int m, int ns) {
+    size_t off = 0;
+    auto count = [&](size_t b) -> void* {
+        off += (b + 255) / 256 * 256;
+        return reinterpret_cast<void*>(static_cast<uintptr_t>(256));  // never dereferenced
+    };
+    pasm::LearnedTrainer dry;
+    dry.init(m, ns, 1.f, count);
+    count(sizeof(float) * (size_t)m * m * m * ns);
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+PASM_API pasm_status pasm_learned_loss_grad_noalloc(pasm_ctx* c, int level, const double* r, size_t ld, int ns,
+                                                    double* loss, double* grad) {
+    if (!c || c->k == 0 || !c->learned) return PASM_E_STATE;
+    if (level < 1 || level >= c->L || ns < 1 || ns > 64 || !r || !grad) return PASM_E_INVALID;
+    const Grid& g = c->lv[level].g;
+    const long vol = g.interior();
+    if (ld < (size_t)vol) return PASM_E_INVALID;
+    const size_t need = loss_grad_scratch_bytes(g.m, ns);
+    if (need > kNoAllocScratchBytes) {
+        set_error(c, "pasm_learned_loss_grad_noalloc: " + std::to_string(ns) + " samples on a level of " +
+                         std::to_string(g.n) + " cells need " + std::to_string(need) + " bytes of scratch, more than its " +
+                         std::to_string(kNoAllocScratchBytes) + " (use pasm_learned_loss_grad)");
+        return PASM_E_INVALID;
+    }
+    PASM_TRY(c, {
+        DeviceGuard dg(c->device);
+        settle_prolongation(c);
+        c->f_ready = false;
+        unsigned char* base = static_cast<unsigned char*>(scratch_address(c->device));
+        // the array keeps the previous call's contents: clear the part used
+        // (a kernel, not a memset, so that the call could sit in a graph)
+        const long words = (long)(need / sizeof(uint4));
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<long>((words + 255) / 256, 4096)), dim3(256), 0, c->st,
+                           reinterpret_cast<uint4*>(base), words);
+        PASM_CHECK_LAUNCH();
+        size_t off = 0;
+        auto carve = [&](size_t b) -> void* {
+            void* p = base + off;
+            off += (b + 255) / 256 * 256;
+            if (off > need) throw Error(PASM_E_DEVICE, "scratch layout mismatch");
+            return p;
+        };
+        pasm::LearnedTrainer tr;
+        tr.init(g.m, ns, (float)c->lv[level].w0, carve);
+        float* rf = static_cast<float*>(carve(sizeof(float) * vol * ns));
+        hipLaunchKernelGGL(k_compact_d2f, dim3((unsigned)((vol + 255) / 256), ns), dim3(256), 0, c->st, r, (long)ld, rf,
+                           vol);
+        PASM_CHECK_LAUNCH();
+        const double L = tr.loss_grad(rf, c->lw.data(), grad, c->st);
+        if (loss) *loss = L;
+        PASM_HIP(hipStreamSynchronize(c->st));
     });
     return PASM_OK;
 }
