@@ -204,6 +204,15 @@ def coarse_start(prob: Problem, k: int):
 _WORKER = {}
 
 
+def _worker_init():
+    # one BLAS thread per worker process: the workers already fill the cores
+    try:
+        from threadpoolctl import threadpool_limits
+        _WORKER["limits"] = threadpool_limits(limits=1)
+    except ImportError:  # pragma: no cover
+        pass
+
+
 def _worker_run(i):
     prob, bvp, lam0, u0, tol, max_iter = (_WORKER[k] for k in
                                           ("prob", "bvp", "lam0", "u0", "tol", "max_iter"))
@@ -238,8 +247,8 @@ def solve(prob: Problem, k: int, bvp, tol: float = 1e-13, max_iter: int = 60,
     else:
         import multiprocessing as mp
         _WORKER.update(prob=prob, bvp=bvp, lam0=lam0, u0=U0, tol=tol, max_iter=max_iter)
-        with mp.get_context("fork").Pool(workers) as pool:
-            res = pool.map(_worker_run, idx)
+        with mp.get_context("fork").Pool(workers, initializer=_worker_init) as pool:
+            res = pool.map(_worker_run, idx, chunksize=1)
         _WORKER.clear()
     lam = np.array([r[0] for r in res])
     U = np.stack([r[1] for r in res])
