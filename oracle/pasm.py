@@ -256,6 +256,104 @@ def solve(prob: Problem, k: int, bvp, tol: float = 1e-13, max_iter: int = 60,
                 picks=[r[4] for r in res], lam0=lam0[idx], index=idx)
 
 
+def _record_one(prob, bvp, lam, u, steps, sample):
+    rec = []
+    for _ in range(steps):
+        out = correction_step(prob, lam, u, bvp)
+        lam, u = out["lam"], out["u"]
+        rec.append((lam, out["index"], out["score"], out["beta"], out["zeta"], u[sample].copy(),
+                    float(np.max(np.abs(u)))))
+    return rec
+
+
+def _worker_record(i):
+    prob, bvp, lam0, u0, steps, sample = (_WORKER[k] for k in
+                                          ("prob", "bvp", "lam0", "u0", "steps", "sample"))
+    return _record_one(prob, bvp, float(lam0[i]), u0[i].copy(), steps, sample)
+
+
+def record_steps(prob: Problem, k: int, bvp, steps: int, sample: np.ndarray, workers: int = 1):
+    """The first `steps` correction steps (Algorithm 1) of each of the k
+    processes of Algorithm 2 (h_1 = H) from the coarse start.  Returns the
+    start (theta_i, and the coarse vectors q_i as columns) and, per step and
+    process: lambda, the selected augmented index, its score, beta = a(u~, u~),
+    zeta = b(u~, u~), the new u at the `sample` node indices and max |u|."""
+    lam0, U0, theta, Q = coarse_start(prob, k)
+    if workers <= 1:
+        res = [_record_one(prob, bvp, float(lam0[i]), U0[i].copy(), steps, sample) for i in range(k)]
+    else:
+        import multiprocessing as mp
+        _WORKER.update(prob=prob, bvp=bvp, lam0=lam0, u0=U0, steps=steps, sample=sample)
+        with mp.get_context("fork").Pool(workers, initializer=_worker_init) as pool:
+            res = pool.map(_worker_record, range(k), chunksize=1)
+        _WORKER.clear()
+    field = lambda f: np.array([[res[i][t][f] for i in range(k)] for t in range(steps)])  # noqa: E731
+    return dict(theta=lam0, Q=Q[:, :k].copy(), lam=field(0), index=field(1), score=field(2), beta=field(3),
+                zeta=field(4), u_sample=field(5), u_max=field(6))
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 with the nested levels of step 2(A)
+# ---------------------------------------------------------------------------
+def level_problem(prob: Problem, n_level: int) -> Problem:
+    """The problem on the intermediate space V_{h_k} (h_k = 1/n_level) of the
+    hierarchy between V_H and V_h.  V_{h_k} is a subspace of V_h, so the
+    forms a(.,.) and b(.,.) restricted to it are the Galerkin products
+    P^T A_h P and P^T M_h P with P the prolongation V_{h_k} -> V_h."""
+    if n_level == prob.n_fine:
+        return prob
+    Pk = prolongation(prob.dim, n_level, prob.n_fine)
+    A = galerkin(Pk, prob.A)
+    M = galerkin(Pk, prob.M)
+    PH = prolongation(prob.dim, prob.n_coarse, n_level)
+    return Problem(prob.dim, prob.n_coarse, n_level, A, M, PH, prob.AH, prob.MH)
+
+
+def solve_nested(prob: Problem, k: int, make_bvp, varpi: int = 1, varpi_n: int = 0,
+                 which: Optional[List[int]] = None):
+    """Algorithm 2 with h_1 = H and its nested step 2(A):
+      1. the coarse eigenpairs (theta_i, q_i) on V_H = V_{h_1};
+      2(A). for every intermediate level h_2, ..., h_{n-1} (ratio 2): start
+         from the previous level's result (a function of the coarser space is
+         also one of the finer space: its nodal values are the prolongation),
+         then `varpi` correction steps (Algorithm 1 with the coarse space V_H,
+         on that level);
+      2(B). `varpi_n` correction steps on the finest level.
+    make_bvp(level_problem) gives the boundary value solver of a level.
+    Returns the finest-level start (after 2(A)) and the final eigenpairs,
+    with per-process eigenvalue histories over the whole schedule."""
+    sizes = level_sizes(prob.n_coarse, prob.n_fine)
+    theta, Q = sla.eigh(prob.AH, prob.MH)
+    idx = list(range(k)) if which is None else list(which)
+    lam = theta[idx].copy()
+    coarse = Q[:, idx].T.copy()              # u_i as functions of V_H (coarse nodal values)
+    hist = [[float(l)] for l in lam]
+    cur_n = prob.n_coarse
+    U = coarse
+    for n_l in sizes[1:-1]:
+        lp = level_problem(prob, n_l)
+        Pstep = prolongation(prob.dim, cur_n, n_l)
+        U = (Pstep @ U.T).T.copy()
+        bvp = make_bvp(lp)
+        for i in range(len(idx)):
+            for _ in range(varpi):
+                out = correction_step(lp, float(lam[i]), U[i], bvp)
+                lam[i], U[i] = out["lam"], out["u"]
+                hist[i].append(float(lam[i]))
+        cur_n = n_l
+    Pstep = prolongation(prob.dim, cur_n, prob.n_fine)
+    U = (Pstep @ U.T).T.copy()
+    lam_start, U_start = lam.copy(), U.copy()
+    if varpi_n > 0:
+        bvp = make_bvp(prob)
+        for i in range(len(idx)):
+            for _ in range(varpi_n):
+                out = correction_step(prob, float(lam[i]), U[i], bvp)
+                lam[i], U[i] = out["lam"], out["u"]
+                hist[i].append(float(lam[i]))
+    return dict(lam_start=lam_start, U_start=U_start, lam=lam, U=U, hist=hist, index=idx)
+
+
 def mg_options_for(workload) -> MGOptions:
     return default_options(workload.dim, workload.smoother, workload.nu_pre,
                            workload.nu_post, workload.vcycles)

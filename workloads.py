@@ -156,3 +156,20 @@ def quadratic_potential_elements(n: int, centre, scale: float = 1.0) -> np.ndarr
 def random_vectors(shape, seed: int = 0, dtype=np.float64) -> np.ndarray:
     """Seeded standard-normal test vectors."""
     return np.random.default_rng(seed).standard_normal(shape).astype(dtype)
+
+
+def sample_nodes(n_dofs: int, count: int = 256, seed: int = 0) -> np.ndarray:
+    """Sorted distinct interior-node indices drawn uniformly (seeded): the
+    entries at which full-size reference vectors are stored and compared."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_dofs, size=min(count, n_dofs), replace=False)).astype(np.int64)
+
+
+def batch_member_at(n_fine: int, count: int = 16, seed: int = 0):
+    """(position, Instance) of the first member of the uneven batch whose fine
+    mesh has n_fine cells per side."""
+    for pos, inst in enumerate(uneven_batch(count, seed=seed)):
+        if inst.n_fine == n_fine:
+            return pos, inst
+    raise ValueError(f"no member with {n_fine} cells")
+
