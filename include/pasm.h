@@ -164,6 +164,24 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* ctx, int n, int* converged);
  * reads u forms them first, so callers see no difference. */
 PASM_API pasm_status pasm_restart(pasm_ctx* ctx);
 
+/* Algorithm 2 with its nested step 2(A): return to the coarse start
+ * (lambda_i = theta_i, u_i = q_i on V_H = V_{h_1}), then for every
+ * intermediate mesh h_2 = H/2, ..., h_{n-1} = 2h in turn take the previous
+ * mesh's result as the start (a coarser P1 function is also a finer one:
+ * its nodal values are prolongated) and run varpi >= 1 correction steps
+ * (Algorithm 1 with the same coarse space V_H, on that mesh; varpi = 1 as in
+ * Remark 3.2).  The context is left on the finest mesh at the start of step
+ * 2(B): the following pasm_iterate / pasm_solve calls are the finest-level
+ * corrections, and the stop test of the first one compares with the last
+ * intermediate eigenvalues.  The operators of an intermediate mesh are the
+ * Galerkin restrictions of the finest ones (for constant coefficients and
+ * per-element kappa: the rediscretisation with kappa averaged over the
+ * children); a context with a potential term returns PASM_E_INVALID.  The
+ * first call allocates the intermediate meshes' vectors (they share the
+ * coarse space and stream); later calls allocate nothing.  Synchronises the
+ * stream once.  With fewer than three meshes it is pasm_restart. */
+PASM_API pasm_status pasm_restart_nested(pasm_ctx* ctx, int varpi);
+
 /* Iterate until converged or opt.max_iter iterations; *iterations (may be
  * NULL) receives the count.  PASM_E_NOTCONV if the cap was reached. */
 PASM_API pasm_status pasm_solve(pasm_ctx* ctx, int* iterations);

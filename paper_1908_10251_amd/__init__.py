@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
     L.pasm_iterate_n.argtypes = [_P, ctypes.c_int, _I]
     L.pasm_solve.argtypes = [_P, _I]
     L.pasm_restart.argtypes = [_P]
+    L.pasm_restart_nested.argtypes = [_P, ctypes.c_int]
     L.pasm_eigenpairs.argtypes = [_P, _D, _D, ctypes.c_size_t]
     L.pasm_eigenvectors_device.argtypes = [_P, _P, ctypes.c_size_t]
     L.pasm_set_state.argtypes = [_P, _D, _D, ctypes.c_size_t]
@@ -219,6 +220,10 @@ def pasm_iterate_n(ctx, n: int) -> bool:
 
 def pasm_restart(ctx) -> None:
     _check(lib().pasm_restart(ctx), ctx)
+
+
+def pasm_restart_nested(ctx, varpi: int = 1) -> None:
+    _check(lib().pasm_restart_nested(ctx, int(varpi)), ctx)
 
 
 def pasm_solve(ctx, allow_notconv: bool = False) -> int:

@@ -103,6 +103,13 @@ struct pasm_ctx {
     std::vector<void*> allocs;
     std::vector<double> lam_h, lam_prev_h;
     std::vector<double> theta_h;  // the k smallest coarse Ritz values (the start), kept on the host
+    // Algorithm 2, step 2(A): contexts of the intermediate levels h_2 .. h_{n-1}
+    // (built on first use; they share this context's coarse space and stream),
+    // and the per-element kappa of those levels (host, when kappa is given)
+    std::vector<pasm_ctx*> nested;
+    std::vector<std::vector<double>> level_kappa;
+    bool general_coef = false;    // a potential term: the nested levels are not rediscretisations
+    bool coarse_shared = false;   // theta, Q, A_H^{-1}, groups belong to another context
     double* zeros = nullptr;      // k zeros: the combination weights of a restart
     double* lam_pin = nullptr;    // pinned host copy of lambda_prev and lambda (2k)
     mutable std::string err;  // last failure (also set by the read-only queries)
@@ -634,7 +641,9 @@ Plan validate(const pasm_options& opt, const pasm_domain* dom, const pasm_coeffi
     return p;
 }
 
-void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
+// share: another context of the same problem whose coarse space (theta, Q,
+// A_H^{-1}, groups, start values) is reused instead of factorising again.
+void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, const pasm_ctx* share = nullptr) {
     const int dim = pl.dim, nH = pl.nH, L = pl.L;
     const bool have_kappa = pl.have_kappa;
     const size_t nel = pl.nel;
@@ -687,6 +696,10 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
             Lv.rho = 2.0;
             upload(Lv, 0, wx);
             upload(Lv, 1, wy);
+            if (!share && l > 0 && l < L - 1) {
+                if (c->level_kappa.size() < (size_t)L) c->level_kappa.resize(L);
+                c->level_kappa[l] = kap;
+            }
             if (l > 0) kap = pasm::coarsen_kappa_2d(kap, n);
         } else {
             Lv.rho = 2.0;  // constant coefficients: zero row sums, D^{-1}A Gershgorin bound 2
@@ -731,12 +744,25 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
         c->Y32 = c->alloc<float>(nf);
     }
     const int N = c->NH;
-    c->theta = c->alloc<double>(N);
-    c->Qcm = c->alloc<double>((size_t)N * N);
-    c->Qrm = c->alloc<double>((size_t)N * N);
-    c->Ainv64 = c->alloc<double>((size_t)N * N);
-    if (c->mixed) c->Ainv32 = c->alloc<float>((size_t)N * N);
-    c->group = c->alloc<int>(N);
+    c->general_coef = general;
+    if (share) {
+        c->coarse_shared = true;
+        c->theta = share->theta;
+        c->Qcm = share->Qcm;
+        c->Qrm = share->Qrm;
+        c->Ainv64 = share->Ainv64;
+        c->Ainv32 = share->Ainv32;
+        c->dstS = share->dstS;
+        c->dstInv = share->dstInv;
+        c->group = share->group;
+    } else {
+        c->theta = c->alloc<double>(N);
+        c->Qcm = c->alloc<double>((size_t)N * N);
+        c->Qrm = c->alloc<double>((size_t)N * N);
+        c->Ainv64 = c->alloc<double>((size_t)N * N);
+        if (c->mixed) c->Ainv32 = c->alloc<float>((size_t)N * N);
+        c->group = c->alloc<int>(N);
+    }
     c->bz = c->alloc<double>(2 * (size_t)k);
     const Grid& gfine = c->gf();
     const long nblk = (dim == 2) ? (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4)
@@ -755,6 +781,10 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     c->awork = c->alloc<char>(pasm::arrow_workspace_bytes(N, k));
     c->dmv = c->alloc<char>(pasm::dense_mv_workspace_bytes(N, 2 * k));
 
+    std::vector<double> th;
+    if (share) {
+        th = share->theta_h;  // the k smallest coarse Ritz values: all the start needs
+    } else {
     // dense coarse pencil from the level-0 operators (Galerkin: rediscretised
     // with the coarsened coefficient, or the Galerkin general stencil)
     const pasm::Level& L0 = c->lv[0];
@@ -839,7 +869,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
         throw Error(PASM_E_DEVICE, "rocsolver_dsygvd failed");
     int info = 0;
     PASM_HIP(hipMemcpyAsync(&info, dInfo, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    std::vector<double> th(N);
+    th.resize(N);
     PASM_HIP(hipMemcpyAsync(th.data(), c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->st));
     PASM_HIP(hipStreamSynchronize(c->st));
     if (info != 0) throw Error(PASM_E_DEVICE, "coarse generalized eigensolve did not converge");
@@ -869,6 +899,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k) {
     const double gtol = 16.0 * DBL_EPSILON * std::fabs(th[N - 1]);
     for (int j = 0; j < N; ++j) grp[j] = (j > 0 && th[j] - th[j - 1] <= gtol) ? grp[j - 1] : j;
     PASM_HIP(hipMemcpyAsync(c->group, grp.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
+    }  // own coarse space
 
     // start: lambda_i = theta_i, u_i = P q_i
     c->lam_h.assign(th.begin(), th.begin() + k);
@@ -1210,6 +1241,11 @@ void learned_setup(pasm_ctx* c) {
         return PASM_E_DEVICE;                                      \
     }
 
+namespace {
+void restart_ctx(pasm_ctx* c);
+void restart_nested(pasm_ctx* c, int varpi);
+}  // namespace
+
 extern "C" {
 
 PASM_API void pasm_default_options(pasm_options* o) {
@@ -1231,6 +1267,8 @@ PASM_API void pasm_default_options(pasm_options* o) {
 PASM_API pasm_status pasm_destroy(pasm_ctx* c) {
     if (!c) return PASM_OK;
     if (c->st) (void)hipStreamSynchronize(c->st);
+    for (pasm_ctx* ch : c->nested) pasm_destroy(ch);  // they use c's stream and coarse space
+    c->nested.clear();
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->lam_pin) (void)hipHostFree(c->lam_pin);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1334,9 +1372,29 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
 
 PASM_API pasm_status pasm_restart(pasm_ctx* c) {
     if (!c || c->k == 0) return PASM_E_STATE;
-    if (c) c->f_ready = false;
+    PASM_TRY(c, restart_ctx(c));
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_restart_nested(pasm_ctx* c, int varpi) {
+    if (!c || c->k == 0) return PASM_E_STATE;
+    if (varpi < 1) return PASM_E_INVALID;
+    if (c->general_coef) {
+        set_error(c, "the nested schedule needs the intermediate levels as rediscretisations (no potential term)");
+        return PASM_E_INVALID;
+    }
+    PASM_TRY(c, restart_nested(c, varpi));
+    return PASM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Return to the start of Algorithm 2 (lambda_i = theta_i, u_i = P q_i).
+void restart_ctx(pasm_ctx* c) {
+    c->f_ready = false;
     c->lstag.assign(c->k, 0);
-    PASM_TRY(c, {
+    {
         const int k = c->k, N = c->NH;
         c->lam_h = c->theta_h;
         c->lam_prev_h = c->theta_h;
@@ -1358,9 +1416,78 @@ PASM_API pasm_status pasm_restart(pasm_ctx* c) {
         } else {
             prolong_coefs(c, c->zeros, c->lam, true);
         }
-    });
-    return PASM_OK;
+    }
 }
+
+// Context of intermediate level l (1 <= l <= L-2) of c: the same problem
+// on the mesh h_l = H / 2^l (the Galerkin operators of c's hierarchy: for
+// constant coefficients and per-element kappa a rediscretisation with the
+// coarsened kappa), the same k, options and stream, c's coarse space.
+pasm_ctx* make_level_ctx(pasm_ctx* c, int l) {
+    std::unique_ptr<pasm_ctx> ch(new pasm_ctx());
+    ch->opt = c->opt;
+    ch->opt.stream = c->st;
+    if (ch->opt.smoother == PASM_LEARNED) ch->opt.smoother = PASM_JACOBI;
+    ch->st = c->st;
+    ch->own_stream = false;
+    ch->device = c->device;
+    const int n = c->lv[l].g.n;
+    pasm_domain dom{c->dim};
+    pasm_coefficients cf{nullptr, nullptr, 0};
+    if ((size_t)l < c->level_kappa.size() && !c->level_kappa[l].empty()) {
+        cf.kappa = c->level_kappa[l].data();
+        cf.n_elements = c->level_kappa[l].size();
+    }
+    const double H = 1.0 / c->lv[0].g.n, h = 1.0 / n;
+    const Plan pl = validate(ch->opt, &dom, &cf, H, h, c->k);
+    build(ch.get(), pl, &cf, c->k, c);
+    return ch.release();
+}
+
+// x_next = P x (all k vectors) between the finest levels of two contexts of
+// the same problem on consecutive meshes, and lambda carried over.
+void carry_to_finer(pasm_ctx* from, pasm_ctx* to) {
+    const Grid& gc = from->gf();
+    const Grid& gf = to->gf();
+    pasm::launch_prolong<double>(gc, from->U, gf, to->U, from->k, gc.plane, gf.plane, false, nullptr, to->st);
+    PASM_HIP(hipMemcpyAsync(to->lam, from->lam, from->k * sizeof(double), hipMemcpyDeviceToDevice, to->st));
+    PASM_HIP(hipMemcpyAsync(to->lam_prev, from->lam, from->k * sizeof(double), hipMemcpyDeviceToDevice, to->st));
+    to->f_ready = false;
+    to->prolong_pending = false;
+    to->lstag.assign(to->k, 0);
+}
+
+// Algorithm 2 with its step 2(A): the coarse start on V_H, then varpi
+// correction steps on each intermediate level h_2, ..., h_{n-1} (each level
+// starting from the previous one's result), leaving the finest level at the
+// start of step 2(B).  All work is enqueued on the context's stream; one
+// synchronisation at the end reads the eigenvalues.
+void restart_nested(pasm_ctx* c, int varpi) {
+    if (c->L <= 2) {
+        restart_ctx(c);
+        return;
+    }
+    if (c->nested.empty()) {
+        settle_prolongation(c);
+        for (int l = 1; l <= c->L - 2; ++l) c->nested.push_back(make_level_ctx(c, l));
+    }
+    c->prolong_pending = false;
+    pasm_ctx* prev = nullptr;
+    for (pasm_ctx* ch : c->nested) {
+        if (!prev) restart_ctx(ch);
+        else carry_to_finer(prev, ch);
+        for (int it = 0; it < varpi; ++it) iterate_once(ch, false);
+        prev = ch;
+    }
+    carry_to_finer(prev, c);
+    PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    PASM_HIP(hipStreamSynchronize(c->st));
+    c->lam_h.assign(c->lam_pin, c->lam_pin + c->k);
+    c->lam_prev_h = c->lam_h;
+}
+}  // namespace
+
+extern "C" {
 
 PASM_API pasm_status pasm_solve(pasm_ctx* c, int* iterations) {
     if (!c || c->k == 0) return PASM_E_STATE;
