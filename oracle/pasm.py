@@ -236,11 +236,12 @@ def _iterate_one(prob, bvp, lam, u, tol, max_iter):
 
 
 def solve(prob: Problem, k: int, bvp, tol: float = 1e-13, max_iter: int = 60,
-          workers: int = 1, which: Optional[List[int]] = None):
+          workers: int = 1, which: Optional[List[int]] = None, start=None):
     """Algorithm 2: every eigenpair corrected independently until its relative
     eigenvalue change drops below tol.  Returns dict with lam (k,), U (k, N),
-    per-eigenpair histories, timestamps and selected Ritz indices."""
-    lam0, U0, _, _ = coarse_start(prob, k)
+    per-eigenpair histories, timestamps and selected Ritz indices.  start:
+    (lambda, U) of the coarse start when already formed by coarse_start."""
+    lam0, U0 = start if start is not None else coarse_start(prob, k)[:2]
     idx = list(range(k)) if which is None else list(which)
     if workers <= 1:
         res = [_iterate_one(prob, bvp, float(lam0[i]), U0[i].copy(), tol, max_iter) for i in idx]

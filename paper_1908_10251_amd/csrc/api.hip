@@ -419,6 +419,28 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         std::swap(x, y);
         return;
     }
+    if constexpr (std::is_same<T, float>::value) {
+        // edge-weight levels (per-element kappa) in FP32: the same marching
+        // phases with the weights streamed beside x and f
+        const Coef<float> cw = c->coef<float>(l);
+        if (c->fuse && !L.const_coef && !L.general && cw.wx && cw.wy && Lc.g.n * 2 == L.g.n &&
+            pasm::march_ew_supported(L.g, (int)L.pre.size()) && pasm::march_ew_supported(L.g, (int)L.post.size())) {
+            const double nodes = (double)L.g.interior() * nrhs, w = sizeof(T);
+            // the two weight planes, counted once per launch (every right-hand
+            // side reads them; after the first they come from the caches)
+            const double cbytes = 2.0 * w * (double)L.g.interior();
+            if (fine) record_start(c);
+            pasm::launch_march_pre_ew(L.g, cw.wx, cw.wy, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
+            if (fine) record_end(c, ((x_zero ? 2.0 : 3.0) + 0.25) * w * nodes + cbytes);
+            std::swap(x, y);
+            vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
+            if (fine) record_start(c);
+            pasm::launch_march_post_ew(L.g, cw.wx, cw.wy, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
+            if (fine) record_end(c, 3.25 * w * nodes + cbytes);
+            std::swap(x, y);
+            return;
+        }
+    }
     if (c->fuse && !c->learned_on && pasm::march3_supported(L.g, L.const_coef, (int)L.pre.size()) &&
         pasm::march3_supported(L.g, L.const_coef, (int)L.post.size())) {
         // 3D marching phases: all steps of a phase in one pass, the

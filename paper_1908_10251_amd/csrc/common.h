@@ -139,6 +139,13 @@ bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* 
 // rows: rows of the band a wavefront marches down (even); 0 picks it so that
 // the whole grid is resident at once where possible.
 bool march_supported(const Grid& g, bool const_coef, int steps);
+// Edge-weight (per-element kappa) levels, FP32: the marching pre-smoothing
+// with residual restriction and post-smoothing with prolongation.
+bool march_ew_supported(const Grid& g, int steps);
+void launch_march_pre_ew(const Grid& g, const float* wx, const float* wy, const float* x0, const float* f, float* out,
+                         const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, hipStream_t st);
+void launch_march_post_ew(const Grid& g, const float* wx, const float* wy, const float* x, const float* f, float* out,
+                          const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st);
 struct MarchShape {
     int strips, segs, mseg, work, blocks;
 };

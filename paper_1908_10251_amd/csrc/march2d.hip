@@ -96,11 +96,22 @@ struct ProlongSrc {
     double* fout;
 };
 
-template <typename T, int S, int MODE, bool XZ>
+// EW: the level's edge weights (per-element kappa): wx at node (i, j) is the
+// weight of the edge to (i + 1, j), wy the weight of the edge to (i, j + 1);
+// A x = sum over the four edges of w (x - x_neighbour), D = sum of the four.
+template <typename T>
+struct EdgeW {
+    const T* wx;
+    const T* wy;
+};
+
+template <typename T, int S, int MODE, bool XZ, bool EW = false>
 __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
                                               T* __restrict__ out, const T* __restrict__ ec, Grid gc,
                                               T* __restrict__ rc, T* __restrict__ rc2, double* __restrict__ part,
-                                              long sf, long sc, SmoothSteps st, MarchShape sh, ProlongSrc ps) {
+                                              long sf, long sc, SmoothSteps st, MarchShape sh, ProlongSrc ps,
+                                              EdgeW<T> ew) {
+    static_assert(!EW || MODE == 1 || MODE == 2, "edge weights: pre-smoothing and post-smoothing phases only");
     // MODE 4: the post-smoothing of one V-cycle and the pre-smoothing of the
     // next in one pass (S = post + pre stages; the host zeroes the momentum
     // coefficient of the first pre-smoothing stage)
@@ -167,7 +178,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     T bs[S], as[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        bs[t] = MODE == 4 ? (T)st.b[t] : (T)st.b[t] * invD;  // MODE 4: scaled by the host
+        bs[t] = (MODE == 4 || EW) ? (T)st.b[t] : (T)st.b[t] * invD;  // MODE 4: scaled by the host; EW: 1/D per node
         as[t] = (T)st.a[t];
     }
 
@@ -175,6 +186,11 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     T fw[S + 2][2];
     T rw[3][2];
     T mw[3][2];  // MODE 3: rw holds A u, mw holds M u
+    // EW: the weights and 1/D of the last S + 3 rows (index j: row r - j)
+    T cwx[EW ? S + 3 : 1][2], cwy[EW ? S + 3 : 1][2], cdi[EW ? S + 3 : 1][2];
+#pragma unroll
+    for (int j = 0; j < (EW ? S + 3 : 1); ++j)
+        cwx[j][0] = cwx[j][1] = cwy[j][0] = cwy[j][1] = cdi[j][0] = cdi[j][1] = T(0);
     double ua = 0.0, um = 0.0;
 #pragma unroll
     for (int t = 0; t <= S; ++t)
@@ -205,7 +221,14 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     struct Slot {
         T x[2], f[2], e0[2], e1[2];
         T q[2][3];  // MODE 5: the three coarse nodes of the triangle under each column
+        T wx[2], wy[2];  // EW: the weights of the edges east and north of each column (kernel orientation)
     };
+    // EW: in a reflected band the kernel's east edge of a node is the grid's
+    // west edge (wx one column lower, same row) and its north edge the grid's
+    // south edge (wy one row lower, same column); indices clamp at 0 only for
+    // kernel positions on the far boundary, whose east / north weights no
+    // interior node uses
+    const int wxa = flip ? max(ga - 1, 0) : ga, wxb = flip ? max(gb - 1, 0) : gb;
     auto load = [&](int r, Slot& sl) {
         const int rr = min(max(r, 0), g.n);
         const long row = (long)gx(rr) * g.pitch + ORIGIN;
@@ -229,6 +252,13 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         sl.f[0] = fr[row + ga];
         sl.f[1] = fr[row + gb];
+        if constexpr (EW) {
+            sl.wx[0] = ew.wx[row + wxa];
+            sl.wx[1] = ew.wx[row + wxb];
+            const long wyrow = (long)(flip ? max(gx(rr) - 1, 0) : rr) * g.pitch + ORIGIN;
+            sl.wy[0] = ew.wy[wyrow + ga];
+            sl.wy[1] = ew.wy[wyrow + gb];
+        }
         if (POSTLIKE || !XZ) {
             sl.x[0] = xr[row + ga];
             sl.x[1] = xr[row + gb];
@@ -275,6 +305,23 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             xw[0][2][cc] = xw[0][1][cc];
             xw[0][1][cc] = xw[0][0][cc];
             xw[0][0][cc] = cx;
+            if constexpr (EW) {
+#pragma unroll
+                for (int j = S + 2; j > 0; --j) {
+                    cwx[j][cc] = cwx[j - 1][cc];
+                    cwy[j][cc] = cwy[j - 1][cc];
+                    cdi[j][cc] = cdi[j - 1][cc];
+                }
+                cwx[0][cc] = detach(sl.wx[cc]);
+                cwy[0][cc] = detach(sl.wy[cc]);
+            }
+        }
+        if constexpr (EW) {
+            // 1 / D of row r: east, west (the left lane's east weight for the
+            // first column), north and south (row r - 1's north) weights
+            const T west0 = from_left(cwx[0][1]);
+            cdi[0][0] = T(1) / (cwx[0][0] + west0 + cwy[0][0] + cwy[1][0]);
+            cdi[0][1] = T(1) / (cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
         }
         if constexpr (PROLONG) {
             // f = lam M x_0 at row r - 1 from the x_0 rows (r, r-1, r-2): the
@@ -317,12 +364,27 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const T nb1 = m0 + right + xw[t - 1][0][1] + xw[t - 1][2][1];
             const T mc[2] = {m0, m1};
             const T nb[2] = {nb0, nb1};
+            if constexpr (EW) {
+                // weights of row q = r - t: window index t (south: t + 1)
+                const T we[2] = {cwx[t][0], cwx[t][1]};
+                const T ww[2] = {from_left(cwx[t][1]), cwx[t][0]};
+                const T xe[2] = {m1, right}, xwv[2] = {left, m0};
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const T Ax = we[cc] * (mc[cc] - xe[cc]) + ww[cc] * (mc[cc] - xwv[cc]) +
+                                 cwy[t][cc] * (mc[cc] - xw[t - 1][0][cc]) + cwy[t + 1][cc] * (mc[cc] - xw[t - 1][2][cc]);
+                    T val = mc[cc] + bs[t - 1] * ((fw[t][cc] - Ax) * cdi[t][cc]);
+                    if (t >= 2) val += as[t - 1] * (mc[cc] - xw[t - 2][2][cc]);
+                    v[cc] = (row_in && inner[cc]) ? val : T(0);
+                }
+            } else {
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
                 const T Ax = w0 * (T(4) * mc[cc] - nb[cc]);
                 T val = mc[cc] + bs[t - 1] * (fw[t][cc] - Ax);
                 if (t >= 2) val += as[t - 1] * (mc[cc] - xw[t - 2][2][cc]);
                 v[cc] = (row_in && inner[cc]) ? val : T(0);
+            }
             }
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
@@ -348,8 +410,18 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const T left = from_left(m1), right = from_right(m0);
             const T nb0 = left + m1 + xw[S][0][0] + xw[S][2][0];
             const T nb1 = m0 + right + xw[S][0][1] + xw[S][2][1];
-            T res0 = fw[S + 1][0] - w0 * (T(4) * m0 - nb0);
-            T res1 = fw[S + 1][1] - w0 * (T(4) * m1 - nb1);
+            T res0, res1;
+            if constexpr (EW) {
+                // weights of row q1 = r - S - 1: window index S + 1 (south: S + 2)
+                const T ww0 = from_left(cwx[S + 1][1]);
+                res0 = fw[S + 1][0] - (cwx[S + 1][0] * (m0 - m1) + ww0 * (m0 - left) +
+                                       cwy[S + 1][0] * (m0 - xw[S][0][0]) + cwy[S + 2][0] * (m0 - xw[S][2][0]));
+                res1 = fw[S + 1][1] - (cwx[S + 1][1] * (m1 - right) + cwx[S + 1][0] * (m1 - m0) +
+                                       cwy[S + 1][1] * (m1 - xw[S][0][1]) + cwy[S + 2][1] * (m1 - xw[S][2][1]));
+            } else {
+                res0 = fw[S + 1][0] - w0 * (T(4) * m0 - nb0);
+                res1 = fw[S + 1][1] - w0 * (T(4) * m1 - nb1);
+            }
             res0 = (row_in && inner[0]) ? res0 : T(0);
             res1 = (row_in && inner[1]) ? res1 : T(0);
 #pragma unroll
@@ -497,23 +569,23 @@ MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows) {
 }
 
 // Returns the wavefronts per right-hand side (MODE 3: pairs of sums in part).
-template <typename T, int S, int MODE>
+template <typename T, int S, int MODE, bool EW = false>
 int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc, T* rc2,
                  double* part, int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows,
-                 hipStream_t st) {
+                 hipStream_t st, EdgeW<T> ew = EdgeW<T>{nullptr, nullptr}) {
     constexpr int TXO = MW - 2 * march_halo(S);
-    static const int slots = device_wave_slots(k_march<T, S, MODE, false>);
+    static const int slots = device_wave_slots(k_march<T, S, MODE, false, EW>);
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
     if constexpr (MODE == 1) {
         if (x_zero) {
-            hipLaunchKernelGGL((k_march<T, S, MODE, true>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
-                               gc, rc, rc2, part, sf, sc, ss, sh, ProlongSrc{});
+            hipLaunchKernelGGL((k_march<T, S, MODE, true, EW>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
+                               gc, rc, rc2, part, sf, sc, ss, sh, ProlongSrc{}, ew);
             PASM_CHECK_LAUNCH();
             return sh.strips * sh.segs;
         }
     }
-    hipLaunchKernelGGL((k_march<T, S, MODE, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
-                       rc2, part, sf, sc, ss, sh, ProlongSrc{});
+    hipLaunchKernelGGL((k_march<T, S, MODE, false, EW>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
+                       rc2, part, sf, sc, ss, sh, ProlongSrc{}, ew);
     PASM_CHECK_LAUNCH();
     return sh.strips * sh.segs;
 }
@@ -536,7 +608,8 @@ void march_pair_launch(const Grid& g, double w0, const double* x, const double* 
     static const int slots = device_wave_slots(k_march<double, S, 4, false>);
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, one_round_rows(g, TXO, nrhs, slots));
     hipLaunchKernelGGL((k_march<double, S, 4, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x, f, out, ec, gc,
-                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh, ProlongSrc{});
+                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh, ProlongSrc{},
+                       EdgeW<double>{nullptr, nullptr});
     PASM_CHECK_LAUNCH();
 }
 
@@ -550,7 +623,7 @@ void march_prolong_launch(const Grid& g, double w0, const double* u, double* fou
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, one_round_rows(g, TXO, nrhs, slots));
     hipLaunchKernelGGL((k_march<double, S, 5, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, u, fout, out,
                        (const double*)nullptr, gc, rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh,
-                       ps);
+                       ps, EdgeW<double>{nullptr, nullptr});
     PASM_CHECK_LAUNCH();
 }
 
@@ -567,7 +640,41 @@ int march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T
     }
 }
 
+template <int MODE>
+void march_dispatch_ew(const Grid& g, const float* x0, const float* f, float* out, const float* ec, const Grid& gc,
+                       float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, const EdgeW<float>& ew,
+                       hipStream_t st) {
+    switch (ss.s) {
+        case 1: march_launch<float, 1, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
+        case 2: march_launch<float, 2, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
+        case 3: march_launch<float, 3, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
+        case 4: march_launch<float, 4, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
+        default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
+    }
+}
+
 }  // namespace
+
+// Edge-weight levels (per-element kappa), FP32 V-cycles: pre-smoothing with
+// the residual restriction and post-smoothing with the prolongation as
+// marching passes, as for constant coefficients.
+bool march_ew_supported(const Grid& g, int steps) {
+    return g.dim == 2 && steps >= 1 && steps <= 4 && g.n >= 256;
+}
+
+void launch_march_pre_ew(const Grid& g, const float* wx, const float* wy, const float* x0, const float* f, float* out,
+                         const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+    if (!march_ew_supported(g, ss.s) || gc.n * 2 != g.n || !wx || !wy)
+        throw Error(PASM_E_INVALID, "edge-weight marching: 2D, at least 256 cells, ratio 2");
+    march_dispatch_ew<1>(g, x0, f, out, nullptr, gc, rc, nrhs, ss, x_zero, EdgeW<float>{wx, wy}, st);
+}
+
+void launch_march_post_ew(const Grid& g, const float* wx, const float* wy, const float* x, const float* f, float* out,
+                          const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st) {
+    if (!march_ew_supported(g, ss.s) || gc.n * 2 != g.n || !wx || !wy)
+        throw Error(PASM_E_INVALID, "edge-weight marching: 2D, at least 256 cells, ratio 2");
+    march_dispatch_ew<2>(g, x, f, out, ec, gc, nullptr, nrhs, ss, false, EdgeW<float>{wx, wy}, st);
+}
 
 // Large 2D levels only: a wavefront walks 64 + 2(S+2) rows in sequence, which
 // needs many strips and segments to fill the machine; smaller levels use the

@@ -167,6 +167,32 @@ def test_batch_every_tile_height_agrees():
             P.pasm_batch_set_tiles(b.b, [0] + [3] * (L - 1))
 
 
+def test_batch_tile_height_8_agrees():
+    # the tallest fused tile (8 x 4 LDS rows per workgroup) fits the LDS with
+    # FP32 V-cycles: compared with per-step smoothing and with height 4 on the
+    # same start, to the mixed-precision bar
+    _say("batch tile height 8 (mixed)")
+    k = 2
+    mem = _members()
+    with P.Batch(H, k, [(1 / nf, kap, vel) for nf, _, kap, vel in mem],
+                 opts=_opts(precision=P.PASM_MIXED, nu=2)) as b:
+        rows, ms = P.pasm_batch_tuning(b.b)
+        L = P.pasm_batch_num_levels(b.b)
+        t8 = [0] + [8 if ms[l][3] >= 0 else 4 for l in range(1, L)]
+        assert any(t == 8 for t in t8[1:]), ms
+        out = {}
+        for name, tiles in (("0", [0] * L), ("4", [0] + [4] * (L - 1)), ("8", t8)):
+            P.pasm_batch_set_tiles(b.b, tiles)
+            P.pasm_batch_restart(b.b)
+            b.iterate()
+            b.iterate()
+            out[name] = b.eigenvalues()
+        for name in ("4", "8"):
+            d = np.max(np.abs(out[name] - out["0"]) / out["0"])
+            _say(f"  tiles {name} vs per-step: {d:.2e}")
+            assert d < 1e-8, name
+
+
 def test_batch_mixed_solve_reaches_discrete_eigenvalues():
     _say("batch mixed solve")
     k = 2

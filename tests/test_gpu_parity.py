@@ -97,6 +97,10 @@ VC = [
     (2, 64, 512, None, "jacobi", 2, False),
     # odd step counts: strip halos rounded up to an even width
     (2, 32, 512, None, "jacobi", 3, False),
+    # per-element kappa on marching levels (FP32 cycles take the edge-weight
+    # marching smoother): ragged strips and bands, odd step counts
+    (2, 32, 512, 1.0, "cheb", 4, False),
+    (2, 16, 256, 1.0, "jacobi", 3, False),
     # general 7-point operators (potential term), Galerkin coarse levels
     (2, 4, 64, 1.0, "cheb", 4, True),
     (2, 8, 64, None, "jacobi", 2, True),
@@ -138,6 +142,35 @@ def test_vcycle_matches_oracle(dim, nc, nf, sig, smoother, nu, pot, precision, f
                 tol = 1e-12 * max(1.0, (nf / 64) ** 2) if precision == P.PASM_FP64 else 2e-5
                 _say(f"  ncyc={ncyc} rhs={r} err={err:.2e} tol={tol:.1e}")
                 assert err < tol, (ncyc, r, err)
+
+
+@pytest.mark.parametrize("precision", [P.PASM_FP64, P.PASM_MIXED])
+def test_vcycle_kappa_2048_matches_oracle(precision):
+    # the rough-coefficient workload's mesh and coefficient (4.2M nodes,
+    # log kappa ~ N(0, 1) per element, H = 1/32, Chebyshev 4/4): one and two
+    # V-cycles on one right-hand side against the oracle's
+    nc, nf = 32, 2048
+    _say(f"vcycle kappa h=1/{nf} H=1/{nc} cheb 4/4 prec={precision}")
+    kap = lognormal_kappa(2, nf, seed=0, sigma=1.0)
+    A, _ = fem.assemble(2, nf, kappa=kap)
+    hier = Hierarchy(2, A, nc, nf)
+    opts = default_options(2, "cheb", 4, 4, 1)
+    rng = np.random.default_rng(8)
+    N = A.shape[0]
+    f = rng.standard_normal((1, N))
+    x0 = rng.standard_normal((1, N))
+    with P.Solver(2, 1 / nc, 1 / nf, 1, kappa=kap, opts=_opts("cheb", 4, precision=precision)) as s:
+        for ncyc in (1, 2):
+            xg = _t(x0)
+            P.pasm_vcycle(s.ctx, _t(f), xg, ncyc)
+            xg = xg.cpu().numpy()[0]
+            xr = x0[0].copy()
+            for _ in range(ncyc):
+                xr = hier.vcycle(len(hier.levels) - 1, xr, f[0], opts)
+            err = np.max(np.abs(xg - xr)) / np.max(np.abs(xr))
+            tol = 1e-12 * (nf / 64) ** 2 if precision == P.PASM_FP64 else 2e-5
+            _say(f"  ncyc={ncyc} err={err:.2e} tol={tol:.1e}")
+            assert err < tol
 
 
 @pytest.mark.parametrize("nf,smoother,pre,post", [(256, "cheb", 4, 4), (512, "jacobi", 2, 2), (256, "cheb", 3, 1),
