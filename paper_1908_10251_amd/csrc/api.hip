@@ -139,6 +139,9 @@ struct pasm_ctx {
     // F64 holds lambda M u for the current U and lam (formed by the last
     // step's prolongation); anything else that touches U, lam or F64 clears it
     bool f_ready = false;
+    // mixed 2D: the last V-cycle's FP32 correction (E32) is still to be added
+    // to U; the step's border pass adds it
+    bool e_pending = false;
     std::vector<char> lstag;  // per eigenpair: the plain V-cycle stagnated too (learned fallback test)
     long lcycles_learned = 0, lcycles_fallback = 0;
     double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
@@ -484,7 +487,7 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
 // cycle's last pass); with next set, this cycle's correction and the
 // next cycle's residual are formed in one pass, x moving to scr.
 void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, bool* r_ready = nullptr,
-               bool next = false) {
+               bool next = false, bool defer_add = false) {
     const int lf = c->L - 1;
     if (!c->mixed) {
         c->pair_next = next;
@@ -502,6 +505,11 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
         pasm::launch_add_resid(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st);
         std::swap(x, scr);
         *r_ready = true;
+        return;
+    }
+    if (defer_add) {
+        // the last cycle of a step (2D): x + e is formed by the border pass
+        c->e_pending = true;
         return;
     }
     pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
@@ -539,7 +547,9 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
             c->border_next = border && cy == ncycles - 1 && !c->mixed;
-            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles);
+            const bool defer = border && cy == ncycles - 1 && c->mixed && c->dim == 2 &&
+                               pasm::coef_kind(c->coef<double>(c->L - 1)) <= 1;
+            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles, defer);
             c->border_next = false;
         }
         if (c->fine_pre_done) throw Error(PASM_E_DEVICE, "paired smoothing phases: a cycle left unfinished");
@@ -1018,11 +1028,20 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
     int lstart = c->L - 2;
     if (c->L >= 2) {
         pasm::Level& Lc = c->lv[c->L - 2];
-        const int nblk = c->border_done   ? c->border_nblk
-                         : c->dim == 2    ? pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B,
-                                                                         Lc.C, c->partial, k, sf, Lc.g.plane, c->st)
-                                          : pasm::launch_border_restrict3(g, c->coef<double>(lf), c->U, Lc.g, Lc.B,
-                                                                          Lc.C, c->partial, k, sf, Lc.g.plane, c->st);
+        int nblk;
+        if (c->e_pending) {
+            // u~ = x + e (the last correction) and the borders of u~ in one pass
+            nblk = pasm::launch_border_restrict_add(g, c->coef<double>(lf), c->U, c->E32, c->Y64, Lc.g, Lc.B, Lc.C,
+                                                    c->partial, k, sf, Lc.g.plane, c->st);
+            std::swap(c->U, c->Y64);
+            c->e_pending = false;
+        } else {
+            nblk = c->border_done ? c->border_nblk
+                   : c->dim == 2  ? pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
+                                                                 c->partial, k, sf, Lc.g.plane, c->st)
+                                  : pasm::launch_border_restrict3(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
+                                                                  c->partial, k, sf, Lc.g.plane, c->st);
+        }
         pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
         bsrc = Lc.B;
         csrc = Lc.C;

@@ -269,6 +269,11 @@ int launch_border(const Grid& g, const Coef<double>& c, const double* u, double*
 // the coarse grid).  Returns the number of blocks per right-hand side.
 int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st);
+// The same after the last V-cycle's correction: borders of un = u + e (e the
+// FP32 correction, added in FP64), un written (2D, constant or edge weights).
+int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
+                               const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
+                               hipStream_t st);
 
 // out[r][0..1] = sums of partial[r][0..nblk)[0..1] in a fixed order.
 void launch_reduce_pairs(const double* partial, int nblk, double* out, int nrhs, hipStream_t st);

@@ -422,21 +422,29 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
     r[(long)blockIdx.z * rstride + id] = (TO)(f[off + id] - Ax);
 }
 
-// Defect correction between two cycles in one pass (2D, constant
-// coefficients): un = u + e on every interior node and r = f - A un (FP64,
-// rounded to FP32) for the next cycle; un at the neighbours is formed again
-// from u and e.  un must not alias u.
-__global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, double w0, const double* __restrict__ u,
+// Defect correction between two cycles in one pass (2D; KIND 0 constant
+// coefficients, 1 edge weights): un = u + e on every interior node and
+// r = f - A un (FP64, rounded to FP32) for the next cycle; un at the
+// neighbours is formed again from u and e.  un must not alias u.
+template <int KIND>
+__global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, const double* __restrict__ u,
                                                       const float* __restrict__ e, const double* __restrict__ f,
                                                       double* __restrict__ un, float* __restrict__ r, long stride) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
     const long off = (long)blockIdx.z * stride;
-    const long id = off + g.idx(i, j);
+    const long gid = g.idx(i, j);
+    const long id = off + gid;
     auto v = [&](long q) { return u[q] + (double)e[q]; };
     const double x0 = v(id);
-    const double Ax = w0 * (4.0 * x0 - (v(id + 1) + v(id - 1) + v(id + g.pitch) + v(id - g.pitch)));
+    double Ax;
+    if (KIND == 0) {
+        Ax = c.w0 * (4.0 * x0 - (v(id + 1) + v(id - 1) + v(id + g.pitch) + v(id - g.pitch)));
+    } else {
+        const double we = c.wx[gid], ww = c.wx[gid - 1], wn = c.wy[gid], ws = c.wy[gid - g.pitch];
+        Ax = (we + ww + wn + ws) * x0 - we * v(id + 1) - ww * v(id - 1) - wn * v(id + g.pitch) - ws * v(id - g.pitch);
+    }
     un[id] = x0;
     r[id] = (float)(f[id] - Ax);
 }
@@ -556,11 +564,15 @@ __global__ __launch_bounds__(BX* BY) void k_border_restrict(Grid g, Coef<double>
 constexpr int BRX = 32, BRY = 8;                  // coarse nodes per workgroup
 constexpr int BFX = 2 * BRX + 1, BFY = 2 * BRY + 1;  // fine nodes with A u, M u
 constexpr int BUX = BFX + 2, BUY = BFY + 2;          // fine nodes of u (halo 1)
-template <int KIND>
+// ADD: u is the V-cycles' iterate before its last correction; the tile
+// holds u + ecor (the FP32 correction, added in FP64) and the owned nodes of
+// the corrected field are written to un (which must not alias u).
+template <int KIND, bool ADD = false>
 __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> cg, const double* __restrict__ u,
                                                           Grid gc, double* __restrict__ bc,
                                                           double* __restrict__ cc, double* __restrict__ partial,
-                                                          long stride, long sc) {
+                                                          long stride, long sc, const float* __restrict__ ecor,
+                                                          double* __restrict__ un) {
     __shared__ double us[BUY][BUX];
     __shared__ double as[BFY][BFX];
     __shared__ double ms[BFY][BFX];
@@ -571,6 +583,7 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
     double bs;
     const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const double* ur = u + (long)blockIdx.z * stride;
+    const float* er = ADD ? ecor + (long)blockIdx.z * stride : nullptr;
     {
         // all of a thread's loads are issued before any of them is used
         constexpr int NPT = (BUX * BUY + 255) / 256;
@@ -580,7 +593,9 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
             const int t = tid + 256 * e;
             const int a = t % BUX, b = t / BUX;
             const int i = fi0 - 1 + a, j = fj0 - 1 + b;
-            v[e] = (t < BUX * BUY && i <= g.n && j <= g.n) ? ur[g.idx(i, j)] : 0.0;
+            const bool in = t < BUX * BUY && i <= g.n && j <= g.n;
+            v[e] = in ? ur[g.idx(i, j)] : 0.0;
+            if (ADD) v[e] += in ? (double)er[g.idx(i, j)] : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < NPT; ++e) {
@@ -616,6 +631,7 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
             if (a < 2 * BRX && b < 2 * BRY) {  // owned
                 ua += x0 * Ax;
                 um += x0 * Mx;
+                if (ADD) un[(long)blockIdx.z * stride + g.idx(i, j)] = x0;
             }
         }
         as[b][a] = Ax;
@@ -1013,14 +1029,18 @@ void launch_add_correction(const float* e, double* u, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_add_correction<float>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
     PASM_CHECK_LAUNCH();
 }
-bool add_resid_supported(const Grid& g, const Coef<double>& c) { return g.dim == 3 || coef_kind(c) == 0; }
+bool add_resid_supported(const Grid& g, const Coef<double>& c) {
+    return g.dim == 3 || (coef_kind(c) <= 1 && c.kpm <= 1 && c.ms == 0);
+}
 
 void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                       double* un, float* r, int nrhs, long stride, hipStream_t st) {
     if (g.dim == 3) return launch_add_resid3(g, c, u, e, f, un, r, nrhs, stride, st);
-    if (coef_kind(c) != 0 || un == u) throw Error(PASM_E_INVALID, "add and residual: constant 2D, separate output");
+    if (!add_resid_supported(g, c) || un == u)
+        throw Error(PASM_E_INVALID, "add and residual: 2D constant or edge-weight operator, separate output");
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    hipLaunchKernelGGL(k_add_resid, grid, blk, 0, st, g, c.w0, u, e, f, un, r, stride);
+    if (coef_kind(c) == 0) hipLaunchKernelGGL(k_add_resid<0>, grid, blk, 0, st, g, c, u, e, f, un, r, stride);
+    else hipLaunchKernelGGL(k_add_resid<1>, grid, blk, 0, st, g, c, u, e, f, un, r, stride);
     PASM_CHECK_LAUNCH();
 }
 
@@ -1046,11 +1066,27 @@ int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u
                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st) {
     if (g.dim != 2 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 2D, ratio 2");
     dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
+    const float* e0 = nullptr;
+    double* u0 = nullptr;
     switch (coef_kind(c)) {
-        case 0: hipLaunchKernelGGL(k_border_restrict_t<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
-        case 1: hipLaunchKernelGGL(k_border_restrict_t<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
-        default: hipLaunchKernelGGL(k_border_restrict_t<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc); break;
+        case 0: hipLaunchKernelGGL(k_border_restrict_t<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0); break;
+        case 1: hipLaunchKernelGGL(k_border_restrict_t<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0); break;
+        default: hipLaunchKernelGGL(k_border_restrict_t<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0); break;
     }
+    PASM_CHECK_LAUNCH();
+    return (int)(grid.x * grid.y);
+}
+
+int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
+                               const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
+                               hipStream_t st) {
+    if (g.dim != 2 || gc.n * 2 != g.n || un == u || coef_kind(c) == 2)
+        throw Error(PASM_E_INVALID, "correction with borders: 2D, ratio 2, constant or edge weights, separate output");
+    dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
+    if (coef_kind(c) == 0)
+        hipLaunchKernelGGL((k_border_restrict_t<0, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e, un);
+    else
+        hipLaunchKernelGGL((k_border_restrict_t<1, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e, un);
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y);
 }
