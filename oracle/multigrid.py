@@ -25,11 +25,16 @@ throughout this project (and by the GPU library, implemented independently) is:
         Chebyshev of degree s on D^{-1} A over [rho/alpha, rho], rho the
         Gershgorin bound max_i sum_j |a_ij| / a_ii.  Written here in the
         two-vector (direction, residual) form of the Chebyshev semi-iteration.
+        conjugate gradients (the smoother of the paper's experiments, Section
+        5: one multigrid step with 2 CG steps for pre- and post-smoothing):
+        nu steps of plain CG on A x = f from the current x.
 
 Parity status: pinned.  The smoothers are checked against the closed-form
 error propagation of Jacobi ((1 - omega t)^nu) and of Chebyshev (the scaled
-Chebyshev polynomial) on exact eigenvectors of D^{-1} A, and the V-cycle
-against its contraction on the Laplacian (tests/test_oracle_multigrid.py).
+Chebyshev polynomial) on exact eigenvectors of D^{-1} A, CG against the
+A-norm minimiser over the Krylov space computed by brute force and its
+finite termination, and the V-cycle against its contraction on the Laplacian
+(tests/test_oracle_multigrid.py).
 """
 from __future__ import annotations
 
@@ -54,7 +59,7 @@ class Level:
 
 @dataclasses.dataclass
 class MGOptions:
-    smoother: str = "jacobi"     # "jacobi" | "cheb" | "learned"
+    smoother: str = "jacobi"     # "jacobi" | "cheb" | "learned" | "cg"
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8
@@ -132,7 +137,35 @@ class Hierarchy:
             rho_j = rho_next
         return x
 
+    @staticmethod
+    def cg(lv: Level, x: np.ndarray, f: np.ndarray, nu: int) -> np.ndarray:
+        """nu steps of (unpreconditioned) conjugate gradients on A x = f:
+        r = f - A x, p = r; then per step alpha = r.r / p.Ap, x += alpha p,
+        r -= alpha Ap, beta = r_new.r_new / r.r, p = r + beta p.  A zero
+        denominator (an exact solution already) leaves x as it is."""
+        if nu <= 0:
+            return x
+        x = x.copy()
+        r = f - lv.A @ x
+        p = r.copy()
+        rr = float(r @ r)
+        for j in range(nu):
+            q = lv.A @ p
+            pq = float(p @ q)
+            alpha = rr / pq if pq != 0.0 else 0.0
+            x = x + alpha * p
+            if j == nu - 1:
+                break
+            r = r - alpha * q
+            rr_new = float(r @ r)
+            beta = rr_new / rr if rr != 0.0 else 0.0
+            p = r + beta * p
+            rr = rr_new
+        return x
+
     def smooth(self, lv: Level, x, f, opts: MGOptions, nu: int):
+        if opts.smoother == "cg":
+            return self.cg(lv, x, f, nu)
         if opts.smoother == "jacobi":
             return self.jacobi(lv, x, f, opts.omega, nu)
         if opts.smoother == "cheb":

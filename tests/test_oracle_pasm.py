@@ -140,3 +140,14 @@ def test_3d_with_degenerate_pairs():
     Qb, _ = np.linalg.qr(Ug)
     s = np.linalg.svd(Qa.T @ Qb, compute_uv=False)
     assert np.min(s) > 1 - 1e-8
+
+
+def test_paper_multigrid_step_reaches_the_same_fixed_points(small2d):
+    # the paper's boundary value solver (one V-cycle with 2 CG pre- and
+    # post-smoothing steps, Section 5) changes the speed only: the same
+    # discrete eigenpairs
+    from oracle.multigrid import MGOptions
+    prob = small2d
+    w, _ = pasm.discrete_eigenpairs(prob.A, prob.M, 4)
+    r = pasm.solve(prob, 4, pasm.MultigridBVP(prob, MGOptions("cg", 2, 2, vcycles=1)), tol=1e-13)
+    assert np.max(np.abs(r["lam"] - w) / w) < 1e-11
