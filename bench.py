@@ -57,6 +57,9 @@ KERNEL_NAMES = {
     "learned": "finest-level learned smoothing step (k_learned_step: residual, two bfloat16 matrix-core "
                "convolutions, update)",
     "batch": "finest batched level smoothing phases (k_smooth_fused, general 7-point operators)",
+    "cg": "finest-level conjugate-gradient smoothing phases (k_cg_start, k_cg_dir: direction update fused with "
+          "A p and p.Ap partial sums, k_cg_update: x, r and r.r partial sums; the inner products added per "
+          "right-hand side by k_cg_reduce; the paper's multigrid step)",
     "kappa": "finest-level smoothing phases (k_march with edge weights, FP32: pre-smoothing with fused residual "
              "restriction, post-smoothing with fused prolongation; the two weight planes streamed beside x and f)",
 }
@@ -265,7 +268,7 @@ def bench_solve(args, wl, pasm, torch):
                               "max_rel_err": float(np.max(rel_err(lam_t))),
                               "bar": 1e-10 if wl.precision == "fp64" else 1e-8}
     flops = None
-    kernel = KERNEL_NAMES[wl.dim]
+    kernel = KERNEL_NAMES["cg"] if wl.smoother == "cg" else KERNEL_NAMES[wl.dim]
     if learned:
         rep = pasm.pasm_learned_report(ctx)
         cfg["learned"] = rep

@@ -82,6 +82,13 @@ typedef enum pasm_smoother {
                               cycle's, and throughout when the learned cycle reduces the
                               residual less per unit time than the plain one at set-up
                               (see pasm_learned_report) */
+    ,
+    PASM_CG = 3            /* the smoother of the paper's experiments (Section 5: one
+                              multigrid step with 2 CG steps for pre- and post-smoothing):
+                              nu_pre / nu_post steps of plain conjugate gradients on
+                              A_l x = f_l from the current iterate, on every level; each
+                              step forms two inner products over the level per
+                              right-hand side (block partial sums added in a fixed order) */
 } pasm_smoother;
 
 /* Unit box (0,1)^dim; dim = 2 or 3. */

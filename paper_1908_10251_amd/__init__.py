@@ -19,7 +19,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pasm.h")
 
 PASM_OK, PASM_E_INVALID, PASM_E_NOMEM, PASM_E_DEVICE, PASM_E_STATE, PASM_E_NOTCONV, PASM_E_BREAKDOWN = range(7)
 PASM_FP64, PASM_MIXED = 0, 1
-PASM_JACOBI, PASM_CHEBYSHEV, PASM_LEARNED = 0, 1, 2
+PASM_JACOBI, PASM_CHEBYSHEV, PASM_LEARNED, PASM_CG = 0, 1, 2, 3
 PASM_OP_STIFFNESS, PASM_OP_MASS = 0, 1
 
 
@@ -328,7 +328,7 @@ def options(precision: int = PASM_FP64, smoother: int = PASM_JACOBI, nu_pre: int
 
 def options_for(workload) -> pasm_options:
     """Options matching a `workloads.Workload` description."""
-    sm = {"cheb": PASM_CHEBYSHEV, "jacobi": PASM_JACOBI, "learned": PASM_LEARNED}[workload.smoother]
+    sm = {"cheb": PASM_CHEBYSHEV, "jacobi": PASM_JACOBI, "learned": PASM_LEARNED, "cg": PASM_CG}[workload.smoother]
     return options(precision=PASM_MIXED if workload.precision == "mixed" else PASM_FP64,
                    smoother=sm,
                    nu_pre=workload.nu_pre, nu_post=workload.nu_post, vcycles=workload.vcycles,

@@ -63,6 +63,8 @@ struct Level {
     // FP64 border / prolongation chain vectors
     double* B = nullptr;
     double* C = nullptr;
+    // conjugate-gradient smoothing work (PASM_CG)
+    CgWork cg{};
 };
 
 }  // namespace
@@ -278,6 +280,17 @@ void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb
     const pasm::Level& L = c->lv[l];
     const Coef<T> cf = c->coef<T>(l);
     const bool fine = (l == c->L - 1);
+    if (c->opt.smoother == PASM_CG) {
+        // x updated in place (no swap); algorithmic bytes of the kernels:
+        // start 3 words (2 from x = 0), first direction 3, later ones 4,
+        // updates 6 (the last of a phase 3: x only)
+        const int S = (int)steps.size();
+        const double words = (x_zero ? 2.0 : 3.0) + 3.0 + 4.0 * (S - 1) + 6.0 * (S - 1) + 3.0;
+        if (fine) record_start(c);
+        pasm::cg_smooth<T>(L.g, cf, x, f, nrhs, S, x_zero, L.cg, c->st);
+        if (fine) record_end(c, words * sizeof(T) * (double)L.g.interior() * nrhs);
+        return;
+    }
     const double nodes = (double)L.g.interior();
     const double coef_bytes = L.const_coef ? 0.0 : (double)(L.general ? 4 : L.g.dim) * sizeof(T) * nodes;
     // tallest fused tile whose LDS fits (general stencils need four coefficient tiles)
@@ -649,7 +662,8 @@ Plan validate(const pasm_options& opt, const pasm_domain* dom, const pasm_coeffi
     if (opt.vcycles < 1 || opt.nu_pre < 0 || opt.nu_post < 0 || opt.max_iter < 1 || !(opt.tol >= 0.0))
         throw Error(PASM_E_INVALID, "bad cycle options");
     if (opt.precision != PASM_FP64 && opt.precision != PASM_MIXED) throw Error(PASM_E_INVALID, "bad precision");
-    if (opt.smoother != PASM_JACOBI && opt.smoother != PASM_CHEBYSHEV && opt.smoother != PASM_LEARNED)
+    if (opt.smoother != PASM_JACOBI && opt.smoother != PASM_CHEBYSHEV && opt.smoother != PASM_LEARNED &&
+        opt.smoother != PASM_CG)
         throw Error(PASM_E_INVALID, "bad smoother");
     if (opt.smoother == PASM_LEARNED && (p.dim != 3 || (coef && (coef->kappa || coef->potential))))
         throw Error(PASM_E_INVALID, "the learned smoother is for 3D problems with constant coefficients");
@@ -684,7 +698,9 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
     c->L = L;
     c->NH = pl.NH;
     c->mixed = (c->opt.precision == PASM_MIXED);
-    c->fuse = c->opt.fused_smoothing != 0;
+    // CG smoothing has no fused (temporally blocked) form: every step needs
+    // the whole level's inner products
+    c->fuse = c->opt.fused_smoothing != 0 && c->opt.smoother != PASM_CG;
     const double omega = c->opt.omega > 0 ? c->opt.omega : (dim == 2 ? 0.8 : 6.0 / 7.0);
     const double alpha = c->opt.cheb_alpha > 0 ? c->opt.cheb_alpha : (dim == 2 ? 4.0 : 6.0);
 
@@ -739,7 +755,9 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
         if (c->opt.smoother == PASM_CHEBYSHEV) {
             Lv.pre = pasm::cheb_steps(Lv.rho, alpha, c->opt.nu_pre);
             Lv.post = pasm::cheb_steps(Lv.rho, alpha, c->opt.nu_post);
-        } else if (c->opt.smoother == PASM_JACOBI || c->opt.smoother == PASM_LEARNED) {
+        } else if (c->opt.smoother == PASM_JACOBI || c->opt.smoother == PASM_LEARNED ||
+                   c->opt.smoother == PASM_CG) {
+            // (CG: only the step counts are used)
             Lv.pre = pasm::jacobi_steps(omega, c->opt.nu_pre);
             Lv.post = pasm::jacobi_steps(omega, c->opt.nu_post);
         } else {
@@ -763,6 +781,20 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
         // B and C adjacent, so the two coarse products with Q^T share one pass
         Lv.B = c->alloc<double>(2 * n);
         Lv.C = Lv.B + n;
+    }
+    if (c->opt.smoother == PASM_CG) {
+        long pmax = 1;
+        for (int l = 1; l < L; ++l) pmax = std::max(pmax, pasm::cg_partials(c->lv[l].g));
+        double* partial = c->alloc<double>((size_t)pmax * k);
+        double* sc = c->alloc<double>(3 * (size_t)k);
+        for (int l = 1; l < L; ++l) {
+            pasm::Level& Lv = c->lv[l];
+            const size_t n = (size_t)Lv.g.plane * k;
+            void* v[4];
+            for (int a = 0; a < 4; ++a)
+                v[a] = c->mixed ? static_cast<void*>(c->alloc<float>(n)) : static_cast<void*>(c->alloc<double>(n));
+            Lv.cg = pasm::CgWork{v[0], v[1], v[2], v[3], partial, sc, sc + k, sc + 2 * k};
+        }
     }
     const size_t nf = (size_t)c->sf() * k;
     c->U = c->alloc<double>(nf);

@@ -139,6 +139,26 @@ bool launch_smooth_fused(const Grid& g, const Coef<T>& c, const T* x0, const T* 
 // rows: rows of the band a wavefront marches down (even); 0 picks it so that
 // the whole grid is resident at once where possible.
 bool march_supported(const Grid& g, bool const_coef, int steps);
+// Conjugate-gradient smoothing (the paper's multigrid step): steps of plain
+// CG on A x = f for nrhs right-hand sides of one level, x updated in place
+// (x_zero: from x = 0, x overwritten).  Work vectors r, pa, pb, q of the
+// cycle's type (one padded plane per right-hand side each), partial sums
+// (cg_partials(g) per right-hand side), and three scalars per right-hand side.
+struct CgWork {
+    void* r;
+    void* pa;
+    void* pb;
+    void* q;
+    double* partial;
+    double* rr;
+    double* alpha;
+    double* beta;
+};
+long cg_partials(const Grid& g);
+template <typename T>
+void cg_smooth(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int steps, bool x_zero, const CgWork& w,
+               hipStream_t st);
+
 // Edge-weight (per-element kappa) levels, FP32: the marching pre-smoothing
 // with residual restriction and post-smoothing with prolongation.
 bool march_ew_supported(const Grid& g, int steps);

@@ -36,7 +36,7 @@ class Workload:
     H: float            # coarse mesh size (the augmenting space V_H)
     h: float            # finest mesh size
     k: int              # number of sought eigenpairs
-    smoother: str       # "jacobi" | "cheb" | "learned"
+    smoother: str       # "jacobi" | "cheb" | "learned" | "cg"
     nu_pre: int
     nu_post: int
     vcycles: int        # V-cycles per boundary value problem
@@ -83,6 +83,11 @@ LAP2D_LARGE_MIXED = Workload("lap2d-H64-h1024-k20-mixed", 2, 1 / 64, 1 / 1024, 2
 # 1e-8 instead of 7), which outweighs its larger dense coarse products.
 LAP2D_LARGE_H64 = Workload("lap2d-H64-h1024-k20", 2, 1 / 64, 1 / 1024, 20, "cheb", 4, 4, 2, "fp64",
                            1e-10, golden="lap2d-H32-h1024-k20")
+# The paper's own boundary value solver (Section 5): one multigrid step (V-cycle)
+# with 2 conjugate-gradient steps for pre- and post-smoothing, on the same
+# 1M-node problem
+LAP2D_LARGE_CG = Workload("lap2d-H64-h1024-k20-cg", 2, 1 / 64, 1 / 1024, 20, "cg", 2, 2, 1, "fp64",
+                          1e-10, golden="lap2d-H32-h1024-k20")
 # 4.2M fine dofs, 50 eigenpairs, log-normal kappa i.i.d. per fine element
 KAPPA2D_MIXED = Workload("kappa2d-H32-h2048-k50-mixed", 2, 1 / 32, 1 / 2048, 50, "cheb", 4, 4, 2,
                          "mixed", 1e-10, kappa="lognormal", seed=0)
@@ -95,8 +100,8 @@ LAP3D = Workload("lap3d-H8-h128-k100-mixed", 3, 1 / 8, 1 / 128, 100, "jacobi", 2
 LAP3D_LEARNED = Workload("lap3d-H8-h128-k100-learned", 3, 1 / 8, 1 / 128, 100, "learned", 2, 2, 2,
                          "mixed", 1e-10, golden="lap3d-H8-h128-k100-mixed")
 
-ALL = [LAP2D_SMALL, LAP2D_LARGE, LAP2D_LARGE_H64, LAP2D_LARGE_MIXED, KAPPA2D_MIXED, BATCH2D_UNEVEN, LAP3D,
-       LAP3D_LEARNED]
+ALL = [LAP2D_SMALL, LAP2D_LARGE, LAP2D_LARGE_H64, LAP2D_LARGE_MIXED, LAP2D_LARGE_CG, KAPPA2D_MIXED, BATCH2D_UNEVEN,
+       LAP3D, LAP3D_LEARNED]
 
 
 def n_elements(dim: int, n: int) -> int:
