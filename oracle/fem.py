@@ -100,11 +100,14 @@ def _scatter(nodes: np.ndarray, local: np.ndarray, size: int) -> sp.csr_matrix:
 def assemble(dim: int, n: int,
              kappa: Optional[np.ndarray] = None,
              potential: Optional[Callable[[np.ndarray], np.ndarray]] = None,
-             full: bool = False):
+             full: bool = False,
+             tensor: Optional[Callable[[np.ndarray], np.ndarray]] = None):
     """Stiffness A (with the potential term, if any) and mass M.
 
     kappa: per-element coefficient (None means 1).
     potential: V(x) evaluated at element centroids, x of shape (E, d).
+    tensor: the diffusion tensor A(x) (E, d, d) evaluated at element
+            centroids (None means the identity): K_T = kappa_T |T| G A_T G^T.
     full: if True return matrices over all nodes, else over interior nodes only
           (homogeneous Dirichlet condition, Section 2).
     """
@@ -114,7 +117,13 @@ def assemble(dim: int, n: int,
     vol, G = element_geometry(X, h)
     kap = np.ones(E) if kappa is None else np.asarray(kappa, dtype=np.float64)
     assert kap.shape == (E,)
-    K_loc = (kap * vol)[:, None, None] * np.einsum("eid,ejd->eij", G, G)
+    if tensor is None:
+        K_loc = (kap * vol)[:, None, None] * np.einsum("eid,ejd->eij", G, G)
+    else:
+        centroid = X.astype(np.float64).mean(axis=1) * h
+        At = np.asarray(tensor(centroid), dtype=np.float64)
+        assert At.shape == (E, dim, dim)
+        K_loc = (kap * vol)[:, None, None] * np.einsum("eid,edf,ejf->eij", G, At, G)
     ref_mass = (np.ones((dim + 1, dim + 1)) + np.eye(dim + 1)) / ((dim + 1) * (dim + 2))
     M_loc = vol[:, None, None] * ref_mass[None]
     if potential is not None:
@@ -142,3 +151,17 @@ def quadratic_potential(centre) -> Callable[[np.ndarray], np.ndarray]:
     """V(x) = |x - c|^2 (the confining potential of the uneven batch)."""
     c = np.asarray(centre, dtype=np.float64)
     return lambda x: np.sum((x - c[None, :]) ** 2, axis=1)
+
+
+def example2_tensor(x: np.ndarray) -> np.ndarray:
+    """The diffusion tensor of the second example (Section 5.2):
+    A(x) = I + (x - 1/2)(x - 1/2)^T, for points x (E, 3)."""
+    y = x - 0.5
+    return np.eye(x.shape[1])[None] + y[:, :, None] * y[:, None, :]
+
+
+def example2_potential(x: np.ndarray) -> np.ndarray:
+    """The zeroth-order coefficient of the second example:
+    phi(x) = exp((x1 - 1/2)(x2 - 1/2)(x3 - 1/2))."""
+    return np.exp(np.prod(x - 0.5, axis=1))
+

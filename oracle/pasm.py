@@ -73,9 +73,14 @@ class Problem:
     MH: np.ndarray            # Galerkin P^T M P (dense)
 
 
-def make_problem(dim: int, n_coarse: int, n_fine: int, kappa=None, centre=None) -> Problem:
-    pot = None if centre is None else quadratic_potential(centre)
-    A, M = assemble(dim, n_fine, kappa=kappa, potential=pot)
+def make_problem(dim: int, n_coarse: int, n_fine: int, kappa=None, centre=None, tensor=None,
+                 potential=None) -> Problem:
+    """The discrete problem on the fine mesh with its coarse space: centre
+    gives the potential |x - c|^2; tensor / potential are callables of the
+    centroids (the second example of Section 5: fem.example2_tensor,
+    fem.example2_potential)."""
+    pot = potential if potential is not None else (None if centre is None else quadratic_potential(centre))
+    A, M = assemble(dim, n_fine, kappa=kappa, potential=pot, tensor=tensor)
     P = prolongation(dim, n_coarse, n_fine)
     AH = galerkin(P, A).toarray()
     MH = galerkin(P, M).toarray()

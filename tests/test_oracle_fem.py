@@ -200,3 +200,61 @@ def test_stencil_built_stiffness_3d_equals_assembly():
         A, _ = fem.assemble(3, n)
         B = constant_stiffness_3d(n)
         assert abs(A - B).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# the full diffusion tensor of the second example (Section 5.2)
+# ---------------------------------------------------------------------------
+def test_tensor_identity_equals_the_scalar_assembly():
+    A0, M0 = fem.assemble(3, 4)
+    A1, M1 = fem.assemble(3, 4, tensor=lambda x: np.repeat(np.eye(3)[None], x.shape[0], axis=0))
+    assert abs(A1 - A0).max() < 1e-14 and abs(M1 - M0).max() == 0.0
+
+
+def test_constant_tensor_integrates_linear_functions_exactly():
+    # a(u, v) = int grad u . C grad v = a^T C b over the unit cube for
+    # u = a.x, v = b.x (the centroid rule is exact for a constant tensor)
+    C = np.array([[2.0, 0.3, -0.2], [0.3, 1.5, 0.4], [-0.2, 0.4, 1.2]])
+    A, _ = fem.assemble(3, 3, full=True, tensor=lambda x: np.repeat(C[None], x.shape[0], axis=0))
+    x = fem.all_node_coords(3, 3).astype(np.float64) / 3
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        a, b = rng.standard_normal(3), rng.standard_normal(3)
+        assert (x @ a) @ (A @ (x @ b)) == pytest.approx(a @ C @ b, rel=1e-12)
+
+
+def test_example2_operator_is_a_symmetric_15_point_stencil():
+    n = 6
+    A, M = fem.assemble(3, n, tensor=fem.example2_tensor, potential=fem.example2_potential)
+    assert abs(A - A.T).max() < 1e-15
+    assert np.min(np.linalg.eigvalsh(A.toarray())) > 0.0
+    # couplings only along the Kuhn edges +-(1,0,0) .. +-(1,1,1)
+    m = n - 1
+    allowed = {0}
+    for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]:
+        d = o[0] + o[1] * m + o[2] * m * m
+        allowed |= {d, -d}
+    Ac = A.tocoo()
+    offs = set((Ac.col - Ac.row).tolist())
+    assert offs <= allowed
+    # the off-axis couplings are really there (the identity tensor has none)
+    assert any(abs(A[i, i + 1 + m]) > 1e-12 for i in range(10))
+    # phi = exp(prod(x - 1/2)) enters as phi M at element centroids: with the
+    # identity tensor the difference to the Laplacian is that mass term
+    A2, _ = fem.assemble(3, n, potential=fem.example2_potential)
+    A3, _ = fem.assemble(3, n)
+    D = (A2 - A3).toarray()
+    assert np.min(np.linalg.eigvalsh(D)) > 0.0
+
+
+def test_example2_galerkin_levels_stay_15_point():
+    from oracle.transfer import galerkin, prolongation
+    A, _ = fem.assemble(3, 8, tensor=fem.example2_tensor, potential=fem.example2_potential)
+    Ac = galerkin(prolongation(3, 4, 8), A).tocoo()
+    m = 3
+    allowed = {0}
+    for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]:
+        d = o[0] + o[1] * m + o[2] * m * m
+        allowed |= {d, -d}
+    big = np.abs(Ac.data) > 1e-14 * np.abs(Ac.data).max()
+    assert set((Ac.col - Ac.row)[big].tolist()) <= allowed

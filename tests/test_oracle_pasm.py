@@ -151,3 +151,15 @@ def test_paper_multigrid_step_reaches_the_same_fixed_points(small2d):
     w, _ = pasm.discrete_eigenpairs(prob.A, prob.M, 4)
     r = pasm.solve(prob, 4, pasm.MultigridBVP(prob, MGOptions("cg", 2, 2, vcycles=1)), tol=1e-13)
     assert np.max(np.abs(r["lam"] - w) / w) < 1e-11
+
+
+def test_example2_operator_solve_reaches_discrete_eigenpairs():
+    # the second example of Section 5 (full tensor and potential, 3D) at a
+    # small size: Algorithm 2 with the paper's multigrid step reaches the
+    # discrete eigenpairs of its pencil
+    from oracle import fem
+    from oracle.multigrid import MGOptions
+    prob = pasm.make_problem(3, 4, 16, tensor=fem.example2_tensor, potential=fem.example2_potential)
+    w, _ = pasm.discrete_eigenpairs(prob.A, prob.M, 1)
+    r = pasm.solve(prob, 1, pasm.MultigridBVP(prob, MGOptions("cg", 2, 2, vcycles=1)), tol=1e-13)
+    assert abs(r["lam"][0] - w[0]) / w[0] < 1e-11

@@ -178,3 +178,39 @@ def batch_member_at(n_fine: int, count: int = 16, seed: int = 0):
             return pos, inst
     raise ValueError(f"no member with {n_fine} cells")
 
+
+def kuhn_centroids(dim: int, n: int) -> np.ndarray:
+    """Element centroids (E, dim) of the Kuhn mesh with n cells per side, in
+    element order (cell x-fastest, then the simplex of permutation p in
+    itertools order, vertices o, o + e[p0], o + e[p0] + e[p1], ...)."""
+    import itertools
+    h = 1.0 / n
+    perms = list(itertools.permutations(range(dim)))
+    cells = np.arange(n ** dim)
+    origin = np.stack([(cells // n ** a) % n for a in range(dim)], axis=1).astype(np.float64)
+    out = np.empty((n ** dim, len(perms), dim))
+    for p, perm in enumerate(perms):
+        # mean of the d+1 path vertices: o + sum_m (d - m) e[perm[m]] / (d + 1)
+        off = np.zeros(dim)
+        for m, axis in enumerate(perm):
+            off[axis] += (dim - m) / (dim + 1.0)
+        out[:, p, :] = origin + off[None, :]
+    return (out * h).reshape(-1, dim)
+
+
+def example2_elements(n: int):
+    """Per-element inputs of the second example of Section 5 on the 3D Kuhn mesh
+    with n cells per side, at element centroids, in element order: the
+    diffusion tensor A = I + (x - 1/2)(x - 1/2)^T as 6 values per element
+    (a11 a22 a33 a12 a13 a23), and phi = exp((x1 - 1/2)(x2 - 1/2)(x3 - 1/2))."""
+    x = kuhn_centroids(3, n) - 0.5
+    ten = np.empty((x.shape[0], 6))
+    ten[:, 0] = 1.0 + x[:, 0] ** 2
+    ten[:, 1] = 1.0 + x[:, 1] ** 2
+    ten[:, 2] = 1.0 + x[:, 2] ** 2
+    ten[:, 3] = x[:, 0] * x[:, 1]
+    ten[:, 4] = x[:, 0] * x[:, 2]
+    ten[:, 5] = x[:, 1] * x[:, 2]
+    phi = np.exp(x[:, 0] * x[:, 1] * x[:, 2])
+    return ten, phi
+
