@@ -96,14 +96,21 @@ typedef struct pasm_domain {
     int dim;
 } pasm_domain;
 
-/* Coefficients of -div(kappa grad u) + V u, constant per fine element
+/* Coefficients of -div(kappa A grad u) + V u, constant per fine element
  * (element order above).  NULL kappa means kappa = 1, NULL potential means
- * V = 0.  kappa must be finite and positive, potential finite and >= 0.
- * Variable coefficients are supported in 2D. */
+ * V = 0, NULL tensor means A = I.  kappa must be finite and positive,
+ * potential finite and >= 0, every tensor symmetric positive definite.
+ * 2D: kappa and potential.  3D: kappa, potential and the full tensor (the
+ * operator of the second example of Section 5 is A = I + (x - 1/2)(x - 1/2)^T,
+ * V = exp(prod_i (x_i - 1/2)), taken at element centroids); any of them makes
+ * every level a 15-point operator (Galerkin coarse levels), smoothed with
+ * unfused Jacobi / Chebyshev / CG sweeps. */
 typedef struct pasm_coefficients {
     const double* kappa;       /* n_elements values or NULL */
     const double* potential;   /* n_elements values of V at the element centroid, or NULL */
-    size_t n_elements;         /* (1/h)^dim * dim! when either array is given */
+    size_t n_elements;         /* (1/h)^dim * dim! when any array is given */
+    const double* tensor;      /* 3D: 6 * n_elements values (a11 a22 a33 a12 a13 a23 per
+                                  element, the diffusion tensor at its centroid), or NULL */
 } pasm_coefficients;
 
 typedef struct pasm_options {

@@ -36,7 +36,8 @@ class pasm_domain(ctypes.Structure):
 class pasm_coefficients(ctypes.Structure):
     _fields_ = [("kappa", ctypes.POINTER(ctypes.c_double)),
                 ("potential", ctypes.POINTER(ctypes.c_double)),
-                ("n_elements", ctypes.c_size_t)]
+                ("n_elements", ctypes.c_size_t),
+                ("tensor", ctypes.POINTER(ctypes.c_double))]
 
 
 class pasm_instance(ctypes.Structure):
@@ -178,7 +179,7 @@ def pasm_default_options() -> pasm_options:
 
 def pasm_setup(dim: int, H: float, h: float, k: int, kappa: Optional[np.ndarray] = None,
                potential: Optional[np.ndarray] = None, options: Optional[pasm_options] = None,
-               stream=None):
+               stream=None, tensor: Optional[np.ndarray] = None):
     """Create a context; returns the opaque handle (ctypes.c_void_p)."""
     L = lib()
     dom = pasm_domain(dim)
@@ -195,6 +196,11 @@ def pasm_setup(dim: int, H: float, h: float, k: int, kappa: Optional[np.ndarray]
         keep.append(pot)
         coef.potential = _dptr(pot)
         n_el = pot.size
+    if tensor is not None:
+        ten = np.ascontiguousarray(tensor, dtype=np.float64).reshape(-1)
+        keep.append(ten)
+        coef.tensor = _dptr(ten)
+        n_el = ten.size // 6
     coef.n_elements = n_el
     opt = options if options is not None else pasm_default_options()
     if stream is not None:
@@ -338,9 +344,9 @@ def options_for(workload) -> pasm_options:
 class Solver:
     """Owning wrapper around a context."""
 
-    def __init__(self, dim, H, h, k, kappa=None, potential=None, opts=None, stream=None):
+    def __init__(self, dim, H, h, k, kappa=None, potential=None, opts=None, stream=None, tensor=None):
         self.k = k
-        self.ctx = pasm_setup(dim, H, h, k, kappa, potential, opts, stream)
+        self.ctx = pasm_setup(dim, H, h, k, kappa, potential, opts, stream, tensor)
 
     def iterate(self) -> bool:
         return pasm_iterate(self.ctx)

@@ -50,6 +50,9 @@ struct Level {
     Grid g;
     bool const_coef = true;
     bool general = false;  // general 7-point stencil (potential term present)
+    bool general3 = false; // 3D general 15-point stencil (tensor, kappa or potential)
+    double* s64 = nullptr; // its 8 planes (FP64), and FP32 copies for mixed cycles
+    float* s32 = nullptr;
     double w0 = 1.0;
     double rho = 2.0;
     // coefficient arrays: 0 wx, 1 wy, 2 wz, 3 diagonal, 4 north-east weight
@@ -110,6 +113,7 @@ struct pasm_ctx {
     // and the per-element kappa of those levels (host, when kappa is given)
     std::vector<pasm_ctx*> nested;
     std::vector<std::vector<double>> level_kappa;
+    std::vector<double> AH3;  // set-up only: the dense coarse operator of a 3D general problem
     bool general_coef = false;    // a potential term: the nested levels are not rediscretisations
     bool coarse_shared = false;   // theta, Q, A_H^{-1}, groups belong to another context
     double* zeros = nullptr;      // k zeros: the combination weights of a restart
@@ -183,6 +187,11 @@ template <>
 Coef<double> pasm_ctx::coef<double>(int l) const {
     Coef<double> c;
     const auto& L = lv[l];
+    if (L.general3) {
+        c.s15 = L.s64;
+        c.w0 = L.w0;
+        return c;
+    }
     if (!L.const_coef) {
         c.wx = L.w64[0];
         c.wy = L.w64[1];
@@ -199,6 +208,11 @@ template <>
 Coef<float> pasm_ctx::coef<float>(int l) const {
     Coef<float> c;
     const auto& L = lv[l];
+    if (L.general3) {
+        c.s15 = L.s32;
+        c.w0 = (float)L.w0;
+        return c;
+    }
     if (!L.const_coef) {
         c.wx = L.w32[0];
         c.wy = L.w32[1];
@@ -292,7 +306,8 @@ void smooth(pasm_ctx* c, int l, T*& x, T*& y, const T* f, const std::vector<Cheb
         return;
     }
     const double nodes = (double)L.g.interior();
-    const double coef_bytes = L.const_coef ? 0.0 : (double)(L.general ? 4 : L.g.dim) * sizeof(T) * nodes;
+    const double coef_bytes =
+        L.const_coef ? 0.0 : (double)(L.general3 ? 8 : (L.general ? 4 : L.g.dim)) * sizeof(T) * nodes;
     // tallest fused tile whose LDS fits (general stencils need four coefficient tiles)
     int rows = 0;
     for (int r : {8, 4}) {
@@ -627,7 +642,7 @@ namespace {
 
 struct Plan {
     int dim, nH, nh, L, NH;
-    bool have_kappa, have_pot;
+    bool have_kappa, have_pot, have_tensor;
     size_t nel;
 };
 
@@ -669,13 +684,27 @@ Plan validate(const pasm_options& opt, const pasm_domain* dom, const pasm_coeffi
         throw Error(PASM_E_INVALID, "the learned smoother is for 3D problems with constant coefficients");
     p.have_kappa = coef && coef->kappa;
     p.have_pot = coef && coef->potential;
+    p.have_tensor = coef && coef->tensor;
+    if (p.have_tensor && (p.dim != 3 || opt.smoother == PASM_LEARNED))
+        throw Error(PASM_E_INVALID, "the diffusion tensor is supported in 3D (not with the learned smoother)");
     p.nel = 1;
     for (int a = 0; a < p.dim; ++a) p.nel *= (size_t)p.nh;
     p.nel *= (p.dim == 2 ? 2 : 6);
-    if (p.have_kappa || p.have_pot) {
-        if (p.dim != 2) throw Error(PASM_E_INVALID, "variable kappa and the potential term are supported in 2D");
+    if (p.have_kappa || p.have_pot || p.have_tensor) {
         if (coef->n_elements != p.nel) throw Error(PASM_E_INVALID, "n_elements does not match the fine mesh");
     }
+    if (p.have_tensor)
+        for (size_t e = 0; e < p.nel; ++e) {
+            const double* t = coef->tensor + 6 * e;
+            bool fin = true;
+            for (int q = 0; q < 6; ++q) fin = fin && std::isfinite(t[q]);
+            // symmetric positive definite: the leading minors
+            const double m1 = t[0], m2 = t[0] * t[1] - t[3] * t[3];
+            const double m3 = t[0] * (t[1] * t[2] - t[5] * t[5]) - t[3] * (t[3] * t[2] - t[5] * t[4]) +
+                              t[4] * (t[3] * t[5] - t[1] * t[4]);
+            if (!fin || !(m1 > 0.0) || !(m2 > 0.0) || !(m3 > 0.0))
+                throw Error(PASM_E_INVALID, "the diffusion tensor must be finite, symmetric positive definite");
+        }
     if (p.have_kappa)
         for (size_t e = 0; e < p.nel; ++e)
             if (!(coef->kappa[e] > 0.0) || !std::isfinite(coef->kappa[e]))
@@ -711,6 +740,11 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
     const bool general = pl.have_pot;
     if (general) pot.assign(coef->potential, coef->potential + nel);
     pasm::Stencil7 sten;   // general stencil of the level being built (host)
+    // 3D with any coefficient: the general 15-point operator on every level
+    const bool general3 = dim == 3 && (have_kappa || pl.have_pot || pl.have_tensor);
+    pasm::Stencil15 sten3;
+    std::vector<double> ten;
+    if (general3 && pl.have_tensor) ten.assign(coef->tensor, coef->tensor + 6 * nel);
     auto upload = [&](pasm::Level& Lv, int a, const std::vector<double>& w) {
         Lv.w64[a] = c->alloc<double>(Lv.g.plane);
         PASM_HIP(hipMemcpyAsync(Lv.w64[a], w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
@@ -725,10 +759,32 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
         pasm::Level& Lv = c->lv[l];
         const int n = nH << l;
         Lv.g = pasm::make_grid(dim, n);
-        Lv.const_coef = !have_kappa && !general;
-        Lv.general = general;
+        Lv.const_coef = !have_kappa && !general && !general3;
+        Lv.general = general && !general3;
+        Lv.general3 = general3;
         Lv.w0 = (dim == 2) ? 1.0 : Lv.g.h;
-        if (general) {
+        if (general3) {
+            // finest level assembled element by element, coarser ones Galerkin
+            sten3 = (l == L - 1) ? pasm::fine_stencil_3d(Lv.g, ten, kap, pot)
+                                 : pasm::galerkin_stencil_3d(c->lv[l + 1].g, sten3, Lv.g);
+            Lv.rho = pasm::gershgorin_3d(Lv.g, sten3);
+            const size_t P = Lv.g.plane;
+            Lv.s64 = c->alloc<double>(8 * P);
+            for (int a = 0; a < 8; ++a)
+                PASM_HIP(hipMemcpyAsync(Lv.s64 + a * P, sten3.a[a].data(), P * sizeof(double), hipMemcpyHostToDevice,
+                                        c->st));
+            PASM_HIP(hipStreamSynchronize(c->st));
+            if (c->mixed) {
+                Lv.s32 = c->alloc<float>(8 * P);
+                pasm::launch_d2f(Lv.s64, Lv.s32, (long)(8 * P), c->st);
+                PASM_CHECK_LAUNCH();
+            }
+            if (l == 0) {
+                std::vector<double> A3;
+                pasm::dense_from_stencil_3d(Lv.g, sten3, A3);
+                c->AH3.swap(A3);
+            }
+        } else if (general) {
             // finest level assembled with the potential, coarser ones Galerkin
             sten = (l == L - 1) ? pasm::fine_stencil_2d(Lv.g, kap, pot)
                                 : pasm::galerkin_stencil_2d(c->lv[l + 1].g, sten, Lv.g);
@@ -808,7 +864,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
         c->Y32 = c->alloc<float>(nf);
     }
     const int N = c->NH;
-    c->general_coef = general;
+    c->general_coef = general || general3;
     if (share) {
         c->coarse_shared = true;
         c->theta = share->theta;
@@ -855,7 +911,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
     const Grid& g0 = L0.g;
     std::vector<double> wx0, wy0, AHgen;
     if (L0.general) pasm::dense_from_stencil_2d(g0, sten, AHgen);
-    if (!L0.const_coef && !L0.general) {
+    if (!L0.const_coef && !L0.general && !L0.general3) {
         wx0.resize(g0.plane);
         wy0.resize(g0.plane);
         PASM_HIP(hipMemcpyAsync(wx0.data(), L0.w64[0], g0.plane * sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -919,6 +975,9 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
                 }
             }
     if (L0.general) AH.swap(AHgen);
+    if (L0.general3) AH.swap(c->AH3);
+    c->AH3.clear();
+    c->AH3.shrink_to_fit();
     double* dA = c->Qcm;
     double* dB = c->Ainv64;  // scratch for M_H during the factorisation
     PASM_HIP(hipMemcpyAsync(dA, AH.data(), AH.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
@@ -1058,7 +1117,7 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
     const double* bsrc = c->Y64;
     const double* csrc = c->R64;
     int lstart = c->L - 2;
-    if (c->L >= 2) {
+    if (c->L >= 2 && !c->lv[lf].general3) {
         pasm::Level& Lc = c->lv[c->L - 2];
         int nblk;
         if (c->e_pending) {

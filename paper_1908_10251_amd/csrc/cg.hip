@@ -65,6 +65,17 @@ __device__ inline T apply_op(const Grid& g, const Coef<T>& c, long id, V v) {
     } else {
         if (KIND == 0)
             return c.w0 * (T(6) * x0 - v(id + 1) - v(id - 1) - v(id + py) - v(id - py) - v(id + pz) - v(id - pz));
+        if (KIND == 3) {
+            // the 15-point operator: diagonal plane, then A(i, i + o) for the
+            // seven Kuhn edge directions o
+            const long P = g.plane;
+            const long o7[7] = {1, py, pz, 1 + py, 1 + pz, py + pz, 1 + py + pz};
+            T acc = c.s15[id] * x0;
+#pragma unroll
+            for (int t = 0; t < 7; ++t)
+                acc += c.s15[(t + 1) * P + id] * v(id + o7[t]) + c.s15[(t + 1) * P + id - o7[t]] * v(id - o7[t]);
+            return acc;
+        }
         const T w1 = c.wx[id], w2 = c.wx[id - 1], w3 = c.wy[id], w4 = c.wy[id - py], w5 = c.wz[id],
                 w6 = c.wz[id - pz];
         return w1 * (x0 - v(id + 1)) + w2 * (x0 - v(id - 1)) + w3 * (x0 - v(id + py)) + w4 * (x0 - v(id - py)) +
@@ -245,7 +256,8 @@ void cg_smooth(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int 
     } else {
         if (kind == 0) cg_run<T, 3, 0>(g, c, x, f, nrhs, steps, x_zero, w, st);
         else if (kind == 1) cg_run<T, 3, 1>(g, c, x, f, nrhs, steps, x_zero, w, st);
-        else throw Error(PASM_E_INVALID, "CG smoothing: no general 3D stencil");
+        else if (kind == 3) cg_run<T, 3, 3>(g, c, x, f, nrhs, steps, x_zero, w, st);
+        else throw Error(PASM_E_INVALID, "CG smoothing: unknown 3D operator");
     }
 }
 

@@ -70,16 +70,17 @@ struct Coef {
     const T* wz = nullptr;
     const T* d = nullptr;
     const T* wne = nullptr;
+    const T* s15 = nullptr;  // 3D general 15-point operator: 8 planes (diagonal, then the entries towards +O_t)
     T w0 = T(1);
     long ms = 0;
     int kpm = 1;
     const T* bsc = nullptr;
 };
 
-// 0: constant, 1: edge weights, 2: general 7-point
+// 0: constant, 1: edge weights, 2: general 7-point (2D), 3: general 15-point (3D)
 template <typename T>
 inline int coef_kind(const Coef<T>& c) {
-    return c.d ? 2 : (c.wx ? 1 : 0);
+    return c.s15 ? 3 : (c.d ? 2 : (c.wx ? 1 : 0));
 }
 
 #define PASM_HIP(call)                                                              \
@@ -323,6 +324,33 @@ Stencil7 fine_stencil_2d(const Grid& g, const std::vector<double>& kap, const st
 Stencil7 galerkin_stencil_2d(const Grid& gf, const Stencil7& sf, const Grid& gc);
 double gershgorin_2d(const Grid& g, const Stencil7& s);
 void dense_from_stencil_2d(const Grid& g, const Stencil7& s, std::vector<double>& A);
+
+// 3D general operators (full diffusion tensor and potential per element,
+// Kuhn mesh): 15-point stencils, 8 planes a[0] (diagonal), a[t] = A(i, i + O_t).
+struct Stencil15 {
+    std::vector<double> a[8];
+};
+// tensor: 6 values per element (a11 a22 a33 a12 a13 a23) or empty (identity);
+// kap: per element factor or empty; pot: V per element or empty
+Stencil15 fine_stencil_3d(const Grid& g, const std::vector<double>& tensor, const std::vector<double>& kap,
+                          const std::vector<double>& pot);
+Stencil15 galerkin_stencil_3d(const Grid& gf, const Stencil15& sf, const Grid& gc);
+double gershgorin_3d(const Grid& g, const Stencil15& s);
+void dense_from_stencil_3d(const Grid& g, const Stencil15& s, std::vector<double>& A);
+template <typename T>
+void launch_smooth3g(const Grid& g, const T* s15, const T* xc, const T* xp, const T* f, T* xn, int nrhs,
+                     long stride, Cheb s, int zmode, hipStream_t st);
+template <typename T>
+void launch_apply3g(const Grid& g, const T* s15, const T* x, T* y, int nrhs, long stride, hipStream_t st);
+template <typename T>
+void launch_resid_restrict3g(const Grid& gf, const T* s15, const T* x, const T* f, const Grid& gc, T* rc, int nrhs,
+                             long sf, long sc, hipStream_t st);
+void launch_resid_cast3g(const Grid& g, const double* s15, const double* u, const double* f, float* r, int nrhs,
+                         long stride, hipStream_t st);
+void launch_add_resid3g(const Grid& g, const double* s15, const double* u, const float* e, const double* f,
+                        double* un, float* r, int nrhs, long stride, hipStream_t st);
+int launch_border3g(const Grid& g, const double* s15, const double* u, double* au, double* mu, double* partial,
+                    int nrhs, long stride, hipStream_t st);
 
 // Chebyshev steps of degree s on [rho/alpha, rho]; damped Jacobi steps.
 std::vector<Cheb> cheb_steps(double rho, double alpha, int s);

@@ -456,6 +456,7 @@ __global__ void k_unpack3(Grid g, const double* __restrict__ compact, long ld, T
 template <typename T>
 void launch_smooth3(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, const T* f, T* xn, int nrhs,
                     long stride, Cheb s, int zmode, hipStream_t st) {
+    if (c.s15) return launch_smooth3g<T>(g, c.s15, xc, xp, f, xn, nrhs, stride, s, zmode, st);
     if (c.wx)
         hipLaunchKernelGGL((k_smooth3<T, false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, xc, xp, f, xn,
                            stride, (T)s.a, (T)s.b, zmode);
@@ -467,6 +468,7 @@ void launch_smooth3(const Grid& g, const Coef<T>& c, const T* xc, const T* xp, c
 
 template <typename T>
 void launch_apply_A3(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride, hipStream_t st) {
+    if (c.s15) return launch_apply3g<T>(g, c.s15, x, y, nrhs, stride, st);
     if (c.wx)
         hipLaunchKernelGGL((k_apply_A3<T, false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, x, y, stride);
     else
@@ -477,6 +479,7 @@ void launch_apply_A3(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs
 template <typename T>
 void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const T* f, const Grid& gc, T* rc,
                             int nrhs, long sf, long sc, hipStream_t st) {
+    if (c.s15) return launch_resid_restrict3g<T>(gf, c.s15, x, f, gc, rc, nrhs, sf, sc, st);
     if (gc.n * 2 == gf.n) {  // the tiled form (ratio 2, which every hierarchy here has)
         const int zb = (gc.m + RCZ - 1) / RCZ;
         dim3 grid((gc.m + RCX - 1) / RCX, (gc.m + RCY - 1) / RCY, zb * nrhs);
@@ -501,6 +504,7 @@ void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const 
 int launch_border_restrict3(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
                             double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st) {
     if (g.dim != 3 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 3D, ratio 2");
+    if (c.s15) throw Error(PASM_E_INVALID, "fused border restriction: no general 3D operator");
     // coarse nodes up to nc (not only the interior ones) own fine nodes for the sums
     const int zb = (gc.n + RCZ - 1) / RCZ;
     dim3 grid((gc.n + RCX - 1) / RCX, (gc.n + RCY - 1) / RCY, zb * nrhs);
@@ -546,6 +550,7 @@ void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double*
 
 void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
                         int nrhs, long stride, hipStream_t st) {
+    if (c.s15) return launch_resid_cast3g(g, c.s15, u, f, r, nrhs, stride, st);
     if (c.wx)
         hipLaunchKernelGGL(k_resid_cast3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
     else
@@ -556,6 +561,7 @@ void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, c
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                        double* un, float* r, int nrhs, long stride, hipStream_t st) {
     if (g.dim != 3 || un == u) throw Error(PASM_E_INVALID, "add and residual: 3D, separate output");
+    if (c.s15) return launch_add_resid3g(g, c.s15, u, e, f, un, r, nrhs, stride, st);
     if (c.wx)
         hipLaunchKernelGGL(k_add_resid3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride);
     else
@@ -565,6 +571,7 @@ void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, co
 
 int launch_border3(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
                    double* partial, int nrhs, long stride, hipStream_t st) {
+    if (c.s15) return launch_border3g(g, c.s15, u, au, mu, partial, nrhs, stride, st);
     dim3 grid = grid3(g.m, nrhs);
     if (c.wx)
         hipLaunchKernelGGL(k_border3<false>, grid, dim3(BX, BY), 0, st, g, c, u, au, mu, partial, stride);
