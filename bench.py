@@ -129,9 +129,13 @@ def cpu_baseline_steps(wl: W.Workload, kap):
     """The oracle (as it stands) on a bounded sample: one correction step
     (its own FP64 V-cycles) of the first c eigenpairs (c = host cores) in c
     worker processes, from the coarse start; time of that step."""
-    from oracle import pasm as O
+    from oracle import fem, pasm as O
     t0 = time.perf_counter()
-    prob = O.make_problem(wl.dim, wl.n_coarse, wl.n_fine, kappa=kap)
+    if wl.tensor == "example2":
+        prob = O.make_problem(wl.dim, wl.n_coarse, wl.n_fine, tensor=fem.example2_tensor,
+                              potential=fem.example2_potential)
+    else:
+        prob = O.make_problem(wl.dim, wl.n_coarse, wl.n_fine, kappa=kap)
     bvp = O.MultigridBVP(prob, O.mg_options_for(wl))
     lam0, U0, _, _ = O.coarse_start(prob, wl.k)
     t_setup = time.perf_counter() - t0
@@ -166,18 +170,21 @@ def line(wl, metric, value, unit, steps, warmup, ms_per_step, config, roof, dtyp
 
 
 def coefficients(wl: W.Workload):
-    """Per-element inputs of a single-instance workload."""
+    """Per-element inputs of a single-instance workload: kappa, potential, tensor."""
     kap = W.lognormal_kappa(wl.dim, wl.n_fine, seed=wl.seed) if wl.kappa == "lognormal" else None
-    return kap, None
+    if wl.tensor == "example2":
+        ten, phi = W.example2_elements(wl.n_fine)
+        return kap, phi, ten
+    return kap, None, None
 
 
 def bench_solve(args, wl, pasm, torch):
     """A step = one whole solve to 1e-8 relative eigenvalue error."""
     opts = pasm.options_for(wl)
     opts.max_iter = args.max_iter
-    kap, pot = coefficients(wl)
+    kap, pot, ten = coefficients(wl)
     t0 = time.perf_counter()
-    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts)
+    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts, tensor=ten)
     t_setup = time.perf_counter() - t0
     ctx, k = solver.ctx, wl.k
     learned = wl.smoother == "learned"
@@ -295,9 +302,9 @@ def bench_solve(args, wl, pasm, torch):
 def bench_steps(args, wl, pasm, torch):
     """Rough-coefficient single instance: correction steps per second."""
     opts = pasm.options_for(wl)
-    kap, pot = coefficients(wl)
+    kap, pot, ten = coefficients(wl)
     t0 = time.perf_counter()
-    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts)
+    solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts, tensor=ten)
     t_setup = time.perf_counter() - t0
     ctx, k = solver.ctx, wl.k
     for _ in range(args.warmup):
@@ -317,16 +324,22 @@ def bench_steps(args, wl, pasm, torch):
     ms_per_step = 1e3 * elapsed / args.iters
     cfg = {"dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": pasm.pasm_num_dofs(ctx),
            "smoother": wl.smoother, "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles, "precision": wl.precision,
-           "kappa": "log-normal, sigma 1, i.i.d. per fine element", "iterations": args.iters,
+           "coefficients": ("A = I + (x-1/2)(x-1/2)^T, phi = exp(prod(x_i - 1/2)) at element centroids (the "
+                            "second example of Section 5)" if wl.tensor == "example2"
+                            else "kappa log-normal, sigma 1, i.i.d. per fine element"), "iterations": args.iters,
            "eigenpairs_with_last_change_below_1e-10": int(np.sum(d[-1] < 1e-10)), "setup_s": t_setup,
            "step": "one outer iteration (one correction step for all k eigenpairs)"}
-    kname = KERNEL_NAMES["kappa"] if wl.precision == "mixed" else KERNEL_NAMES[2]
+    kname = (KERNEL_NAMES["cg"] if wl.smoother == "cg"
+             else KERNEL_NAMES["kappa"] if wl.precision == "mixed" else KERNEL_NAMES[2])
     roof = roofline(launches, ms, bpl, wl.name, kname)
     solver.close()
     out = line(wl, "eigenpair correction steps/sec", k / (ms_per_step / 1e3), "eigenpair-steps/s", args.iters,
                args.warmup, ms_per_step, cfg, roof, "f32+f64" if wl.precision == "mixed" else "f64")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_steps(wl, kap)
+    if wl.tensor == "example2":
+        # eigenpairs whose last step changed the eigenvalue by less than 1e-8
+        out["config"]["eigenpairs_with_last_change_below_1e-8"] = int(np.sum(d[-1] < 1e-8))
     return out
 
 
@@ -423,7 +436,7 @@ def main():
     torch.cuda.set_device(0)
     if wl is W.BATCH2D_UNEVEN:
         out = bench_batch(args, wl, pasm, torch)
-    elif wl.kappa != "one":
+    elif wl.kappa != "one" or wl.tensor != "none":
         out = bench_steps(args, wl, pasm, torch)
     else:
         out = bench_solve(args, wl, pasm, torch)

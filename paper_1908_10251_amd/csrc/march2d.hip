@@ -527,7 +527,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             um += __shfl_xor(um, o, 64);
         }
         if (lane == 0) {
-            const long b = (long)z * (sh.strips * sh.segs) + (work % (sh.strips * sh.segs));
+            const long b = (long)z * (sh.strips * sh.segs) + (long)band * sh.strips + strip;
             part[2 * b] = ua;
             part[2 * b + 1] = um;
         }

@@ -406,17 +406,34 @@ __global__ __launch_bounds__(BX* BY) void k_mass_rhs(Grid g, const double* __res
     f[off + id] = l * mass2(g, u + off, id);
 }
 
-template <int KIND, typename TO>
+// RB right-hand sides per workgroup (edge weights of a single problem: the
+// weights are loaded once for all of them; RB = 1 for batches, whose members
+// have planes of their own).
+template <int KIND, typename TO, int RB = 1>
 __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, const double* __restrict__ u,
                                                        const double* __restrict__ f,
-                                                       TO* __restrict__ r, long stride, long rstride) {
+                                                       TO* __restrict__ r, long stride, long rstride, int nrhs) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
+    const long id = g.idx(i, j);
+    if (RB > 1 && KIND == 1) {
+        const double we = cg.wx[id], ww = cg.wx[id - 1], wn = cg.wy[id], ws = cg.wy[id - g.pitch];
+        const double D = we + ww + wn + ws;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int z = blockIdx.z * RB + q;
+            if (z >= nrhs) break;
+            const double* ur = u + (long)z * stride;
+            const double Ax = D * ur[id] - we * ur[id + 1] - ww * ur[id - 1] - wn * ur[id + g.pitch] -
+                              ws * ur[id - g.pitch];
+            r[(long)z * rstride + id] = (TO)(f[(long)z * stride + id] - Ax);
+        }
+        return;
+    }
     double bs;
     const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const long off = (long)blockIdx.z * stride;
-    const long id = g.idx(i, j);
     double Ax, D;
     Stiff2<double, KIND>::apply(g, c, u + off, id, Ax, D);
     r[(long)blockIdx.z * rstride + id] = (TO)(f[off + id] - Ax);
@@ -426,27 +443,37 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
 // coefficients, 1 edge weights): un = u + e on every interior node and
 // r = f - A un (FP64, rounded to FP32) for the next cycle; un at the
 // neighbours is formed again from u and e.  un must not alias u.
-template <int KIND>
+template <int KIND, int RB = 1>
 __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, const double* __restrict__ u,
                                                       const float* __restrict__ e, const double* __restrict__ f,
-                                                      double* __restrict__ un, float* __restrict__ r, long stride) {
+                                                      double* __restrict__ un, float* __restrict__ r, long stride,
+                                                      int nrhs) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
-    const long off = (long)blockIdx.z * stride;
     const long gid = g.idx(i, j);
-    const long id = off + gid;
-    auto v = [&](long q) { return u[q] + (double)e[q]; };
-    const double x0 = v(id);
-    double Ax;
-    if (KIND == 0) {
-        Ax = c.w0 * (4.0 * x0 - (v(id + 1) + v(id - 1) + v(id + g.pitch) + v(id - g.pitch)));
-    } else {
-        const double we = c.wx[gid], ww = c.wx[gid - 1], wn = c.wy[gid], ws = c.wy[gid - g.pitch];
-        Ax = (we + ww + wn + ws) * x0 - we * v(id + 1) - ww * v(id - 1) - wn * v(id + g.pitch) - ws * v(id - g.pitch);
+    double we = 0.0, ww = 0.0, wn = 0.0, ws = 0.0;
+    if (KIND == 1) {
+        // loaded once for the workgroup's RB right-hand sides
+        we = c.wx[gid], ww = c.wx[gid - 1], wn = c.wy[gid], ws = c.wy[gid - g.pitch];
     }
-    un[id] = x0;
-    r[id] = (float)(f[id] - Ax);
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int z = blockIdx.z * RB + q;
+        if (z >= nrhs) break;
+        const long id = (long)z * stride + gid;
+        auto v = [&](long p) { return u[p] + (double)e[p]; };
+        const double x0 = v(id);
+        double Ax;
+        if (KIND == 0) {
+            Ax = c.w0 * (4.0 * x0 - (v(id + 1) + v(id - 1) + v(id + g.pitch) + v(id - g.pitch)));
+        } else {
+            Ax = (we + ww + wn + ws) * x0 - we * v(id + 1) - ww * v(id - 1) - wn * v(id + g.pitch) -
+                 ws * v(id - g.pitch);
+        }
+        un[id] = x0;
+        r[id] = (float)(f[id] - Ax);
+    }
 }
 
 template <typename TE>
@@ -567,23 +594,45 @@ constexpr int BUX = BFX + 2, BUY = BFY + 2;          // fine nodes of u (halo 1)
 // ADD: u is the V-cycles' iterate before its last correction; the tile
 // holds u + ecor (the FP32 correction, added in FP64) and the owned nodes of
 // the corrected field are written to un (which must not alias u).
-template <int KIND, bool ADD = false>
+// ZF (single problems with edge weights): a 1D grid whose consecutive
+// pieces of work are the right-hand sides of one tile, on one die (workgroup
+// w runs on die w % 8), so the tile's weights are read from HBM once;
+// otherwise tile (x, y) and right-hand side z from the 3D grid.
+struct BorderWork {
+    int ntx, nty, nrhs;  // tiles per direction and right-hand sides (ZF)
+};
+template <int KIND, bool ADD = false, bool ZF = false>
 __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> cg, const double* __restrict__ u,
                                                           Grid gc, double* __restrict__ bc,
                                                           double* __restrict__ cc, double* __restrict__ partial,
                                                           long stride, long sc, const float* __restrict__ ecor,
-                                                          double* __restrict__ un) {
+                                                          double* __restrict__ un, BorderWork bw) {
+    int bx, by, bz, nbx, nby;
+    if (ZF) {
+        const int total = bw.ntx * bw.nty * bw.nrhs;
+        const int per = gridDim.x / 8;
+        const int work = (blockIdx.x % 8) * per + blockIdx.x / 8;
+        if (work >= total) return;  // uniform per workgroup
+        bz = work % bw.nrhs;
+        bx = (work / bw.nrhs) % bw.ntx;
+        by = work / (bw.nrhs * bw.ntx);
+        nbx = bw.ntx;
+        nby = bw.nty;
+    } else {
+        bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+        nbx = gridDim.x, nby = gridDim.y;
+    }
     __shared__ double us[BUY][BUX];
     __shared__ double as[BFY][BFX];
     __shared__ double ms[BFY][BFX];
     __shared__ double sh[8];
     const int tid = threadIdx.x;
-    const int I0 = blockIdx.x * BRX + 1, J0 = blockIdx.y * BRY + 1;  // first coarse node
+    const int I0 = bx * BRX + 1, J0 = by * BRY + 1;  // first coarse node
     const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;                    // first fine node with A u
     double bs;
-    const Coef<double> c = member_coef(cg, blockIdx.z, bs);
-    const double* ur = u + (long)blockIdx.z * stride;
-    const float* er = ADD ? ecor + (long)blockIdx.z * stride : nullptr;
+    const Coef<double> c = member_coef(cg, bz, bs);
+    const double* ur = u + (long)bz * stride;
+    const float* er = ADD ? ecor + (long)bz * stride : nullptr;
     {
         // all of a thread's loads are issued before any of them is used
         constexpr int NPT = (BUX * BUY + 255) / 256;
@@ -631,7 +680,7 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
             if (a < 2 * BRX && b < 2 * BRY) {  // owned
                 ua += x0 * Ax;
                 um += x0 * Mx;
-                if (ADD) un[(long)blockIdx.z * stride + g.idx(i, j)] = x0;
+                if (ADD) un[(long)bz * stride + g.idx(i, j)] = x0;
             }
         }
         as[b][a] = Ax;
@@ -647,7 +696,7 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
                                                 as[b + 1][a] + as[b + 1][a + 1]);
             const double rc = ms[b][a] + 0.5 * (ms[b][a - 1] + ms[b - 1][a] + ms[b - 1][a - 1] + ms[b][a + 1] +
                                                 ms[b + 1][a] + ms[b + 1][a + 1]);
-            const long cid = (long)blockIdx.z * sc + gc.idx(I, J);
+            const long cid = (long)bz * sc + gc.idx(I, J);
             bc[cid] = rb;
             cc[cid] = rc;
         }
@@ -662,8 +711,8 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
     }
     __syncthreads();
     if (tid == 0) {
-        const long nblk = (long)gridDim.x * gridDim.y;
-        const long blk = (long)blockIdx.z * nblk + blockIdx.y * gridDim.x + blockIdx.x;
+        const long nblk = (long)nbx * nby;
+        const long blk = (long)bz * nblk + (long)by * nbx + bx;
         partial[2 * blk] = sh[0] + sh[2] + sh[4] + sh[6];
         partial[2 * blk + 1] = sh[1] + sh[3] + sh[5] + sh[7];
     }
@@ -1013,10 +1062,19 @@ void launch_resid_to(const Grid& g, const Coef<double>& c, const double* u, cons
                      long stride, hipStream_t st) {
     if (g.dim == 3) throw Error(PASM_E_INVALID, "residual kernel: 2D only");
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    const bool single = c.kpm <= 1 && c.ms == 0;
     switch (coef_kind(c)) {
-        case 0: hipLaunchKernelGGL((k_resid_cast<0, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride); break;
-        case 1: hipLaunchKernelGGL((k_resid_cast<1, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride); break;
-        default: hipLaunchKernelGGL((k_resid_cast<2, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride); break;
+        case 0: hipLaunchKernelGGL((k_resid_cast<0, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs); break;
+        case 1:
+            if (single) {
+                constexpr int RB = 4;
+                const dim3 gr = grid_for(g.m, g.m, (nrhs + RB - 1) / RB);
+                hipLaunchKernelGGL((k_resid_cast<1, TO, RB>), gr, blk, 0, st, g, c, u, f, r, stride, stride, nrhs);
+            } else {
+                hipLaunchKernelGGL((k_resid_cast<1, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs);
+            }
+            break;
+        default: hipLaunchKernelGGL((k_resid_cast<2, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs); break;
     }
     PASM_CHECK_LAUNCH();
 }
@@ -1039,8 +1097,13 @@ void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, con
     if (!add_resid_supported(g, c) || un == u)
         throw Error(PASM_E_INVALID, "add and residual: 2D constant or edge-weight operator, separate output");
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (coef_kind(c) == 0) hipLaunchKernelGGL(k_add_resid<0>, grid, blk, 0, st, g, c, u, e, f, un, r, stride);
-    else hipLaunchKernelGGL(k_add_resid<1>, grid, blk, 0, st, g, c, u, e, f, un, r, stride);
+    if (coef_kind(c) == 0) {
+        hipLaunchKernelGGL((k_add_resid<0, 1>), grid, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs);
+    } else {
+        constexpr int RB = 4;
+        const dim3 gr = grid_for(g.m, g.m, (nrhs + RB - 1) / RB);
+        hipLaunchKernelGGL((k_add_resid<1, RB>), gr, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs);
+    }
     PASM_CHECK_LAUNCH();
 }
 
@@ -1068,10 +1131,19 @@ int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u
     dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
     const float* e0 = nullptr;
     double* u0 = nullptr;
+    const BorderWork bw{(int)grid.x, (int)grid.y, nrhs};
     switch (coef_kind(c)) {
-        case 0: hipLaunchKernelGGL(k_border_restrict_t<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0); break;
-        case 1: hipLaunchKernelGGL(k_border_restrict_t<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0); break;
-        default: hipLaunchKernelGGL(k_border_restrict_t<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0); break;
+        case 0: hipLaunchKernelGGL(k_border_restrict_t<0>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0, bw); break;
+        case 1:
+            if (c.kpm <= 1 && c.ms == 0) {
+                const int total = (int)(grid.x * grid.y) * nrhs;
+                hipLaunchKernelGGL((k_border_restrict_t<1, false, true>), dim3((total + 7) / 8 * 8), blk, 0, st, g, c, u,
+                                   gc, bc, cc, partial, stride, sc, e0, u0, bw);
+            } else {
+                hipLaunchKernelGGL(k_border_restrict_t<1>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0, bw);
+            }
+            break;
+        default: hipLaunchKernelGGL(k_border_restrict_t<2>, grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e0, u0, bw); break;
     }
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y);
@@ -1083,10 +1155,15 @@ int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const doubl
     if (g.dim != 2 || gc.n * 2 != g.n || un == u || coef_kind(c) == 2)
         throw Error(PASM_E_INVALID, "correction with borders: 2D, ratio 2, constant or edge weights, separate output");
     dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
-    if (coef_kind(c) == 0)
-        hipLaunchKernelGGL((k_border_restrict_t<0, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e, un);
-    else
-        hipLaunchKernelGGL((k_border_restrict_t<1, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e, un);
+    const BorderWork bw{(int)grid.x, (int)grid.y, nrhs};
+    if (coef_kind(c) == 0) {
+        hipLaunchKernelGGL((k_border_restrict_t<0, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride, sc, e, un,
+                           bw);
+    } else {
+        const int total = (int)(grid.x * grid.y) * nrhs;
+        hipLaunchKernelGGL((k_border_restrict_t<1, true, true>), dim3((total + 7) / 8 * 8), blk, 0, st, g, c, u, gc, bc, cc,
+                           partial, stride, sc, e, un, bw);
+    }
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y);
 }

@@ -45,6 +45,7 @@ class Workload:
     kappa: str = "one"  # "one" | "lognormal"
     potential: str = "none"  # "none" | "quadratic"
     seed: int = 0
+    tensor: str = "none"  # "none" | "example2" (A = I + (x-1/2)(x-1/2)^T with phi = exp(prod(x_i - 1/2)))
     golden: str = ""    # name of the workload whose stored discrete eigenvalues apply (default: own name)
 
     @property
@@ -100,8 +101,15 @@ LAP3D = Workload("lap3d-H8-h128-k100-mixed", 3, 1 / 8, 1 / 128, 100, "jacobi", 2
 LAP3D_LEARNED = Workload("lap3d-H8-h128-k100-learned", 3, 1 / 8, 1 / 128, 100, "learned", 2, 2, 2,
                          "mixed", 1e-10, golden="lap3d-H8-h128-k100-mixed")
 
+# The second example of Section 5: -div(A grad u) + phi u = lambda u on the cube,
+# A = I + (x - 1/2)(x - 1/2)^T, phi = exp(prod (x_i - 1/2)); the paper's H = 1/16,
+# 200 eigenpairs and multigrid step (one V-cycle, CG(2) pre- and post-smoothing),
+# with h = 1/128 (its n = 5 levels would reach h = 1/256)
+EX2_3D = Workload("ex2-3d-H16-h128-k200-cg", 3, 1 / 16, 1 / 128, 200, "cg", 2, 2, 1, "mixed", 1e-10,
+                  tensor="example2")
+
 ALL = [LAP2D_SMALL, LAP2D_LARGE, LAP2D_LARGE_H64, LAP2D_LARGE_MIXED, LAP2D_LARGE_CG, KAPPA2D_MIXED, BATCH2D_UNEVEN,
-       LAP3D, LAP3D_LEARNED]
+       LAP3D, LAP3D_LEARNED, EX2_3D]
 
 
 def n_elements(dim: int, n: int) -> int:
