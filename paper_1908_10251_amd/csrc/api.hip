@@ -494,6 +494,10 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
     if (zero_after_pre) {
         // x = 0: the residual is f, restricted
         pasm::launch_restrict<T>(L.g, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
+    } else if (L.general3) {
+        // 15-point operator: the residual into the free buffer y, then restricted
+        pasm::launch_resid3g<T>(L.g, c->coef<T>(l).s15, x, f, y, nrhs, L.g.plane, c->st);
+        pasm::launch_restrict<T>(L.g, y, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
     } else {
         pasm::launch_resid_restrict<T>(L.g, c->coef<T>(l), x, f, Lc.g, fc, nrhs, L.g.plane, Lc.g.plane, c->st);
     }
@@ -536,7 +540,7 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
         return;
     }
     if (defer_add) {
-        // the last cycle of a step (2D): x + e is formed by the border pass
+        // the last cycle of a step: x + e is formed by the border pass
         c->e_pending = true;
         return;
     }
@@ -575,8 +579,9 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
             c->border_next = border && cy == ncycles - 1 && !c->mixed;
-            const bool defer = border && cy == ncycles - 1 && c->mixed && c->dim == 2 &&
-                               pasm::coef_kind(c->coef<double>(c->L - 1)) <= 1;
+            const bool defer = cy == ncycles - 1 && c->mixed && eig &&
+                               ((border && c->dim == 2 && pasm::coef_kind(c->coef<double>(c->L - 1)) <= 1) ||
+                                c->lv[c->L - 1].general3);
             one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles, defer);
             c->border_next = false;
         }
@@ -1137,6 +1142,14 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
         bsrc = Lc.B;
         csrc = Lc.C;
         lstart = c->L - 3;
+    } else if (c->e_pending) {
+        // 15-point operator: u~ = x + e and A u~, M u~ in one pass; u~ goes to
+        // the buffer of f (formed again for the next step) and is swapped in
+        const int nblk = pasm::launch_border3g(g, c->coef<double>(lf).s15, c->U, c->Y64, c->R64, c->partial, k, sf,
+                                               c->st, c->E32, c->F64);
+        std::swap(c->U, c->F64);
+        c->e_pending = false;
+        pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);
     } else {
         const int nblk = pasm::launch_border(g, c->coef<double>(lf), c->U, c->Y64, c->R64, c->partial, k, sf, c->st);
         pasm::launch_reduce_pairs(c->partial, nblk, c->bz, k, c->st);

@@ -21,25 +21,32 @@ namespace {
 
 constexpr int CX = 64, CY = 4;  // one workgroup: 64 x 4 nodes of one (z-)plane
 
+// Kernels that apply the operator take RB right-hand sides per thread, so
+// that the coefficients of a node's row are read once for all of them; the
+// vector updates take one.
+template <int DIM, int KIND>
+constexpr int rhs_block() { return KIND == 0 ? 1 : 4; }
+
 struct NodeIdx {
     long id;    // padded index of the node in its plane / volume
-    int r;      // right-hand side
+    int r0;     // first right-hand side of the thread's group
     long blk;   // workgroup index within the right-hand side
     bool ok;    // an interior node
 };
 
-template <int DIM>
+// blockIdx.z: the right-hand side group (2D), or (plane, group) (3D)
+template <int DIM, int RB>
 __device__ inline NodeIdx node_of(const Grid& g) {
     NodeIdx n;
     const int i = blockIdx.x * CX + threadIdx.x + 1;
     const int j = blockIdx.y * CY + threadIdx.y + 1;
     int l = 0;
     if (DIM == 2) {
-        n.r = blockIdx.z;
+        n.r0 = blockIdx.z * RB;
         n.blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
     } else {
         l = blockIdx.z % g.m + 1;
-        n.r = blockIdx.z / g.m;
+        n.r0 = (blockIdx.z / g.m) * RB;
         n.blk = ((long)(l - 1) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     }
     n.ok = i <= g.m && j <= g.m;
@@ -47,55 +54,122 @@ __device__ inline NodeIdx node_of(const Grid& g) {
     return n;
 }
 
-// (A v)(id) for the level operator, v given as a callable of the padded
-// index (so that v can be formed on the fly).  KIND: 0 constant coefficient
-// (w0 times the 5- or 7-point Laplacian), 1 edge weights, 2 general 2D
-// 7-point stencil (diagonal, edge weights and the "/" diagonal weight).
-template <typename T, int DIM, int KIND, typename V>
-__device__ inline T apply_op(const Grid& g, const Coef<T>& c, long id, V v) {
-    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
-    const T x0 = v(id);
-    if (DIM == 2) {
-        if (KIND == 0) return c.w0 * (T(4) * x0 - v(id + 1) - v(id - 1) - v(id + py) - v(id - py));
-        const T we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - py];
-        if (KIND == 1)
-            return we * (x0 - v(id + 1)) + ww * (x0 - v(id - 1)) + wn * (x0 - v(id + py)) + ws * (x0 - v(id - py));
-        return c.d[id] * x0 - we * v(id + 1) - ww * v(id - 1) - wn * v(id + py) - ws * v(id - py) -
-               c.wne[id] * v(id + py + 1) - c.wne[id - py - 1] * v(id - py - 1);
-    } else {
-        if (KIND == 0)
-            return c.w0 * (T(6) * x0 - v(id + 1) - v(id - 1) - v(id + py) - v(id - py) - v(id + pz) - v(id - pz));
-        if (KIND == 3) {
-            // the 15-point operator: diagonal plane, then A(i, i + o) for the
-            // seven Kuhn edge directions o
-            const long P = g.plane;
-            const long o7[7] = {1, py, pz, 1 + py, 1 + pz, py + pz, 1 + py + pz};
-            T acc = c.s15[id] * x0;
-#pragma unroll
-            for (int t = 0; t < 7; ++t)
-                acc += c.s15[(t + 1) * P + id] * v(id + o7[t]) + c.s15[(t + 1) * P + id - o7[t]] * v(id - o7[t]);
-            return acc;
-        }
-        const T w1 = c.wx[id], w2 = c.wx[id - 1], w3 = c.wy[id], w4 = c.wy[id - py], w5 = c.wz[id],
-                w6 = c.wz[id - pz];
-        return w1 * (x0 - v(id + 1)) + w2 * (x0 - v(id - 1)) + w3 * (x0 - v(id + py)) + w4 * (x0 - v(id - py)) +
-               w5 * (x0 - v(id + pz)) + w6 * (x0 - v(id - pz));
-    }
-}
+// The level operator's row at one node, its coefficients held in registers:
+// KIND 0 constant coefficient (w0 times the 5- or 7-point Laplacian), 1 edge
+// weights, 2 general 2D 7-point stencil (diagonal, edge weights and the "/"
+// diagonal weight), 3 the 3D 15-point operator (diagonal plane, then
+// A(i, i + o) for the seven Kuhn edge directions o).  apply() takes v as a
+// callable of the padded index (so that v can be formed on the fly).
+template <typename T, int DIM, int KIND>
+struct OpRow;
 
-// Sum of one double per thread over the workgroup (fixed order), stored by
-// thread 0 at out.
-__device__ inline void block_partial(double v, double* out) {
-    __shared__ double sh[CX * CY / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+template <typename T, int DIM>
+struct OpRow<T, DIM, 0> {
+    T w0;
+    __device__ inline void load(const Grid&, const Coef<T>& c, long) { w0 = c.w0; }
+    template <typename V>
+    __device__ inline T apply(const Grid& g, long id, V v) const {
+        const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+        const T x0 = v(id);
+        if (DIM == 2) return w0 * (T(4) * x0 - v(id + 1) - v(id - 1) - v(id + py) - v(id - py));
+        return w0 * (T(6) * x0 - v(id + 1) - v(id - 1) - v(id + py) - v(id - py) - v(id + pz) - v(id - pz));
+    }
+};
+
+template <typename T>
+struct OpRow<T, 2, 1> {
+    T we, ww, wn, ws;
+    __device__ inline void load(const Grid& g, const Coef<T>& c, long id) {
+        we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - g.pitch];
+    }
+    template <typename V>
+    __device__ inline T apply(const Grid& g, long id, V v) const {
+        const long py = g.pitch;
+        const T x0 = v(id);
+        return we * (x0 - v(id + 1)) + ww * (x0 - v(id - 1)) + wn * (x0 - v(id + py)) + ws * (x0 - v(id - py));
+    }
+};
+
+template <typename T>
+struct OpRow<T, 2, 2> {
+    T d, we, ww, wn, ws, wne, wsw;
+    __device__ inline void load(const Grid& g, const Coef<T>& c, long id) {
+        const long py = g.pitch;
+        d = c.d[id], we = c.wx[id], ww = c.wx[id - 1], wn = c.wy[id], ws = c.wy[id - py];
+        wne = c.wne[id], wsw = c.wne[id - py - 1];
+    }
+    template <typename V>
+    __device__ inline T apply(const Grid& g, long id, V v) const {
+        const long py = g.pitch;
+        return d * v(id) - we * v(id + 1) - ww * v(id - 1) - wn * v(id + py) - ws * v(id - py) -
+               wne * v(id + py + 1) - wsw * v(id - py - 1);
+    }
+};
+
+template <typename T>
+struct OpRow<T, 3, 1> {
+    T w[6];
+    __device__ inline void load(const Grid& g, const Coef<T>& c, long id) {
+        const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+        w[0] = c.wx[id], w[1] = c.wx[id - 1], w[2] = c.wy[id], w[3] = c.wy[id - py], w[4] = c.wz[id],
+        w[5] = c.wz[id - pz];
+    }
+    template <typename V>
+    __device__ inline T apply(const Grid& g, long id, V v) const {
+        const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+        const T x0 = v(id);
+        return w[0] * (x0 - v(id + 1)) + w[1] * (x0 - v(id - 1)) + w[2] * (x0 - v(id + py)) +
+               w[3] * (x0 - v(id - py)) + w[4] * (x0 - v(id + pz)) + w[5] * (x0 - v(id - pz));
+    }
+};
+
+template <typename T>
+struct OpRow<T, 3, 3> {
+    T d, up[7], dn[7];
+    __device__ static inline long off(const Grid& g, int t) {
+        const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+        const long o7[7] = {1, py, pz, 1 + py, 1 + pz, py + pz, 1 + py + pz};
+        return o7[t];
+    }
+    __device__ inline void load(const Grid& g, const Coef<T>& c, long id) {
+        const long P = g.plane;
+        d = c.s15[id];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            up[t] = c.s15[(t + 1) * P + id];
+            dn[t] = c.s15[(t + 1) * P + id - off(g, t)];
+        }
+    }
+    template <typename V>
+    __device__ inline T apply(const Grid& g, long id, V v) const {
+        T acc = d * v(id);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            const long o = off(g, t);
+            acc += up[t] * v(id + o) + dn[t] * v(id - o);
+        }
+        return acc;
+    }
+};
+
+// Sums of RB doubles per thread over the workgroup (each in a fixed order);
+// the sum of value q goes to out[q * nblk], for q < nvalid.
+template <int RB>
+__device__ inline void block_partials(double (&v)[RB], double* out, long nblk, int nvalid) {
+    __shared__ double sh[RB][CX * CY / 64];
     const int t = threadIdx.y * CX + threadIdx.x;
-    if ((t & 63) == 0) sh[t >> 6] = v;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        double s = v[q];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if ((t & 63) == 0) sh[q][t >> 6] = s;
+    }
     __syncthreads();
-    if (t == 0) {
+    if (t < RB && t < nvalid) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < CX * CY / 64; ++w) s += sh[w];
-        *out = s;
+        for (int w = 0; w < CX * CY / 64; ++w) s += sh[t][w];
+        out[(long)t * nblk] = s;
     }
 }
 
@@ -103,20 +177,28 @@ __device__ inline void block_partial(double v, double* out) {
 template <typename T, int DIM, int KIND, bool XZ>
 __global__ __launch_bounds__(CX* CY) void k_cg_start(Grid g, Coef<T> c, const T* __restrict__ x,
                                                      const T* __restrict__ f, T* __restrict__ r,
-                                                     double* __restrict__ partial, long stride, long nblk) {
-    const NodeIdx n = node_of<DIM>(g);
-    const long off = (long)n.r * stride;
-    double acc = 0.0;
-    if (n.ok) {
-        T rv = f[off + n.id];
-        if (!XZ) {
-            const T* xr = x + off;
-            rv -= apply_op<T, DIM, KIND>(g, c, n.id, [&](long q) { return xr[q]; });
+                                                     double* __restrict__ partial, long stride, long nblk, int nrhs) {
+    constexpr int RB = XZ ? 1 : rhs_block<DIM, KIND>();
+    const NodeIdx n = node_of<DIM, RB>(g);
+    const int nv = min(RB, nrhs - n.r0);
+    double acc[RB];
+    OpRow<T, DIM, KIND> row;
+    if (!XZ && n.ok) row.load(g, c, n.id);
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        acc[q] = 0.0;
+        if (n.ok && q < nv) {
+            const long off = (long)(n.r0 + q) * stride;
+            T rv = f[off + n.id];
+            if (!XZ) {
+                const T* xr = x + off;
+                rv -= row.apply(g, n.id, [&](long k) { return xr[k]; });
+            }
+            r[off + n.id] = rv;
+            acc[q] = (double)rv * (double)rv;
         }
-        r[off + n.id] = rv;
-        acc = (double)rv * (double)rv;
     }
-    block_partial(acc, partial + (long)n.r * nblk + n.blk);
+    block_partials<RB>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, nv);
 }
 
 // p_new = r + beta p_old (FIRST: p_new = r), q = A p_new; partial sums of p_new.q
@@ -124,22 +206,30 @@ template <typename T, int DIM, int KIND, bool FIRST>
 __global__ __launch_bounds__(CX* CY) void k_cg_dir(Grid g, Coef<T> c, const T* __restrict__ r,
                                                    const T* __restrict__ pold, const double* __restrict__ beta,
                                                    T* __restrict__ pnew, T* __restrict__ q,
-                                                   double* __restrict__ partial, long stride, long nblk) {
-    const NodeIdx n = node_of<DIM>(g);
-    const long off = (long)n.r * stride;
-    double acc = 0.0;
-    if (n.ok) {
-        const T* rr = r + off;
-        const T* po = pold + off;
-        const T b = FIRST ? T(0) : (T)beta[n.r];
-        auto pv = [&](long k) { return FIRST ? rr[k] : rr[k] + b * po[k]; };
-        const T p0 = pv(n.id);
-        const T qv = apply_op<T, DIM, KIND>(g, c, n.id, pv);
-        pnew[off + n.id] = p0;
-        q[off + n.id] = qv;
-        acc = (double)p0 * (double)qv;
+                                                   double* __restrict__ partial, long stride, long nblk, int nrhs) {
+    constexpr int RB = rhs_block<DIM, KIND>();
+    const NodeIdx n = node_of<DIM, RB>(g);
+    const int nv = min(RB, nrhs - n.r0);
+    double acc[RB];
+    OpRow<T, DIM, KIND> row;
+    if (n.ok) row.load(g, c, n.id);
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+        acc[u] = 0.0;
+        if (n.ok && u < nv) {
+            const long off = (long)(n.r0 + u) * stride;
+            const T* rr = r + off;
+            const T* po = pold + off;
+            const T b = FIRST ? T(0) : (T)beta[n.r0 + u];
+            auto pv = [&](long k) { return FIRST ? rr[k] : rr[k] + b * po[k]; };
+            const T p0 = pv(n.id);
+            const T qv = row.apply(g, n.id, pv);
+            pnew[off + n.id] = p0;
+            q[off + n.id] = qv;
+            acc[u] = (double)p0 * (double)qv;
+        }
     }
-    block_partial(acc, partial + (long)n.r * nblk + n.blk);
+    block_partials<RB>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, nv);
 }
 
 // x += alpha p (XZ: x = alpha p); with RR also r -= alpha q and partial sums of r.r
@@ -148,20 +238,20 @@ __global__ __launch_bounds__(CX* CY) void k_cg_update(Grid g, T* __restrict__ x,
                                                       const T* __restrict__ p, const T* __restrict__ q,
                                                       const double* __restrict__ alpha, double* __restrict__ partial,
                                                       long stride, long nblk) {
-    const NodeIdx n = node_of<DIM>(g);
-    const long off = (long)n.r * stride;
-    double acc = 0.0;
+    const NodeIdx n = node_of<DIM, 1>(g);
+    const long off = (long)n.r0 * stride;
+    double acc[1] = {0.0};
     if (n.ok) {
-        const T a = (T)alpha[n.r];
+        const T a = (T)alpha[n.r0];
         const long k = off + n.id;
         x[k] = XZ ? a * p[k] : x[k] + a * p[k];
         if (RR) {
             const T rv = r[k] - a * q[k];
             r[k] = rv;
-            acc = (double)rv * (double)rv;
+            acc[0] = (double)rv * (double)rv;
         }
     }
-    if (RR) block_partial(acc, partial + (long)n.r * nblk + n.blk);
+    if (RR) block_partials<1>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, 1);
 }
 
 // Per right-hand side: s = sum of its nblk partials (fixed order), then
@@ -193,8 +283,11 @@ __global__ __launch_bounds__(256) void k_cg_reduce(const double* __restrict__ pa
 template <typename T, int DIM, int KIND>
 void cg_run(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int steps, bool x_zero, const CgWork& w,
             hipStream_t st) {
+    constexpr int RB = rhs_block<DIM, KIND>();
     const dim3 blk(CX, CY);
+    const int ngrp = (nrhs + RB - 1) / RB;
     const dim3 grid((g.m + CX - 1) / CX, (g.m + CY - 1) / CY, DIM == 2 ? nrhs : g.m * nrhs);
+    const dim3 grid_op(grid.x, grid.y, DIM == 2 ? ngrp : g.m * ngrp);
     const long nblk = (long)grid.x * grid.y * (DIM == 2 ? 1 : g.m);
     const long sd = g.plane;
     T* r = static_cast<T*>(w.r);
@@ -202,17 +295,19 @@ void cg_run(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int ste
     T* pb = static_cast<T*>(w.pb);
     T* q = static_cast<T*>(w.q);
     if (x_zero)
-        hipLaunchKernelGGL((k_cg_start<T, DIM, KIND, true>), grid, blk, 0, st, g, c, x, f, r, w.partial, sd, nblk);
+        hipLaunchKernelGGL((k_cg_start<T, DIM, KIND, true>), grid, blk, 0, st, g, c, x, f, r, w.partial, sd, nblk,
+                           nrhs);
     else
-        hipLaunchKernelGGL((k_cg_start<T, DIM, KIND, false>), grid, blk, 0, st, g, c, x, f, r, w.partial, sd, nblk);
+        hipLaunchKernelGGL((k_cg_start<T, DIM, KIND, false>), grid_op, blk, 0, st, g, c, x, f, r, w.partial, sd,
+                           nblk, nrhs);
     hipLaunchKernelGGL(k_cg_reduce<0>, dim3(nrhs), dim3(256), 0, st, w.partial, nblk, w.rr, (double*)nullptr);
     for (int s = 0; s < steps; ++s) {
         if (s == 0)
-            hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, true>), grid, blk, 0, st, g, c, r, pb, w.beta, pa, q, w.partial,
-                               sd, nblk);
+            hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, true>), grid_op, blk, 0, st, g, c, r, pb, w.beta, pa, q,
+                               w.partial, sd, nblk, nrhs);
         else
-            hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, false>), grid, blk, 0, st, g, c, r, pb, w.beta, pa, q,
-                               w.partial, sd, nblk);
+            hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, false>), grid_op, blk, 0, st, g, c, r, pb, w.beta, pa, q,
+                               w.partial, sd, nblk, nrhs);
         hipLaunchKernelGGL(k_cg_reduce<1>, dim3(nrhs), dim3(256), 0, st, w.partial, nblk, w.rr, w.alpha);
         const bool last = s == steps - 1, xz = x_zero && s == 0;
         if (last) {

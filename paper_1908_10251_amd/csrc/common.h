@@ -345,12 +345,17 @@ void launch_apply3g(const Grid& g, const T* s15, const T* x, T* y, int nrhs, lon
 template <typename T>
 void launch_resid_restrict3g(const Grid& gf, const T* s15, const T* x, const T* f, const Grid& gc, T* rc, int nrhs,
                              long sf, long sc, hipStream_t st);
+template <typename T>
+void launch_resid3g(const Grid& g, const T* s15, const T* x, const T* f, T* r, int nrhs, long stride,
+                    hipStream_t st);
 void launch_resid_cast3g(const Grid& g, const double* s15, const double* u, const double* f, float* r, int nrhs,
                          long stride, hipStream_t st);
 void launch_add_resid3g(const Grid& g, const double* s15, const double* u, const float* e, const double* f,
                         double* un, float* r, int nrhs, long stride, hipStream_t st);
+// the borders' fine-level vectors of the 15-point operator; with e (and un),
+// of u + e, written to un
 int launch_border3g(const Grid& g, const double* s15, const double* u, double* au, double* mu, double* partial,
-                    int nrhs, long stride, hipStream_t st);
+                    int nrhs, long stride, hipStream_t st, const float* e = nullptr, double* un = nullptr);
 
 // Chebyshev steps of degree s on [rho/alpha, rho]; damped Jacobi steps.
 std::vector<Cheb> cheb_steps(double rho, double alpha, int s);

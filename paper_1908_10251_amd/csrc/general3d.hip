@@ -255,23 +255,77 @@ __device__ inline double mass15(const Grid& g, const double* __restrict__ x, lon
     return h3 * (0.4 * x[id] + ax / 20.0 + fd / 30.0);
 }
 
+// The 15 coefficients of the operator's row at id, in registers, so that
+// kernels looping over several right-hand sides read them once.
+template <typename T>
+struct Row15 {
+    T d, up[7], dn[7];
+    __device__ inline void load(const Grid& g, const T* __restrict__ s15, long id) {
+        const long P = g.plane;
+        d = s15[id];
+#pragma unroll
+        for (int t = 1; t < 8; ++t) {
+            up[t - 1] = s15[t * P + id];
+            dn[t - 1] = s15[t * P + id - off3(g, t)];
+        }
+    }
+    template <typename V>
+    __device__ inline T apply(const Grid& g, long id, V v) const {
+        T a = d * v(id);
+#pragma unroll
+        for (int t = 1; t < 8; ++t) {
+            const long o = off3(g, t);
+            a += up[t - 1] * v(id + o) + dn[t - 1] * v(id - o);
+        }
+        return a;
+    }
+};
+
+// Kernels over RB right-hand sides per thread: blockIdx.z = (plane, group of RB)
+constexpr int RB3 = 4;
+inline dim3 grid3rb(int m, int nrhs) { return dim3((m + GX - 1) / GX, (m + GY - 1) / GY, m * ((nrhs + RB3 - 1) / RB3)); }
+
+struct P3b {
+    long id;
+    int r0;  // first right-hand side of the thread's group
+    bool ok;
+};
+__device__ inline P3b p3b(const Grid& g) {
+    P3b p;
+    const int i = blockIdx.x * GX + threadIdx.x + 1;
+    const int j = blockIdx.y * GY + threadIdx.y + 1;
+    const int l = blockIdx.z % g.m + 1;
+    p.r0 = (blockIdx.z / g.m) * RB3;
+    p.ok = i <= g.m && j <= g.m;
+    p.id = g.idx(i, j, l);
+    return p;
+}
+
 template <typename T>
 __global__ __launch_bounds__(GX* GY) void k_smooth3g(Grid g, const T* __restrict__ s15, const T* __restrict__ xc,
                                                      const T* xp, const T* __restrict__ f, T* xn, long stride, T a,
-                                                     T b, int zmode) {
-    const P3 p = p3(g);
+                                                     T b, int zmode, int nrhs) {
+    const P3b p = p3b(g);
     if (!p.ok) return;
-    const long off = (long)p.r * stride;
-    const T fv = f[off + p.id];
-    const T D = s15[p.id];
-    if (zmode & 1) {
-        xn[off + p.id] = b * fv / D;
-        return;
+    Row15<T> row;
+    if (zmode & 1) row.d = s15[p.id];
+    else row.load(g, s15, p.id);
+#pragma unroll
+    for (int q = 0; q < RB3; ++q) {
+        const int z = p.r0 + q;
+        if (z >= nrhs) break;
+        const long off = (long)z * stride;
+        const T fv = f[off + p.id];
+        if (zmode & 1) {
+            xn[off + p.id] = b * fv / row.d;
+            continue;
+        }
+        const T* xr = xc + off;
+        const T x0 = xr[p.id];
+        T v = x0 + b * (fv - row.apply(g, p.id, [&](long k) { return xr[k]; })) / row.d;
+        if (a != T(0)) v += a * (x0 - ((zmode & 2) ? T(0) : xp[off + p.id]));
+        xn[off + p.id] = v;
     }
-    const T x0 = xc[off + p.id];
-    T v = x0 + b * (fv - apply15<T>(g, s15, xc + off, p.id)) / D;
-    if (a != T(0)) v += a * (x0 - ((zmode & 2) ? T(0) : xp[off + p.id]));
-    xn[off + p.id] = v;
 }
 
 template <typename T>
@@ -309,75 +363,132 @@ __global__ __launch_bounds__(GX* GY) void k_resid_restrict3g(Grid gf, const T* _
     rc[(long)p.r * sc + gc.idx(I, J, L)] = acc;
 }
 
+// r = f - A x (type T), RB right-hand sides per thread
+template <typename T>
+__global__ __launch_bounds__(GX* GY) void k_resid3g(Grid g, const T* __restrict__ s15, const T* __restrict__ x,
+                                                    const T* __restrict__ f, T* __restrict__ r, long stride,
+                                                    int nrhs) {
+    const P3b p = p3b(g);
+    if (!p.ok) return;
+    Row15<T> row;
+    row.load(g, s15, p.id);
+#pragma unroll
+    for (int q = 0; q < RB3; ++q) {
+        const int z = p.r0 + q;
+        if (z >= nrhs) break;
+        const long off = (long)z * stride;
+        const T* xr = x + off;
+        r[off + p.id] = f[off + p.id] - row.apply(g, p.id, [&](long k) { return xr[k]; });
+    }
+}
+
 __global__ __launch_bounds__(GX* GY) void k_resid_cast3g(Grid g, const double* __restrict__ s15,
                                                          const double* __restrict__ u, const double* __restrict__ f,
-                                                         float* __restrict__ r, long stride) {
-    const P3 p = p3(g);
+                                                         float* __restrict__ r, long stride, int nrhs) {
+    const P3b p = p3b(g);
     if (!p.ok) return;
-    const long off = (long)p.r * stride;
-    r[off + p.id] = (float)(f[off + p.id] - apply15<double>(g, s15, u + off, p.id));
+    Row15<double> row;
+    row.load(g, s15, p.id);
+#pragma unroll
+    for (int q = 0; q < RB3; ++q) {
+        const int z = p.r0 + q;
+        if (z >= nrhs) break;
+        const long off = (long)z * stride;
+        const double* ur = u + off;
+        r[off + p.id] = (float)(f[off + p.id] - row.apply(g, p.id, [&](long k) { return ur[k]; }));
+    }
 }
 
 __global__ __launch_bounds__(GX* GY) void k_add_resid3g(Grid g, const double* __restrict__ s15,
                                                         const double* __restrict__ u, const float* __restrict__ e,
                                                         const double* __restrict__ f, double* __restrict__ un,
-                                                        float* __restrict__ r, long stride) {
-    const P3 p = p3(g);
+                                                        float* __restrict__ r, long stride, int nrhs) {
+    const P3b p = p3b(g);
     if (!p.ok) return;
-    const long off = (long)p.r * stride;
-    const double* ur = u + off;
-    const float* er = e + off;
-    const long P = g.plane;
-    auto v = [&](long q) { return ur[q] + (double)er[q]; };
-    const double x0 = v(p.id);
-    double Ax = s15[p.id] * x0;
+    Row15<double> row;
+    row.load(g, s15, p.id);
 #pragma unroll
-    for (int t = 1; t < 8; ++t) {
-        const long o = off3(g, t);
-        Ax += s15[t * P + p.id] * v(p.id + o) + s15[t * P + p.id - o] * v(p.id - o);
+    for (int q = 0; q < RB3; ++q) {
+        const int z = p.r0 + q;
+        if (z >= nrhs) break;
+        const long off = (long)z * stride;
+        const double* ur = u + off;
+        const float* er = e + off;
+        auto v = [&](long k) { return ur[k] + (double)er[k]; };
+        const double x0 = v(p.id);
+        un[off + p.id] = x0;
+        r[off + p.id] = (float)(f[off + p.id] - row.apply(g, p.id, v));
     }
-    un[off + p.id] = x0;
-    r[off + p.id] = (float)(f[off + p.id] - Ax);
 }
 
 // au = A u, mu = M u and per-workgroup sums of u.Au, u.Mu
+// The borders' fine-level vectors and scalars, RB right-hand sides per
+// thread: A x, M x and partial sums of x.A x and x.M x per workgroup; with
+// ADD, x = u + e (the last FP32 correction added in FP64), written to un.
+template <bool ADD>
 __global__ __launch_bounds__(GX* GY) void k_border3g(Grid g, const double* __restrict__ s15,
-                                                     const double* __restrict__ u, double* __restrict__ au,
+                                                     const double* __restrict__ u, const float* __restrict__ e,
+                                                     double* __restrict__ un, double* __restrict__ au,
                                                      double* __restrict__ mu, double* __restrict__ partial,
-                                                     long stride) {
-    __shared__ double sh[2 * GX * GY / 64];
-    const P3 p = p3(g);
-    const long off = (long)p.r * stride;
-    double a = 0.0, m = 0.0;
-    if (p.ok) {
-        const double* ur = u + off;
-        const double Ax = apply15<double>(g, s15, ur, p.id);
-        const double Mx = mass15(g, ur, p.id);
-        au[off + p.id] = Ax;
-        mu[off + p.id] = Mx;
-        a = ur[p.id] * Ax;
-        m = ur[p.id] * Mx;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_down(a, o, 64);
-        m += __shfl_down(m, o, 64);
+                                                     long stride, int nrhs) {
+    __shared__ double sh[RB3][2][GX * GY / 64];
+    const P3b p = p3b(g);
+    const int nv = min(RB3, nrhs - p.r0);
+    Row15<double> row;
+    if (p.ok) row.load(g, s15, p.id);
+    double a[RB3], m[RB3];
+#pragma unroll
+    for (int q = 0; q < RB3; ++q) {
+        a[q] = m[q] = 0.0;
+        if (p.ok && q < nv) {
+            const long off = (long)(p.r0 + q) * stride;
+            const double* ur = u + off;
+            const float* er = e + off;
+            auto v = [&](long k) { return ADD ? ur[k] + (double)er[k] : ur[k]; };
+            const double x0 = v(p.id);
+            const double Ax = row.apply(g, p.id, v);
+            // M x of the Kuhn mass matrix: h^3 (0.4 centre, 1/20 axis and
+            // body diagonals, 1/30 face diagonals)
+            double ax = 0.0, fd = 0.0;
+#pragma unroll
+            for (int t = 1; t < 8; ++t) {
+                const long o = off3(g, t);
+                const double s2 = v(p.id + o) + v(p.id - o);
+                if (t <= 3 || t == 7) ax += s2;
+                else fd += s2;
+            }
+            const double Mx = g.h * g.h * g.h * (0.4 * x0 + ax / 20.0 + fd / 30.0);
+            if (ADD) un[off + p.id] = x0;
+            au[off + p.id] = Ax;
+            mu[off + p.id] = Mx;
+            a[q] = x0 * Ax;
+            m[q] = x0 * Mx;
+        }
     }
     const int t = threadIdx.y * GX + threadIdx.x;
-    if ((t & 63) == 0) {
-        sh[2 * (t >> 6)] = a;
-        sh[2 * (t >> 6) + 1] = m;
+#pragma unroll
+    for (int q = 0; q < RB3; ++q) {
+        double sa = a[q], sm = m[q];
+        for (int o = 32; o > 0; o >>= 1) {
+            sa += __shfl_down(sa, o, 64);
+            sm += __shfl_down(sm, o, 64);
+        }
+        if ((t & 63) == 0) {
+            sh[q][0][t >> 6] = sa;
+            sh[q][1][t >> 6] = sm;
+        }
     }
     __syncthreads();
-    if (t == 0) {
+    if (t < RB3 && t < nv) {
         double sa = 0.0, sm = 0.0;
         for (int w = 0; w < GX * GY / 64; ++w) {
-            sa += sh[2 * w];
-            sm += sh[2 * w + 1];
+            sa += sh[t][0][w];
+            sm += sh[t][1][w];
         }
         const long nblk = (long)gridDim.x * gridDim.y * g.m;
         const long blk = ((long)(blockIdx.z % g.m) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        partial[2 * ((long)p.r * nblk + blk)] = sa;
-        partial[2 * ((long)p.r * nblk + blk) + 1] = sm;
+        partial[2 * ((long)(p.r0 + t) * nblk + blk)] = sa;
+        partial[2 * ((long)(p.r0 + t) * nblk + blk) + 1] = sm;
     }
 }
 
@@ -386,8 +497,8 @@ __global__ __launch_bounds__(GX* GY) void k_border3g(Grid g, const double* __res
 template <typename T>
 void launch_smooth3g(const Grid& g, const T* s15, const T* xc, const T* xp, const T* f, T* xn, int nrhs,
                      long stride, Cheb s, int zmode, hipStream_t st) {
-    hipLaunchKernelGGL((k_smooth3g<T>), grid3g(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, xc, xp, f, xn, stride, (T)s.a,
-                       (T)s.b, zmode);
+    hipLaunchKernelGGL((k_smooth3g<T>), grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, xc, xp, f, xn, stride,
+                       (T)s.a, (T)s.b, zmode, nrhs);
     PASM_CHECK_LAUNCH();
 }
 
@@ -408,20 +519,38 @@ void launch_resid_restrict3g(const Grid& gf, const T* s15, const T* x, const T* 
 
 void launch_resid_cast3g(const Grid& g, const double* s15, const double* u, const double* f, float* r, int nrhs,
                          long stride, hipStream_t st) {
-    hipLaunchKernelGGL(k_resid_cast3g, grid3g(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, f, r, stride);
+    hipLaunchKernelGGL(k_resid_cast3g, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, f, r, stride, nrhs);
     PASM_CHECK_LAUNCH();
 }
 
 void launch_add_resid3g(const Grid& g, const double* s15, const double* u, const float* e, const double* f,
                         double* un, float* r, int nrhs, long stride, hipStream_t st) {
-    hipLaunchKernelGGL(k_add_resid3g, grid3g(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, e, f, un, r, stride);
+    hipLaunchKernelGGL(k_add_resid3g, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, e, f, un, r, stride,
+                       nrhs);
     PASM_CHECK_LAUNCH();
 }
 
+template <typename T>
+void launch_resid3g(const Grid& g, const T* s15, const T* x, const T* f, T* r, int nrhs, long stride,
+                    hipStream_t st) {
+    hipLaunchKernelGGL((k_resid3g<T>), grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, x, f, r, stride, nrhs);
+    PASM_CHECK_LAUNCH();
+}
+template void launch_resid3g<double>(const Grid&, const double*, const double*, const double*, double*, int, long,
+                                     hipStream_t);
+template void launch_resid3g<float>(const Grid&, const float*, const float*, const float*, float*, int, long,
+                                    hipStream_t);
+
 int launch_border3g(const Grid& g, const double* s15, const double* u, double* au, double* mu, double* partial,
-                    int nrhs, long stride, hipStream_t st) {
-    const dim3 grid = grid3g(g.m, nrhs);
-    hipLaunchKernelGGL(k_border3g, grid, dim3(GX, GY), 0, st, g, s15, u, au, mu, partial, stride);
+                    int nrhs, long stride, hipStream_t st, const float* e, double* un) {
+    if ((e == nullptr) != (un == nullptr)) throw Error(PASM_E_INVALID, "general 3D borders: correction and output");
+    const dim3 grid = grid3rb(g.m, nrhs);
+    if (e)
+        hipLaunchKernelGGL(k_border3g<true>, grid, dim3(GX, GY), 0, st, g, s15, u, e, un, au, mu, partial, stride,
+                           nrhs);
+    else
+        hipLaunchKernelGGL(k_border3g<false>, grid, dim3(GX, GY), 0, st, g, s15, u, e, un, au, mu, partial, stride,
+                           nrhs);
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y * g.m);
 }
