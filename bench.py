@@ -299,16 +299,32 @@ def bench_solve(args, wl, pasm, torch):
     return out
 
 
+def coefficient_text(wl: W.Workload) -> str:
+    if wl.tensor == "example2":
+        return ("A = I + (x-1/2)(x-1/2)^T, phi = exp(prod(x_i - 1/2)) at element centroids (the second example "
+                "of Section 5)")
+    if wl.kappa == "lognormal":
+        return "kappa log-normal, sigma 1, i.i.d. per fine element"
+    return "constant (Laplacian)"
+
+
 def bench_steps(args, wl, pasm, torch):
-    """Rough-coefficient single instance: correction steps per second."""
+    """Single instances that the method does not take to 1e-8 for every
+    eigenpair (rough coefficients, the cube's clusters) and the second
+    example: correction steps per second, the state carried from step to
+    step."""
     opts = pasm.options_for(wl)
     kap, pot, ten = coefficients(wl)
     t0 = time.perf_counter()
     solver = pasm.Solver(wl.dim, wl.H, wl.h, wl.k, kappa=kap, potential=pot, opts=opts, tensor=ten)
     t_setup = time.perf_counter() - t0
     ctx, k = solver.ctx, wl.k
+    learned = wl.smoother == "learned"
+    if learned and args.learned == "on":
+        pasm.pasm_learned_enable(ctx, True)  # override the set-up speed test
     for _ in range(args.warmup):
         pasm.pasm_iterate(ctx)
+    rep0 = pasm.pasm_learned_report(ctx) if learned else None
     pasm.pasm_profile(ctx, 0, True)
     hist = [solver.eigenpairs(False)[0]]
     torch.cuda.synchronize()
@@ -322,20 +338,38 @@ def bench_steps(args, wl, pasm, torch):
     H = np.array(hist)
     d = np.abs(H[1:] - H[:-1]) / H[1:]
     ms_per_step = 1e3 * elapsed / args.iters
-    cfg = {"dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": pasm.pasm_num_dofs(ctx),
+    n_dofs = pasm.pasm_num_dofs(ctx)
+    cfg = {"dim": wl.dim, "H": wl.H, "h": wl.h, "k": k, "fine_dofs": n_dofs,
            "smoother": wl.smoother, "nu": [wl.nu_pre, wl.nu_post], "vcycles": wl.vcycles, "precision": wl.precision,
-           "coefficients": ("A = I + (x-1/2)(x-1/2)^T, phi = exp(prod(x_i - 1/2)) at element centroids (the "
-                            "second example of Section 5)" if wl.tensor == "example2"
-                            else "kappa log-normal, sigma 1, i.i.d. per fine element"), "iterations": args.iters,
+           "coefficients": coefficient_text(wl), "iterations": args.iters,
            "eigenpairs_with_last_change_below_1e-10": int(np.sum(d[-1] < 1e-10)), "setup_s": t_setup,
            "step": "one outer iteration (one correction step for all k eigenpairs)"}
-    kname = (KERNEL_NAMES["cg"] if wl.smoother == "cg"
-             else KERNEL_NAMES["kappa"] if wl.precision == "mixed" else KERNEL_NAMES[2])
-    roof = roofline(launches, ms, bpl, wl.name, kname)
+    flops = None
+    if wl.smoother == "cg":
+        kname = KERNEL_NAMES["cg"]
+    elif wl.dim == 3:
+        kname = KERNEL_NAMES[3]
+    else:
+        kname = KERNEL_NAMES["kappa"] if wl.precision == "mixed" else KERNEL_NAMES[2]
+    if learned:
+        rep = pasm.pasm_learned_report(ctx)
+        cfg["learned"] = rep
+        cfg["learned_mode"] = args.learned
+        # the timed launches are the learned step's only if the learned
+        # smoother ran (the set-up speed test may have left it off)
+        if rep["cycles_learned"] > rep0["cycles_learned"]:
+            # 16 channels x 27 taps multiply-adds in each of the two layers per node
+            flops = 2.0 * 2 * 16 * 27 * n_dofs * k
+            kname = KERNEL_NAMES["learned"]
+            if rep["cycles_fallback"] > rep0["cycles_fallback"]:
+                kname += "; some cycles fell back to plain smoothing"
+        else:
+            kname += " (the learned smoother was off: the set-up speed test found plain cycles faster)"
+    roof = roofline(launches, ms, bpl, wl.name, kname, flops)
     solver.close()
     out = line(wl, "eigenpair correction steps/sec", k / (ms_per_step / 1e3), "eigenpair-steps/s", args.iters,
                args.warmup, ms_per_step, cfg, roof, "f32+f64" if wl.precision == "mixed" else "f64")
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not learned:
         out["cpu_baseline"] = cpu_baseline_steps(wl, kap)
     if wl.tensor == "example2":
         # eigenpairs whose last step changed the eigenvalue by less than 1e-8
@@ -436,7 +470,7 @@ def main():
     torch.cuda.set_device(0)
     if wl is W.BATCH2D_UNEVEN:
         out = bench_batch(args, wl, pasm, torch)
-    elif wl.kappa != "one" or wl.tensor != "none":
+    elif wl.kappa != "one" or wl.tensor != "none" or wl.dim == 3:
         out = bench_steps(args, wl, pasm, torch)
     else:
         out = bench_solve(args, wl, pasm, torch)

@@ -86,6 +86,10 @@ struct pasm_ctx {
     bool own_stream = false;
     bool mixed = false;
     bool fuse = true;      // temporal blocking of smoothing phases (2D)
+    // The correction step's right-hand side f = lam M u is never stored: the
+    // FP64 residual passes of a mixed-precision step form it from u (2D edge
+    // weights, at most two V-cycles, so that u is still the step's start).
+    bool f_mass = false;
     std::vector<pasm::Level> lv;
     // finest level, FP64 (padded layout: boundary entries stay zero)
     double *U = nullptr, *F64 = nullptr, *Y64 = nullptr, *R64 = nullptr;
@@ -519,7 +523,7 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
 // cycle's last pass); with next set, this cycle's correction and the
 // next cycle's residual are formed in one pass, x moving to scr.
 void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, bool* r_ready = nullptr,
-               bool next = false, bool defer_add = false) {
+               bool next = false, bool defer_add = false, const double* lam_mass = nullptr) {
     const int lf = c->L - 1;
     if (!c->mixed) {
         c->pair_next = next;
@@ -528,13 +532,14 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
         return;
     }
     const Grid& g = c->gf();
-    if (!(r_ready && *r_ready)) pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st);
+    if (!(r_ready && *r_ready))
+        pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st, lam_mass);
     if (r_ready) *r_ready = false;
     float* e = c->E32;
     float* ye = c->Y32;
     vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
     if (next && r_ready && pasm::add_resid_supported(g, c->coef<double>(lf))) {
-        pasm::launch_add_resid(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st);
+        pasm::launch_add_resid(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st, lam_mass);
         std::swap(x, scr);
         *r_ready = true;
         return;
@@ -582,7 +587,10 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
             const bool defer = cy == ncycles - 1 && c->mixed && eig &&
                                ((border && c->dim == 2 && pasm::coef_kind(c->coef<double>(c->L - 1)) <= 1) ||
                                 c->lv[c->L - 1].general3);
-            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles, defer);
+            // f = lam M u formed by the residual passes (the first two cycles
+            // of a step start from u itself or from u + e with u still in x)
+            const double* lam_mass = (eig && c->f_mass && cy < 2) ? c->lam : nullptr;
+            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles, defer, lam_mass);
             c->border_next = false;
         }
         if (c->fine_pre_done) throw Error(PASM_E_DEVICE, "paired smoothing phases: a cycle left unfinished");
@@ -870,6 +878,8 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
     }
     const int N = c->NH;
     c->general_coef = general || general3;
+    c->f_mass = c->mixed && c->L >= 2 && c->opt.vcycles <= 2 &&
+                pasm::mass_rhs_fusable(c->gf(), c->coef<double>(c->L - 1));
     if (share) {
         c->coarse_shared = true;
         c->theta = share->theta;
@@ -1066,10 +1076,10 @@ void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, b
         // 2D: from the coarse space straight to the finest level (P1
         // interpolation on the coarse triangles), with the next step's
         // right-hand side lambda M u from the same pass
-        pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->F64, k, L0.g.plane, c->sf(), s,
-                                  lamf ? lamf : c->mu, c->st);
+        pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->f_mass ? nullptr : c->F64, k, L0.g.plane,
+                                  c->sf(), s, lamf ? lamf : c->mu, c->st);
         std::swap(c->U, c->Y64);
-        c->f_ready = true;
+        c->f_ready = !c->f_mass;
         return;
     }
     for (int l = 1; l < c->L - 1; ++l)
@@ -1105,7 +1115,7 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
     const long sf = c->sf();
     // Algorithm 1, step 1: f = lambda M u (unless the previous step's
     // prolongation formed it), V-cycles from x = u (in place in U)
-    if (!c->f_ready) pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, sf, c->st);
+    if (!c->f_ready && !c->f_mass) pasm::launch_mass_rhs(g, c->U, c->lam, c->F64, k, sf, c->st);
     c->f_ready = false;
     c->border_done = false;
     if (c->L > 1) {

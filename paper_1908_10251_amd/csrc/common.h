@@ -225,10 +225,14 @@ void launch_dst_solve(const Grid& g, const double* S, const double* inv, const T
                       int nrhs, hipStream_t st);
 
 // un = u + e and r = f - A un (to FP32) in one pass (3D, or 2D with constant
-// coefficients); un must not alias u.
+// coefficients or edge weights); un must not alias u.  With lam (2D edge
+// weights, mass_rhs_fusable): f is not read but formed as lam M u.
 bool add_resid_supported(const Grid& g, const Coef<double>& c);
 void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
-                      double* un, float* r, int nrhs, long stride, hipStream_t st);
+                      double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
+// the residual kernels can form f = lam M u from u themselves (2D edge
+// weights of a single problem)
+bool mass_rhs_fusable(const Grid& g, const Coef<double>& c);
 // un = u + e and r = f - A un (to FP32) in one pass (3D); un must not alias u.
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                        double* un, float* r, int nrhs, long stride, hipStream_t st);
@@ -263,9 +267,10 @@ void launch_mass_rhs(const Grid& g, const double* u, const double* lam, double* 
 // y = M_h x
 void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long stride, hipStream_t st);
 
-// r32 = (f - A u) in FP64, rounded to FP32
+// r32 = (f - A u) in FP64, rounded to FP32; with lam (mass_rhs_fusable), f
+// is not read but formed as lam M u
 void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f,
-                       float* r, int nrhs, long stride, hipStream_t st);
+                       float* r, int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
 // r = f - A u in FP64, stored as TO (2D)
 template <typename TO>
 void launch_resid_to(const Grid& g, const Coef<double>& c, const double* u, const double* f, TO* r, int nrhs,

@@ -408,11 +408,13 @@ __global__ __launch_bounds__(BX* BY) void k_mass_rhs(Grid g, const double* __res
 
 // RB right-hand sides per workgroup (edge weights of a single problem: the
 // weights are loaded once for all of them; RB = 1 for batches, whose members
-// have planes of their own).
-template <int KIND, typename TO, int RB = 1>
+// have planes of their own).  MASS: f is not read but formed as lam M u
+// from u itself (u is the start of the correction step, f = lam M u).
+template <int KIND, typename TO, int RB = 1, bool MASS = false>
 __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, const double* __restrict__ u,
                                                        const double* __restrict__ f,
-                                                       TO* __restrict__ r, long stride, long rstride, int nrhs) {
+                                                       TO* __restrict__ r, long stride, long rstride, int nrhs,
+                                                       const double* __restrict__ lam) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
@@ -425,12 +427,22 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
             const int z = blockIdx.z * RB + q;
             if (z >= nrhs) break;
             const double* ur = u + (long)z * stride;
-            const double Ax = D * ur[id] - we * ur[id + 1] - ww * ur[id - 1] - wn * ur[id + g.pitch] -
-                              ws * ur[id - g.pitch];
-            r[(long)z * rstride + id] = (TO)(f[(long)z * stride + id] - Ax);
+            const int p = g.pitch;
+            const double u0 = ur[id], uE = ur[id + 1], uW = ur[id - 1], uN = ur[id + p], uS = ur[id - p];
+            const double Ax = D * u0 - we * uE - ww * uW - wn * uN - ws * uS;
+            double fv;
+            if (MASS) {
+                // lam M u with the neighbours in the order of k_prolong_mass
+                const double sn = uE + uW + uN + uS + ur[id + p + 1] + ur[id - p - 1];
+                fv = lam[z] * (g.h * g.h * __builtin_fma(sn, 1.0 / 12.0, 0.5 * u0));
+            } else {
+                fv = f[(long)z * stride + id];
+            }
+            r[(long)z * rstride + id] = (TO)(fv - Ax);
         }
         return;
     }
+    static_assert(!MASS || (RB > 1 && KIND == 1), "mass right-hand side: edge weights, several right-hand sides");
     double bs;
     const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const long off = (long)blockIdx.z * stride;
@@ -443,11 +455,13 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
 // coefficients, 1 edge weights): un = u + e on every interior node and
 // r = f - A un (FP64, rounded to FP32) for the next cycle; un at the
 // neighbours is formed again from u and e.  un must not alias u.
-template <int KIND, int RB = 1>
+// MASS: f is not read but formed as lam M u from u itself (u is then the
+// start of the correction step: the step's first cycle).
+template <int KIND, int RB = 1, bool MASS = false>
 __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, const double* __restrict__ u,
                                                       const float* __restrict__ e, const double* __restrict__ f,
                                                       double* __restrict__ un, float* __restrict__ r, long stride,
-                                                      int nrhs) {
+                                                      int nrhs, const double* __restrict__ lam) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
@@ -457,22 +471,32 @@ __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, co
         // loaded once for the workgroup's RB right-hand sides
         we = c.wx[gid], ww = c.wx[gid - 1], wn = c.wy[gid], ws = c.wy[gid - g.pitch];
     }
+    const int p = g.pitch;
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
         const int z = blockIdx.z * RB + q;
         if (z >= nrhs) break;
         const long id = (long)z * stride + gid;
-        auto v = [&](long p) { return u[p] + (double)e[p]; };
-        const double x0 = v(id);
+        // every load of the right-hand side before its stores
+        const double u0 = u[id], uE = u[id + 1], uW = u[id - 1], uN = u[id + p], uS = u[id - p];
+        const double x0 = u0 + (double)e[id], xE = uE + (double)e[id + 1], xW = uW + (double)e[id - 1],
+                     xN = uN + (double)e[id + p], xS = uS + (double)e[id - p];
         double Ax;
         if (KIND == 0) {
-            Ax = c.w0 * (4.0 * x0 - (v(id + 1) + v(id - 1) + v(id + g.pitch) + v(id - g.pitch)));
+            Ax = c.w0 * (4.0 * x0 - (xE + xW + xN + xS));
         } else {
-            Ax = (we + ww + wn + ws) * x0 - we * v(id + 1) - ww * v(id - 1) - wn * v(id + g.pitch) -
-                 ws * v(id - g.pitch);
+            Ax = (we + ww + wn + ws) * x0 - we * xE - ww * xW - wn * xN - ws * xS;
+        }
+        double fv;
+        if (MASS) {
+            // lam M u with the neighbours in the order of k_prolong_mass
+            const double sn = uE + uW + uN + uS + u[id + p + 1] + u[id - p - 1];
+            fv = lam[z] * (g.h * g.h * __builtin_fma(sn, 1.0 / 12.0, 0.5 * u0));
+        } else {
+            fv = f[id];
         }
         un[id] = x0;
-        r[id] = (float)(f[id] - Ax);
+        r[id] = (float)(fv - Ax);
     }
 }
 
@@ -791,7 +815,7 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
                           us[b][a];
         const long id = (long)z * sf + gf.idx(i, j);
         xn[id] = x0;
-        f[id] = lz * (h2 * __builtin_fma(sn, 1.0 / 12.0, 0.5 * x0));
+        if (f) f[id] = lz * (h2 * __builtin_fma(sn, 1.0 / 12.0, 0.5 * x0));
     }
 }
 
@@ -1052,9 +1076,22 @@ void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long st
 }
 
 void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
-                       int nrhs, long stride, hipStream_t st) {
+                       int nrhs, long stride, hipStream_t st, const double* lam) {
+    if (lam) {
+        if (!mass_rhs_fusable(g, c)) throw Error(PASM_E_INVALID, "residual with lam M u: 2D edge weights only");
+        constexpr int RB = 4;
+        const dim3 gr = grid_for(g.m, g.m, (nrhs + RB - 1) / RB), blk(BX, BY);
+        hipLaunchKernelGGL((k_resid_cast<1, float, RB, true>), gr, blk, 0, st, g, c, u, f, r, stride, stride, nrhs,
+                           lam);
+        PASM_CHECK_LAUNCH();
+        return;
+    }
     if (g.dim == 3) return launch_resid_cast3(g, c, u, f, r, nrhs, stride, st);
     launch_resid_to<float>(g, c, u, f, r, nrhs, stride, st);
+}
+
+bool mass_rhs_fusable(const Grid& g, const Coef<double>& c) {
+    return g.dim == 2 && coef_kind(c) == 1 && c.kpm <= 1 && c.ms == 0;
 }
 
 template <typename TO>
@@ -1064,17 +1101,24 @@ void launch_resid_to(const Grid& g, const Coef<double>& c, const double* u, cons
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
     const bool single = c.kpm <= 1 && c.ms == 0;
     switch (coef_kind(c)) {
-        case 0: hipLaunchKernelGGL((k_resid_cast<0, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs); break;
+        case 0: hipLaunchKernelGGL((k_resid_cast<0, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs,
+                               nullptr);
+            break;
         case 1:
             if (single) {
                 constexpr int RB = 4;
                 const dim3 gr = grid_for(g.m, g.m, (nrhs + RB - 1) / RB);
-                hipLaunchKernelGGL((k_resid_cast<1, TO, RB>), gr, blk, 0, st, g, c, u, f, r, stride, stride, nrhs);
+                hipLaunchKernelGGL((k_resid_cast<1, TO, RB>), gr, blk, 0, st, g, c, u, f, r, stride, stride, nrhs,
+                                   nullptr);
             } else {
-                hipLaunchKernelGGL((k_resid_cast<1, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs);
+                hipLaunchKernelGGL((k_resid_cast<1, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs,
+                                   nullptr);
             }
             break;
-        default: hipLaunchKernelGGL((k_resid_cast<2, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs); break;
+        default:
+            hipLaunchKernelGGL((k_resid_cast<2, TO>), grid, blk, 0, st, g, c, u, f, r, stride, stride, nrhs,
+                               nullptr);
+            break;
     }
     PASM_CHECK_LAUNCH();
 }
@@ -1092,17 +1136,21 @@ bool add_resid_supported(const Grid& g, const Coef<double>& c) {
 }
 
 void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
-                      double* un, float* r, int nrhs, long stride, hipStream_t st) {
+                      double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam) {
+    if (lam && !mass_rhs_fusable(g, c)) throw Error(PASM_E_INVALID, "add and residual with lam M u: 2D edge weights");
     if (g.dim == 3) return launch_add_resid3(g, c, u, e, f, un, r, nrhs, stride, st);
     if (!add_resid_supported(g, c) || un == u)
         throw Error(PASM_E_INVALID, "add and residual: 2D constant or edge-weight operator, separate output");
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
     if (coef_kind(c) == 0) {
-        hipLaunchKernelGGL((k_add_resid<0, 1>), grid, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs);
+        hipLaunchKernelGGL((k_add_resid<0, 1>), grid, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs, nullptr);
     } else {
         constexpr int RB = 4;
         const dim3 gr = grid_for(g.m, g.m, (nrhs + RB - 1) / RB);
-        hipLaunchKernelGGL((k_add_resid<1, RB>), gr, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs);
+        if (lam)
+            hipLaunchKernelGGL((k_add_resid<1, RB, true>), gr, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs, lam);
+        else
+            hipLaunchKernelGGL((k_add_resid<1, RB>), gr, blk, 0, st, g, c, u, e, f, un, r, stride, nrhs, nullptr);
     }
     PASM_CHECK_LAUNCH();
 }
