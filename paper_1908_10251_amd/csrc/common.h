@@ -169,6 +169,8 @@ void launch_march_post_ew(const Grid& g, const float* wx, const float* wy, const
                           const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st);
 struct MarchShape {
     int strips, segs, mseg, work, blocks;
+    int zg;    // right-hand sides whose pieces of the same strip and band run back to back
+    int nrhs;
 };
 template <typename T>
 void launch_march_pre(const Grid& g, T w0, const T* x0, const T* f, T* out, const Grid& gc, T* rc, int nrhs,

@@ -132,9 +132,11 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int per = sh.blocks / XCDS;
     const int work = (blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
     if (work >= sh.work) return;  // uniform per wavefront
-    const int strip = work % sh.strips;
-    const int band = (work / sh.strips) % sh.segs;
-    const int z = work / (sh.strips * sh.segs);
+    const int zl = work % sh.zg, rest = work / sh.zg;
+    const int strip = rest % sh.strips;
+    const int band = (rest / sh.strips) % sh.segs;
+    const int z = (rest / (sh.strips * sh.segs)) * sh.zg + zl;
+    if (z >= sh.nrhs) return;  // a ragged last group of right-hand sides
     const int MSEG = sh.mseg;
     const int lane = threadIdx.x;
     // Odd bands run point-reflected: kernel position (i, r) is grid node
@@ -544,26 +546,36 @@ int device_wave_slots(K kernel) {
     return std::max(1, cus * per_cu);
 }
 
-// Rows per band: all wavefronts resident at once where the grid allows it
-// (a second partial round would double the time), else 64.
-MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows) {
+// Rows per band.  A wavefront walks its band's rows plus `extra` rows of
+// halo (rounded up to the unrolled body of `unr` rows), and the launch runs
+// in rounds of `slots` resident wavefronts, the last one possibly partial:
+// the band height is the one that minimises rounds x rows walked (taller
+// bands walk fewer halo rows in total, shorter ones leave less of a last
+// round idle).  rows > 0 fixes the height instead.
+MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows, int extra = 0, int unr = 1) {
     MarchShape sh{};
     sh.strips = (g.n + 1 + txo - 1) / txo;
     const long base = (long)sh.strips * nrhs;
     int mseg = rows;
     if (mseg <= 0) {
-        const long bands64 = (g.n + 1 + 63) / 64;
-        if (base * bands64 >= slots) {
-            mseg = 64;
-        } else {
-            const long bands = std::max<long>(1, slots / base);
-            mseg = (int)((g.n + 1 + bands - 1) / bands);
-            mseg = std::max(16, (mseg + 1) & ~1);
+        double best = 0.0;
+        for (int m = 16; m <= 512; m += 2) {
+            const long segs = (g.n + 1 + m - 1) / m;
+            const long rounds = (base * segs + slots - 1) / slots;
+            const long walked = (m + extra + unr - 1) / unr * unr;
+            const double cost = (double)rounds * walked;
+            if (mseg <= 0 || cost < best) {
+                best = cost;
+                mseg = m;
+            }
+            if (m >= g.n + 1) break;
         }
     }
     sh.mseg = (mseg + 1) & ~1;
     sh.segs = (g.n + 1 + sh.mseg - 1) / sh.mseg;
-    sh.work = (int)(base * sh.segs);
+    sh.zg = 1;
+    sh.nrhs = nrhs;
+    sh.work = (int)((long)sh.strips * sh.segs * nrhs);
     sh.blocks = (sh.work + XCDS - 1) / XCDS * XCDS;
     return sh;
 }
@@ -575,7 +587,8 @@ int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* 
                  hipStream_t st, EdgeW<T> ew = EdgeW<T>{nullptr, nullptr}) {
     constexpr int TXO = MW - 2 * march_halo(S);
     static const int slots = device_wave_slots(k_march<T, S, MODE, false, EW>);
-    const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows);
+    constexpr int UNR = MODE == 4 ? lcm_(3, prefetch_rows<T>()) : march_unroll(S, prefetch_rows<T>());
+    const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows, 2 * S + 4, UNR);
     if constexpr (MODE == 1) {
         if (x_zero) {
             hipLaunchKernelGGL((k_march<T, S, MODE, true, EW>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
@@ -644,11 +657,12 @@ template <int MODE>
 void march_dispatch_ew(const Grid& g, const float* x0, const float* f, float* out, const float* ec, const Grid& gc,
                        float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, const EdgeW<float>& ew,
                        hipStream_t st) {
+    const int rows = 0;
     switch (ss.s) {
-        case 1: march_launch<float, 1, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
-        case 2: march_launch<float, 2, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
-        case 3: march_launch<float, 3, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
-        case 4: march_launch<float, 4, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, 0, st, ew); break;
+        case 1: march_launch<float, 1, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
+        case 2: march_launch<float, 2, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
+        case 3: march_launch<float, 3, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
+        case 4: march_launch<float, 4, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
         default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
     }
 }

@@ -657,6 +657,24 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
     const Coef<double> c = member_coef(cg, bz, bs);
     const double* ur = u + (long)bz * stride;
     const float* er = ADD ? ecor + (long)bz * stride : nullptr;
+    // edge weights (single problems): the four weights of each node this
+    // thread forms A u at, loaded with the tile so that no load waits after
+    // the barrier
+    constexpr int NC = (BFX * BFY + 255) / 256;
+    constexpr bool PW = KIND == 1 && ZF;
+    double pw[PW ? NC : 1][4];
+    if constexpr (PW) {
+        const int p = g.pitch;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) {
+            const int t = tid + 256 * e;
+            const int a = t % BFX, b = t / BFX;
+            const int i = fi0 + a, j = fj0 + b;
+            const bool in = t < BFX * BFY && i <= g.m && j <= g.m;
+            const long id = g.idx(in ? i : fi0, in ? j : fj0);
+            pw[e][0] = c.wx[id], pw[e][1] = c.wx[id - 1], pw[e][2] = c.wy[id], pw[e][3] = c.wy[id - p];
+        }
+    }
     {
         // all of a thread's loads are issued before any of them is used
         constexpr int NPT = (BUX * BUY + 255) / 256;
@@ -679,7 +697,10 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
     __syncthreads();
     const double h2 = g.h * g.h;
     double ua = 0.0, um = 0.0;
-    for (int t = tid; t < BFX * BFY; t += 256) {
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+        const int t = tid + 256 * e;
+        if (t >= BFX * BFY) break;
         const int a = t % BFX, b = t / BFX;
         const int i = fi0 + a, j = fj0 + b;
         double Ax = 0.0, Mx = 0.0;
@@ -689,6 +710,9 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
             const double xne = us[b + 2][a + 2], xsw = us[b][a];
             if (KIND == 0) {
                 Ax = c.w0 * (4.0 * x0 - xe - xw - xn - xs);
+            } else if (PW) {
+                const double we = pw[e][0], ww = pw[e][1], wn = pw[e][2], ws = pw[e][3];
+                Ax = (we + ww + wn + ws) * x0 - we * xe - ww * xw - wn * xn - ws * xs;
             } else {
                 const long id = g.idx(i, j);
                 const int p = g.pitch;
