@@ -169,7 +169,6 @@ void launch_march_post_ew(const Grid& g, const float* wx, const float* wy, const
                           const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st);
 struct MarchShape {
     int strips, segs, mseg, work, blocks;
-    int zg;    // right-hand sides whose pieces of the same strip and band run back to back
     int nrhs;
 };
 template <typename T>

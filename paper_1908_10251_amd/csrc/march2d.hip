@@ -25,6 +25,10 @@
 //         wavefront), which the augmented pencil needs next.
 // Steps follow x_{t+1} = x_t + a_t (x_t - x_{t-1}) + b_t D^{-1} (f - A x_t)
 // with a_0 = 0 (a phase starts fresh).
+//
+// Levels with edge weights (per-element kappa, FP32 cycles) march in
+// k_march_ew below: PRE and POST as above, two right-hand sides per
+// wavefront sharing the weights.
 #include <algorithm>
 
 #include "common.h"
@@ -83,6 +87,15 @@ __device__ inline float detach(float v) {
     return r;
 }
 
+// 1 / d for the diagonal of an edge-weight row (positive, normal): the
+// hardware reciprocal refined by one Newton step (within an ulp of the
+// quotient, without the division's scaling and fix-up).
+__device__ inline float recip(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
+}
+__device__ inline double recip(double d) { return 1.0 / d; }
+
 // MODE 5: the coarse-space field q (padded level, ratio 2^lr to the fine grid)
 // that the first pre-smoothing interpolates, with the weights beta of the old
 // field and the eigenvalues lam of the right-hand side f = lam M x_0 it forms.
@@ -96,7 +109,7 @@ struct ProlongSrc {
     double* fout;
 };
 
-// EW: the level's edge weights (per-element kappa): wx at node (i, j) is the
+// The level's edge weights (per-element kappa): wx at node (i, j) is the
 // weight of the edge to (i + 1, j), wy the weight of the edge to (i, j + 1);
 // A x = sum over the four edges of w (x - x_neighbour), D = sum of the four.
 template <typename T>
@@ -105,13 +118,11 @@ struct EdgeW {
     const T* wy;
 };
 
-template <typename T, int S, int MODE, bool XZ, bool EW = false>
+template <typename T, int S, int MODE, bool XZ>
 __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_march(Grid g, T w0, const T* __restrict__ x0, const T* __restrict__ f,
                                               T* __restrict__ out, const T* __restrict__ ec, Grid gc,
                                               T* __restrict__ rc, T* __restrict__ rc2, double* __restrict__ part,
-                                              long sf, long sc, SmoothSteps st, MarchShape sh, ProlongSrc ps,
-                                              EdgeW<T> ew) {
-    static_assert(!EW || MODE == 1 || MODE == 2, "edge weights: pre-smoothing and post-smoothing phases only");
+                                              long sf, long sc, SmoothSteps st, MarchShape sh, ProlongSrc ps) {
     // MODE 4: the post-smoothing of one V-cycle and the pre-smoothing of the
     // next in one pass (S = post + pre stages; the host zeroes the momentum
     // coefficient of the first pre-smoothing stage)
@@ -132,11 +143,9 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int per = sh.blocks / XCDS;
     const int work = (blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
     if (work >= sh.work) return;  // uniform per wavefront
-    const int zl = work % sh.zg, rest = work / sh.zg;
-    const int strip = rest % sh.strips;
-    const int band = (rest / sh.strips) % sh.segs;
-    const int z = (rest / (sh.strips * sh.segs)) * sh.zg + zl;
-    if (z >= sh.nrhs) return;  // a ragged last group of right-hand sides
+    const int strip = work % sh.strips;
+    const int band = (work / sh.strips) % sh.segs;
+    const int z = work / (sh.strips * sh.segs);
     const int MSEG = sh.mseg;
     const int lane = threadIdx.x;
     // Odd bands run point-reflected: kernel position (i, r) is grid node
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     T bs[S], as[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        bs[t] = (MODE == 4 || EW) ? (T)st.b[t] : (T)st.b[t] * invD;  // MODE 4: scaled by the host; EW: 1/D per node
+        bs[t] = MODE == 4 ? (T)st.b[t] : (T)st.b[t] * invD;  // MODE 4: scaled by the host
         as[t] = (T)st.a[t];
     }
 
@@ -188,11 +197,6 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     T fw[S + 2][2];
     T rw[3][2];
     T mw[3][2];  // MODE 3: rw holds A u, mw holds M u
-    // EW: the weights and 1/D of the last S + 3 rows (index j: row r - j)
-    T cwx[EW ? S + 3 : 1][2], cwy[EW ? S + 3 : 1][2], cdi[EW ? S + 3 : 1][2];
-#pragma unroll
-    for (int j = 0; j < (EW ? S + 3 : 1); ++j)
-        cwx[j][0] = cwx[j][1] = cwy[j][0] = cwy[j][1] = cdi[j][0] = cdi[j][1] = T(0);
     double ua = 0.0, um = 0.0;
 #pragma unroll
     for (int t = 0; t <= S; ++t)
@@ -223,14 +227,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     struct Slot {
         T x[2], f[2], e0[2], e1[2];
         T q[2][3];  // MODE 5: the three coarse nodes of the triangle under each column
-        T wx[2], wy[2];  // EW: the weights of the edges east and north of each column (kernel orientation)
     };
-    // EW: in a reflected band the kernel's east edge of a node is the grid's
-    // west edge (wx one column lower, same row) and its north edge the grid's
-    // south edge (wy one row lower, same column); indices clamp at 0 only for
-    // kernel positions on the far boundary, whose east / north weights no
-    // interior node uses
-    const int wxa = flip ? max(ga - 1, 0) : ga, wxb = flip ? max(gb - 1, 0) : gb;
     auto load = [&](int r, Slot& sl) {
         const int rr = min(max(r, 0), g.n);
         const long row = (long)gx(rr) * g.pitch + ORIGIN;
@@ -254,13 +251,6 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         sl.f[0] = fr[row + ga];
         sl.f[1] = fr[row + gb];
-        if constexpr (EW) {
-            sl.wx[0] = ew.wx[row + wxa];
-            sl.wx[1] = ew.wx[row + wxb];
-            const long wyrow = (long)(flip ? max(gx(rr) - 1, 0) : rr) * g.pitch + ORIGIN;
-            sl.wy[0] = ew.wy[wyrow + ga];
-            sl.wy[1] = ew.wy[wyrow + gb];
-        }
         if (POSTLIKE || !XZ) {
             sl.x[0] = xr[row + ga];
             sl.x[1] = xr[row + gb];
@@ -307,23 +297,6 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             xw[0][2][cc] = xw[0][1][cc];
             xw[0][1][cc] = xw[0][0][cc];
             xw[0][0][cc] = cx;
-            if constexpr (EW) {
-#pragma unroll
-                for (int j = S + 2; j > 0; --j) {
-                    cwx[j][cc] = cwx[j - 1][cc];
-                    cwy[j][cc] = cwy[j - 1][cc];
-                    cdi[j][cc] = cdi[j - 1][cc];
-                }
-                cwx[0][cc] = detach(sl.wx[cc]);
-                cwy[0][cc] = detach(sl.wy[cc]);
-            }
-        }
-        if constexpr (EW) {
-            // 1 / D of row r: east, west (the left lane's east weight for the
-            // first column), north and south (row r - 1's north) weights
-            const T west0 = from_left(cwx[0][1]);
-            cdi[0][0] = T(1) / (cwx[0][0] + west0 + cwy[0][0] + cwy[1][0]);
-            cdi[0][1] = T(1) / (cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
         }
         if constexpr (PROLONG) {
             // f = lam M x_0 at row r - 1 from the x_0 rows (r, r-1, r-2): the
@@ -366,20 +339,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const T nb1 = m0 + right + xw[t - 1][0][1] + xw[t - 1][2][1];
             const T mc[2] = {m0, m1};
             const T nb[2] = {nb0, nb1};
-            if constexpr (EW) {
-                // weights of row q = r - t: window index t (south: t + 1)
-                const T we[2] = {cwx[t][0], cwx[t][1]};
-                const T ww[2] = {from_left(cwx[t][1]), cwx[t][0]};
-                const T xe[2] = {m1, right}, xwv[2] = {left, m0};
-#pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    const T Ax = we[cc] * (mc[cc] - xe[cc]) + ww[cc] * (mc[cc] - xwv[cc]) +
-                                 cwy[t][cc] * (mc[cc] - xw[t - 1][0][cc]) + cwy[t + 1][cc] * (mc[cc] - xw[t - 1][2][cc]);
-                    T val = mc[cc] + bs[t - 1] * ((fw[t][cc] - Ax) * cdi[t][cc]);
-                    if (t >= 2) val += as[t - 1] * (mc[cc] - xw[t - 2][2][cc]);
-                    v[cc] = (row_in && inner[cc]) ? val : T(0);
-                }
-            } else {
+            {
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
                 const T Ax = w0 * (T(4) * mc[cc] - nb[cc]);
@@ -413,14 +373,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const T nb0 = left + m1 + xw[S][0][0] + xw[S][2][0];
             const T nb1 = m0 + right + xw[S][0][1] + xw[S][2][1];
             T res0, res1;
-            if constexpr (EW) {
-                // weights of row q1 = r - S - 1: window index S + 1 (south: S + 2)
-                const T ww0 = from_left(cwx[S + 1][1]);
-                res0 = fw[S + 1][0] - (cwx[S + 1][0] * (m0 - m1) + ww0 * (m0 - left) +
-                                       cwy[S + 1][0] * (m0 - xw[S][0][0]) + cwy[S + 2][0] * (m0 - xw[S][2][0]));
-                res1 = fw[S + 1][1] - (cwx[S + 1][1] * (m1 - right) + cwx[S + 1][0] * (m1 - m0) +
-                                       cwy[S + 1][1] * (m1 - xw[S][0][1]) + cwy[S + 2][1] * (m1 - xw[S][2][1]));
-            } else {
+            {
                 res0 = fw[S + 1][0] - w0 * (T(4) * m0 - nb0);
                 res1 = fw[S + 1][1] - w0 * (T(4) * m1 - nb1);
             }
@@ -536,6 +489,312 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Edge-weight marching (per-element kappa, FP32 cycles) over NR right-hand
+// sides per wavefront.  The same marching order, windows and arithmetic as
+// k_march's edge-weight phases (PRE: S steps from x_0, residual, restriction;
+// POST: x_0 = x + P e_c, S steps), but a wavefront carries NR right-hand
+// sides of one strip and band together, so the two weight planes and 1/D are
+// read and formed once for all of them: the weights are as many bytes per node
+// as an FP32 vector pair, and reading them once per right-hand side made them
+// half of the launch's traffic.
+//
+// Loads and stores are raw buffer accesses over the NR right-hand sides'
+// blocks: each lane's column offsets are fixed for the whole march, a row's
+// offset and a right-hand side's block offset are uniform scalar offsets, so
+// no lane forms a 64-bit address per row.  Accesses of a right-hand side past
+// the last one (a ragged last group) fall outside the resource: loads return
+// 0, stores are dropped.  Stores that must not happen (halo columns, rows of
+// other bands) take an offset past the end of the resource instead of a
+// branch.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRawBufferWord3 = 0x00020000;  // 32-bit data format, raw (stride 0) addressing
+constexpr unsigned kDropped = 0x80000000u;   // out of range of every resource below (blocks < 2 GiB)
+__device__ inline rsrc_t make_rsrc(const void* p, long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kRawBufferWord3);
+}
+__device__ inline float bload(rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ inline void bstore(float v, rsrc_t r, unsigned vo) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, 0, 0);
+}
+
+template <int S, int PF>
+constexpr int ew_unroll() { return lcm_(lcm_(3, S + 2), PF); }
+
+template <int S, int MODE, bool XZ, int NR>
+__global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_march_ew(
+    Grid g, const float* __restrict__ x0, const float* __restrict__ f, float* __restrict__ out,
+    const float* __restrict__ ec, Grid gc, float* __restrict__ rc, long sf, long sc, SmoothSteps st, MarchShape sh,
+    EdgeW<float> ew) {
+    static_assert(MODE == 1 || MODE == 2, "edge-weight marching: PRE and POST phases");
+    using T = float;
+    constexpr bool POST = MODE == 2;
+    constexpr int PF = 6 / NR > 2 ? 6 / NR : 3;  // rows in flight
+    constexpr int HX = march_halo(S);
+    constexpr int TXO = MW - 2 * HX;
+    const int per = sh.blocks / XCDS;
+    const int work = (blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
+    if (work >= sh.work) return;  // uniform per wavefront
+    const int strip = work % sh.strips;
+    const int band = (work / sh.strips) % sh.segs;
+    const int z0 = (work / (sh.strips * sh.segs)) * NR;
+    const int nv = min(NR, sh.nrhs - z0);
+    const int MSEG = sh.mseg;
+    const int lane = threadIdx.x;
+    // odd bands point-reflected, as in k_march
+    const bool flip = band & 1;
+    const int y0 = flip ? g.n + 1 - (band + 1) * MSEG : band * MSEG;
+    const int fs = flip ? -1 : 1;
+    auto gx = [&](int i) { return flip ? g.n - i : i; };
+    auto gcx = [&](int I) { return flip ? gc.n - I : I; };
+    const int c0 = 2 * lane;
+    const int i0 = strip * TXO - HX + c0;  // global column (even)
+    bool inner[2], owned[2];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        inner[cc] = (i0 + cc) >= 1 && (i0 + cc) <= g.m;
+        owned[cc] = (c0 + cc) >= HX && (c0 + cc) < MW - HX;
+    }
+    // resources over the group's right-hand sides (blocks of sf words; the
+    // coarse blocks of sc words) and the two weight planes
+    const unsigned pb = (unsigned)(sf * 4), cb = (unsigned)(sc * 4);
+    const rsrc_t xs = make_rsrc((POST || !XZ) ? x0 + (long)z0 * sf : f, (long)nv * pb);
+    const rsrc_t fsr = make_rsrc(f + (long)z0 * sf, (long)nv * pb);
+    const rsrc_t os = make_rsrc(out + (long)z0 * sf, (long)nv * pb);
+    const rsrc_t es = make_rsrc(POST ? ec + (long)z0 * sc : f, POST ? (long)nv * cb : 0);
+    const rsrc_t rs = make_rsrc(POST ? out : rc + (long)z0 * sc, POST ? 0 : (long)nv * cb);
+    const rsrc_t wxs = make_rsrc(ew.wx, (long)sf * 4), wys = make_rsrc(ew.wy, (long)sf * 4);
+
+    T bs[S], as[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        bs[t] = (T)st.b[t];
+        as[t] = (T)st.a[t];
+    }
+    T xw[NR][S + 1][3][2];
+    T fw[NR][S + 2][2];
+    T rw[NR][3][2];
+    // the weights and 1/D of the last S + 2 rows (index j: row r - j), the
+    // west weight of the first column, and the north weights of row
+    // r - S - 2 (the residual's south weights); S + 2 rows, the f window's
+    // period
+    T cwx[S + 2][2], cwy[S + 2][2], cdi[S + 2][2], cww[S + 2];
+    T cwys[2] = {T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < S + 2; ++j) cwx[j][0] = cwx[j][1] = cwy[j][0] = cwy[j][1] = cdi[j][0] = cdi[j][1] = cww[j] = T(0);
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+#pragma unroll
+        for (int t = 0; t <= S; ++t)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xw[n][t][k][0] = xw[n][t][k][1] = T(0);
+#pragma unroll
+        for (int j = 0; j < S + 2; ++j) fw[n][j][0] = fw[n][j][1] = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rw[n][k][0] = rw[n][k][1] = T(0);
+    }
+
+    const int r_begin = y0 - 2 - S;
+    const int r_end = y0 + MSEG + S + 1;
+    // per-lane column offsets (bytes), fixed for the march; positions outside
+    // the grid clamp onto the boundary ring, whose stored values are zero
+    const int ia = min(max(i0, 0), g.n), ib = min(max(i0 + 1, 0), g.n);
+    const int ga = gx(ia), gb = gx(ib);
+    const unsigned va = 4u * ga, vb = 4u * gb;
+    // in a reflected band the kernel's east edge is the grid's west edge (wx
+    // one column lower) and its north edge the grid's south edge (wy one row
+    // lower)
+    const unsigned vwa = 4u * (flip ? max(ga - 1, 0) : ga), vwb = 4u * (flip ? max(gb - 1, 0) : gb);
+    // POST: coarse nodes (I, J) and (I + a, J + b) of each column's nodal
+    // interpolation (a = i & 1 per lane, b = r & 1 per row)
+    unsigned ve0[2], ve1[2];
+    {
+        const int cols[2] = {ia, ib};
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int i = cols[cc];
+            ve0[cc] = 4u * gcx(i >> 1);
+            ve1[cc] = 4u * (gcx(i >> 1) + fs * (i & 1));
+        }
+    }
+    // store offsets of the lane's columns (dropped outside the owned,
+    // interior columns)
+    const unsigned sa = (owned[0] && inner[0]) ? va : kDropped, sb = (owned[1] && inner[1]) ? vb : kDropped;
+    // restriction (PRE): the coarse node centred on the lane's first column
+    const int Ir = i0 >> 1;
+    const bool rown = owned[0] && Ir >= 1 && Ir <= gc.m;
+    const unsigned vr = 4u * gcx(Ir);
+
+    struct Slot {
+        T x[NR][2], f[NR][2], e0[NR][2], e1[NR][2];
+        T wx[2], wy[2];
+    };
+    auto load = [&](int r, Slot& sl) {
+        const int rr = min(max(r, 0), g.n);
+        const unsigned so = 4u * (unsigned)(gx(rr) * g.pitch + ORIGIN);
+        const unsigned sw = 4u * (unsigned)((flip ? max(gx(rr) - 1, 0) : rr) * g.pitch + ORIGIN);
+        sl.wx[0] = bload(wxs, vwa, so);
+        sl.wx[1] = bload(wxs, vwb, so);
+        sl.wy[0] = bload(wys, va, sw);
+        sl.wy[1] = bload(wys, vb, sw);
+        unsigned sc0 = 0, sc1 = 0;
+        if constexpr (POST) {
+            const int b = rr & 1;
+            sc0 = 4u * (unsigned)(gcx(rr >> 1) * gc.pitch + ORIGIN);
+            sc1 = 4u * (unsigned)(gcx(rr >> 1) * gc.pitch + ORIGIN + fs * b * gc.pitch);
+        }
+#pragma unroll
+        for (int n = 0; n < NR; ++n) {
+            sl.f[n][0] = bload(fsr, va, so + n * pb);
+            sl.f[n][1] = bload(fsr, vb, so + n * pb);
+            if (POST || !XZ) {
+                sl.x[n][0] = bload(xs, va, so + n * pb);
+                sl.x[n][1] = bload(xs, vb, so + n * pb);
+            }
+            if constexpr (POST) {
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    sl.e0[n][cc] = bload(es, ve0[cc], sc0 + n * cb);
+                    sl.e1[n][cc] = bload(es, ve1[cc], sc1 + n * cb);
+                }
+            }
+        }
+    };
+    // row r enters the windows
+    auto shift_in = [&](const Slot& sl, const int r) {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+                T cx;
+                if constexpr (POST) cx = sl.x[n][cc] + T(0.5) * (sl.e0[n][cc] + sl.e1[n][cc]);
+                else if constexpr (!XZ) cx = detach(sl.x[n][cc]);
+                else cx = T(0);
+#pragma unroll
+                for (int j = S + 1; j > 0; --j) fw[n][j][cc] = fw[n][j - 1][cc];
+                fw[n][0][cc] = detach(sl.f[n][cc]);
+                xw[n][0][2][cc] = xw[n][0][1][cc];
+                xw[n][0][1][cc] = xw[n][0][0][cc];
+                xw[n][0][0][cc] = cx;
+            }
+            cwys[cc] = cwy[S + 1][cc];
+#pragma unroll
+            for (int j = S + 1; j > 0; --j) {
+                cwx[j][cc] = cwx[j - 1][cc];
+                cwy[j][cc] = cwy[j - 1][cc];
+                cdi[j][cc] = cdi[j - 1][cc];
+            }
+            cwx[0][cc] = detach(sl.wx[cc]);
+            cwy[0][cc] = detach(sl.wy[cc]);
+        }
+#pragma unroll
+        for (int j = S + 1; j > 0; --j) cww[j] = cww[j - 1];
+        // 1 / D of row r: east, west (the left lane's east weight for the
+        // first column), north and south (row r - 1's north) weights
+        cww[0] = from_left(cwx[0][1]);
+        cdi[0][0] = recip(cwx[0][0] + cww[0] + cwy[0][0] + cwy[1][0]);
+        cdi[0][1] = recip(cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
+    };
+    // after row r entered: every stage advances one row, x_S of row r - S is
+    // stored, and (PRE) the residual and its restriction
+    auto advance = [&](const int r) {
+#pragma unroll
+        for (int t = 1; t <= S; ++t) {
+            const int q = r - t;
+            const bool row_in = q >= 1 && q <= g.m;  // uniform
+            const T we[2] = {cwx[t][0], cwx[t][1]};
+            const T ww[2] = {cww[t], cwx[t][0]};
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+                const T m0 = xw[n][t - 1][1][0], m1 = xw[n][t - 1][1][1];
+                const T left = from_left(m1), right = from_right(m0);
+                const T mc[2] = {m0, m1};
+                const T xe[2] = {m1, right}, xwv[2] = {left, m0};
+                T v[2];
+                // x + b ((f + sum w x_nb) / D - x)
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    T sfv = __builtin_fmaf(we[cc], xe[cc], fw[n][t][cc]);
+                    sfv = __builtin_fmaf(ww[cc], xwv[cc], sfv);
+                    sfv = __builtin_fmaf(cwy[t][cc], xw[n][t - 1][0][cc], sfv);
+                    sfv = __builtin_fmaf(cwy[t + 1][cc], xw[n][t - 1][2][cc], sfv);
+                    T val = __builtin_fmaf(bs[t - 1], __builtin_fmaf(sfv, cdi[t][cc], -mc[cc]), mc[cc]);
+                    if (t >= 2) val = __builtin_fmaf(as[t - 1], mc[cc] - xw[n][t - 2][2][cc], val);
+                    v[cc] = (row_in && inner[cc]) ? val : T(0);
+                }
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    xw[n][t][2][cc] = xw[n][t][1][cc];
+                    xw[n][t][1][cc] = xw[n][t][0][cc];
+                    xw[n][t][0][cc] = v[cc];
+                }
+            }
+        }
+        {
+            const int q = r - S;
+            const bool st_row = q >= y0 && q < y0 + MSEG && q >= 1 && q <= g.m;  // uniform
+            const unsigned so = 4u * (unsigned)(gx(max(q, 0)) * g.pitch + ORIGIN);
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+                bstore(xw[n][S][0][0], os, st_row ? so + n * pb + sa : kDropped);
+                bstore(xw[n][S][0][1], os, st_row ? so + n * pb + sb : kDropped);
+            }
+        }
+        if constexpr (!POST) {
+            // residual at row r - S - 1 from x_S rows (r-S, r-S-1, r-S-2), in
+            // the difference form (the restricted residual is small against
+            // D x once the error is smooth); then the restriction to the
+            // coarse node centred at (i0, r - S - 2)
+            const int q1 = r - S - 1;
+            const bool row_in = q1 >= 1 && q1 <= g.m;
+            const int q2 = r - S - 2;
+            const bool rrow = ((q2 & 1) == 0) && q2 >= y0 && q2 < y0 + MSEG && (q2 >> 1) >= 1 && (q2 >> 1) <= gc.m;
+            const unsigned sor = 4u * (unsigned)(gcx(max(q2, 0) >> 1) * gc.pitch + ORIGIN);
+            const T ww0 = cww[S + 1];
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+                const T m0 = xw[n][S][1][0], m1 = xw[n][S][1][1];
+                const T left = from_left(m1), right = from_right(m0);
+                T res0 = fw[n][S + 1][0] - (cwx[S + 1][0] * (m0 - m1) + ww0 * (m0 - left) +
+                                            cwy[S + 1][0] * (m0 - xw[n][S][0][0]) + cwys[0] * (m0 - xw[n][S][2][0]));
+                T res1 = fw[n][S + 1][1] - (cwx[S + 1][1] * (m1 - right) + cwx[S + 1][0] * (m1 - m0) +
+                                            cwy[S + 1][1] * (m1 - xw[n][S][0][1]) + cwys[1] * (m1 - xw[n][S][2][1]));
+                res0 = (row_in && inner[0]) ? res0 : T(0);
+                res1 = (row_in && inner[1]) ? res1 : T(0);
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    rw[n][2][cc] = rw[n][1][cc];
+                    rw[n][1][cc] = rw[n][0][cc];
+                }
+                rw[n][0][0] = res0;
+                rw[n][0][1] = res1;
+                const T mid_left = from_left(rw[n][1][1]);  // (i0-1, q2)
+                const T dn_left = from_left(rw[n][2][1]);   // (i0-1, q2-1)
+                const T rv = rw[n][1][0] + T(0.5) * (rw[n][1][1] + mid_left + rw[n][0][0] + rw[n][2][0] +
+                                                     rw[n][0][1] + dn_left);
+                bstore(rv, rs, (rrow && rown) ? sor + n * cb + vr : kDropped);
+            }
+        }
+    };
+
+    Slot q[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load(r_begin + p, q[p]);
+    constexpr int UNR = ew_unroll<S, PF>();
+    const int iters = (r_end - r_begin + UNR) / UNR;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int r = r_begin + it * UNR + u;
+            shift_in(q[u % PF], r);
+            load(r + PF, q[u % PF]);
+            advance(r);
+        }
+    }
+}
+
 // Workgroup slots of the whole device for a kernel (one wavefront each).
 template <typename K>
 int device_wave_slots(K kernel) {
@@ -573,7 +832,6 @@ MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows, in
     }
     sh.mseg = (mseg + 1) & ~1;
     sh.segs = (g.n + 1 + sh.mseg - 1) / sh.mseg;
-    sh.zg = 1;
     sh.nrhs = nrhs;
     sh.work = (int)((long)sh.strips * sh.segs * nrhs);
     sh.blocks = (sh.work + XCDS - 1) / XCDS * XCDS;
@@ -581,24 +839,24 @@ MarchShape march_shape(const Grid& g, int txo, int nrhs, int slots, int rows, in
 }
 
 // Returns the wavefronts per right-hand side (MODE 3: pairs of sums in part).
-template <typename T, int S, int MODE, bool EW = false>
+template <typename T, int S, int MODE>
 int march_launch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T* ec, const Grid& gc, T* rc, T* rc2,
                  double* part, int nrhs, long sf, long sc, const SmoothSteps& ss, bool x_zero, int rows,
-                 hipStream_t st, EdgeW<T> ew = EdgeW<T>{nullptr, nullptr}) {
+                 hipStream_t st) {
     constexpr int TXO = MW - 2 * march_halo(S);
-    static const int slots = device_wave_slots(k_march<T, S, MODE, false, EW>);
+    static const int slots = device_wave_slots(k_march<T, S, MODE, false>);
     constexpr int UNR = MODE == 4 ? lcm_(3, prefetch_rows<T>()) : march_unroll(S, prefetch_rows<T>());
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, rows, 2 * S + 4, UNR);
     if constexpr (MODE == 1) {
         if (x_zero) {
-            hipLaunchKernelGGL((k_march<T, S, MODE, true, EW>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
-                               gc, rc, rc2, part, sf, sc, ss, sh, ProlongSrc{}, ew);
+            hipLaunchKernelGGL((k_march<T, S, MODE, true>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec,
+                               gc, rc, rc2, part, sf, sc, ss, sh, ProlongSrc{});
             PASM_CHECK_LAUNCH();
             return sh.strips * sh.segs;
         }
     }
-    hipLaunchKernelGGL((k_march<T, S, MODE, false, EW>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
-                       rc2, part, sf, sc, ss, sh, ProlongSrc{}, ew);
+    hipLaunchKernelGGL((k_march<T, S, MODE, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x0, f, out, ec, gc, rc,
+                       rc2, part, sf, sc, ss, sh, ProlongSrc{});
     PASM_CHECK_LAUNCH();
     return sh.strips * sh.segs;
 }
@@ -621,8 +879,7 @@ void march_pair_launch(const Grid& g, double w0, const double* x, const double* 
     static const int slots = device_wave_slots(k_march<double, S, 4, false>);
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, one_round_rows(g, TXO, nrhs, slots));
     hipLaunchKernelGGL((k_march<double, S, 4, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, x, f, out, ec, gc,
-                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh, ProlongSrc{},
-                       EdgeW<double>{nullptr, nullptr});
+                       rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh, ProlongSrc{});
     PASM_CHECK_LAUNCH();
 }
 
@@ -636,7 +893,7 @@ void march_prolong_launch(const Grid& g, double w0, const double* u, double* fou
     const MarchShape sh = march_shape(g, TXO, nrhs, slots, one_round_rows(g, TXO, nrhs, slots));
     hipLaunchKernelGGL((k_march<double, S, 5, false>), dim3(sh.blocks), dim3(NL), 0, st, g, w0, u, fout, out,
                        (const double*)nullptr, gc, rc, (double*)nullptr, (double*)nullptr, g.plane, gc.plane, ss, sh,
-                       ps, EdgeW<double>{nullptr, nullptr});
+                       ps);
     PASM_CHECK_LAUNCH();
 }
 
@@ -653,18 +910,47 @@ int march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T
     }
 }
 
+// Edge-weight phases: NR right-hand sides per wavefront (a ragged last
+// group is padded by right-hand sides whose accesses fall outside the
+// buffers).
+template <int S, int MODE, int NR>
+void march_launch_ew(const Grid& g, const float* x0, const float* f, float* out, const float* ec, const Grid& gc,
+                     float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, const EdgeW<float>& ew,
+                     hipStream_t st) {
+    constexpr int TXO = MW - 2 * march_halo(S);
+    constexpr int PF = 6 / NR > 2 ? 6 / NR : 3;
+    static const int slots = device_wave_slots(k_march_ew<S, MODE, false, NR>);
+    const int ngrp = (nrhs + NR - 1) / NR;
+    MarchShape sh = march_shape(g, TXO, ngrp, slots, 0, 2 * S + 4, ew_unroll<S, PF>());
+    sh.nrhs = nrhs;
+    if (MODE == 1 && x_zero)
+        hipLaunchKernelGGL((k_march_ew<S, MODE, true, NR>), dim3(sh.blocks), dim3(NL), 0, st, g, x0, f, out, ec, gc,
+                           rc, g.plane, gc.plane, ss, sh, ew);
+    else
+        hipLaunchKernelGGL((k_march_ew<S, MODE, false, NR>), dim3(sh.blocks), dim3(NL), 0, st, g, x0, f, out, ec, gc,
+                           rc, g.plane, gc.plane, ss, sh, ew);
+    PASM_CHECK_LAUNCH();
+}
+
+template <int MODE, int NR>
+void march_dispatch_ew_nr(const Grid& g, const float* x0, const float* f, float* out, const float* ec,
+                          const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero,
+                          const EdgeW<float>& ew, hipStream_t st) {
+    switch (ss.s) {
+        case 1: march_launch_ew<1, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 2: march_launch_ew<2, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 3: march_launch_ew<3, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 4: march_launch_ew<4, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
+    }
+}
+
 template <int MODE>
 void march_dispatch_ew(const Grid& g, const float* x0, const float* f, float* out, const float* ec, const Grid& gc,
                        float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, const EdgeW<float>& ew,
                        hipStream_t st) {
-    const int rows = 0;
-    switch (ss.s) {
-        case 1: march_launch<float, 1, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
-        case 2: march_launch<float, 2, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
-        case 3: march_launch<float, 3, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
-        case 4: march_launch<float, 4, MODE, true>(g, 1.f, x0, f, out, ec, gc, rc, nullptr, nullptr, nrhs, g.plane, gc.plane, ss, x_zero, rows, st, ew); break;
-        default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
-    }
+    if (nrhs >= 2) march_dispatch_ew_nr<MODE, 2>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
+    else march_dispatch_ew_nr<MODE, 1>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
 }
 
 }  // namespace

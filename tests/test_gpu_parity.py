@@ -173,6 +173,44 @@ def test_vcycle_kappa_2048_matches_oracle(precision):
             assert err < tol
 
 
+@pytest.mark.parametrize("smoother,nu", [("cheb", 4), ("jacobi", 3), ("cheb", 2), ("jacobi", 1)])
+def test_vcycle_kappa_odd_rhs_count_matches_oracle(smoother, nu):
+    # FP32 cycles on edge-weight levels march two right-hand sides per
+    # wavefront: three right-hand sides leave a ragged last pair, and every
+    # step count has its own kernel.  Each right-hand side against the
+    # oracle's V-cycle, and the first one against a context of one
+    # right-hand side (a partner must not leak into it).
+    nc, nf, k = 8, 512, 3
+    _say(f"vcycle kappa h=1/{nf} k={k} {smoother} nu={nu} mixed")
+    kap = lognormal_kappa(2, nf, seed=21, sigma=1.0)
+    A, _ = fem.assemble(2, nf, kappa=kap)
+    hier = Hierarchy(2, A, nc, nf)
+    opts = default_options(2, smoother, nu, nu, 1)
+    rng = np.random.default_rng(23)
+    N = A.shape[0]
+    f = rng.standard_normal((k, N))
+    x0 = rng.standard_normal((k, N))
+    o = _opts(smoother, nu, precision=P.PASM_MIXED)
+    with P.Solver(2, 1 / nc, 1 / nf, k, kappa=kap, opts=o) as s:
+        xg = _t(x0)
+        P.pasm_vcycle(s.ctx, _t(f), xg, 2)
+        xg = xg.cpu().numpy()
+    with P.Solver(2, 1 / nc, 1 / nf, 1, kappa=kap, opts=o) as s1:
+        x1 = _t(x0[:1])
+        P.pasm_vcycle(s1.ctx, _t(f[:1]), x1, 2)
+        x1 = x1.cpu().numpy()[0]
+    for r in range(k):
+        xr = x0[r].copy()
+        for _ in range(2):
+            xr = hier.vcycle(len(hier.levels) - 1, xr, f[r], opts)
+        err = np.max(np.abs(xg[r] - xr)) / np.max(np.abs(xr))
+        _say(f"  rhs={r} err={err:.2e}")
+        assert err < 2e-5, (r, err)
+    d = np.max(np.abs(xg[0] - x1)) / np.max(np.abs(x1))
+    _say(f"  rhs 0 alone vs with partners: {d:.2e}")
+    assert d < 1e-6
+
+
 @pytest.mark.parametrize("nf,smoother,pre,post", [(256, "cheb", 4, 4), (512, "jacobi", 2, 2), (256, "cheb", 3, 1),
                                                   (512, "cheb", 1, 4), (256, "jacobi", 1, 1), (512, "jacobi", 3, 3)])
 def test_paired_smoothing_phases_equal_single_cycles(nf, smoother, pre, post):
