@@ -90,6 +90,9 @@ struct pasm_ctx {
     // FP64 residual passes of a mixed-precision step form it from u (2D edge
     // weights, at most two V-cycles, so that u is still the step's start).
     bool f_mass = false;
+    // R32 holds the first residual of the next correction step (formed by
+    // the prolongation pass that produced u; f_mass contexts)
+    bool r32_ready = false;
     std::vector<pasm::Level> lv;
     // finest level, FP64 (padded layout: boundary entries stay zero)
     double *U = nullptr, *F64 = nullptr, *Y64 = nullptr, *R64 = nullptr;
@@ -579,7 +582,10 @@ std::vector<double> resid_norms(pasm_ctx* c, const double* x, const double* f, i
 void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, int ncycles,
                 bool border = false, bool eig = false) {
     if (!c->learned_on) {
-        bool r_ready = false;
+        // the first residual of a correction step may come from the
+        // prolongation that formed u; any other call forms its own
+        bool r_ready = eig && c->r32_ready;
+        c->r32_ready = false;
         c->fine_pre_done = false;
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
@@ -1076,8 +1082,16 @@ void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, b
         // 2D: from the coarse space straight to the finest level (P1
         // interpolation on the coarse triangles), with the next step's
         // right-hand side lambda M u from the same pass
-        pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->f_mass ? nullptr : c->F64, k, L0.g.plane,
-                                  c->sf(), s, lamf ? lamf : c->mu, c->st);
+        if (c->f_mass) {
+            // and the next step's first residual lambda M u - A u, in FP32
+            const pasm::Coef<double>& cf = c->coef<double>(c->L - 1);
+            pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, nullptr, k, L0.g.plane, c->sf(), s,
+                                      lamf ? lamf : c->mu, c->st, cf.wx, cf.wy, c->R32);
+            c->r32_ready = true;
+        } else {
+            pasm::launch_prolong_mass(L0.g, L0.B, c->gf(), c->U, c->Y64, c->F64, k, L0.g.plane, c->sf(), s,
+                                      lamf ? lamf : c->mu, c->st);
+        }
         std::swap(c->U, c->Y64);
         c->f_ready = !c->f_mass;
         return;
@@ -1706,6 +1720,7 @@ PASM_API pasm_status pasm_set_state(pasm_ctx* c, const double* lambda, const dou
             }
     PASM_TRY(c, {
         c->prolong_pending = false;  // the state is replaced
+        c->r32_ready = false;
         c->lam_h.assign(lambda, lambda + c->k);
         c->lam_prev_h = c->lam_h;
         PASM_HIP(hipMemcpyAsync(c->lam, lambda, c->k * sizeof(double), hipMemcpyHostToDevice, c->st));

@@ -240,10 +240,13 @@ void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, co
 void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                           double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                           hipStream_t st);
-// xn = P xc + beta[r] xo and f = lam[r] M xn (double; xn != xo)
+// xn = P xc + beta[r] xo and f = lam[r] M xn (double; xn != xo; f may be
+// null).  With r32 (2D, edge weights wx, wy of the fine level, f null):
+// r32 = lam[r] M xn - A xn in FP32 instead of f.
 void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
-                         hipStream_t st);
+                         hipStream_t st, const double* wx = nullptr, const double* wy = nullptr,
+                         float* r32 = nullptr);
 // x_f = alpha * (P x_c) + beta[r] * x_f  (beta == nullptr: x_f = P x_c;
 // add = true: x_f += P x_c)
 template <typename T>

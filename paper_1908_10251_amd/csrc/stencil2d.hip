@@ -777,19 +777,25 @@ __global__ __launch_bounds__(256) void k_border_restrict_t(Grid g, Coef<double> 
 //   xn = ((R - a) x(I,J) + (a - b) x(I+1,J) + b x(I+1,J+1)) / R,
 // on the upper one the same with the roles of a, b and of (I+1,J), (I,J+1)
 // exchanged (R = 2 gives the midpoints of the coarse edges).
+// RES (edge weights wx, wy of the fine level): instead of f, the next
+// step's first residual r = lam M xn - A xn, rounded to FP32, with the
+// arithmetic of the residual kernel (k_resid_cast with the mass term), so
+// that it equals what that kernel would form from xn.
 constexpr int PMX = 64, PMY = 16;
+// A workgroup covers one tile for RB right-hand sides in turn (RES: the
+// weights of its nodes are loaded once for all of them).
+template <bool RES = false, int RB = 1>
 __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __restrict__ xc, Grid gf,
                                                       const double* __restrict__ xo, double* __restrict__ xn,
                                                       double* __restrict__ f, long sc, long sf,
                                                       const double* __restrict__ beta,
-                                                      const double* __restrict__ lam, int lr) {
-    constexpr int UX = PMX + 2, UY = PMY + 2, NPT = (UX * UY + 255) / 256;
+                                                      const double* __restrict__ lam, int lr,
+                                                      const double* __restrict__ wx, const double* __restrict__ wy,
+                                                      float* __restrict__ r32, int nrhs) {
+    constexpr int UX = PMX + 2, UY = PMY + 2, NPT = (UX * UY + 255) / 256, NO = PMX * PMY / 256;
     __shared__ double us[UY][UX];
-    const int tid = threadIdx.x, z = blockIdx.z;
+    const int tid = threadIdx.x;
     const int i0 = blockIdx.x * PMX + 1, j0 = blockIdx.y * PMY + 1;
-    const double* cr = xc + (long)z * sc;
-    const double* xr = xo + (long)z * sf;
-    const double bz = beta[z], lz = lam[z];
     const int R = 1 << lr;
     const double invR = 1.0 / R;
     // the coarse nodes under the tile and its halo (at most 35 x 11 for R >= 2)
@@ -797,7 +803,6 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
     __shared__ double cs[CSY][CSX];
     const int I0 = (i0 - 1) >> lr, J0 = (j0 - 1) >> lr;
     const int CX = min(((i0 + PMX) >> lr) - I0 + 2, CSX), CY = min(((j0 + PMY) >> lr) - J0 + 2, CSY);
-    double xv[NPT];
     bool ok[NPT];
     int ic_[NPT], jc_[NPT];
 #pragma unroll
@@ -807,39 +812,73 @@ __global__ __launch_bounds__(256) void k_prolong_mass(Grid gc, const double* __r
         ok[e] = t < UX * UY && i >= 1 && i <= gf.m && j >= 1 && j <= gf.m;
         ic_[e] = ok[e] ? i : i0;
         jc_[e] = ok[e] ? j : j0;
-        xv[e] = xr[gf.idx(ic_[e], jc_[e])];
     }
-    for (int t = tid; t < CX * CY; t += 256) {
-        const int a = t % CX, b = t / CX;
-        cs[b][a] = cr[gc.idx(min(I0 + a, gc.n), min(J0 + b, gc.n))];
-    }
-    __syncthreads();
+    // the thread's output nodes t = tid + 256 e and (RES) their four weights
+    double w4[RES ? NO : 1][4];
+    if constexpr (RES) {
+        const int p = gf.pitch;
 #pragma unroll
-    for (int e = 0; e < NPT; ++e) {
-        const int t = tid + 256 * e;
-        const int a = ic_[e] & (R - 1), b = jc_[e] & (R - 1);
-        const int ir = (ic_[e] >> lr) - I0, jr = (jc_[e] >> lr) - J0;  // within the staged block
-        const bool lower = a >= b;
-        const int wa = lower ? a : b, wb = lower ? b : a;  // the larger and the smaller offset
-        const double c0 = cs[jr][ir], c1 = lower ? cs[jr][ir + 1] : cs[jr + 1][ir], c2 = cs[jr + 1][ir + 1];
-        // explicit fused multiply-adds: the marching pre-smoothing that forms
-        // the same field on the fly rounds identically
-        double v = __builtin_fma((double)wb, c2, __builtin_fma((double)(wa - wb), c1, (double)(R - wa) * c0)) * invR;
-        if (bz != 0.0) v = __builtin_fma(bz, xv[e], v);  // a zero weight drops the old field (whatever it holds)
-        if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
+        for (int e = 0; e < NO; ++e) {
+            const int t = tid + 256 * e;
+            const int i = min(i0 + t % PMX, gf.m), j = min(j0 + t / PMX, gf.m);
+            const long gid = gf.idx(i, j);
+            w4[e][0] = wx[gid], w4[e][1] = wx[gid - 1], w4[e][2] = wy[gid], w4[e][3] = wy[gid - p];
+        }
     }
-    __syncthreads();
     const double h2 = gf.h * gf.h;
-    for (int t = tid; t < PMX * PMY; t += 256) {
-        const int a = t % PMX, b = t / PMX;
-        const int i = i0 + a, j = j0 + b;
-        if (i > gf.m || j > gf.m) continue;
-        const double x0 = us[b + 1][a + 1];
-        const double sn = us[b + 1][a + 2] + us[b + 1][a] + us[b + 2][a + 1] + us[b][a + 1] + us[b + 2][a + 2] +
-                          us[b][a];
-        const long id = (long)z * sf + gf.idx(i, j);
-        xn[id] = x0;
-        if (f) f[id] = lz * (h2 * __builtin_fma(sn, 1.0 / 12.0, 0.5 * x0));
+    for (int q = 0; q < RB; ++q) {
+        const int z = blockIdx.z * RB + q;
+        if (z >= nrhs) break;  // uniform per workgroup
+        if (q > 0) __syncthreads();  // the previous right-hand side's tile is consumed
+        const double* cr = xc + (long)z * sc;
+        const double* xr = xo + (long)z * sf;
+        const double bz = beta[z], lz = lam[z];
+        double xv[NPT];
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) xv[e] = xr[gf.idx(ic_[e], jc_[e])];
+        for (int t = tid; t < CX * CY; t += 256) {
+            const int a = t % CX, b = t / CX;
+            cs[b][a] = cr[gc.idx(min(I0 + a, gc.n), min(J0 + b, gc.n))];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            const int t = tid + 256 * e;
+            const int a = ic_[e] & (R - 1), b = jc_[e] & (R - 1);
+            const int ir = (ic_[e] >> lr) - I0, jr = (jc_[e] >> lr) - J0;  // within the staged block
+            const bool lower = a >= b;
+            const int wa = lower ? a : b, wb = lower ? b : a;  // the larger and the smaller offset
+            const double c0 = cs[jr][ir], c1 = lower ? cs[jr][ir + 1] : cs[jr + 1][ir], c2 = cs[jr + 1][ir + 1];
+            // explicit fused multiply-adds: the marching pre-smoothing that
+            // forms the same field on the fly rounds identically
+            double v =
+                __builtin_fma((double)wb, c2, __builtin_fma((double)(wa - wb), c1, (double)(R - wa) * c0)) * invR;
+            if (bz != 0.0) v = __builtin_fma(bz, xv[e], v);  // a zero weight drops the old field (whatever it holds)
+            if (t < UX * UY) us[t / UX][t % UX] = ok[e] ? v : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < NO; ++e) {
+            const int t = tid + 256 * e;
+            const int a = t % PMX, b = t / PMX;
+            const int i = i0 + a, j = j0 + b;
+            if (i > gf.m || j > gf.m) continue;
+            const double x0 = us[b + 1][a + 1];
+            const double sn = us[b + 1][a + 2] + us[b + 1][a] + us[b + 2][a + 1] + us[b][a + 1] + us[b + 2][a + 2] +
+                              us[b][a];
+            const long gid = gf.idx(i, j), id = (long)z * sf + gid;
+            xn[id] = x0;
+            const double fv = lz * (h2 * __builtin_fma(sn, 1.0 / 12.0, 0.5 * x0));
+            if constexpr (RES) {
+                const double we = w4[e][0], ww = w4[e][1], wn = w4[e][2], ws = w4[e][3];
+                const double D = we + ww + wn + ws;
+                const double Ax = D * x0 - we * us[b + 1][a + 2] - ww * us[b + 1][a] - wn * us[b + 2][a + 1] -
+                                  ws * us[b][a + 1];
+                r32[id] = (float)(fv - Ax);
+            } else {
+                if (f) f[id] = fv;
+            }
+        }
     }
 }
 
@@ -1055,8 +1094,10 @@ void launch_prolong(const Grid& gc, const T* xc, const Grid& gf, T* xf, int nrhs
 
 void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                          double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
-                         hipStream_t st) {
+                         hipStream_t st, const double* wx, const double* wy, float* r32) {
     if (xn == xo) throw Error(PASM_E_INVALID, "prolong with mass: separate output");
+    if (r32 && (gf.dim != 2 || !wx || !wy || f))
+        throw Error(PASM_E_INVALID, "prolong with the first residual: 2D edge weights, no f");
     if (gf.dim == 3) {
         if (gc.n * 2 != gf.n) throw Error(PASM_E_INVALID, "prolong with mass (3D): ratio 2");
         return launch_prolong_mass3(gc, xc, gf, xo, xn, f, nrhs, sc, sf, beta, lam, st);
@@ -1065,7 +1106,15 @@ void launch_prolong_mass(const Grid& gc, const double* xc, const Grid& gf, const
     while ((gc.n << lr) < gf.n) ++lr;
     if (lr < 1 || (gc.n << lr) != gf.n) throw Error(PASM_E_INVALID, "prolong with mass: power-of-two ratio");
     dim3 grid((gf.m + PMX - 1) / PMX, (gf.m + PMY - 1) / PMY, nrhs);
-    hipLaunchKernelGGL(k_prolong_mass, grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta, lam, lr);
+    if (r32) {
+        constexpr int RB = 5;
+        grid.z = (nrhs + RB - 1) / RB;
+        hipLaunchKernelGGL((k_prolong_mass<true, RB>), grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta,
+                           lam, lr, wx, wy, r32, nrhs);
+    } else {
+        hipLaunchKernelGGL((k_prolong_mass<false, 1>), grid, dim3(256), 0, st, gc, xc, gf, xo, xn, f, sc, sf, beta,
+                           lam, lr, wx, wy, r32, nrhs);
+    }
     PASM_CHECK_LAUNCH();
 }
 
