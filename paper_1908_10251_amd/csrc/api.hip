@@ -590,9 +590,10 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
         for (int cy = 0; cy < ncycles; ++cy) {
             // the last FP64 cycle may form the borders of the next step on its way out
             c->border_next = border && cy == ncycles - 1 && !c->mixed;
+            const int kind = pasm::coef_kind(c->coef<double>(c->L - 1));
             const bool defer = cy == ncycles - 1 && c->mixed && eig &&
-                               ((border && c->dim == 2 && pasm::coef_kind(c->coef<double>(c->L - 1)) <= 1) ||
-                                c->lv[c->L - 1].general3);
+                               ((border && c->dim == 2 && kind <= 1) || c->lv[c->L - 1].general3 ||
+                                (c->dim == 3 && kind == 0));
             // f = lam M u formed by the residual passes (the first two cycles
             // of a step start from u itself or from u + e with u still in x)
             const double* lam_mass = (eig && c->f_mass && cy < 2) ? c->lam : nullptr;
@@ -884,7 +885,8 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
     }
     const int N = c->NH;
     c->general_coef = general || general3;
-    c->f_mass = c->mixed && c->L >= 2 && c->opt.vcycles <= 2 &&
+    // (not with the learned smoother: its cycle checks read f itself)
+    c->f_mass = c->mixed && c->L >= 2 && c->opt.vcycles <= 2 && c->opt.smoother != PASM_LEARNED &&
                 pasm::mass_rhs_fusable(c->gf(), c->coef<double>(c->L - 1));
     if (share) {
         c->coarse_shared = true;
@@ -1103,10 +1105,10 @@ void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, b
     if (s) {
         // the new u into the scratch field (then swapped in), with the next
         // step's right-hand side lambda M u from the same pass
-        pasm::launch_prolong_mass(Lc.g, Lc.B, c->gf(), c->U, c->Y64, c->F64, k, Lc.g.plane, c->sf(), s,
-                                  lamf ? lamf : c->mu, c->st);
+        pasm::launch_prolong_mass(Lc.g, Lc.B, c->gf(), c->U, c->Y64, c->f_mass ? nullptr : c->F64, k, Lc.g.plane,
+                                  c->sf(), s, lamf ? lamf : c->mu, c->st);
         std::swap(c->U, c->Y64);
-        c->f_ready = true;
+        c->f_ready = !c->f_mass;
         return;
     }
     pasm::launch_prolong<double>(Lc.g, Lc.B, c->gf(), c->U, k, Lc.g.plane, c->sf(), false, s, c->st);
@@ -1151,8 +1153,10 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
         int nblk;
         if (c->e_pending) {
             // u~ = x + e (the last correction) and the borders of u~ in one pass
-            nblk = pasm::launch_border_restrict_add(g, c->coef<double>(lf), c->U, c->E32, c->Y64, Lc.g, Lc.B, Lc.C,
-                                                    c->partial, k, sf, Lc.g.plane, c->st);
+            nblk = c->dim == 2 ? pasm::launch_border_restrict_add(g, c->coef<double>(lf), c->U, c->E32, c->Y64, Lc.g,
+                                                                  Lc.B, Lc.C, c->partial, k, sf, Lc.g.plane, c->st)
+                               : pasm::launch_border_restrict3(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
+                                                               c->partial, k, sf, Lc.g.plane, c->st, c->E32, c->Y64);
             std::swap(c->U, c->Y64);
             c->e_pending = false;
         } else {

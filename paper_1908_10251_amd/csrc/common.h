@@ -235,8 +235,12 @@ void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, con
 // weights of a single problem)
 bool mass_rhs_fusable(const Grid& g, const Coef<double>& c);
 // un = u + e and r = f - A un (to FP32) in one pass (3D); un must not alias u.
+// With lam (constant coefficients): f is not read but formed as lam M u.
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
-                       double* un, float* r, int nrhs, long stride, hipStream_t st);
+                       double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
+// r32 = f - A u (3D); with lam (constant coefficients) f = lam M u is formed
+void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
+                        int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
 void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                           double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                           hipStream_t st);
@@ -288,9 +292,11 @@ void launch_add_correction(const double* e, double* u, long n, hipStream_t st);
 // (u . au, u . mu).  Returns the number of blocks per right-hand side.
 // 3D: b_c = P^T A u, c_c = P^T M u on the next coarser grid and the pairs
 // (u.Au, u.Mu) per workgroup in partial (through an LDS tile); returns the
-// pairs per right-hand side
+// pairs per right-hand side.  With e and un (constant coefficients): of
+// u + e (the last FP32 correction, added in FP64), written to un.
 int launch_border_restrict3(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
-                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st);
+                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st,
+                            const float* e = nullptr, double* un = nullptr);
 int launch_border(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
                   double* partial, int nrhs, long stride, hipStream_t st);
 

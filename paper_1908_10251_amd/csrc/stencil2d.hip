@@ -959,8 +959,6 @@ template <typename T>
 void launch_apply_A3(const Grid& g, const Coef<T>& c, const T* x, T* y, int nrhs, long stride, hipStream_t st);
 void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double* f, int nrhs, long stride,
                       hipStream_t st);
-void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
-                        int nrhs, long stride, hipStream_t st);
 int launch_border3(const Grid& g, const Coef<double>& c, const double* u, double* au, double* mu,
                    double* partial, int nrhs, long stride, hipStream_t st);
 template <typename T>
@@ -1150,6 +1148,7 @@ void launch_apply_M(const Grid& g, const double* x, double* y, int nrhs, long st
 
 void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
                        int nrhs, long stride, hipStream_t st, const double* lam) {
+    if (lam && g.dim == 3) return launch_resid_cast3(g, c, u, f, r, nrhs, stride, st, lam);
     if (lam) {
         if (!mass_rhs_fusable(g, c)) throw Error(PASM_E_INVALID, "residual with lam M u: 2D edge weights only");
         constexpr int RB = 4;
@@ -1164,7 +1163,8 @@ void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, co
 }
 
 bool mass_rhs_fusable(const Grid& g, const Coef<double>& c) {
-    return g.dim == 2 && coef_kind(c) == 1 && c.kpm <= 1 && c.ms == 0;
+    if (c.kpm > 1 || c.ms != 0) return false;
+    return (g.dim == 2 && coef_kind(c) == 1) || (g.dim == 3 && coef_kind(c) == 0);
 }
 
 template <typename TO>
@@ -1211,7 +1211,7 @@ bool add_resid_supported(const Grid& g, const Coef<double>& c) {
 void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                       double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam) {
     if (lam && !mass_rhs_fusable(g, c)) throw Error(PASM_E_INVALID, "add and residual with lam M u: 2D edge weights");
-    if (g.dim == 3) return launch_add_resid3(g, c, u, e, f, un, r, nrhs, stride, st);
+    if (g.dim == 3) return launch_add_resid3(g, c, u, e, f, un, r, nrhs, stride, st, lam);
     if (!add_resid_supported(g, c) || un == u)
         throw Error(PASM_E_INVALID, "add and residual: 2D constant or edge-weight operator, separate output");
     dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);

@@ -148,16 +148,27 @@ __global__ __launch_bounds__(BX* BY) void k_restrict3(Grid gf, const T* __restri
 constexpr int RCX = 8, RCY = 8, RCZ = 4;                                 // coarse nodes per workgroup
 constexpr int RFX = 2 * RCX + 1, RFY = 2 * RCY + 1, RFZ = 2 * RCZ + 1;   // fine nodes with values
 constexpr int RUX = RFX + 2, RUY = RFY + 2, RUZ = RFZ + 2;               // fine nodes of x (halo 1)
-template <typename T, int MODE, bool CONST>
-__global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, const T* __restrict__ x,
+// ADD (MODE 1): x is the V-cycles' iterate before its last correction; the
+// tile holds x + ecor (the FP32 correction, added in FP64) and the own nodes
+// of the corrected field are written to xout (which must not alias x).
+// Threads per workgroup: the border mode's FP64 tiles take 73 KB of LDS, two
+// workgroups per compute unit, so it runs 512 threads each to keep as many
+// wavefronts resident as the residual mode.
+template <int MODE>
+constexpr int tile3_threads() { return MODE == 1 ? 512 : 256; }
+template <typename T, int MODE, bool CONST, bool ADD = false>
+__global__ __launch_bounds__(tile3_threads<MODE>()) void k_tile_restrict3(Grid gf, Coef<T> c, const T* __restrict__ x,
                                                         const T* __restrict__ f, Grid gc, T* __restrict__ oc,
                                                         T* __restrict__ oc2, double* __restrict__ partial, long sf,
-                                                        long sc, int zblocks) {
-    constexpr int NU = RUX * RUY * RUZ, NV = RFX * RFY * RFZ, NPT = (NU + 255) / 256;
+                                                        long sc, int zblocks, const float* __restrict__ ecor,
+                                                        T* __restrict__ xout) {
+    static_assert(!ADD || MODE == 1, "the correction is added in the border mode only");
+    constexpr int TB = tile3_threads<MODE>();
+    constexpr int NU = RUX * RUY * RUZ, NV = RFX * RFY * RFZ, NPT = (NU + TB - 1) / TB;
     __shared__ T us[NU];
     __shared__ T vs[NV];
     __shared__ T ws[MODE == 1 ? NV : 1];
-    __shared__ double sh[8];
+    __shared__ double sh[2 * TB / 64];
     const int tid = threadIdx.x;
     const int zb = blockIdx.z % zblocks, r = blockIdx.z / zblocks;
     const int I0 = blockIdx.x * RCX + 1, J0 = blockIdx.y * RCY + 1, K0 = zb * RCZ + 1;
@@ -168,21 +179,22 @@ __global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, cons
         T v[NPT];
 #pragma unroll
         for (int e = 0; e < NPT; ++e) {
-            const int t = tid + 256 * e;
+            const int t = tid + TB * e;
             const int a = t % RUX, b = (t / RUX) % RUY, cz = t / (RUX * RUY);
             const int i = min(fi0 - 1 + a, gf.n), j = min(fj0 - 1 + b, gf.n), k = min(fk0 - 1 + cz, gf.n);
             v[e] = xr[gf.idx(i, j, k)];
+            if constexpr (ADD) v[e] += (T)ecor[(long)r * sf + gf.idx(i, j, k)];
             if (t >= NU || fi0 - 1 + a > gf.n || fj0 - 1 + b > gf.n || fk0 - 1 + cz > gf.n) v[e] = T(0);
         }
 #pragma unroll
         for (int e = 0; e < NPT; ++e)
-            if (tid + 256 * e < NU) us[tid + 256 * e] = v[e];
+            if (tid + TB * e < NU) us[tid + TB * e] = v[e];
     }
     __syncthreads();
     const T* fr = MODE == 0 ? f + (long)r * sf : nullptr;
     double ua = 0.0, um = 0.0;
     const double h3 = gf.h * gf.h * gf.h;
-    for (int t = tid; t < NV; t += 256) {
+    for (int t = tid; t < NV; t += TB) {
         const int a = t % RFX, b = (t / RFX) % RFY, cz = t / (RFX * RFY);
         const int i = fi0 + a, j = fj0 + b, k = fk0 + cz;
         T val = T(0), wal = T(0);
@@ -212,6 +224,7 @@ __global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, cons
                 if (a < 2 * RCX && b < 2 * RCY && cz < 2 * RCZ) {  // own node
                     ua += (double)(x0 * val);
                     um += (double)(x0 * wal);
+                    if constexpr (ADD) xout[(long)r * sf + gf.idx(i, j, k)] = x0;
                 }
             }
         }
@@ -222,7 +235,7 @@ __global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, cons
     {
         const int cx = tid % RCX, cy = (tid / RCX) % RCY, cz = tid / (RCX * RCY);
         const int I = I0 + cx, J = J0 + cy, K = K0 + cz;
-        if (I <= gc.m && J <= gc.m && K <= gc.m) {
+        if (cz < RCZ && I <= gc.m && J <= gc.m && K <= gc.m) {
             const int q = ((2 * cz + 1) * RFY + (2 * cy + 1)) * RFX + (2 * cx + 1);
             T sv = T(0), sw = T(0);
 #pragma unroll
@@ -251,8 +264,14 @@ __global__ __launch_bounds__(256) void k_tile_restrict3(Grid gf, Coef<T> c, cons
         if (tid == 0) {
             const long per = (long)gridDim.x * gridDim.y * zblocks;  // workgroups per right-hand side
             const long b = (long)r * per + ((long)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            partial[2 * b] = sh[0] + sh[2] + sh[4] + sh[6];
-            partial[2 * b + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+            double sa = 0.0, sm = 0.0;
+#pragma unroll
+            for (int w = 0; w < TB / 64; ++w) {
+                sa += sh[2 * w];
+                sm += sh[2 * w + 1];
+            }
+            partial[2 * b] = sa;
+            partial[2 * b + 1] = sm;
         }
     }
 }
@@ -315,7 +334,7 @@ __global__ __launch_bounds__(256) void k_prolong_mass3(Grid gc, const double* __
         const double bd = us[q + 1 + QY + QZ] + us[q - 1 - QY - QZ];
         const long id = (long)r * sf + gf.idx(i, j, k);
         xn[id] = x0;
-        f[id] = lz * (h3 * (0.4 * x0 + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0)));
+        if (f) f[id] = lz * (h3 * (0.4 * x0 + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0)));
     }
 }
 
@@ -357,26 +376,32 @@ __global__ __launch_bounds__(BX* BY) void k_mass_rhs3(Grid g, const double* __re
     f[off + id] = l * mass3(g, u + off, id);
 }
 
-template <bool CONST>
+// MASS: f is not read but formed as lam M u from u itself (u is the start of
+// the correction step, f = lam M u), with the arithmetic of k_prolong_mass3.
+template <bool CONST, bool MASS = false>
 __global__ __launch_bounds__(BX* BY) void k_resid_cast3(Grid g, Coef<double> c, const double* __restrict__ u,
                                                         const double* __restrict__ f, float* __restrict__ r,
-                                                        long stride) {
+                                                        long stride, const double* __restrict__ lam) {
     const Pos p = pos3(g.m);
     if (!p.ok) return;
     const long off = (long)p.r * stride;
     const long id = g.idx(p.i, p.j, p.l);
     double Ax, D;
     stiff3<double, CONST>(g, c, u + off, id, Ax, D);
-    r[off + id] = (float)(f[off + id] - Ax);
+    const double fv = MASS ? lam[p.r] * mass3(g, u + off, id) : f[off + id];
+    r[off + id] = (float)(fv - Ax);
 }
 
 // Defect correction between two cycles in one pass: un = u + e on every
 // interior node and r = f - A un (FP64, rounded to FP32) for the next cycle;
 // un at the neighbours is formed again from u and e.  un must not alias u.
-template <bool CONST>
+// MASS: f is not read but formed as lam M u from u itself (u is then the
+// start of the correction step: the step's first cycle).
+template <bool CONST, bool MASS = false>
 __global__ __launch_bounds__(BX* BY) void k_add_resid3(Grid g, Coef<double> c, const double* __restrict__ u,
                                                        const float* __restrict__ e, const double* __restrict__ f,
-                                                       double* __restrict__ un, float* __restrict__ r, long stride) {
+                                                       double* __restrict__ un, float* __restrict__ r, long stride,
+                                                       const double* __restrict__ lam) {
     const Pos p = pos3(g.m);
     if (!p.ok) return;
     const long off = (long)p.r * stride;
@@ -384,6 +409,8 @@ __global__ __launch_bounds__(BX* BY) void k_add_resid3(Grid g, Coef<double> c, c
     const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
     const double* ur = u + off;
     const float* er = e + off;
+    // every load before the stores
+    const double fv = MASS ? lam[p.r] * mass3(g, ur, id) : f[off + id];
     auto v = [&](long q) { return ur[q] + (double)er[q]; };
     const double x0 = v(id), xe = v(id + 1), xw = v(id - 1), xn = v(id + py), xs = v(id - py), xu = v(id + pz),
                  xd = v(id - pz);
@@ -396,7 +423,7 @@ __global__ __launch_bounds__(BX* BY) void k_add_resid3(Grid g, Coef<double> c, c
         Ax = (w1 + w2 + w3 + w4 + w5 + w6) * x0 - w1 * xe - w2 * xw - w3 * xn - w4 * xs - w5 * xu - w6 * xd;
     }
     un[off + id] = x0;
-    r[off + id] = (float)(f[off + id] - Ax);
+    r[off + id] = (float)(fv - Ax);
 }
 
 template <bool CONST>
@@ -485,10 +512,10 @@ void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const 
         dim3 grid((gc.m + RCX - 1) / RCX, (gc.m + RCY - 1) / RCY, zb * nrhs);
         if (c.wx)
             hipLaunchKernelGGL((k_tile_restrict3<T, 0, false>), grid, dim3(256), 0, st, gf, c, x, f, gc, rc,
-                               (T*)nullptr, nullptr, sf, sc, zb);
+                               (T*)nullptr, nullptr, sf, sc, zb, nullptr, (T*)nullptr);
         else
             hipLaunchKernelGGL((k_tile_restrict3<T, 0, true>), grid, dim3(256), 0, st, gf, c, x, f, gc, rc,
-                               (T*)nullptr, nullptr, sf, sc, zb);
+                               (T*)nullptr, nullptr, sf, sc, zb, nullptr, (T*)nullptr);
         PASM_CHECK_LAUNCH();
         return;
     }
@@ -502,18 +529,26 @@ void launch_resid_restrict3(const Grid& gf, const Coef<T>& c, const T* x, const 
 }
 
 int launch_border_restrict3(const Grid& g, const Coef<double>& c, const double* u, const Grid& gc, double* bc,
-                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st) {
+                            double* cc, double* partial, int nrhs, long stride, long sc, hipStream_t st,
+                            const float* e, double* un) {
     if (g.dim != 3 || gc.n * 2 != g.n) throw Error(PASM_E_INVALID, "fused border restriction: 3D, ratio 2");
     if (c.s15) throw Error(PASM_E_INVALID, "fused border restriction: no general 3D operator");
+    if ((e == nullptr) != (un == nullptr) || (un && (un == u || c.wx)))
+        throw Error(PASM_E_INVALID, "correction with borders (3D): constant coefficients, separate output");
     // coarse nodes up to nc (not only the interior ones) own fine nodes for the sums
     const int zb = (gc.n + RCZ - 1) / RCZ;
     dim3 grid((gc.n + RCX - 1) / RCX, (gc.n + RCY - 1) / RCY, zb * nrhs);
-    if (c.wx)
-        hipLaunchKernelGGL((k_tile_restrict3<double, 1, false>), grid, dim3(256), 0, st, g, c, u, (const double*)nullptr,
-                           gc, bc, cc, partial, stride, sc, zb);
+    if (e)
+        hipLaunchKernelGGL((k_tile_restrict3<double, 1, true, true>), grid, dim3(tile3_threads<1>()), 0, st, g, c, u,
+                           (const double*)nullptr, gc, bc, cc, partial, stride, sc, zb, e, un);
+    else if (c.wx)
+        hipLaunchKernelGGL((k_tile_restrict3<double, 1, false>), grid, dim3(tile3_threads<1>()), 0, st, g, c, u,
+                           (const double*)nullptr,
+                           gc, bc, cc, partial, stride, sc, zb, nullptr, (double*)nullptr);
     else
-        hipLaunchKernelGGL((k_tile_restrict3<double, 1, true>), grid, dim3(256), 0, st, g, c, u, (const double*)nullptr,
-                           gc, bc, cc, partial, stride, sc, zb);
+        hipLaunchKernelGGL((k_tile_restrict3<double, 1, true>), grid, dim3(tile3_threads<1>()), 0, st, g, c, u,
+                           (const double*)nullptr,
+                           gc, bc, cc, partial, stride, sc, zb, nullptr, (double*)nullptr);
     PASM_CHECK_LAUNCH();
     return (int)(grid.x * grid.y * zb);
 }
@@ -549,23 +584,35 @@ void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double*
 }
 
 void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
-                        int nrhs, long stride, hipStream_t st) {
+                        int nrhs, long stride, hipStream_t st, const double* lam) {
+    if (lam && (c.s15 || c.wx)) throw Error(PASM_E_INVALID, "residual with lam M u (3D): constant coefficients");
     if (c.s15) return launch_resid_cast3g(g, c.s15, u, f, r, nrhs, stride, st);
-    if (c.wx)
-        hipLaunchKernelGGL(k_resid_cast3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
+    if (lam)
+        hipLaunchKernelGGL((k_resid_cast3<true, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride,
+                           lam);
+    else if (c.wx)
+        hipLaunchKernelGGL((k_resid_cast3<false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride,
+                           nullptr);
     else
-        hipLaunchKernelGGL(k_resid_cast3<true>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride);
+        hipLaunchKernelGGL((k_resid_cast3<true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride,
+                           nullptr);
     PASM_CHECK_LAUNCH();
 }
 
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
-                       double* un, float* r, int nrhs, long stride, hipStream_t st) {
+                       double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam) {
     if (g.dim != 3 || un == u) throw Error(PASM_E_INVALID, "add and residual: 3D, separate output");
+    if (lam && (c.s15 || c.wx)) throw Error(PASM_E_INVALID, "add and residual with lam M u (3D): constant coefficients");
     if (c.s15) return launch_add_resid3g(g, c.s15, u, e, f, un, r, nrhs, stride, st);
-    if (c.wx)
-        hipLaunchKernelGGL(k_add_resid3<false>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride);
+    if (lam)
+        hipLaunchKernelGGL((k_add_resid3<true, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r,
+                           stride, lam);
+    else if (c.wx)
+        hipLaunchKernelGGL((k_add_resid3<false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride,
+                           nullptr);
     else
-        hipLaunchKernelGGL(k_add_resid3<true>, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride);
+        hipLaunchKernelGGL((k_add_resid3<true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride,
+                           nullptr);
     PASM_CHECK_LAUNCH();
 }
 

@@ -509,20 +509,48 @@ def test_fine_equal_coarse_returns_coarse_ritz_pairs():
     assert np.all(flags & 1)
 
 
-def test_3d_solve_with_degenerate_pair():
-    _say("solve lap3d H=1/4 h=1/16 k=4")
+@pytest.mark.parametrize("precision", [P.PASM_FP64, P.PASM_MIXED])
+def test_3d_solve_with_degenerate_pair(precision):
+    _say(f"solve lap3d H=1/4 h=1/16 k=4 prec={precision}")
     prob = O.make_problem(3, 4, 16)
     w, V = O.discrete_eigenpairs(prob.A, prob.M, 4)
-    with P.Solver(3, 1 / 4, 1 / 16, 4, opts=_opts("jacobi", 2, tol=1e-12)) as s:
+    with P.Solver(3, 1 / 4, 1 / 16, 4, opts=_opts("jacobi", 2, tol=1e-12, precision=precision)) as s:
         s.solve()
         lam, U = s.eigenpairs()
-    assert np.max(np.abs(np.sort(lam) - w) / w) < 1e-10
+    assert np.max(np.abs(np.sort(lam) - w) / w) < (1e-10 if precision == P.PASM_FP64 else 1e-8)
     # the double eigenvalue: compare subspaces
     idx = [i for i in range(4) if abs(lam[i] - w[1]) < 1e-8 * w[1]]
     assert len(idx) == 2
     Qa, _ = np.linalg.qr(V[:, 1:3])
     Qb, _ = np.linalg.qr(U[idx].T)
     assert np.min(np.linalg.svd(Qa.T @ Qb, compute_uv=False)) > 1 - 1e-10
+
+
+@pytest.mark.parametrize("vcycles", [1, 2])
+def test_3d_mixed_one_step_matches_oracle(vcycles):
+    # mixed precision on the cube: the step's residuals form lambda M u
+    # from u (f is never stored) and the last FP32 correction is added in
+    # the border pass; against the oracle's FP64 step, 1e-8 on lambda and
+    # 1e-6 on u
+    nc, nf, k = 4, 32, 4
+    _say(f"one mixed 3D step H=1/{nc} h=1/{nf} k={k} vcycles={vcycles}")
+    prob = O.make_problem(3, nc, nf)
+    lam0, U0, _, _ = O.coarse_start(prob, k)
+    bvp = O.MultigridBVP(prob, default_options(3, "jacobi", 2, 2, vcycles))
+    o = P.options(precision=P.PASM_MIXED, smoother=P.PASM_JACOBI, nu_pre=2, nu_post=2, vcycles=vcycles)
+    with P.Solver(3, 1 / nc, 1 / nf, k, opts=o) as s:
+        P.pasm_set_state(s.ctx, lam0, U0)
+        s.iterate()
+        lam, U = s.eigenpairs()
+        bz, _, _ = P.pasm_last_borders(s.ctx, k)
+    for i in range(k):
+        ref = O.correction_step(prob, lam0[i], U0[i], bvp)
+        eu = np.max(np.abs(U[i] - ref["u"])) / np.max(np.abs(ref["u"]))
+        _say(f"  pair {i}: lambda {abs(lam[i] - ref['lam']) / ref['lam']:.1e} u {eu:.1e}")
+        assert bz[i, 0] == pytest.approx(ref["beta"], rel=1e-6)
+        assert bz[i, 1] == pytest.approx(ref["zeta"], rel=1e-6)
+        assert abs(lam[i] - ref["lam"]) / ref["lam"] < 1e-8
+        assert eu < 1e-6
 
 
 def test_variable_kappa_lowest_eigenpair():
