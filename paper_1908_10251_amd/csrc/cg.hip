@@ -23,9 +23,10 @@ constexpr int CX = 64, CY = 4;  // one workgroup: 64 x 4 nodes of one (z-)plane
 
 // Kernels that apply the operator take RB right-hand sides per thread, so
 // that the coefficients of a node's row are read once for all of them; the
-// vector updates take one.
+// vector updates take UB, so that a workgroup's reduction serves that many.
 template <int DIM, int KIND>
 constexpr int rhs_block() { return KIND == 0 ? 1 : 4; }
+constexpr int UB = 4;
 
 struct NodeIdx {
     long id;    // padded index of the node in its plane / volume
@@ -178,24 +179,32 @@ template <typename T, int DIM, int KIND, bool XZ>
 __global__ __launch_bounds__(CX* CY) void k_cg_start(Grid g, Coef<T> c, const T* __restrict__ x,
                                                      const T* __restrict__ f, T* __restrict__ r,
                                                      double* __restrict__ partial, long stride, long nblk, int nrhs) {
-    constexpr int RB = XZ ? 1 : rhs_block<DIM, KIND>();
+    constexpr int RB = XZ ? UB : rhs_block<DIM, KIND>();
     const NodeIdx n = node_of<DIM, RB>(g);
     const int nv = min(RB, nrhs - n.r0);
     double acc[RB];
     OpRow<T, DIM, KIND> row;
     if (!XZ && n.ok) row.load(g, c, n.id);
+    // every right-hand side's value before any store
+    T rv[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        rv[q] = T(0);
+        if (n.ok && q < nv) {
+            const long off = (long)(n.r0 + q) * stride;
+            rv[q] = f[off + n.id];
+            if (!XZ) {
+                const T* xr = x + off;
+                rv[q] -= row.apply(g, n.id, [&](long k) { return xr[k]; });
+            }
+        }
+    }
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
         acc[q] = 0.0;
         if (n.ok && q < nv) {
-            const long off = (long)(n.r0 + q) * stride;
-            T rv = f[off + n.id];
-            if (!XZ) {
-                const T* xr = x + off;
-                rv -= row.apply(g, n.id, [&](long k) { return xr[k]; });
-            }
-            r[off + n.id] = rv;
-            acc[q] = (double)rv * (double)rv;
+            r[(long)(n.r0 + q) * stride + n.id] = rv[q];
+            acc[q] = (double)rv[q] * (double)rv[q];
         }
     }
     block_partials<RB>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, nv);
@@ -213,20 +222,29 @@ __global__ __launch_bounds__(CX* CY) void k_cg_dir(Grid g, Coef<T> c, const T* _
     double acc[RB];
     OpRow<T, DIM, KIND> row;
     if (n.ok) row.load(g, c, n.id);
+    // every right-hand side's values before any store
+    T p0[RB], qv[RB];
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
-        acc[u] = 0.0;
+        p0[u] = qv[u] = T(0);
         if (n.ok && u < nv) {
             const long off = (long)(n.r0 + u) * stride;
             const T* rr = r + off;
             const T* po = pold + off;
             const T b = FIRST ? T(0) : (T)beta[n.r0 + u];
             auto pv = [&](long k) { return FIRST ? rr[k] : rr[k] + b * po[k]; };
-            const T p0 = pv(n.id);
-            const T qv = row.apply(g, n.id, pv);
-            pnew[off + n.id] = p0;
-            q[off + n.id] = qv;
-            acc[u] = (double)p0 * (double)qv;
+            p0[u] = pv(n.id);
+            qv[u] = row.apply(g, n.id, pv);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+        acc[u] = 0.0;
+        if (n.ok && u < nv) {
+            const long off = (long)(n.r0 + u) * stride;
+            pnew[off + n.id] = p0[u];
+            q[off + n.id] = qv[u];
+            acc[u] = (double)p0[u] * (double)qv[u];
         }
     }
     block_partials<RB>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, nv);
@@ -237,21 +255,37 @@ template <typename T, int DIM, bool RR, bool XZ>
 __global__ __launch_bounds__(CX* CY) void k_cg_update(Grid g, T* __restrict__ x, T* __restrict__ r,
                                                       const T* __restrict__ p, const T* __restrict__ q,
                                                       const double* __restrict__ alpha, double* __restrict__ partial,
-                                                      long stride, long nblk) {
-    const NodeIdx n = node_of<DIM, 1>(g);
-    const long off = (long)n.r0 * stride;
-    double acc[1] = {0.0};
-    if (n.ok) {
-        const T a = (T)alpha[n.r0];
-        const long k = off + n.id;
-        x[k] = XZ ? a * p[k] : x[k] + a * p[k];
-        if (RR) {
-            const T rv = r[k] - a * q[k];
-            r[k] = rv;
-            acc[0] = (double)rv * (double)rv;
+                                                      long stride, long nblk, int nrhs) {
+    const NodeIdx n = node_of<DIM, UB>(g);
+    const int nv = min(UB, nrhs - n.r0);
+    double acc[UB];
+    // every load of the thread's right-hand sides before any store
+    T av[UB], pv[UB], qv[UB], rv[UB], xv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        av[u] = pv[u] = qv[u] = rv[u] = xv[u] = T(0);
+        if (n.ok && u < nv) {
+            const long k = (long)(n.r0 + u) * stride + n.id;
+            av[u] = (T)alpha[n.r0 + u];
+            pv[u] = p[k];
+            if (RR) qv[u] = q[k], rv[u] = r[k];
+            if (!XZ) xv[u] = x[k];
         }
     }
-    if (RR) block_partials<1>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, 1);
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        acc[u] = 0.0;
+        if (n.ok && u < nv) {
+            const long k = (long)(n.r0 + u) * stride + n.id;
+            x[k] = XZ ? av[u] * pv[u] : xv[u] + av[u] * pv[u];
+            if (RR) {
+                const T rn = rv[u] - av[u] * qv[u];
+                r[k] = rn;
+                acc[u] = (double)rn * (double)rn;
+            }
+        }
+    }
+    if (RR) block_partials<UB>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, nv);
 }
 
 // Per right-hand side: s = sum of its nblk partials (fixed order), then
@@ -286,7 +320,8 @@ void cg_run(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int ste
     constexpr int RB = rhs_block<DIM, KIND>();
     const dim3 blk(CX, CY);
     const int ngrp = (nrhs + RB - 1) / RB;
-    const dim3 grid((g.m + CX - 1) / CX, (g.m + CY - 1) / CY, DIM == 2 ? nrhs : g.m * nrhs);
+    const int ngu = (nrhs + UB - 1) / UB;
+    const dim3 grid((g.m + CX - 1) / CX, (g.m + CY - 1) / CY, DIM == 2 ? ngu : g.m * ngu);
     const dim3 grid_op(grid.x, grid.y, DIM == 2 ? ngrp : g.m * ngrp);
     const long nblk = (long)grid.x * grid.y * (DIM == 2 ? 1 : g.m);
     const long sd = g.plane;
@@ -313,17 +348,17 @@ void cg_run(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int ste
         if (last) {
             if (xz)
                 hipLaunchKernelGGL((k_cg_update<T, DIM, false, true>), grid, blk, 0, st, g, x, r, pa, q, w.alpha,
-                                   w.partial, sd, nblk);
+                                   w.partial, sd, nblk, nrhs);
             else
                 hipLaunchKernelGGL((k_cg_update<T, DIM, false, false>), grid, blk, 0, st, g, x, r, pa, q, w.alpha,
-                                   w.partial, sd, nblk);
+                                   w.partial, sd, nblk, nrhs);
         } else {
             if (xz)
                 hipLaunchKernelGGL((k_cg_update<T, DIM, true, true>), grid, blk, 0, st, g, x, r, pa, q, w.alpha,
-                                   w.partial, sd, nblk);
+                                   w.partial, sd, nblk, nrhs);
             else
                 hipLaunchKernelGGL((k_cg_update<T, DIM, true, false>), grid, blk, 0, st, g, x, r, pa, q, w.alpha,
-                                   w.partial, sd, nblk);
+                                   w.partial, sd, nblk, nrhs);
             hipLaunchKernelGGL(k_cg_reduce<2>, dim3(nrhs), dim3(256), 0, st, w.partial, nblk, w.rr, w.beta);
         }
         std::swap(pa, pb);  // the new direction is the old one of the next step
