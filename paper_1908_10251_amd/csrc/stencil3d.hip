@@ -403,6 +403,153 @@ __global__ __launch_bounds__(256) void k_resid_restrict3z(Grid gf, T w0, const T
     }
 }
 
+// The borders of a correction step marching along z (3D, constant
+// coefficients, FP64): A u and M u, their restrictions P^T A u, P^T M u to
+// the next coarser grid, and the sums u.Au, u.Mu over each fine node once.
+// A workgroup owns ZTX x ZTY coarse nodes (up to nc, whose fine nodes it owns
+// for the sums) and ZKC coarse planes, keeps three fine planes of u (one-node
+// halo) in an LDS ring and one plane of A u and M u; after each fine plane
+// every thread adds that plane's share to the restrictions of its coarse
+// node (centre plane 2K: the node and its six in-plane Kuhn neighbours; plane
+// 2K - 1 and 2K + 1: the four neighbours along the edge directions with
+// z component -1 and +1), and writes coarse plane K once plane 2K + 1 is in.
+// ADD: the ring holds u + e (the last FP32 correction, added in FP64) and
+// the own nodes of the corrected field are written to un.
+template <bool ADD>
+__global__ __launch_bounds__(256) void k_border3z(Grid gf, double w0, const double* __restrict__ u,
+                                                  const float* __restrict__ e, double* __restrict__ un, Grid gc,
+                                                  double* __restrict__ bc, double* __restrict__ cc,
+                                                  double* __restrict__ partial, long sf, long sc, int zchunks) {
+    __shared__ double xs[3][ZNU];
+    __shared__ double va[ZNR], vm[ZNR];
+    __shared__ double sh[8];
+    const int tid = threadIdx.x;
+    const int zc = blockIdx.z % zchunks, r = blockIdx.z / zchunks;
+    const int I0 = blockIdx.x * ZTX + 1, J0 = blockIdx.y * ZTY + 1;
+    const int K0 = zc * ZKC + 1, K1 = min(K0 + ZKC, gc.n + 1);  // coarse planes [K0, K1), up to nc
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;
+    const double* xr = u + (long)r * sf;
+    const float* er = ADD ? e + (long)r * sf : nullptr;
+    long xo[ZPU];
+    bool xin[ZPU];
+#pragma unroll
+    for (int q = 0; q < ZPU; ++q) {
+        const int t = tid + 256 * q;
+        const int i = fi0 - 1 + t % ZUX, j = fj0 - 1 + t / ZUX;
+        xin[q] = t < ZNU && i <= gf.n && j <= gf.n;
+        xo[q] = (long)min(j, gf.n) * gf.pitch + ORIGIN + min(i, gf.n);
+    }
+    const long pz = (long)gf.pitch * (gf.n + 1);
+    auto load_x = [&](int k, double (&v)[ZPU]) {
+        const long base = (long)min(max(k, 0), gf.n) * pz;
+#pragma unroll
+        for (int q = 0; q < ZPU; ++q) {
+            v[q] = xr[base + xo[q]];
+            if (ADD) v[q] += (double)er[base + xo[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < ZPU; ++q)
+            if (!xin[q] || k < 0 || k > gf.n) v[q] = 0.0;
+    };
+    auto store_x = [&](int slot, const double (&v)[ZPU]) {
+#pragma unroll
+        for (int q = 0; q < ZPU; ++q)
+            if (tid + 256 * q < ZNU) xs[slot][tid + 256 * q] = v[q];
+    };
+    const double h3 = gf.h * gf.h * gf.h;
+    // this thread's coarse node and its running restrictions for the coarse
+    // planes K (index 0) and K + 1 (index 1) around the current fine plane
+    const int cx = tid % ZTX, cy = tid / ZTX;
+    const int I = I0 + cx, J = J0 + cy;
+    const int qc = (2 * cy + 1) * ZRX + (2 * cx + 1);
+    double ba[2] = {0.0, 0.0}, bm[2] = {0.0, 0.0};
+    double ua = 0.0, um = 0.0;
+    const int p0 = 2 * K0 - 1, p1 = 2 * K1 - 1;
+    const int own_hi = 2 * K1 - 2;  // own fine planes [p0, own_hi]
+    double xa[ZPU], xb[ZPU];
+    load_x(p0 - 1, xa);
+    load_x(p0, xb);
+    store_x((p0 - 1 + 3) % 3, xa);
+    store_x(p0 % 3, xb);
+    load_x(p0 + 1, xa);
+    for (int p = p0; p <= p1; ++p) {
+        store_x((p + 1) % 3, xa);
+        if (p + 2 <= p1 + 1) load_x(p + 2, xa);
+        __syncthreads();
+        {
+            const double* xm = xs[(p + 2) % 3];
+            const double* x0 = xs[p % 3];
+            const double* xp = xs[(p + 1) % 3];
+            const bool pin = p >= 1 && p <= gf.m;
+            for (int t = tid; t < ZNR; t += 256) {
+                const int a = t % ZRX, b = t / ZRX;
+                const int i = fi0 + a, j = fj0 + b;
+                double Ax = 0.0, Mx = 0.0;
+                if (pin && i <= gf.m && j <= gf.m) {
+                    const int q = (b + 1) * ZUX + (a + 1);
+                    const double c = x0[q];
+                    const double xe = x0[q + 1], xw = x0[q - 1], xn = x0[q + ZUX], xsv = x0[q - ZUX], xu = xp[q],
+                                 xd = xm[q];
+                    Ax = w0 * (6.0 * c - (xe + xw + xn + xsv + xu + xd));
+                    const double ax = xe + xw + xn + xsv + xu + xd;
+                    const double fd = x0[q + 1 + ZUX] + x0[q - 1 - ZUX] + xp[q + 1] + xm[q - 1] + xp[q + ZUX] +
+                                      xm[q - ZUX];
+                    const double bd = xp[q + 1 + ZUX] + xm[q - 1 - ZUX];
+                    Mx = h3 * (0.4 * c + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0));
+                    if (a < 2 * ZTX && b < 2 * ZTY && p <= own_hi) {  // own node
+                        ua += c * Ax;
+                        um += c * Mx;
+                        if (ADD) un[(long)r * sf + (long)p * pz + (long)j * gf.pitch + ORIGIN + i] = c;
+                    }
+                }
+                va[t] = Ax;
+                vm[t] = Mx;
+            }
+        }
+        __syncthreads();
+        {
+            // this plane's share of the restrictions
+            const int dy = ZRX;
+            if ((p & 1) == 0) {
+                // centre plane of K = p / 2 (index 0)
+                ba[0] += va[qc] + 0.5 * (va[qc + 1] + va[qc - 1] + va[qc + dy] + va[qc - dy] + va[qc + 1 + dy] +
+                                         va[qc - 1 - dy]);
+                bm[0] += vm[qc] + 0.5 * (vm[qc + 1] + vm[qc - 1] + vm[qc + dy] + vm[qc - dy] + vm[qc + 1 + dy] +
+                                         vm[qc - 1 - dy]);
+            } else {
+                // upper plane of K = (p - 1) / 2 (index 0), lower plane of K + 1 (index 1)
+                ba[0] += 0.5 * (va[qc] + va[qc + 1] + va[qc + dy] + va[qc + 1 + dy]);
+                bm[0] += 0.5 * (vm[qc] + vm[qc + 1] + vm[qc + dy] + vm[qc + 1 + dy]);
+                ba[1] += 0.5 * (va[qc] + va[qc - 1] + va[qc - dy] + va[qc - 1 - dy]);
+                bm[1] += 0.5 * (vm[qc] + vm[qc - 1] + vm[qc - dy] + vm[qc - 1 - dy]);
+                const int K = (p - 1) >> 1;
+                if (K >= K0 && I <= gc.m && J <= gc.m && K <= gc.m) {
+                    const long cid = (long)r * sc + gc.idx(I, J, K);
+                    bc[cid] = ba[0];
+                    cc[cid] = bm[0];
+                }
+                ba[0] = ba[1], bm[0] = bm[1];
+                ba[1] = 0.0, bm[1] = 0.0;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ua += __shfl_down(ua, o, 64);
+        um += __shfl_down(um, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        sh[2 * (tid >> 6)] = ua;
+        sh[2 * (tid >> 6) + 1] = um;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const long per = (long)gridDim.x * gridDim.y * zchunks;  // workgroups per right-hand side
+        const long b = (long)r * per + ((long)zc * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partial[2 * b] = sh[0] + sh[2] + sh[4] + sh[6];
+        partial[2 * b + 1] = sh[1] + sh[3] + sh[5] + sh[7];
+    }
+}
+
 // Prolongation and combination with the mass right-hand side of the next
 // step (3D): xn = P xc + beta[r] xo on every fine node, and f = lam[r] M xn on
 // the workgroup's 32 x 8 x 4 nodes (xn on their one-node halo is formed again
@@ -670,6 +817,20 @@ int launch_border_restrict3(const Grid& g, const Coef<double>& c, const double* 
     if (c.s15) throw Error(PASM_E_INVALID, "fused border restriction: no general 3D operator");
     if ((e == nullptr) != (un == nullptr) || (un && (un == u || c.wx)))
         throw Error(PASM_E_INVALID, "correction with borders (3D): constant coefficients, separate output");
+    if (!c.wx) {
+        // constant coefficients: marching along z; coarse nodes up to nc own
+        // fine nodes for the sums
+        const int zc = (gc.n + ZKC - 1) / ZKC;
+        dim3 grid((gc.n + ZTX - 1) / ZTX, (gc.n + ZTY - 1) / ZTY, zc * nrhs);
+        if (e)
+            hipLaunchKernelGGL(k_border3z<true>, grid, dim3(256), 0, st, g, c.w0, u, e, un, gc, bc, cc, partial,
+                               stride, sc, zc);
+        else
+            hipLaunchKernelGGL(k_border3z<false>, grid, dim3(256), 0, st, g, c.w0, u, e, un, gc, bc, cc, partial,
+                               stride, sc, zc);
+        PASM_CHECK_LAUNCH();
+        return (int)(grid.x * grid.y * zc);
+    }
     // coarse nodes up to nc (not only the interior ones) own fine nodes for the sums
     const int zb = (gc.n + RCZ - 1) / RCZ;
     dim3 grid((gc.n + RCX - 1) / RCX, (gc.n + RCY - 1) / RCY, zb * nrhs);
