@@ -384,7 +384,7 @@ __global__ __launch_bounds__(BX* BY) void k_prolong(Grid gc, const T* __restrict
     if (a | b) v = T(0.5) * (v + cr[cid + a + (long)b * gc.pitch]);
     const long id = (long)blockIdx.z * sf + gf.idx(i, j);
     if (mode == 1) v += xf[id];
-    else if (mode == 2) v += T(beta[blockIdx.z]) * xf[id];
+    else if (mode == 2 && beta[blockIdx.z] != 0.0) v += T(beta[blockIdx.z]) * xf[id];  // a zero weight drops the old field
     xf[id] = v;
 }
 

@@ -625,7 +625,7 @@ __global__ __launch_bounds__(BX* BY) void k_prolong3(Grid gc, const T* __restric
     if (a | b | e) v = T(0.5) * (v + cr[cid + a + (long)b * gc.pitch + (long)e * gc.pitch * (gc.n + 1)]);
     const long id = (long)p.r * sf + gf.idx(p.i, p.j, p.l);
     if (mode == 1) v += xf[id];
-    else if (mode == 2) v += T(beta[p.r]) * xf[id];
+    else if (mode == 2 && beta[p.r] != 0.0) v += T(beta[p.r]) * xf[id];  // a zero weight drops the old field
     xf[id] = v;
 }
 
