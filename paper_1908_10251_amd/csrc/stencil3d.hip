@@ -550,6 +550,103 @@ __global__ __launch_bounds__(256) void k_border3z(Grid gf, double w0, const doub
     }
 }
 
+// The FP64 residual of a mixed-precision step marching along z (3D,
+// constant coefficients), with f = lam M u formed from u: r = lam M u - A x
+// rounded to FP32, x = u (first cycle) or x = u + e (ADD: the first cycle's
+// correction added in FP64, x written to un).  A workgroup owns 32 x 32 fine
+// nodes of a chunk of ZRC fine planes and keeps three planes of u (and e)
+// with a one-node halo in LDS rings; the arithmetic is that of
+// k_resid_cast3 / k_add_resid3 with the mass term.
+constexpr int ZFX = 32, ZFY = 32, ZRC = 16;
+constexpr int ZQX = ZFX + 2, ZQY = ZFY + 2, ZNQ = ZQX * ZQY, ZPQ = (ZNQ + 255) / 256, ZPO = ZFX * ZFY / 256;
+template <bool ADD>
+__global__ __launch_bounds__(256) void k_resid3z(Grid g, double w0, const double* __restrict__ u,
+                                                 const float* __restrict__ e, const double* __restrict__ lam,
+                                                 double* __restrict__ un, float* __restrict__ r, long sf,
+                                                 int zchunks) {
+    __shared__ double us[3][ZNQ];
+    __shared__ float es[ADD ? 3 : 1][ADD ? ZNQ : 1];
+    const int tid = threadIdx.x;
+    const int zc = blockIdx.z % zchunks, z = blockIdx.z / zchunks;
+    const int i0 = blockIdx.x * ZFX + 1, j0 = blockIdx.y * ZFY + 1;
+    const int k0 = zc * ZRC + 1, k1 = min(k0 + ZRC, g.m + 1);  // fine planes [k0, k1)
+    const double* ur = u + (long)z * sf;
+    const float* er = ADD ? e + (long)z * sf : nullptr;
+    const double lz = lam[z];
+    long qo[ZPQ];
+    bool qin[ZPQ];
+#pragma unroll
+    for (int q = 0; q < ZPQ; ++q) {
+        const int t = tid + 256 * q;
+        const int i = i0 - 1 + t % ZQX, j = j0 - 1 + t / ZQX;
+        qin[q] = t < ZNQ && i <= g.n && j <= g.n;
+        qo[q] = (long)min(j, g.n) * g.pitch + ORIGIN + min(i, g.n);
+    }
+    const long pz = (long)g.pitch * (g.n + 1);
+    auto load = [&](int k, double (&vu)[ZPQ], float (&ve)[ZPQ]) {
+        const long base = (long)min(max(k, 0), g.n) * pz;
+#pragma unroll
+        for (int q = 0; q < ZPQ; ++q) {
+            vu[q] = ur[base + qo[q]];
+            if (ADD) ve[q] = er[base + qo[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < ZPQ; ++q)
+            if (!qin[q] || k > g.n) vu[q] = 0.0, ve[q] = 0.0f;
+    };
+    auto store = [&](int slot, const double (&vu)[ZPQ], const float (&ve)[ZPQ]) {
+#pragma unroll
+        for (int q = 0; q < ZPQ; ++q)
+            if (tid + 256 * q < ZNQ) {
+                us[slot][tid + 256 * q] = vu[q];
+                if (ADD) es[slot][tid + 256 * q] = ve[q];
+            }
+    };
+    const double h3 = g.h * g.h * g.h;
+    double au[ZPQ], bu[ZPQ];
+    float ae[ZPQ], be[ZPQ];
+    load(k0 - 1, au, ae);
+    load(k0, bu, be);
+    store((k0 - 1) % 3, au, ae);
+    store(k0 % 3, bu, be);
+    load(k0 + 1, au, ae);
+    for (int p = k0; p < k1; ++p) {
+        store((p + 1) % 3, au, ae);
+        if (p + 1 < k1) load(p + 2, au, ae);  // one plane ahead
+        __syncthreads();
+        const double* um = us[(p + 2) % 3];
+        const double* u0 = us[p % 3];
+        const double* up = us[(p + 1) % 3];
+        const float* em = es[ADD ? (p + 2) % 3 : 0];
+        const float* e0 = es[ADD ? p % 3 : 0];
+        const float* ep = es[ADD ? (p + 1) % 3 : 0];
+#pragma unroll
+        for (int q = 0; q < ZPO; ++q) {
+            const int t = tid + 256 * q;
+            const int a = t % ZFX, b = t / ZFX;
+            const int i = i0 + a, j = j0 + b;
+            if (i > g.m || j > g.m) continue;
+            const int c = (b + 1) * ZQX + (a + 1);
+            // lam M u, the neighbours in the order of the mass kernels
+            const double ax = u0[c + 1] + u0[c - 1] + u0[c + ZQX] + u0[c - ZQX] + up[c] + um[c];
+            const double fd = u0[c + 1 + ZQX] + u0[c - 1 - ZQX] + up[c + 1] + um[c - 1] + up[c + ZQX] + um[c - ZQX];
+            const double bd = up[c + 1 + ZQX] + um[c - 1 - ZQX];
+            const double fv = lz * (h3 * (0.4 * u0[c] + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0)));
+            double x0 = u0[c], xe = u0[c + 1], xw = u0[c - 1], xn = u0[c + ZQX], xs = u0[c - ZQX], xu = up[c],
+                   xd = um[c];
+            if (ADD) {
+                x0 += (double)e0[c], xe += (double)e0[c + 1], xw += (double)e0[c - 1], xn += (double)e0[c + ZQX];
+                xs += (double)e0[c - ZQX], xu += (double)ep[c], xd += (double)em[c];
+            }
+            const double Ax = w0 * (6.0 * x0 - (xe + xw + xn + xs + xu + xd));
+            const long id = (long)z * sf + (long)p * pz + (long)j * g.pitch + ORIGIN + i;
+            if (ADD) un[id] = x0;
+            r[id] = (float)(fv - Ax);
+        }
+        __syncthreads();
+    }
+}
+
 // Prolongation and combination with the mass right-hand side of the next
 // step (3D): xn = P xc + beta[r] xo on every fine node, and f = lam[r] M xn on
 // the workgroup's 32 x 8 x 4 nodes (xn on their one-node halo is formed again
@@ -883,9 +980,12 @@ void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, c
                         int nrhs, long stride, hipStream_t st, const double* lam) {
     if (lam && (c.s15 || c.wx)) throw Error(PASM_E_INVALID, "residual with lam M u (3D): constant coefficients");
     if (c.s15) return launch_resid_cast3g(g, c.s15, u, f, r, nrhs, stride, st);
-    if (lam)
-        hipLaunchKernelGGL((k_resid_cast3<true, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride,
-                           lam);
+    if (lam) {
+        const int zc = (g.m + ZRC - 1) / ZRC;
+        dim3 grid((g.m + ZFX - 1) / ZFX, (g.m + ZFY - 1) / ZFY, zc * nrhs);
+        hipLaunchKernelGGL(k_resid3z<false>, grid, dim3(256), 0, st, g, c.w0, u, (const float*)nullptr, lam,
+                           (double*)nullptr, r, stride, zc);
+    }
     else if (c.wx)
         hipLaunchKernelGGL((k_resid_cast3<false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride,
                            nullptr);
@@ -900,9 +1000,11 @@ void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, co
     if (g.dim != 3 || un == u) throw Error(PASM_E_INVALID, "add and residual: 3D, separate output");
     if (lam && (c.s15 || c.wx)) throw Error(PASM_E_INVALID, "add and residual with lam M u (3D): constant coefficients");
     if (c.s15) return launch_add_resid3g(g, c.s15, u, e, f, un, r, nrhs, stride, st);
-    if (lam)
-        hipLaunchKernelGGL((k_add_resid3<true, true>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r,
-                           stride, lam);
+    if (lam) {
+        const int zc = (g.m + ZRC - 1) / ZRC;
+        dim3 grid((g.m + ZFX - 1) / ZFX, (g.m + ZFY - 1) / ZFY, zc * nrhs);
+        hipLaunchKernelGGL(k_resid3z<true>, grid, dim3(256), 0, st, g, c.w0, u, e, lam, un, r, stride, zc);
+    }
     else if (c.wx)
         hipLaunchKernelGGL((k_add_resid3<false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride,
                            nullptr);
