@@ -1104,8 +1104,12 @@ void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, b
     const pasm::Level& Lc = c->lv[c->L - 2];
     if (s && c->f_mass) {
         // no f to form (the residual passes form lambda M u): u = P q + s u~
-        // node by node, in place
-        pasm::launch_prolong<double>(Lc.g, Lc.B, c->gf(), c->U, k, Lc.g.plane, c->sf(), false, s, c->st);
+        // into the scratch field (then swapped in), with the next step's
+        // first residual lambda M u - A u in FP32 from the same pass
+        pasm::launch_prolong_resid3(Lc.g, Lc.B, c->gf(), c->coef<double>(c->L - 1), c->U, c->Y64, c->R32, k,
+                                    Lc.g.plane, c->sf(), s, lamf ? lamf : c->mu, c->st);
+        std::swap(c->U, c->Y64);
+        c->r32_ready = true;
         c->f_ready = false;
         return;
     }

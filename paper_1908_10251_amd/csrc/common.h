@@ -241,6 +241,11 @@ void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, co
 // r32 = f - A u (3D); with lam (constant coefficients) f = lam M u is formed
 void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
                         int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
+// xn = P xc + beta[r] xo and the next step's first residual
+// r32 = lam[r] M xn - A xn (3D, constant coefficients, ratio 2; xn != xo)
+void launch_prolong_resid3(const Grid& gc, const double* xc, const Grid& gf, const Coef<double>& c, const double* xo,
+                           double* xn, float* r, int nrhs, long sc, long sf, const double* beta, const double* lam,
+                           hipStream_t st);
 void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, const double* xo, double* xn,
                           double* f, int nrhs, long sc, long sf, const double* beta, const double* lam,
                           hipStream_t st);

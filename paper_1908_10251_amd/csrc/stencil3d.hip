@@ -557,13 +557,19 @@ __global__ __launch_bounds__(256) void k_border3z(Grid gf, double w0, const doub
 // nodes of a chunk of ZRC fine planes and keeps three planes of u (and e)
 // with a one-node halo in LDS rings; the arithmetic is that of
 // k_resid_cast3 / k_add_resid3 with the mass term.
+// PRO: u itself is formed in the ring, u = P q + beta u~ (q the coarse-space
+// field on the next coarser grid, u~ the old field in the input, a zero beta
+// dropping it), and written to un: the prolongation of a correction step and
+// the next step's first residual in one pass.
 constexpr int ZFX = 32, ZFY = 32, ZRC = 16;
 constexpr int ZQX = ZFX + 2, ZQY = ZFY + 2, ZNQ = ZQX * ZQY, ZPQ = (ZNQ + 255) / 256, ZPO = ZFX * ZFY / 256;
-template <bool ADD>
+template <bool ADD, bool PRO = false>
 __global__ __launch_bounds__(256) void k_resid3z(Grid g, double w0, const double* __restrict__ u,
                                                  const float* __restrict__ e, const double* __restrict__ lam,
                                                  double* __restrict__ un, float* __restrict__ r, long sf,
-                                                 int zchunks) {
+                                                 int zchunks, Grid gc, const double* __restrict__ xc, long sc,
+                                                 const double* __restrict__ beta) {
+    static_assert(!(ADD && PRO), "the prolonging pass starts a step");
     __shared__ double us[3][ZNQ];
     __shared__ float es[ADD ? 3 : 1][ADD ? ZNQ : 1];
     const int tid = threadIdx.x;
@@ -575,24 +581,47 @@ __global__ __launch_bounds__(256) void k_resid3z(Grid g, double w0, const double
     const double lz = lam[z];
     long qo[ZPQ];
     bool qin[ZPQ];
+    int qi[ZPQ], qj[ZPQ];
 #pragma unroll
     for (int q = 0; q < ZPQ; ++q) {
         const int t = tid + 256 * q;
         const int i = i0 - 1 + t % ZQX, j = j0 - 1 + t / ZQX;
         qin[q] = t < ZNQ && i <= g.n && j <= g.n;
-        qo[q] = (long)min(j, g.n) * g.pitch + ORIGIN + min(i, g.n);
+        qi[q] = min(i, g.n);
+        qj[q] = min(j, g.n);
+        qo[q] = (long)qj[q] * g.pitch + ORIGIN + qi[q];
     }
     const long pz = (long)g.pitch * (g.n + 1);
+    const double* cr = PRO ? xc + (long)z * sc : nullptr;
+    const double bz = PRO ? beta[z] : 0.0;
+    const long cpz = (long)gc.pitch * (gc.n + 1);
     auto load = [&](int k, double (&vu)[ZPQ], float (&ve)[ZPQ]) {
-        const long base = (long)min(max(k, 0), g.n) * pz;
+        const int kc = min(max(k, 0), g.n);
+        const long base = (long)kc * pz;
 #pragma unroll
         for (int q = 0; q < ZPQ; ++q) {
             vu[q] = ur[base + qo[q]];
             if (ADD) ve[q] = er[base + qo[q]];
         }
+        if constexpr (PRO) {
+            // the nodal interpolation: the coarse node, or the mean of the
+            // two ends of the coarse Kuhn edge the fine node halves
+#pragma unroll
+            for (int q = 0; q < ZPQ; ++q) {
+                const int i = qi[q], j = qj[q];
+                const long cid = gc.idx(i >> 1, j >> 1, kc >> 1);
+                double v = cr[cid];
+                if ((i | j | kc) & 1)
+                    v = 0.5 * (v + cr[cid + (i & 1) + (long)(j & 1) * gc.pitch + (long)(kc & 1) * cpz]);
+                if (bz != 0.0) v += bz * vu[q];
+                vu[q] = v;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < ZPQ; ++q)
-            if (!qin[q] || k > g.n) vu[q] = 0.0, ve[q] = 0.0f;
+            if (!qin[q] || k > g.n || (PRO && (qi[q] < 1 || qj[q] < 1 || qi[q] > g.m || qj[q] > g.m || kc < 1 ||
+                                               kc > g.m)))
+                vu[q] = 0.0, ve[q] = 0.0f;
     };
     auto store = [&](int slot, const double (&vu)[ZPQ], const float (&ve)[ZPQ]) {
 #pragma unroll
@@ -640,7 +669,7 @@ __global__ __launch_bounds__(256) void k_resid3z(Grid g, double w0, const double
             }
             const double Ax = w0 * (6.0 * x0 - (xe + xw + xn + xs + xu + xd));
             const long id = (long)z * sf + (long)p * pz + (long)j * g.pitch + ORIGIN + i;
-            if (ADD) un[id] = x0;
+            if (ADD || PRO) un[id] = x0;
             r[id] = (float)(fv - Ax);
         }
         __syncthreads();
@@ -970,6 +999,18 @@ void launch_prolong_mass3(const Grid& gc, const double* xc, const Grid& gf, cons
     PASM_CHECK_LAUNCH();
 }
 
+void launch_prolong_resid3(const Grid& gc, const double* xc, const Grid& gf, const Coef<double>& c, const double* xo,
+                           double* xn, float* r, int nrhs, long sc, long sf, const double* beta, const double* lam,
+                           hipStream_t st) {
+    if (gf.dim != 3 || gc.n * 2 != gf.n || c.wx || c.s15 || xn == xo)
+        throw Error(PASM_E_INVALID, "prolongation with the first residual (3D): constant coefficients, ratio 2");
+    const int zc = (gf.m + ZRC - 1) / ZRC;
+    dim3 grid((gf.m + ZFX - 1) / ZFX, (gf.m + ZFY - 1) / ZFY, zc * nrhs);
+    hipLaunchKernelGGL((k_resid3z<false, true>), grid, dim3(256), 0, st, gf, c.w0, xo, (const float*)nullptr, lam,
+                       xn, r, sf, zc, gc, xc, sc, beta);
+    PASM_CHECK_LAUNCH();
+}
+
 void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double* f, int nrhs, long stride,
                       hipStream_t st) {
     hipLaunchKernelGGL(k_mass_rhs3, grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, u, lam, f, stride);
@@ -983,8 +1024,8 @@ void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, c
     if (lam) {
         const int zc = (g.m + ZRC - 1) / ZRC;
         dim3 grid((g.m + ZFX - 1) / ZFX, (g.m + ZFY - 1) / ZFY, zc * nrhs);
-        hipLaunchKernelGGL(k_resid3z<false>, grid, dim3(256), 0, st, g, c.w0, u, (const float*)nullptr, lam,
-                           (double*)nullptr, r, stride, zc);
+        hipLaunchKernelGGL((k_resid3z<false>), grid, dim3(256), 0, st, g, c.w0, u, (const float*)nullptr, lam,
+                           (double*)nullptr, r, stride, zc, g, (const double*)nullptr, 0L, (const double*)nullptr);
     }
     else if (c.wx)
         hipLaunchKernelGGL((k_resid_cast3<false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, f, r, stride,
@@ -1003,7 +1044,8 @@ void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, co
     if (lam) {
         const int zc = (g.m + ZRC - 1) / ZRC;
         dim3 grid((g.m + ZFX - 1) / ZFX, (g.m + ZFY - 1) / ZFY, zc * nrhs);
-        hipLaunchKernelGGL(k_resid3z<true>, grid, dim3(256), 0, st, g, c.w0, u, e, lam, un, r, stride, zc);
+        hipLaunchKernelGGL((k_resid3z<true>), grid, dim3(256), 0, st, g, c.w0, u, e, lam, un, r, stride, zc, g,
+                           (const double*)nullptr, 0L, (const double*)nullptr);
     }
     else if (c.wx)
         hipLaunchKernelGGL((k_add_resid3<false>), grid3(g.m, nrhs), dim3(BX, BY), 0, st, g, c, u, e, f, un, r, stride,
