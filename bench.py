@@ -450,7 +450,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the eigenpairs are independent, "
-              f"so a multi-GPU run would shard them, which this build does not do.", file=sys.stderr)
+              f"so a multi-GPU run would shard them, which this program does not do.", file=sys.stderr)
         sys.exit(2)
 
     import torch
