@@ -1102,6 +1102,13 @@ void prolong_coefs(pasm_ctx* c, const double* s, const double* lamf = nullptr, b
         pasm::launch_prolong<double>(c->lv[l - 1].g, c->lv[l - 1].B, c->lv[l].g, c->lv[l].B, k, c->lv[l - 1].g.plane,
                                      c->lv[l].g.plane, false, nullptr, c->st);
     const pasm::Level& Lc = c->lv[c->L - 2];
+    if (s && c->f_mass && c->lv[c->L - 1].general3) {
+        // no f to form (the residual passes form lambda M u): u = P q + s u~
+        // node by node, in place
+        pasm::launch_prolong<double>(Lc.g, Lc.B, c->gf(), c->U, k, Lc.g.plane, c->sf(), false, s, c->st);
+        c->f_ready = false;
+        return;
+    }
     if (s && c->f_mass) {
         // no f to form (the residual passes form lambda M u): u = P q + s u~
         // into the scratch field (then swapped in), with the next step's

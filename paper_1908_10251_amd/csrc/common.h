@@ -369,9 +369,11 @@ template <typename T>
 void launch_resid3g(const Grid& g, const T* s15, const T* x, const T* f, T* r, int nrhs, long stride,
                     hipStream_t st);
 void launch_resid_cast3g(const Grid& g, const double* s15, const double* u, const double* f, float* r, int nrhs,
-                         long stride, hipStream_t st);
+                         long stride, hipStream_t st,
+                         const double* lam = nullptr);
 void launch_add_resid3g(const Grid& g, const double* s15, const double* u, const float* e, const double* f,
-                        double* un, float* r, int nrhs, long stride, hipStream_t st);
+                        double* un, float* r, int nrhs, long stride, hipStream_t st,
+                        const double* lam = nullptr);
 // the borders' fine-level vectors of the 15-point operator; with e (and un),
 // of u + e, written to un
 int launch_border3g(const Grid& g, const double* s15, const double* u, double* au, double* mu, double* partial,

@@ -382,9 +382,25 @@ __global__ __launch_bounds__(GX* GY) void k_resid3g(Grid g, const T* __restrict_
     }
 }
 
+// lam M u at id with the arithmetic of the 3D prolongation kernel that forms
+// f (axis and body diagonals / 20, face diagonals / 30, summed in its order)
+__device__ inline double lam_mass15(const Grid& g, const double* __restrict__ u, long id, double lam) {
+    const long py = g.pitch, pz = (long)g.pitch * (g.n + 1);
+    const double ax = u[id + 1] + u[id - 1] + u[id + py] + u[id - py] + u[id + pz] + u[id - pz];
+    const double fd = u[id + 1 + py] + u[id - 1 - py] + u[id + 1 + pz] + u[id - 1 - pz] + u[id + py + pz] +
+                      u[id - py - pz];
+    const double bd = u[id + 1 + py + pz] + u[id - 1 - py - pz];
+    const double h3 = g.h * g.h * g.h;
+    return lam * (h3 * (0.4 * u[id] + (ax + bd) * (1.0 / 20.0) + fd * (1.0 / 30.0)));
+}
+
+// MASS: f is not read but formed as lam M u from u itself (u is the start
+// of the correction step).
+template <bool MASS = false>
 __global__ __launch_bounds__(GX* GY) void k_resid_cast3g(Grid g, const double* __restrict__ s15,
                                                          const double* __restrict__ u, const double* __restrict__ f,
-                                                         float* __restrict__ r, long stride, int nrhs) {
+                                                         float* __restrict__ r, long stride, int nrhs,
+                                                         const double* __restrict__ lam) {
     const P3b p = p3b(g);
     if (!p.ok) return;
     Row15<double> row;
@@ -395,14 +411,18 @@ __global__ __launch_bounds__(GX* GY) void k_resid_cast3g(Grid g, const double* _
         if (z >= nrhs) break;
         const long off = (long)z * stride;
         const double* ur = u + off;
-        r[off + p.id] = (float)(f[off + p.id] - row.apply(g, p.id, [&](long k) { return ur[k]; }));
+        const double fv = MASS ? lam_mass15(g, ur, p.id, lam[z]) : f[off + p.id];
+        r[off + p.id] = (float)(fv - row.apply(g, p.id, [&](long k) { return ur[k]; }));
     }
 }
 
+// MASS: f formed as lam M u from u (the step's first cycle).
+template <bool MASS = false>
 __global__ __launch_bounds__(GX* GY) void k_add_resid3g(Grid g, const double* __restrict__ s15,
                                                         const double* __restrict__ u, const float* __restrict__ e,
                                                         const double* __restrict__ f, double* __restrict__ un,
-                                                        float* __restrict__ r, long stride, int nrhs) {
+                                                        float* __restrict__ r, long stride, int nrhs,
+                                                        const double* __restrict__ lam) {
     const P3b p = p3b(g);
     if (!p.ok) return;
     Row15<double> row;
@@ -414,10 +434,12 @@ __global__ __launch_bounds__(GX* GY) void k_add_resid3g(Grid g, const double* __
         const long off = (long)z * stride;
         const double* ur = u + off;
         const float* er = e + off;
+        const double fv = MASS ? lam_mass15(g, ur, p.id, lam[z]) : f[off + p.id];
         auto v = [&](long k) { return ur[k] + (double)er[k]; };
         const double x0 = v(p.id);
+        const double Ax = row.apply(g, p.id, v);
         un[off + p.id] = x0;
-        r[off + p.id] = (float)(f[off + p.id] - row.apply(g, p.id, v));
+        r[off + p.id] = (float)(fv - Ax);
     }
 }
 
@@ -518,15 +540,24 @@ void launch_resid_restrict3g(const Grid& gf, const T* s15, const T* x, const T* 
 }
 
 void launch_resid_cast3g(const Grid& g, const double* s15, const double* u, const double* f, float* r, int nrhs,
-                         long stride, hipStream_t st) {
-    hipLaunchKernelGGL(k_resid_cast3g, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, f, r, stride, nrhs);
+                         long stride, hipStream_t st, const double* lam) {
+    if (lam)
+        hipLaunchKernelGGL(k_resid_cast3g<true>, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, f, r, stride,
+                           nrhs, lam);
+    else
+        hipLaunchKernelGGL(k_resid_cast3g<false>, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, f, r, stride,
+                           nrhs, nullptr);
     PASM_CHECK_LAUNCH();
 }
 
 void launch_add_resid3g(const Grid& g, const double* s15, const double* u, const float* e, const double* f,
-                        double* un, float* r, int nrhs, long stride, hipStream_t st) {
-    hipLaunchKernelGGL(k_add_resid3g, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, e, f, un, r, stride,
-                       nrhs);
+                        double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam) {
+    if (lam)
+        hipLaunchKernelGGL(k_add_resid3g<true>, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, e, f, un, r,
+                           stride, nrhs, lam);
+    else
+        hipLaunchKernelGGL(k_add_resid3g<false>, grid3rb(g.m, nrhs), dim3(GX, GY), 0, st, g, s15, u, e, f, un, r,
+                           stride, nrhs, nullptr);
     PASM_CHECK_LAUNCH();
 }
 

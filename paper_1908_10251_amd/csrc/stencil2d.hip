@@ -1164,7 +1164,7 @@ void launch_resid_cast(const Grid& g, const Coef<double>& c, const double* u, co
 
 bool mass_rhs_fusable(const Grid& g, const Coef<double>& c) {
     if (c.kpm > 1 || c.ms != 0) return false;
-    return (g.dim == 2 && coef_kind(c) == 1) || (g.dim == 3 && coef_kind(c) == 0);
+    return (g.dim == 2 && coef_kind(c) == 1) || (g.dim == 3 && (coef_kind(c) == 0 || c.s15));
 }
 
 template <typename TO>

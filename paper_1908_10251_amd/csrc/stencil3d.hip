@@ -1019,8 +1019,8 @@ void launch_mass_rhs3(const Grid& g, const double* u, const double* lam, double*
 
 void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, const double* f, float* r,
                         int nrhs, long stride, hipStream_t st, const double* lam) {
-    if (lam && (c.s15 || c.wx)) throw Error(PASM_E_INVALID, "residual with lam M u (3D): constant coefficients");
-    if (c.s15) return launch_resid_cast3g(g, c.s15, u, f, r, nrhs, stride, st);
+    if (lam && c.wx) throw Error(PASM_E_INVALID, "residual with lam M u (3D): constant or 15-point operators");
+    if (c.s15) return launch_resid_cast3g(g, c.s15, u, f, r, nrhs, stride, st, lam);
     if (lam) {
         const int zc = (g.m + ZRC - 1) / ZRC;
         dim3 grid((g.m + ZFX - 1) / ZFX, (g.m + ZFY - 1) / ZFY, zc * nrhs);
@@ -1039,8 +1039,8 @@ void launch_resid_cast3(const Grid& g, const Coef<double>& c, const double* u, c
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                        double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam) {
     if (g.dim != 3 || un == u) throw Error(PASM_E_INVALID, "add and residual: 3D, separate output");
-    if (lam && (c.s15 || c.wx)) throw Error(PASM_E_INVALID, "add and residual with lam M u (3D): constant coefficients");
-    if (c.s15) return launch_add_resid3g(g, c.s15, u, e, f, un, r, nrhs, stride, st);
+    if (lam && c.wx) throw Error(PASM_E_INVALID, "add and residual with lam M u (3D): constant or 15-point operators");
+    if (c.s15) return launch_add_resid3g(g, c.s15, u, e, f, un, r, nrhs, stride, st, lam);
     if (lam) {
         const int zc = (g.m + ZRC - 1) / ZRC;
         dim3 grid((g.m + ZFX - 1) / ZFX, (g.m + ZFY - 1) / ZFY, zc * nrhs);
