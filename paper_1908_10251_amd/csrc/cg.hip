@@ -250,6 +250,120 @@ __global__ __launch_bounds__(CX* CY) void k_cg_dir(Grid g, Coef<T> c, const T* _
     block_partials<RB>(acc, partial + (long)n.r0 * nblk + n.blk, nblk, nv);
 }
 
+// The direction pass for 3D 15-point operators marching along z: a
+// workgroup owns ZX x ZY nodes of a chunk of ZC planes for RB right-hand
+// sides, and keeps the last three planes of the new direction
+// p = r + beta p_old (one-node halo) for all of them in an LDS ring, formed
+// while the plane enters; q = A p comes from the ring, each node's 15
+// coefficients loaded once for the RB right-hand sides.  The arithmetic is
+// k_cg_dir's; the partial sums are per workgroup of this grid.
+constexpr int ZX = 32, ZY = 16, ZC = 16;
+constexpr int ZHX = ZX + 2, ZHY = ZY + 2, ZN = ZHX * ZHY, ZPL = (ZN + CX * CY - 1) / (CX * CY),
+              ZOWN = ZX * ZY / (CX * CY);
+template <typename T, bool FIRST, int RB>
+__global__ __launch_bounds__(CX* CY) void k_cg_dir_z(Grid g, Coef<T> c, const T* __restrict__ r,
+                                                     const T* __restrict__ pold, const double* __restrict__ beta,
+                                                     T* __restrict__ pnew, T* __restrict__ q,
+                                                     double* __restrict__ partial, long stride, long nblk, int nrhs,
+                                                     int zchunks) {
+    constexpr int NT = CX * CY;
+    __shared__ T ring[RB][3][ZN];
+    const int tid = threadIdx.y * CX + threadIdx.x;
+    const int zc = blockIdx.z % zchunks, grp = blockIdx.z / zchunks;
+    const int r0 = grp * RB, nv = min(RB, nrhs - r0);
+    const int i0 = blockIdx.x * ZX + 1, j0 = blockIdx.y * ZY + 1;
+    const int k0 = zc * ZC + 1, k1 = min(k0 + ZC, g.m + 1);
+    const long blk = ((long)zc * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const long pz = (long)g.pitch * (g.n + 1);
+    // ring positions of this thread (clamped onto the grid; outside the
+    // interior the direction is zero)
+    long ho[ZPL];
+    bool hin[ZPL];
+#pragma unroll
+    for (int e = 0; e < ZPL; ++e) {
+        const int t = tid + NT * e;
+        const int i = i0 - 1 + t % ZHX, j = j0 - 1 + t / ZHX;
+        hin[e] = t < ZN && i >= 1 && j >= 1 && i <= g.m && j <= g.m;
+        ho[e] = (long)min(j, g.n) * g.pitch + ORIGIN + min(i, g.n);
+    }
+    T b[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) b[u] = (!FIRST && u < nv) ? (T)beta[r0 + u] : T(0);
+    // the direction at plane k of the ring positions, for every right-hand side
+    auto form = [&](int k, T (&v)[RB][ZPL]) {
+        const bool kin = k >= 1 && k <= g.m;
+        const long base = (long)min(max(k, 0), g.n) * pz;
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const long off = (long)(r0 + min(u, nv - 1)) * stride + base;
+#pragma unroll
+            for (int e = 0; e < ZPL; ++e) {
+                const T rv = r[off + ho[e]];
+                const T pv = FIRST ? rv : rv + b[u] * pold[off + ho[e]];
+                v[u][e] = (kin && hin[e]) ? pv : T(0);
+            }
+        }
+    };
+    auto store = [&](int slot, const T (&v)[RB][ZPL]) {
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+#pragma unroll
+            for (int e = 0; e < ZPL; ++e)
+                if (tid + NT * e < ZN) ring[u][slot][tid + NT * e] = v[u][e];
+    };
+    double acc[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) acc[u] = 0.0;
+    T va[RB][ZPL], vb[RB][ZPL];
+    form(k0 - 1, va);
+    form(k0, vb);
+    store((k0 - 1) % 3, va);
+    store(k0 % 3, vb);
+    form(k0 + 1, va);
+    // ring offsets of the seven Kuhn edge directions (x, y within the plane;
+    // z by the ring slot)
+    constexpr int o_in[7] = {1, ZHX, 0, 1 + ZHX, 1, ZHX, 1 + ZHX};
+    constexpr int o_dz[7] = {0, 0, 1, 0, 1, 1, 1};
+    for (int k = k0; k < k1; ++k) {
+        store((k + 1) % 3, va);
+        if (k + 1 < k1) form(k + 2, va);  // one plane ahead
+        __syncthreads();
+        const int s0 = k % 3, sp = (k + 1) % 3, sm = (k + 2) % 3;
+#pragma unroll
+        for (int e = 0; e < ZOWN; ++e) {
+            const int t = tid + NT * e;
+            const int a = t % ZX, bb = t / ZX;
+            const int i = i0 + a, j = j0 + bb;
+            if (i > g.m || j > g.m) continue;
+            const long gid = (long)k * pz + (long)j * g.pitch + ORIGIN + i;
+            OpRow<T, 3, 3> row;
+            row.load(g, c, gid);
+            const int hc = (bb + 1) * ZHX + (a + 1);
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                if (u >= nv) break;
+                const T* R0 = ring[u][s0];
+                const T* RP = ring[u][sp];
+                const T* RM = ring[u][sm];
+                const T p0 = R0[hc];
+                T qv = row.d * p0;
+#pragma unroll
+                for (int tt = 0; tt < 7; ++tt) {
+                    const T* Ru = o_dz[tt] ? RP : R0;
+                    const T* Rd = o_dz[tt] ? RM : R0;
+                    qv += row.up[tt] * Ru[hc + o_in[tt]] + row.dn[tt] * Rd[hc - o_in[tt]];
+                }
+                const long id = (long)(r0 + u) * stride + gid;
+                pnew[id] = p0;
+                q[id] = qv;
+                acc[u] += (double)p0 * (double)qv;
+            }
+        }
+        __syncthreads();
+    }
+    block_partials<RB>(acc, partial + (long)r0 * nblk + blk, nblk, nv);
+}
+
 // x += alpha p (XZ: x = alpha p); with RR also r -= alpha q and partial sums of r.r
 template <typename T, int DIM, bool RR, bool XZ>
 __global__ __launch_bounds__(CX* CY) void k_cg_update(Grid g, T* __restrict__ x, T* __restrict__ r,
@@ -336,14 +450,29 @@ void cg_run(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int ste
         hipLaunchKernelGGL((k_cg_start<T, DIM, KIND, false>), grid_op, blk, 0, st, g, c, x, f, r, w.partial, sd,
                            nblk, nrhs);
     hipLaunchKernelGGL(k_cg_reduce<0>, dim3(nrhs), dim3(256), 0, st, w.partial, nblk, w.rr, (double*)nullptr);
+    // 15-point operators: the direction pass marching along z
+    constexpr bool ZM = DIM == 3 && KIND == 3;
+    const int nzc = (g.m + ZC - 1) / ZC;
+    const dim3 grid_z((g.m + ZX - 1) / ZX, (g.m + ZY - 1) / ZY, nzc * ngrp);
+    const long nblk_z = (long)grid_z.x * grid_z.y * nzc;
     for (int s = 0; s < steps; ++s) {
-        if (s == 0)
-            hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, true>), grid_op, blk, 0, st, g, c, r, pb, w.beta, pa, q,
-                               w.partial, sd, nblk, nrhs);
-        else
-            hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, false>), grid_op, blk, 0, st, g, c, r, pb, w.beta, pa, q,
-                               w.partial, sd, nblk, nrhs);
-        hipLaunchKernelGGL(k_cg_reduce<1>, dim3(nrhs), dim3(256), 0, st, w.partial, nblk, w.rr, w.alpha);
+        if constexpr (ZM) {
+            if (s == 0)
+                hipLaunchKernelGGL((k_cg_dir_z<T, true, RB>), grid_z, blk, 0, st, g, c, r, pb, w.beta, pa, q,
+                                   w.partial, sd, nblk_z, nrhs, nzc);
+            else
+                hipLaunchKernelGGL((k_cg_dir_z<T, false, RB>), grid_z, blk, 0, st, g, c, r, pb, w.beta, pa, q,
+                                   w.partial, sd, nblk_z, nrhs, nzc);
+        } else {
+            if (s == 0)
+                hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, true>), grid_op, blk, 0, st, g, c, r, pb, w.beta, pa, q,
+                                   w.partial, sd, nblk, nrhs);
+            else
+                hipLaunchKernelGGL((k_cg_dir<T, DIM, KIND, false>), grid_op, blk, 0, st, g, c, r, pb, w.beta, pa, q,
+                                   w.partial, sd, nblk, nrhs);
+        }
+        hipLaunchKernelGGL(k_cg_reduce<1>, dim3(nrhs), dim3(256), 0, st, w.partial, ZM ? nblk_z : nblk, w.rr,
+                           w.alpha);
         const bool last = s == steps - 1, xz = x_zero && s == 0;
         if (last) {
             if (xz)
