@@ -26,10 +26,11 @@ Files
     python -m oracle.make_golden [target ...]
 
 targets: eigenvalues, vectors, kappa-step1, batch-step1, cube-step1,
-laplace-steps3 (default: all).
+ex2-step1, laplace-steps3 (default: all).
 """
 from __future__ import annotations
 
+import dataclasses
 import json
 import os
 import sys
@@ -133,6 +134,20 @@ def write_cube_step1(workers: int) -> str:
     return _steps(wl.name, prob, wl, 1, workers, True)
 
 
+EX2_PAIRS = 16  # processes recorded for the second example (of its 200)
+
+
+def write_ex2_step1(workers: int) -> str:
+    """The second example (full tensor and potential on the cube, the
+    paper's CG(2) multigrid step): the first EX2_PAIRS processes' first
+    step; each process is independent of the others."""
+    wl = W.EX2_3D
+    prob = O.make_problem(3, wl.n_coarse, wl.n_fine, tensor=fem.example2_tensor, potential=fem.example2_potential)
+    sub = dataclasses.replace(wl, k=EX2_PAIRS)
+    return _steps(wl.name, prob, sub, 1, workers, True, pairs_of=wl.k,
+                  coefficients="A = I + (x-1/2)(x-1/2)^T, phi = exp(prod(x_i - 1/2)) at element centroids")
+
+
 def write_laplace_steps3(workers: int) -> str:
     wl = W.LAP2D_LARGE_H64
     prob = O.make_problem(2, wl.n_coarse, wl.n_fine)
@@ -141,7 +156,7 @@ def write_laplace_steps3(workers: int) -> str:
 
 if __name__ == "__main__":
     targets = sys.argv[1:] or ["eigenvalues", "vectors", "kappa-step1", "batch-step1", "cube-step1",
-                               "laplace-steps3"]
+                               "ex2-step1", "laplace-steps3"]
     workers = min(8, O.cpu_count())
     for tg in targets:
         if tg == "eigenvalues":
@@ -155,6 +170,8 @@ if __name__ == "__main__":
             write_batch_step1(workers)
         elif tg == "cube-step1":
             write_cube_step1(workers)
+        elif tg == "ex2-step1":
+            write_ex2_step1(workers)
         elif tg == "laplace-steps3":
             write_laplace_steps3(workers)
         else:

@@ -153,6 +153,34 @@ def test_one_step_cube_2m_nodes_100_pairs():
     _one_step_case(3, wl, wl.name, wl.n_fine)
 
 
+def test_one_step_example2_2m_nodes():
+    # the second example at the benchmark's size (128^3, H = 1/16, full
+    # tensor and potential, the paper's CG(2) multigrid step): the stored
+    # first step of the oracle's first 16 processes (each process is
+    # independent of the others, so a context of those 16 takes the same
+    # step as the 200 of the benchmark), from the identical start
+    wl = W.EX2_3D
+    g = _load(wl.name, "step1.npz")
+    k = g["lam"].shape[1]
+    _say(f"one step {wl.name}: 128^3, first {k} of {wl.k} processes, full tensor + potential, CG(2)")
+    U0 = _start(3, wl.n_coarse, wl.n_fine, g)
+    ten, phi = W.example2_elements(wl.n_fine)
+    for prec, lam_tol, u_tol in ((P.PASM_FP64, 1e-10, 1e-8), (P.PASM_MIXED, 1e-8, 1e-6)):
+        opts = P.options(precision=prec, smoother=P.PASM_CG, nu_pre=wl.nu_pre, nu_post=wl.nu_post,
+                         vcycles=wl.vcycles)
+        with P.Solver(3, wl.H, wl.h, k, tensor=ten, potential=phi, opts=opts) as s:
+            P.pasm_set_state(s.ctx, g["theta"], U0)
+            s.iterate()
+            tag = "fp64" if prec == P.PASM_FP64 else "mixed"
+            lam, rank, score, bz = _compare_step(s, g, 0, k, lam_tol, u_tol, tag=tag)
+            if prec == P.PASM_FP64:
+                assert np.array_equal(rank, g["index"][0].astype(np.int32)), (rank, g["index"][0])
+                assert np.max(np.abs(score - g["score"][0]) / g["score"][0]) < 1e-8
+                assert np.max(np.abs(bz[:, 0] - g["beta"][0]) / g["beta"][0]) < 1e-10
+                assert np.max(np.abs(bz[:, 1] - g["zeta"][0]) / g["zeta"][0]) < 1e-10
+        gc.collect()
+
+
 def test_three_steps_laplace_1m_nodes_from_the_library_start():
     # the library's own coarse start (a restart): the coarse eigenvectors
     # match the oracle's up to sign, so u is compared up to sign
