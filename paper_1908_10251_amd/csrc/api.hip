@@ -908,8 +908,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
     }
     c->bz = c->alloc<double>(2 * (size_t)k);
     const Grid& gfine = c->gf();
-    const long nblk = (dim == 2) ? (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4)
-                                 : (long)((gfine.m + 63) / 64) * ((gfine.m + 3) / 4) * gfine.m;
+    const long nblk = pasm::border_partial_blocks(gfine);
     c->partial = c->alloc<double>(2 * (size_t)nblk * k);
     c->pp = c->alloc<double>(2 * (size_t)N * k);
     c->qq = c->pp + (size_t)N * k;

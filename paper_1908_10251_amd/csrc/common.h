@@ -316,6 +316,21 @@ int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const doubl
                                const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
                                hipStream_t st);
 
+// The borders after the last correction as a row-marching pass (rows2d.hip),
+// used by launch_border_restrict_add where rows_supported holds (2D edge
+// weights of a single problem); max_blocks is the capacity of partial in
+// pairs per right-hand side.
+bool rows_supported(const Grid& g, const Coef<double>& c);
+int launch_border_rows(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
+                       const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
+                       long max_blocks, hipStream_t st);
+// Pairs of partial sums per right-hand side that the borders' buffer holds
+// (2D: one per 64 x 4 block of the finest level).
+inline long border_partial_blocks(const Grid& g) {
+    const long b = (long)((g.m + 63) / 64) * ((g.m + 3) / 4);
+    return g.dim == 2 ? b : b * g.m;
+}
+
 // out[r][0..1] = sums of partial[r][0..nblk)[0..1] in a fixed order.
 void launch_reduce_pairs(const double* partial, int nblk, double* out, int nrhs, hipStream_t st);
 

@@ -1275,6 +1275,8 @@ int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const doubl
                                hipStream_t st) {
     if (g.dim != 2 || gc.n * 2 != g.n || un == u || coef_kind(c) == 2)
         throw Error(PASM_E_INVALID, "correction with borders: 2D, ratio 2, constant or edge weights, separate output");
+    if (rows_supported(g, c))
+        return launch_border_rows(g, c, u, e, un, gc, bc, cc, partial, nrhs, stride, sc, border_partial_blocks(g), st);
     dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
     const BorderWork bw{(int)grid.x, (int)grid.y, nrhs};
     if (coef_kind(c) == 0) {
