@@ -553,6 +553,33 @@ def test_3d_mixed_one_step_matches_oracle(vcycles):
         assert eu < 1e-6
 
 
+@pytest.mark.parametrize("nc,nf,k", [(6, 192, 5), (5, 160, 3)])
+def test_2d_mixed_kappa_one_step_ragged_strips(nc, nf, k):
+    # mixed precision with a rough per-element kappa on grids whose interior
+    # (191, 159 nodes per side) leaves a partial last strip and band in the
+    # row-marching border pass (strips of 60 columns) and in the marching
+    # smoother, and a coarse space that is no power of two; against the
+    # oracle's FP64 step, 1e-8 on lambda and 1e-6 on u and the borders
+    _say(f"one mixed kappa step H=1/{nc} h=1/{nf} k={k}")
+    kap = lognormal_kappa(2, nf, seed=12, sigma=1.0)
+    prob = O.make_problem(2, nc, nf, kappa=kap)
+    lam0, U0, _, _ = O.coarse_start(prob, k)
+    bvp = O.MultigridBVP(prob, default_options(2, "cheb", 4, 4, 2))
+    with P.Solver(2, 1 / nc, 1 / nf, k, kappa=kap, opts=_opts("cheb", 4, precision=P.PASM_MIXED)) as s:
+        P.pasm_set_state(s.ctx, lam0, U0)
+        s.iterate()
+        lam, U = s.eigenpairs()
+        bz, _, _ = P.pasm_last_borders(s.ctx, k)
+    for i in range(k):
+        ref = O.correction_step(prob, lam0[i], U0[i], bvp)
+        eu = np.max(np.abs(U[i] - ref["u"])) / np.max(np.abs(ref["u"]))
+        _say(f"  pair {i}: lambda {abs(lam[i] - ref['lam']) / ref['lam']:.1e} u {eu:.1e}")
+        assert bz[i, 0] == pytest.approx(ref["beta"], rel=1e-6)
+        assert bz[i, 1] == pytest.approx(ref["zeta"], rel=1e-6)
+        assert abs(lam[i] - ref["lam"]) / ref["lam"] < 1e-8
+        assert eu < 1e-6
+
+
 def test_variable_kappa_lowest_eigenpair():
     _say("solve kappa2d H=1/8 h=1/64 k=1")
     kap = lognormal_kappa(2, 64, seed=4, sigma=0.5)
