@@ -55,23 +55,24 @@ constexpr int march_unroll(int S, int PF) { return lcm_(lcm_(3, S + 2), PF); }
 // that every lane's first column, the centre of a restriction, is even.
 constexpr int march_halo(int S) { return (S + 3) & ~1; }
 
-// Cross-lane moves of a double by one lane (DPP wave shifts; the lane at the
-// wavefront edge receives 0, which only ever reaches halo columns).
+// Cross-lane moves by one lane (DPP wave shifts).  The lane at the wavefront
+// edge has no source and receives 0 (bound control), which only ever reaches
+// halo columns; with no old value to merge, no register has to be zeroed first.
 __device__ inline double from_left(double v) {  // value of lane l - 1
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ inline double from_right(double v) {  // value of lane l + 1
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ inline float from_left(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 __device__ inline float from_right(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
 // A register copy the compiler cannot fold away: the copy, not the loaded
@@ -692,18 +693,22 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
         for (int j = S + 1; j > 0; --j) cww[j] = cww[j - 1];
         // 1 / D of row r: east, west (the left lane's east weight for the
-        // first column), north and south (row r - 1's north) weights
+        // first column), north and south (row r - 1's north) weights.  On
+        // boundary and outside nodes it is 0: there every stage keeps
+        // x = (1 - b) x + a (x - x_prev), which stays at the loaded 0, so the
+        // stages need no mask (and no branch on the row)
         cww[0] = from_left(cwx[0][1]);
-        cdi[0][0] = recip(cwx[0][0] + cww[0] + cwy[0][0] + cwy[1][0]);
-        cdi[0][1] = recip(cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
+        const bool rin = r >= 1 && r <= g.m;
+        const T d0 = recip(cwx[0][0] + cww[0] + cwy[0][0] + cwy[1][0]);
+        const T d1 = recip(cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
+        cdi[0][0] = (rin && inner[0]) ? d0 : T(0);
+        cdi[0][1] = (rin && inner[1]) ? d1 : T(0);
     };
     // after row r entered: every stage advances one row, x_S of row r - S is
     // stored, and (PRE) the residual and its restriction
     auto advance = [&](const int r) {
 #pragma unroll
         for (int t = 1; t <= S; ++t) {
-            const int q = r - t;
-            const bool row_in = q >= 1 && q <= g.m;  // uniform
             const T we[2] = {cwx[t][0], cwx[t][1]};
             const T ww[2] = {cww[t], cwx[t][0]};
 #pragma unroll
@@ -722,7 +727,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     sfv = __builtin_fmaf(cwy[t + 1][cc], xw[n][t - 1][2][cc], sfv);
                     T val = __builtin_fmaf(bs[t - 1], __builtin_fmaf(sfv, cdi[t][cc], -mc[cc]), mc[cc]);
                     if (t >= 2) val = __builtin_fmaf(as[t - 1], mc[cc] - xw[n][t - 2][2][cc], val);
-                    v[cc] = (row_in && inner[cc]) ? val : T(0);
+                    v[cc] = val;
                 }
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
@@ -746,9 +751,10 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             // residual at row r - S - 1 from x_S rows (r-S, r-S-1, r-S-2), in
             // the difference form (the restricted residual is small against
             // D x once the error is smooth); then the restriction to the
-            // coarse node centred at (i0, r - S - 2)
-            const int q1 = r - S - 1;
-            const bool row_in = q1 >= 1 && q1 <= g.m;
+            // coarse node centred at (i0, r - S - 2).  An interior coarse
+            // node's seven fine nodes are interior, so the residuals of
+            // boundary and outside nodes (finite, not zero) never reach a
+            // stored value
             const int q2 = r - S - 2;
             const bool rrow = ((q2 & 1) == 0) && q2 >= y0 && q2 < y0 + MSEG && (q2 >> 1) >= 1 && (q2 >> 1) <= gc.m;
             const unsigned sor = 4u * (unsigned)(gcx(max(q2, 0) >> 1) * gc.pitch + ORIGIN);
@@ -761,8 +767,6 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                             cwy[S + 1][0] * (m0 - xw[n][S][0][0]) + cwys[0] * (m0 - xw[n][S][2][0]));
                 T res1 = fw[n][S + 1][1] - (cwx[S + 1][1] * (m1 - right) + cwx[S + 1][0] * (m1 - m0) +
                                             cwy[S + 1][1] * (m1 - xw[n][S][0][1]) + cwys[1] * (m1 - xw[n][S][2][1]));
-                res0 = (row_in && inner[0]) ? res0 : T(0);
-                res1 = (row_in && inner[1]) ? res1 : T(0);
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
                     rw[n][2][cc] = rw[n][1][cc];
