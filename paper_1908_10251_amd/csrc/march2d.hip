@@ -88,6 +88,10 @@ __device__ inline float detach(float v) {
     return r;
 }
 
+// Fused multiply-add in the type of the operands.
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // 1 / d for the diagonal of an edge-weight row (positive, normal): the
 // hardware reciprocal refined by one Newton step (within an ulp of the
 // quotient, without the division's scaling and fix-up).
@@ -187,12 +191,19 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const double invPR = 1.0 / PR;
     const double h2 = g.h * g.h;
     const T invD = T(1) / (T(4) * w0);
+    // MODE 4: the steps come scaled by 1 / D from the host, the stages form
+    // x + b' (f - A x) with masks; the one-phase modes form
+    // x + b ((f + w0 sum x_nb) / D - x) with 1 / D = 0 on boundary and outside
+    // nodes (a row outside the grid selects 0 for the whole row, a column
+    // outside has 0 in cdl), where x then stays at the loaded 0 and needs no
+    // mask
     T bs[S], as[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        bs[t] = MODE == 4 ? (T)st.b[t] : (T)st.b[t] * invD;  // MODE 4: scaled by the host
+        bs[t] = (T)st.b[t];
         as[t] = (T)st.a[t];
     }
+    const T cdl[2] = {inner[0] ? invD : T(0), inner[1] ? invD : T(0)};
 
     T xw[S + 1][3][2];
     T fw[S + 2][2];
@@ -340,14 +351,23 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const T nb1 = m0 + right + xw[t - 1][0][1] + xw[t - 1][2][1];
             const T mc[2] = {m0, m1};
             const T nb[2] = {nb0, nb1};
-            {
+            if constexpr (MODE == 4) {
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-                const T Ax = w0 * (T(4) * mc[cc] - nb[cc]);
-                T val = mc[cc] + bs[t - 1] * (fw[t][cc] - Ax);
-                if (t >= 2) val += as[t - 1] * (mc[cc] - xw[t - 2][2][cc]);
-                v[cc] = (row_in && inner[cc]) ? val : T(0);
-            }
+                for (int cc = 0; cc < 2; ++cc) {
+                    const T Ax = w0 * (T(4) * mc[cc] - nb[cc]);
+                    T val = mc[cc] + bs[t - 1] * (fw[t][cc] - Ax);
+                    if (t >= 2) val += as[t - 1] * (mc[cc] - xw[t - 2][2][cc]);
+                    v[cc] = (row_in && inner[cc]) ? val : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const T cd = row_in ? cdl[cc] : T(0);
+                    const T sn = fma_t(w0, nb[cc], fw[t][cc]);
+                    T val = fma_t(bs[t - 1], fma_t(sn, cd, -mc[cc]), mc[cc]);
+                    if (t >= 2) val += as[t - 1] * (mc[cc] - xw[t - 2][2][cc]);
+                    v[cc] = val;
+                }
             }
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
@@ -378,8 +398,12 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 res0 = fw[S + 1][0] - w0 * (T(4) * m0 - nb0);
                 res1 = fw[S + 1][1] - w0 * (T(4) * m1 - nb1);
             }
-            res0 = (row_in && inner[0]) ? res0 : T(0);
-            res1 = (row_in && inner[1]) ? res1 : T(0);
+            // (an interior coarse node's seven fine nodes are interior: the
+            // residuals of other nodes, finite, reach no stored value)
+            if constexpr (MODE == 4) {
+                res0 = (row_in && inner[0]) ? res0 : T(0);
+                res1 = (row_in && inner[1]) ? res1 : T(0);
+            }
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
                 rw[2][cc] = rw[1][cc];
@@ -401,7 +425,6 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
         if (MODE == 3) {
             // A u and M u at row r - S - 1 from u = x_S rows (r-S, r-S-1, r-S-2)
             const int q1 = r - S - 1;
-            const bool row_in = q1 >= 1 && q1 <= g.m;
             const T m0 = xw[S][1][0], m1 = xw[S][1][1];
             const T left = from_left(m1), right = from_right(m0);
             const T up0 = xw[S][0][0], up1 = xw[S][0][1], dn0 = xw[S][2][0], dn1 = xw[S][2][1];
@@ -414,11 +437,9 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             T a0 = w0 * (T(4) * m0 - nb0), a1 = w0 * (T(4) * m1 - nb1);
             T b0 = h2 * (T(0.5) * m0 + (nb0 + ne0 + sw0) * T(1.0 / 12.0));
             T b1 = h2 * (T(0.5) * m1 + (nb1 + ne1 + sw1) * T(1.0 / 12.0));
-            const bool in0 = row_in && inner[0], in1 = row_in && inner[1];
-            a0 = in0 ? a0 : T(0);
-            a1 = in1 ? a1 : T(0);
-            b0 = in0 ? b0 : T(0);
-            b1 = in1 ? b1 : T(0);
+            // no masks: u = 0 off the interior, so those nodes add nothing to
+            // the sums, and the restrictions to interior coarse nodes read
+            // interior fine nodes only
             if (q1 >= y0 && q1 < y0 + MSEG) {  // this wavefront's own rows (and columns) for the sums
                 if (owned[0]) {
                     ua += (double)(m0 * a0);
