@@ -88,6 +88,14 @@ __device__ inline float detach(float v) {
     return r;
 }
 
+// Waits until every vector memory access of the wavefront has completed
+// (s_waitcnt vmcnt(0), the other counters left at their maximum).  Issued once
+// after the prologue's loads: the loop header then joins the back edge with
+// an empty state, so its wait is for the oldest row in flight only; without
+// it the header waits for every outstanding access once per unrolled body,
+// because the prologue leaves the first rows in other registers.
+__device__ inline void drain_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Fused multiply-add in the type of the operands.
 __device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -478,6 +486,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     Slot q[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) load(r_begin + p, q[p]);
+    drain_vmem();
     // The loop body covers UNR rows, a multiple of PF and of the periods of
     // the rotating row windows (3 rows of x, S + 2 rows of f), so that after
     // unrolling every window and slot is back in its own registers at the
@@ -807,6 +816,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     Slot q[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) load(r_begin + p, q[p]);
+    drain_vmem();
     constexpr int UNR = ew_unroll<S, PF>();
     const int iters = (r_end - r_begin + UNR) / UNR;
     for (int it = 0; it < iters; ++it) {
