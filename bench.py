@@ -250,6 +250,28 @@ def bench_solve(args, wl, pasm, torch):
     pasm.pasm_profile(ctx, 0, False)
     err = rel_err(lam)
     ms_per_step = 1e3 * elapsed / args.steps
+    replay = None
+    if not learned:
+        # the same solves without profiling events, launched one kernel at a
+        # time and replayed from recorded graphs (pasm_use_graph)
+        def timed_solves(n):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(n):
+                one_solve(first_check)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / n
+
+        t_eager = timed_solves(args.steps)
+        pasm.pasm_use_graph(ctx, True)
+        timed_solves(3)  # record the steps' graphs
+        t_graph = timed_solves(args.steps)
+        _, graphs, replayed = pasm.pasm_graph_stats(ctx)
+        lam_g = solver.eigenpairs(False)[0]
+        pasm.pasm_use_graph(ctx, False)
+        replay = {"ms_per_solve_eager": 1e3 * t_eager, "ms_per_solve_graph": 1e3 * t_graph,
+                  "eigenpairs_per_s_graph": k / t_graph, "graphs": graphs, "replayed_steps": replayed,
+                  "max_rel_err_graph": float(np.max(rel_err(lam_g)))}
     value = k / (ms_per_step / 1e3) if float(np.max(err)) <= 1e-8 else 0.0
     n_dofs = pasm.pasm_num_dofs(ctx)
     sweeps = wl.vcycles * (2 if learned else wl.nu_pre + wl.nu_post)
@@ -258,6 +280,8 @@ def bench_solve(args, wl, pasm, torch):
            "precision": wl.precision, "iterations_per_step": iters, "max_rel_err": float(np.max(err)),
            "eigenpairs_within_1e-8": int(np.sum(err <= 1e-8)), "reference": ref_kind, "setup_s": t_setup,
            "fine_dof_updates_per_s": n_dofs * k * sweeps * float(np.mean(iters)) / (ms_per_step / 1e3)}
+    if replay:
+        cfg["graph_replay"] = replay
     if args.nested:
         cfg["start"] = (f"nested (Algorithm 2 step 2(A)): {args.nested} correction step(s) on each intermediate mesh "
                         f"before the finest-level steps; iterations_per_step counts finest-level steps")
@@ -308,6 +332,29 @@ def coefficient_text(wl: W.Workload) -> str:
     return "constant (Laplacian)"
 
 
+def graph_replay_steps(args, pasm, torch, ctx, k):
+    """The same correction steps without profiling events, launched one
+    kernel at a time and then replayed from recorded graphs (pasm_use_graph);
+    reported beside the timed region's value, which carries the events that
+    time the roofline kernel."""
+    def timed(n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            pasm.pasm_iterate(ctx)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / n
+
+    t_eager = timed(args.iters)
+    pasm.pasm_use_graph(ctx, True)
+    timed(7)  # record: the step states recur every 6 steps (3 eigenvalue buffers, 2 for u)
+    t_graph = timed(args.iters)
+    _, graphs, replayed = pasm.pasm_graph_stats(ctx)
+    pasm.pasm_use_graph(ctx, False)
+    return {"ms_per_step_eager": 1e3 * t_eager, "ms_per_step_graph": 1e3 * t_graph,
+            "eigenpair_steps_per_s_graph": k / t_graph, "graphs": graphs, "replayed_steps": replayed}
+
+
 def bench_steps(args, wl, pasm, torch):
     """Single instances that the method does not take to 1e-8 for every
     eigenpair (rough coefficients, the cube's clusters) and the second
@@ -335,6 +382,8 @@ def bench_steps(args, wl, pasm, torch):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     launches, ms, bpl = pasm.pasm_profile_read(ctx, 0)
+    pasm.pasm_profile(ctx, 0, False)
+    replay = graph_replay_steps(args, pasm, torch, ctx, k) if not learned else None
     H = np.array(hist)
     d = np.abs(H[1:] - H[:-1]) / H[1:]
     ms_per_step = 1e3 * elapsed / args.iters
@@ -344,6 +393,8 @@ def bench_steps(args, wl, pasm, torch):
            "coefficients": coefficient_text(wl), "iterations": args.iters,
            "eigenpairs_with_last_change_below_1e-10": int(np.sum(d[-1] < 1e-10)), "setup_s": t_setup,
            "step": "one outer iteration (one correction step for all k eigenpairs)"}
+    if replay:
+        cfg["graph_replay"] = replay
     flops = None
     if wl.smoother == "cg":
         kname = KERNEL_NAMES["cg"]

@@ -268,6 +268,24 @@ PASM_API pasm_status pasm_apply_operator(pasm_ctx* ctx, int level, int op, const
 PASM_API pasm_status pasm_vcycle(pasm_ctx* ctx, const double* f, double* x, size_t ld, int nrhs,
                                  int ncycles);
 
+/* Graph replay of correction steps (the batching of Algorithm 1's launches,
+ * which the paper leaves to the implementation).  enable = 1: pasm_iterate,
+ * pasm_iterate_n and pasm_solve record the launches of a correction step
+ * into a hipGraph the first time a step starts from a given context state
+ * (which buffers hold u, f and the eigenvalues, and which fused pass forms
+ * what; at most 16 graphs are kept; a context's very first step runs
+ * unrecorded) and replay it for every later step from that state: the same kernels and arguments, so the same results bit for
+ * bit, with one launch per step instead of one per kernel.  Steps that
+ * record profiling events (pasm_profile) or run the learned smoother run
+ * unrecorded.  A step whose recording fails runs unrecorded and switches the
+ * replay off for the context.  enable = 0 (the default) destroys the graphs.
+ * The call synchronises the context's stream.  The graphs belong to the
+ * context and are destroyed with it. */
+PASM_API pasm_status pasm_use_graph(pasm_ctx* ctx, int enable);
+/* Whether the replay is on, the graphs held and the steps replayed from a
+ * graph since set-up (any output may be NULL). */
+PASM_API pasm_status pasm_graph_stats(const pasm_ctx* ctx, int* enabled, int* graphs, long* replays);
+
 /* Time the launches of one kernel class inside subsequent pasm_iterate calls
  * with HIP events recorded on the context's stream (enable = 1 starts and
  * clears the record, 0 stops).  kernel: 0 = fine-level smoothing sweep. */

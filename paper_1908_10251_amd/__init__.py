@@ -102,6 +102,9 @@ def lib() -> ctypes.CDLL:
     L.pasm_last_error.restype = ctypes.c_char_p
     L.pasm_apply_operator.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_size_t, ctypes.c_int]
     L.pasm_vcycle.argtypes = [_P, _P, _P, ctypes.c_size_t, ctypes.c_int, ctypes.c_int]
+    L.pasm_use_graph.argtypes = [_P, ctypes.c_int]
+    L.pasm_graph_stats.argtypes = [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_long)]
     L.pasm_profile.argtypes = [_P, ctypes.c_int, ctypes.c_int]
     L.pasm_profile_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _D, _D]
     _F = ctypes.POINTER(ctypes.c_float)
@@ -302,6 +305,17 @@ def pasm_apply_operator(ctx, level: int, op: int, x, y) -> None:
 
 def pasm_vcycle(ctx, f, x, ncycles: int) -> None:
     _check(lib().pasm_vcycle(ctx, _torch_ptr(f), _torch_ptr(x), x.shape[1], x.shape[0], ncycles), ctx)
+
+
+def pasm_use_graph(ctx, enable: bool) -> None:
+    _check(lib().pasm_use_graph(ctx, int(enable)), ctx)
+
+
+def pasm_graph_stats(ctx):
+    """(enabled, graphs held, steps replayed from a graph)."""
+    e, g, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
+    _check(lib().pasm_graph_stats(ctx, ctypes.byref(e), ctypes.byref(g), ctypes.byref(r)), ctx)
+    return bool(e.value), g.value, r.value
 
 
 def pasm_profile(ctx, kernel: int, enable: bool) -> None:

@@ -73,6 +73,30 @@ struct Level {
 }  // namespace
 }  // namespace pasm
 
+namespace pasm {
+namespace {
+// The host state a correction step's launches depend on beyond the
+// context's fixed set-up: the rotating buffers, the eigenvalue buffers and
+// the flags that say which fused pass forms what.  Two steps that start from
+// equal states (and the same deferral) launch the same kernels with the same
+// arguments and leave equal states behind.
+struct StepState {
+    double *U, *F64, *Y64, *R64;
+    double *lam, *lam_prev, *mu;
+    const double* pend_beta;
+    int border_nblk;
+    bool f_ready, r32_ready, border_next, border_done, pair_next, fine_pre_done, prolong_pending, e_pending;
+    bool same(const StepState& o) const { return std::memcmp(this, &o, sizeof *this) == 0; }
+};
+struct StepGraph {
+    StepState pre, post;
+    bool defer;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+}  // namespace
+}  // namespace pasm
+
 using pasm::Cheb;
 using pasm::Coef;
 using pasm::Error;
@@ -166,6 +190,12 @@ struct pasm_ctx {
     double* Xb = nullptr;       // finest-level backup of x for a rejected V-cycle
     double* rnpart = nullptr;   // residual-norm partials and per-rhs sums
     double* rnsum = nullptr;
+    // graph replay of correction steps (pasm_use_graph): one captured graph
+    // per host state a step starts from, and the states stepped once eagerly
+    bool use_graph = false;
+    long graph_replays = 0;
+    std::vector<pasm::StepGraph> graphs;
+    bool stepped = false;
     // profiling of the fine-level smoothing sweeps
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -1259,6 +1289,118 @@ void settle_prolongation(pasm_ctx* c) {
     c->f_ready = true;
 }
 
+// Graph replay of correction steps.  A step's launches are a function of the
+// state it starts from (StepState) and the deferral flag.  A step from a state
+// without a graph is captured into one (which records the launches without
+// running them, while the host state advances as if they had run) and then
+// launched; later steps from that state replay the graph and take its
+// recorded end state.  The states cycle with the rotation of the eigenvalue
+// buffers (3) and of u between two buffers (2), so a run of steps needs a
+// handful of graphs.  Steps that read device data on the host (the learned
+// smoother's fallback test) or record profiling events always run eagerly.
+constexpr size_t kMaxStepGraphs = 16;
+
+pasm::StepState save_state(const pasm_ctx* c) {
+    pasm::StepState t;
+    std::memset(&t, 0, sizeof t);  // padding included: states compare bytewise
+    t.U = c->U;
+    t.F64 = c->F64;
+    t.Y64 = c->Y64;
+    t.R64 = c->R64;
+    t.lam = c->lam;
+    t.lam_prev = c->lam_prev;
+    t.mu = c->mu;
+    t.pend_beta = c->pend_beta;
+    t.border_nblk = c->border_nblk;
+    t.f_ready = c->f_ready;
+    t.r32_ready = c->r32_ready;
+    t.border_next = c->border_next;
+    t.border_done = c->border_done;
+    t.pair_next = c->pair_next;
+    t.fine_pre_done = c->fine_pre_done;
+    t.prolong_pending = c->prolong_pending;
+    t.e_pending = c->e_pending;
+    return t;
+}
+
+void load_state(pasm_ctx* c, const pasm::StepState& t) {
+    c->U = t.U;
+    c->F64 = t.F64;
+    c->Y64 = t.Y64;
+    c->R64 = t.R64;
+    c->lam = t.lam;
+    c->lam_prev = t.lam_prev;
+    c->mu = t.mu;
+    c->pend_beta = t.pend_beta;
+    c->border_nblk = t.border_nblk;
+    c->f_ready = t.f_ready;
+    c->r32_ready = t.r32_ready;
+    c->border_next = t.border_next;
+    c->border_done = t.border_done;
+    c->pair_next = t.pair_next;
+    c->fine_pre_done = t.fine_pre_done;
+    c->prolong_pending = t.prolong_pending;
+    c->e_pending = t.e_pending;
+}
+
+void drop_graphs(pasm_ctx* c) {
+    for (pasm::StepGraph& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+void step(pasm_ctx* c, bool defer = false) {
+    if (!c->use_graph || c->prof || c->learned_on) {
+        iterate_once(c, defer);
+        return;
+    }
+    const pasm::StepState pre = save_state(c);
+    for (const pasm::StepGraph& g : c->graphs)
+        if (g.defer == defer && g.pre.same(pre)) {
+            PASM_HIP(hipGraphLaunch(g.exec, c->st));
+            load_state(c, g.post);
+            ++c->graph_replays;
+            return;
+        }
+    if (!c->stepped) {
+        // the first step of a context runs eagerly: the launch helpers query
+        // the device (occupancy) on their first call
+        c->stepped = true;
+        iterate_once(c, defer);
+        return;
+    }
+    if (c->graphs.size() >= kMaxStepGraphs) drop_graphs(c);
+    pasm::StepGraph g{};
+    g.pre = pre;
+    g.defer = defer;
+    PASM_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    try {
+        iterate_once(c, defer);
+    } catch (...) {
+        // nothing ran: back to the state the step started from, and on
+        // without graphs for this context
+        hipGraph_t part = nullptr;
+        (void)hipStreamEndCapture(c->st, &part);
+        if (part) (void)hipGraphDestroy(part);
+        (void)hipGetLastError();
+        load_state(c, pre);
+        drop_graphs(c);
+        c->use_graph = false;
+        iterate_once(c, defer);
+        return;
+    }
+    PASM_HIP(hipStreamEndCapture(c->st, &g.graph));
+    g.post = save_state(c);
+    if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g.graph);
+        throw Error(PASM_E_DEVICE, "hipGraphInstantiate failed for a correction step");
+    }
+    c->graphs.push_back(g);
+    PASM_HIP(hipGraphLaunch(g.exec, c->st));
+}
+
 // ---------------------------------------------------------------------------
 // learned smoother: training data, training, rates
 // ---------------------------------------------------------------------------
@@ -1459,6 +1601,7 @@ PASM_API pasm_status pasm_destroy(pasm_ctx* c) {
     if (c->st) (void)hipStreamSynchronize(c->st);
     for (pasm_ctx* ch : c->nested) pasm_destroy(ch);  // they use c's stream and coarse space
     c->nested.clear();
+    drop_graphs(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->lam_pin) (void)hipHostFree(c->lam_pin);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1507,7 +1650,7 @@ PASM_API pasm_status pasm_setup(pasm_ctx** out, const pasm_domain* dom, const pa
 PASM_API pasm_status pasm_iterate(pasm_ctx* c, int* converged) {
     if (!c || c->k == 0) return PASM_E_STATE;
     PASM_TRY(c, {
-        iterate_once(c);
+        step(c);
         c->lam_prev_h = c->lam_h;
         PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
         PASM_HIP(hipStreamSynchronize(c->st));
@@ -1534,7 +1677,7 @@ PASM_API pasm_status pasm_iterate_n(pasm_ctx* c, int n, int* converged) {
     if (!c || c->k == 0) return PASM_E_STATE;
     if (n < 1) return PASM_E_INVALID;
     PASM_TRY(c, {
-        for (int i = 0; i < n; ++i) iterate_once(c, i + 1 < n);
+        for (int i = 0; i < n; ++i) step(c, i + 1 < n);
         // the eigenvalues before and after the last step, in one synchronisation
         // (pinned host memory: both copies are asynchronous)
         PASM_HIP(hipMemcpyAsync(c->lam_pin, c->lam_prev, c->k * sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -2126,6 +2269,24 @@ PASM_API pasm_status pasm_learned_loss_grad_noalloc(pasm_ctx* c, int level, cons
         if (loss) *loss = L;
         PASM_HIP(hipStreamSynchronize(c->st));
     });
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_use_graph(pasm_ctx* c, int enable) {
+    if (!c) return PASM_E_STATE;
+    PASM_TRY(c, {
+        PASM_HIP(hipStreamSynchronize(c->st));
+        drop_graphs(c);
+    });
+    c->use_graph = enable != 0;
+    return PASM_OK;
+}
+
+PASM_API pasm_status pasm_graph_stats(const pasm_ctx* c, int* enabled, int* graphs, long* replays) {
+    if (!c) return PASM_E_STATE;
+    if (enabled) *enabled = c->use_graph ? 1 : 0;
+    if (graphs) *graphs = (int)c->graphs.size();
+    if (replays) *replays = c->graph_replays;
     return PASM_OK;
 }
 
