@@ -491,19 +491,20 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
         // edge-weight levels (per-element kappa) in FP32: the same marching
         // phases with the weights streamed beside x and f
         const Coef<float> cw = c->coef<float>(l);
-        if (c->fuse && !L.const_coef && !L.general && cw.wx && cw.wy && Lc.g.n * 2 == L.g.n &&
-            pasm::march_ew_supported(L.g, (int)L.pre.size()) && pasm::march_ew_supported(L.g, (int)L.post.size())) {
+        if (c->fuse && !L.const_coef && Lc.g.n * 2 == L.g.n && pasm::march_coef_supported(L.g, cw, (int)L.pre.size()) &&
+            pasm::march_coef_supported(L.g, cw, (int)L.post.size())) {
             const double nodes = (double)L.g.interior() * nrhs, w = sizeof(T);
-            // the two weight planes, counted once per launch (every right-hand
+            // the weight planes (two, or four with the diagonal and the
+            // diagonal couplings), counted once per launch (every right-hand
             // side reads them; after the first they come from the caches)
-            const double cbytes = 2.0 * w * (double)L.g.interior();
+            const double cbytes = (L.general ? 4.0 : 2.0) * w * (double)L.g.interior();
             if (fine) record_start(c);
-            pasm::launch_march_pre_ew(L.g, cw.wx, cw.wy, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
+            pasm::launch_march_pre_ew(L.g, cw, x, f, y, Lc.g, fc, nrhs, to_steps(L.pre), x_zero, c->st);
             if (fine) record_end(c, ((x_zero ? 2.0 : 3.0) + 0.25) * w * nodes + cbytes);
             std::swap(x, y);
             vcycle<T>(c, l - 1, xc, yc, fc, true, nrhs);
             if (fine) record_start(c);
-            pasm::launch_march_post_ew(L.g, cw.wx, cw.wy, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
+            pasm::launch_march_post_ew(L.g, cw, x, f, y, Lc.g, xc, nrhs, to_steps(L.post), c->st);
             if (fine) record_end(c, 3.25 * w * nodes + cbytes);
             std::swap(x, y);
             return;

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "common.h"
 
@@ -245,6 +246,36 @@ const double* bainv<double>(const pasm_batch* b) { return b->Ainv64; }
 template <>
 const float* bainv<float>(const pasm_batch* b) { return b->Ainv32; }
 
+// Levels of 256 cells and more in FP32 with fused smoothing march (both
+// phases need at least one step): every member's right-hand sides in one
+// launch per phase, the member's coefficient planes and smoothing scale
+// picked per pair of right-hand sides.
+template <typename T>
+bool bmarch(const pasm_batch* b, int l) {
+    if constexpr (!std::is_same<T, float>::value) {
+        return false;
+    } else {
+        const BLevel& Lv = b->lv[l];
+        return b->opt.fused_smoothing && b->lv[l - 1].g.n * 2 == Lv.g.n &&
+               pasm::march_coef_supported(Lv.g, b->coef<float>(l), (int)Lv.pre.size()) &&
+               pasm::march_coef_supported(Lv.g, b->coef<float>(l), (int)Lv.post.size());
+    }
+}
+
+// Coefficient planes per member the smoothers read: the two edge-weight
+// planes, or four with the diagonal and the diagonal couplings.
+double bcoef_planes(const pasm_batch* b) { return b->lv.back().c64[3] ? 4.0 : 2.0; }
+
+pasm::SmoothSteps to_steps(const std::vector<Cheb>& v) {
+    pasm::SmoothSteps ss{};
+    ss.s = (int)v.size();
+    for (size_t j = 0; j < v.size() && j < 8; ++j) {
+        ss.a[j] = v[j].a;
+        ss.b[j] = v[j].b;
+    }
+    return ss;
+}
+
 // One V-cycle from zero for every member on the right-hand sides already in
 // the levels' F planes (each member's top-level residual, written by
 // bresidual); the correction ends in the returned pointer of each level.
@@ -260,8 +291,21 @@ std::vector<T*> bvcycle(pasm_batch* b) {
         BLevel& Lv = b->lv[l];
         const int nr = Lv.count * k;
         const T* f = static_cast<const T*>(Lv.F);
-        bsmooth<T>(b, l, cur[l], oth[l], f, Lv.pre, true, nr, Lv.rows);
         const BLevel& Lc = b->lv[l - 1];
+        if (bmarch<T>(b, l)) {
+            // marching pre-smoothing from zero with the residual restriction
+            // to every member's coarse right-hand side
+            const bool fine = (l == b->Lmax - 1) && b->prof;
+            const double nodes = (double)Lv.g.interior() * nr;
+            if (fine) brecord_start(b);
+            pasm::launch_march_pre_ew(Lv.g, b->coef<float>(l), reinterpret_cast<const float*>(cur[l]),
+                                      reinterpret_cast<const float*>(f), reinterpret_cast<float*>(oth[l]), Lc.g,
+                                      static_cast<float*>(Lc.F), nr, to_steps(Lv.pre), true, b->st);
+            if (fine) brecord_end(b, (2.25 * nodes + bcoef_planes(b) * nodes / b->k) * sizeof(T));
+            std::swap(cur[l], oth[l]);
+            continue;
+        }
+        bsmooth<T>(b, l, cur[l], oth[l], f, Lv.pre, true, nr, Lv.rows);
         if (Lv.pre.empty())
             pasm::launch_restrict<T>(Lv.g, f, Lc.g, static_cast<T*>(Lc.F), nr, Lv.g.plane, Lc.g.plane, b->st);
         else
@@ -275,6 +319,18 @@ std::vector<T*> bvcycle(pasm_batch* b) {
         BLevel& Lv = b->lv[l];
         const BLevel& Lc = b->lv[l - 1];
         const int nr = Lv.count * k;
+        if (bmarch<T>(b, l)) {
+            // marching post-smoothing whose x_0 = x + P e_c is formed in the pass
+            const bool fine = (l == b->Lmax - 1) && b->prof;
+            const double nodes = (double)Lv.g.interior() * nr;
+            if (fine) brecord_start(b);
+            pasm::launch_march_post_ew(Lv.g, b->coef<float>(l), reinterpret_cast<const float*>(cur[l]),
+                                       static_cast<const float*>(Lv.F), reinterpret_cast<float*>(oth[l]), Lc.g,
+                                       reinterpret_cast<const float*>(cur[l - 1]), nr, to_steps(Lv.post), b->st);
+            if (fine) brecord_end(b, (3.25 * nodes + bcoef_planes(b) * nodes / b->k) * sizeof(T));
+            std::swap(cur[l], oth[l]);
+            continue;
+        }
         // x = 0 after pre-smoothing only when there is none: then x = P e_c
         pasm::launch_prolong<T>(Lc.g, cur[l - 1], Lv.g, cur[l], nr, Lc.g.plane, Lv.g.plane, !Lv.pre.empty(),
                                 nullptr, b->st);

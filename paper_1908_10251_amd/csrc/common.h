@@ -160,12 +160,15 @@ template <typename T>
 void cg_smooth(const Grid& g, const Coef<T>& c, T* x, const T* f, int nrhs, int steps, bool x_zero, const CgWork& w,
                hipStream_t st);
 
-// Edge-weight (per-element kappa) levels, FP32: the marching pre-smoothing
-// with residual restriction and post-smoothing with prolongation.
+// Levels with edge weights (per-element kappa) or the general 7-point
+// operator (kappa and a potential), FP32, single problems or every member of
+// a batch level: the marching pre-smoothing with residual restriction and
+// post-smoothing with prolongation.
 bool march_ew_supported(const Grid& g, int steps);
-void launch_march_pre_ew(const Grid& g, const float* wx, const float* wy, const float* x0, const float* f, float* out,
+bool march_coef_supported(const Grid& g, const Coef<float>& c, int steps);
+void launch_march_pre_ew(const Grid& g, const Coef<float>& c, const float* x0, const float* f, float* out,
                          const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, hipStream_t st);
-void launch_march_post_ew(const Grid& g, const float* wx, const float* wy, const float* x, const float* f, float* out,
+void launch_march_post_ew(const Grid& g, const Coef<float>& c, const float* x, const float* f, float* out,
                           const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st);
 struct MarchShape {
     int strips, segs, mseg, work, blocks;

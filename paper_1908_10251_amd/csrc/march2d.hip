@@ -125,10 +125,20 @@ struct ProlongSrc {
 // The level's edge weights (per-element kappa): wx at node (i, j) is the
 // weight of the edge to (i + 1, j), wy the weight of the edge to (i, j + 1);
 // A x = sum over the four edges of w (x - x_neighbour), D = sum of the four.
+// GEN (a potential term: the general 7-point operator of the "/" mesh):
+// (A x)_(i,j) = d x - the four edge terms - wne(i,j) x(i+1,j+1)
+// - wne(i-1,j-1) x(i-1,j-1), with the diagonal d given.  Batches: the planes
+// of right-hand side z belong to member z / kpm, ms elements apart, whose
+// smoothing steps b are scaled by bsc[member].
 template <typename T>
 struct EdgeW {
     const T* wx;
     const T* wy;
+    const T* d = nullptr;
+    const T* wne = nullptr;
+    long ms = 0;
+    int kpm = 1;
+    const T* bsc = nullptr;
 };
 
 template <typename T, int S, int MODE, bool XZ>
@@ -554,7 +564,7 @@ __device__ inline void bstore(float v, rsrc_t r, unsigned vo) {
 template <int S, int PF>
 constexpr int ew_unroll() { return lcm_(lcm_(3, S + 2), PF); }
 
-template <int S, int MODE, bool XZ, int NR>
+template <int S, int MODE, bool XZ, int NR, bool GEN>
 __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_march_ew(
     Grid g, const float* __restrict__ x0, const float* __restrict__ f, float* __restrict__ out,
     const float* __restrict__ ec, Grid gc, float* __restrict__ rc, long sf, long sc, SmoothSteps st, MarchShape sh,
@@ -596,12 +606,19 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const rsrc_t os = make_rsrc(out + (long)z0 * sf, (long)nv * pb);
     const rsrc_t es = make_rsrc(POST ? ec + (long)z0 * sc : f, POST ? (long)nv * cb : 0);
     const rsrc_t rs = make_rsrc(POST ? out : rc + (long)z0 * sc, POST ? 0 : (long)nv * cb);
-    const rsrc_t wxs = make_rsrc(ew.wx, (long)sf * 4), wys = make_rsrc(ew.wy, (long)sf * 4);
+    // the coefficient planes of the group's member (every group lies within
+    // one member: NR divides the right-hand sides per member)
+    const int mem = z0 / ew.kpm;
+    const long wo = (long)mem * ew.ms;
+    const rsrc_t wxs = make_rsrc(ew.wx + wo, (long)sf * 4), wys = make_rsrc(ew.wy + wo, (long)sf * 4);
+    const rsrc_t dds = make_rsrc(GEN ? ew.d + wo : ew.wx, GEN ? (long)sf * 4 : 0);
+    const rsrc_t nes = make_rsrc(GEN ? ew.wne + wo : ew.wx, GEN ? (long)sf * 4 : 0);
+    const T bsm = ew.bsc ? ew.bsc[mem] : T(1);
 
     T bs[S], as[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        bs[t] = (T)st.b[t];
+        bs[t] = (T)st.b[t] * bsm;
         as[t] = (T)st.a[t];
     }
     T xw[NR][S + 1][3][2];
@@ -615,6 +632,17 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
     T cwys[2] = {T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < S + 2; ++j) cwx[j][0] = cwx[j][1] = cwy[j][0] = cwy[j][1] = cdi[j][0] = cdi[j][1] = cww[j] = T(0);
+    // GEN: the north-east weights of the last S + 2 rows, the south-west
+    // weight of the first column (the left lane's north-east weight one row
+    // lower), the diagonal (PRE: the residual), and the north-east weights of
+    // row r - S - 2 (the residual's south-west weights)
+    constexpr int GW = GEN ? S + 2 : 1, GD = GEN && !POST ? S + 2 : 1;
+    T cne[GW][2], csw[GW], cdd[GD][2];
+    T cnes[2] = {T(0), T(0)}, csws = T(0);
+#pragma unroll
+    for (int j = 0; j < GW; ++j) cne[j][0] = cne[j][1] = csw[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < GD; ++j) cdd[j][0] = cdd[j][1] = T(0);
 #pragma unroll
     for (int n = 0; n < NR; ++n) {
 #pragma unroll
@@ -660,7 +688,7 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
     struct Slot {
         T x[NR][2], f[NR][2], e0[NR][2], e1[NR][2];
-        T wx[2], wy[2];
+        T wx[2], wy[2], ne[GEN ? 2 : 1], dd[GEN ? 2 : 1];
     };
     auto load = [&](int r, Slot& sl) {
         const int rr = min(max(r, 0), g.n);
@@ -670,6 +698,14 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
         sl.wx[1] = bload(wxs, vwb, so);
         sl.wy[0] = bload(wys, va, sw);
         sl.wy[1] = bload(wys, vb, sw);
+        if constexpr (GEN) {
+            // the kernel's north-east neighbour is the grid's south-west one
+            // in a reflected band: the weight one column and one row lower
+            sl.ne[0] = bload(nes, vwa, sw);
+            sl.ne[1] = bload(nes, vwb, sw);
+            sl.dd[0] = bload(dds, va, so);
+            sl.dd[1] = bload(dds, vb, so);
+        }
         unsigned sc0 = 0, sc1 = 0;
         if constexpr (POST) {
             const int b = rr & 1;
@@ -719,6 +755,23 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
             cwx[0][cc] = detach(sl.wx[cc]);
             cwy[0][cc] = detach(sl.wy[cc]);
+            if constexpr (GEN) {
+                cnes[cc] = cne[S + 1][cc];
+#pragma unroll
+                for (int j = S + 1; j > 0; --j) cne[j][cc] = cne[j - 1][cc];
+                cne[0][cc] = detach(sl.ne[cc]);
+                if constexpr (!POST) {
+#pragma unroll
+                    for (int j = S + 1; j > 0; --j) cdd[j][cc] = cdd[j - 1][cc];
+                    cdd[0][cc] = detach(sl.dd[cc]);
+                }
+            }
+        }
+        if constexpr (GEN) {
+            csws = csw[S + 1];
+#pragma unroll
+            for (int j = S + 1; j > 0; --j) csw[j] = csw[j - 1];
+            csw[0] = from_left(cne[0][1]);
         }
 #pragma unroll
         for (int j = S + 1; j > 0; --j) cww[j] = cww[j - 1];
@@ -729,8 +782,14 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
         // stages need no mask (and no branch on the row)
         cww[0] = from_left(cwx[0][1]);
         const bool rin = r >= 1 && r <= g.m;
-        const T d0 = recip(cwx[0][0] + cww[0] + cwy[0][0] + cwy[1][0]);
-        const T d1 = recip(cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
+        T d0, d1;
+        if constexpr (GEN) {
+            d0 = recip(sl.dd[0]);
+            d1 = recip(sl.dd[1]);
+        } else {
+            d0 = recip(cwx[0][0] + cww[0] + cwy[0][0] + cwy[1][0]);
+            d1 = recip(cwx[0][1] + cwx[0][0] + cwy[0][1] + cwy[1][1]);
+        }
         cdi[0][0] = (rin && inner[0]) ? d0 : T(0);
         cdi[0][1] = (rin && inner[1]) ? d1 : T(0);
     };
@@ -748,6 +807,18 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 const T mc[2] = {m0, m1};
                 const T xe[2] = {m1, right}, xwv[2] = {left, m0};
                 T v[2];
+                // GEN: the diagonal neighbours (i + 1, q + 1), (i - 1, q - 1)
+                T xne[2], xsw[2], wa[2], wb[2];
+                if constexpr (GEN) {
+                    xne[0] = xw[n][t - 1][0][1];
+                    xne[1] = from_right(xw[n][t - 1][0][0]);
+                    xsw[0] = from_left(xw[n][t - 1][2][1]);
+                    xsw[1] = xw[n][t - 1][2][0];
+                    wa[0] = cne[t][0];
+                    wa[1] = cne[t][1];
+                    wb[0] = csw[t + 1];
+                    wb[1] = cne[t + 1][0];
+                }
                 // x + b ((f + sum w x_nb) / D - x)
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
@@ -755,6 +826,10 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     sfv = __builtin_fmaf(ww[cc], xwv[cc], sfv);
                     sfv = __builtin_fmaf(cwy[t][cc], xw[n][t - 1][0][cc], sfv);
                     sfv = __builtin_fmaf(cwy[t + 1][cc], xw[n][t - 1][2][cc], sfv);
+                    if constexpr (GEN) {
+                        sfv = __builtin_fmaf(wa[cc], xne[cc], sfv);
+                        sfv = __builtin_fmaf(wb[cc], xsw[cc], sfv);
+                    }
                     T val = __builtin_fmaf(bs[t - 1], __builtin_fmaf(sfv, cdi[t][cc], -mc[cc]), mc[cc]);
                     if (t >= 2) val = __builtin_fmaf(as[t - 1], mc[cc] - xw[n][t - 2][2][cc], val);
                     v[cc] = val;
@@ -793,10 +868,24 @@ __global__ __launch_bounds__(NL) __attribute__((amdgpu_waves_per_eu(2))) void k_
             for (int n = 0; n < NR; ++n) {
                 const T m0 = xw[n][S][1][0], m1 = xw[n][S][1][1];
                 const T left = from_left(m1), right = from_right(m0);
-                T res0 = fw[n][S + 1][0] - (cwx[S + 1][0] * (m0 - m1) + ww0 * (m0 - left) +
-                                            cwy[S + 1][0] * (m0 - xw[n][S][0][0]) + cwys[0] * (m0 - xw[n][S][2][0]));
-                T res1 = fw[n][S + 1][1] - (cwx[S + 1][1] * (m1 - right) + cwx[S + 1][0] * (m1 - m0) +
-                                            cwy[S + 1][1] * (m1 - xw[n][S][0][1]) + cwys[1] * (m1 - xw[n][S][2][1]));
+                T ax0 = cwx[S + 1][0] * (m0 - m1) + ww0 * (m0 - left) + cwy[S + 1][0] * (m0 - xw[n][S][0][0]) +
+                        cwys[0] * (m0 - xw[n][S][2][0]);
+                T ax1 = cwx[S + 1][1] * (m1 - right) + cwx[S + 1][0] * (m1 - m0) +
+                        cwy[S + 1][1] * (m1 - xw[n][S][0][1]) + cwys[1] * (m1 - xw[n][S][2][1]);
+                if constexpr (GEN) {
+                    // the diagonal couplings, and the rest of the diagonal
+                    // (d minus the six weights) times x
+                    const T ne0 = xw[n][S][0][1], ne1 = from_right(xw[n][S][0][0]);
+                    const T sw0 = from_left(xw[n][S][2][1]), sw1 = xw[n][S][2][0];
+                    const T wa0 = cne[S + 1][0], wa1 = cne[S + 1][1], wb0 = csws, wb1 = cnes[0];
+                    ax0 += wa0 * (m0 - ne0) + wb0 * (m0 - sw0) +
+                           (cdd[S + 1][0] - (cwx[S + 1][0] + ww0 + cwy[S + 1][0] + cwys[0] + wa0 + wb0)) * m0;
+                    ax1 += wa1 * (m1 - ne1) + wb1 * (m1 - sw1) +
+                           (cdd[S + 1][1] - (cwx[S + 1][1] + cwx[S + 1][0] + cwy[S + 1][1] + cwys[1] + wa1 + wb1)) *
+                               m1;
+                }
+                T res0 = fw[n][S + 1][0] - ax0;
+                T res1 = fw[n][S + 1][1] - ax1;
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
                     rw[n][2][cc] = rw[n][1][cc];
@@ -948,67 +1037,92 @@ int march_dispatch(const Grid& g, T w0, const T* x0, const T* f, T* out, const T
 // Edge-weight phases: NR right-hand sides per wavefront (a ragged last
 // group is padded by right-hand sides whose accesses fall outside the
 // buffers).
-template <int S, int MODE, int NR>
+template <int S, int MODE, int NR, bool GEN>
 void march_launch_ew(const Grid& g, const float* x0, const float* f, float* out, const float* ec, const Grid& gc,
                      float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, const EdgeW<float>& ew,
                      hipStream_t st) {
     constexpr int TXO = MW - 2 * march_halo(S);
     constexpr int PF = 6 / NR > 2 ? 6 / NR : 3;
-    static const int slots = device_wave_slots(k_march_ew<S, MODE, false, NR>);
+    static const int slots = device_wave_slots(k_march_ew<S, MODE, false, NR, GEN>);
     const int ngrp = (nrhs + NR - 1) / NR;
     MarchShape sh = march_shape(g, TXO, ngrp, slots, 0, 2 * S + 4, ew_unroll<S, PF>());
     sh.nrhs = nrhs;
     if (MODE == 1 && x_zero)
-        hipLaunchKernelGGL((k_march_ew<S, MODE, true, NR>), dim3(sh.blocks), dim3(NL), 0, st, g, x0, f, out, ec, gc,
-                           rc, g.plane, gc.plane, ss, sh, ew);
+        hipLaunchKernelGGL((k_march_ew<S, MODE, true, NR, GEN>), dim3(sh.blocks), dim3(NL), 0, st, g, x0, f, out, ec,
+                           gc, rc, g.plane, gc.plane, ss, sh, ew);
     else
-        hipLaunchKernelGGL((k_march_ew<S, MODE, false, NR>), dim3(sh.blocks), dim3(NL), 0, st, g, x0, f, out, ec, gc,
-                           rc, g.plane, gc.plane, ss, sh, ew);
+        hipLaunchKernelGGL((k_march_ew<S, MODE, false, NR, GEN>), dim3(sh.blocks), dim3(NL), 0, st, g, x0, f, out, ec,
+                           gc, rc, g.plane, gc.plane, ss, sh, ew);
     PASM_CHECK_LAUNCH();
 }
 
-template <int MODE, int NR>
+template <int MODE, int NR, bool GEN>
 void march_dispatch_ew_nr(const Grid& g, const float* x0, const float* f, float* out, const float* ec,
                           const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero,
                           const EdgeW<float>& ew, hipStream_t st) {
     switch (ss.s) {
-        case 1: march_launch_ew<1, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
-        case 2: march_launch_ew<2, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
-        case 3: march_launch_ew<3, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
-        case 4: march_launch_ew<4, MODE, NR>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 1: march_launch_ew<1, MODE, NR, GEN>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 2: march_launch_ew<2, MODE, NR, GEN>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 3: march_launch_ew<3, MODE, NR, GEN>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
+        case 4: march_launch_ew<4, MODE, NR, GEN>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st); break;
         default: throw Error(PASM_E_INVALID, "marching smoother supports 1..4 steps");
     }
 }
 
+// Two right-hand sides per wavefront unless a pair could straddle two
+// members of a batch (an odd number of right-hand sides per member).
 template <int MODE>
 void march_dispatch_ew(const Grid& g, const float* x0, const float* f, float* out, const float* ec, const Grid& gc,
                        float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, const EdgeW<float>& ew,
                        hipStream_t st) {
-    if (nrhs >= 2) march_dispatch_ew_nr<MODE, 2>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
-    else march_dispatch_ew_nr<MODE, 1>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
+    const bool per_member = ew.ms != 0 || ew.bsc;
+    const bool pairs = nrhs >= 2 && (!per_member || ew.kpm % 2 == 0);
+    if (ew.d) {
+        if (pairs) march_dispatch_ew_nr<MODE, 2, true>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
+        else march_dispatch_ew_nr<MODE, 1, true>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
+    } else {
+        if (pairs) march_dispatch_ew_nr<MODE, 2, false>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
+        else march_dispatch_ew_nr<MODE, 1, false>(g, x0, f, out, ec, gc, rc, nrhs, ss, x_zero, ew, st);
+    }
+}
+
+EdgeW<float> edge_weights_of(const Coef<float>& c) {
+    EdgeW<float> ew{c.wx, c.wy};
+    ew.d = c.d;
+    ew.wne = c.wne;
+    ew.ms = c.ms;
+    ew.kpm = std::max(1, c.kpm);
+    ew.bsc = c.bsc;
+    return ew;
 }
 
 }  // namespace
 
-// Edge-weight levels (per-element kappa), FP32 V-cycles: pre-smoothing with
-// the residual restriction and post-smoothing with the prolongation as
-// marching passes, as for constant coefficients.
+// Levels with edge weights (per-element kappa) or the general 7-point
+// operator (kappa and a potential), FP32 V-cycles: pre-smoothing with the
+// residual restriction and post-smoothing with the prolongation as marching
+// passes, as for constant coefficients.  Batches: every member's planes.
 bool march_ew_supported(const Grid& g, int steps) {
     return g.dim == 2 && steps >= 1 && steps <= 4 && g.n >= 256;
 }
 
-void launch_march_pre_ew(const Grid& g, const float* wx, const float* wy, const float* x0, const float* f, float* out,
-                         const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, hipStream_t st) {
-    if (!march_ew_supported(g, ss.s) || gc.n * 2 != g.n || !wx || !wy)
-        throw Error(PASM_E_INVALID, "edge-weight marching: 2D, at least 256 cells, ratio 2");
-    march_dispatch_ew<1>(g, x0, f, out, nullptr, gc, rc, nrhs, ss, x_zero, EdgeW<float>{wx, wy}, st);
+bool march_coef_supported(const Grid& g, const Coef<float>& c, int steps) {
+    const int kind = coef_kind(c);
+    return march_ew_supported(g, steps) && (kind == 1 || (kind == 2 && c.wne)) && c.wx && c.wy;
 }
 
-void launch_march_post_ew(const Grid& g, const float* wx, const float* wy, const float* x, const float* f, float* out,
+void launch_march_pre_ew(const Grid& g, const Coef<float>& c, const float* x0, const float* f, float* out,
+                         const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, hipStream_t st) {
+    if (!march_coef_supported(g, c, ss.s) || gc.n * 2 != g.n)
+        throw Error(PASM_E_INVALID, "coefficient marching: 2D, at least 256 cells, ratio 2, edge weights or 7 points");
+    march_dispatch_ew<1>(g, x0, f, out, nullptr, gc, rc, nrhs, ss, x_zero, edge_weights_of(c), st);
+}
+
+void launch_march_post_ew(const Grid& g, const Coef<float>& c, const float* x, const float* f, float* out,
                           const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st) {
-    if (!march_ew_supported(g, ss.s) || gc.n * 2 != g.n || !wx || !wy)
-        throw Error(PASM_E_INVALID, "edge-weight marching: 2D, at least 256 cells, ratio 2");
-    march_dispatch_ew<2>(g, x, f, out, ec, gc, nullptr, nrhs, ss, false, EdgeW<float>{wx, wy}, st);
+    if (!march_coef_supported(g, c, ss.s) || gc.n * 2 != g.n)
+        throw Error(PASM_E_INVALID, "coefficient marching: 2D, at least 256 cells, ratio 2, edge weights or 7 points");
+    march_dispatch_ew<2>(g, x, f, out, ec, gc, nullptr, nrhs, ss, false, edge_weights_of(c), st);
 }
 
 // Large 2D levels only: a wavefront walks 64 + 2(S+2) rows in sequence, which

@@ -79,6 +79,39 @@ def test_batch_one_step_matches_oracle_per_member(fused):
                 assert d < 1e-8, (i, j, d)
 
 
+def test_batch_large_members_mixed_one_step_matches_oracle():
+    """Members of 256 and 512 cells march their FP32 levels of 256 cells and
+    more in one launch per phase, each pair of right-hand sides with its
+    member's coefficient planes and smoothing scale; an odd number of
+    right-hand sides per member marches them one per wavefront.  One batched
+    mixed-precision step from the oracle's coarse starts against the
+    oracle's FP64 step per member."""
+    _say("batch, members of 256 and 512 cells, k = 3, mixed: one step")
+    k = 3
+    mem = []
+    for i, (nf, c) in enumerate([(256, (0.3, 0.6)), (512, (0.7, 0.2))]):
+        kap = lognormal_kappa(2, nf, seed=40 + i, sigma=0.5)
+        mem.append((nf, c, kap, quadratic_potential_elements(nf, c, VSCALE)))
+    with P.Batch(H, k, [(1 / nf, kap, vel) for nf, _, kap, vel in mem], opts=_opts(precision=P.PASM_MIXED)) as b:
+        refs = []
+        for i, (nf, c, kap, vel) in enumerate(mem):
+            prob = _oracle_problem(nf, c, kap)
+            lam0, U0, _, _ = O.coarse_start(prob, k)
+            P.pasm_batch_set_state(b.b, i, lam0, U0)
+            bvp = O.MultigridBVP(prob, default_options(2, "cheb", 4, 4, 2))
+            refs.append([O.correction_step(prob, lam0[j], U0[j], bvp) for j in range(k)])
+        b.iterate()
+        for i in range(len(mem)):
+            lg, Ug = b.eigenpairs(i)
+            for j in range(k):
+                ref = refs[i][j]
+                el = abs(lg[j] - ref["lam"]) / ref["lam"]
+                d = np.max(np.abs(Ug[j] - ref["u"])) / np.max(np.abs(ref["u"]))
+                _say(f"  member {i} pair {j}: lambda {el:.2e}, u {d:.2e}")
+                assert el < 1e-8, (i, j, el)
+                assert d < 1e-6, (i, j, d)
+
+
 def test_batch_equals_single_instances():
     """Three iterations of the batch give each member's single-context history."""
     _say("batch vs single contexts")

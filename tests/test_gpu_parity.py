@@ -211,6 +211,37 @@ def test_vcycle_kappa_odd_rhs_count_matches_oracle(smoother, nu):
     assert d < 1e-6
 
 
+@pytest.mark.parametrize("smoother,nu", [("cheb", 4), ("jacobi", 2), ("cheb", 1)])
+def test_vcycle_kappa_potential_odd_rhs_count_matches_oracle(smoother, nu):
+    # kappa and a potential: the general 7-point operator (its diagonal and
+    # the "/" diagonal couplings streamed with the edge weights) marches in
+    # FP32 on the levels of 256 cells and more; three right-hand sides leave
+    # a ragged last pair.  Each right-hand side against the oracle's V-cycle.
+    nc, nf, k = 8, 512, 3
+    _say(f"vcycle kappa + potential h=1/{nf} k={k} {smoother} nu={nu} mixed")
+    kap = lognormal_kappa(2, nf, seed=31, sigma=1.0)
+    vel, vfn = _potential(nf, True)
+    A, _ = fem.assemble(2, nf, kappa=kap, potential=vfn)
+    hier = Hierarchy(2, A, nc, nf)
+    opts = default_options(2, smoother, nu, nu, 1)
+    rng = np.random.default_rng(33)
+    N = A.shape[0]
+    f = rng.standard_normal((k, N))
+    x0 = rng.standard_normal((k, N))
+    o = _opts(smoother, nu, precision=P.PASM_MIXED)
+    with P.Solver(2, 1 / nc, 1 / nf, k, kappa=kap, potential=vel, opts=o) as s:
+        xg = _t(x0)
+        P.pasm_vcycle(s.ctx, _t(f), xg, 2)
+        xg = xg.cpu().numpy()
+    for r in range(k):
+        xr = x0[r].copy()
+        for _ in range(2):
+            xr = hier.vcycle(len(hier.levels) - 1, xr, f[r], opts)
+        err = np.max(np.abs(xg[r] - xr)) / np.max(np.abs(xr))
+        _say(f"  rhs={r} err={err:.2e}")
+        assert err < 2e-5, (r, err)
+
+
 @pytest.mark.parametrize("nf,smoother,pre,post", [(256, "cheb", 4, 4), (512, "jacobi", 2, 2), (256, "cheb", 3, 1),
                                                   (512, "cheb", 1, 4), (256, "jacobi", 1, 1), (512, "jacobi", 3, 3)])
 def test_paired_smoothing_phases_equal_single_cycles(nf, smoother, pre, post):
