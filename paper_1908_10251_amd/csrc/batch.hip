@@ -385,33 +385,80 @@ void bprolong_coefs(pasm_batch* b, const double* s, bool coarse_ready = false) {
     }
 }
 
+// Mixed precision with two V-cycles on 2D members with coefficient planes:
+// f = lambda M u is never stored.  The first residual is formed from u, the
+// first correction and the second residual in one pass (u + e into the f
+// buffer, u kept), and the second correction inside the border pass, which
+// writes u~ back into u.
+bool bfused_defect(const pasm_batch* b) {
+    if (!b->mixed || b->opt.vcycles != 2) return false;
+    const int kind = pasm::coef_kind(b->coef<double>(b->Lmax - 1));
+    if (kind != 1 && kind != 2) return false;
+    for (const BGroup& G : b->grp)
+        if (G.top < 1) return false;
+    return true;
+}
+
 // The device work of one correction step for every member.
 void biterate_device(pasm_batch* b) {
     const int k = b->k, N = b->NH, L = b->Lmax;
-    // Algorithm 1, step 1: f = lambda M u, V-cycles (defect correction)
-    for (const BGroup& G : b->grp) {
-        const Grid& g = b->lv[G.top].g;
-        pasm::launch_mass_rhs(g, G.U, b->lam + (long)G.a * k, G.F64, (G.b - G.a) * k, g.plane, b->st);
-    }
-    for (int cy = 0; cy < b->opt.vcycles; ++cy) {
-        if (b->mixed) {
-            bresidual<float>(b);
-            bcorrect<float>(b, bvcycle<float>(b));
-        } else {
-            bresidual<double>(b);
-            bcorrect<double>(b, bvcycle<double>(b));
+    if (bfused_defect(b)) {
+        // Algorithm 1, step 1 as defect correction: r = lambda M u - A u
+        for (const BGroup& G : b->grp) {
+            const BLevel& Lv = b->lv[G.top];
+            float* r = static_cast<float*>(Lv.F) + (long)G.a * k * Lv.g.plane;
+            pasm::launch_resid_mass_members(Lv.g, b->coef64_slots(G.top, G.a), G.U, b->lam + (long)G.a * k, r,
+                                            (G.b - G.a) * k, Lv.g.plane, b->st);
         }
-    }
-    // step 2: borders fused with the first restriction: P^T A u~ and P^T M u~
-    // of every group land in the B and C planes one level below its top
-    for (const BGroup& G : b->grp) {
-        const BLevel& Lv = b->lv[G.top];
-        const BLevel& Lc = b->lv[G.top - 1];
-        const long o = (long)G.a * k * Lc.g.plane;
-        const int nblk = pasm::launch_border_restrict(Lv.g, b->coef64_slots(G.top, G.a), G.U, Lc.g, Lc.B + o,
-                                                      Lc.C + o, G.partial, (G.b - G.a) * k, Lv.g.plane, Lc.g.plane,
-                                                      b->st);
-        pasm::launch_reduce_pairs(G.partial, nblk, b->bz + 2L * G.a * k, (G.b - G.a) * k, b->st);
+        std::vector<float*> cur = bvcycle<float>(b);
+        // x = u + e (into the f buffer) and r = lambda M u - A x
+        for (const BGroup& G : b->grp) {
+            const BLevel& Lv = b->lv[G.top];
+            const long o = (long)G.a * k * Lv.g.plane;
+            pasm::launch_add_resid_members(Lv.g, b->coef64_slots(G.top, G.a), G.U, cur[G.top] + o, G.F64,
+                                           static_cast<float*>(Lv.F) + o, (G.b - G.a) * k, Lv.g.plane,
+                                           b->lam + (long)G.a * k, b->st);
+        }
+        cur = bvcycle<float>(b);
+        // step 2: u~ = x + e into u, with the borders and their first
+        // restriction (P^T A u~, P^T M u~ in the B and C planes one level
+        // below each group's top)
+        for (const BGroup& G : b->grp) {
+            const BLevel& Lv = b->lv[G.top];
+            const BLevel& Lc = b->lv[G.top - 1];
+            const long oc = (long)G.a * k * Lc.g.plane;
+            const int nblk = pasm::launch_border_restrict_add(
+                Lv.g, b->coef64_slots(G.top, G.a), G.F64, cur[G.top] + (long)G.a * k * Lv.g.plane, G.U, Lc.g,
+                Lc.B + oc, Lc.C + oc, G.partial, (G.b - G.a) * k, Lv.g.plane, Lc.g.plane, b->st);
+            pasm::launch_reduce_pairs(G.partial, nblk, b->bz + 2L * G.a * k, (G.b - G.a) * k, b->st);
+        }
+    } else {
+        // Algorithm 1, step 1: f = lambda M u, V-cycles (defect correction)
+        for (const BGroup& G : b->grp) {
+            const Grid& g = b->lv[G.top].g;
+            pasm::launch_mass_rhs(g, G.U, b->lam + (long)G.a * k, G.F64, (G.b - G.a) * k, g.plane, b->st);
+        }
+        for (int cy = 0; cy < b->opt.vcycles; ++cy) {
+            if (b->mixed) {
+                bresidual<float>(b);
+                bcorrect<float>(b, bvcycle<float>(b));
+            } else {
+                bresidual<double>(b);
+                bcorrect<double>(b, bvcycle<double>(b));
+            }
+        }
+        // step 2: borders fused with the first restriction: P^T A u~ and
+        // P^T M u~ of every group land in the B and C planes one level below
+        // its top
+        for (const BGroup& G : b->grp) {
+            const BLevel& Lv = b->lv[G.top];
+            const BLevel& Lc = b->lv[G.top - 1];
+            const long o = (long)G.a * k * Lc.g.plane;
+            const int nblk = pasm::launch_border_restrict(Lv.g, b->coef64_slots(G.top, G.a), G.U, Lc.g, Lc.B + o,
+                                                          Lc.C + o, G.partial, (G.b - G.a) * k, Lv.g.plane,
+                                                          Lc.g.plane, b->st);
+            pasm::launch_reduce_pairs(G.partial, nblk, b->bz + 2L * G.a * k, (G.b - G.a) * k, b->st);
+        }
     }
     // the chain continues for the members whose top is at least two levels up
     for (int l = L - 3; l >= 0; --l) {

@@ -237,6 +237,14 @@ void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, con
 // the residual kernels can form f = lam M u from u themselves (2D edge
 // weights of a single problem)
 bool mass_rhs_fusable(const Grid& g, const Coef<double>& c);
+// Batch members (2D, edge weights or the general 7-point operator, each
+// right-hand side with its member's coefficient planes), f = lam M u formed
+// from u: r = lam M u - A u; and un = u + e with r = lam M u - A un in one
+// pass (un must not alias u).  lam holds one value per right-hand side.
+void launch_resid_mass_members(const Grid& g, const Coef<double>& c, const double* u, const double* lam, float* r,
+                               int nrhs, long stride, hipStream_t st);
+void launch_add_resid_members(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
+                              float* r, int nrhs, long stride, const double* lam, hipStream_t st);
 // un = u + e and r = f - A un (to FP32) in one pass (3D); un must not alias u.
 // With lam (constant coefficients): f is not read but formed as lam M u.
 void launch_add_resid3(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,

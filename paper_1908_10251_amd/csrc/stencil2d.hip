@@ -442,13 +442,14 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
         }
         return;
     }
-    static_assert(!MASS || (RB > 1 && KIND == 1), "mass right-hand side: edge weights, several right-hand sides");
+    static_assert(!MASS || KIND >= 1, "mass right-hand side: edge weights or the general operator");
     double bs;
     const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const long off = (long)blockIdx.z * stride;
     double Ax, D;
     Stiff2<double, KIND>::apply(g, c, u + off, id, Ax, D);
-    r[(long)blockIdx.z * rstride + id] = (TO)(f[off + id] - Ax);
+    const double fv = MASS ? lam[blockIdx.z] * mass2(g, u + off, id) : f[off + id];
+    r[(long)blockIdx.z * rstride + id] = (TO)(fv - Ax);
 }
 
 // Defect correction between two cycles in one pass (2D; KIND 0 constant
@@ -498,6 +499,40 @@ __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, co
         un[id] = x0;
         r[id] = (float)(fv - Ax);
     }
+}
+
+// The same for batches (right-hand side z of member z / kpm, the member's
+// coefficient planes) with edge weights (KIND 1) or the general operator
+// (KIND 2), f = lam M u formed from u: un = u + e, r = lam M u - A un.
+template <int KIND>
+__global__ __launch_bounds__(BX* BY) void k_add_resid_m(Grid g, Coef<double> cg, const double* __restrict__ u,
+                                                        const float* __restrict__ e, double* __restrict__ un,
+                                                        float* __restrict__ r, long stride,
+                                                        const double* __restrict__ lam) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > g.m || j > g.m) return;
+    const int z = blockIdx.z;
+    double bs;
+    const Coef<double> c = member_coef(cg, z, bs);
+    const int p = g.pitch;
+    const long gid = g.idx(i, j), id = (long)z * stride + gid;
+    // every load before the stores
+    const double u0 = u[id], uE = u[id + 1], uW = u[id - 1], uN = u[id + p], uS = u[id - p];
+    const double uNE = u[id + p + 1], uSW = u[id - p - 1];
+    const double x0 = u0 + (double)e[id], xE = uE + (double)e[id + 1], xW = uW + (double)e[id - 1],
+                 xN = uN + (double)e[id + p], xS = uS + (double)e[id - p];
+    const double we = c.wx[gid], ww = c.wx[gid - 1], wn = c.wy[gid], ws = c.wy[gid - p];
+    double Ax;
+    if (KIND == 1) {
+        Ax = (we + ww + wn + ws) * x0 - we * xE - ww * xW - wn * xN - ws * xS;
+    } else {
+        const double xNE = uNE + (double)e[id + p + 1], xSW = uSW + (double)e[id - p - 1];
+        Ax = c.d[gid] * x0 - we * xE - ww * xW - wn * xN - ws * xS - c.wne[gid] * xNE - c.wne[gid - p - 1] * xSW;
+    }
+    const double fv = lam[z] * (g.h * g.h * (0.5 * u0 + (uE + uW + uN + uS + uNE + uSW) * (1.0 / 12.0)));
+    un[id] = x0;
+    r[id] = (float)(fv - Ax);
 }
 
 template <typename TE>
@@ -1200,6 +1235,34 @@ template void launch_resid_to<float>(const Grid&, const Coef<double>&, const dou
 template void launch_resid_to<double>(const Grid&, const Coef<double>&, const double*, const double*, double*, int,
                                       long, hipStream_t);
 
+void launch_resid_mass_members(const Grid& g, const Coef<double>& c, const double* u, const double* lam, float* r,
+                                int nrhs, long stride, hipStream_t st) {
+    const int kind = coef_kind(c);
+    if (g.dim != 2 || (kind != 1 && kind != 2))
+        throw Error(PASM_E_INVALID, "residual with lam M u: 2D, edge weights or the general operator");
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    if (kind == 2)
+        hipLaunchKernelGGL((k_resid_cast<2, float, 1, true>), grid, blk, 0, st, g, c, u, (const double*)nullptr, r,
+                           stride, stride, nrhs, lam);
+    else
+        hipLaunchKernelGGL((k_resid_cast<1, float, 1, true>), grid, blk, 0, st, g, c, u, (const double*)nullptr, r,
+                           stride, stride, nrhs, lam);
+    PASM_CHECK_LAUNCH();
+}
+
+void launch_add_resid_members(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
+                              float* r, int nrhs, long stride, const double* lam, hipStream_t st) {
+    const int kind = coef_kind(c);
+    if (g.dim != 2 || (kind != 1 && kind != 2) || un == u)
+        throw Error(PASM_E_INVALID, "add and residual of members: 2D, 5- or 7-point operator, separate output");
+    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
+    if (kind == 2)
+        hipLaunchKernelGGL(k_add_resid_m<2>, grid, blk, 0, st, g, c, u, e, un, r, stride, lam);
+    else
+        hipLaunchKernelGGL(k_add_resid_m<1>, grid, blk, 0, st, g, c, u, e, un, r, stride, lam);
+    PASM_CHECK_LAUNCH();
+}
+
 void launch_add_correction(const float* e, double* u, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_add_correction<float>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
     PASM_CHECK_LAUNCH();
@@ -1273,8 +1336,23 @@ int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u
 int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
                                const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
                                hipStream_t st) {
-    if (g.dim != 2 || gc.n * 2 != g.n || un == u || coef_kind(c) == 2)
-        throw Error(PASM_E_INVALID, "correction with borders: 2D, ratio 2, constant or edge weights, separate output");
+    if (g.dim != 2 || gc.n * 2 != g.n || un == u || coef_kind(c) > 2)
+        throw Error(PASM_E_INVALID, "correction with borders: 2D, ratio 2, 5- or 7-point operator, separate output");
+    if (coef_kind(c) == 2 || c.kpm > 1 || c.ms != 0) {
+        // the general operator or batch members: the tile kernel, each
+        // right-hand side with its member's coefficient planes
+        if (coef_kind(c) == 0) throw Error(PASM_E_INVALID, "correction with borders: members need coefficient planes");
+        dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
+        const BorderWork bw{(int)grid.x, (int)grid.y, nrhs};
+        if (coef_kind(c) == 2)
+            hipLaunchKernelGGL((k_border_restrict_t<2, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride,
+                               sc, e, un, bw);
+        else
+            hipLaunchKernelGGL((k_border_restrict_t<1, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride,
+                               sc, e, un, bw);
+        PASM_CHECK_LAUNCH();
+        return (int)(grid.x * grid.y);
+    }
     if (rows_supported(g, c))
         return launch_border_rows(g, c, u, e, un, gc, bc, cc, partial, nrhs, stride, sc, border_partial_blocks(g), st);
     dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
