@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void k_border3z(Grid gf, double w0, const doub
 // The FP64 residual of a mixed-precision step marching along z (3D,
 // constant coefficients), with f = lam M u formed from u: r = lam M u - A x
 // rounded to FP32, x = u (first cycle) or x = u + e (ADD: the first cycle's
-// correction added in FP64, x written to un).  A workgroup owns 32 x 32 fine
+// correction added in FP64, x written to un).  A workgroup owns 64 x 16 fine
 // nodes of a chunk of ZRC fine planes and keeps three planes of u (and e)
 // with a one-node halo in LDS rings; the arithmetic is that of
 // k_resid_cast3 / k_add_resid3 with the mass term.
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void k_border3z(Grid gf, double w0, const doub
 // field on the next coarser grid, u~ the old field in the input, a zero beta
 // dropping it), and written to un: the prolongation of a correction step and
 // the next step's first residual in one pass.
-constexpr int ZFX = 32, ZFY = 32, ZRC = 16;
+constexpr int ZFX = 64, ZFY = 16, ZRC = 32;
 constexpr int ZQX = ZFX + 2, ZQY = ZFY + 2, ZNQ = ZQX * ZQY, ZPQ = (ZNQ + 255) / 256, ZPO = ZFX * ZFY / 256;
 template <bool ADD, bool PRO = false>
 __global__ __launch_bounds__(256) void k_resid3z(Grid g, double w0, const double* __restrict__ u,
