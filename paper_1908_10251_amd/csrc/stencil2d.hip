@@ -442,14 +442,13 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
         }
         return;
     }
-    static_assert(!MASS || KIND >= 1, "mass right-hand side: edge weights or the general operator");
+    static_assert(!MASS || (RB > 1 && KIND == 1), "mass right-hand side: edge weights, several right-hand sides");
     double bs;
     const Coef<double> c = member_coef(cg, blockIdx.z, bs);
     const long off = (long)blockIdx.z * stride;
     double Ax, D;
     Stiff2<double, KIND>::apply(g, c, u + off, id, Ax, D);
-    const double fv = MASS ? lam[blockIdx.z] * mass2(g, u + off, id) : f[off + id];
-    r[(long)blockIdx.z * rstride + id] = (TO)(fv - Ax);
+    r[(long)blockIdx.z * rstride + id] = (TO)(f[off + id] - Ax);
 }
 
 // Defect correction between two cycles in one pass (2D; KIND 0 constant
@@ -503,36 +502,49 @@ __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, co
 
 // The same for batches (right-hand side z of member z / kpm, the member's
 // coefficient planes) with edge weights (KIND 1) or the general operator
-// (KIND 2), f = lam M u formed from u: un = u + e, r = lam M u - A un.
-template <int KIND>
-__global__ __launch_bounds__(BX* BY) void k_add_resid_m(Grid g, Coef<double> cg, const double* __restrict__ u,
-                                                        const float* __restrict__ e, double* __restrict__ un,
-                                                        float* __restrict__ r, long stride,
-                                                        const double* __restrict__ lam) {
+// (KIND 2), f = lam M u formed from u: un = u + e, r = lam M u - A un
+// (ADD), or r = lam M u - A u.  RB consecutive right-hand sides of one
+// member per thread (RB divides kpm) share the coefficient loads.
+template <int KIND, int RB, bool ADD>
+__global__ __launch_bounds__(BX* BY) void k_resid_mass_m(Grid g, Coef<double> cg, const double* __restrict__ u,
+                                                         const float* __restrict__ e, double* __restrict__ un,
+                                                         float* __restrict__ r, long stride,
+                                                         const double* __restrict__ lam) {
     const int i = blockIdx.x * BX + threadIdx.x + 1;
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.m || j > g.m) return;
-    const int z = blockIdx.z;
+    const int z0 = blockIdx.z * RB;
     double bs;
-    const Coef<double> c = member_coef(cg, z, bs);
+    const Coef<double> c = member_coef(cg, z0, bs);
     const int p = g.pitch;
-    const long gid = g.idx(i, j), id = (long)z * stride + gid;
-    // every load before the stores
-    const double u0 = u[id], uE = u[id + 1], uW = u[id - 1], uN = u[id + p], uS = u[id - p];
-    const double uNE = u[id + p + 1], uSW = u[id - p - 1];
-    const double x0 = u0 + (double)e[id], xE = uE + (double)e[id + 1], xW = uW + (double)e[id - 1],
-                 xN = uN + (double)e[id + p], xS = uS + (double)e[id - p];
+    const long gid = g.idx(i, j);
     const double we = c.wx[gid], ww = c.wx[gid - 1], wn = c.wy[gid], ws = c.wy[gid - p];
-    double Ax;
-    if (KIND == 1) {
-        Ax = (we + ww + wn + ws) * x0 - we * xE - ww * xW - wn * xN - ws * xS;
-    } else {
-        const double xNE = uNE + (double)e[id + p + 1], xSW = uSW + (double)e[id - p - 1];
-        Ax = c.d[gid] * x0 - we * xE - ww * xW - wn * xN - ws * xS - c.wne[gid] * xNE - c.wne[gid - p - 1] * xSW;
+    double wa = 0.0, wb = 0.0, d = we + ww + wn + ws;
+    if (KIND == 2) {
+        wa = c.wne[gid];
+        wb = c.wne[gid - p - 1];
+        d = c.d[gid];
     }
-    const double fv = lam[z] * (g.h * g.h * (0.5 * u0 + (uE + uW + uN + uS + uNE + uSW) * (1.0 / 12.0)));
-    un[id] = x0;
-    r[id] = (float)(fv - Ax);
+    const double h2 = g.h * g.h;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int z = z0 + q;
+        const long id = (long)z * stride + gid;
+        // every load of the right-hand side before its stores
+        const double u0 = u[id], uE = u[id + 1], uW = u[id - 1], uN = u[id + p], uS = u[id - p];
+        const double uNE = u[id + p + 1], uSW = u[id - p - 1];
+        double x0 = u0, xE = uE, xW = uW, xN = uN, xS = uS, xNE = uNE, xSW = uSW;
+        if (ADD) {
+            x0 += (double)e[id], xE += (double)e[id + 1], xW += (double)e[id - 1], xN += (double)e[id + p];
+            xS += (double)e[id - p];
+            if (KIND == 2) xNE += (double)e[id + p + 1], xSW += (double)e[id - p - 1];
+        }
+        double Ax = d * x0 - we * xE - ww * xW - wn * xN - ws * xS;
+        if (KIND == 2) Ax -= wa * xNE + wb * xSW;
+        const double fv = lam[z] * (h2 * (0.5 * u0 + (uE + uW + uN + uS + uNE + uSW) * (1.0 / 12.0)));
+        if (ADD) un[id] = x0;
+        r[id] = (float)(fv - Ax);
+    }
 }
 
 template <typename TE>
@@ -1235,32 +1247,46 @@ template void launch_resid_to<float>(const Grid&, const Coef<double>&, const dou
 template void launch_resid_to<double>(const Grid&, const Coef<double>&, const double*, const double*, double*, int,
                                       long, hipStream_t);
 
-void launch_resid_mass_members(const Grid& g, const Coef<double>& c, const double* u, const double* lam, float* r,
-                                int nrhs, long stride, hipStream_t st) {
-    const int kind = coef_kind(c);
-    if (g.dim != 2 || (kind != 1 && kind != 2))
-        throw Error(PASM_E_INVALID, "residual with lam M u: 2D, edge weights or the general operator");
-    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (kind == 2)
-        hipLaunchKernelGGL((k_resid_cast<2, float, 1, true>), grid, blk, 0, st, g, c, u, (const double*)nullptr, r,
-                           stride, stride, nrhs, lam);
-    else
-        hipLaunchKernelGGL((k_resid_cast<1, float, 1, true>), grid, blk, 0, st, g, c, u, (const double*)nullptr, r,
-                           stride, stride, nrhs, lam);
+namespace {
+// Right-hand sides per thread of the member passes: the largest of 5, 4, 2
+// that divides the right-hand sides per member.
+int member_rb(const Coef<double>& c) {
+    const int kpm = std::max(1, c.kpm);
+    for (int rb : {5, 4, 2})
+        if (kpm % rb == 0) return rb;
+    return 1;
+}
+template <int KIND, bool ADD>
+void launch_mass_m(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un, float* r,
+                   int nrhs, long stride, const double* lam, hipStream_t st) {
+    const int rb = member_rb(c);
+    const dim3 gr = grid_for(g.m, g.m, nrhs / rb), blk(BX, BY);
+    switch (rb) {
+        case 5: hipLaunchKernelGGL((k_resid_mass_m<KIND, 5, ADD>), gr, blk, 0, st, g, c, u, e, un, r, stride, lam); break;
+        case 4: hipLaunchKernelGGL((k_resid_mass_m<KIND, 4, ADD>), gr, blk, 0, st, g, c, u, e, un, r, stride, lam); break;
+        case 2: hipLaunchKernelGGL((k_resid_mass_m<KIND, 2, ADD>), gr, blk, 0, st, g, c, u, e, un, r, stride, lam); break;
+        default: hipLaunchKernelGGL((k_resid_mass_m<KIND, 1, ADD>), gr, blk, 0, st, g, c, u, e, un, r, stride, lam); break;
+    }
     PASM_CHECK_LAUNCH();
+}
+}  // namespace
+
+void launch_resid_mass_members(const Grid& g, const Coef<double>& c, const double* u, const double* lam, float* r,
+                               int nrhs, long stride, hipStream_t st) {
+    const int kind = coef_kind(c);
+    if (g.dim != 2 || (kind != 1 && kind != 2) || nrhs % std::max(1, c.kpm) != 0)
+        throw Error(PASM_E_INVALID, "residual with lam M u: 2D, edge weights or the general operator, whole members");
+    if (kind == 2) launch_mass_m<2, false>(g, c, u, nullptr, nullptr, r, nrhs, stride, lam, st);
+    else launch_mass_m<1, false>(g, c, u, nullptr, nullptr, r, nrhs, stride, lam, st);
 }
 
 void launch_add_resid_members(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
                               float* r, int nrhs, long stride, const double* lam, hipStream_t st) {
     const int kind = coef_kind(c);
-    if (g.dim != 2 || (kind != 1 && kind != 2) || un == u)
+    if (g.dim != 2 || (kind != 1 && kind != 2) || un == u || nrhs % std::max(1, c.kpm) != 0)
         throw Error(PASM_E_INVALID, "add and residual of members: 2D, 5- or 7-point operator, separate output");
-    dim3 grid = grid_for(g.m, g.m, nrhs), blk(BX, BY);
-    if (kind == 2)
-        hipLaunchKernelGGL(k_add_resid_m<2>, grid, blk, 0, st, g, c, u, e, un, r, stride, lam);
-    else
-        hipLaunchKernelGGL(k_add_resid_m<1>, grid, blk, 0, st, g, c, u, e, un, r, stride, lam);
-    PASM_CHECK_LAUNCH();
+    if (kind == 2) launch_mass_m<2, true>(g, c, u, e, un, r, nrhs, stride, lam, st);
+    else launch_mass_m<1, true>(g, c, u, e, un, r, nrhs, stride, lam, st);
 }
 
 void launch_add_correction(const float* e, double* u, long n, hipStream_t st) {
