@@ -56,7 +56,9 @@ KERNEL_NAMES = {
        "post-smoothing with fused prolongation)",
     "learned": "finest-level learned smoothing step (k_learned_step: residual, two bfloat16 matrix-core "
                "convolutions, update)",
-    "batch": "finest batched level smoothing phases (k_smooth_fused, general 7-point operators)",
+    "batch": "finest batched level smoothing phases (k_march_ew over every member of the level: the general "
+             "7-point operators' planes of each pair's member streamed beside x and f, pre-smoothing with fused "
+             "residual restriction, post-smoothing with fused prolongation)",
     "cg": "finest-level conjugate-gradient smoothing phases (k_cg_start, k_cg_dir: direction update fused with "
           "A p and p.Ap partial sums, k_cg_update: x, r and r.r partial sums; the inner products added per "
           "right-hand side by k_cg_reduce; the paper's multigrid step)",

@@ -1367,17 +1367,21 @@ int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const doubl
     if (coef_kind(c) == 2 || c.kpm > 1 || c.ms != 0) {
         // the general operator or batch members: the tile kernel, each
         // right-hand side with its member's coefficient planes
+        // (consecutive pieces of work are the right-hand sides of one tile,
+        // on one die: a member's coefficient tile is read from HBM once)
         if (coef_kind(c) == 0) throw Error(PASM_E_INVALID, "correction with borders: members need coefficient planes");
-        dim3 grid((gc.n + BRX - 1) / BRX, (gc.n + BRY - 1) / BRY, nrhs), blk(256);
-        const BorderWork bw{(int)grid.x, (int)grid.y, nrhs};
+        const int ntx = (gc.n + BRX - 1) / BRX, nty = (gc.n + BRY - 1) / BRY;
+        const BorderWork bw{ntx, nty, nrhs};
+        const int total = ntx * nty * nrhs;
+        const dim3 grid((total + 7) / 8 * 8), blk(256);
         if (coef_kind(c) == 2)
-            hipLaunchKernelGGL((k_border_restrict_t<2, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride,
-                               sc, e, un, bw);
+            hipLaunchKernelGGL((k_border_restrict_t<2, true, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial,
+                               stride, sc, e, un, bw);
         else
-            hipLaunchKernelGGL((k_border_restrict_t<1, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial, stride,
-                               sc, e, un, bw);
+            hipLaunchKernelGGL((k_border_restrict_t<1, true, true>), grid, blk, 0, st, g, c, u, gc, bc, cc, partial,
+                               stride, sc, e, un, bw);
         PASM_CHECK_LAUNCH();
-        return (int)(grid.x * grid.y);
+        return ntx * nty;
     }
     if (rows_supported(g, c))
         return launch_border_rows(g, c, u, e, un, gc, bc, cc, partial, nrhs, stride, sc, border_partial_blocks(g), st);
