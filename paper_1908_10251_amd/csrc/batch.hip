@@ -246,7 +246,7 @@ const double* bainv<double>(const pasm_batch* b) { return b->Ainv64; }
 template <>
 const float* bainv<float>(const pasm_batch* b) { return b->Ainv32; }
 
-// Levels of 256 cells and more in FP32 with fused smoothing march (both
+// Levels of 128 cells and more in FP32 with fused smoothing march (both
 // phases need at least one step): every member's right-hand sides in one
 // launch per phase, the member's coefficient planes and smoothing scale
 // picked per pair of right-hand sides.

@@ -1102,8 +1102,10 @@ EdgeW<float> edge_weights_of(const Coef<float>& c) {
 // operator (kappa and a potential), FP32 V-cycles: pre-smoothing with the
 // residual restriction and post-smoothing with the prolongation as marching
 // passes, as for constant coefficients.  Batches: every member's planes.
+// (from 128 cells: with many right-hand sides the strips, bands and pairs
+// still fill the machine; measured faster than the tile smoothers there)
 bool march_ew_supported(const Grid& g, int steps) {
-    return g.dim == 2 && steps >= 1 && steps <= 4 && g.n >= 256;
+    return g.dim == 2 && steps >= 1 && steps <= 4 && g.n >= 128;
 }
 
 bool march_coef_supported(const Grid& g, const Coef<float>& c, int steps) {
@@ -1114,14 +1116,14 @@ bool march_coef_supported(const Grid& g, const Coef<float>& c, int steps) {
 void launch_march_pre_ew(const Grid& g, const Coef<float>& c, const float* x0, const float* f, float* out,
                          const Grid& gc, float* rc, int nrhs, const SmoothSteps& ss, bool x_zero, hipStream_t st) {
     if (!march_coef_supported(g, c, ss.s) || gc.n * 2 != g.n)
-        throw Error(PASM_E_INVALID, "coefficient marching: 2D, at least 256 cells, ratio 2, edge weights or 7 points");
+        throw Error(PASM_E_INVALID, "coefficient marching: 2D, at least 128 cells, ratio 2, edge weights or 7 points");
     march_dispatch_ew<1>(g, x0, f, out, nullptr, gc, rc, nrhs, ss, x_zero, edge_weights_of(c), st);
 }
 
 void launch_march_post_ew(const Grid& g, const Coef<float>& c, const float* x, const float* f, float* out,
                           const Grid& gc, const float* ec, int nrhs, const SmoothSteps& ss, hipStream_t st) {
     if (!march_coef_supported(g, c, ss.s) || gc.n * 2 != g.n)
-        throw Error(PASM_E_INVALID, "coefficient marching: 2D, at least 256 cells, ratio 2, edge weights or 7 points");
+        throw Error(PASM_E_INVALID, "coefficient marching: 2D, at least 128 cells, ratio 2, edge weights or 7 points");
     march_dispatch_ew<2>(g, x, f, out, ec, gc, nullptr, nrhs, ss, false, edge_weights_of(c), st);
 }
 
