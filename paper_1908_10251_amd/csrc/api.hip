@@ -85,7 +85,7 @@ struct StepState {
     double *lam, *lam_prev, *mu;
     const double* pend_beta;
     int border_nblk;
-    bool f_ready, r32_ready, border_next, border_done, pair_next, fine_pre_done, prolong_pending, e_pending;
+    bool f_ready, r32_ready, border_next, border_done, pair_next, fine_pre_done, prolong_pending, e_pending, e_split;
     bool same(const StepState& o) const { return std::memcmp(this, &o, sizeof *this) == 0; }
 };
 struct StepGraph {
@@ -124,6 +124,9 @@ struct pasm_ctx {
     double* stage = nullptr;
     // finest level, FP32 (mixed)
     float *E32 = nullptr, *R32 = nullptr, *Y32 = nullptr;
+    // 2D mixed: the last cycle's correction while E32 still holds the one
+    // before (u + E32 not stored; the border pass adds both, e_split)
+    float* E2_32 = nullptr;
     // coarse space
     double *theta = nullptr, *Qcm = nullptr, *Qrm = nullptr, *Ainv64 = nullptr;
     float* Ainv32 = nullptr;
@@ -179,6 +182,7 @@ struct pasm_ctx {
     // mixed 2D: the last V-cycle's FP32 correction (E32) is still to be added
     // to U; the step's border pass adds it
     bool e_pending = false;
+    bool e_split = false;
     std::vector<char> lstag;  // per eigenpair: the plain V-cycle stagnated too (learned fallback test)
     long lcycles_learned = 0, lcycles_fallback = 0;
     double lthreshold = 0.0;    // > 0: fallback threshold set by the caller
@@ -556,8 +560,11 @@ void vcycle(pasm_ctx* c, int l, T*& x, T*& y, const T* f, bool x_zero, int nrhs)
 // Mixed: r_ready says that R32 already holds f - A x (formed by the previous
 // cycle's last pass); with next set, this cycle's correction and the
 // next cycle's residual are formed in one pass, x moving to scr.
+// keep_sum: the next cycle is the step's last, its correction added by the
+// border pass, so x + e is not stored: x stays, e stays in E32 and the next
+// correction goes to E2_32 (e_split).
 void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs, bool* r_ready = nullptr,
-               bool next = false, bool defer_add = false, const double* lam_mass = nullptr) {
+               bool next = false, bool defer_add = false, const double* lam_mass = nullptr, bool keep_sum = false) {
     const int lf = c->L - 1;
     if (!c->mixed) {
         c->pair_next = next;
@@ -569,9 +576,15 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
     if (!(r_ready && *r_ready))
         pasm::launch_resid_cast(g, c->coef<double>(lf), x, f, c->R32, nrhs, g.plane, c->st, lam_mass);
     if (r_ready) *r_ready = false;
-    float* e = c->E32;
+    float* e = c->e_split ? c->E2_32 : c->E32;
     float* ye = c->Y32;
     vcycle<float>(c, lf, e, ye, c->R32, true, nrhs);
+    if (next && r_ready && keep_sum && !c->e_split) {
+        pasm::launch_resid_of_sum(g, c->coef<double>(lf), x, e, f, c->R32, nrhs, g.plane, c->st, lam_mass);
+        c->e_split = true;
+        *r_ready = true;
+        return;
+    }
     if (next && r_ready && pasm::add_resid_supported(g, c->coef<double>(lf))) {
         pasm::launch_add_resid(g, c->coef<double>(lf), x, e, f, scr, c->R32, nrhs, g.plane, c->st, lam_mass);
         std::swap(x, scr);
@@ -582,6 +595,11 @@ void one_cycle(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs,
         // the last cycle of a step: x + e is formed by the border pass
         c->e_pending = true;
         return;
+    }
+    if (c->e_split) {
+        // x + e0 first, as the stored sum would have been
+        pasm::launch_add_correction(c->E32, x, g.plane * nrhs, c->st);
+        c->e_split = false;
     }
     pasm::launch_add_correction(e, x, g.plane * nrhs, c->st);
 }
@@ -628,7 +646,10 @@ void bvp_cycles(pasm_ctx* c, double*& x, double*& scr, const double* f, int nrhs
             // f = lam M u formed by the residual passes (the first two cycles
             // of a step start from u itself or from u + e with u still in x)
             const double* lam_mass = (eig && c->f_mass && cy < 2) ? c->lam : nullptr;
-            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles, defer, lam_mass);
+            // the next cycle deferred to a row-marching border pass: u + e not stored
+            const bool keep = cy + 2 == ncycles && c->mixed && eig && border && c->E2_32 &&
+                              pasm::rows_supported(c->gf(), c->coef<double>(c->L - 1));
+            one_cycle(c, x, scr, f, nrhs, &r_ready, cy + 1 < ncycles, defer, lam_mass, keep);
             c->border_next = false;
         }
         if (c->fine_pre_done) throw Error(PASM_E_DEVICE, "paired smoothing phases: a cycle left unfinished");
@@ -913,6 +934,7 @@ void build(pasm_ctx* c, const Plan& pl, const pasm_coefficients* coef, int k, co
         c->E32 = c->alloc<float>(nf);
         c->R32 = c->alloc<float>(nf);
         c->Y32 = c->alloc<float>(nf);
+        if (c->dim == 2) c->E2_32 = c->alloc<float>(nf);
     }
     const int N = c->NH;
     c->general_coef = general || general3;
@@ -1201,12 +1223,16 @@ void iterate_once(pasm_ctx* c, bool defer = false) {
         int nblk;
         if (c->e_pending) {
             // u~ = x + e (the last correction) and the borders of u~ in one pass
-            nblk = c->dim == 2 ? pasm::launch_border_restrict_add(g, c->coef<double>(lf), c->U, c->E32, c->Y64, Lc.g,
-                                                                  Lc.B, Lc.C, c->partial, k, sf, Lc.g.plane, c->st)
+            // (e_split: u~ = (x + e0) + e, e0 the cycle before's correction)
+            nblk = c->dim == 2 ? pasm::launch_border_restrict_add(g, c->coef<double>(lf), c->U,
+                                                                  c->e_split ? c->E2_32 : c->E32, c->Y64, Lc.g, Lc.B,
+                                                                  Lc.C, c->partial, k, sf, Lc.g.plane, c->st,
+                                                                  c->e_split ? c->E32 : nullptr)
                                : pasm::launch_border_restrict3(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
                                                                c->partial, k, sf, Lc.g.plane, c->st, c->E32, c->Y64);
             std::swap(c->U, c->Y64);
             c->e_pending = false;
+            c->e_split = false;
         } else {
             nblk = c->border_done ? c->border_nblk
                    : c->dim == 2  ? pasm::launch_border_restrict(g, c->coef<double>(lf), c->U, Lc.g, Lc.B, Lc.C,
@@ -1321,6 +1347,7 @@ pasm::StepState save_state(const pasm_ctx* c) {
     t.fine_pre_done = c->fine_pre_done;
     t.prolong_pending = c->prolong_pending;
     t.e_pending = c->e_pending;
+    t.e_split = c->e_split;
     return t;
 }
 
@@ -1342,6 +1369,7 @@ void load_state(pasm_ctx* c, const pasm::StepState& t) {
     c->fine_pre_done = t.fine_pre_done;
     c->prolong_pending = t.prolong_pending;
     c->e_pending = t.e_pending;
+    c->e_split = t.e_split;
 }
 
 void drop_graphs(pasm_ctx* c) {

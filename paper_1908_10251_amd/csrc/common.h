@@ -234,6 +234,10 @@ void launch_dst_solve(const Grid& g, const double* S, const double* inv, const T
 bool add_resid_supported(const Grid& g, const Coef<double>& c);
 void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
                       double* un, float* r, int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
+// The same without storing un = u + e (2D edge weights): u and e stay, and
+// the border pass after the next cycle forms (u + e) + e' itself.
+void launch_resid_of_sum(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
+                         float* r, int nrhs, long stride, hipStream_t st, const double* lam = nullptr);
 // the residual kernels can form f = lam M u from u themselves (2D edge
 // weights of a single problem)
 bool mass_rhs_fusable(const Grid& g, const Coef<double>& c);
@@ -325,7 +329,7 @@ int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u
 // FP32 correction, added in FP64), un written (2D, constant or edge weights).
 int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
                                const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
-                               hipStream_t st);
+                               hipStream_t st, const float* e0 = nullptr);
 
 // The borders after the last correction as a row-marching pass (rows2d.hip),
 // used by launch_border_restrict_add where rows_supported holds (2D edge
@@ -334,7 +338,7 @@ int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const doubl
 bool rows_supported(const Grid& g, const Coef<double>& c);
 int launch_border_rows(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
                        const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
-                       long max_blocks, hipStream_t st);
+                       long max_blocks, hipStream_t st, const float* e0 = nullptr);
 // Pairs of partial sums per right-hand side that the borders' buffer holds
 // (2D: one per 64 x 4 block of the finest level).
 inline long border_partial_blocks(const Grid& g) {

@@ -50,7 +50,8 @@ struct RowWork {
 };
 
 // ---------------------------------------------------------------------------
-// Borders of un = u + e (e the FP32 correction, added in FP64), un written:
+// Borders of un = u + e (e the FP32 correction, added in FP64), un written
+// (E0: un = (u + e0) + e, the corrections of two cycles in their order):
 // A un and M un at every fine node, bc = P^T A un and cc = P^T M un on the
 // next coarser grid gc (centre 1, the six neighbours of the "/" mesh 1/2),
 // and the sums un.A un, un.M un over the piece's own fine nodes (one pair per
@@ -62,9 +63,11 @@ struct RowWork {
 // ---------------------------------------------------------------------------
 constexpr int BOWN = RL - 4;
 
+template <bool E0>
 __global__ __launch_bounds__(RL* RWG) void k_border_rows(Grid g, const double* __restrict__ wx,
                                                          const double* __restrict__ wy, const double* __restrict__ u,
-                                                         const float* __restrict__ e, double* __restrict__ un,
+                                                         const float* __restrict__ e, const float* __restrict__ e0,
+                                                         double* __restrict__ un,
                                                          Grid gc, double* __restrict__ bc, double* __restrict__ cc,
                                                          double* __restrict__ partial, long stride, long sc,
                                                          RowWork rw) {
@@ -89,14 +92,16 @@ __global__ __launch_bounds__(RL* RWG) void k_border_rows(Grid g, const double* _
     const long zo = (long)z * stride, zq = (long)z * sc;
     const double h2 = g.h * g.h;
     double su[RNS], swx[RNS], swy[RNS];
-    float se[RNS];
+    float se[RNS], s0[RNS];
     auto load = [&](int s, int jj) {
         const long o = (long)jj * p + col;
         swx[s] = wx[o];
         swy[s] = wy[o];
         su[s] = u[zo + o];
         se[s] = e[zo + o];
+        if (E0) s0[s] = e0[zo + o];
     };
+    auto xsum = [&](int s) { return E0 ? (su[s] + (double)s0[s]) + (double)se[s] : su[s] + (double)se[s]; };
 #pragma unroll
     for (int s = 0; s < RNS - 1; ++s) load(s, min(ja - 1 + s, jb1 + 1));  // rows ja - 1 .. ja + 2
     // restriction state: of A un and M un, the sum of S and SW of the coarse
@@ -108,8 +113,8 @@ __global__ __launch_bounds__(RL* RWG) void k_border_rows(Grid g, const double* _
         const int S = q % RNS, C = (q + 1) % RNS, N = (q + 2) % RNS, P = (q + 4) % RNS;
         load(P, min(j + 3, jb1 + 1));  // row j + 3 into the free slot (the last rows load row jb1 + 1 again)
         const double we = swx[C], ww = lane_prev(we), wn = swy[C], ws = swy[S];
-        const double x0 = su[C] + (double)se[C];
-        const double xn = su[N] + (double)se[N], xs = su[S] + (double)se[S];
+        const double x0 = xsum(C);
+        const double xn = xsum(N), xs = xsum(S);
         const double xe = lane_next(x0), xw = lane_prev(x0);
         const double xne = lane_next(xn), xsw = lane_prev(xs);
         const double Ax = (we + ww + wn + ws) * x0 - we * xe - ww * xw - wn * xn - ws * xs;
@@ -161,7 +166,7 @@ int row_slots() {
     int dev = 0, cus = 0, per_cu = 0;
     PASM_HIP(hipGetDevice(&dev));
     PASM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    PASM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_border_rows, RL * RWG, 0));
+    PASM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_border_rows<false>, RL * RWG, 0));
     return std::max(1, cus * per_cu * RWG);
 }
 
@@ -197,7 +202,7 @@ bool rows_supported(const Grid& g, const Coef<double>& c) {
 
 int launch_border_rows(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
                        const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
-                       long max_blocks, hipStream_t st) {
+                       long max_blocks, hipStream_t st, const float* e0) {
     if (!rows_supported(g, c) || gc.n * 2 != g.n || un == u)
         throw Error(PASM_E_INVALID, "row-marching borders: 2D edge weights, ratio 2, separate output");
     static const int slots = row_slots();
@@ -206,8 +211,13 @@ int launch_border_rows(const Grid& g, const Coef<double>& c, const double* u, co
     const RowWork rw = row_shape(strips, gc.m, nrhs, slots, maxb);
     if ((long)strips * rw.bands > max_blocks) throw Error(PASM_E_INVALID, "row-marching borders: partial sums");
     const int wgs = (rw.work + RWG - 1) / RWG;
-    hipLaunchKernelGGL(k_border_rows, dim3((wgs + RXCD - 1) / RXCD * RXCD), dim3(RL * RWG), 0, st, g, c.wx, c.wy, u,
-                       e, un, gc, bc, cc, partial, stride, sc, rw);
+    const dim3 grid((wgs + RXCD - 1) / RXCD * RXCD), blk(RL * RWG);
+    if (e0)
+        hipLaunchKernelGGL(k_border_rows<true>, grid, blk, 0, st, g, c.wx, c.wy, u, e, e0, un, gc, bc, cc, partial,
+                           stride, sc, rw);
+    else
+        hipLaunchKernelGGL(k_border_rows<false>, grid, blk, 0, st, g, c.wx, c.wy, u, e, (const float*)nullptr, un, gc,
+                           bc, cc, partial, stride, sc, rw);
     PASM_CHECK_LAUNCH();
     return strips * rw.bands;
 }

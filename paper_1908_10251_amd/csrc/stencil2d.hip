@@ -456,8 +456,9 @@ __global__ __launch_bounds__(BX* BY) void k_resid_cast(Grid g, Coef<double> cg, 
 // r = f - A un (FP64, rounded to FP32) for the next cycle; un at the
 // neighbours is formed again from u and e.  un must not alias u.
 // MASS: f is not read but formed as lam M u from u itself (u is then the
-// start of the correction step: the step's first cycle).
-template <int KIND, int RB = 1, bool MASS = false>
+// start of the correction step: the step's first cycle).  !WUN: un is not
+// stored (the caller keeps u and e and adds them again later).
+template <int KIND, int RB = 1, bool MASS = false, bool WUN = true>
 __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, const double* __restrict__ u,
                                                       const float* __restrict__ e, const double* __restrict__ f,
                                                       double* __restrict__ un, float* __restrict__ r, long stride,
@@ -495,7 +496,7 @@ __global__ __launch_bounds__(BX* BY) void k_add_resid(Grid g, Coef<double> c, co
         } else {
             fv = f[id];
         }
-        un[id] = x0;
+        if (WUN) un[id] = x0;
         r[id] = (float)(fv - Ax);
     }
 }
@@ -1317,6 +1318,21 @@ void launch_add_resid(const Grid& g, const Coef<double>& c, const double* u, con
     PASM_CHECK_LAUNCH();
 }
 
+void launch_resid_of_sum(const Grid& g, const Coef<double>& c, const double* u, const float* e, const double* f,
+                         float* r, int nrhs, long stride, hipStream_t st, const double* lam) {
+    if (!rows_supported(g, c) || (lam && !mass_rhs_fusable(g, c)))
+        throw Error(PASM_E_INVALID, "residual of u + e without storing it: 2D edge weights of a single problem");
+    constexpr int RB = 4;
+    const dim3 gr = grid_for(g.m, g.m, (nrhs + RB - 1) / RB), blk(BX, BY);
+    if (lam)
+        hipLaunchKernelGGL((k_add_resid<1, RB, true, false>), gr, blk, 0, st, g, c, u, e, f, (double*)nullptr, r,
+                           stride, nrhs, lam);
+    else
+        hipLaunchKernelGGL((k_add_resid<1, RB, false, false>), gr, blk, 0, st, g, c, u, e, f, (double*)nullptr, r,
+                           stride, nrhs, nullptr);
+    PASM_CHECK_LAUNCH();
+}
+
 void launch_add_correction(const double* e, double* u, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_add_correction<double>, dim3(flat_blocks(n)), dim3(256), 0, st, e, u, n);
     PASM_CHECK_LAUNCH();
@@ -1361,9 +1377,16 @@ int launch_border_restrict(const Grid& g, const Coef<double>& c, const double* u
 
 int launch_border_restrict_add(const Grid& g, const Coef<double>& c, const double* u, const float* e, double* un,
                                const Grid& gc, double* bc, double* cc, double* partial, int nrhs, long stride, long sc,
-                               hipStream_t st) {
+                               hipStream_t st, const float* e0) {
     if (g.dim != 2 || gc.n * 2 != g.n || un == u || coef_kind(c) > 2)
         throw Error(PASM_E_INVALID, "correction with borders: 2D, ratio 2, 5- or 7-point operator, separate output");
+    if (e0) {
+        // two corrections: un = (u + e0) + e
+        if (!rows_supported(g, c))
+            throw Error(PASM_E_INVALID, "two corrections with borders: 2D edge weights of a single problem");
+        return launch_border_rows(g, c, u, e, un, gc, bc, cc, partial, nrhs, stride, sc, border_partial_blocks(g), st,
+                                  e0);
+    }
     if (coef_kind(c) == 2 || c.kpm > 1 || c.ms != 0) {
         // the general operator or batch members: the tile kernel, each
         // right-hand side with its member's coefficient planes
